@@ -1,0 +1,241 @@
+"""FP64 CPU oracle of the recursive differentiable transparent-mesh tracer.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the benchmark's CPU-baseline leg, never by the product package.  It shares no
+code with the HIP library; both consume the same seeded numpy inputs.
+
+The C++ source (oracle.cpp) states what each function computes and which
+passage of the paper it follows.  This module only marshals numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+FLAG_DEGEN, FLAG_LEAK, FLAG_GRAZING, FLAG_TIRB, FLAG_TRUNC = 1, 2, 4, 8, 16
+TREE_FIELDS = (["depth", "kind", "tri"] + ["o%d" % i for i in range(3)]
+               + ["d%d" % i for i in range(3)] + ["W%d" % i for i in range(3)]
+               + ["R", "T"] + ["A%d" % i for i in range(3)]
+               + ["t", "entering", "tir", "cos_i"] + ["E%d" % i for i in range(3)])
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.cpp into liboracle.so (g++, FP64, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Env(C.Structure):
+    _fields_ = [("kind", C.c_int), ("W", C.c_int), ("H", C.c_int),
+                ("tex", C.POINTER(C.c_double)), ("n_freq", C.c_int),
+                ("n_layers", C.c_int), ("width", C.c_int), ("in_pad", C.c_int),
+                ("weights", C.POINTER(C.c_double)), ("biases", C.POINTER(C.c_double))]
+
+
+class _Scene(C.Structure):
+    _fields_ = [("V", C.POINTER(C.c_double)), ("nv", C.c_int),
+                ("F", C.POINTER(C.c_int)), ("nf", C.c_int),
+                ("eta", C.c_double), ("sigma", C.c_double * 3),
+                ("env", C.POINTER(_Env)), ("max_depth", C.c_int),
+                ("terminal_env", C.c_int), ("t_eps", C.c_double), ("use_bvh", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or \
+                os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB_PATH)
+        dp, ip, i64 = C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_int64
+        L.or_vertex_normals.argtypes = [dp, C.c_int, ip, C.c_int, dp]
+        L.or_camera_rays.argtypes = [dp, C.c_int, C.c_int, dp, dp]
+        L.or_intersect.argtypes = [C.POINTER(_Scene), dp, dp, ip, i64, ip, dp, dp, dp]
+        L.or_env_eval.argtypes = [C.POINTER(_Env), dp, i64, dp]
+        L.or_env_eval_grad.argtypes = [C.POINTER(_Env), dp, i64, dp, dp]
+        L.or_trace.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, ip,
+                               C.POINTER(C.c_uint64), ip]
+        L.or_trace_grad.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, dp, dp, dp]
+        L.or_trace_tree.argtypes = [C.POINTER(_Scene), dp, dp, dp, C.c_int]
+        L.or_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a, t=C.c_double):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+class Env:
+    """Equirect map [H,W,3] or MLP (weights list [out,in], biases list)."""
+
+    def __init__(self, tex=None, mlp=None):
+        self._keep = []
+        s = _Env()
+        if tex is not None:
+            t = _d(tex)
+            self._keep.append(t)
+            s.kind, s.H, s.W = 0, t.shape[0], t.shape[1]
+            s.tex = _p(t)
+        else:
+            Ws, Bs, n_freq = mlp
+            w = _d(np.concatenate([np.asarray(x, np.float64).ravel() for x in Ws]))
+            b = _d(np.concatenate([np.asarray(x, np.float64).ravel() for x in Bs]))
+            self._keep += [w, b]
+            s.kind = 1
+            s.n_freq = n_freq
+            s.n_layers = len(Ws) - 1
+            s.width = Ws[0].shape[0]
+            s.in_pad = Ws[0].shape[1]
+            s.weights, s.biases = _p(w), _p(b)
+        self.s = s
+
+    def eval(self, dirs):
+        d = _d(dirs).reshape(-1, 3)
+        out = np.empty_like(d)
+        assert lib().or_env_eval(C.byref(self.s), _p(d), len(d), _p(out)) == 0
+        return out
+
+    def eval_grad(self, dirs, grad_rgb):
+        d = _d(dirs).reshape(-1, 3)
+        g = _d(grad_rgb).reshape(-1, 3)
+        out = np.empty_like(d)
+        assert lib().or_env_eval_grad(C.byref(self.s), _p(d), len(d), _p(g), _p(out)) == 0
+        return out
+
+
+class Scene:
+    """Mesh + material + environment + tracing parameters for the oracle."""
+
+    def __init__(self, V, F, eta, sigma, env: Env, max_depth: int,
+                 terminal_env: bool = False, t_eps: float = 1e-5, use_bvh: bool = True):
+        self.V = _d(V).reshape(-1, 3)
+        self.F = np.ascontiguousarray(F, dtype=np.int32).reshape(-1, 3)
+        self.env = env
+        self.eta = float(eta)
+        sg = np.broadcast_to(np.asarray(sigma, np.float64), (3,))
+        self.sigma = sg.copy()
+        self.max_depth = int(max_depth)
+        self.terminal_env = bool(terminal_env)
+        self.t_eps = float(t_eps)
+        self.use_bvh = bool(use_bvh)
+
+    def _s(self):
+        s = _Scene()
+        s.V, s.nv = _p(self.V), len(self.V)
+        s.F, s.nf = _p(self.F, C.c_int), len(self.F)
+        s.eta = self.eta
+        for k in range(3):
+            s.sigma[k] = float(self.sigma[k])
+        s.env = C.pointer(self.env.s)
+        s.max_depth = self.max_depth
+        s.terminal_env = int(self.terminal_env)
+        s.t_eps = self.t_eps
+        s.use_bvh = int(self.use_bvh)
+        return s
+
+    def with_(self, **kw):
+        sc = Scene(self.V, self.F, self.eta, self.sigma, self.env, self.max_depth,
+                   self.terminal_env, self.t_eps, self.use_bvh)
+        for k, v in kw.items():
+            if k == "V":
+                v = _d(v).reshape(-1, 3)
+            if k == "sigma":
+                v = np.broadcast_to(np.asarray(v, np.float64), (3,)).copy()
+            setattr(sc, k, v)
+        return sc
+
+    def trace(self, o, d):
+        """Returns dict(rgb [n,3], wtrunc [n,3], flags [n], hash [n], nseg [n])."""
+        o, d = _d(o).reshape(-1, 3), _d(d).reshape(-1, 3)
+        n = len(o)
+        rgb, wt = np.empty((n, 3)), np.empty((n, 3))
+        fl, ns = np.empty(n, np.int32), np.empty(n, np.int32)
+        hs = np.empty(n, np.uint64)
+        s = self._s()
+        rc = lib().or_trace(C.byref(s), _p(o), _p(d), n, _p(rgb), _p(wt), _p(fl, C.c_int),
+                            _p(hs, C.c_uint64), _p(ns, C.c_int))
+        assert rc == 0, "or_trace rejected its arguments"
+        return {"rgb": rgb, "wtrunc": wt, "flags": fl, "hash": hs, "nseg": ns}
+
+    def trace_grad(self, o, d, grad_rgb):
+        """Returns dict(rgb, dV [nv,3], d_eta, d_sigma [3])."""
+        o, d = _d(o).reshape(-1, 3), _d(d).reshape(-1, 3)
+        g = _d(grad_rgb).reshape(-1, 3)
+        n = len(o)
+        rgb = np.empty((n, 3))
+        dV = np.empty_like(self.V)
+        de = np.zeros(1)
+        ds = np.zeros(3)
+        s = self._s()
+        rc = lib().or_trace_grad(C.byref(s), _p(o), _p(d), n, _p(g), _p(rgb), _p(dV),
+                                 _p(de), _p(ds))
+        assert rc == 0, "or_trace_grad rejected its arguments"
+        return {"rgb": rgb, "dV": dV, "d_eta": float(de[0]), "d_sigma": ds}
+
+    def tree(self, o, d, max_rec: int = 4096):
+        """Depth-first node records of one camera ray (list of dicts)."""
+        o, d = _d(o).reshape(3), _d(d).reshape(3)
+        nd = len(TREE_FIELDS)
+        out = np.zeros((max_rec, nd))
+        s = self._s()
+        k = lib().or_trace_tree(C.byref(s), _p(o), _p(d), _p(out), max_rec)
+        assert k >= 0
+        return [dict(zip(TREE_FIELDS, row)) for row in out[:min(k, max_rec)]]
+
+    def intersect(self, o, d, skip=None):
+        o, d = _d(o).reshape(-1, 3), _d(d).reshape(-1, 3)
+        n = len(o)
+        tri = np.empty(n, np.int32)
+        t, b1, b2 = np.empty(n), np.empty(n), np.empty(n)
+        sk = None if skip is None else np.ascontiguousarray(skip, np.int32)
+        s = self._s()
+        rc = lib().or_intersect(C.byref(s), _p(o), _p(d),
+                                None if sk is None else _p(sk, C.c_int), n,
+                                _p(tri, C.c_int), _p(t), _p(b1), _p(b2))
+        assert rc == 0
+        return tri, t, b1, b2
+
+
+def vertex_normals(V, F):
+    V = _d(V).reshape(-1, 3)
+    F = np.ascontiguousarray(F, np.int32).reshape(-1, 3)
+    N = np.empty_like(V)
+    assert lib().or_vertex_normals(_p(V), len(V), _p(F, C.c_int), len(F), _p(N)) == 0
+    return N
+
+
+def camera_rays(cam):
+    """Camera (synth.Camera) -> o, d arrays [H*W,3], pixel index y*W + x."""
+    a = _d(cam.as_array())
+    n = cam.width * cam.height
+    o, d = np.empty((n, 3)), np.empty((n, 3))
+    assert lib().or_camera_rays(_p(a), cam.width, cam.height, _p(o), _p(d)) == 0
+    return o, d
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def assert_tree_record_size():
+    assert lib().or_tree_record_doubles() == len(TREE_FIELDS)

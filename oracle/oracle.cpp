@@ -1,0 +1,1003 @@
+// FP64 CPU oracle of the recursive differentiable transparent-mesh ray tracer.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+// benchmark's CPU-baseline leg load this library.  It shares no code, header,
+// table or helper with the HIP library; both sides only consume the same
+// seeded input arrays.
+//
+// What it computes (paper, Sec. 3.3 "Differentiable Mesh Ray Tracer" and
+// Sec. 3.2 "Light Interaction with Transparent Objects"):
+//   * vertex normals: mean of unit face normals, normalised (Eq. 12-13);
+//   * closest-hit ray/triangle intersection ("first triangle the ray hits");
+//   * recursive tracing to a depth cap: a miss returns the environment
+//     radiance, a hit splits into a reflected ray (Eq. 3) and a refracted ray
+//     (Eq. 4-6), blended with the Fresnel weights R and T = 1 - R (Eq. 7-8),
+//     total internal reflection keeps only the reflected ray, and a hit
+//     reached from inside the object is attenuated by exp(-sigma t), the
+//     Beer-Lambert integral (Eq. 9-11) for a constant absorption rate;
+//   * gradients of the rendered colours with respect to vertex positions,
+//     IoR and absorption rate, by plain reverse-mode automatic
+//     differentiation (a Wengert tape per camera ray), with the discrete path
+//     (triangle ids, TIR branches, hit/miss, env texel cell) held fixed.
+//
+// Readings where the paper is silent or garbled are listed in the design
+// notes; in short: cos(theta_i) = -d.n, eta_r = eta_t/eta_i with ambient IoR
+// 1, normals are renormalised, inside/outside is decided by the geometric
+// normal of the hit, a ray hitting at the depth cap contributes 0 and its
+// weight is reported as truncated, the environment is at infinity (equirect
+// bilinear lookup or a frequency-encoded MLP of the direction).
+//
+// parity pins: see tests/test_oracle_*.py (closed forms for a glass slab,
+// Fresnel textbook values, energy conservation, invisible object at eta = 1,
+// brute force vs BVH, central finite differences for every gradient).
+//
+// Everything is FP64.  The MLP environment emulates bfloat16 rounding of its
+// inputs, weights and hidden activations and accumulates in FP64.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// reverse-mode AD: a Wengert list of binary nodes with local partials
+// ---------------------------------------------------------------------------
+struct TapeNode {
+  int a, b;
+  double da, db;
+};
+
+struct Tape {
+  std::vector<TapeNode> nodes;
+  int push(int a, double da, int b, double db) {
+    nodes.push_back({a, b, da, db});
+    return (int)nodes.size() - 1;
+  }
+};
+
+thread_local Tape* g_tape = nullptr;
+
+struct Var {
+  double v;
+  int i;  // tape index, -1 = constant
+  Var() : v(0.0), i(-1) {}
+  Var(double x) : v(x), i(-1) {}
+};
+
+inline Var mk(double v, int a, double da, int b = -1, double db = 0.0) {
+  Var r;
+  r.v = v;
+  if (a < 0 && b < 0) {
+    r.i = -1;
+  } else {
+    r.i = g_tape->push(a, da, b, db);
+  }
+  return r;
+}
+inline Var leaf(double v) {
+  Var r;
+  r.v = v;
+  r.i = g_tape->push(-1, 0.0, -1, 0.0);
+  return r;
+}
+inline Var operator+(Var x, Var y) { return mk(x.v + y.v, x.i, 1.0, y.i, 1.0); }
+inline Var operator-(Var x, Var y) { return mk(x.v - y.v, x.i, 1.0, y.i, -1.0); }
+inline Var operator*(Var x, Var y) { return mk(x.v * y.v, x.i, y.v, y.i, x.v); }
+inline Var operator/(Var x, Var y) {
+  return mk(x.v / y.v, x.i, 1.0 / y.v, y.i, -x.v / (y.v * y.v));
+}
+inline Var operator-(Var x) { return mk(-x.v, x.i, -1.0); }
+inline Var Sqrt(Var x) {
+  double s = std::sqrt(x.v);
+  return mk(s, x.i, 0.5 / s);
+}
+inline Var Exp(Var x) {
+  double e = std::exp(x.v);
+  return mk(e, x.i, e);
+}
+inline Var Acos(Var x) {
+  double s = std::sqrt(std::max(1.0 - x.v * x.v, 0.0));
+  return mk(std::acos(x.v), x.i, -1.0 / s);
+}
+inline Var Atan2(Var y, Var x) {
+  double r2 = x.v * x.v + y.v * y.v;
+  return mk(std::atan2(y.v, x.v), y.i, x.v / r2, x.i, -y.v / r2);
+}
+inline Var Sin(Var x) { return mk(std::sin(x.v), x.i, std::cos(x.v)); }
+inline Var Cos(Var x) { return mk(std::cos(x.v), x.i, -std::sin(x.v)); }
+inline Var Relu(Var x) { return x.v > 0.0 ? x : Var(0.0); }
+inline double val(Var x) { return x.v; }
+
+inline double Sqrt(double x) { return std::sqrt(x); }
+inline double Exp(double x) { return std::exp(x); }
+inline double Acos(double x) { return std::acos(x); }
+inline double Atan2(double y, double x) { return std::atan2(y, x); }
+inline double Sin(double x) { return std::sin(x); }
+inline double Cos(double x) { return std::cos(x); }
+inline double Relu(double x) { return x > 0.0 ? x : 0.0; }
+inline double val(double x) { return x; }
+
+template <class S>
+struct V3 {
+  S x, y, z;
+};
+template <class S>
+inline V3<S> add(V3<S> a, V3<S> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class S>
+inline V3<S> sub(V3<S> a, V3<S> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class S>
+inline V3<S> scl(V3<S> a, S s) { return {a.x * s, a.y * s, a.z * s}; }
+template <class S>
+inline S dot(V3<S> a, V3<S> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class S>
+inline V3<S> cross(V3<S> a, V3<S> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <class S>
+inline V3<S> normalize(V3<S> a) {
+  S n = Sqrt(dot(a, a));
+  return {a.x / n, a.y / n, a.z / n};
+}
+template <class S>
+inline V3<double> vval(V3<S> a) { return {val(a.x), val(a.y), val(a.z)}; }
+
+// ---------------------------------------------------------------------------
+// bfloat16 rounding (round to nearest, ties to even) of a double value that is
+// first rounded to float.  Used only by the MLP environment.
+// ---------------------------------------------------------------------------
+inline double bf16_round(double x) {
+  float f = (float)x;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  uint32_t lsb = (u >> 16) & 1u;
+  u = (u + 0x7FFFu + lsb) & 0xFFFF0000u;
+  float g;
+  std::memcpy(&g, &u, 4);
+  return (double)g;
+}
+// Rounding is a step function: derivative taken as identity (straight-through),
+// the same convention as the device's input-gradient of the MLP.
+inline Var bf16_round(Var x) { return mk(bf16_round(x.v), x.i, 1.0); }
+
+}  // namespace
+
+extern "C" {
+
+// Environment description.  kind 0 = equirect map [H][W][3], kind 1 = MLP.
+typedef struct {
+  int kind;
+  int W, H;
+  const double* tex;        // [H*W*3]
+  int n_freq;               // MLP: encoding frequencies (input = 3 + 6 n_freq)
+  int n_layers;             // MLP: hidden layers
+  int width;                // MLP: hidden width
+  int in_pad;               // MLP: padded input width
+  const double* weights;    // MLP: concatenated row-major [out][in] per layer
+  const double* biases;     // MLP: concatenated per layer
+} or_env;
+
+typedef struct {
+  const double* V;  // [nv*3]
+  int nv;
+  const int* F;     // [nf*3]
+  int nf;
+  double eta;       // IoR of the object (ambient medium 1)
+  double sigma[3];  // RGB absorption rate per unit length
+  const or_env* env;
+  int max_depth;     // D: generations 0..D are intersected; a hit at D is truncated
+  int terminal_env;  // 0: truncated hit returns 0; 1: returns A * E(d)
+  double t_eps;      // minimum hit distance
+  int use_bvh;       // 1: BVH, 0: brute force over all triangles
+} or_scene;
+
+enum {
+  OR_FLAG_DEGEN = 1,    // shading normal on the wrong side, geometric normal used
+  OR_FLAG_LEAK = 2,     // a ray inside the object escaped without a hit
+  OR_FLAG_GRAZING = 4,  // cos(theta_i) < 0.02 somewhere on the path
+  OR_FLAG_TIRB = 8,     // |1 - sin^2 theta_t| < 1e-3 somewhere (TIR boundary)
+  OR_FLAG_TRUNC = 16,   // some hit reached the depth cap
+};
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// BVH (binary, median split on the longest centroid axis, <= 4 tris / leaf)
+// ---------------------------------------------------------------------------
+struct BNode {
+  double lo[3], hi[3];
+  int left, right;   // children, or -1
+  int first, count;  // leaf range into order[]
+};
+
+struct BVH {
+  std::vector<BNode> nodes;
+  std::vector<int> order;
+};
+
+void tri_bounds(const or_scene& sc, int f, double lo[3], double hi[3]) {
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = 1e300;
+    hi[k] = -1e300;
+  }
+  for (int j = 0; j < 3; ++j) {
+    const double* p = sc.V + 3 * sc.F[3 * f + j];
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], p[k]);
+      hi[k] = std::max(hi[k], p[k]);
+    }
+  }
+}
+
+int build_rec(const or_scene& sc, BVH& b, std::vector<double>& cen, int first, int count) {
+  BNode n;
+  for (int k = 0; k < 3; ++k) {
+    n.lo[k] = 1e300;
+    n.hi[k] = -1e300;
+  }
+  for (int i = first; i < first + count; ++i) {
+    double lo[3], hi[3];
+    tri_bounds(sc, b.order[i], lo, hi);
+    for (int k = 0; k < 3; ++k) {
+      n.lo[k] = std::min(n.lo[k], lo[k]);
+      n.hi[k] = std::max(n.hi[k], hi[k]);
+    }
+  }
+  // widen each box by a small relative margin so that pruning is conservative
+  for (int k = 0; k < 3; ++k) {
+    double m = 1e-9 * (std::fabs(n.lo[k]) + std::fabs(n.hi[k])) + 1e-12;
+    n.lo[k] -= m;
+    n.hi[k] += m;
+  }
+  n.left = n.right = -1;
+  n.first = first;
+  n.count = count;
+  int idx = (int)b.nodes.size();
+  b.nodes.push_back(n);
+  if (count <= 4) return idx;
+  double clo[3] = {1e300, 1e300, 1e300}, chi[3] = {-1e300, -1e300, -1e300};
+  for (int i = first; i < first + count; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      clo[k] = std::min(clo[k], cen[3 * b.order[i] + k]);
+      chi[k] = std::max(chi[k], cen[3 * b.order[i] + k]);
+    }
+  }
+  int ax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+  int mid = first + count / 2;
+  std::nth_element(b.order.begin() + first, b.order.begin() + mid, b.order.begin() + first + count,
+                   [&](int p, int q) {
+                     double cp = cen[3 * p + ax], cq = cen[3 * q + ax];
+                     return cp < cq || (cp == cq && p < q);
+                   });
+  int l = build_rec(sc, b, cen, first, mid - first);
+  int r = build_rec(sc, b, cen, mid, first + count - mid);
+  b.nodes[idx].left = l;
+  b.nodes[idx].right = r;
+  b.nodes[idx].count = 0;
+  return idx;
+}
+
+void build_bvh(const or_scene& sc, BVH& b) {
+  b.nodes.clear();
+  b.order.resize(sc.nf);
+  std::vector<double> cen(3 * (size_t)sc.nf);
+  for (int f = 0; f < sc.nf; ++f) {
+    b.order[f] = f;
+    for (int k = 0; k < 3; ++k) {
+      double s = 0;
+      for (int j = 0; j < 3; ++j) s += sc.V[3 * sc.F[3 * f + j] + k];
+      cen[3 * f + k] = s / 3.0;
+    }
+  }
+  if (sc.nf > 0) build_rec(sc, b, cen, 0, sc.nf);
+}
+
+// Moller-Trumbore in FP64 with inclusive edges.  Returns true on a hit with
+// t > t_eps; outputs t and the barycentric weights of v1 and v2.
+bool mt_hit(const or_scene& sc, int f, const double o[3], const double d[3], double& t, double& b1,
+            double& b2) {
+  const double* v0 = sc.V + 3 * sc.F[3 * f + 0];
+  const double* v1 = sc.V + 3 * sc.F[3 * f + 1];
+  const double* v2 = sc.V + 3 * sc.F[3 * f + 2];
+  V3<double> e1{v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
+  V3<double> e2{v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+  V3<double> dd{d[0], d[1], d[2]};
+  V3<double> s{o[0] - v0[0], o[1] - v0[1], o[2] - v0[2]};
+  V3<double> p = cross(dd, e2);
+  double det = dot(e1, p);
+  if (det == 0.0) return false;
+  double inv = 1.0 / det;
+  double u = dot(s, p) * inv;
+  if (u < 0.0 || u > 1.0) return false;
+  V3<double> q = cross(s, e1);
+  double v = dot(dd, q) * inv;
+  if (v < 0.0 || u + v > 1.0) return false;
+  double tt = dot(e2, q) * inv;
+  if (!(tt > sc.t_eps)) return false;
+  t = tt;
+  b1 = u;
+  b2 = v;
+  return true;
+}
+
+struct Hit {
+  int tri = -1;
+  double t = 0, b1 = 0, b2 = 0;
+};
+
+inline bool better(double t, int f, const Hit& h) {
+  return h.tri < 0 || t < h.t || (t == h.t && f < h.tri);
+}
+
+Hit closest_brute(const or_scene& sc, const double o[3], const double d[3], int skip) {
+  Hit h;
+  for (int f = 0; f < sc.nf; ++f) {
+    if (f == skip) continue;
+    double t, b1, b2;
+    if (mt_hit(sc, f, o, d, t, b1, b2) && better(t, f, h)) {
+      h.tri = f;
+      h.t = t;
+      h.b1 = b1;
+      h.b2 = b2;
+    }
+  }
+  return h;
+}
+
+// slab test; returns entry distance or +inf when the box is missed
+double box_enter(const BNode& n, const double o[3], const double d[3], double tmax) {
+  double t0 = 0.0, t1 = tmax;
+  for (int k = 0; k < 3; ++k) {
+    if (d[k] == 0.0) {
+      if (o[k] < n.lo[k] || o[k] > n.hi[k]) return INFINITY;
+      continue;
+    }
+    double a = (n.lo[k] - o[k]) / d[k];
+    double b = (n.hi[k] - o[k]) / d[k];
+    if (a > b) std::swap(a, b);
+    t0 = std::max(t0, a);
+    t1 = std::min(t1, b);
+  }
+  return t0 <= t1 ? t0 : INFINITY;
+}
+
+Hit closest_bvh(const or_scene& sc, const BVH& b, const double o[3], const double d[3], int skip) {
+  Hit h;
+  if (b.nodes.empty()) return h;
+  int stack[128];
+  int sp = 0;
+  stack[sp++] = 0;
+  while (sp) {
+    const BNode& n = b.nodes[stack[--sp]];
+    double tmax = h.tri >= 0 ? h.t * (1.0 + 1e-12) : INFINITY;
+    if (box_enter(n, o, d, tmax) == INFINITY) continue;
+    if (n.left < 0) {
+      for (int i = n.first; i < n.first + n.count; ++i) {
+        int f = b.order[i];
+        if (f == skip) continue;
+        double t, b1, b2;
+        if (mt_hit(sc, f, o, d, t, b1, b2) && better(t, f, h)) {
+          h.tri = f;
+          h.t = t;
+          h.b1 = b1;
+          h.b2 = b2;
+        }
+      }
+    } else {
+      stack[sp++] = n.right;
+      stack[sp++] = n.left;
+    }
+  }
+  return h;
+}
+
+// ---------------------------------------------------------------------------
+// per-ray evaluation context
+// ---------------------------------------------------------------------------
+struct Shared {
+  const or_scene* sc;
+  BVH bvh;
+  std::vector<double> Nv;                 // vertex normals (FP64 values)
+  std::vector<std::vector<int>> vfaces;   // vertex -> incident faces (ascending)
+};
+
+template <class S>
+struct Ctx;
+
+template <>
+struct Ctx<double> {
+  const Shared* sh;
+  double eta;
+  double sigma[3];
+  V3<double> pos(int v) const {
+    const double* p = sh->sc->V + 3 * v;
+    return {p[0], p[1], p[2]};
+  }
+  V3<double> nrm(int v) {
+    const double* p = sh->Nv.data() + 3 * v;
+    return {p[0], p[1], p[2]};
+  }
+};
+
+template <class S>
+V3<S> vertex_normal_def(const Shared& sh, int v, Ctx<S>& cx);
+
+template <>
+struct Ctx<Var> {
+  const Shared* sh;
+  Var eta;
+  Var sigma[3];
+  std::unordered_map<int, V3<Var>> P;   // vertex -> leaf position
+  std::unordered_map<int, V3<Var>> N;   // vertex -> normal on the tape
+  V3<Var> pos(int v) {
+    auto it = P.find(v);
+    if (it != P.end()) return it->second;
+    const double* p = sh->sc->V + 3 * v;
+    V3<Var> r{leaf(p[0]), leaf(p[1]), leaf(p[2])};
+    P.emplace(v, r);
+    return r;
+  }
+  V3<Var> nrm(int v) {
+    auto it = N.find(v);
+    if (it != N.end()) return it->second;
+    V3<Var> r = vertex_normal_def<Var>(*sh, v, *this);
+    N.emplace(v, r);
+    return r;
+  }
+};
+
+// Eq. 12-13: vertex normal = normalised sum of unit face normals of the faces
+// around the vertex (the constant 1/3 cancels in the normalisation).  Faces
+// of zero area contribute nothing.
+template <class S>
+V3<S> vertex_normal_def(const Shared& sh, int v, Ctx<S>& cx) {
+  V3<S> acc{S(0.0), S(0.0), S(0.0)};
+  const int* F = sh.sc->F;
+  for (int f : sh.vfaces[v]) {
+    V3<S> a = cx.pos(F[3 * f]), b = cx.pos(F[3 * f + 1]), c = cx.pos(F[3 * f + 2]);
+    V3<S> n = cross(sub(b, a), sub(c, a));
+    double len2 = val(dot(n, n));
+    if (!(len2 > 0.0)) continue;
+    acc = add(acc, normalize(n));
+  }
+  if (!(val(dot(acc, acc)) > 0.0)) return acc;
+  return normalize(acc);
+}
+
+// ---------------------------------------------------------------------------
+// environment
+// ---------------------------------------------------------------------------
+struct EnvOut {
+  int cell_x, cell_y;  // discrete texel cell (for path signatures)
+};
+
+// Equirect lookup at a unit direction: phi = atan2(x, -z), theta = acos(y),
+// u = phi / 2pi + 1/2, v = theta / pi, texel coords (uW - 1/2, vH - 1/2),
+// bilinear, wrapping in u and clamping in v, row 0 at the zenith.
+template <class S>
+V3<S> env_equirect(const or_env& e, V3<S> d, EnvOut& eo) {
+  const double PI = 3.14159265358979323846;
+  S y = d.y;
+  if (val(y) > 1.0) y = S(1.0);
+  if (val(y) < -1.0) y = S(-1.0);
+  S phi = Atan2(d.x, -d.z);
+  S th = Acos(y);
+  S u = phi / S(2.0 * PI) + S(0.5);
+  S v = th / S(PI);
+  S x = u * S((double)e.W) - S(0.5);
+  S yy = v * S((double)e.H) - S(0.5);
+  double x0 = std::floor(val(x)), y0 = std::floor(val(yy));
+  S fx = x - S(x0), fy = yy - S(y0);
+  long ix0 = (long)x0, iy0 = (long)y0;
+  eo.cell_x = (int)ix0;
+  eo.cell_y = (int)iy0;
+  auto wrapx = [&](long i) { return (int)(((i % e.W) + e.W) % e.W); };
+  auto clampy = [&](long i) { return (int)std::min<long>(std::max<long>(i, 0), e.H - 1); };
+  int xa = wrapx(ix0), xb = wrapx(ix0 + 1);
+  int ya = clampy(iy0), yb = clampy(iy0 + 1);
+  auto T = [&](int r, int c, int ch) { return e.tex[((size_t)r * e.W + c) * 3 + ch]; };
+  S w00 = (S(1.0) - fx) * (S(1.0) - fy), w01 = fx * (S(1.0) - fy);
+  S w10 = (S(1.0) - fx) * fy, w11 = fx * fy;
+  V3<S> out;
+  S* o[3] = {&out.x, &out.y, &out.z};
+  for (int ch = 0; ch < 3; ++ch)
+    *o[ch] = w00 * S(T(ya, xa, ch)) + w01 * S(T(ya, xb, ch)) + w10 * S(T(yb, xa, ch)) +
+             w11 * S(T(yb, xb, ch));
+  return out;
+}
+
+// MLP environment: gamma(d) = [d, sin(2^k pi d), cos(2^k pi d)] for k < n_freq,
+// zero-padded; hidden layers with ReLU; linear RGB head.  The encoded input
+// and each post-ReLU activation are rounded to bfloat16; weights are given
+// already on the bfloat16 grid; biases and accumulation are FP64 here.
+template <class S>
+V3<S> env_mlp(const or_env& e, V3<S> d, EnvOut& eo) {
+  const double PI = 3.14159265358979323846;
+  eo.cell_x = eo.cell_y = 0;
+  std::vector<S> h((size_t)e.in_pad, S(0.0));
+  S dc[3] = {d.x, d.y, d.z};
+  int k = 0;
+  for (int c = 0; c < 3; ++c) h[k++] = dc[c];
+  for (int f = 0; f < e.n_freq; ++f) {
+    double w = std::ldexp(PI, f);
+    for (int c = 0; c < 3; ++c) h[k++] = Sin(S(w) * dc[c]);
+    for (int c = 0; c < 3; ++c) h[k++] = Cos(S(w) * dc[c]);
+  }
+  for (auto& x : h) x = bf16_round(x);
+  const double* W = e.weights;
+  const double* B = e.biases;
+  int in = e.in_pad;
+  for (int l = 0; l <= e.n_layers; ++l) {
+    int out = l < e.n_layers ? e.width : 3;
+    std::vector<S> z((size_t)out);
+    for (int j = 0; j < out; ++j) {
+      S acc = S(B[j]);
+      for (int i = 0; i < in; ++i) acc = acc + S(W[(size_t)j * in + i]) * h[i];
+      z[j] = l < e.n_layers ? bf16_round(Relu(acc)) : acc;
+    }
+    W += (size_t)out * in;
+    B += out;
+    h.swap(z);
+    in = out;
+  }
+  return {h[0], h[1], h[2]};
+}
+
+template <class S>
+V3<S> env_eval(const or_env& e, V3<S> d, EnvOut& eo) {
+  return e.kind == 0 ? env_equirect(e, d, eo) : env_mlp(e, d, eo);
+}
+
+// ---------------------------------------------------------------------------
+// recursive tracer
+// ---------------------------------------------------------------------------
+struct PathInfo {
+  int flags = 0;
+  double wtrunc[3] = {0, 0, 0};
+  int nseg = 0;
+  uint64_t hash = 1469598103934665603ull;
+  void mix(uint64_t x) {
+    for (int i = 0; i < 8; ++i) {
+      hash ^= (x >> (8 * i)) & 0xFF;
+      hash *= 1099511628211ull;
+    }
+  }
+};
+
+struct TreeRec {
+  double depth, kind, tri;   // kind 0 miss, 1 hit, 2 truncated
+  double o[3], d[3], W[3];
+  double R, T, A[3], t, entering, tir, cos_i;
+  double E[3];
+};
+
+template <class S>
+V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bool inside,
+            PathInfo& pi, std::vector<TreeRec>* tree) {
+  const Shared& sh = *cx.sh;
+  const or_scene& sc = *sh.sc;
+  pi.nseg++;
+  double od[3] = {val(o.x), val(o.y), val(o.z)}, dd[3] = {val(d.x), val(d.y), val(d.z)};
+  Hit h = sc.use_bvh ? closest_bvh(sc, sh.bvh, od, dd, skip) : closest_brute(sc, od, dd, skip);
+  TreeRec rec{};
+  if (tree) {
+    rec.depth = g;
+    rec.tri = h.tri;
+    for (int k = 0; k < 3; ++k) {
+      rec.o[k] = od[k];
+      rec.d[k] = dd[k];
+      rec.W[k] = W[k];
+    }
+  }
+  if (h.tri < 0) {
+    // Procedure step 3: no hit -> radiance from the environment.
+    if (inside) pi.flags |= OR_FLAG_LEAK;
+    EnvOut eo;
+    V3<S> E = env_eval(*sc.env, d, eo);
+    pi.mix(0xE0000000ull ^ ((uint64_t)(uint32_t)eo.cell_x << 16) ^ (uint64_t)(uint32_t)eo.cell_y);
+    if (tree) {
+      rec.kind = 0;
+      rec.E[0] = val(E.x);
+      rec.E[1] = val(E.y);
+      rec.E[2] = val(E.z);
+      tree->push_back(rec);
+    }
+    return E;
+  }
+  const int* F = sc.F;
+  int i0 = F[3 * h.tri], i1 = F[3 * h.tri + 1], i2 = F[3 * h.tri + 2];
+  V3<S> v0 = cx.pos(i0), v1 = cx.pos(i1), v2 = cx.pos(i2);
+  // differentiable intersection: Moller-Trumbore on the tape, so t and the
+  // barycentrics depend on the ray and the three vertices
+  V3<S> e1 = sub(v1, v0), e2 = sub(v2, v0), s = sub(o, v0);
+  V3<S> p = cross(d, e2);
+  S det = dot(e1, p);
+  S inv = S(1.0) / det;
+  V3<S> q = cross(s, e1);
+  S b1 = dot(s, p) * inv;
+  S b2 = dot(d, q) * inv;
+  S t = dot(e2, q) * inv;
+  S b0 = S(1.0) - b1 - b2;
+  V3<S> x = add(o, scl(d, t));
+  V3<S> ng = cross(e1, e2);
+  // Procedure step 2: outside / inside by the geometric normal of the hit
+  bool entering = val(dot(d, ng)) < 0.0;
+  // Eq. 12: shading normal = barycentric blend of vertex normals, renormalised
+  V3<S> m = add(add(scl(cx.nrm(i0), b0), scl(cx.nrm(i1), b1)), scl(cx.nrm(i2), b2));
+  V3<S> n = normalize(m);
+  if (!entering) n = scl(n, S(-1.0));
+  S cos_i = -dot(d, n);
+  if (!(val(cos_i) > 0.0)) {
+    pi.flags |= OR_FLAG_DEGEN;
+    n = normalize(ng);
+    if (!entering) n = scl(n, S(-1.0));
+    cos_i = -dot(d, n);
+  }
+  if (val(cos_i) < 0.02) pi.flags |= OR_FLAG_GRAZING;
+  // eta_r = eta_t / eta_i, ambient medium 1
+  S eta_i = entering ? S(1.0) : cx.eta;
+  S eta_t = entering ? cx.eta : S(1.0);
+  S eta_r = eta_t / eta_i;
+  // Procedure step 5 / Eq. 11: attenuation over the interior segment just
+  // travelled (the ray hit the surface from inside)
+  V3<S> A{S(1.0), S(1.0), S(1.0)};
+  if (!entering) {
+    A = {Exp(-cx.sigma[0] * t), Exp(-cx.sigma[1] * t), Exp(-cx.sigma[2] * t)};
+  }
+  double Av[3] = {val(A.x), val(A.y), val(A.z)};
+  if (tree) {
+    rec.t = val(t);
+    rec.entering = entering;
+    rec.cos_i = val(cos_i);
+    for (int k = 0; k < 3; ++k) rec.A[k] = Av[k];
+  }
+  // Procedure step 1: the depth cap
+  if (g >= sc.max_depth) {
+    pi.flags |= OR_FLAG_TRUNC;
+    for (int k = 0; k < 3; ++k) pi.wtrunc[k] += W[k] * Av[k];
+    pi.mix(0x70000000ull ^ (uint64_t)h.tri);
+    if (tree) {
+      rec.kind = 2;
+      tree->push_back(rec);
+    }
+    if (sc.terminal_env) {
+      EnvOut eo;
+      V3<S> E = env_eval(*sc.env, d, eo);
+      return {A.x * E.x, A.y * E.y, A.z * E.z};
+    }
+    return {S(0.0), S(0.0), S(0.0)};
+  }
+  // Snell: sin^2(theta_t) = sin^2(theta_i) / eta_r^2
+  S sin2t = (S(1.0) - cos_i * cos_i) / (eta_r * eta_r);
+  if (std::fabs(1.0 - val(sin2t)) < 1e-3) pi.flags |= OR_FLAG_TIRB;
+  // Eq. 3 with omega_i = -d
+  V3<S> rdir = normalize(add(d, scl(n, S(2.0) * cos_i)));
+  bool tir = val(sin2t) > 1.0;
+  pi.mix(((uint64_t)h.tri << 2) ^ (tir ? 1u : 0u) ^ (entering ? 2u : 0u));
+  // the child that continues on the same side of the surface as the parent
+  // stays outside/inside accordingly
+  bool r_inside = !entering, t_inside = entering;
+  if (tir) {
+    // total internal reflection: reflection only, R = 1
+    if (tree) {
+      rec.kind = 1;
+      rec.R = 1.0;
+      rec.T = 0.0;
+      rec.tir = 1;
+      tree->push_back(rec);
+    }
+    double Wr[3] = {W[0] * Av[0], W[1] * Av[1], W[2] * Av[2]};
+    V3<S> Lr = trace(cx, x, rdir, h.tri, g + 1, Wr, r_inside, pi, tree);
+    return {A.x * Lr.x, A.y * Lr.y, A.z * Lr.z};
+  }
+  S cos_t = Sqrt(S(1.0) - sin2t);
+  // Eq. 7-8
+  S rs = (eta_i * cos_i - eta_t * cos_t) / (eta_i * cos_i + eta_t * cos_t);
+  S rp = (eta_i * cos_t - eta_t * cos_i) / (eta_i * cos_t + eta_t * cos_i);
+  S R = S(0.5) * (rs * rs + rp * rp);
+  S T = S(1.0) - R;
+  // Eq. 4-6 with omega_i = -d: omega_t = d/eta_r + (cos_i/eta_r - cos_t) n
+  V3<S> tdir = normalize(add(scl(d, S(1.0) / eta_r), scl(n, cos_i / eta_r - cos_t)));
+  if (tree) {
+    rec.kind = 1;
+    rec.R = val(R);
+    rec.T = val(T);
+    rec.tir = 0;
+    tree->push_back(rec);
+  }
+  double Wr[3], Wt[3];
+  for (int k = 0; k < 3; ++k) {
+    Wr[k] = W[k] * Av[k] * val(R);
+    Wt[k] = W[k] * Av[k] * val(T);
+  }
+  // Procedure step 4: trace both children and blend with R and T
+  V3<S> Lr = trace(cx, x, rdir, h.tri, g + 1, Wr, r_inside, pi, tree);
+  V3<S> Lt = trace(cx, x, tdir, h.tri, g + 1, Wt, t_inside, pi, tree);
+  return {A.x * (R * Lr.x + T * Lt.x), A.y * (R * Lr.y + T * Lt.y), A.z * (R * Lr.z + T * Lt.z)};
+}
+
+void make_shared(const or_scene* sc, Shared& sh, bool need_normals) {
+  sh.sc = sc;
+  if (sc->use_bvh) build_bvh(*sc, sh.bvh);
+  sh.vfaces.assign(sc->nv, {});
+  for (int f = 0; f < sc->nf; ++f)
+    for (int j = 0; j < 3; ++j) sh.vfaces[sc->F[3 * f + j]].push_back(f);
+  if (need_normals) {
+    sh.Nv.assign(3 * (size_t)sc->nv, 0.0);
+    Ctx<double> cx{&sh, sc->eta, {sc->sigma[0], sc->sigma[1], sc->sigma[2]}};
+    for (int v = 0; v < sc->nv; ++v) {
+      V3<double> n = vertex_normal_def<double>(sh, v, cx);
+      sh.Nv[3 * v] = n.x;
+      sh.Nv[3 * v + 1] = n.y;
+      sh.Nv[3 * v + 2] = n.z;
+    }
+  }
+}
+
+bool valid_scene(const or_scene* sc) {
+  if (!sc || !sc->V || !sc->F || !sc->env || sc->nv <= 0 || sc->nf <= 0) return false;
+  if (sc->max_depth < 0 || sc->max_depth > 30) return false;
+  for (int i = 0; i < 3 * sc->nf; ++i)
+    if (sc->F[i] < 0 || sc->F[i] >= sc->nv) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// Vertex normals (Eq. 12-13).  N: [nv*3].
+int or_vertex_normals(const double* V, int nv, const int* F, int nf, double* N) {
+  or_env dummy{};
+  or_scene sc{};
+  sc.V = V;
+  sc.nv = nv;
+  sc.F = F;
+  sc.nf = nf;
+  sc.env = &dummy;
+  if (!valid_scene(&sc)) return 1;
+  Shared sh;
+  make_shared(&sc, sh, true);
+  std::memcpy(N, sh.Nv.data(), sizeof(double) * 3 * (size_t)nv);
+  return 0;
+}
+
+// Pinhole camera rays: eye, target, up hint, vertical FOV in degrees;
+// right-handed, image row 0 at the top, rays through pixel centres.
+// o, d: [W*H*3], pixel index = y*W + x.
+int or_camera_rays(const double* cam, int W, int H, double* o, double* d) {
+  const double PI = 3.14159265358979323846;
+  V3<double> eye{cam[0], cam[1], cam[2]}, tgt{cam[3], cam[4], cam[5]}, up{cam[6], cam[7], cam[8]};
+  V3<double> f = normalize(sub(tgt, eye));
+  V3<double> r = normalize(cross(f, up));
+  V3<double> u = cross(r, f);
+  double th = std::tan(0.5 * cam[9] * PI / 180.0);
+  double aspect = (double)W / (double)H;
+  for (int y = 0; y < H; ++y)
+    for (int x = 0; x < W; ++x) {
+      double px = (2.0 * (x + 0.5) / W - 1.0) * th * aspect;
+      double py = (1.0 - 2.0 * (y + 0.5) / H) * th;
+      V3<double> dd = normalize(add(f, add(scl(r, px), scl(u, py))));
+      size_t i = (size_t)y * W + x;
+      o[3 * i] = eye.x;
+      o[3 * i + 1] = eye.y;
+      o[3 * i + 2] = eye.z;
+      d[3 * i] = dd.x;
+      d[3 * i + 1] = dd.y;
+      d[3 * i + 2] = dd.z;
+    }
+  return 0;
+}
+
+// Closest hit for n rays (skip[i] = triangle to ignore, -1 for none).
+int or_intersect(const or_scene* sc, const double* o, const double* d, const int* skip, int64_t n,
+                 int* tri, double* t, double* b1, double* b2) {
+  if (!valid_scene(sc)) return 1;
+  Shared sh;
+  make_shared(sc, sh, false);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) {
+    int sk = skip ? skip[i] : -1;
+    Hit h = sc->use_bvh ? closest_bvh(*sc, sh.bvh, o + 3 * i, d + 3 * i, sk)
+                        : closest_brute(*sc, o + 3 * i, d + 3 * i, sk);
+    tri[i] = h.tri;
+    t[i] = h.t;
+    b1[i] = h.b1;
+    b2[i] = h.b2;
+  }
+  return 0;
+}
+
+// Environment radiance for n unit directions.  cell: [n*2] texel cell or NULL.
+int or_env_eval(const or_env* env, const double* dirs, int64_t n, double* rgb) {
+  if (!env) return 1;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    EnvOut eo;
+    V3<double> d{dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
+    V3<double> e = env_eval<double>(*env, d, eo);
+    rgb[3 * i] = e.x;
+    rgb[3 * i + 1] = e.y;
+    rgb[3 * i + 2] = e.z;
+  }
+  return 0;
+}
+
+// Gradient of sum(grad_rgb * E(dirs)) with respect to the directions.
+int or_env_eval_grad(const or_env* env, const double* dirs, int64_t n, const double* grad_rgb,
+                     double* grad_dirs) {
+  if (!env) return 1;
+#pragma omp parallel
+  {
+    Tape tape;
+    g_tape = &tape;
+#pragma omp for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+      tape.nodes.clear();
+      EnvOut eo;
+      V3<Var> d{leaf(dirs[3 * i]), leaf(dirs[3 * i + 1]), leaf(dirs[3 * i + 2])};
+      V3<Var> e = env_eval<Var>(*env, d, eo);
+      std::vector<double> adj(tape.nodes.size(), 0.0);
+      if (e.x.i >= 0) adj[e.x.i] += grad_rgb[3 * i];
+      if (e.y.i >= 0) adj[e.y.i] += grad_rgb[3 * i + 1];
+      if (e.z.i >= 0) adj[e.z.i] += grad_rgb[3 * i + 2];
+      for (int k = (int)tape.nodes.size() - 1; k >= 0; --k) {
+        double a = adj[k];
+        if (a == 0.0) continue;
+        const TapeNode& tn = tape.nodes[k];
+        if (tn.a >= 0) adj[tn.a] += tn.da * a;
+        if (tn.b >= 0) adj[tn.b] += tn.db * a;
+      }
+      grad_dirs[3 * i] = adj[d.x.i];
+      grad_dirs[3 * i + 1] = adj[d.y.i];
+      grad_dirs[3 * i + 2] = adj[d.z.i];
+    }
+    g_tape = nullptr;
+  }
+  return 0;
+}
+
+// Forward render of n camera rays (o, d unit).  Outputs per ray: rgb [n*3],
+// truncated weight [n*3], flags [n], path signature hash [n], segment count [n].
+// Any output pointer may be NULL.
+int or_trace(const or_scene* sc, const double* o, const double* d, int64_t n, double* rgb,
+             double* wtrunc, int* flags, uint64_t* hash, int* nseg) {
+  if (!valid_scene(sc)) return 1;
+  Shared sh;
+  make_shared(sc, sh, true);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < n; ++i) {
+    Ctx<double> cx{&sh, sc->eta, {sc->sigma[0], sc->sigma[1], sc->sigma[2]}};
+    PathInfo pi;
+    double W[3] = {1, 1, 1};
+    V3<double> oo{o[3 * i], o[3 * i + 1], o[3 * i + 2]}, dd{d[3 * i], d[3 * i + 1], d[3 * i + 2]};
+    V3<double> L = trace<double>(cx, oo, dd, -1, 0, W, false, pi, nullptr);
+    if (rgb) {
+      rgb[3 * i] = L.x;
+      rgb[3 * i + 1] = L.y;
+      rgb[3 * i + 2] = L.z;
+    }
+    if (wtrunc)
+      for (int k = 0; k < 3; ++k) wtrunc[3 * i + k] = pi.wtrunc[k];
+    if (flags) flags[i] = pi.flags;
+    if (hash) hash[i] = pi.hash;
+    if (nseg) nseg[i] = pi.nseg;
+  }
+  return 0;
+}
+
+// Forward + reverse-mode gradient.  The scalar loss is sum_i grad_rgb[i] . C_i.
+// dV [nv*3], d_eta [1], d_sigma [3] are overwritten.  rgb may be NULL.
+int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t n,
+                  const double* grad_rgb, double* rgb, double* dV, double* d_eta,
+                  double* d_sigma) {
+  if (!valid_scene(sc)) return 1;
+  Shared sh;
+  make_shared(sc, sh, true);
+  int nth = 1;
+#ifdef _OPENMP
+  nth = omp_get_max_threads();
+#endif
+  std::vector<std::vector<double>> accV(nth);
+  std::vector<double> accE(nth, 0.0), accS(3 * (size_t)nth, 0.0);
+#pragma omp parallel
+  {
+    int tid = 0;
+#ifdef _OPENMP
+    tid = omp_get_thread_num();
+#endif
+    accV[tid].assign(3 * (size_t)sc->nv, 0.0);
+    Tape tape;
+    g_tape = &tape;
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+      const double* g = grad_rgb + 3 * i;
+      tape.nodes.clear();
+      Ctx<Var> cx;
+      cx.sh = &sh;
+      cx.eta = leaf(sc->eta);
+      for (int k = 0; k < 3; ++k) cx.sigma[k] = leaf(sc->sigma[k]);
+      PathInfo pi;
+      double W[3] = {1, 1, 1};
+      V3<Var> oo{Var(o[3 * i]), Var(o[3 * i + 1]), Var(o[3 * i + 2])};
+      V3<Var> dd{Var(d[3 * i]), Var(d[3 * i + 1]), Var(d[3 * i + 2])};
+      V3<Var> L = trace<Var>(cx, oo, dd, -1, 0, W, false, pi, nullptr);
+      if (rgb) {
+        rgb[3 * i] = L.x.v;
+        rgb[3 * i + 1] = L.y.v;
+        rgb[3 * i + 2] = L.z.v;
+      }
+      if (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0) continue;
+      std::vector<double> adj(tape.nodes.size(), 0.0);
+      if (L.x.i >= 0) adj[L.x.i] += g[0];
+      if (L.y.i >= 0) adj[L.y.i] += g[1];
+      if (L.z.i >= 0) adj[L.z.i] += g[2];
+      for (int k = (int)tape.nodes.size() - 1; k >= 0; --k) {
+        double a = adj[k];
+        if (a == 0.0) continue;
+        const TapeNode& tn = tape.nodes[k];
+        if (tn.a >= 0) adj[tn.a] += tn.da * a;
+        if (tn.b >= 0) adj[tn.b] += tn.db * a;
+      }
+      accE[tid] += adj[cx.eta.i];
+      for (int k = 0; k < 3; ++k) accS[3 * tid + k] += adj[cx.sigma[k].i];
+      for (auto& kv : cx.P) {
+        double* dst = accV[tid].data() + 3 * (size_t)kv.first;
+        dst[0] += adj[kv.second.x.i];
+        dst[1] += adj[kv.second.y.i];
+        dst[2] += adj[kv.second.z.i];
+      }
+    }
+    g_tape = nullptr;
+  }
+  std::memset(dV, 0, sizeof(double) * 3 * (size_t)sc->nv);
+  *d_eta = 0.0;
+  d_sigma[0] = d_sigma[1] = d_sigma[2] = 0.0;
+  for (int t = 0; t < nth; ++t) {
+    if (accV[t].empty()) continue;
+    for (size_t j = 0; j < 3 * (size_t)sc->nv; ++j) dV[j] += accV[t][j];
+    *d_eta += accE[t];
+    for (int k = 0; k < 3; ++k) d_sigma[k] += accS[3 * t + k];
+  }
+  return 0;
+}
+
+// Dump the path tree of one camera ray in depth-first order (parent before
+// children, reflected child before refracted child).  Each record is
+// or_tree_record_doubles() doubles.  Returns the number of records in the
+// tree (only the first max_rec are written).
+int or_trace_tree(const or_scene* sc, const double* o, const double* d, double* out, int max_rec) {
+  if (!valid_scene(sc)) return -1;
+  Shared sh;
+  make_shared(sc, sh, true);
+  Ctx<double> cx{&sh, sc->eta, {sc->sigma[0], sc->sigma[1], sc->sigma[2]}};
+  PathInfo pi;
+  double W[3] = {1, 1, 1};
+  std::vector<TreeRec> tree;
+  trace<double>(cx, {o[0], o[1], o[2]}, {d[0], d[1], d[2]}, -1, 0, W, false, pi, &tree);
+  int k = std::min<int>((int)tree.size(), max_rec);
+  std::memcpy(out, tree.data(), sizeof(TreeRec) * (size_t)k);
+  return (int)tree.size();
+}
+
+int or_tree_record_doubles(void) { return (int)(sizeof(TreeRec) / sizeof(double)); }
+
+}  // extern "C"
