@@ -481,12 +481,14 @@ struct EnvOut {
   int cell_x, cell_y;  // discrete texel cell (for path signatures)
 };
 
-// Equirect lookup at a unit direction: phi = atan2(x, -z), theta = acos(y),
+// Equirect lookup at a direction (normalised first): phi = atan2(x, -z), theta = acos(y),
 // u = phi / 2pi + 1/2, v = theta / pi, texel coords (uW - 1/2, vH - 1/2),
 // bilinear, wrapping in u and clamping in v, row 0 at the zenith.
 template <class S>
-V3<S> env_equirect(const or_env& e, V3<S> d, EnvOut& eo) {
+V3<S> env_equirect(const or_env& e, V3<S> dir, EnvOut& eo) {
   const double PI = 3.14159265358979323846;
+  // the environment is a function of direction only
+  V3<S> d = normalize(dir);
   S y = d.y;
   if (val(y) > 1.0) y = S(1.0);
   if (val(y) < -1.0) y = S(-1.0);
@@ -521,8 +523,9 @@ V3<S> env_equirect(const or_env& e, V3<S> d, EnvOut& eo) {
 // and each post-ReLU activation are rounded to bfloat16; weights are given
 // already on the bfloat16 grid; biases and accumulation are FP64 here.
 template <class S>
-V3<S> env_mlp(const or_env& e, V3<S> d, EnvOut& eo) {
+V3<S> env_mlp(const or_env& e, V3<S> dir, EnvOut& eo) {
   const double PI = 3.14159265358979323846;
+  V3<S> d = normalize(dir);
   eo.cell_x = eo.cell_y = 0;
   std::vector<S> h((size_t)e.in_pad, S(0.0));
   S dc[3] = {d.x, d.y, d.z};
