@@ -1,0 +1,210 @@
+/*
+ * difftrans.h - C ABI of the MI355X recursive differentiable transparent-mesh
+ * ray tracer (libdifftrans.so, HIP for gfx950).
+ *
+ * The method (paper Sec. 3.2-3.3): each camera ray is traced through a closed
+ * triangle mesh of one transparent material.  At every surface hit it splits
+ * into a reflected ray (Eq. 3) and a refracted ray (Snell, Eq. 4-6) blended
+ * with the Fresnel weights R and T = 1 - R (Eq. 7-8); past the critical angle
+ * only the reflected ray survives (total internal reflection); a segment
+ * travelled inside the object is attenuated by exp(-sigma t) (Beer-Lambert,
+ * Eq. 9-11, constant RGB absorption rate); a ray that leaves the object takes
+ * the environment radiance of its direction.  The shading normal is the
+ * barycentric blend of vertex normals (Eq. 12), each the normalised mean of the
+ * unit normals of the faces around the vertex (Eq. 13).  The hit point is a
+ * differentiable function of the three vertices of the first triangle hit, so
+ * pixel losses back-propagate to vertex positions, the index of refraction and
+ * the absorption rate (the interior derivative with the discrete path - which
+ * triangles are hit, which splits are total internal reflections - held fixed).
+ *
+ * Conventions, for every call below:
+ *  - All array pointers are DEVICE pointers owned by the caller, unless a
+ *    comment says HOST.  The library never allocates device memory; every
+ *    buffer it needs is sized by a *_bytes query and passed in by the caller.
+ *  - Floating point arrays are float32, index arrays int32, row-major:
+ *    V [nv][3], F [nf][3] (counter-clockwise seen from outside, so the
+ *    geometric normal (v1-v0)x(v2-v0) points out), rgb [npix][3].
+ *  - Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  Argument checks happen on the host before anything is queued;
+ *    on a non-OK status nothing was queued.  Outputs are overwritten.
+ *  - The IoR and sigma live in device memory so an optimiser can update them
+ *    without a host synchronisation.
+ *  - Errors are returned as dt_status; dt_last_error() gives a thread-local
+ *    message for the last failing call on this thread.  No exceptions cross
+ *    the ABI.  Data problems found on the device (a ray that leaves the object
+ *    from inside, a shading normal on the wrong side, a full ray queue) are
+ *    reported per pixel in the optional `flags` output and in `stats`.
+ *  - The library keeps no global state besides that error string.
+ */
+#ifndef DIFFTRANS_H
+#define DIFFTRANS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dt_status;
+#define DT_OK 0
+#define DT_ERR_INVALID_ARGUMENT 1
+#define DT_ERR_WORKSPACE_TOO_SMALL 2
+#define DT_ERR_CAPACITY 3
+#define DT_ERR_HIP 4
+#define DT_ERR_UNSUPPORTED 5
+
+/* per-pixel flags (bit set if any node of the pixel's ray tree had it) */
+#define DT_FLAG_DEGEN 1     /* shading normal faced away; geometric normal used */
+#define DT_FLAG_LEAK 2      /* a ray inside the object left it without a hit */
+#define DT_FLAG_GRAZING 4   /* cos(theta_i) < 0.02 at some hit */
+#define DT_FLAG_TIRB 8      /* |1 - sin^2(theta_t)| < 1e-3 at some hit */
+#define DT_FLAG_TRUNC 16    /* some hit reached the depth cap */
+#define DT_FLAG_OVERFLOW 32 /* a child ray was dropped: ray queue full */
+#define DT_FLAG_STACK 64    /* BVH traversal stack overflowed (result invalid) */
+
+#define DT_MAX_DEPTH 16
+#define DT_STATS_LEN 40
+/* stats layout (int64, device): [0..DT_MAX_DEPTH] rays intersected in each
+ * generation, [32] total rays, [33] dropped children, [34] generations run,
+ * [35] BVH depth used by traversal.  Written by dt_trace_forward. */
+#define DT_STAT_TOTAL 32
+#define DT_STAT_DROPPED 33
+#define DT_STAT_GENERATIONS 34
+
+/* ------------------------------------------------------------------ mesh */
+
+/* Size of the caller-owned acceleration-structure blob and of the build
+ * workspace for a mesh of nv vertices and nf faces (nv >= 3, nf >= 1). */
+dt_status dt_bvh_bytes(int32_t nv, int32_t nf, size_t* bvh_bytes, size_t* ws_bytes);
+
+/* Build the scene acceleration data from V [nv][3] and F [nf][3]: unit face
+ * normals, vertex normals (Eq. 13: normalised sum of the unit normals of the
+ * incident faces, in ascending face order, zero-area faces skipped), and a
+ * linear BVH (63-bit Morton codes of face centroids, stable radix sort, binary
+ * radix tree with index tie-break, bottom-up box fit).  Call again whenever V
+ * changes.  Face indices must lie in [0, nv) (checked on the device only
+ * through DT_FLAG results, not here: the caller guarantees it). */
+dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, int32_t nf,
+                       void* bvh, size_t bvh_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* Copy the vertex normals held in a blob built for (nv, nf) to N [nv][3]. */
+dt_status dt_bvh_vertex_normals(const void* bvh, int32_t nv, int32_t nf, float* N, void* stream);
+
+/* ----------------------------------------------------------- environment */
+
+#define DT_ENV_EQUIRECT 0
+#define DT_ENV_MLP 1
+
+/* Environment radiance as a function of direction (the environment is at
+ * infinity).  EQUIRECT: texels [height][width][3], row 0 at the zenith (+y),
+ * phi = atan2(x, -z), theta = polar angle from +y, u = phi/2pi + 1/2,
+ * v = theta/pi, bilinear at texel coordinates (uW - 1/2, vH - 1/2), wrapping
+ * in u, clamping in v.  MLP: input [d, sin(2^k pi d), cos(2^k pi d)] for
+ * k < n_freq, zero-padded to in_pad (64); n_layers hidden layers of width
+ * `hidden` with ReLU; linear RGB head; bfloat16 weights ([out][in] row-major
+ * per layer, concatenated), float32 biases, bfloat16 activations, float32
+ * accumulation.  Directions need not be unit: they are normalised first. */
+typedef struct {
+  int32_t kind;
+  int32_t width, height;
+  const float* texels;
+  int32_t n_freq, n_layers, hidden, in_pad;
+  const uint16_t* weights;
+  const float* biases;
+} dt_env;
+
+/* rgb[i] = E(dirs[i]) for n directions (dirs, rgb: device [n][3]). */
+dt_status dt_env_query(const dt_env* env, const float* dirs, int64_t n, float* rgb,
+                       void* stream);
+
+/* grad_dirs[i] = (dE/dd)^T grad_rgb[i] (device [n][3] each). */
+dt_status dt_env_query_backward(const dt_env* env, const float* dirs, int64_t n,
+                                const float* grad_rgb, float* grad_dirs, void* stream);
+
+/* ------------------------------------------------------------- tracing */
+
+typedef struct {
+  const float* V;      /* [nv][3] */
+  int32_t nv;
+  const int32_t* F;    /* [nf][3] */
+  int32_t nf;
+  const void* bvh;     /* built by dt_build_bvh from this V, F */
+  const float* ior;    /* [1]  IoR of the object, ambient medium 1 */
+  const float* sigma;  /* [3]  RGB absorption per unit length */
+  const dt_env* env;   /* HOST struct describing device data */
+} dt_scene;
+
+typedef struct {
+  int32_t max_depth;          /* D in [0, 16]: generations 0..D are intersected,
+                                 a hit in generation D is truncated */
+  int32_t terminal_env;       /* 0: truncated hit contributes 0;
+                                 1: it contributes A * E(d) */
+  float t_eps;                /* minimum hit distance (1e-5) */
+  int32_t checkpoint_stride;  /* backward: store every k-th generation and
+                                 recompute the rest (1 = store all) */
+  int64_t queue_capacity;     /* max rays per generation >= 1
+                                 (0 = worst case n_rays * 2^g) */
+} dt_trace_params;
+
+/* Pinhole camera (HOST struct): right-handed, vertical FOV, image row 0 at
+ * the top, one ray through each pixel centre.  Pixel (x, y) of this camera
+ * is output pixel pixel_offset + y*width + x. */
+typedef struct {
+  float eye[3], target[3], up[3];
+  float fov_deg;
+  int32_t width, height;
+  int64_t pixel_offset;
+} dt_camera;
+
+#define DT_RAYS_EXPLICIT 0
+#define DT_RAYS_CAMERAS 1
+typedef struct {
+  int32_t kind;
+  int64_t n;                 /* EXPLICIT: number of rays = pixels */
+  const float* o;            /* EXPLICIT: origins [n][3] */
+  const float* d;            /* EXPLICIT: unit directions [n][3] */
+  int32_t n_cameras;         /* CAMERAS */
+  const dt_camera* cameras;  /* CAMERAS: HOST array */
+  int64_t n_pixels;          /* CAMERAS: size of the output pixel range */
+} dt_rays;
+
+/* Workspace and tape sizes for tracing n_rays camera rays against a mesh.
+ * The tape carries the forward state the backward needs: every generation
+ * when checkpoint_stride == 1, every k-th generation otherwise. */
+dt_status dt_trace_bytes(const dt_trace_params* p, int64_t n_rays, int32_t nv, int32_t nf,
+                         size_t* ws_bytes, size_t* tape_bytes);
+
+/* Forward render.  rgb [npix][3] (required), wtrunc [npix][3] (optional:
+ * accumulated weight of truncated rays), flags [npix] (optional), stats
+ * [DT_STATS_LEN] int64 (optional).  tape may be NULL for a forward-only
+ * render; when given it must be tape_bytes long and is later read by
+ * dt_trace_backward with the same scene, rays and params. */
+dt_status dt_trace_forward(const dt_scene* sc, const dt_rays* rays, const dt_trace_params* p,
+                           float* rgb, float* wtrunc, int32_t* flags, int64_t* stats,
+                           void* tape, size_t tape_bytes, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* Backward: given dLoss/drgb [npix][3], accumulate nothing and overwrite
+ * dV [nv][3], d_ior [1], d_sigma [3] with dLoss/d(V, ior, sigma).  Generations
+ * not stored on the tape are recomputed from the nearest stored one. */
+dt_status dt_trace_backward(const dt_scene* sc, const dt_rays* rays, const dt_trace_params* p,
+                            const float* grad_rgb, const void* tape, size_t tape_bytes,
+                            float* dV, float* d_ior, float* d_sigma, void* ws, size_t ws_bytes,
+                            void* stream);
+
+/* Closest hit of n rays (o, d [n][3], skip [n] = triangle to ignore or -1,
+ * may be NULL) with t > t_eps; ties in t go to the smaller triangle id.
+ * Outputs tri [n] (-1 = miss), t [n], b [n][2] (weights of v1 and v2).
+ * brute_force = 1 tests every triangle with the same predicate. */
+dt_status dt_intersect(const dt_scene* sc, const float* o, const float* d, const int32_t* skip,
+                       int64_t n, float t_eps, int32_t brute_force, int32_t* tri, float* t,
+                       float* b, void* stream);
+
+const char* dt_status_string(dt_status s);
+const char* dt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIFFTRANS_H */

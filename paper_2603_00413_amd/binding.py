@@ -1,0 +1,315 @@
+"""ctypes binding of libdifftrans.so (argument marshalling only).
+
+Every compute step runs in the HIP library; this module converts torch
+tensors (device memory, owned by the caller) into pointers, passes the current
+HIP stream, and turns non-OK status codes into exceptions.  The functions
+keep the C entry points' names.  Buffers the library needs (BVH blob,
+workspace, tape) are sized with the *_bytes queries and allocated here with
+torch, because the library itself never allocates.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdifftrans.so")
+
+DT_OK = 0
+FLAG_DEGEN, FLAG_LEAK, FLAG_GRAZING, FLAG_TIRB, FLAG_TRUNC, FLAG_OVERFLOW, FLAG_STACK = \
+    1, 2, 4, 8, 16, 32, 64
+MAX_DEPTH = 16
+STATS_LEN = 40
+STAT_TOTAL, STAT_DROPPED, STAT_GENERATIONS, STAT_BVH_DEPTH = 32, 33, 34, 35
+ENV_EQUIRECT, ENV_MLP = 0, 1
+RAYS_EXPLICIT, RAYS_CAMERAS = 0, 1
+
+
+class DTError(RuntimeError):
+    pass
+
+
+class _Env(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
+                ("texels", C.c_void_p), ("n_freq", C.c_int32), ("n_layers", C.c_int32),
+                ("hidden", C.c_int32), ("in_pad", C.c_int32), ("weights", C.c_void_p),
+                ("biases", C.c_void_p)]
+
+
+class _Scene(C.Structure):
+    _fields_ = [("V", C.c_void_p), ("nv", C.c_int32), ("F", C.c_void_p), ("nf", C.c_int32),
+                ("bvh", C.c_void_p), ("ior", C.c_void_p), ("sigma", C.c_void_p),
+                ("env", C.POINTER(_Env))]
+
+
+class _Params(C.Structure):
+    _fields_ = [("max_depth", C.c_int32), ("terminal_env", C.c_int32), ("t_eps", C.c_float),
+                ("checkpoint_stride", C.c_int32), ("queue_capacity", C.c_int64)]
+
+
+class _Camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3),
+                ("fov_deg", C.c_float), ("width", C.c_int32), ("height", C.c_int32),
+                ("pixel_offset", C.c_int64)]
+
+
+class _Rays(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int64), ("o", C.c_void_p), ("d", C.c_void_p),
+                ("n_cameras", C.c_int32), ("cameras", C.POINTER(_Camera)), ("n_pixels", C.c_int64)]
+
+
+_lib = None
+EXPORTS = ["dt_bvh_bytes", "dt_build_bvh", "dt_bvh_vertex_normals", "dt_env_query",
+           "dt_env_query_backward", "dt_trace_bytes", "dt_trace_forward", "dt_trace_backward",
+           "dt_intersect", "dt_status_string", "dt_last_error"]
+
+
+def load(path: str = LIB_PATH):
+    """Open the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise DTError(f"{path} is missing: build it with paper_2603_00413_amd/csrc/build.py "
+                      "(there is no fallback path)")
+    L = C.CDLL(path)
+    vp, sz, i32, i64 = C.c_void_p, C.POINTER(C.c_size_t), C.c_int32, C.c_int64
+    L.dt_bvh_bytes.argtypes = [i32, i32, sz, sz]
+    L.dt_build_bvh.argtypes = [vp, i32, vp, i32, vp, C.c_size_t, vp, C.c_size_t, vp]
+    L.dt_bvh_vertex_normals.argtypes = [vp, i32, i32, vp, vp]
+    L.dt_env_query.argtypes = [C.POINTER(_Env), vp, i64, vp, vp]
+    L.dt_env_query_backward.argtypes = [C.POINTER(_Env), vp, i64, vp, vp, vp]
+    L.dt_trace_bytes.argtypes = [C.POINTER(_Params), i64, i32, i32, sz, sz]
+    L.dt_trace_forward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params), vp, vp,
+                                   vp, vp, vp, C.c_size_t, vp, C.c_size_t, vp]
+    L.dt_trace_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params), vp, vp,
+                                    C.c_size_t, vp, vp, vp, vp, C.c_size_t, vp]
+    L.dt_intersect.argtypes = [C.POINTER(_Scene), vp, vp, vp, i64, C.c_float, i32, vp, vp, vp, vp]
+    L.dt_status_string.argtypes = [i32]
+    L.dt_status_string.restype = C.c_char_p
+    L.dt_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if not hasattr(L, name):
+            raise DTError(f"{path} does not export {name}")
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != DT_OK:
+        L = load()
+        raise DTError(f"{L.dt_status_string(st).decode()}: {L.dt_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_check(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise DTError("the HIP library takes device tensors only")
+        if t is not None and not t.is_contiguous():
+            raise DTError("tensors must be contiguous")
+
+
+def _bytes(n: int, device) -> torch.Tensor:
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------ mesh
+def dt_bvh_bytes(nv: int, nf: int):
+    a, b = C.c_size_t(), C.c_size_t()
+    _check(load().dt_bvh_bytes(nv, nf, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+class Mesh:
+    """Device mesh + its acceleration blob.  `build()` re-runs the device
+    build (normals + LBVH) after V changes."""
+
+    def __init__(self, V: torch.Tensor, F: torch.Tensor):
+        _dev_check(V, F)
+        assert V.dtype == torch.float32 and F.dtype == torch.int32
+        self.V, self.F = V, F
+        self.nv, self.nf = V.shape[0], F.shape[0]
+        nb, nw = dt_bvh_bytes(self.nv, self.nf)
+        self.blob = _bytes(nb, V.device)
+        self.ws = _bytes(nw, V.device)
+        self.build()
+
+    def build(self):
+        dt_build_bvh(self.V, self.F, self.blob, self.ws)
+        return self
+
+    def vertex_normals(self) -> torch.Tensor:
+        N = torch.empty_like(self.V)
+        _check(load().dt_bvh_vertex_normals(_ptr(self.blob), self.nv, self.nf, _ptr(N),
+                                            _stream(self.V.device)))
+        return N
+
+
+def dt_build_bvh(V, F, blob, ws):
+    _dev_check(V, F, blob, ws)
+    _check(load().dt_build_bvh(_ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(blob), blob.numel(),
+                               _ptr(ws), ws.numel(), _stream(V.device)))
+
+
+# ------------------------------------------------------------------ environment
+class Env:
+    """Equirect map [H, W, 3] float32 on the device."""
+
+    def __init__(self, texels: torch.Tensor):
+        _dev_check(texels)
+        assert texels.dtype == torch.float32 and texels.dim() == 3 and texels.shape[2] == 3
+        self.texels = texels
+        s = _Env()
+        s.kind = ENV_EQUIRECT
+        s.height, s.width = texels.shape[0], texels.shape[1]
+        s.texels = texels.data_ptr()
+        self.s = s
+
+
+def dt_env_query(env: Env, dirs: torch.Tensor) -> torch.Tensor:
+    _dev_check(dirs)
+    out = torch.empty_like(dirs)
+    _check(load().dt_env_query(C.byref(env.s), _ptr(dirs), dirs.shape[0], _ptr(out),
+                               _stream(dirs.device)))
+    return out
+
+
+def dt_env_query_backward(env: Env, dirs: torch.Tensor, grad_rgb: torch.Tensor) -> torch.Tensor:
+    _dev_check(dirs, grad_rgb)
+    out = torch.empty_like(dirs)
+    _check(load().dt_env_query_backward(C.byref(env.s), _ptr(dirs), dirs.shape[0], _ptr(grad_rgb),
+                                        _ptr(out), _stream(dirs.device)))
+    return out
+
+
+# ------------------------------------------------------------------ tracing
+@dataclass
+class Params:
+    max_depth: int = 4
+    terminal_env: bool = False
+    t_eps: float = 1e-5
+    checkpoint_stride: int = 1
+    queue_capacity: int = 0
+
+    def c(self) -> _Params:
+        p = _Params()
+        p.max_depth, p.terminal_env, p.t_eps = self.max_depth, int(self.terminal_env), self.t_eps
+        p.checkpoint_stride, p.queue_capacity = self.checkpoint_stride, int(self.queue_capacity)
+        return p
+
+
+class Rays:
+    """Explicit rays (o, d device [n,3]) or a list of synth.Camera-like objects."""
+
+    def __init__(self, o=None, d=None, cameras=None):
+        self._keep = []
+        r = _Rays()
+        if cameras is None:
+            _dev_check(o, d)
+            r.kind, r.n, r.o, r.d = RAYS_EXPLICIT, o.shape[0], o.data_ptr(), d.data_ptr()
+            self.n_rays = self.n_pixels = o.shape[0]
+            self._keep += [o, d]
+        else:
+            arr = (_Camera * len(cameras))()
+            off = 0
+            for i, c in enumerate(cameras):
+                for k in range(3):
+                    arr[i].eye[k], arr[i].target[k], arr[i].up[k] = c.eye[k], c.target[k], c.up[k]
+                arr[i].fov_deg, arr[i].width, arr[i].height = c.fov_deg, c.width, c.height
+                arr[i].pixel_offset = off
+                off += c.width * c.height
+            self._keep.append(arr)
+            r.kind, r.n_cameras, r.cameras, r.n_pixels = RAYS_CAMERAS, len(cameras), arr, off
+            self.n_rays = self.n_pixels = off
+        self.s = r
+
+
+class Scene:
+    """Mesh + device IoR [1] + device sigma [3] + environment."""
+
+    def __init__(self, mesh: Mesh, ior: torch.Tensor, sigma: torch.Tensor, env: Env):
+        _dev_check(ior, sigma)
+        self.mesh, self.ior, self.sigma, self.env = mesh, ior, sigma, env
+
+    def c(self) -> _Scene:
+        s = _Scene()
+        m = self.mesh
+        s.V, s.nv, s.F, s.nf = m.V.data_ptr(), m.nv, m.F.data_ptr(), m.nf
+        s.bvh, s.ior, s.sigma = m.blob.data_ptr(), self.ior.data_ptr(), self.sigma.data_ptr()
+        s.env = C.pointer(self.env.s)
+        return s
+
+
+def dt_trace_bytes(params: Params, n_rays: int, nv: int, nf: int):
+    a, b = C.c_size_t(), C.c_size_t()
+    _check(load().dt_trace_bytes(C.byref(params.c()), n_rays, nv, nf, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+class Buffers:
+    """Workspace + tape sized for (params, rays, mesh); reusable across calls."""
+
+    def __init__(self, params: Params, rays: Rays, mesh: Mesh, tape: bool):
+        self.ws_bytes, self.tape_bytes = dt_trace_bytes(params, rays.n_rays, mesh.nv, mesh.nf)
+        dev = mesh.V.device
+        self.ws = _bytes(self.ws_bytes, dev)
+        self.tape = _bytes(self.tape_bytes, dev) if tape else None
+        self.stats = torch.zeros(STATS_LEN, dtype=torch.int64, device=dev)
+
+
+def dt_trace_forward(scene: Scene, rays: Rays, params: Params, buf: Buffers,
+                     want_aux: bool = True):
+    """Returns (rgb [npix,3], wtrunc [npix,3] or None, flags [npix] or None)."""
+    dev = scene.mesh.V.device
+    npix = rays.n_pixels
+    rgb = torch.empty(npix, 3, dtype=torch.float32, device=dev)
+    wtrunc = torch.empty(npix, 3, dtype=torch.float32, device=dev) if want_aux else None
+    flags = torch.empty(npix, dtype=torch.int32, device=dev) if want_aux else None
+    sc, p = scene.c(), params.c()
+    tape = buf.tape
+    _check(load().dt_trace_forward(C.byref(sc), C.byref(rays.s), C.byref(p), _ptr(rgb), _ptr(wtrunc),
+                                   _ptr(flags), _ptr(buf.stats), _ptr(tape),
+                                   0 if tape is None else tape.numel(), _ptr(buf.ws), buf.ws.numel(),
+                                   _stream(dev)))
+    return rgb, wtrunc, flags
+
+
+def dt_trace_backward(scene: Scene, rays: Rays, params: Params, buf: Buffers,
+                      grad_rgb: torch.Tensor):
+    """Returns (dV [nv,3], d_ior [1], d_sigma [3]) for the last forward on buf."""
+    if buf.tape is None:
+        raise DTError("the forward pass was run without a tape")
+    _dev_check(grad_rgb)
+    dev = scene.mesh.V.device
+    dV = torch.empty(scene.mesh.nv, 3, dtype=torch.float32, device=dev)
+    d_ior = torch.empty(1, dtype=torch.float32, device=dev)
+    d_sigma = torch.empty(3, dtype=torch.float32, device=dev)
+    sc, p = scene.c(), params.c()
+    _check(load().dt_trace_backward(C.byref(sc), C.byref(rays.s), C.byref(p), _ptr(grad_rgb),
+                                    _ptr(buf.tape), buf.tape.numel(), _ptr(dV), _ptr(d_ior),
+                                    _ptr(d_sigma), _ptr(buf.ws), buf.ws.numel(), _stream(dev)))
+    return dV, d_ior, d_sigma
+
+
+def dt_intersect(scene: Scene, o, d, skip=None, t_eps: float = 1e-5, brute_force: bool = False):
+    _dev_check(o, d, skip)
+    n = o.shape[0]
+    dev = o.device
+    tri = torch.empty(n, dtype=torch.int32, device=dev)
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    b = torch.empty(n, 2, dtype=torch.float32, device=dev)
+    sc = scene.c()
+    _check(load().dt_intersect(C.byref(sc), _ptr(o), _ptr(d), _ptr(skip), n, t_eps,
+                               int(brute_force), _ptr(tri), _ptr(t), _ptr(b), _stream(dev)))
+    return tri, t, b

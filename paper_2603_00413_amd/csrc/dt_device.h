@@ -1,0 +1,395 @@
+// Device functions of the tracer: closest-hit traversal, environment lookup,
+// and the shading step (classification, shading normal, Snell / TIR, Fresnel,
+// absorption) shared by the forward kernels and the adjoint.
+#pragma once
+
+#include "dt_internal.h"
+
+#define DT_PI 3.14159265358979323846f
+
+// ------------------------------------------------------------------ device views
+struct EnvDev {
+  int kind, W, H;
+  const float* tex;
+  int n_freq, n_layers, hidden, in_pad;
+  const uint16_t* w;
+  const float* b;
+};
+
+struct SceneDev {
+  const float* V;
+  const int32_t* F;
+  int nv, nf;
+  BvhView bvh;
+  const float* ior;
+  const float* sigma;
+  EnvDev env;
+  int max_depth, terminal_env;
+  float t_eps;
+};
+
+// ------------------------------------------------------------------ environment (equirect)
+// Texel lookup at a direction (normalised here): phi = atan2(x, -z),
+// theta = polar angle from +y (computed as atan2(sqrt(x^2+z^2), y), which is
+// acos(y) for a unit direction but well conditioned at the poles),
+// texel coordinates (uW - 1/2, vH - 1/2) with u = phi/2pi + 1/2, v = theta/pi;
+// bilinear, wrap in u, clamp in v.
+struct EquirectTap {
+  int x0, x1, y0, y1;
+  float fx, fy;
+  float dphi_dd[3], dth_dd[3];
+};
+
+__device__ __forceinline__ void equirect_tap(const EnvDev& e, v3 d, EquirectTap& tp, bool grad) {
+  float rho2 = d.x * d.x + d.z * d.z;
+  float rho = sqrtf(rho2);
+  float phi = atan2f(d.x, -d.z);
+  float th = atan2f(rho, d.y);
+  float x = (phi * (0.5f / DT_PI) + 0.5f) * (float)e.W - 0.5f;
+  float y = th * (1.0f / DT_PI) * (float)e.H - 0.5f;
+  if (!(x > -2.0f && x < (float)e.W + 1.0f)) x = 0.0f;  // NaN direction
+  if (!(y > -2.0f && y < (float)e.H + 1.0f)) y = 0.0f;
+  float xf = floorf(x), yf = floorf(y);
+  tp.fx = x - xf;
+  tp.fy = y - yf;
+  int xi = (int)xf, yi = (int)yf;
+  tp.x0 = ((xi % e.W) + e.W) % e.W;
+  tp.x1 = (tp.x0 + 1 == e.W) ? 0 : tp.x0 + 1;
+  tp.y0 = min(max(yi, 0), e.H - 1);
+  tp.y1 = min(max(yi + 1, 0), e.H - 1);
+  if (grad) {
+    // d phi / d d, d theta / d d (both independent of |d|)
+    float r2 = d.x * d.x + d.y * d.y + d.z * d.z;
+    float ip = rho2 > 0.f ? 1.0f / rho2 : 0.f;
+    tp.dphi_dd[0] = -d.z * ip;
+    tp.dphi_dd[1] = 0.f;
+    tp.dphi_dd[2] = d.x * ip;
+    float ir = rho > 0.f ? 1.0f / (rho * r2) : 0.f;
+    tp.dth_dd[0] = d.x * d.y * ir;
+    tp.dth_dd[1] = -rho / r2;
+    tp.dth_dd[2] = d.z * d.y * ir;
+    // clamping in v makes the lookup constant in theta outside the centres
+    if (yi < 0 || yi + 1 > e.H - 1) tp.dth_dd[0] = tp.dth_dd[1] = tp.dth_dd[2] = 0.f;
+  }
+}
+
+__device__ __forceinline__ v3 texel(const EnvDev& e, int y, int x) {
+  const float* p = e.tex + ((size_t)y * e.W + x) * 3;
+  return mk3(p[0], p[1], p[2]);
+}
+
+__device__ __forceinline__ v3 env_equirect(const EnvDev& e, v3 d) {
+  EquirectTap tp;
+  equirect_tap(e, d, tp, false);
+  v3 t00 = texel(e, tp.y0, tp.x0), t01 = texel(e, tp.y0, tp.x1);
+  v3 t10 = texel(e, tp.y1, tp.x0), t11 = texel(e, tp.y1, tp.x1);
+  float gx = 1.f - tp.fx, gy = 1.f - tp.fy;
+  return t00 * (gx * gy) + t01 * (tp.fx * gy) + t10 * (gx * tp.fy) + t11 * (tp.fx * tp.fy);
+}
+
+// value and dE/dd^T g (g: upstream adjoint of the RGB value)
+__device__ __forceinline__ v3 env_equirect_grad(const EnvDev& e, v3 d, v3 g, v3* dd) {
+  EquirectTap tp;
+  equirect_tap(e, d, tp, true);
+  v3 t00 = texel(e, tp.y0, tp.x0), t01 = texel(e, tp.y0, tp.x1);
+  v3 t10 = texel(e, tp.y1, tp.x0), t11 = texel(e, tp.y1, tp.x1);
+  float gx = 1.f - tp.fx, gy = 1.f - tp.fy;
+  v3 E = t00 * (gx * gy) + t01 * (tp.fx * gy) + t10 * (gx * tp.fy) + t11 * (tp.fx * tp.fy);
+  v3 dEdfx = (t01 - t00) * gy + (t11 - t10) * tp.fy;
+  v3 dEdfy = (t10 - t00) * gx + (t11 - t01) * tp.fx;
+  float sx = dot(g, dEdfx) * ((float)e.W * (0.5f / DT_PI));
+  float sy = dot(g, dEdfy) * ((float)e.H / DT_PI);
+  *dd = mk3(sx * tp.dphi_dd[0] + sy * tp.dth_dd[0], sx * tp.dphi_dd[1] + sy * tp.dth_dd[1],
+            sx * tp.dphi_dd[2] + sy * tp.dth_dd[2]);
+  return E;
+}
+
+// ------------------------------------------------------------------ closest hit
+struct Hit {
+  float t, b1, b2;
+  int tri;  // original triangle id, -1 = miss
+};
+
+struct RayPre {
+  v3 o, d;
+  v3 inv;  // reciprocal direction (zero components replaced by a tiny value)
+  int kx, ky, kz;
+  float Sx, Sy, Sz;
+};
+
+__device__ __forceinline__ float safe_rcp(float x) {
+  const float tiny = 1e-30f;
+  float y = fabsf(x) < tiny ? copysignf(tiny, x) : x;
+  return 1.0f / y;
+}
+
+__device__ __forceinline__ RayPre ray_pre(v3 o, v3 d) {
+  RayPre r;
+  r.o = o;
+  r.d = d;
+  r.inv = mk3(safe_rcp(d.x), safe_rcp(d.y), safe_rcp(d.z));
+  float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+  int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+  int kx = kz == 2 ? 0 : kz + 1;
+  int ky = kx == 2 ? 0 : kx + 1;
+  if (comp(d, kz) < 0.f) {
+    int t = kx;
+    kx = ky;
+    ky = t;
+  }
+  r.kx = kx;
+  r.ky = ky;
+  r.kz = kz;
+  float dz = comp(d, kz);
+  r.Sx = comp(d, kx) / dz;
+  r.Sy = comp(d, ky) / dz;
+  r.Sz = 1.0f / dz;
+  return r;
+}
+
+// Watertight ray/triangle test (shear to ray space, signed edge functions,
+// FP64 recomputation of edge functions that come out exactly zero); edges
+// inclusive, no back-face culling.  Accepts t in (t_eps, tbest]; equal t is
+// decided by the triangle id (smaller wins).
+__device__ __forceinline__ bool tri_test(const RayPre& r, v3 a, v3 b, v3 c, int tri, float t_eps,
+                                         Hit& h) {
+  v3 A = a - r.o, B = b - r.o, C = c - r.o;
+  float Az = comp(A, r.kz), Bz = comp(B, r.kz), Cz = comp(C, r.kz);
+  float Ax = comp(A, r.kx) - r.Sx * Az, Ay = comp(A, r.ky) - r.Sy * Az;
+  float Bx = comp(B, r.kx) - r.Sx * Bz, By = comp(B, r.ky) - r.Sy * Bz;
+  float Cx = comp(C, r.kx) - r.Sx * Cz, Cy = comp(C, r.ky) - r.Sy * Cz;
+  float U = Cx * By - Cy * Bx;
+  float V = Ax * Cy - Ay * Cx;
+  float W = Bx * Ay - By * Ax;
+  if (U == 0.f || V == 0.f || W == 0.f) {
+    U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+    V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+    W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+  }
+  if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return false;
+  float det = U + V + W;
+  if (det == 0.f) return false;
+  float T = U * (r.Sz * Az) + V * (r.Sz * Bz) + W * (r.Sz * Cz);
+  float t = T / det;
+  if (!(t > t_eps)) return false;
+  if (h.tri >= 0 && (t > h.t || (t == h.t && tri > h.tri))) return false;
+  float inv = 1.0f / det;
+  h.t = t;
+  h.b1 = V * inv;
+  h.b2 = W * inv;
+  h.tri = tri;
+  return true;
+}
+
+// robust slab test against one child box; returns entry distance or +inf
+__device__ __forceinline__ float box_enter(const RayPre& r, float lx, float ly, float lz, float hx,
+                                           float hy, float hz, float tmax) {
+  float t0x = (lx - r.o.x) * r.inv.x, t1x = (hx - r.o.x) * r.inv.x;
+  float t0y = (ly - r.o.y) * r.inv.y, t1y = (hy - r.o.y) * r.inv.y;
+  float t0z = (lz - r.o.z) * r.inv.z, t1z = (hz - r.o.z) * r.inv.z;
+  float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+  float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+  // widen by a few ulps so that a box is never rejected for a triangle the
+  // triangle test would accept (equal-t ties included)
+  tf *= 1.0000005f;
+  return tn <= tf ? tn : INFINITY;
+}
+
+#define DT_STACK 64
+
+// Closest hit with an LDS stack: stk points at this lane's column
+// (stride = blockDim.x entries).  Sets *overflow if the stack would overflow.
+__device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int skip, float t_eps,
+                                           uint32_t* stk, int stride, bool* overflow) {
+  Hit h;
+  h.tri = -1;
+  h.t = INFINITY;
+  h.b1 = h.b2 = 0.f;
+  RayPre r = ray_pre(o, d);
+  const float4* L = bv.leaves;
+  if (bv.nf == 1) {
+    int f = __float_as_int(L[0].w);
+    if (f != skip) tri_test(r, xyz(L[0]), xyz(L[1]), xyz(L[2]), f, t_eps, h);
+    return h;
+  }
+  int sp = 0;
+  uint32_t node = 0;
+  // a depth-first walk visits each of the nf - 1 internal nodes at most once
+  for (int guard = 0; guard < bv.nf + 64; ++guard) {
+    if (node >= (uint32_t)(bv.nf - 1)) {
+      *overflow = true;
+      break;
+    }
+    const BvhNode& n = bv.nodes[node];
+    float4 a = n.a, b = n.b, c = n.c;
+    int4 ch = n.d;
+    float tmax = h.tri >= 0 ? h.t : INFINITY;
+    float t0 = box_enter(r, a.x, a.y, a.z, a.w, b.x, b.y, tmax);
+    float t1 = box_enter(r, b.z, b.w, c.x, c.y, c.z, c.w, tmax);
+    uint32_t c0 = (uint32_t)ch.x, c1 = (uint32_t)ch.y;
+    // leaves are tested right away
+    if (t0 != INFINITY && (c0 & DT_LEAF_BIT)) {
+      uint32_t j = min(c0 & ~DT_LEAF_BIT, (uint32_t)(bv.nf - 1));
+      int f = __float_as_int(L[3 * j].w);
+      if (f != skip) tri_test(r, xyz(L[3 * j]), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), f, t_eps, h);
+      t0 = INFINITY;
+    }
+    if (t1 != INFINITY && (c1 & DT_LEAF_BIT)) {
+      uint32_t j = min(c1 & ~DT_LEAF_BIT, (uint32_t)(bv.nf - 1));
+      int f = __float_as_int(L[3 * j].w);
+      if (f != skip) tri_test(r, xyz(L[3 * j]), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), f, t_eps, h);
+      t1 = INFINITY;
+    }
+    bool h0 = t0 != INFINITY, h1 = t1 != INFINITY;
+    if (h0 && h1) {
+      uint32_t nearc = t0 <= t1 ? c0 : c1, farc = t0 <= t1 ? c1 : c0;
+      if (sp < DT_STACK) {
+        stk[sp * stride] = farc;
+        ++sp;
+      } else {
+        *overflow = true;
+      }
+      node = nearc;
+      continue;
+    }
+    if (h0) {
+      node = c0;
+      continue;
+    }
+    if (h1) {
+      node = c1;
+      continue;
+    }
+    if (sp == 0) break;
+    --sp;
+    node = stk[sp * stride];
+  }
+  return h;
+}
+
+// brute force over every triangle with the same predicate
+__device__ __forceinline__ Hit closest_brute(const BvhView& bv, v3 o, v3 d, int skip, float t_eps) {
+  Hit h;
+  h.tri = -1;
+  h.t = INFINITY;
+  h.b1 = h.b2 = 0.f;
+  RayPre r = ray_pre(o, d);
+  const float4* L = bv.leaves;
+  for (int j = 0; j < bv.nf; ++j) {
+    int f = __float_as_int(L[3 * j].w);
+    if (f == skip) continue;
+    tri_test(r, xyz(L[3 * j]), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), f, t_eps, h);
+  }
+  return h;
+}
+
+// ------------------------------------------------------------------ shading
+// decision bits stored per ray (forward) and re-used by emit / adjoint
+#define C_HIT 1u
+#define C_ENTER 2u
+#define C_TIR 4u
+#define C_DEGEN 8u
+#define C_TRUNC 16u
+#define C_HAS_R 32u
+#define C_HAS_T 64u
+#define C_GRAZE 128u
+#define C_TIRB 256u
+
+struct HitGeo {
+  int i0, i1, i2;
+  v3 p0, p1, p2;
+  v3 n0, n1, n2;
+};
+
+__device__ __forceinline__ int vclampi(int i, int nv) { return i < 0 ? 0 : (i >= nv ? nv - 1 : i); }
+
+__device__ __forceinline__ HitGeo load_geo(const SceneDev& sc, int tri) {
+  HitGeo g;
+  tri = tri < 0 ? 0 : (tri >= sc.nf ? sc.nf - 1 : tri);
+  g.i0 = vclampi(sc.F[3 * tri], sc.nv);
+  g.i1 = vclampi(sc.F[3 * tri + 1], sc.nv);
+  g.i2 = vclampi(sc.F[3 * tri + 2], sc.nv);
+  g.p0 = load3(sc.V + 3 * g.i0);
+  g.p1 = load3(sc.V + 3 * g.i1);
+  g.p2 = load3(sc.V + 3 * g.i2);
+  g.n0 = xyz(sc.bvh.vn[g.i0]);
+  g.n1 = xyz(sc.bvh.vn[g.i1]);
+  g.n2 = xyz(sc.bvh.vn[g.i2]);
+  return g;
+}
+
+struct Shade {
+  v3 x;        // hit point (child origin)
+  v3 n;        // oriented unit normal (against the incident ray)
+  v3 m;        // unnormalised interpolated normal (smooth case)
+  float cos_i;
+  float eta, eta_i, eta_t, eta_r;
+  float sin2t, cos_t;
+  float rs, rp, R, T;
+  v3 A;        // attenuation over the segment just travelled
+  v3 ur, ut;   // unnormalised child directions
+  v3 dr, dt;   // unit child directions
+  uint32_t code;
+};
+
+// Paper Sec. 3.2-3.3.  `code_in` (when nonzero) supplies the discrete
+// decisions recorded by the forward pass so that every later recomputation
+// takes the same branches.
+__device__ __forceinline__ Shade shade(const SceneDev& sc, const HitGeo& g, v3 o, v3 d, float t,
+                                       float b1, float b2, uint32_t code_in) {
+  Shade s;
+  s.x = o + d * t;
+  v3 ng = cross(g.p1 - g.p0, g.p2 - g.p0);
+  bool entering = code_in ? (code_in & C_ENTER) != 0u : dot(d, ng) < 0.f;
+  float b0 = 1.f - b1 - b2;
+  s.m = g.n0 * b0 + g.n1 * b1 + g.n2 * b2;
+  v3 n = normalize3(s.m);
+  if (!entering) n = -n;
+  float ci = -dot(d, n);
+  bool degen = code_in ? (code_in & C_DEGEN) != 0u : !(ci > 0.f);
+  if (degen) {
+    n = normalize3(ng);
+    if (!entering) n = -n;
+    ci = -dot(d, n);
+  }
+  s.n = n;
+  s.cos_i = ci;
+  s.eta = sc.ior[0];
+  s.eta_i = entering ? 1.f : s.eta;
+  s.eta_t = entering ? s.eta : 1.f;
+  s.eta_r = s.eta_t / s.eta_i;
+  if (entering) {
+    s.A = mk3(1.f, 1.f, 1.f);
+  } else {
+    s.A = mk3(expf(-sc.sigma[0] * t), expf(-sc.sigma[1] * t), expf(-sc.sigma[2] * t));
+  }
+  s.sin2t = (1.f - ci * ci) / (s.eta_r * s.eta_r);
+  bool tir = code_in ? (code_in & C_TIR) != 0u : s.sin2t > 1.f;
+  s.ur = d + n * (2.f * ci);
+  s.dr = normalize3(s.ur);
+  if (tir) {
+    s.cos_t = 0.f;
+    s.rs = s.rp = 1.f;
+    s.R = 1.f;
+    s.T = 0.f;
+    s.ut = s.dt = mk3(0.f, 0.f, 0.f);
+  } else {
+    s.cos_t = sqrtf(fmaxf(1.f - s.sin2t, 0.f));
+    float a = s.eta_i * ci, b = s.eta_t * s.cos_t;
+    float c = s.eta_i * s.cos_t, e = s.eta_t * ci;
+    s.rs = (a - b) / (a + b);
+    s.rp = (c - e) / (c + e);
+    s.R = 0.5f * (s.rs * s.rs + s.rp * s.rp);
+    s.T = 1.f - s.R;
+    s.ut = d * (1.f / s.eta_r) + n * (ci / s.eta_r - s.cos_t);
+    s.dt = normalize3(s.ut);
+  }
+  uint32_t code = C_HIT;
+  if (entering) code |= C_ENTER;
+  if (tir) code |= C_TIR;
+  if (degen) code |= C_DEGEN;
+  if (ci < 0.02f) code |= C_GRAZE;
+  if (fabsf(1.f - s.sin2t) < 1e-3f) code |= C_TIRB;
+  s.code = code;
+  return s;
+}

@@ -1,0 +1,1114 @@
+// Wavefront recursive tracer (forward and adjoint) on the device.
+//
+// Rays are processed one generation at a time (generation g = rays created by
+// g surface interactions; camera rays are generation 0).  Per generation:
+//   k_trace : closest hit + shading decisions for every ray of the queue;
+//             misses add W * E(d) to their pixel; counts of the children
+//             each chunk of the queue will emit are accumulated.
+//   k_scan  : exclusive scan of the per-chunk child counts.
+//   k_emit  : every ray writes its reflected / refracted child into the next
+//             queue at its scanned position (stable: the order of generation
+//             g+1 is a pure function of generation g, so a recomputation
+//             reproduces it bit for bit).
+// The adjoint walks the generations backwards, each node gathering the
+// subtree radiance and ray adjoints of its (at most two) children.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "dt_device.h"
+
+namespace {
+
+constexpr int TB = 64;                // threads per block of the traversal kernel (one wave)
+constexpr int CHUNK = 2048;           // rays per compaction chunk
+constexpr int EB = 256;               // threads per block of the emit kernel
+constexpr int AB = 256;               // threads per block of the adjoint kernel
+constexpr uint32_t RAY_INSIDE = 1u;   // ray flag: travelling inside the object
+
+struct Gen {
+  float4 *o, *d, *w, *hit;  // origin+skip, dir+pixel, weight+flags, (t, tri, b1, b2)
+  uint32_t* code;
+  int2* child;
+};
+
+struct Counters {
+  uint32_t count[DT_MAX_DEPTH + 2];
+  uint32_t nrefl[DT_MAX_DEPTH + 2];
+  uint32_t work[DT_MAX_DEPTH + 2];
+  uint32_t dropped;
+  uint32_t pad[3];
+};
+
+struct Adj {
+  float4 *L, *O, *D;  // subtree radiance, d loss / d origin, d loss / d direction
+};
+
+// ------------------------------------------------------------------ plan
+struct Plan {
+  int D, k;
+  int64_t N, npix;
+  int64_t cap[DT_MAX_DEPTH + 2];
+  int64_t maxcap, maxchunks;
+  bool store_all;
+  // tape
+  size_t tape_hdr;
+  size_t t_o[DT_MAX_DEPTH + 1], t_d[DT_MAX_DEPTH + 1], t_w[DT_MAX_DEPTH + 1];
+  size_t t_hit[DT_MAX_DEPTH + 1], t_code[DT_MAX_DEPTH + 1], t_child[DT_MAX_DEPTH + 1];
+  size_t tape_bytes;
+  // workspace
+  size_t w_ctr, w_part0, w_part1;
+  size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
+  size_t w_adj[2][3];
+  size_t w_dN, w_sbar;
+  size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
+  size_t ws_bytes;
+};
+
+bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t nv, Plan& P) {
+  P.D = p->max_depth;
+  P.k = p->checkpoint_stride < 1 ? 1 : p->checkpoint_stride;
+  if (P.k > P.D + 1) P.k = P.D + 1;
+  P.store_all = P.k == 1;
+  P.N = n_rays;
+  P.npix = npix;
+  int64_t capu = p->queue_capacity;
+  P.maxcap = 1;
+  for (int g = 0; g <= DT_MAX_DEPTH + 1; ++g) {
+    int64_t worst = g <= 40 ? (n_rays << (g > 30 ? 30 : g)) : INT64_MAX;
+    int64_t c = g == 0 ? n_rays : (capu > 0 && capu < worst ? capu : worst);
+    if (c > (int64_t)0x7fffffff) c = 0x7fffffff;
+    if (c < 1) c = 1;
+    P.cap[g] = c;
+    if (g <= P.D && c > P.maxcap) P.maxcap = c;
+  }
+  P.maxchunks = (P.maxcap + CHUNK - 1) / CHUNK;
+  // tape
+  size_t o = 0;
+  P.tape_hdr = o;
+  o = dt_align(o + sizeof(Counters));
+  for (int g = 0; g <= DT_MAX_DEPTH; ++g) {
+    P.t_o[g] = P.t_d[g] = P.t_w[g] = P.t_hit[g] = P.t_code[g] = P.t_child[g] = (size_t)-1;
+  }
+  for (int g = 0; g <= P.D; ++g) {
+    bool stored = P.store_all || (g % P.k) == 0;
+    if (!stored) continue;
+    size_t c = (size_t)P.cap[g];
+    P.t_o[g] = o;
+    o = dt_align(o + 16 * c);
+    P.t_d[g] = o;
+    o = dt_align(o + 16 * c);
+    P.t_w[g] = o;
+    o = dt_align(o + 16 * c);
+    if (P.store_all) {
+      P.t_hit[g] = o;
+      o = dt_align(o + 16 * c);
+      P.t_code[g] = o;
+      o = dt_align(o + 4 * c);
+      P.t_child[g] = o;
+      o = dt_align(o + 8 * c);
+    }
+  }
+  P.tape_bytes = o;
+  // workspace
+  size_t mc = (size_t)P.maxcap;
+  o = 0;
+  P.w_ctr = o;
+  o = dt_align(o + sizeof(Counters));
+  P.w_part0 = o;
+  o = dt_align(o + 8 * ((size_t)P.maxchunks + 1));
+  P.w_part1 = o;
+  o = dt_align(o + 8 * ((size_t)P.maxchunks + 1));
+  for (int b = 0; b < 2; ++b) {
+    P.w_ro[b] = o;
+    o = dt_align(o + 16 * mc);
+    P.w_rd[b] = o;
+    o = dt_align(o + 16 * mc);
+    P.w_rw[b] = o;
+    o = dt_align(o + 16 * mc);
+  }
+  P.w_hit = o;
+  o = dt_align(o + 16 * mc);
+  P.w_code = o;
+  o = dt_align(o + 4 * mc);
+  for (int b = 0; b < 2; ++b)
+    for (int j = 0; j < 3; ++j) {
+      P.w_adj[b][j] = o;
+      o = dt_align(o + 16 * mc);
+    }
+  P.w_dN = o;
+  o = dt_align(o + 12 * (size_t)nv);
+  P.w_sbar = o;
+  o = dt_align(o + 16 * (size_t)nv);
+  size_t kk = P.store_all ? 0 : (size_t)P.k;
+  P.w_seg_o = o;
+  o = dt_align(o + 16 * mc * kk);
+  P.w_seg_d = o;
+  o = dt_align(o + 16 * mc * kk);
+  P.w_seg_w = o;
+  o = dt_align(o + 16 * mc * kk);
+  P.w_seg_hit = o;
+  o = dt_align(o + 16 * mc * kk);
+  P.w_seg_code = o;
+  o = dt_align(o + 4 * mc * kk);
+  P.w_seg_child = o;
+  o = dt_align(o + 8 * mc * kk);
+  P.ws_bytes = o;
+  return true;
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_zero_f32(float* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+__global__ void k_init_counters(Counters* c, uint32_t n0) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int g = 0; g < DT_MAX_DEPTH + 2; ++g) {
+      c->count[g] = 0;
+      c->nrefl[g] = 0;
+      c->work[g] = 0;
+    }
+    c->count[0] = n0;
+    c->dropped = 0;
+  }
+}
+
+__global__ void k_load_counters(Counters* c, const Counters* src) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *c = *src;
+    for (int g = 0; g < DT_MAX_DEPTH + 2; ++g) c->work[g] = 0;
+  }
+}
+
+__global__ void k_save_counters(Counters* dst, const Counters* c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *c;
+}
+
+__global__ void k_reset_work(Counters* c, int g) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) c->work[g] = 0;
+}
+
+__global__ void k_stats(const Counters* c, int D, const BvhHeader* hdr, int64_t* stats) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int64_t tot = 0, gens = 0;
+    for (int i = 0; i < DT_STATS_LEN; ++i) stats[i] = 0;
+    for (int g = 0; g <= D; ++g) {
+      stats[g] = c->count[g];
+      tot += c->count[g];
+      if (c->count[g]) gens = g + 1;
+    }
+    stats[DT_STAT_TOTAL] = tot;
+    stats[DT_STAT_DROPPED] = c->dropped;
+    stats[DT_STAT_GENERATIONS] = gens;
+    stats[35] = hdr->depth;
+  }
+}
+
+// ------------------------------------------------------------------ ray generation (a3)
+struct CamDev {
+  float eye[3], f[3], r[3], u[3];
+  float th, aspect;
+  int W, H;
+  int64_t pixel_offset, base;
+  int tiled;
+};
+
+// Pinhole camera rays through pixel centres; 8x8 pixel tiles are laid out
+// consecutively in the queue so that a wave starts on a coherent patch.
+__global__ void k_raygen(Gen q, CamDev c) {
+  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t n = (int64_t)c.W * c.H;
+  if (r >= n) return;
+  int x, y;
+  if (c.tiled) {
+    int64_t tile = r >> 6;
+    int s = (int)(r & 63);
+    int tx = (int)(tile % (c.W >> 3)), ty = (int)(tile / (c.W >> 3));
+    x = tx * 8 + (s & 7);
+    y = ty * 8 + (s >> 3);
+  } else {
+    x = (int)(r % c.W);
+    y = (int)(r / c.W);
+  }
+  float px = (2.0f * ((float)x + 0.5f) / (float)c.W - 1.0f) * c.th * c.aspect;
+  float py = (1.0f - 2.0f * ((float)y + 0.5f) / (float)c.H) * c.th;
+  v3 f = mk3(c.f[0], c.f[1], c.f[2]), rt = mk3(c.r[0], c.r[1], c.r[2]), up = mk3(c.u[0], c.u[1], c.u[2]);
+  v3 d = normalize3(f + rt * px + up * py);
+  int64_t i = c.base + r;
+  int pix = (int)(c.pixel_offset + (int64_t)y * c.W + x);
+  q.o[i] = make_float4(c.eye[0], c.eye[1], c.eye[2], __int_as_float(-1));
+  q.d[i] = make_float4(d.x, d.y, d.z, __int_as_float(pix));
+  q.w[i] = make_float4(1.f, 1.f, 1.f, __int_as_float(0));
+}
+
+__global__ void k_rays_explicit(Gen q, const float* o, const float* d, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  q.o[i] = make_float4(o[3 * i], o[3 * i + 1], o[3 * i + 2], __int_as_float(-1));
+  q.d[i] = make_float4(d[3 * i], d[3 * i + 1], d[3 * i + 2], __int_as_float((int)i));
+  q.w[i] = make_float4(1.f, 1.f, 1.f, __int_as_float(0));
+}
+
+__device__ __forceinline__ void add_rgb(float* rgb, int pix, v3 v) {
+  atomicAdd(rgb + 3 * pix, v.x);
+  atomicAdd(rgb + 3 * pix + 1, v.y);
+  atomicAdd(rgb + 3 * pix + 2, v.z);
+}
+
+__device__ __forceinline__ v3 mul3(v3 a, v3 b) { return mk3(a.x * b.x, a.y * b.y, a.z * b.z); }
+
+// ------------------------------------------------------------------ k_trace (a4 + a5 decisions + a6)
+__global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
+                                              unsigned long long* part, float* rgb, float* wtrunc,
+                                              int32_t* flags, int accumulate) {
+  __shared__ uint32_t stk[DT_STACK * TB];
+  const uint32_t n = ctr->count[g];
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(&ctr->work[g], 64u);
+    base = (uint32_t)__shfl((int)base, 0);
+    if (base >= n) break;
+    uint32_t i = base + lane;
+    bool active = i < n;
+    bool has_r = false, has_t = false;
+    if (active) {
+      float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i];
+      v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
+      int skip = __float_as_int(o4.w);
+      int pix = __float_as_int(d4.w);
+      uint32_t rfl = (uint32_t)__float_as_int(w4.w);
+      bool ovf = false;
+      Hit h = closest_hit(sc.bvh, o, d, skip, sc.t_eps, stk + threadIdx.x, TB, &ovf);
+      q.hit[i] = make_float4(h.t, __int_as_float(h.tri), h.b1, h.b2);
+      uint32_t code = 0;
+      int pf = ovf ? DT_FLAG_STACK : 0;
+      if (h.tri < 0) {
+        if (rfl & RAY_INSIDE) pf |= DT_FLAG_LEAK;
+        if (accumulate) add_rgb(rgb, pix, mul3(W, env_equirect(sc.env, d)));
+      } else {
+        HitGeo geo = load_geo(sc, h.tri);
+        Shade s = shade(sc, geo, o, d, h.t, h.b1, h.b2, 0u);
+        code = s.code;
+        if (code & C_DEGEN) pf |= DT_FLAG_DEGEN;
+        if (code & C_GRAZE) pf |= DT_FLAG_GRAZING;
+        if (code & C_TIRB) pf |= DT_FLAG_TIRB;
+        if (g >= sc.max_depth) {
+          code |= C_TRUNC;
+          pf |= DT_FLAG_TRUNC;
+          if (accumulate) {
+            v3 wa = mul3(W, s.A);
+            if (wtrunc) add_rgb(wtrunc, pix, wa);
+            if (sc.terminal_env) add_rgb(rgb, pix, mul3(wa, env_equirect(sc.env, d)));
+          }
+        } else {
+          code |= C_HAS_R;
+          has_r = true;
+          if (!(code & C_TIR)) {
+            code |= C_HAS_T;
+            has_t = true;
+          }
+        }
+      }
+      q.code[i] = code;
+      if (accumulate && flags && pf) atomicOr(flags + pix, pf);
+    }
+    uint64_t br = __ballot(has_r), bt = __ballot(has_t);
+    if (lane == 0 && (br | bt))
+      atomicAdd(part + base / CHUNK,
+                (unsigned long long)__popcll(br) | ((unsigned long long)__popcll(bt) << 32));
+  }
+}
+
+// ------------------------------------------------------------------ k_scan (compaction offsets)
+// Single block: exclusive scan of the per-chunk (reflect | refract << 32)
+// counts of generation g, next-generation count, reset of the other
+// partial array and of the next work cursor.
+__global__ void k_scan(Counters* ctr, int g, unsigned long long* part, unsigned long long* other,
+                       int64_t other_n, int64_t cap_next) {
+  __shared__ unsigned long long sh[1024];
+  const uint32_t n = ctr->count[g];
+  const int64_t nch = ((int64_t)n + CHUNK - 1) / CHUNK;
+  unsigned long long carry = 0;
+  for (int64_t base = 0; base < nch; base += blockDim.x) {
+    int64_t i = base + threadIdx.x;
+    unsigned long long v = i < nch ? part[i] : 0ull;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+      unsigned long long x = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0ull;
+      __syncthreads();
+      sh[threadIdx.x] += x;
+      __syncthreads();
+    }
+    unsigned long long inc = sh[threadIdx.x];
+    unsigned long long tot = sh[blockDim.x - 1];
+    if (i < nch) part[i] = carry + inc - v;
+    carry += tot;
+    __syncthreads();
+  }
+  for (int64_t i = threadIdx.x; i < other_n; i += blockDim.x) other[i] = 0ull;
+  if (threadIdx.x == 0) {
+    uint32_t nr = (uint32_t)(carry & 0xffffffffull), nt = (uint32_t)(carry >> 32);
+    uint64_t tot = (uint64_t)nr + nt;
+    ctr->nrefl[g] = nr;
+    ctr->count[g + 1] = (uint32_t)(tot < (uint64_t)cap_next ? tot : (uint64_t)cap_next);
+    ctr->work[g + 1] = 0;
+  }
+}
+
+// ------------------------------------------------------------------ k_emit (a5 children)
+// Block b re-walks chunk b in order and writes each ray's children at its
+// scanned position: reflected children fill [0, n_r) of the next queue,
+// refracted children [n_r, n_r + n_t).  write_rays = 0 computes indices only.
+__global__ void __launch_bounds__(EB) k_emit(SceneDev sc, Gen q, Gen nx, int g, Counters* ctr,
+                                             const unsigned long long* part, int64_t cap_next,
+                                             int write_rays, int32_t* flags) {
+  __shared__ uint32_t wr[EB / 64], wt[EB / 64];
+  const uint32_t n = ctr->count[g];
+  const int64_t base = (int64_t)blockIdx.x * CHUNK;
+  if (base >= n) return;
+  const uint32_t nr_tot = ctr->nrefl[g];
+  unsigned long long c = part[blockIdx.x];
+  uint32_t carry_r = (uint32_t)(c & 0xffffffffull), carry_t = (uint32_t)(c >> 32);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int s = 0; s < CHUNK / EB; ++s) {
+    int64_t i = base + (int64_t)s * EB + threadIdx.x;
+    bool active = i < n;
+    uint32_t code = active ? q.code[i] : 0u;
+    bool hr = (code & C_HAS_R) != 0u, ht = (code & C_HAS_T) != 0u;
+    uint64_t br = __ballot(hr), bt = __ballot(ht);
+    if (lane == 0) {
+      wr[wv] = (uint32_t)__popcll(br);
+      wt[wv] = (uint32_t)__popcll(bt);
+    }
+    __syncthreads();
+    uint32_t or_ = 0, ot = 0, tr = 0, tt = 0;
+    for (int k = 0; k < EB / 64; ++k) {
+      if (k < wv) {
+        or_ += wr[k];
+        ot += wt[k];
+      }
+      tr += wr[k];
+      tt += wt[k];
+    }
+    uint32_t ir = carry_r + or_ + (uint32_t)__popcll(br & lt);
+    uint32_t it = nr_tot + carry_t + ot + (uint32_t)__popcll(bt & lt);
+    if (active) {
+      int cr = -1, ctd = -1;
+      if (hr || ht) {
+        float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i], h4 = q.hit[i];
+        v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
+        int pix = __float_as_int(d4.w);
+        int tri = __float_as_int(h4.y);
+        HitGeo geo = load_geo(sc, tri);
+        Shade sh = shade(sc, geo, o, d, h4.x, h4.z, h4.w, code);
+        v3 wa = mul3(W, sh.A);
+        bool entering = (code & C_ENTER) != 0u;
+        if (hr) {
+          if ((int64_t)ir < cap_next) {
+            cr = (int)ir;
+            if (write_rays) {
+              nx.o[ir] = make_float4(sh.x.x, sh.x.y, sh.x.z, __int_as_float(tri));
+              nx.d[ir] = make_float4(sh.dr.x, sh.dr.y, sh.dr.z, __int_as_float(pix));
+              v3 wr3 = wa * sh.R;
+              nx.w[ir] = make_float4(wr3.x, wr3.y, wr3.z, __int_as_float(entering ? 0 : (int)RAY_INSIDE));
+            }
+          } else if (write_rays) {
+            atomicAdd(&ctr->dropped, 1u);
+            if (flags) atomicOr(flags + pix, DT_FLAG_OVERFLOW);
+          }
+        }
+        if (ht) {
+          if ((int64_t)it < cap_next) {
+            ctd = (int)it;
+            if (write_rays) {
+              nx.o[it] = make_float4(sh.x.x, sh.x.y, sh.x.z, __int_as_float(tri));
+              nx.d[it] = make_float4(sh.dt.x, sh.dt.y, sh.dt.z, __int_as_float(pix));
+              v3 wt3 = wa * sh.T;
+              nx.w[it] = make_float4(wt3.x, wt3.y, wt3.z, __int_as_float(entering ? (int)RAY_INSIDE : 0));
+            }
+          } else if (write_rays) {
+            atomicAdd(&ctr->dropped, 1u);
+            if (flags) atomicOr(flags + pix, DT_FLAG_OVERFLOW);
+          }
+        }
+      }
+      if (q.child) q.child[i] = make_int2(cr, ctd);
+    }
+    carry_r += tr;
+    carry_t += tt;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ adjoint (a7)
+__device__ __forceinline__ v3 norm_bwd(v3 u, v3 uhat, v3 gbar) {
+  float il = 1.0f / len3(u);
+  return (gbar - uhat * dot(uhat, gbar)) * il;
+}
+
+__device__ __forceinline__ void atomic_add3(float* p, int idx, v3 v) {
+  atomicAdd(p + 3 * idx, v.x);
+  atomicAdd(p + 3 * idx + 1, v.y);
+  atomicAdd(p + 3 * idx + 2, v.z);
+}
+
+__global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
+                                                const float* grad_rgb, Adj nxt, Adj cur, float* dV,
+                                                float* dN, float* d_eta, float* d_sigma) {
+  const uint32_t n = ctr->count[g];
+  float acc_eta = 0.f, acc_s0 = 0.f, acc_s1 = 0.f, acc_s2 = 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i], h4 = q.hit[i];
+    uint32_t code = q.code[i];
+    v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
+    int pix = __float_as_int(d4.w);
+    v3 gp = load3(grad_rgb + 3 * pix);
+    v3 gW = mul3(gp, W);
+    if (!(code & C_HIT)) {
+      v3 dd;
+      v3 E = env_equirect_grad(sc.env, d, gW, &dd);
+      cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
+      cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      cur.D[i] = make_float4(dd.x, dd.y, dd.z, 0.f);
+      continue;
+    }
+    bool trunc = (code & C_TRUNC) != 0u;
+    if (trunc && !sc.terminal_env) {
+      cur.L[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      cur.D[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      continue;
+    }
+    float t = h4.x, b1 = h4.z, b2 = h4.w;
+    int tri = __float_as_int(h4.y);
+    HitGeo geo = load_geo(sc, tri);
+    Shade s = shade(sc, geo, o, d, t, b1, b2, code);
+    const bool entering = (code & C_ENTER) != 0u, tir = (code & C_TIR) != 0u;
+    const bool degen = (code & C_DEGEN) != 0u;
+    v3 L, Abar, dbar = mk3(0.f, 0.f, 0.f), xbar = mk3(0.f, 0.f, 0.f), nbar = mk3(0.f, 0.f, 0.f);
+    float cibar = 0.f, ctbar = 0.f, etarbar = 0.f, etaibar = 0.f, etatbar = 0.f;
+    if (trunc) {
+      // terminal mode ENV: L = A * E(d)
+      v3 dd;
+      v3 E = env_equirect_grad(sc.env, d, mul3(gW, s.A), &dd);
+      L = mul3(s.A, E);
+      Abar = mul3(gW, E);
+      dbar = dd;
+    } else {
+      int2 ch = q.child[i];
+      v3 Lr = mk3(0.f, 0.f, 0.f), Lt = mk3(0.f, 0.f, 0.f), drb = Lr, dtb = Lr;
+      if (ch.x >= 0) {
+        Lr = xyz(nxt.L[ch.x]);
+        xbar += xyz(nxt.O[ch.x]);
+        drb = xyz(nxt.D[ch.x]);
+      }
+      if (ch.y >= 0) {
+        Lt = xyz(nxt.L[ch.y]);
+        xbar += xyz(nxt.O[ch.y]);
+        dtb = xyz(nxt.D[ch.y]);
+      }
+      v3 M = Lr * s.R + Lt * s.T;
+      L = mul3(s.A, M);
+      Abar = mul3(gW, M);
+      // reflected direction u_r = d + 2 cos_i n (Eq. 3)
+      v3 urb = norm_bwd(s.ur, s.dr, drb);
+      dbar += urb;
+      cibar += 2.f * dot(s.n, urb);
+      nbar += urb * (2.f * s.cos_i);
+      if (!tir) {
+        // Fresnel weights (Eq. 7-8): dL/dR with T = 1 - R
+        float Rbar = dot(mul3(gW, s.A), Lr - Lt);
+        // refracted direction u_t = d / eta_r + (cos_i / eta_r - cos_t) n (Eq. 4-6)
+        v3 utb = norm_bwd(s.ut, s.dt, dtb);
+        float nu = dot(s.n, utb);
+        float ier = 1.f / s.eta_r;
+        dbar += utb * ier;
+        etarbar += -dot(d, utb) * ier * ier - s.cos_i * ier * ier * nu;
+        cibar += nu * ier;
+        ctbar += -nu;
+        nbar += utb * (s.cos_i * ier - s.cos_t);
+        float a = s.eta_i * s.cos_i, b = s.eta_t * s.cos_t;
+        float c = s.eta_i * s.cos_t, e = s.eta_t * s.cos_i;
+        float rsb = Rbar * s.rs, rpb = Rbar * s.rp;
+        float ab2 = (a + b) * (a + b), ce2 = (c + e) * (c + e);
+        float abar = rsb * 2.f * b / ab2, bbar = -rsb * 2.f * a / ab2;
+        float cbar = rpb * 2.f * e / ce2, ebar = -rpb * 2.f * c / ce2;
+        cibar += abar * s.eta_i + ebar * s.eta_t;
+        ctbar += bbar * s.eta_t + cbar * s.eta_i;
+        etaibar += abar * s.cos_i + cbar * s.cos_t;
+        etatbar += bbar * s.cos_t + ebar * s.cos_i;
+        // cos_t = sqrt(1 - sin^2 t), sin^2 t = (1 - cos_i^2) / eta_r^2
+        if (s.cos_t > 0.f) {
+          float s2b = -ctbar / (2.f * s.cos_t);
+          cibar += s2b * (-2.f * s.cos_i * ier * ier);
+          etarbar += s2b * (-2.f * (1.f - s.cos_i * s.cos_i) * ier * ier * ier);
+        }
+      }
+    }
+    // IoR: entering eta_i = 1, eta_t = eta_r = eta; leaving eta_i = eta, eta_t = 1, eta_r = 1/eta
+    float etabar = entering ? (etatbar + etarbar) : (etaibar - etarbar / (s.eta * s.eta));
+    acc_eta += etabar;
+    // absorption A = exp(-sigma t) on interior segments (Eq. 11)
+    float tbar = 0.f;
+    if (!entering) {
+      float sg0 = sc.sigma[0], sg1 = sc.sigma[1], sg2 = sc.sigma[2];
+      acc_s0 += -Abar.x * t * s.A.x;
+      acc_s1 += -Abar.y * t * s.A.y;
+      acc_s2 += -Abar.z * t * s.A.z;
+      tbar += -(Abar.x * sg0 * s.A.x + Abar.y * sg1 * s.A.y + Abar.z * sg2 * s.A.z);
+    }
+    // cos_i = -d . n
+    dbar += s.n * (-cibar);
+    nbar += d * (-cibar);
+    // children start at x = o + t d
+    v3 obar = xbar;
+    dbar += xbar * t;
+    tbar += dot(d, xbar);
+    // shading normal n = +-normalize(m), m = sum b_k N_k (Eq. 12)
+    const float sgn = entering ? 1.f : -1.f;
+    v3 p0b = mk3(0.f, 0.f, 0.f), p1b = p0b, p2b = p0b;
+    float b1bar = 0.f, b2bar = 0.f;
+    v3 e1 = geo.p1 - geo.p0, e2 = geo.p2 - geo.p0;
+    if (!degen) {
+      v3 nh = normalize3(s.m);
+      v3 mbar = norm_bwd(s.m, nh, nbar * sgn);
+      float b0 = 1.f - b1 - b2;
+      if (dN) {
+        atomic_add3(dN, geo.i0, mbar * b0);
+        atomic_add3(dN, geo.i1, mbar * b1);
+        atomic_add3(dN, geo.i2, mbar * b2);
+      }
+      b1bar += dot(geo.n1 - geo.n0, mbar);
+      b2bar += dot(geo.n2 - geo.n0, mbar);
+    } else {
+      v3 ng = cross(e1, e2);
+      v3 nh = normalize3(ng);
+      v3 ngbar = norm_bwd(ng, nh, nbar * sgn);
+      v3 e1b = cross(e2, ngbar), e2b = cross(ngbar, e1);
+      p1b += e1b;
+      p2b += e2b;
+      p0b += -(e1b + e2b);
+    }
+    // differentiable intersection (t, b1, b2 as functions of o, d, p0, p1, p2)
+    {
+      v3 sv = o - geo.p0;
+      v3 pv = cross(d, e2);
+      float det = dot(e1, pv);
+      float inv = 1.f / det;
+      v3 qv = cross(sv, e1);
+      float invbar = tbar * dot(e2, qv) + b1bar * dot(sv, pv) + b2bar * dot(d, qv);
+      v3 e2b = qv * (tbar * inv);
+      v3 qb = e2 * (tbar * inv) + d * (b2bar * inv);
+      dbar += qv * (b2bar * inv);
+      v3 svb = pv * (b1bar * inv);
+      v3 pb = sv * (b1bar * inv);
+      float detbar = -invbar * inv * inv;
+      v3 e1b = pv * detbar;
+      pb += e1 * detbar;
+      svb += cross(e1, qb);
+      e1b += cross(qb, sv);
+      dbar += cross(e2, pb);
+      e2b += cross(pb, d);
+      obar += svb;
+      p0b += -(svb + e1b + e2b);
+      p1b += e1b;
+      p2b += e2b;
+    }
+    atomic_add3(dV, geo.i0, p0b);
+    atomic_add3(dV, geo.i1, p1b);
+    atomic_add3(dV, geo.i2, p2b);
+    cur.L[i] = make_float4(L.x, L.y, L.z, 0.f);
+    cur.O[i] = make_float4(obar.x, obar.y, obar.z, 0.f);
+    cur.D[i] = make_float4(dbar.x, dbar.y, dbar.z, 0.f);
+  }
+  // block reduction of the scalar gradients
+  __shared__ float red[4][AB];
+  red[0][threadIdx.x] = acc_eta;
+  red[1][threadIdx.x] = acc_s0;
+  red[2][threadIdx.x] = acc_s1;
+  red[3][threadIdx.x] = acc_s2;
+  __syncthreads();
+  for (int st = AB / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (red[0][0] != 0.f) atomicAdd(d_eta, red[0][0]);
+    if (red[1][0] != 0.f) atomicAdd(d_sigma, red[1][0]);
+    if (red[2][0] != 0.f) atomicAdd(d_sigma + 1, red[2][0]);
+    if (red[3][0] != 0.f) atomicAdd(d_sigma + 2, red[3][0]);
+  }
+}
+
+// ------------------------------------------------------------------ normals backward (Eq. 13)
+// N_v = normalize(s_v), s_v = sum of unit face normals u_f, u_f = normalize(c_f),
+// c_f = (p1 - p0) x (p2 - p0).
+__global__ void k_nbwd_vertex(const BvhView bv, const float* dN, float4* sbar) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= bv.nv) return;
+  v3 s = mk3(0.f, 0.f, 0.f);
+  for (int k = bv.csr_off[v]; k < bv.csr_off[v + 1]; ++k) s += xyz(bv.fn[bv.csr_idx[k]]);
+  float l2 = dot(s, s);
+  v3 r = mk3(0.f, 0.f, 0.f);
+  if (l2 > 0.f) {
+    v3 N = xyz(bv.vn[v]);
+    v3 g = load3(dN + 3 * v);
+    r = (g - N * dot(N, g)) * (1.0f / sqrtf(l2));
+  }
+  sbar[v] = make_float4(r.x, r.y, r.z, 0.f);
+}
+
+__global__ void k_nbwd_face(const BvhView bv, const float* V, const int32_t* F, const float4* sbar,
+                            float* dV) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= bv.nf) return;
+  float4 u4 = bv.fn[f];
+  if (u4.w == 0.f) return;
+  int i0 = F[3 * f], i1 = F[3 * f + 1], i2 = F[3 * f + 2];
+  v3 ub = xyz(sbar[i0]) + xyz(sbar[i1]) + xyz(sbar[i2]);
+  v3 p0 = load3(V + 3 * i0), p1 = load3(V + 3 * i1), p2 = load3(V + 3 * i2);
+  v3 e1 = p1 - p0, e2 = p2 - p0;
+  v3 c = cross(e1, e2);
+  v3 u = xyz(u4);
+  v3 cb = (ub - u * dot(u, ub)) * (1.0f / len3(c));
+  v3 e1b = cross(e2, cb), e2b = cross(cb, e1);
+  atomic_add3(dV, i1, e1b);
+  atomic_add3(dV, i2, e2b);
+  atomic_add3(dV, i0, -(e1b + e2b));
+}
+
+// ------------------------------------------------------------------ env / intersect kernels
+__global__ void k_env_query(EnvDev e, const float* dirs, int64_t n, float* rgb) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  v3 E = env_equirect(e, load3(dirs + 3 * i));
+  rgb[3 * i] = E.x;
+  rgb[3 * i + 1] = E.y;
+  rgb[3 * i + 2] = E.z;
+}
+
+__global__ void k_env_query_bwd(EnvDev e, const float* dirs, int64_t n, const float* g, float* gd) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  v3 dd;
+  env_equirect_grad(e, load3(dirs + 3 * i), load3(g + 3 * i), &dd);
+  gd[3 * i] = dd.x;
+  gd[3 * i + 1] = dd.y;
+  gd[3 * i + 2] = dd.z;
+}
+
+__global__ void __launch_bounds__(TB) k_intersect(BvhView bv, const float* o, const float* d,
+                                                  const int32_t* skip, int64_t n, float t_eps,
+                                                  int brute, int32_t* tri, float* t, float* b) {
+  __shared__ uint32_t stk[DT_STACK * TB];
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  v3 oo = load3(o + 3 * i), dd = load3(d + 3 * i);
+  int sk = skip ? skip[i] : -1;
+  bool ovf = false;
+  Hit h = brute ? closest_brute(bv, oo, dd, sk, t_eps)
+                : closest_hit(bv, oo, dd, sk, t_eps, stk + threadIdx.x, TB, &ovf);
+  tri[i] = ovf ? -2 : h.tri;
+  t[i] = h.t;
+  b[2 * i] = h.b1;
+  b[2 * i + 1] = h.b2;
+}
+
+// ------------------------------------------------------------------ host helpers
+dt_status make_env(const dt_env* env, EnvDev& e) {
+  DT_REQUIRE(env, "environment descriptor is NULL");
+  if (env->kind != DT_ENV_EQUIRECT) {
+    dt_set_error("environment kind %d is not supported by this entry point", env->kind);
+    return DT_ERR_UNSUPPORTED;
+  }
+  DT_REQUIRE(env->texels && env->width >= 1 && env->height >= 1,
+             "equirect environment needs texels and width, height >= 1");
+  e.kind = env->kind;
+  e.W = env->width;
+  e.H = env->height;
+  e.tex = env->texels;
+  e.n_freq = env->n_freq;
+  e.n_layers = env->n_layers;
+  e.hidden = env->hidden;
+  e.in_pad = env->in_pad;
+  e.w = env->weights;
+  e.b = env->biases;
+  return DT_OK;
+}
+
+dt_status make_scene(const dt_scene* sc, const dt_trace_params* p, SceneDev& s) {
+  DT_REQUIRE(sc && p, "scene or params is NULL");
+  DT_REQUIRE(sc->V && sc->F && sc->bvh && sc->ior && sc->sigma && sc->env,
+             "scene has a NULL pointer (V, F, bvh, ior, sigma, env)");
+  DT_REQUIRE(sc->nv >= 3 && sc->nf >= 1 && sc->nf < (1 << 30) && sc->nv < (1 << 30),
+             "scene needs nv >= 3 and 1 <= nf < 2^30 (got %d, %d)", sc->nv, sc->nf);
+  DT_REQUIRE(p->max_depth >= 0 && p->max_depth <= DT_MAX_DEPTH, "max_depth must be in [0, %d]",
+             DT_MAX_DEPTH);
+  DT_REQUIRE(p->t_eps >= 0.f && p->t_eps < 1.f, "t_eps must be in [0, 1)");
+  DT_REQUIRE(p->checkpoint_stride >= 1, "checkpoint_stride must be >= 1");
+  DT_REQUIRE(p->queue_capacity >= 0, "queue_capacity must be >= 0");
+  s.V = sc->V;
+  s.F = sc->F;
+  s.nv = sc->nv;
+  s.nf = sc->nf;
+  s.bvh = bvh_view(sc->bvh, sc->nv, sc->nf);
+  s.ior = sc->ior;
+  s.sigma = sc->sigma;
+  if (dt_status st = make_env(sc->env, s.env)) return st;
+  s.max_depth = p->max_depth;
+  s.terminal_env = p->terminal_env ? 1 : 0;
+  s.t_eps = p->t_eps;
+  return DT_OK;
+}
+
+dt_status ray_counts(const dt_rays* r, int64_t& n_rays, int64_t& npix) {
+  DT_REQUIRE(r, "rays is NULL");
+  if (r->kind == DT_RAYS_EXPLICIT) {
+    DT_REQUIRE(r->n >= 1 && r->n < (1ll << 31), "explicit rays need 1 <= n < 2^31");
+    DT_REQUIRE(r->o && r->d, "explicit rays need o and d");
+    n_rays = npix = r->n;
+    return DT_OK;
+  }
+  DT_REQUIRE(r->kind == DT_RAYS_CAMERAS, "unknown ray kind %d", r->kind);
+  DT_REQUIRE(r->n_cameras >= 1 && r->cameras, "camera rays need n_cameras >= 1 and cameras");
+  DT_REQUIRE(r->n_pixels >= 1 && r->n_pixels < (1ll << 31), "n_pixels must be in [1, 2^31)");
+  int64_t tot = 0;
+  for (int c = 0; c < r->n_cameras; ++c) {
+    const dt_camera& cam = r->cameras[c];
+    DT_REQUIRE(cam.width >= 1 && cam.height >= 1, "camera %d has an empty image", c);
+    DT_REQUIRE(cam.fov_deg > 0.f && cam.fov_deg < 180.f, "camera %d fov must be in (0, 180)", c);
+    int64_t np = (int64_t)cam.width * cam.height;
+    DT_REQUIRE(cam.pixel_offset >= 0 && cam.pixel_offset + np <= r->n_pixels,
+               "camera %d pixels [%lld, %lld) exceed n_pixels %lld", c, (long long)cam.pixel_offset,
+               (long long)(cam.pixel_offset + np), (long long)r->n_pixels);
+    tot += np;
+  }
+  DT_REQUIRE(tot < (1ll << 31), "too many camera rays");
+  n_rays = tot;
+  npix = r->n_pixels;
+  return DT_OK;
+}
+
+Gen gen_at(char* base, size_t o, size_t d, size_t w, size_t hit, size_t code, size_t child) {
+  Gen g;
+  g.o = o == (size_t)-1 ? nullptr : (float4*)(base + o);
+  g.d = d == (size_t)-1 ? nullptr : (float4*)(base + d);
+  g.w = w == (size_t)-1 ? nullptr : (float4*)(base + w);
+  g.hit = hit == (size_t)-1 ? nullptr : (float4*)(base + hit);
+  g.code = code == (size_t)-1 ? nullptr : (uint32_t*)(base + code);
+  g.child = child == (size_t)-1 ? nullptr : (int2*)(base + child);
+  return g;
+}
+
+unsigned trace_grid(int64_t cap) {
+  int64_t waves = (cap + 63) / 64;
+  int64_t lim = 256 * 10;  // resident waves the LDS stack allows on 256 CUs
+  return (unsigned)(waves < lim ? (waves < 1 ? 1 : waves) : lim);
+}
+
+dt_status emit_rays(const dt_rays* r, Gen g0, hipStream_t s) {
+  if (r->kind == DT_RAYS_EXPLICIT) {
+    hipLaunchKernelGGL(k_rays_explicit, dim3(dt_blocks(r->n, 256)), dim3(256), 0, s, g0, r->o, r->d,
+                       r->n);
+    DT_CHECK_LAUNCH();
+    return DT_OK;
+  }
+  int64_t base = 0;
+  for (int c = 0; c < r->n_cameras; ++c) {
+    const dt_camera& cam = r->cameras[c];
+    double e[3] = {cam.eye[0], cam.eye[1], cam.eye[2]};
+    double f[3] = {cam.target[0] - e[0], cam.target[1] - e[1], cam.target[2] - e[2]};
+    double fl = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    DT_REQUIRE(fl > 0.0, "camera %d: eye equals target", c);
+    for (int k = 0; k < 3; ++k) f[k] /= fl;
+    double up[3] = {cam.up[0], cam.up[1], cam.up[2]};
+    double rt[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+    double rl = sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+    DT_REQUIRE(rl > 0.0, "camera %d: up is parallel to the view direction", c);
+    for (int k = 0; k < 3; ++k) rt[k] /= rl;
+    double u[3] = {rt[1] * f[2] - rt[2] * f[1], rt[2] * f[0] - rt[0] * f[2], rt[0] * f[1] - rt[1] * f[0]};
+    CamDev cd;
+    for (int k = 0; k < 3; ++k) {
+      cd.eye[k] = (float)e[k];
+      cd.f[k] = (float)f[k];
+      cd.r[k] = (float)rt[k];
+      cd.u[k] = (float)u[k];
+    }
+    cd.th = (float)tan(0.5 * (double)cam.fov_deg * 3.14159265358979323846 / 180.0);
+    cd.aspect = (float)((double)cam.width / (double)cam.height);
+    cd.W = cam.width;
+    cd.H = cam.height;
+    cd.pixel_offset = cam.pixel_offset;
+    cd.base = base;
+    cd.tiled = (cam.width % 8 == 0 && cam.height % 8 == 0) ? 1 : 0;
+    int64_t np = (int64_t)cam.width * cam.height;
+    hipLaunchKernelGGL(k_raygen, dim3(dt_blocks(np, 256)), dim3(256), 0, s, g0, cd);
+    DT_CHECK_LAUNCH();
+    base += np;
+  }
+  return DT_OK;
+}
+
+// run generation g of the wavefront: trace, and (g < D) scan + emit
+dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen nxt, Counters* ctr,
+                         unsigned long long* part_g, unsigned long long* part_other, float* rgb,
+                         float* wtrunc, int32_t* flags, int accumulate, int write_next,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_trace, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
+                     rgb, wtrunc, flags, accumulate);
+  DT_CHECK_LAUNCH();
+  if (g < P.D) {
+    int64_t other_n = (P.cap[g + 1] + CHUNK - 1) / CHUNK + 1;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctr, g, part_g, part_other, other_n,
+                       P.cap[g + 1]);
+    int64_t nch = (P.cap[g] + CHUNK - 1) / CHUNK;
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nch), dim3(EB), 0, s, sc, cur, nxt, g, ctr, part_g,
+                       P.cap[g + 1], write_next, accumulate ? flags : nullptr);
+    DT_CHECK_LAUNCH();
+  }
+  return DT_OK;
+}
+
+dt_status zero_f32(float* p, int64_t n, hipStream_t s) {
+  if (!p || n <= 0) return DT_OK;
+  unsigned nb = dt_blocks(n, 256);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_zero_f32, dim3(nb), dim3(256), 0, s, p, n);
+  DT_CHECK_LAUNCH();
+  return DT_OK;
+}
+
+dt_status zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
+  if (!p || n <= 0) return DT_OK;
+  unsigned nb = dt_blocks(n, 256);
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_zero_u64, dim3(nb), dim3(256), 0, s, p, n);
+  DT_CHECK_LAUNCH();
+  return DT_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" dt_status dt_trace_bytes(const dt_trace_params* p, int64_t n_rays, int32_t nv, int32_t nf,
+                                    size_t* ws_bytes, size_t* tape_bytes) {
+  DT_REQUIRE(p && ws_bytes && tape_bytes, "dt_trace_bytes: NULL argument");
+  DT_REQUIRE(n_rays >= 1 && n_rays < (1ll << 31), "dt_trace_bytes: n_rays must be in [1, 2^31)");
+  DT_REQUIRE(nv >= 3 && nf >= 1, "dt_trace_bytes: need nv >= 3 and nf >= 1");
+  DT_REQUIRE(p->max_depth >= 0 && p->max_depth <= DT_MAX_DEPTH, "max_depth must be in [0, %d]",
+             DT_MAX_DEPTH);
+  DT_REQUIRE(p->checkpoint_stride >= 1 && p->queue_capacity >= 0, "bad checkpoint_stride / capacity");
+  Plan P;
+  make_plan(p, n_rays, n_rays, nv, P);
+  *ws_bytes = P.ws_bytes;
+  *tape_bytes = P.tape_bytes;
+  return DT_OK;
+}
+
+extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays,
+                                      const dt_trace_params* p, float* rgb, float* wtrunc,
+                                      int32_t* flags, int64_t* stats, void* tape, size_t tape_bytes,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  SceneDev sc;
+  if (dt_status st = make_scene(scene, p, sc)) return st;
+  int64_t N, npix;
+  if (dt_status st = ray_counts(rays, N, npix)) return st;
+  DT_REQUIRE(rgb && ws, "dt_trace_forward: rgb and ws are required");
+  Plan P;
+  make_plan(p, N, npix, scene->nv, P);
+  if (ws_bytes < P.ws_bytes) {
+    dt_set_error("dt_trace_forward: workspace has %zu bytes, needs %zu", ws_bytes, P.ws_bytes);
+    return DT_ERR_WORKSPACE_TOO_SMALL;
+  }
+  if (tape && tape_bytes < P.tape_bytes) {
+    dt_set_error("dt_trace_forward: tape has %zu bytes, needs %zu", tape_bytes, P.tape_bytes);
+    return DT_ERR_WORKSPACE_TOO_SMALL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)ws;
+  char* T = (char*)tape;
+  Counters* ctr = (Counters*)(W + P.w_ctr);
+  unsigned long long* part[2] = {(unsigned long long*)(W + P.w_part0),
+                                 (unsigned long long*)(W + P.w_part1)};
+  hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, s, ctr, (uint32_t)N);
+  if (dt_status st = zero_u64(part[0], P.maxchunks + 1, s)) return st;
+  if (dt_status st = zero_f32(rgb, 3 * npix, s)) return st;
+  if (dt_status st = zero_f32(wtrunc, 3 * npix, s)) return st;
+  if (dt_status st = zero_f32((float*)flags, npix, s)) return st;
+
+  // where generation g lives during the forward pass: on the tape when it is
+  // stored there, otherwise in the ping-pong scratch queues of the workspace
+  auto gen_fwd = [&](int g) -> Gen {
+    Gen G;
+    if (T && (P.store_all || g % P.k == 0)) {
+      G = gen_at(T, P.t_o[g], P.t_d[g], P.t_w[g], (size_t)-1, (size_t)-1, (size_t)-1);
+    } else {
+      G = gen_at(W, P.w_ro[g & 1], P.w_rd[g & 1], P.w_rw[g & 1], (size_t)-1, (size_t)-1, (size_t)-1);
+    }
+    if (T && P.store_all) {
+      G.hit = (float4*)(T + P.t_hit[g]);
+      G.code = (uint32_t*)(T + P.t_code[g]);
+      G.child = (int2*)(T + P.t_child[g]);
+    } else {
+      G.hit = (float4*)(W + P.w_hit);
+      G.code = (uint32_t*)(W + P.w_code);
+      G.child = nullptr;
+    }
+    return G;
+  };
+  for (int g = 0; g <= P.D; ++g) {
+    Gen cur = gen_fwd(g);
+    if (g == 0)
+      if (dt_status st = emit_rays(rays, cur, s)) return st;
+    Gen nxt = g < P.D ? gen_fwd(g + 1) : cur;
+    if (dt_status st = run_generation(sc, P, g, cur, nxt, ctr, part[g & 1], part[(g + 1) & 1], rgb,
+                                      wtrunc, flags, 1, 1, s))
+      return st;
+  }
+  if (T) hipLaunchKernelGGL(k_save_counters, dim3(1), dim3(64), 0, s, (Counters*)(T + P.tape_hdr), ctr);
+  if (stats) hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, s, ctr, P.D, sc.bvh.hdr, stats);
+  DT_CHECK_LAUNCH();
+  return DT_OK;
+}
+
+extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* rays,
+                                       const dt_trace_params* p, const float* grad_rgb,
+                                       const void* tape, size_t tape_bytes, float* dV, float* d_ior,
+                                       float* d_sigma, void* ws, size_t ws_bytes, void* stream) {
+  SceneDev sc;
+  if (dt_status st = make_scene(scene, p, sc)) return st;
+  int64_t N, npix;
+  if (dt_status st = ray_counts(rays, N, npix)) return st;
+  DT_REQUIRE(grad_rgb && tape && dV && d_ior && d_sigma && ws,
+             "dt_trace_backward: grad_rgb, tape, dV, d_ior, d_sigma and ws are required");
+  Plan P;
+  make_plan(p, N, npix, scene->nv, P);
+  if (ws_bytes < P.ws_bytes || tape_bytes < P.tape_bytes) {
+    dt_set_error("dt_trace_backward: workspace %zu/%zu or tape %zu/%zu bytes too small", ws_bytes,
+                 P.ws_bytes, tape_bytes, P.tape_bytes);
+    return DT_ERR_WORKSPACE_TOO_SMALL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  char* W = (char*)ws;
+  char* T = (char*)tape;
+  Counters* ctr = (Counters*)(W + P.w_ctr);
+  unsigned long long* part[2] = {(unsigned long long*)(W + P.w_part0),
+                                 (unsigned long long*)(W + P.w_part1)};
+  float* dN = (float*)(W + P.w_dN);
+  float4* sbar = (float4*)(W + P.w_sbar);
+  hipLaunchKernelGGL(k_load_counters, dim3(1), dim3(64), 0, s, ctr, (const Counters*)(T + P.tape_hdr));
+  if (dt_status st = zero_f32(dV, 3 * (int64_t)scene->nv, s)) return st;
+  if (dt_status st = zero_f32(dN, 3 * (int64_t)scene->nv, s)) return st;
+  if (dt_status st = zero_f32(d_ior, 1, s)) return st;
+  if (dt_status st = zero_f32(d_sigma, 3, s)) return st;
+  Adj adj[2];
+  for (int b = 0; b < 2; ++b) {
+    adj[b].L = (float4*)(W + P.w_adj[b][0]);
+    adj[b].O = (float4*)(W + P.w_adj[b][1]);
+    adj[b].D = (float4*)(W + P.w_adj[b][2]);
+  }
+  auto adjoint = [&](int g, Gen q) -> dt_status {
+    int64_t blocks = (P.cap[g] + AB - 1) / AB;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
+                       adj[(g + 1) & 1], adj[g & 1], dV, dN, d_ior, d_sigma);
+    DT_CHECK_LAUNCH();
+    return DT_OK;
+  };
+  if (P.store_all) {
+    for (int g = P.D; g >= 0; --g) {
+      Gen q = gen_at(T, P.t_o[g], P.t_d[g], P.t_w[g], P.t_hit[g], P.t_code[g], P.t_child[g]);
+      if (dt_status st = adjoint(g, q)) return st;
+    }
+  } else {
+    // recompute each segment [g0, g0 + k) from its stored first generation
+    int nseg = (P.D + P.k) / P.k;
+    size_t mc = (size_t)P.maxcap;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+      int g0 = sg * P.k;
+      int g1 = g0 + P.k - 1 < P.D ? g0 + P.k - 1 : P.D;
+      Gen seg[DT_MAX_DEPTH + 1];
+      for (int g = g0; g <= g1; ++g) {
+        int j = g - g0;
+        seg[j].o = (float4*)(W + P.w_seg_o) + mc * j;
+        seg[j].d = (float4*)(W + P.w_seg_d) + mc * j;
+        seg[j].w = (float4*)(W + P.w_seg_w) + mc * j;
+        seg[j].hit = (float4*)(W + P.w_seg_hit) + mc * j;
+        seg[j].code = (uint32_t*)(W + P.w_seg_code) + mc * j;
+        seg[j].child = (int2*)(W + P.w_seg_child) + mc * j;
+      }
+      // generation g0 reads its rays from the tape
+      seg[0].o = (float4*)(T + P.t_o[g0]);
+      seg[0].d = (float4*)(T + P.t_d[g0]);
+      seg[0].w = (float4*)(T + P.t_w[g0]);
+      hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, s, ctr, g0);
+      if (dt_status st = zero_u64(part[g0 & 1], P.maxchunks + 1, s)) return st;
+      for (int g = g0; g <= g1; ++g) {
+        int j = g - g0;
+        Gen nxt = g < g1 ? seg[j + 1] : seg[j];
+        if (dt_status st = run_generation(sc, P, g, seg[j], nxt, ctr, part[g & 1], part[(g + 1) & 1],
+                                          nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0, s))
+          return st;
+      }
+      for (int g = g1; g >= g0; --g)
+        if (dt_status st = adjoint(g, seg[g - g0])) return st;
+    }
+  }
+  hipLaunchKernelGGL(k_nbwd_vertex, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, dN, sbar);
+  hipLaunchKernelGGL(k_nbwd_face, dim3(dt_blocks(scene->nf, 256)), dim3(256), 0, s, sc.bvh, sc.V, sc.F,
+                     sbar, dV);
+  DT_CHECK_LAUNCH();
+  return DT_OK;
+}
+
+extern "C" dt_status dt_env_query(const dt_env* env, const float* dirs, int64_t n, float* rgb,
+                                  void* stream) {
+  EnvDev e;
+  if (dt_status st = make_env(env, e)) return st;
+  DT_REQUIRE(dirs && rgb && n >= 0, "dt_env_query: bad arguments");
+  if (n == 0) return DT_OK;
+  hipLaunchKernelGGL(k_env_query, dim3(dt_blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, e, dirs,
+                     n, rgb);
+  DT_CHECK_LAUNCH();
+  return DT_OK;
+}
+
+extern "C" dt_status dt_env_query_backward(const dt_env* env, const float* dirs, int64_t n,
+                                           const float* grad_rgb, float* grad_dirs, void* stream) {
+  EnvDev e;
+  if (dt_status st = make_env(env, e)) return st;
+  DT_REQUIRE(dirs && grad_rgb && grad_dirs && n >= 0, "dt_env_query_backward: bad arguments");
+  if (n == 0) return DT_OK;
+  hipLaunchKernelGGL(k_env_query_bwd, dim3(dt_blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, e,
+                     dirs, n, grad_rgb, grad_dirs);
+  DT_CHECK_LAUNCH();
+  return DT_OK;
+}
+
+extern "C" dt_status dt_intersect(const dt_scene* scene, const float* o, const float* d,
+                                  const int32_t* skip, int64_t n, float t_eps, int32_t brute_force,
+                                  int32_t* tri, float* t, float* b, void* stream) {
+  DT_REQUIRE(scene && scene->bvh && o && d && tri && t && b, "dt_intersect: NULL argument");
+  DT_REQUIRE(scene->nv >= 3 && scene->nf >= 1, "dt_intersect: bad mesh size");
+  DT_REQUIRE(n >= 0 && n < (1ll << 31), "dt_intersect: bad ray count");
+  if (n == 0) return DT_OK;
+  BvhView bv = bvh_view(scene->bvh, scene->nv, scene->nf);
+  hipLaunchKernelGGL(k_intersect, dim3(dt_blocks(n, TB)), dim3(TB), 0, (hipStream_t)stream, bv, o, d,
+                     skip, n, t_eps, brute_force ? 1 : 0, tri, t, b);
+  DT_CHECK_LAUNCH();
+  return DT_OK;
+}

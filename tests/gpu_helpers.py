@@ -1,0 +1,89 @@
+"""Helpers shared by the GPU parity tests: build the same seeded scene for the
+HIP path (float32 device tensors) and for the FP64 oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_00413_amd import binding as B
+from paper_2603_00413_amd import synth
+
+# pixels whose trees contain a node in one of these states are excluded from
+# the tolerance checks (degenerate normal, leak, grazing, TIR boundary)
+BAD = B.FLAG_DEGEN | B.FLAG_LEAK | B.FLAG_GRAZING | B.FLAG_TIRB
+HARD = B.FLAG_OVERFLOW | B.FLAG_STACK
+
+
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda:0")
+
+
+class Pair:
+    """The same scene on the device and in the oracle."""
+
+    def __init__(self, V, F, ior, sigma, tex, cams, depth, terminal_env=False,
+                 capacity=0, stride=1):
+        dev = device()
+        self.V64, self.F = np.asarray(V, np.float64), np.asarray(F, np.int32)
+        # both sides see exactly the float32-rounded geometry and texels
+        self.V32 = self.V64.astype(np.float32)
+        self.tex = np.asarray(tex, np.float32)
+        self.cams = cams
+        self.depth = depth
+        self.sigma = np.broadcast_to(np.asarray(sigma, np.float64), (3,)).astype(np.float32)
+        self.ior = np.float32(ior)
+        self.mesh = B.Mesh(torch.from_numpy(self.V32).to(dev), torch.from_numpy(self.F).to(dev))
+        self.env = B.Env(torch.from_numpy(self.tex).to(dev))
+        self.ior_t = torch.tensor([self.ior], dtype=torch.float32, device=dev)
+        self.sigma_t = torch.from_numpy(self.sigma.copy()).to(dev)
+        self.scene = B.Scene(self.mesh, self.ior_t, self.sigma_t, self.env)
+        self.rays = B.Rays(cameras=cams)
+        self.params = B.Params(max_depth=depth, terminal_env=terminal_env,
+                               checkpoint_stride=stride, queue_capacity=capacity)
+        self.orc = oracle.Scene(self.V32.astype(np.float64), self.F, float(self.ior),
+                                self.sigma.astype(np.float64), oracle.Env(tex=self.tex), depth,
+                                terminal_env=terminal_env)
+        o, d = [], []
+        for c in cams:
+            oo, dd = oracle.camera_rays(c)
+            o.append(oo)
+            d.append(dd)
+        self.o, self.d = np.concatenate(o), np.concatenate(d)
+
+    def gpu_forward(self, tape=True, params=None):
+        p = params or self.params
+        buf = B.Buffers(p, self.rays, self.mesh, tape=tape)
+        rgb, wt, fl = B.dt_trace_forward(self.scene, self.rays, p, buf)
+        torch.cuda.synchronize()
+        return buf, rgb.cpu().numpy().astype(np.float64), wt.cpu().numpy().astype(np.float64), \
+            fl.cpu().numpy()
+
+    def gpu_backward(self, buf, grad, params=None):
+        p = params or self.params
+        g = torch.from_numpy(np.asarray(grad, np.float32)).to(self.mesh.V.device)
+        dV, de, ds = B.dt_trace_backward(self.scene, self.rays, p, buf, g)
+        torch.cuda.synchronize()
+        return dV.cpu().numpy().astype(np.float64), float(de.cpu()[0]), ds.cpu().numpy().astype(np.float64)
+
+
+def rel_err(g, o):
+    """Per pixel-channel |g - o| / max(|o|, 1e-3 * mean(o))."""
+    floor = 1e-3 * max(np.abs(o).mean(), 1e-30)
+    return np.abs(g - o) / np.maximum(np.abs(o), floor)
+
+
+def icosphere_pair(sigma=(0.0, 0.0, 0.0), res=64, **kw):
+    wl = synth.icosphere_scene(sigma=sigma, res=res)
+    return Pair(wl.V, wl.F, wl.ior, wl.sigma, wl.env, wl.cameras, wl.max_depth, **kw)
+
+
+def torus_pair(n_views=2, res=96, nu=320, nv=160, **kw):
+    V, F = synth.displaced_torus(seed=2, nu=nu, nv=nv)
+    tex = synth.env_equirect(512, 256, seed=2)
+    eyes = synth.views_on_sphere(n_views, 3.0, seed=2)
+    cams = [synth.look_at_camera(e, res, res) for e in eyes]
+    return Pair(V, F, 1.45, 0.3, tex, cams, 6, **kw)

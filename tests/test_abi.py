@@ -1,0 +1,62 @@
+"""The C-ABI library loads, exports every entry point the header declares,
+and rejects bad arguments on the host (no device work is queued)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2603_00413_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "difftrans.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dt_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ["dt_build_bvh", "dt_trace_forward", "dt_trace_backward", "dt_env_query"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.load()
+    for name in declared():
+        assert hasattr(L, name), name
+    assert set(B.EXPORTS) <= set(declared())
+
+
+def test_host_validation_without_device():
+    L = B.load()
+    a, b = C.c_size_t(), C.c_size_t()
+    assert L.dt_bvh_bytes(0, 0, C.byref(a), C.byref(b)) == 1
+    assert "nv >= 3" in L.dt_last_error().decode()
+    assert L.dt_bvh_bytes(642, 1280, C.byref(a), C.byref(b)) == 0
+    assert a.value > 1280 * 48 and b.value > 0
+    p = B.Params(max_depth=17).c()
+    assert L.dt_trace_bytes(C.byref(p), 100, 3, 1, C.byref(a), C.byref(b)) == 1
+    p = B.Params(max_depth=6, checkpoint_stride=2).c()
+    assert L.dt_trace_bytes(C.byref(p), 4096, 642, 1280, C.byref(a), C.byref(b)) == 0
+    ws2, tape2 = a.value, b.value
+    p = B.Params(max_depth=6, checkpoint_stride=1).c()
+    assert L.dt_trace_bytes(C.byref(p), 4096, 642, 1280, C.byref(a), C.byref(b)) == 0
+    assert b.value > tape2          # storing every generation costs more tape
+    # a null scene is rejected before anything touches a device
+    assert L.dt_trace_forward(None, None, None, None, None, None, None, None, 0, None, 0, None) == 1
+    assert L.dt_status_string(2) == b"workspace too small"
+
+
+def test_queue_capacity_bounds_tape():
+    L = B.load()
+    a, b = C.c_size_t(), C.c_size_t()
+    p = B.Params(max_depth=6, queue_capacity=0).c()
+    L.dt_trace_bytes(C.byref(p), 1 << 20, 51200, 102400, C.byref(a), C.byref(b))
+    worst = b.value
+    p = B.Params(max_depth=6, queue_capacity=2 << 20).c()
+    L.dt_trace_bytes(C.byref(p), 1 << 20, 51200, 102400, C.byref(a), C.byref(b))
+    assert b.value < worst / 5

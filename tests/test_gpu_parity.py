@@ -1,0 +1,212 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (the benchmark spec): radiance within 1e-4 relative (|g - o| / max(|o|,
+1e-3 mean(o)) per pixel-channel) away from grazing / TIR-boundary rays;
+gradients within 1e-3 relative (dV as a whole-array L2 ratio, dIoR and each
+dsigma_c as scalars).  Index work (BVH vs brute force) is bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_00413_amd import binding as B
+from paper_2603_00413_amd import synth
+from tests.gpu_helpers import BAD, HARD, Pair, device, icosphere_pair, rel_err, torus_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------- a1 normals
+@pytest.mark.parametrize("which", ["icosphere", "torus", "sdf"])
+def test_vertex_normals(which):
+    dev = device()
+    if which == "icosphere":
+        V, F = synth.icosphere(3)
+    elif which == "torus":
+        V, F = synth.displaced_torus(seed=2)
+    else:
+        V, F = synth.sdf_union_mesh(seed=3, res=48)
+    V32 = V.astype(np.float32)
+    m = B.Mesh(torch.from_numpy(V32).to(dev), torch.from_numpy(F).to(dev))
+    N = m.vertex_normals().cpu().numpy()
+    No = oracle.vertex_normals(V32.astype(np.float64), F)
+    err = np.abs(N - No).max()
+    _print(which, "normals max abs err", err)
+    assert err < 2e-5
+
+
+# ---------------------------------------------------------------- a2 + a4 BVH and intersection
+@pytest.mark.parametrize("which", ["torus", "sdf", "tiny"])
+def test_bvh_matches_brute_force_bit_exact(which):
+    dev = device()
+    if which == "torus":
+        V, F = synth.displaced_torus(seed=2, nu=160, nv=80)
+    elif which == "sdf":
+        V, F = synth.sdf_union_mesh(seed=3, res=48)
+    else:
+        V, F = synth.icosphere(0)
+    rng = np.random.default_rng(1)
+    n = 20000
+    o = rng.normal(size=(n, 3))
+    o = o / np.linalg.norm(o, axis=1, keepdims=True) * rng.uniform(0.0, 3.0, (n, 1))
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    V32 = V.astype(np.float32)
+    m = B.Mesh(torch.from_numpy(V32).to(dev), torch.from_numpy(F).to(dev))
+    env = B.Env(torch.ones(4, 8, 3, device=dev))
+    one = torch.ones(1, device=dev)
+    sc = B.Scene(m, one, torch.zeros(3, device=dev), env)
+    ot = torch.from_numpy(o.astype(np.float32)).to(dev)
+    dt = torch.from_numpy(d.astype(np.float32)).to(dev)
+    tri_b, t_b, b_b = B.dt_intersect(sc, ot, dt, brute_force=False)
+    tri_f, t_f, b_f = B.dt_intersect(sc, ot, dt, brute_force=True)
+    tri_b, tri_f = tri_b.cpu().numpy(), tri_f.cpu().numpy()
+    assert (tri_b != -2).all(), "traversal stack overflow"
+    assert np.array_equal(tri_b, tri_f)
+    hit = tri_b >= 0
+    assert np.array_equal(t_b.cpu().numpy()[hit], t_f.cpu().numpy()[hit])
+    assert np.array_equal(b_b.cpu().numpy()[hit], b_f.cpu().numpy()[hit])
+    # against the FP64 oracle on the same float32 inputs
+    osc = oracle.Scene(V32.astype(np.float64), F, 1.0, 0.0, oracle.Env(tex=np.ones((4, 8, 3))), 4)
+    tri_o, t_o, b1_o, b2_o = osc.intersect(o.astype(np.float32).astype(np.float64),
+                                          d.astype(np.float32).astype(np.float64))
+    bb = b_b.cpu().numpy()
+    margin = np.minimum(np.minimum(b1_o, b2_o), 1 - b1_o - b2_o)
+    safe = (tri_o >= 0) & (margin > 1e-4)
+    _print(which, "hits", hit.mean(), "safe", safe.mean())
+    assert np.array_equal(tri_b[safe], tri_o[safe])
+    tb = t_b.cpu().numpy()
+    assert np.all(np.abs(tb[safe] - t_o[safe]) <= 1e-5 * np.maximum(t_o[safe], 1e-2))
+    assert np.all(np.abs(bb[safe, 0] - b1_o[safe]) <= 1e-4)
+    # misses agree except near silhouettes
+    assert ((tri_b >= 0) == (tri_o >= 0)).mean() > 0.999
+
+
+# ---------------------------------------------------------------- a6 environment
+def test_env_query_and_backward():
+    dev = device()
+    tex = synth.env_equirect(512, 256, seed=2)
+    env = B.Env(torch.from_numpy(tex).to(dev))
+    oenv = oracle.Env(tex=tex)
+    rng = np.random.default_rng(3)
+    d = rng.normal(size=(50000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d32 = d.astype(np.float32)
+    dt = torch.from_numpy(d32).to(dev)
+    E = B.dt_env_query(env, dt).cpu().numpy()
+    Eo = oenv.eval(d32.astype(np.float64))
+    err = rel_err(E, Eo)
+    _print("env max rel err", err.max(), "p999", np.quantile(err, 0.999))
+    assert np.quantile(err, 0.999) < 1e-4
+    g = rng.normal(size=d.shape).astype(np.float32)
+    gd = B.dt_env_query_backward(env, dt, torch.from_numpy(g).to(dev)).cpu().numpy()
+    gdo = oenv.eval_grad(d32.astype(np.float64), g.astype(np.float64))
+    num = np.linalg.norm(gd - gdo, axis=1)
+    den = np.linalg.norm(gdo, axis=1) + 1e-3
+    _print("env grad rel err p99", np.quantile(num / den, 0.99))
+    # directions next to a texel-cell edge may pick the other cell in FP32
+    assert np.quantile(num / den, 0.99) < 1e-3
+
+
+# ---------------------------------------------------------------- a3-a6 forward radiance
+@pytest.mark.parametrize("sigma", [(0.0, 0.0, 0.0), (0.5, 0.2, 0.1)])
+def test_forward_icosphere(sigma):
+    P = icosphere_pair(sigma=sigma)
+    _, rgb, wt, fl = P.gpu_forward(tape=False)
+    ref = P.orc.trace(P.o, P.d)
+    assert not (fl & HARD).any()
+    ok = ((fl | ref["flags"]) & BAD) == 0
+    err = rel_err(rgb, ref["rgb"])
+    _print("C1 sigma", sigma, "excluded", 1 - ok.mean(), "max err", err[ok].max())
+    assert 1 - ok.mean() < 0.05
+    assert err[ok].max() <= 1e-4
+    np.testing.assert_allclose(wt[ok], ref["wtrunc"][ok], rtol=1e-4, atol=1e-6)
+
+
+def test_forward_energy_conservation():
+    """sigma = 0 and a unit environment: every pixel is 1 - W_trunc, and 1 with
+    the environment taken at truncation."""
+    dev = device()
+    V, F = synth.displaced_torus(seed=2, nu=160, nv=80)
+    cams = [synth.look_at_camera(e, 64, 64) for e in synth.views_on_sphere(2, 3.0, seed=4)]
+    P = Pair(V, F, 1.5, 0.0, synth.env_constant(16, 8), cams, 6)
+    _, rgb, wt, fl = P.gpu_forward(tape=False)
+    assert np.abs(rgb - (1.0 - wt)).max() < 2e-5
+    P2 = Pair(V, F, 1.5, 0.0, synth.env_constant(16, 8), cams, 6, terminal_env=True)
+    _, rgb2, _, _ = P2.gpu_forward(tape=False)
+    assert np.abs(rgb2 - 1.0).max() < 2e-5
+
+
+def test_forward_torus_small():
+    P = torus_pair(n_views=2, res=96)
+    buf, rgb, wt, fl = P.gpu_forward(tape=False)
+    ref = P.orc.trace(P.o, P.d)
+    assert not (fl & HARD).any()
+    ok = ((fl | ref["flags"]) & BAD) == 0
+    err = rel_err(rgb, ref["rgb"])
+    bad = ok[:, None] & (err > 1e-4)
+    _print("torus excluded", 1 - ok.mean(), "max err", err[ok].max(), "n>1e-4", bad.any(1).sum())
+    stats = buf.stats.cpu().numpy()
+    _print("segments gpu", stats[B.STAT_TOTAL], "oracle", ref["nseg"].sum())
+    assert 1 - ok.mean() < 0.05
+    assert bad.any(1).mean() < 1e-3
+    assert abs(stats[B.STAT_TOTAL] - ref["nseg"].sum()) <= 1e-3 * ref["nseg"].sum()
+
+
+# ---------------------------------------------------------------- a7 gradients
+def _grad_check(P, seed=0):
+    buf, rgb, wt, fl = P.gpu_forward(tape=True)
+    ref = P.orc.trace(P.o, P.d)
+    ok = ((fl | ref["flags"]) & (BAD | HARD)) == 0
+    g = np.random.default_rng(seed).normal(size=rgb.shape) * ok[:, None]
+    dV, de, ds = P.gpu_backward(buf, g)
+    o = P.orc.trace_grad(P.o, P.d, g)
+    ev = np.linalg.norm(dV - o["dV"]) / np.linalg.norm(o["dV"])
+    ee = abs(de - o["d_eta"]) / abs(o["d_eta"])
+    es = np.abs(ds - o["d_sigma"]) / np.abs(o["d_sigma"])
+    _print("grad rel err dV", ev, "deta", ee, "dsigma", es)
+    return ev, ee, es
+
+
+@pytest.mark.parametrize("sigma", [(0.0, 0.0, 0.0), (0.5, 0.2, 0.1)])
+def test_backward_icosphere(sigma):
+    P = icosphere_pair(sigma=sigma)
+    ev, ee, es = _grad_check(P)
+    assert ev <= 1e-3 and ee <= 1e-3 and (es <= 1e-3).all()
+
+
+def test_backward_torus_small():
+    P = torus_pair(n_views=2, res=64)
+    ev, ee, es = _grad_check(P, seed=1)
+    assert ev <= 1e-3 and ee <= 1e-3 and (es <= 1e-3).all()
+
+
+# ---------------------------------------------------------------- a8 recompute == store
+@pytest.mark.parametrize("stride", [2, 3, 7])
+def test_recompute_matches_store_all(stride):
+    P = torus_pair(n_views=2, res=64)
+    buf, rgb, _, fl = P.gpu_forward(tape=True)
+    g = np.random.default_rng(2).normal(size=rgb.shape)
+    dV1, de1, ds1 = P.gpu_backward(buf, g)
+    p2 = B.Params(max_depth=P.depth, checkpoint_stride=stride)
+    buf2, rgb2, _, _ = P.gpu_forward(tape=True, params=p2)
+    assert np.array_equal(rgb, rgb2) or np.abs(rgb - rgb2).max() < 1e-6
+    dV2, de2, ds2 = P.gpu_backward(buf2, g, params=p2)
+    assert np.linalg.norm(dV1 - dV2) <= 1e-6 * np.linalg.norm(dV1) + 1e-9
+    assert abs(de1 - de2) <= 1e-6 * abs(de1) + 1e-9
+    assert np.all(np.abs(ds1 - ds2) <= 1e-6 * np.abs(ds1) + 1e-9)
+    assert buf2.tape_bytes < buf.tape_bytes
+
+
+def test_queue_overflow_is_reported():
+    """A queue too small for the tree drops children and says so per pixel."""
+    P = icosphere_pair(res=32, capacity=700)
+    buf, rgb, wt, fl = P.gpu_forward(tape=False)
+    stats = buf.stats.cpu().numpy()
+    assert stats[B.STAT_DROPPED] > 0
+    assert (fl & B.FLAG_OVERFLOW).any()
