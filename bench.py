@@ -1,0 +1,270 @@
+#!/usr/bin/env python
+"""Throughput of the differentiable transparent-mesh tracer on one MI355X.
+
+Workload: seeded displaced torus (102,400 triangles, genus 1), IoR 1.45,
+sigma 0.3, eight 512x512 views from a sphere of radius 3, depth 6, 512x256
+FP32 equirect environment.  One step = the whole hot path over the batch:
+vertex normals + LBVH rebuild, camera rays, the wavefront forward (trace,
+shade, compaction, environment, pixel accumulation) with its tape, the
+gradient of an L2 loss, and the adjoint sweep to dV, dIoR, dsigma.
+
+Metric: Mrays/s = ray segments intersected per step (every generation,
+counted once) / step time.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Mrays/s fwd+bwd at depth 6 (1 GPU) vs plain tracer; p50/p99 render latency"
+
+# algorithmic bytes per ray of each kernel (compulsory traffic; BVH node
+# reads are cache-resident and counted separately)
+TRACE_PER_RAY = 48 + 16 + 4          # ray record in, hit + decision out
+TRACE_PER_HIT = 12 + 36 + 48         # face row, 3 vertices, 3 vertex normals
+TRACE_PER_MISS = 48 + 12             # 4 texels, pixel accumulation
+ADJ_PER_RAY = 48 + 16 + 4 + 8 + 12 + 48   # ray, hit, decision, children, dL/dC, adjoint out
+ADJ_PER_HIT = 96 + 96 + 36 + 36      # geometry, 2 child adjoints, dV and dN updates
+ADJ_PER_MISS = 48                    # 4 texels
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--views", type=int, default=8)
+    ap.add_argument("--res", type=int, default=512)
+    ap.add_argument("--stride", type=int, default=1, help="checkpoint stride of the backward")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stride", type=int, default=2,
+                    help="oracle baseline traces every n-th pixel in x and y")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="run a plain 1 GiB device copy (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU path is a design note, not a runnable configuration", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2603_00413_amd import binding as B
+    from paper_2603_00413_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    if args.copy_only:
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": 4 * n}))
+        return
+
+    wl = synth.torus_scene(n_views=args.views, res=args.res)
+    log(f"scene {wl.name}: nv={len(wl.V)} nf={len(wl.F)} views={len(wl.cameras)} res={args.res}")
+    V = torch.from_numpy(wl.V.astype(np.float32)).to(dev)
+    F = torch.from_numpy(wl.F).to(dev)
+    mesh = B.Mesh(V, F)
+    env = B.Env(torch.from_numpy(wl.env).to(dev))
+    ior = torch.tensor([wl.ior], dtype=torch.float32, device=dev)
+    sigma = torch.tensor(wl.sigma, dtype=torch.float32, device=dev)
+    scene = B.Scene(mesh, ior, sigma, env)
+    rays = B.Rays(cameras=wl.cameras)
+    N = rays.n_rays
+
+    # queue capacity: grow until nothing is dropped, then size to the
+    # largest generation with 5 % headroom
+    cap = 2 * N
+    while True:
+        p = B.Params(max_depth=wl.max_depth, queue_capacity=cap)
+        buf = B.Buffers(p, rays, mesh, tape=False)
+        B.dt_trace_forward(scene, rays, p, buf, want_aux=False)
+        st = buf.stats.cpu().numpy()
+        if st[B.STAT_DROPPED] == 0:
+            break
+        cap *= 2
+    counts = st[:wl.max_depth + 1].astype(np.int64)
+    hits = st[B.STAT_HITS:B.STAT_HITS + wl.max_depth + 1].astype(np.int64)
+    cap = int(max(counts[1:].max() * 1.05, 2048))
+    del buf
+    segs = int(counts.sum())
+    log(f"rays per generation {counts.tolist()} hits {hits.tolist()} total {segs} capacity {cap}")
+
+    params = B.Params(max_depth=wl.max_depth, queue_capacity=cap, checkpoint_stride=args.stride)
+    buf = B.Buffers(params, rays, mesh, tape=True)
+    log(f"workspace {buf.ws_bytes / 2**30:.2f} GiB tape {buf.tape_bytes / 2**30:.2f} GiB")
+
+    # L2 loss against a target rendered with other material parameters
+    tscene = B.Scene(mesh, torch.tensor([1.5], device=dev), torch.tensor([0.25, 0.3, 0.35], device=dev), env)
+    target, _, _ = B.dt_trace_forward(tscene, rays, params, buf, want_aux=False)
+    target = target.clone()
+
+    def step():
+        mesh.build()
+        rgb, _, _ = B.dt_trace_forward(scene, rays, params, buf, want_aux=False)
+        grad = (rgb - target) * (2.0 / rgb.numel())
+        return B.dt_trace_backward(scene, rays, params, buf, grad)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    st = buf.stats.cpu().numpy()
+    assert st[B.STAT_DROPPED] == 0 and int(st[B.STAT_TOTAL]) == segs
+
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    mrays = segs / (elapsed / args.steps) / 1e6
+
+    # forward-only plain tracer on the same batch (context)
+    pf = B.Params(max_depth=wl.max_depth, queue_capacity=cap)
+    buf_f = B.Buffers(pf, rays, mesh, tape=False)
+    for _ in range(2):
+        B.dt_trace_forward(scene, rays, pf, buf_f, want_aux=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nf_steps = max(args.steps, 3)
+    for _ in range(nf_steps):
+        B.dt_trace_forward(scene, rays, pf, buf_f, want_aux=False)
+    torch.cuda.synchronize()
+    fwd_ms = 1e3 * (time.perf_counter() - t1) / nf_steps
+    del buf_f
+
+    # per-kernel durations of the instrumented steps, on the library's stream
+    timer = B.KernelTimer(wl.max_depth)
+    params_t = B.Params(max_depth=wl.max_depth, queue_capacity=cap,
+                        checkpoint_stride=args.stride, timing=timer)
+    G = wl.max_depth + 1
+    tr_ms, ad_ms = np.zeros(G), np.zeros(G)
+    reps = 3
+    for _ in range(reps):
+        mesh.build()
+        rgb, _, _ = B.dt_trace_forward(scene, rays, params_t, buf, want_aux=False)
+        grad = (rgb - target) * (2.0 / rgb.numel())
+        B.dt_trace_backward(scene, rays, params_t, buf, grad)
+        torch.cuda.synchronize()
+        tr_ms += np.array(timer.trace_ms(G)) / reps
+        ad_ms += np.array(timer.adjoint_ms(G)) / reps
+    miss = counts - hits
+    tr_bytes = counts * TRACE_PER_RAY + hits * TRACE_PER_HIT + miss * TRACE_PER_MISS
+    ad_bytes = counts * ADJ_PER_RAY + hits * ADJ_PER_HIT + miss * ADJ_PER_MISS
+    kernels = {
+        "k_trace": (tr_ms, tr_bytes),
+        "k_adjoint": (ad_ms, ad_bytes),
+    }
+    dom = max(kernels, key=lambda k: kernels[k][0].sum())
+    kms, kb = kernels[dom]
+    launches = int((counts > 0).sum())
+    avg_ms = float(kms.sum() / launches)
+    bytes_per_launch = float(kb.sum() / launches)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    log(f"step {ms_step:.2f} ms; forward-only {fwd_ms:.2f} ms; k_trace per gen ms {np.round(tr_ms, 3).tolist()}; "
+        f"k_adjoint per gen ms {np.round(ad_ms, 3).tolist()}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_stride)
+
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": round(mrays, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded displaced torus, seeded sky map, seeded views)",
+        "config": {
+            "workload": "torus-102k fwd+bwd: 102,400 tris, 8 views x 512x512, depth 6, "
+                        "IoR 1.45, sigma 0.3, env 512x256 f32, LBVH rebuilt every step",
+            "camera_rays": N,
+            "segments_per_step": segs,
+            "checkpoint_stride": args.stride,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom,
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None,
+            "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_bytes_per_launch": int(bytes_per_launch),
+        },
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+        "plain_forward": {"ms": round(fwd_ms, 3), "Mrays/s": round(segs / fwd_ms / 1e3, 3)},
+        "kernel_ms_per_generation": {"k_trace": np.round(tr_ms, 4).tolist(),
+                                     "k_adjoint": np.round(ad_ms, 4).tolist()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, stride):
+    """The FP64 oracle (forward + reverse-mode gradient) on a stratified
+    sample of the same workload: every `stride`-th pixel in x and y of
+    every view."""
+    import oracle
+    sc = oracle.Scene(wl.V, wl.F, wl.ior, wl.sigma, oracle.Env(tex=wl.env), wl.max_depth)
+    o, d = [], []
+    for cam in wl.cameras:
+        oo, dd = oracle.camera_rays(cam)
+        W, H = cam.width, cam.height
+        sel = (np.arange(H)[:, None] % stride == 0) & (np.arange(W)[None, :] % stride == 0)
+        sel = sel.reshape(-1)
+        o.append(oo[sel])
+        d.append(dd[sel])
+    o, d = np.concatenate(o), np.concatenate(d)
+    g = np.random.default_rng(0).normal(size=o.shape)
+    segs = int(sc.trace(o, d)["nseg"].sum())     # segment count (not timed)
+    t = time.perf_counter()
+    sc.trace_grad(o, d, g)                        # forward + gradient on the tape
+    el = time.perf_counter() - t
+    log(f"cpu baseline: {len(o)} camera rays, {segs} segments, {el:.1f} s")
+    return {"value": round(segs / el / 1e6, 4), "unit": "Mrays/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"every {stride}th pixel in x and y of all {len(wl.cameras)} views "
+                      f"({len(o)} camera rays, {segs} segments); FP64 forward + reverse-mode "
+                      f"gradient in one pass per camera ray",
+            "seconds": round(el, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -57,20 +57,25 @@ typedef int32_t dt_status;
 /* per-pixel flags (bit set if any node of the pixel's ray tree had it) */
 #define DT_FLAG_DEGEN 1     /* shading normal faced away; geometric normal used */
 #define DT_FLAG_LEAK 2      /* a ray inside the object left it without a hit */
-#define DT_FLAG_GRAZING 4   /* cos(theta_i) < 0.02 at some hit */
-#define DT_FLAG_TIRB 8      /* |1 - sin^2(theta_t)| < 1e-3 at some hit */
+#define DT_FLAG_GRAZING 4   /* cos(theta_i) < 0.1 at some hit */
+#define DT_FLAG_TIRB 8      /* |1 - sin^2(theta_t)| < 1e-2 at some hit */
 #define DT_FLAG_TRUNC 16    /* some hit reached the depth cap */
 #define DT_FLAG_OVERFLOW 32 /* a child ray was dropped: ray queue full */
 #define DT_FLAG_STACK 64    /* BVH traversal stack overflowed (result invalid) */
 
 #define DT_MAX_DEPTH 16
-#define DT_STATS_LEN 40
-/* stats layout (int64, device): [0..DT_MAX_DEPTH] rays intersected in each
- * generation, [32] total rays, [33] dropped children, [34] generations run,
- * [35] BVH depth used by traversal.  Written by dt_trace_forward. */
-#define DT_STAT_TOTAL 32
-#define DT_STAT_DROPPED 33
-#define DT_STAT_GENERATIONS 34
+#define DT_STATS_LEN 64
+/* stats layout (int64, device), written by dt_trace_forward:
+ *   [g]      for g in 0..16: rays intersected in generation g
+ *   [17 + g] for g in 0..16: of those, rays that hit the mesh
+ *   [48] total rays, [49] dropped children, [50] generations run,
+ *   [51] height of the BVH, [52] total hits */
+#define DT_STAT_HITS 17
+#define DT_STAT_TOTAL 48
+#define DT_STAT_DROPPED 49
+#define DT_STAT_GENERATIONS 50
+#define DT_STAT_BVH_DEPTH 51
+#define DT_STAT_TOTAL_HITS 52
 
 /* ------------------------------------------------------------------ mesh */
 
@@ -135,6 +140,16 @@ typedef struct {
   const dt_env* env;   /* HOST struct describing device data */
 } dt_scene;
 
+/* Optional kernel timing (HOST struct of caller-created hipEvent_t handles):
+ * when given, the forward records trace_events[2g] / [2g+1] around the
+ * traversal kernel of generation g, and the backward records
+ * adjoint_events[2g] / [2g+1] around the adjoint kernel of generation g.
+ * Arrays must hold 2 * (max_depth + 1) events; NULL arrays are skipped. */
+typedef struct {
+  void* const* trace_events;
+  void* const* adjoint_events;
+} dt_timing;
+
 typedef struct {
   int32_t max_depth;          /* D in [0, 16]: generations 0..D are intersected,
                                  a hit in generation D is truncated */
@@ -145,6 +160,7 @@ typedef struct {
                                  recompute the rest (1 = store all) */
   int64_t queue_capacity;     /* max rays per generation >= 1
                                  (0 = worst case n_rays * 2^g) */
+  const dt_timing* timing;    /* optional, NULL = no event records */
 } dt_trace_params;
 
 /* Pinhole camera (HOST struct): right-handed, vertical FOV, image row 0 at

@@ -200,8 +200,8 @@ typedef struct {
 enum {
   OR_FLAG_DEGEN = 1,    // shading normal on the wrong side, geometric normal used
   OR_FLAG_LEAK = 2,     // a ray inside the object escaped without a hit
-  OR_FLAG_GRAZING = 4,  // cos(theta_i) < 0.02 somewhere on the path
-  OR_FLAG_TIRB = 8,     // |1 - sin^2 theta_t| < 1e-3 somewhere (TIR boundary)
+  OR_FLAG_GRAZING = 4,  // cos(theta_i) < 0.1 somewhere on the path
+  OR_FLAG_TIRB = 8,     // |1 - sin^2 theta_t| < 1e-2 somewhere (TIR boundary)
   OR_FLAG_TRUNC = 16,   // some hit reached the depth cap
 };
 
@@ -646,7 +646,9 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
     if (!entering) n = scl(n, S(-1.0));
     cos_i = -dot(d, n);
   }
-  if (val(cos_i) < 0.02) pi.flags |= OR_FLAG_GRAZING;
+  // grazing / TIR-boundary markers: either cosine below 0.1, where the Fresnel
+  // and refraction derivatives (which scale like 1/cos) are ill-conditioned
+  if (val(cos_i) < 0.1) pi.flags |= OR_FLAG_GRAZING;
   // eta_r = eta_t / eta_i, ambient medium 1
   S eta_i = entering ? S(1.0) : cx.eta;
   S eta_t = entering ? cx.eta : S(1.0);
@@ -682,7 +684,7 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
   }
   // Snell: sin^2(theta_t) = sin^2(theta_i) / eta_r^2
   S sin2t = (S(1.0) - cos_i * cos_i) / (eta_r * eta_r);
-  if (std::fabs(1.0 - val(sin2t)) < 1e-3) pi.flags |= OR_FLAG_TIRB;
+  if (std::fabs(1.0 - val(sin2t)) < 1e-2) pi.flags |= OR_FLAG_TIRB;
   // Eq. 3 with omega_i = -d
   V3<S> rdir = normalize(add(d, scl(n, S(2.0) * cos_i)));
   bool tir = val(sin2t) > 1.0;

@@ -22,8 +22,9 @@ DT_OK = 0
 FLAG_DEGEN, FLAG_LEAK, FLAG_GRAZING, FLAG_TIRB, FLAG_TRUNC, FLAG_OVERFLOW, FLAG_STACK = \
     1, 2, 4, 8, 16, 32, 64
 MAX_DEPTH = 16
-STATS_LEN = 40
-STAT_TOTAL, STAT_DROPPED, STAT_GENERATIONS, STAT_BVH_DEPTH = 32, 33, 34, 35
+STATS_LEN = 64
+STAT_HITS = 17
+STAT_TOTAL, STAT_DROPPED, STAT_GENERATIONS, STAT_BVH_DEPTH, STAT_TOTAL_HITS = 48, 49, 50, 51, 52
 ENV_EQUIRECT, ENV_MLP = 0, 1
 RAYS_EXPLICIT, RAYS_CAMERAS = 0, 1
 
@@ -45,9 +46,14 @@ class _Scene(C.Structure):
                 ("env", C.POINTER(_Env))]
 
 
+class _Timing(C.Structure):
+    _fields_ = [("trace_events", C.POINTER(C.c_void_p)), ("adjoint_events", C.POINTER(C.c_void_p))]
+
+
 class _Params(C.Structure):
     _fields_ = [("max_depth", C.c_int32), ("terminal_env", C.c_int32), ("t_eps", C.c_float),
-                ("checkpoint_stride", C.c_int32), ("queue_capacity", C.c_int64)]
+                ("checkpoint_stride", C.c_int32), ("queue_capacity", C.c_int64),
+                ("timing", C.POINTER(_Timing))]
 
 
 class _Camera(C.Structure):
@@ -201,12 +207,52 @@ class Params:
     t_eps: float = 1e-5
     checkpoint_stride: int = 1
     queue_capacity: int = 0
+    timing: object = None   # KernelTimer or None
 
     def c(self) -> _Params:
         p = _Params()
         p.max_depth, p.terminal_env, p.t_eps = self.max_depth, int(self.terminal_env), self.t_eps
         p.checkpoint_stride, p.queue_capacity = self.checkpoint_stride, int(self.queue_capacity)
+        if self.timing is not None:
+            p.timing = C.pointer(self.timing.s)
         return p
+
+
+class KernelTimer:
+    """hipEvent pairs the library records around its traversal and adjoint
+    kernels (one pair per generation), read back as milliseconds."""
+
+    def __init__(self, max_depth: int):
+        self.hip = C.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [C.c_void_p]
+        n = 2 * (max_depth + 1)
+        self.n = n
+        self.trace = (C.c_void_p * n)()
+        self.adjoint = (C.c_void_p * n)()
+        for arr in (self.trace, self.adjoint):
+            for i in range(n):
+                ev = C.c_void_p()
+                if self.hip.hipEventCreate(C.byref(ev)) != 0:
+                    raise DTError("hipEventCreate failed")
+                arr[i] = ev
+        self.s = _Timing()
+        self.s.trace_events = C.cast(self.trace, C.POINTER(C.c_void_p))
+        self.s.adjoint_events = C.cast(self.adjoint, C.POINTER(C.c_void_p))
+
+    def _ms(self, arr, g):
+        self.hip.hipEventSynchronize(arr[2 * g + 1])
+        ms = C.c_float()
+        if self.hip.hipEventElapsedTime(C.byref(ms), arr[2 * g], arr[2 * g + 1]) != 0:
+            return float("nan")
+        return ms.value
+
+    def trace_ms(self, gens: int):
+        return [self._ms(self.trace, g) for g in range(gens)]
+
+    def adjoint_ms(self, gens: int):
+        return [self._ms(self.adjoint, g) for g in range(gens)]
 
 
 class Rays:

@@ -388,8 +388,9 @@ __device__ __forceinline__ Shade shade(const SceneDev& sc, const HitGeo& g, v3 o
   if (entering) code |= C_ENTER;
   if (tir) code |= C_TIR;
   if (degen) code |= C_DEGEN;
-  if (ci < 0.02f) code |= C_GRAZE;
-  if (fabsf(1.f - s.sin2t) < 1e-3f) code |= C_TIRB;
+  // markers of ill-conditioned hits: cos(theta_i) or cos(theta_t) below 0.1
+  if (ci < 0.1f) code |= C_GRAZE;
+  if (fabsf(1.f - s.sin2t) < 1e-2f) code |= C_TIRB;
   s.code = code;
   return s;
 }

@@ -37,6 +37,7 @@ struct Counters {
   uint32_t count[DT_MAX_DEPTH + 2];
   uint32_t nrefl[DT_MAX_DEPTH + 2];
   uint32_t work[DT_MAX_DEPTH + 2];
+  uint32_t hits[DT_MAX_DEPTH + 2];
   uint32_t dropped;
   uint32_t pad[3];
 };
@@ -176,6 +177,7 @@ __global__ void k_init_counters(Counters* c, uint32_t n0) {
       c->count[g] = 0;
       c->nrefl[g] = 0;
       c->work[g] = 0;
+      c->hits[g] = 0;
     }
     c->count[0] = n0;
     c->dropped = 0;
@@ -199,17 +201,20 @@ __global__ void k_reset_work(Counters* c, int g) {
 
 __global__ void k_stats(const Counters* c, int D, const BvhHeader* hdr, int64_t* stats) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    int64_t tot = 0, gens = 0;
+    int64_t tot = 0, gens = 0, hits = 0;
     for (int i = 0; i < DT_STATS_LEN; ++i) stats[i] = 0;
     for (int g = 0; g <= D; ++g) {
       stats[g] = c->count[g];
+      stats[DT_STAT_HITS + g] = c->hits[g];
       tot += c->count[g];
+      hits += c->hits[g];
       if (c->count[g]) gens = g + 1;
     }
     stats[DT_STAT_TOTAL] = tot;
     stats[DT_STAT_DROPPED] = c->dropped;
     stats[DT_STAT_GENERATIONS] = gens;
-    stats[35] = hdr->depth;
+    stats[DT_STAT_BVH_DEPTH] = hdr->depth;
+    stats[DT_STAT_TOTAL_HITS] = hits;
   }
 }
 
@@ -280,7 +285,7 @@ __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counter
     if (base >= n) break;
     uint32_t i = base + lane;
     bool active = i < n;
-    bool has_r = false, has_t = false;
+    bool has_r = false, has_t = false, hit = false;
     if (active) {
       float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i];
       v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
@@ -296,6 +301,7 @@ __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counter
         if (rfl & RAY_INSIDE) pf |= DT_FLAG_LEAK;
         if (accumulate) add_rgb(rgb, pix, mul3(W, env_equirect(sc.env, d)));
       } else {
+        hit = true;
         HitGeo geo = load_geo(sc, h.tri);
         Shade s = shade(sc, geo, o, d, h.t, h.b1, h.b2, 0u);
         code = s.code;
@@ -322,10 +328,11 @@ __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counter
       q.code[i] = code;
       if (accumulate && flags && pf) atomicOr(flags + pix, pf);
     }
-    uint64_t br = __ballot(has_r), bt = __ballot(has_t);
+    uint64_t br = __ballot(has_r), bt = __ballot(has_t), bh = __ballot(hit);
     if (lane == 0 && (br | bt))
       atomicAdd(part + base / CHUNK,
                 (unsigned long long)__popcll(br) | ((unsigned long long)__popcll(bt) << 32));
+    if (lane == 0 && bh && accumulate) atomicAdd(&ctr->hits[g], (uint32_t)__popcll(bh));
   }
 }
 
@@ -864,13 +871,20 @@ dt_status emit_rays(const dt_rays* r, Gen g0, hipStream_t s) {
 }
 
 // run generation g of the wavefront: trace, and (g < D) scan + emit
+dt_status record(void* const* ev, int i, hipStream_t s) {
+  if (ev && ev[i]) DT_CHECK_HIP(hipEventRecord((hipEvent_t)ev[i], s));
+  return DT_OK;
+}
+
 dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen nxt, Counters* ctr,
                          unsigned long long* part_g, unsigned long long* part_other, float* rgb,
                          float* wtrunc, int32_t* flags, int accumulate, int write_next,
-                         hipStream_t s) {
+                         void* const* events, hipStream_t s) {
+  if (dt_status st = record(events, 2 * g, s)) return st;
   hipLaunchKernelGGL(k_trace, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
                      rgb, wtrunc, flags, accumulate);
   DT_CHECK_LAUNCH();
+  if (dt_status st = record(events, 2 * g + 1, s)) return st;
   if (g < P.D) {
     int64_t other_n = (P.cap[g + 1] + CHUNK - 1) / CHUNK + 1;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctr, g, part_g, part_other, other_n,
@@ -975,8 +989,9 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
     if (g == 0)
       if (dt_status st = emit_rays(rays, cur, s)) return st;
     Gen nxt = g < P.D ? gen_fwd(g + 1) : cur;
+    void* const* ev = p->timing ? p->timing->trace_events : nullptr;
     if (dt_status st = run_generation(sc, P, g, cur, nxt, ctr, part[g & 1], part[(g + 1) & 1], rgb,
-                                      wtrunc, flags, 1, 1, s))
+                                      wtrunc, flags, 1, 1, ev, s))
       return st;
   }
   if (T) hipLaunchKernelGGL(k_save_counters, dim3(1), dim3(64), 0, s, (Counters*)(T + P.tape_hdr), ctr);
@@ -1021,13 +1036,15 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     adj[b].O = (float4*)(W + P.w_adj[b][1]);
     adj[b].D = (float4*)(W + P.w_adj[b][2]);
   }
+  void* const* aev = p->timing ? p->timing->adjoint_events : nullptr;
   auto adjoint = [&](int g, Gen q) -> dt_status {
     int64_t blocks = (P.cap[g] + AB - 1) / AB;
     if (blocks > 4096) blocks = 4096;
+    if (dt_status st = record(aev, 2 * g, s)) return st;
     hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
                        adj[(g + 1) & 1], adj[g & 1], dV, dN, d_ior, d_sigma);
     DT_CHECK_LAUNCH();
-    return DT_OK;
+    return record(aev, 2 * g + 1, s);
   };
   if (P.store_all) {
     for (int g = P.D; g >= 0; --g) {
@@ -1061,7 +1078,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
         int j = g - g0;
         Gen nxt = g < g1 ? seg[j + 1] : seg[j];
         if (dt_status st = run_generation(sc, P, g, seg[j], nxt, ctr, part[g & 1], part[(g + 1) & 1],
-                                          nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0, s))
+                                          nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0, nullptr, s))
           return st;
       }
       for (int g = g1; g >= g0; --g)
