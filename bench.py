@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--res", type=int, default=512)
     ap.add_argument("--stride", type=int, default=1, help="checkpoint stride of the backward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-stride", type=int, default=2,
+    ap.add_argument("--cpu-stride", type=int, default=1,
                     help="oracle baseline traces every n-th pixel in x and y")
     ap.add_argument("--copy-only", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")

@@ -223,7 +223,9 @@ class KernelTimer:
     kernels (one pair per generation), read back as milliseconds."""
 
     def __init__(self, max_depth: int):
-        self.hip = C.CDLL("libamdhip64.so")
+        # the HIP runtime the library itself is bound to (dlsym searches the
+        # library's dependencies), so events and streams share one runtime
+        self.hip = load()
         self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
         self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
         self.hip.hipEventSynchronize.argtypes = [C.c_void_p]

@@ -210,3 +210,37 @@ def test_queue_overflow_is_reported():
     stats = buf.stats.cpu().numpy()
     assert stats[B.STAT_DROPPED] > 0
     assert (fl & B.FLAG_OVERFLOW).any()
+
+
+# ---------------------------------------------------------------- full benchmark size, sampled
+def test_full_size_torus_sampled_pixels():
+    """The benchmark workload (8 views x 512^2, depth 6, 102,400 tris) traced in
+    full on the device; the oracle checks 3,000 sampled pixels one by one, and
+    the gradient of a loss that weights only those pixels."""
+    dev = device()
+    wl = synth.torus_scene(n_views=8, res=512)
+    P = Pair(wl.V, wl.F, wl.ior, wl.sigma, wl.env, wl.cameras, wl.max_depth,
+             capacity=int(1.2 * 2 ** 21))
+    buf, rgb, wt, fl = P.gpu_forward(tape=True)
+    st = buf.stats.cpu().numpy()
+    assert st[B.STAT_DROPPED] == 0 and not (fl & HARD).any()
+    rng = np.random.default_rng(7)
+    pix = np.sort(rng.choice(len(P.o), 3000, replace=False))
+    ref = P.orc.trace(P.o[pix], P.d[pix])
+    ok = ((fl[pix] | ref["flags"]) & BAD) == 0
+    err = rel_err(rgb[pix], ref["rgb"])
+    bad = ok[:, None] & (err > 1e-4)
+    _print("full-size sampled: excluded", 1 - ok.mean(), "max err", err[ok].max(),
+           "pixels over 1e-4", bad.any(1).sum())
+    assert 1 - ok.mean() < 0.05
+    assert bad.any(1).mean() < 2e-3
+    g = np.zeros_like(rgb)
+    gs = rng.normal(size=(len(pix), 3)) * ok[:, None]
+    g[pix] = gs
+    dV, de, ds = P.gpu_backward(buf, g)
+    o = P.orc.trace_grad(P.o[pix], P.d[pix], gs)
+    ev = np.linalg.norm(dV - o["dV"]) / np.linalg.norm(o["dV"])
+    ee = abs(de - o["d_eta"]) / abs(o["d_eta"])
+    es = np.abs(ds - o["d_sigma"]) / np.abs(o["d_sigma"])
+    _print("full-size sampled grads: dV", ev, "deta", ee, "dsigma", es)
+    assert ev <= 1e-3 and ee <= 1e-3 and (es <= 1e-3).all()
