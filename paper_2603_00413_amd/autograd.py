@@ -1,0 +1,136 @@
+"""Differentiable rendering as a torch.autograd.Function.
+
+`render(V, ior, sigma)` traces every camera ray of a `Tracer` through the
+mesh (V, F) and returns pixel colours; its backward runs the device adjoint
+and returns dLoss/dV, dLoss/dIoR and dLoss/dsigma (paper Sec. 3.3: vertex
+positions, index of refraction and absorption rate are optimised jointly).
+
+Memory policy: the forward keeps the per-generation ray state the adjoint
+needs.  When storing every generation fits the memory budget it does so;
+otherwise it stores every k-th generation and the backward recomputes the
+others, with k the smallest stride whose tape + workspace fit the budget.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding as B
+
+
+def choose_stride(max_depth: int, n_rays: int, nv: int, nf: int, capacity: int,
+                  budget_bytes: int) -> int:
+    """Smallest checkpoint stride k (1 = store every generation) whose tape
+    plus workspace fit in budget_bytes; the stride of least memory if none fits."""
+    best_k, best_bytes = 1, None
+    for k in range(1, max_depth + 2):
+        p = B.Params(max_depth=max_depth, checkpoint_stride=k, queue_capacity=capacity)
+        ws, tape = B.dt_trace_bytes(p, n_rays, nv, nf)
+        if ws + tape <= budget_bytes:
+            return k
+        if best_bytes is None or ws + tape < best_bytes:
+            best_k, best_bytes = k, ws + tape
+    return best_k
+
+
+class Tracer:
+    """Fixed part of a differentiable render: faces, environment, cameras and
+    trace parameters.  Reuses its buffers between calls."""
+
+    def __init__(self, F: torch.Tensor, env: B.Env, cameras, max_depth: int = 6,
+                 memory_budget: int | None = None, queue_capacity: int | None = None,
+                 terminal_env: bool = False, t_eps: float = 1e-5):
+        self.F = F
+        self.env = env
+        self.rays = B.Rays(cameras=cameras)
+        self.max_depth = max_depth
+        self.terminal_env = terminal_env
+        self.t_eps = t_eps
+        self.memory_budget = memory_budget
+        self.capacity = queue_capacity or 2 * self.rays.n_rays
+        self.stride = None
+        self.last_stats = None
+        self._mesh = None
+        self._buf = None
+        self._key = None
+        self.version = 0     # bumped by every forward: the tape holds only the last one
+
+    def _params(self, stride=None, timing=None) -> B.Params:
+        return B.Params(max_depth=self.max_depth, terminal_env=self.terminal_env, t_eps=self.t_eps,
+                        checkpoint_stride=stride or self.stride or 1,
+                        queue_capacity=self.capacity, timing=timing)
+
+    def _budget(self, device) -> int:
+        if self.memory_budget is not None:
+            return int(self.memory_budget)
+        free, _ = torch.cuda.mem_get_info(device)
+        return int(0.5 * free)
+
+    def _prepare(self, V: torch.Tensor):
+        nv, nf = V.shape[0], self.F.shape[0]
+        if self._mesh is None or self._mesh.nv != nv or self._mesh.V.device != V.device:
+            self._mesh = B.Mesh(V, self.F)
+        else:
+            self._mesh.V = V
+            self._mesh.build()
+        key = (self.capacity, nv, nf)
+        if self._buf is None or self._key != key:
+            self.stride = choose_stride(self.max_depth, self.rays.n_rays, nv, nf, self.capacity,
+                                        self._budget(V.device))
+            self._buf = B.Buffers(self._params(), self.rays, self._mesh, tape=True)
+            self._key = key
+        return self._mesh, self._buf
+
+    def forward(self, V: torch.Tensor, ior: torch.Tensor, sigma: torch.Tensor):
+        V = V.detach().contiguous().float()
+        while True:
+            mesh, buf = self._prepare(V)
+            scene = B.Scene(mesh, ior.detach().contiguous().float(),
+                            sigma.detach().contiguous().float(), self.env)
+            rgb, _, _ = B.dt_trace_forward(scene, self.rays, self._params(), buf, want_aux=False)
+            stats = buf.stats.cpu()          # one small read: did a ray queue overflow?
+            self.last_stats = stats
+            if int(stats[B.STAT_DROPPED]) == 0:
+                self.version += 1
+                return rgb, scene, buf
+            self.capacity *= 2               # grow and trace again
+
+    def backward(self, scene, buf, grad_rgb: torch.Tensor, version: int):
+        if version != self.version:
+            raise B.DTError("this Tracer ran another forward since; its tape holds only the "
+                            "latest one (use one Tracer per outstanding graph)")
+        return B.dt_trace_backward(scene, self.rays, self._params(), buf,
+                                   grad_rgb.contiguous().float())
+
+
+class DTTrace(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, V, ior, sigma, tracer: Tracer):
+        rgb, scene, buf = tracer.forward(V, ior, sigma)
+        ctx.tracer, ctx.scene, ctx.buf, ctx.version = tracer, scene, buf, tracer.version
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        dV, d_ior, d_sigma = ctx.tracer.backward(ctx.scene, ctx.buf, grad_rgb, ctx.version)
+        return dV, d_ior.reshape(1), d_sigma.reshape(3), None
+
+
+def render(V: torch.Tensor, ior: torch.Tensor, sigma: torch.Tensor, tracer: Tracer):
+    """Pixel colours [n_pixels, 3], differentiable in V, ior and sigma.
+    sigma may be [3] (RGB) or [1] (one rate for all channels)."""
+    if sigma.numel() == 1:
+        return _BroadcastSigma.apply(V, ior, sigma, tracer)
+    return DTTrace.apply(V, ior, sigma, tracer)
+
+
+class _BroadcastSigma(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, V, ior, sigma, tracer):
+        rgb, scene, buf = tracer.forward(V, ior, sigma.expand(3))
+        ctx.tracer, ctx.scene, ctx.buf, ctx.version = tracer, scene, buf, tracer.version
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        dV, d_ior, d_sigma = ctx.tracer.backward(ctx.scene, ctx.buf, grad_rgb, ctx.version)
+        return dV, d_ior.reshape(1), d_sigma.sum().reshape(1), None

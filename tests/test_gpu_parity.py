@@ -244,3 +244,42 @@ def test_full_size_torus_sampled_pixels():
     es = np.abs(ds - o["d_sigma"]) / np.abs(o["d_sigma"])
     _print("full-size sampled grads: dV", ev, "deta", ee, "dsigma", es)
     assert ev <= 1e-3 and ee <= 1e-3 and (es <= 1e-3).all()
+
+
+# ---------------------------------------------------------------- a8 autograd.Function
+def test_autograd_function_and_memory_policy():
+    """loss.backward() through render() matches the direct C-ABI adjoint; a
+    memory budget too small for the full tape switches to recomputation with
+    the same gradients."""
+    from paper_2603_00413_amd.autograd import Tracer, choose_stride, render
+    dev = device()
+    P = torus_pair(n_views=2, res=64)
+    V = torch.from_numpy(P.V32).to(dev).requires_grad_(True)
+    ior = torch.tensor([float(P.ior)], device=dev, requires_grad=True)
+    sigma = torch.tensor([0.3], device=dev, requires_grad=True)
+    target = torch.rand(P.rays.n_pixels, 3, device=dev)
+    grads = []
+    for budget in (None, 1):
+        tr = Tracer(P.mesh.F, P.env, P.cams, max_depth=P.depth, memory_budget=budget)
+        V.grad = ior.grad = sigma.grad = None
+        loss = ((render(V, ior, sigma, tr) - target) ** 2).mean()
+        loss.backward()
+        grads.append((V.grad.clone(), ior.grad.clone(), sigma.grad.clone(), tr.stride))
+    assert grads[0][3] == 1 and grads[1][3] > 1
+    for a, b in zip(grads[0][:3], grads[1][:3]):
+        assert torch.linalg.norm(a - b) <= 1e-6 * torch.linalg.norm(a) + 1e-9
+    # direct adjoint with the same upstream gradient
+    buf, rgb, _, _ = P.gpu_forward(tape=True)
+    g = (2.0 / rgb.size) * (rgb - target.cpu().numpy())
+    dV, de, ds = P.gpu_backward(buf, g)
+    assert np.linalg.norm(grads[0][0].cpu().numpy() - dV) <= 1e-5 * np.linalg.norm(dV)
+    assert abs(float(grads[0][1]) - de) <= 1e-5 * abs(de)
+    assert abs(float(grads[0][2]) - ds.sum()) <= 1e-5 * abs(ds.sum())
+    # a second forward on the same Tracer invalidates the first graph's tape
+    tr = Tracer(P.mesh.F, P.env, P.cams, max_depth=P.depth)
+    out1 = render(V, ior, sigma, tr)
+    render(V, ior, sigma, tr)
+    with pytest.raises(B.DTError):
+        out1.sum().backward()
+    k = choose_stride(6, 1 << 20, 51200, 102400, 2 << 20, 1 << 62)
+    assert k == 1
