@@ -25,6 +25,7 @@ constexpr int TB = 64;                // threads per block of the traversal kern
 constexpr int CHUNK = 2048;           // rays per compaction chunk
 constexpr int EB = 256;               // threads per block of the emit kernel
 constexpr int AB = 256;               // threads per block of the adjoint kernel
+constexpr int ADJ_MAX_BLOCKS = 4096;  // grid cap of the adjoint kernel
 constexpr uint32_t RAY_INSIDE = 1u;   // ray flag: travelling inside the object
 
 struct Gen {
@@ -62,7 +63,7 @@ struct Plan {
   size_t w_ctr, w_part0, w_part1;
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
-  size_t w_dN, w_sbar;
+  size_t w_dN, w_sbar, w_red;
   size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
   size_t ws_bytes;
 };
@@ -142,6 +143,8 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = dt_align(o + 12 * (size_t)nv);
   P.w_sbar = o;
   o = dt_align(o + 16 * (size_t)nv);
+  P.w_red = o;  // per-(generation, block) partial sums of dIoR and dsigma
+  o = dt_align(o + 16 * (size_t)(DT_MAX_DEPTH + 1) * ADJ_MAX_BLOCKS);
   size_t kk = P.store_all ? 0 : (size_t)P.k;
   P.w_seg_o = o;
   o = dt_align(o + 16 * mc * kk);
@@ -473,7 +476,7 @@ __device__ __forceinline__ void atomic_add3(float* p, int idx, v3 v) {
 
 __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
                                                 const float* grad_rgb, Adj nxt, Adj cur, float* dV,
-                                                float* dN, float* d_eta, float* d_sigma) {
+                                                float* dN, float4* red) {
   const uint32_t n = ctr->count[g];
   float acc_eta = 0.f, acc_s0 = 0.f, acc_s1 = 0.f, acc_s2 = 0.f;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -642,22 +645,47 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
     cur.D[i] = make_float4(dbar.x, dbar.y, dbar.z, 0.f);
   }
   // block reduction of the scalar gradients
-  __shared__ float red[4][AB];
-  red[0][threadIdx.x] = acc_eta;
-  red[1][threadIdx.x] = acc_s0;
-  red[2][threadIdx.x] = acc_s1;
-  red[3][threadIdx.x] = acc_s2;
+  __shared__ float red_s[4][AB];
+  red_s[0][threadIdx.x] = acc_eta;
+  red_s[1][threadIdx.x] = acc_s0;
+  red_s[2][threadIdx.x] = acc_s1;
+  red_s[3][threadIdx.x] = acc_s2;
   __syncthreads();
   for (int st = AB / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st)
-      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + st];
+      for (int k = 0; k < 4; ++k) red_s[k][threadIdx.x] += red_s[k][threadIdx.x + st];
+    __syncthreads();
+  }
+  // one slot per block: the final sum runs in a fixed order, so the scalar
+  // gradients do not depend on the order blocks finish in
+  if (threadIdx.x == 0)
+    red[(size_t)g * ADJ_MAX_BLOCKS + blockIdx.x] = make_float4(red_s[0][0], red_s[1][0], red_s[2][0],
+                                                               red_s[3][0]);
+}
+
+// dIoR, dsigma = ordered sums of the per-(generation, block) partials
+__global__ void k_reduce_scalars(const float4* red, int n, float* d_eta, float* d_sigma) {
+  __shared__ double sh[4][256];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    float4 v = red[i];
+    a[0] += v.x;
+    a[1] += v.y;
+    a[2] += v.z;
+    a[3] += v.w;
+  }
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    if (red[0][0] != 0.f) atomicAdd(d_eta, red[0][0]);
-    if (red[1][0] != 0.f) atomicAdd(d_sigma, red[1][0]);
-    if (red[2][0] != 0.f) atomicAdd(d_sigma + 1, red[2][0]);
-    if (red[3][0] != 0.f) atomicAdd(d_sigma + 2, red[3][0]);
+    *d_eta = (float)sh[0][0];
+    d_sigma[0] = (float)sh[1][0];
+    d_sigma[1] = (float)sh[2][0];
+    d_sigma[2] = (float)sh[3][0];
   }
 }
 
@@ -1025,11 +1053,12 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
                                  (unsigned long long*)(W + P.w_part1)};
   float* dN = (float*)(W + P.w_dN);
   float4* sbar = (float4*)(W + P.w_sbar);
+  float4* red = (float4*)(W + P.w_red);
+  const int nred = (DT_MAX_DEPTH + 1) * ADJ_MAX_BLOCKS;
   hipLaunchKernelGGL(k_load_counters, dim3(1), dim3(64), 0, s, ctr, (const Counters*)(T + P.tape_hdr));
   if (dt_status st = zero_f32(dV, 3 * (int64_t)scene->nv, s)) return st;
   if (dt_status st = zero_f32(dN, 3 * (int64_t)scene->nv, s)) return st;
-  if (dt_status st = zero_f32(d_ior, 1, s)) return st;
-  if (dt_status st = zero_f32(d_sigma, 3, s)) return st;
+  if (dt_status st = zero_f32((float*)red, 4 * (int64_t)nred, s)) return st;
   Adj adj[2];
   for (int b = 0; b < 2; ++b) {
     adj[b].L = (float4*)(W + P.w_adj[b][0]);
@@ -1039,10 +1068,10 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   void* const* aev = p->timing ? p->timing->adjoint_events : nullptr;
   auto adjoint = [&](int g, Gen q) -> dt_status {
     int64_t blocks = (P.cap[g] + AB - 1) / AB;
-    if (blocks > 4096) blocks = 4096;
+    if (blocks > ADJ_MAX_BLOCKS) blocks = ADJ_MAX_BLOCKS;
     if (dt_status st = record(aev, 2 * g, s)) return st;
     hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                       adj[(g + 1) & 1], adj[g & 1], dV, dN, d_ior, d_sigma);
+                       adj[(g + 1) & 1], adj[g & 1], dV, dN, red);
     DT_CHECK_LAUNCH();
     return record(aev, 2 * g + 1, s);
   };
@@ -1085,6 +1114,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
         if (dt_status st = adjoint(g, seg[g - g0])) return st;
     }
   }
+  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(256), 0, s, red, nred, d_ior, d_sigma);
   hipLaunchKernelGGL(k_nbwd_vertex, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, dN, sbar);
   hipLaunchKernelGGL(k_nbwd_face, dim3(dt_blocks(scene->nf, 256)), dim3(256), 0, s, sc.bvh, sc.V, sc.F,
                      sbar, dV);
