@@ -41,7 +41,8 @@ class _Env(C.Structure):
     _fields_ = [("kind", C.c_int), ("W", C.c_int), ("H", C.c_int),
                 ("tex", C.POINTER(C.c_double)), ("n_freq", C.c_int),
                 ("n_layers", C.c_int), ("width", C.c_int), ("in_pad", C.c_int),
-                ("weights", C.POINTER(C.c_double)), ("biases", C.POINTER(C.c_double))]
+                ("weights", C.POINTER(C.c_double)), ("biases", C.POINTER(C.c_double)),
+                ("exact", C.c_int)]
 
 
 class _Scene(C.Structure):
@@ -86,9 +87,10 @@ def _p(a, t=C.c_double):
 
 
 class Env:
-    """Equirect map [H,W,3] or MLP (weights list [out,in], biases list)."""
+    """Equirect map [H,W,3] or MLP (weights list [out,in], biases list, n_freq);
+    exact=True evaluates the MLP in plain FP64 without bfloat16 rounding."""
 
-    def __init__(self, tex=None, mlp=None):
+    def __init__(self, tex=None, mlp=None, exact=False):
         self._keep = []
         s = _Env()
         if tex is not None:
@@ -107,6 +109,7 @@ class Env:
             s.width = Ws[0].shape[0]
             s.in_pad = Ws[0].shape[1]
             s.weights, s.biases = _p(w), _p(b)
+            s.exact = int(bool(exact))
         self.s = s
 
     def eval(self, dirs):

@@ -181,6 +181,7 @@ typedef struct {
   int in_pad;               // MLP: padded input width
   const double* weights;    // MLP: concatenated row-major [out][in] per layer
   const double* biases;     // MLP: concatenated per layer
+  int exact;                // MLP: 1 = no bfloat16 rounding anywhere (pure FP64 network)
 } or_env;
 
 typedef struct {
@@ -536,7 +537,8 @@ V3<S> env_mlp(const or_env& e, V3<S> dir, EnvOut& eo) {
     for (int c = 0; c < 3; ++c) h[k++] = Sin(S(w) * dc[c]);
     for (int c = 0; c < 3; ++c) h[k++] = Cos(S(w) * dc[c]);
   }
-  for (auto& x : h) x = bf16_round(x);
+  if (!e.exact)
+    for (auto& x : h) x = bf16_round(x);
   const double* W = e.weights;
   const double* B = e.biases;
   int in = e.in_pad;
@@ -546,7 +548,10 @@ V3<S> env_mlp(const or_env& e, V3<S> dir, EnvOut& eo) {
     for (int j = 0; j < out; ++j) {
       S acc = S(B[j]);
       for (int i = 0; i < in; ++i) acc = acc + S(W[(size_t)j * in + i]) * h[i];
-      z[j] = l < e.n_layers ? bf16_round(Relu(acc)) : acc;
+      if (l < e.n_layers)
+        z[j] = e.exact ? Relu(acc) : bf16_round(Relu(acc));
+      else
+        z[j] = acc;
     }
     W += (size_t)out * in;
     B += out;
