@@ -170,17 +170,35 @@ def dt_build_bvh(V, F, blob, ws):
 
 # ------------------------------------------------------------------ environment
 class Env:
-    """Equirect map [H, W, 3] float32 on the device."""
+    """Environment on the device: an equirect map [H, W, 3] float32, or (via
+    Env.mlp) a frequency-encoded MLP with bfloat16 weights."""
 
-    def __init__(self, texels: torch.Tensor):
-        _dev_check(texels)
-        assert texels.dtype == torch.float32 and texels.dim() == 3 and texels.shape[2] == 3
-        self.texels = texels
+    def __init__(self, texels: torch.Tensor = None):
         s = _Env()
-        s.kind = ENV_EQUIRECT
-        s.height, s.width = texels.shape[0], texels.shape[1]
-        s.texels = texels.data_ptr()
+        if texels is not None:
+            _dev_check(texels)
+            assert texels.dtype == torch.float32 and texels.dim() == 3 and texels.shape[2] == 3
+            self.texels = texels
+            s.kind = ENV_EQUIRECT
+            s.height, s.width = texels.shape[0], texels.shape[1]
+            s.texels = texels.data_ptr()
         self.s = s
+
+    @staticmethod
+    def mlp(Ws, Bs, n_freq: int, device) -> "Env":
+        """Ws: per-layer [out, in] weights (bf16-representable), Bs: biases;
+        hidden layers of equal width, last layer [3, width], first [width, 64]."""
+        e = Env()
+        w = torch.cat([torch.as_tensor(x, dtype=torch.float32).reshape(-1) for x in Ws])
+        e.weights = w.to(torch.bfloat16).view(torch.int16).to(device).contiguous()
+        e.biases = torch.cat([torch.as_tensor(x, dtype=torch.float32).reshape(-1)
+                              for x in Bs]).to(device).contiguous()
+        s = e.s
+        s.kind = ENV_MLP
+        s.n_freq, s.n_layers = int(n_freq), len(Ws) - 1
+        s.hidden, s.in_pad = int(Ws[0].shape[0]), int(Ws[0].shape[1])
+        s.weights, s.biases = e.weights.data_ptr(), e.biases.data_ptr()
+        return e
 
 
 def dt_env_query(env: Env, dirs: torch.Tensor) -> torch.Tensor:

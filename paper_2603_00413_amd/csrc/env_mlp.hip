@@ -1,0 +1,365 @@
+// Environment MLP on bf16 matrix cores (gfx950 MFMA 16x16x16, FP32 accumulate).
+//
+// E(d) = head( relu(... relu(W0 gamma(u) + b0) ...) ), u = d / |d|,
+// gamma(u) = [u, sin(2^k pi u), cos(2^k pi u)]_{k < n_freq}, zero-padded to 64.
+// The encoded input and every post-ReLU activation are rounded to bf16
+// (round to nearest even); weights are bf16, biases and accumulation FP32.
+//
+// One wave evaluates 16 rays.  Layers are computed transposed,
+// D[out][ray] = W[out][in] * H[in][ray], so W is the MFMA A operand and the
+// activations the B operand; the accumulator layout of one layer (lane l holds
+// rows 4*(l/16)+j of column l%16) is exactly the B layout the next layer
+// needs, and activations never leave registers.  The input gradient runs the
+// same way with W^T as the A operand and the upstream gradient split into two
+// bf16 parts (hi + lo), which keeps ~16 bits of it through the bf16 products.
+#include "dt_queue.h"
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// encoding component k of the unit direction u
+__device__ __forceinline__ float enc(int k, v3 u, int n_freq) {
+  if (k < 3) return comp(u, k);
+  int r = k - 3, f = r / 6, c = r % 6;
+  if (f >= n_freq) return 0.f;
+  float x = ldexpf(DT_PI, f) * comp(u, c < 3 ? c : c - 3);
+  return c < 3 ? sinf(x) : cosf(x);
+}
+
+// d enc_k / d u (only the component of u it depends on)
+__device__ __forceinline__ void denc(int k, v3 u, int n_freq, float& dx, float& dy, float& dz,
+                                     float g) {
+  if (k < 3) {
+    if (k == 0) dx += g;
+    if (k == 1) dy += g;
+    if (k == 2) dz += g;
+    return;
+  }
+  int r = k - 3, f = r / 6, c = r % 6;
+  if (f >= n_freq) return;
+  int ax = c < 3 ? c : c - 3;
+  float w = ldexpf(DT_PI, f);
+  float x = w * comp(u, ax);
+  float v = c < 3 ? w * cosf(x) : -w * sinf(x);
+  if (ax == 0) dx += g * v;
+  if (ax == 1) dy += g * v;
+  if (ax == 2) dz += g * v;
+}
+
+constexpr int IN = 64;  // padded input width
+
+// One wave: lane l works on ray l % 16 (all four lane groups q = l / 16 carry
+// the same ray).  Returns E in lanes with q == 0; when GRAD, also returns
+// the direction gradient of dot(gbar, E) with respect to d (all lanes).
+template <int HID, int NL, bool GRAD>
+__device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar) {
+  const int l = threadIdx.x & 63, q = l >> 4, r16 = l & 15;
+  constexpr int KB = HID / 16;
+  float inv_len = 1.0f / sqrtf(dot(d, d));
+  v3 u = d * inv_len;
+  bf16x4 x[IN / 16];
+#pragma unroll
+  for (int kb = 0; kb < IN / 16; ++kb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[kb][j] = f2bf(enc(kb * 16 + 4 * q + j, u, e.n_freq));
+  bf16x4 act[NL][KB];
+  const uint16_t* W = e.w;
+  const float* B = e.b;
+  // first hidden layer, on the encoding
+#pragma unroll
+  for (int ob = 0; ob < KB; ++ob) {
+    f32x4 acc;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = B[ob * 16 + 4 * q + j];
+#pragma unroll
+    for (int kb = 0; kb < IN / 16; ++kb) {
+      bf16x4 a = *(const bf16x4*)(W + (size_t)(ob * 16 + r16) * IN + kb * 16 + 4 * q);
+      acc = mfma(a, x[kb], acc);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) act[0][ob][j] = f2bf(fmaxf(acc[j], 0.f));
+  }
+  W += (size_t)HID * IN;
+  B += HID;
+  // further hidden layers
+#pragma unroll
+  for (int L = 1; L < NL; ++L) {
+#pragma unroll
+    for (int ob = 0; ob < KB; ++ob) {
+      f32x4 acc;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = B[ob * 16 + 4 * q + j];
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        bf16x4 a = *(const bf16x4*)(W + (size_t)(ob * 16 + r16) * HID + kb * 16 + 4 * q);
+        acc = mfma(a, act[L - 1][kb], acc);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) act[L][ob][j] = f2bf(fmaxf(acc[j], 0.f));
+    }
+    W += (size_t)HID * HID;
+    B += HID;
+  }
+  // linear RGB head (3 rows, padded to 16)
+  f32x4 out;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out[j] = (4 * q + j < 3) ? B[4 * q + j] : 0.f;
+#pragma unroll
+  for (int kb = 0; kb < KB; ++kb) {
+    bf16x4 a = {0, 0, 0, 0};
+    if (r16 < 3) a = *(const bf16x4*)(W + (size_t)r16 * HID + kb * 16 + 4 * q);
+    out = mfma(a, act[NL - 1][kb], out);
+  }
+  v3 E = mk3(out[0], out[1], out[2]);
+  if (!GRAD) return E;
+
+  // ---- input gradient: delta_out rows 0..2 = gbar, B layout
+  const uint16_t* Wl[NL + 1];
+  {
+    const uint16_t* p = e.w;
+    for (int L = 0; L <= NL; ++L) {
+      Wl[L] = p;
+      p += (size_t)(L == NL ? 3 : HID) * (L == 0 ? IN : HID);
+    }
+  }
+  bf16x4 dh[KB], dl[KB];  // delta of the current layer's output, hi / lo parts
+  {
+    f32x4 g0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) g0[j] = (q == 0 && j < 3) ? comp(gbar, j) : 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      dh[0][j] = f2bf(g0[j]);
+      dl[0][j] = f2bf(g0[j] - bf2f(dh[0][j]));
+    }
+  }
+  // head: delta_hidden = W_head^T delta_out, masked by the last ReLU
+  bf16x4 nh[KB], nl[KB];
+#pragma unroll
+  for (int ib = 0; ib < KB; ++ib) {
+    bf16x4 a;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int o = 4 * q + j;
+      a[j] = o < 3 ? (short)Wl[NL][(size_t)o * HID + ib * 16 + r16] : (short)0;
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma(a, dh[0], acc);
+    acc = mfma(a, dl[0], acc);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float v = bf2f(act[NL - 1][ib][j]) > 0.f ? acc[j] : 0.f;
+      nh[ib][j] = f2bf(v);
+      nl[ib][j] = f2bf(v - bf2f(nh[ib][j]));
+    }
+  }
+  // hidden layers NL-1 .. 1: delta_{L-1} = W_L^T delta_L, masked by relu'(layer L-1)
+#pragma unroll
+  for (int L = NL - 1; L >= 1; --L) {
+    bf16x4 th[KB], tl[KB];
+#pragma unroll
+    for (int ib = 0; ib < KB; ++ib) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) {
+        bf16x4 a;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          a[j] = (short)Wl[L][(size_t)(kb * 16 + 4 * q + j) * HID + ib * 16 + r16];
+        acc = mfma(a, nh[kb], acc);
+        acc = mfma(a, nl[kb], acc);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v = bf2f(act[L - 1][ib][j]) > 0.f ? acc[j] : 0.f;
+        th[ib][j] = f2bf(v);
+        tl[ib][j] = f2bf(v - bf2f(th[ib][j]));
+      }
+    }
+#pragma unroll
+    for (int ib = 0; ib < KB; ++ib) {
+      nh[ib] = th[ib];
+      nl[ib] = tl[ib];
+    }
+  }
+  // first layer: delta_enc = W_0^T delta_0 (64 rows), then d enc / d u
+  float gx = 0.f, gy = 0.f, gz = 0.f;
+#pragma unroll
+  for (int ib = 0; ib < IN / 16; ++ib) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      bf16x4 a;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        a[j] = (short)Wl[0][(size_t)(kb * 16 + 4 * q + j) * IN + ib * 16 + r16];
+      acc = mfma(a, nh[kb], acc);
+      acc = mfma(a, nl[kb], acc);
+    }
+    // acc[j] = d loss / d enc_k for k = ib*16 + 4q + j of ray r16
+#pragma unroll
+    for (int j = 0; j < 4; ++j) denc(ib * 16 + 4 * q + j, u, e.n_freq, gx, gy, gz, acc[j]);
+  }
+  // the four lane groups hold different k of the same ray
+  gx += __shfl_xor(gx, 16);
+  gy += __shfl_xor(gy, 16);
+  gz += __shfl_xor(gz, 16);
+  gx += __shfl_xor(gx, 32);
+  gy += __shfl_xor(gy, 32);
+  gz += __shfl_xor(gz, 32);
+  // through u = d / |d|
+  v3 gu = mk3(gx, gy, gz);
+  *dbar = (gu - u * dot(u, gu)) * inv_len;
+  return E;
+}
+
+// ------------------------------------------------------------------ kernels
+// Each wave takes 16 consecutive items; items past `count` run on a dummy
+// direction and write nothing.
+template <int HID, int NL>
+__global__ void __launch_bounds__(256) k_mlp_query(EnvDev e, const float* dirs, int64_t n, float* rgb) {
+  int64_t item = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + (threadIdx.x & 15);
+  bool valid = item < n;
+  v3 d = valid ? load3(dirs + 3 * item) : mk3(0.f, 1.f, 0.f);
+  v3 dummy;
+  v3 E = mlp_wave<HID, NL, false>(e, d, mk3(0.f, 0.f, 0.f), &dummy);
+  if (valid && (threadIdx.x & 63) < 16) {
+    rgb[3 * item] = E.x;
+    rgb[3 * item + 1] = E.y;
+    rgb[3 * item + 2] = E.z;
+  }
+}
+
+template <int HID, int NL>
+__global__ void __launch_bounds__(256) k_mlp_query_bwd(EnvDev e, const float* dirs, int64_t n,
+                                                       const float* g, float* gd) {
+  int64_t item = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + (threadIdx.x & 15);
+  bool valid = item < n;
+  v3 d = valid ? load3(dirs + 3 * item) : mk3(0.f, 1.f, 0.f);
+  v3 gb = valid ? load3(g + 3 * item) : mk3(0.f, 0.f, 0.f);
+  v3 db;
+  mlp_wave<HID, NL, true>(e, d, gb, &db);
+  if (valid && (threadIdx.x & 63) < 16) {
+    gd[3 * item] = db.x;
+    gd[3 * item + 1] = db.y;
+    gd[3 * item + 2] = db.z;
+  }
+}
+
+template <int HID, int NL>
+__global__ void __launch_bounds__(256) k_mlp_trace_fwd(EnvDev e, Gen q, const uint32_t* list,
+                                                       const Counters* ctr, int g, float* rgb) {
+  const uint32_t n = ctr->nmiss[g];
+  const int64_t wave0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (wave0 >= n) return;  // uniform per wave
+  int64_t item = wave0 + (threadIdx.x & 15);
+  bool valid = item < n;
+  uint32_t i = valid ? list[item] : 0u;
+  float4 d4 = valid ? q.d[i] : make_float4(0.f, 1.f, 0.f, 0.f);
+  v3 dummy;
+  v3 E = mlp_wave<HID, NL, false>(e, xyz(d4), mk3(0.f, 0.f, 0.f), &dummy);
+  if (valid && (threadIdx.x & 63) < 16) {
+    float4 w4 = q.w[i];
+    int pix = __float_as_int(d4.w);
+    atomicAdd(rgb + 3 * pix, w4.x * E.x);
+    atomicAdd(rgb + 3 * pix + 1, w4.y * E.y);
+    atomicAdd(rgb + 3 * pix + 2, w4.z * E.z);
+  }
+}
+
+template <int HID, int NL>
+__global__ void __launch_bounds__(256) k_mlp_trace_bwd(EnvDev e, Gen q, const uint32_t* list,
+                                                       const Counters* ctr, int g,
+                                                       const float* grad_rgb, Adj cur) {
+  const uint32_t n = ctr->nmiss[g];
+  const int64_t wave0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (wave0 >= n) return;
+  int64_t item = wave0 + (threadIdx.x & 15);
+  bool valid = item < n;
+  uint32_t i = valid ? list[item] : 0u;
+  float4 d4 = valid ? q.d[i] : make_float4(0.f, 1.f, 0.f, 0.f);
+  v3 gb = mk3(0.f, 0.f, 0.f);
+  if (valid) {
+    float4 w4 = q.w[i];
+    int pix = __float_as_int(d4.w);
+    v3 gp = load3(grad_rgb + 3 * pix);
+    gb = mk3(gp.x * w4.x, gp.y * w4.y, gp.z * w4.z);
+  }
+  v3 db;
+  v3 E = mlp_wave<HID, NL, true>(e, xyz(d4), gb, &db);
+  if (valid && (threadIdx.x & 63) < 16) {
+    cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
+    cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    cur.D[i] = make_float4(db.x, db.y, db.z, 0.f);
+  }
+}
+
+// dispatch over the supported (hidden width, hidden layers) shapes
+#define DT_MLP_SHAPES(X) X(64, 1) X(64, 2) X(64, 3) X(64, 4) X(128, 1) X(128, 2) X(128, 3) X(128, 4)
+
+unsigned mlp_blocks(int64_t n) {
+  int64_t b = (n + 63) / 64;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+}  // namespace
+
+bool mlp_supported(const EnvDev& e) {
+  return e.in_pad == IN && (e.hidden == 64 || e.hidden == 128) && e.n_layers >= 1 &&
+         e.n_layers <= 4 && e.n_freq >= 0 && 3 + 6 * e.n_freq <= IN && e.w && e.b;
+}
+
+#define DT_LAUNCH(H, L, kern, grid, ...)                                                    \
+  if (e.hidden == H && e.n_layers == L) {                                                   \
+    hipLaunchKernelGGL((kern<H, L>), dim3(grid), dim3(256), 0, s, __VA_ARGS__);             \
+    DT_CHECK_LAUNCH();                                                                      \
+    return DT_OK;                                                                           \
+  }
+
+dt_status mlp_query(const EnvDev& e, const float* dirs, int64_t n, float* rgb, hipStream_t s) {
+#define X(H, L) DT_LAUNCH(H, L, k_mlp_query, mlp_blocks(n), e, dirs, n, rgb)
+  DT_MLP_SHAPES(X)
+#undef X
+  dt_set_error("environment MLP shape (hidden %d, layers %d) is not supported", e.hidden, e.n_layers);
+  return DT_ERR_UNSUPPORTED;
+}
+
+dt_status mlp_query_backward(const EnvDev& e, const float* dirs, int64_t n, const float* g,
+                             float* gd, hipStream_t s) {
+#define X(H, L) DT_LAUNCH(H, L, k_mlp_query_bwd, mlp_blocks(n), e, dirs, n, g, gd)
+  DT_MLP_SHAPES(X)
+#undef X
+  dt_set_error("environment MLP shape (hidden %d, layers %d) is not supported", e.hidden, e.n_layers);
+  return DT_ERR_UNSUPPORTED;
+}
+
+dt_status mlp_trace_forward(const EnvDev& e, Gen q, const uint32_t* list, const Counters* ctr,
+                            int g, int64_t cap, float* rgb, hipStream_t s) {
+#define X(H, L) DT_LAUNCH(H, L, k_mlp_trace_fwd, mlp_blocks(cap), e, q, list, ctr, g, rgb)
+  DT_MLP_SHAPES(X)
+#undef X
+  dt_set_error("environment MLP shape (hidden %d, layers %d) is not supported", e.hidden, e.n_layers);
+  return DT_ERR_UNSUPPORTED;
+}
+
+dt_status mlp_trace_backward(const EnvDev& e, Gen q, const uint32_t* list, const Counters* ctr,
+                             int g, int64_t cap, const float* grad_rgb, Adj cur, hipStream_t s) {
+#define X(H, L) DT_LAUNCH(H, L, k_mlp_trace_bwd, mlp_blocks(cap), e, q, list, ctr, g, grad_rgb, cur)
+  DT_MLP_SHAPES(X)
+#undef X
+  dt_set_error("environment MLP shape (hidden %d, layers %d) is not supported", e.hidden, e.n_layers);
+  return DT_ERR_UNSUPPORTED;
+}

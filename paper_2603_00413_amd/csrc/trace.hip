@@ -17,7 +17,7 @@
 #include <stdio.h>
 #include <string.h>
 
-#include "dt_device.h"
+#include "dt_queue.h"
 
 namespace {
 
@@ -26,27 +26,6 @@ constexpr int CHUNK = 2048;           // rays per compaction chunk
 constexpr int EB = 256;               // threads per block of the emit kernel
 constexpr int AB = 256;               // threads per block of the adjoint kernel
 constexpr int ADJ_MAX_BLOCKS = 4096;  // grid cap of the adjoint kernel
-constexpr uint32_t RAY_INSIDE = 1u;   // ray flag: travelling inside the object
-
-struct Gen {
-  float4 *o, *d, *w, *hit;  // origin+skip, dir+pixel, weight+flags, (t, tri, b1, b2)
-  uint32_t* code;
-  int2* child;
-};
-
-struct Counters {
-  uint32_t count[DT_MAX_DEPTH + 2];
-  uint32_t nrefl[DT_MAX_DEPTH + 2];
-  uint32_t work[DT_MAX_DEPTH + 2];
-  uint32_t hits[DT_MAX_DEPTH + 2];
-  uint32_t dropped;
-  uint32_t pad[3];
-};
-
-struct Adj {
-  float4 *L, *O, *D;  // subtree radiance, d loss / d origin, d loss / d direction
-};
-
 // ------------------------------------------------------------------ plan
 struct Plan {
   int D, k;
@@ -63,7 +42,7 @@ struct Plan {
   size_t w_ctr, w_part0, w_part1;
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
-  size_t w_dN, w_sbar, w_red;
+  size_t w_dN, w_sbar, w_red, w_miss;
   size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
   size_t ws_bytes;
 };
@@ -145,6 +124,8 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = dt_align(o + 16 * (size_t)nv);
   P.w_red = o;  // per-(generation, block) partial sums of dIoR and dsigma
   o = dt_align(o + 16 * (size_t)(DT_MAX_DEPTH + 1) * ADJ_MAX_BLOCKS);
+  P.w_miss = o;  // miss list of the current generation (MLP environment)
+  o = dt_align(o + 4 * mc);
   size_t kk = P.store_all ? 0 : (size_t)P.k;
   P.w_seg_o = o;
   o = dt_align(o + 16 * mc * kk);
@@ -181,6 +162,7 @@ __global__ void k_init_counters(Counters* c, uint32_t n0) {
       c->nrefl[g] = 0;
       c->work[g] = 0;
       c->hits[g] = 0;
+      c->nmiss[g] = 0;
     }
     c->count[0] = n0;
     c->dropped = 0;
@@ -190,7 +172,10 @@ __global__ void k_init_counters(Counters* c, uint32_t n0) {
 __global__ void k_load_counters(Counters* c, const Counters* src) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *c = *src;
-    for (int g = 0; g < DT_MAX_DEPTH + 2; ++g) c->work[g] = 0;
+    for (int g = 0; g < DT_MAX_DEPTH + 2; ++g) {
+      c->work[g] = 0;
+      c->nmiss[g] = 0;
+    }
   }
 }
 
@@ -277,7 +262,7 @@ __device__ __forceinline__ v3 mul3(v3 a, v3 b) { return mk3(a.x * b.x, a.y * b.y
 // ------------------------------------------------------------------ k_trace (a4 + a5 decisions + a6)
 __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
-                                              int32_t* flags, int accumulate) {
+                                              int32_t* flags, int accumulate, uint32_t* miss_list) {
   __shared__ uint32_t stk[DT_STACK * TB];
   const uint32_t n = ctr->count[g];
   const int lane = threadIdx.x & 63;
@@ -288,7 +273,7 @@ __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counter
     if (base >= n) break;
     uint32_t i = base + lane;
     bool active = i < n;
-    bool has_r = false, has_t = false, hit = false;
+    bool has_r = false, has_t = false, hit = false, listed = false;
     if (active) {
       float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i];
       v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
@@ -302,7 +287,12 @@ __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counter
       int pf = ovf ? DT_FLAG_STACK : 0;
       if (h.tri < 0) {
         if (rfl & RAY_INSIDE) pf |= DT_FLAG_LEAK;
-        if (accumulate) add_rgb(rgb, pix, mul3(W, env_equirect(sc.env, d)));
+        if (accumulate) {
+          if (sc.env.kind == DT_ENV_EQUIRECT)
+            add_rgb(rgb, pix, mul3(W, env_equirect(sc.env, d)));
+          else
+            listed = true;  // evaluated in batches on the matrix cores
+        }
       } else {
         hit = true;
         HitGeo geo = load_geo(sc, h.tri);
@@ -336,6 +326,13 @@ __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counter
       atomicAdd(part + base / CHUNK,
                 (unsigned long long)__popcll(br) | ((unsigned long long)__popcll(bt) << 32));
     if (lane == 0 && bh && accumulate) atomicAdd(&ctr->hits[g], (uint32_t)__popcll(bh));
+    uint64_t bm = __ballot(listed);
+    if (bm) {
+      uint32_t mbase = 0;
+      if (lane == 0) mbase = atomicAdd(&ctr->nmiss[g], (uint32_t)__popcll(bm));
+      mbase = (uint32_t)__shfl((int)mbase, 0);
+      if (listed) miss_list[mbase + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = i;
+    }
   }
 }
 
@@ -488,6 +485,7 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
     v3 gp = load3(grad_rgb + 3 * pix);
     v3 gW = mul3(gp, W);
     if (!(code & C_HIT)) {
+      if (sc.env.kind != DT_ENV_EQUIRECT) continue;  // written by the MLP kernel
       v3 dd;
       v3 E = env_equirect_grad(sc.env, d, gW, &dd);
       cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
@@ -689,6 +687,23 @@ __global__ void k_reduce_scalars(const float4* red, int n, float* d_eta, float* 
   }
 }
 
+// miss list of generation g from the recorded decisions (adjoint, MLP environment)
+__global__ void k_list_misses(Gen q, int g, Counters* ctr, uint32_t* list) {
+  const uint32_t n = ctr->count[g];
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ll; base < n;
+       base += (int64_t)gridDim.x * blockDim.x) {
+    int64_t i = base + lane;
+    bool miss = i < n && !(q.code[i] & C_HIT);
+    uint64_t bm = __ballot(miss);
+    if (!bm) continue;
+    uint32_t mb = 0;
+    if (lane == 0) mb = atomicAdd(&ctr->nmiss[g], (uint32_t)__popcll(bm));
+    mb = (uint32_t)__shfl((int)mb, 0);
+    if (miss) list[mb + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)i;
+  }
+}
+
 // ------------------------------------------------------------------ normals backward (Eq. 13)
 // N_v = normalize(s_v), s_v = sum of unit face normals u_f, u_f = normalize(c_f),
 // c_f = (p1 - p0) x (p2 - p0).
@@ -766,12 +781,11 @@ __global__ void __launch_bounds__(TB) k_intersect(BvhView bv, const float* o, co
 // ------------------------------------------------------------------ host helpers
 dt_status make_env(const dt_env* env, EnvDev& e) {
   DT_REQUIRE(env, "environment descriptor is NULL");
-  if (env->kind != DT_ENV_EQUIRECT) {
-    dt_set_error("environment kind %d is not supported by this entry point", env->kind);
-    return DT_ERR_UNSUPPORTED;
-  }
-  DT_REQUIRE(env->texels && env->width >= 1 && env->height >= 1,
-             "equirect environment needs texels and width, height >= 1");
+  DT_REQUIRE(env->kind == DT_ENV_EQUIRECT || env->kind == DT_ENV_MLP, "unknown environment kind %d",
+             env->kind);
+  if (env->kind == DT_ENV_EQUIRECT)
+    DT_REQUIRE(env->texels && env->width >= 1 && env->height >= 1,
+               "equirect environment needs texels and width, height >= 1");
   e.kind = env->kind;
   e.W = env->width;
   e.H = env->height;
@@ -782,6 +796,12 @@ dt_status make_env(const dt_env* env, EnvDev& e) {
   e.in_pad = env->in_pad;
   e.w = env->weights;
   e.b = env->biases;
+  if (env->kind == DT_ENV_MLP && !mlp_supported(e)) {
+    dt_set_error("environment MLP needs weights, biases, in_pad 64, hidden 64 or 128, 1-4 layers, "
+                 "3 + 6 n_freq <= 64 (got in_pad %d hidden %d layers %d n_freq %d)",
+                 env->in_pad, env->hidden, env->n_layers, env->n_freq);
+    return DT_ERR_UNSUPPORTED;
+  }
   return DT_OK;
 }
 
@@ -804,6 +824,10 @@ dt_status make_scene(const dt_scene* sc, const dt_trace_params* p, SceneDev& s) 
   s.ior = sc->ior;
   s.sigma = sc->sigma;
   if (dt_status st = make_env(sc->env, s.env)) return st;
+  if (s.env.kind == DT_ENV_MLP && p->terminal_env) {
+    dt_set_error("terminal_env with an MLP environment is not supported");
+    return DT_ERR_UNSUPPORTED;
+  }
   s.max_depth = p->max_depth;
   s.terminal_env = p->terminal_env ? 1 : 0;
   s.t_eps = p->t_eps;
@@ -907,12 +931,14 @@ dt_status record(void* const* ev, int i, hipStream_t s) {
 dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen nxt, Counters* ctr,
                          unsigned long long* part_g, unsigned long long* part_other, float* rgb,
                          float* wtrunc, int32_t* flags, int accumulate, int write_next,
-                         void* const* events, hipStream_t s) {
+                         void* const* events, uint32_t* miss_list, hipStream_t s) {
   if (dt_status st = record(events, 2 * g, s)) return st;
   hipLaunchKernelGGL(k_trace, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
-                     rgb, wtrunc, flags, accumulate);
+                     rgb, wtrunc, flags, accumulate, miss_list);
   DT_CHECK_LAUNCH();
   if (dt_status st = record(events, 2 * g + 1, s)) return st;
+  if (accumulate && sc.env.kind == DT_ENV_MLP)
+    if (dt_status st = mlp_trace_forward(sc.env, cur, miss_list, ctr, g, P.cap[g], rgb, s)) return st;
   if (g < P.D) {
     int64_t other_n = (P.cap[g + 1] + CHUNK - 1) / CHUNK + 1;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctr, g, part_g, part_other, other_n,
@@ -1019,7 +1045,7 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
     Gen nxt = g < P.D ? gen_fwd(g + 1) : cur;
     void* const* ev = p->timing ? p->timing->trace_events : nullptr;
     if (dt_status st = run_generation(sc, P, g, cur, nxt, ctr, part[g & 1], part[(g + 1) & 1], rgb,
-                                      wtrunc, flags, 1, 1, ev, s))
+                                      wtrunc, flags, 1, 1, ev, (uint32_t*)(W + P.w_miss), s))
       return st;
   }
   if (T) hipLaunchKernelGGL(k_save_counters, dim3(1), dim3(64), 0, s, (Counters*)(T + P.tape_hdr), ctr);
@@ -1070,6 +1096,13 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     int64_t blocks = (P.cap[g] + AB - 1) / AB;
     if (blocks > ADJ_MAX_BLOCKS) blocks = ADJ_MAX_BLOCKS;
     if (dt_status st = record(aev, 2 * g, s)) return st;
+    if (sc.env.kind == DT_ENV_MLP) {
+      uint32_t* ml = (uint32_t*)(W + P.w_miss);
+      hipLaunchKernelGGL(k_list_misses, dim3((unsigned)blocks), dim3(AB), 0, s, q, g, ctr, ml);
+      DT_CHECK_LAUNCH();
+      if (dt_status st = mlp_trace_backward(sc.env, q, ml, ctr, g, P.cap[g], grad_rgb, adj[g & 1], s))
+        return st;
+    }
     hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
                        adj[(g + 1) & 1], adj[g & 1], dV, dN, red);
     DT_CHECK_LAUNCH();
@@ -1107,7 +1140,8 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
         int j = g - g0;
         Gen nxt = g < g1 ? seg[j + 1] : seg[j];
         if (dt_status st = run_generation(sc, P, g, seg[j], nxt, ctr, part[g & 1], part[(g + 1) & 1],
-                                          nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0, nullptr, s))
+                                          nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0, nullptr,
+                                          (uint32_t*)(W + P.w_miss), s))
           return st;
       }
       for (int g = g1; g >= g0; --g)
@@ -1128,6 +1162,7 @@ extern "C" dt_status dt_env_query(const dt_env* env, const float* dirs, int64_t 
   if (dt_status st = make_env(env, e)) return st;
   DT_REQUIRE(dirs && rgb && n >= 0, "dt_env_query: bad arguments");
   if (n == 0) return DT_OK;
+  if (e.kind == DT_ENV_MLP) return mlp_query(e, dirs, n, rgb, (hipStream_t)stream);
   hipLaunchKernelGGL(k_env_query, dim3(dt_blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, e, dirs,
                      n, rgb);
   DT_CHECK_LAUNCH();
@@ -1140,6 +1175,8 @@ extern "C" dt_status dt_env_query_backward(const dt_env* env, const float* dirs,
   if (dt_status st = make_env(env, e)) return st;
   DT_REQUIRE(dirs && grad_rgb && grad_dirs && n >= 0, "dt_env_query_backward: bad arguments");
   if (n == 0) return DT_OK;
+  if (e.kind == DT_ENV_MLP)
+    return mlp_query_backward(e, dirs, n, grad_rgb, grad_dirs, (hipStream_t)stream);
   hipLaunchKernelGGL(k_env_query_bwd, dim3(dt_blocks(n, 256)), dim3(256), 0, (hipStream_t)stream, e,
                      dirs, n, grad_rgb, grad_dirs);
   DT_CHECK_LAUNCH();
