@@ -209,6 +209,57 @@ dt_status dt_trace_backward(const dt_scene* sc, const dt_rays* rays, const dt_tr
                             float* dV, float* d_ior, float* d_sigma, void* ws, size_t ws_bytes,
                             void* stream);
 
+/* ------------------------------------------------------------- serving */
+
+/* A render server keeps several scenes resident and advances every admitted
+ * request together: each dt_serve_step traces one surface interaction of every
+ * live ray of every request (rays of requests admitted at different times,
+ * with different scenes, environments, resolutions and depth caps share one
+ * compacted queue), after first appending the camera rays of the requests
+ * admitted in this call.  A request is finished when its slot has no live
+ * rays left (slot_live[slot] == 0 after a step); its image is then complete in
+ * the caller's pixel pool.  The ray/shading arithmetic is the tracer's, so a
+ * request's image matches dt_trace_forward of the same camera up to the
+ * order of the FP32 pixel additions. */
+#define DT_SERVE_MAX_SCENES 8
+#define DT_SERVE_MAX_ENVS 8
+#define DT_SERVE_MAX_SLOTS 256
+
+typedef struct {            /* one resident scene (device data, BVH built) */
+  const float* V;
+  int32_t nv;
+  const int32_t* F;
+  int32_t nf;
+  const void* bvh;
+  const float* ior;         /* [1] */
+  const float* sigma;       /* [3] */
+} dt_serve_scene;
+
+typedef struct {            /* a request admitted by this step */
+  int32_t slot;             /* request slot in [0, DT_SERVE_MAX_SLOTS), unused by live rays */
+  int32_t scene;            /* index into scenes */
+  int32_t env;              /* index into envs: the scene's own (render) or another (relight) */
+  int32_t max_depth;        /* [0, 16] */
+  dt_camera camera;         /* pixel_offset: first pixel of its image in the pool */
+} dt_serve_admit;
+
+/* Workspace of a server with queue_capacity live rays (both queues + scan). */
+dt_status dt_serve_bytes(int64_t queue_capacity, size_t* ws_bytes);
+/* Empty the queue (call once before the first step). */
+dt_status dt_serve_reset(void* ws, size_t ws_bytes, int64_t queue_capacity, void* stream);
+/* One step.  scenes, envs, admits: HOST arrays (equirect environments);
+ * pixels: device pool [n_pixels][3] (an admitted request's image is cleared by
+ * its admitting step, then accumulated into); slot_live: device
+ * [DT_SERVE_MAX_SLOTS], overwritten with each slot's live rays after the step;
+ * stats: device int64 [3] or NULL: rays traced since reset, rays dropped since
+ * reset (queue full), live rays.  step: 0, 1, 2, ... since the reset (selects
+ * the queue buffer). */
+dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scenes, const dt_env* envs,
+                        int32_t n_envs, const dt_serve_admit* admits, int32_t n_admits,
+                        int64_t step, float* pixels, int64_t n_pixels, uint32_t* slot_live,
+                        int64_t* stats, int64_t queue_capacity, float t_eps, void* ws,
+                        size_t ws_bytes, void* stream);
+
 /* Closest hit of n rays (o, d [n][3], skip [n] = triangle to ignore or -1,
  * may be NULL) with t > t_eps; ties in t go to the smaller triangle id.
  * Outputs tri [n] (-1 = miss), t [n], b [n][2] (weights of v1 and v2).

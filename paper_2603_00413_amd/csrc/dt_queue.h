@@ -28,6 +28,45 @@ struct Adj {
   float4 *L, *O, *D;  // subtree radiance, d loss / d origin, d loss / d direction
 };
 
+// Pinhole camera for one image: basis computed on the host in FP64.
+struct CamDev {
+  float eye[3], f[3], r[3], u[3];
+  float th, aspect;
+  int W, H;
+  int64_t pixel_offset, base;
+  int tiled;
+};
+
+// direction of the r-th ray of a camera (8x8 tiles in queue order when the
+// image is a multiple of 8 in both sizes, row-major otherwise)
+__device__ __forceinline__ v3 camera_ray(const CamDev& c, int64_t r, int& x, int& y) {
+  if (c.tiled) {
+    int64_t tile = r >> 6;
+    int s = (int)(r & 63);
+    int tx = (int)(tile % (c.W >> 3)), ty = (int)(tile / (c.W >> 3));
+    x = tx * 8 + (s & 7);
+    y = ty * 8 + (s >> 3);
+  } else {
+    x = (int)(r % c.W);
+    y = (int)(r / c.W);
+  }
+  float px = (2.0f * ((float)x + 0.5f) / (float)c.W - 1.0f) * c.th * c.aspect;
+  float py = (1.0f - 2.0f * ((float)y + 0.5f) / (float)c.H) * c.th;
+  v3 f = mk3(c.f[0], c.f[1], c.f[2]), rt = mk3(c.r[0], c.r[1], c.r[2]), up = mk3(c.u[0], c.u[1], c.u[2]);
+  return normalize3(f + rt * px + up * py);
+}
+
+// host: environment descriptor check + device view (trace.hip)
+dt_status make_env(const dt_env* env, EnvDev& e);
+
+// host: camera basis (right-handed, y up hint given by the camera, vertical FOV)
+dt_status make_camera(const dt_camera& cam, int index, CamDev& cd);
+
+// chunked compaction scan shared by the tracer and the server (trace.hip)
+constexpr int DT_CHUNK = 2048;
+dt_status chunk_scan(Counters* ctr, int g, unsigned long long* part, unsigned long long* other,
+                     int64_t other_n, int64_t cap_next, hipStream_t s);
+
 // environment MLP launchers (env_mlp.hip)
 bool mlp_supported(const EnvDev& e);
 dt_status mlp_query(const EnvDev& e, const float* dirs, int64_t n, float* rgb, hipStream_t s);

@@ -22,7 +22,7 @@
 namespace {
 
 constexpr int TB = 64;                // threads per block of the traversal kernel (one wave)
-constexpr int CHUNK = 2048;           // rays per compaction chunk
+constexpr int CHUNK = DT_CHUNK;       // rays per compaction chunk
 constexpr int EB = 256;               // threads per block of the emit kernel
 constexpr int AB = 256;               // threads per block of the adjoint kernel
 constexpr int ADJ_MAX_BLOCKS = 4096;  // grid cap of the adjoint kernel
@@ -207,14 +207,6 @@ __global__ void k_stats(const Counters* c, int D, const BvhHeader* hdr, int64_t*
 }
 
 // ------------------------------------------------------------------ ray generation (a3)
-struct CamDev {
-  float eye[3], f[3], r[3], u[3];
-  float th, aspect;
-  int W, H;
-  int64_t pixel_offset, base;
-  int tiled;
-};
-
 // Pinhole camera rays through pixel centres; 8x8 pixel tiles are laid out
 // consecutively in the queue so that a wave starts on a coherent patch.
 __global__ void k_raygen(Gen q, CamDev c) {
@@ -222,20 +214,7 @@ __global__ void k_raygen(Gen q, CamDev c) {
   int64_t n = (int64_t)c.W * c.H;
   if (r >= n) return;
   int x, y;
-  if (c.tiled) {
-    int64_t tile = r >> 6;
-    int s = (int)(r & 63);
-    int tx = (int)(tile % (c.W >> 3)), ty = (int)(tile / (c.W >> 3));
-    x = tx * 8 + (s & 7);
-    y = ty * 8 + (s >> 3);
-  } else {
-    x = (int)(r % c.W);
-    y = (int)(r / c.W);
-  }
-  float px = (2.0f * ((float)x + 0.5f) / (float)c.W - 1.0f) * c.th * c.aspect;
-  float py = (1.0f - 2.0f * ((float)y + 0.5f) / (float)c.H) * c.th;
-  v3 f = mk3(c.f[0], c.f[1], c.f[2]), rt = mk3(c.r[0], c.r[1], c.r[2]), up = mk3(c.u[0], c.u[1], c.u[2]);
-  v3 d = normalize3(f + rt * px + up * py);
+  v3 d = camera_ray(c, r, x, y);
   int64_t i = c.base + r;
   int pix = (int)(c.pixel_offset + (int64_t)y * c.W + x);
   q.o[i] = make_float4(c.eye[0], c.eye[1], c.eye[2], __int_as_float(-1));
@@ -779,32 +758,6 @@ __global__ void __launch_bounds__(TB) k_intersect(BvhView bv, const float* o, co
 }
 
 // ------------------------------------------------------------------ host helpers
-dt_status make_env(const dt_env* env, EnvDev& e) {
-  DT_REQUIRE(env, "environment descriptor is NULL");
-  DT_REQUIRE(env->kind == DT_ENV_EQUIRECT || env->kind == DT_ENV_MLP, "unknown environment kind %d",
-             env->kind);
-  if (env->kind == DT_ENV_EQUIRECT)
-    DT_REQUIRE(env->texels && env->width >= 1 && env->height >= 1,
-               "equirect environment needs texels and width, height >= 1");
-  e.kind = env->kind;
-  e.W = env->width;
-  e.H = env->height;
-  e.tex = env->texels;
-  e.n_freq = env->n_freq;
-  e.n_layers = env->n_layers;
-  e.hidden = env->hidden;
-  e.in_pad = env->in_pad;
-  e.w = env->weights;
-  e.b = env->biases;
-  if (env->kind == DT_ENV_MLP && !mlp_supported(e)) {
-    dt_set_error("environment MLP needs weights, biases, in_pad 64, hidden 64 or 128, 1-4 layers, "
-                 "3 + 6 n_freq <= 64 (got in_pad %d hidden %d layers %d n_freq %d)",
-                 env->in_pad, env->hidden, env->n_layers, env->n_freq);
-    return DT_ERR_UNSUPPORTED;
-  }
-  return DT_OK;
-}
-
 dt_status make_scene(const dt_scene* sc, const dt_trace_params* p, SceneDev& s) {
   DT_REQUIRE(sc && p, "scene or params is NULL");
   DT_REQUIRE(sc->V && sc->F && sc->bvh && sc->ior && sc->sigma && sc->env,
@@ -889,31 +842,9 @@ dt_status emit_rays(const dt_rays* r, Gen g0, hipStream_t s) {
   int64_t base = 0;
   for (int c = 0; c < r->n_cameras; ++c) {
     const dt_camera& cam = r->cameras[c];
-    double e[3] = {cam.eye[0], cam.eye[1], cam.eye[2]};
-    double f[3] = {cam.target[0] - e[0], cam.target[1] - e[1], cam.target[2] - e[2]};
-    double fl = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
-    DT_REQUIRE(fl > 0.0, "camera %d: eye equals target", c);
-    for (int k = 0; k < 3; ++k) f[k] /= fl;
-    double up[3] = {cam.up[0], cam.up[1], cam.up[2]};
-    double rt[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
-    double rl = sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
-    DT_REQUIRE(rl > 0.0, "camera %d: up is parallel to the view direction", c);
-    for (int k = 0; k < 3; ++k) rt[k] /= rl;
-    double u[3] = {rt[1] * f[2] - rt[2] * f[1], rt[2] * f[0] - rt[0] * f[2], rt[0] * f[1] - rt[1] * f[0]};
     CamDev cd;
-    for (int k = 0; k < 3; ++k) {
-      cd.eye[k] = (float)e[k];
-      cd.f[k] = (float)f[k];
-      cd.r[k] = (float)rt[k];
-      cd.u[k] = (float)u[k];
-    }
-    cd.th = (float)tan(0.5 * (double)cam.fov_deg * 3.14159265358979323846 / 180.0);
-    cd.aspect = (float)((double)cam.width / (double)cam.height);
-    cd.W = cam.width;
-    cd.H = cam.height;
-    cd.pixel_offset = cam.pixel_offset;
+    if (dt_status st = make_camera(cam, c, cd)) return st;
     cd.base = base;
-    cd.tiled = (cam.width % 8 == 0 && cam.height % 8 == 0) ? 1 : 0;
     int64_t np = (int64_t)cam.width * cam.height;
     hipLaunchKernelGGL(k_raygen, dim3(dt_blocks(np, 256)), dim3(256), 0, s, g0, cd);
     DT_CHECK_LAUNCH();
@@ -970,6 +901,69 @@ dt_status zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ shared host helpers
+dt_status make_env(const dt_env* env, EnvDev& e) {
+  DT_REQUIRE(env, "environment descriptor is NULL");
+  DT_REQUIRE(env->kind == DT_ENV_EQUIRECT || env->kind == DT_ENV_MLP, "unknown environment kind %d",
+             env->kind);
+  if (env->kind == DT_ENV_EQUIRECT)
+    DT_REQUIRE(env->texels && env->width >= 1 && env->height >= 1,
+               "equirect environment needs texels and width, height >= 1");
+  e.kind = env->kind;
+  e.W = env->width;
+  e.H = env->height;
+  e.tex = env->texels;
+  e.n_freq = env->n_freq;
+  e.n_layers = env->n_layers;
+  e.hidden = env->hidden;
+  e.in_pad = env->in_pad;
+  e.w = env->weights;
+  e.b = env->biases;
+  if (env->kind == DT_ENV_MLP && !mlp_supported(e)) {
+    dt_set_error("environment MLP needs weights, biases, in_pad 64, hidden 64 or 128, 1-4 layers, "
+                 "3 + 6 n_freq <= 64 (got in_pad %d hidden %d layers %d n_freq %d)",
+                 env->in_pad, env->hidden, env->n_layers, env->n_freq);
+    return DT_ERR_UNSUPPORTED;
+  }
+  return DT_OK;
+}
+
+
+dt_status make_camera(const dt_camera& cam, int c, CamDev& cd) {
+  double e[3] = {cam.eye[0], cam.eye[1], cam.eye[2]};
+  double f[3] = {cam.target[0] - e[0], cam.target[1] - e[1], cam.target[2] - e[2]};
+  double fl = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  DT_REQUIRE(fl > 0.0, "camera %d: eye equals target", c);
+  for (int k = 0; k < 3; ++k) f[k] /= fl;
+  double up[3] = {cam.up[0], cam.up[1], cam.up[2]};
+  double rt[3] = {f[1] * up[2] - f[2] * up[1], f[2] * up[0] - f[0] * up[2], f[0] * up[1] - f[1] * up[0]};
+  double rl = sqrt(rt[0] * rt[0] + rt[1] * rt[1] + rt[2] * rt[2]);
+  DT_REQUIRE(rl > 0.0, "camera %d: up is parallel to the view direction", c);
+  for (int k = 0; k < 3; ++k) rt[k] /= rl;
+  double u[3] = {rt[1] * f[2] - rt[2] * f[1], rt[2] * f[0] - rt[0] * f[2], rt[0] * f[1] - rt[1] * f[0]};
+  for (int k = 0; k < 3; ++k) {
+    cd.eye[k] = (float)e[k];
+    cd.f[k] = (float)f[k];
+    cd.r[k] = (float)rt[k];
+    cd.u[k] = (float)u[k];
+  }
+  cd.th = (float)tan(0.5 * (double)cam.fov_deg * 3.14159265358979323846 / 180.0);
+  cd.aspect = (float)((double)cam.width / (double)cam.height);
+  cd.W = cam.width;
+  cd.H = cam.height;
+  cd.pixel_offset = cam.pixel_offset;
+  cd.base = 0;
+  cd.tiled = (cam.width % 8 == 0 && cam.height % 8 == 0) ? 1 : 0;
+  return DT_OK;
+}
+
+dt_status chunk_scan(Counters* ctr, int g, unsigned long long* part, unsigned long long* other,
+                     int64_t other_n, int64_t cap_next, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctr, g, part, other, other_n, cap_next);
+  DT_CHECK_LAUNCH();
+  return DT_OK;
+}
 
 // ------------------------------------------------------------------ C ABI
 extern "C" dt_status dt_trace_bytes(const dt_trace_params* p, int64_t n_rays, int32_t nv, int32_t nf,
