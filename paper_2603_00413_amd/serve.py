@@ -193,6 +193,10 @@ class Server:
                 est += r.n_pixels
                 admits.append(r)
                 active[r.slot] = r
+            if not admits and not active:
+                r = waiting[0]
+                raise B.DTError(f"request {r.rid} ({r.n_pixels} pixels) can never be admitted: "
+                                f"pixel pool {self.n_pixels}, queue capacity {self.cap}")
             arr = (_Admit * max(len(admits), 1))()
             for i, r in enumerate(admits):
                 a = arr[i]
