@@ -50,6 +50,10 @@ def parse():
                     help="oracle baseline traces every n-th pixel in x and y")
     ap.add_argument("--copy-only", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="offered load as a fraction of the measured one-at-a-time capacity")
     return ap.parse_args()
 
 
@@ -190,6 +194,12 @@ def main():
     log(f"step {ms_step:.2f} ms; forward-only {fwd_ms:.2f} ms; k_trace per gen ms {np.round(tr_ms, 3).tolist()}; "
         f"k_adjoint per gen ms {np.round(ad_ms, 3).tolist()}")
 
+    serving = None
+    if not args.no_serve:
+        del buf
+        torch.cuda.empty_cache()
+        serving = serving_bench(args, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(wl, args.cpu_stride)
@@ -227,14 +237,83 @@ def main():
             "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_bytes_per_launch": int(bytes_per_launch),
         },
-        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
-                       "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+        "step_latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                            "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+        "serving": serving,
         "plain_forward": {"ms": round(fwd_ms, 3), "Mrays/s": round(segs / fwd_ms / 1e3, 3)},
         "kernel_ms_per_generation": {"k_trace": np.round(tr_ms, 4).tolist(),
                                      "k_adjoint": np.round(ad_ms, 4).tolist()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def serving_bench(args, dev):
+    """Render server on four resident scenes under a Poisson request stream,
+    against one-request-at-a-time plain tracing of the same stream."""
+    from paper_2603_00413_amd import synth
+    from paper_2603_00413_amd.serve import Request, Server, run_fifo
+    rng = np.random.default_rng(4)
+    srv = Server(dev, queue_capacity=24 << 20, pixel_pool=24 << 20)
+    sizes = (50_000, 150_000, 300_000, 500_000)
+    nf = []
+    for k, target in enumerate(sizes):
+        V, F = synth.sdf_union_faces(target, seed=41 + k)
+        nf.append(len(F))
+        srv.add_scene(V, F, float(rng.uniform(1.37, 1.6)), tuple(rng.uniform(0.05, 0.5, 3)),
+                      synth.env_equirect(512, 256, seed=100 + k))
+    relight = [srv.add_env(synth.env_equirect(512, 256, seed=200 + k)) for k in range(4)]
+    eyes = synth.views_on_sphere(args.serve_requests, 3.0, seed=5)
+
+    def make_stream(times):
+        r2 = np.random.default_rng(6)
+        out = []
+        for i in range(args.serve_requests):
+            res = int(r2.choice([128, 256, 512, 1024]))
+            sc = int(r2.integers(0, 4))
+            env = None if r2.uniform() < 0.7 else relight[int(r2.integers(0, 4))]
+            out.append(Request(i, sc, synth.look_at_camera(eyes[i], res, res),
+                               int(r2.integers(4, 9)), env, arrival=float(times[i])))
+        return out
+
+    # one-at-a-time capacity: the same requests back to back
+    warm = make_stream(np.zeros(args.serve_requests))[:16]
+    run_fifo(srv, warm, realtime=False)
+    solo = make_stream(np.zeros(args.serve_requests))
+    t = time.perf_counter()
+    _, traced_solo = run_fifo(srv, solo, realtime=False)
+    solo_s = time.perf_counter() - t
+    mu = args.serve_requests / solo_s
+    lam = args.serve_load * mu
+    arrivals = np.cumsum(np.random.default_rng(7).exponential(1.0 / lam, args.serve_requests))
+    log(f"serving: scenes {nf} faces; one-at-a-time {mu:.1f} req/s; offered {lam:.1f} req/s")
+
+    t = time.perf_counter()
+    served = srv.run(make_stream(arrivals), realtime=True)
+    span = time.perf_counter() - t
+    assert srv.dropped == 0
+    lat = np.array([r.latency for r in served]) * 1e3
+    t = time.perf_counter()
+    fifo, traced_fifo = run_fifo(srv, make_stream(arrivals), realtime=True)
+    span_f = time.perf_counter() - t
+    lat_f = np.array([r.latency for r in fifo]) * 1e3
+    out = {
+        "workload": "4 resident SDF-union scenes (%s tris), Poisson stream of %d requests "
+                    "(70%% render / 30%% relight, 128^2-1024^2, depth 4-8), offered load %.2f of "
+                    "one-at-a-time capacity" % ("/".join(str(x) for x in nf), args.serve_requests,
+                                                 args.serve_load),
+        "requests_per_s_offered": round(lam, 2),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "Mrays/s": round(srv.traced / span / 1e6, 2),
+        "device_steps": srv.steps,
+        "fifo_plain_tracer": {"p50_ms": round(float(np.percentile(lat_f, 50)), 3),
+                              "p99_ms": round(float(np.percentile(lat_f, 99)), 3),
+                              "Mrays/s": round(traced_fifo / span_f / 1e6, 2)},
+    }
+    log(f"serving: p50 {out['p50_ms']} ms p99 {out['p99_ms']} ms {out['Mrays/s']} Mrays/s; "
+        f"fifo p50 {out['fifo_plain_tracer']['p50_ms']} ms p99 {out['fifo_plain_tracer']['p99_ms']} ms")
+    return out
 
 
 def cpu_baseline(wl, stride):

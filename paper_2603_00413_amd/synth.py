@@ -286,6 +286,17 @@ def sdf_union_mesh(seed: int = 3, res: int = 128, shell: float | None = None):
     return marching_tetrahedra(random_sdf_union(seed), res, shell=shell)
 
 
+def sdf_union_faces(target_faces: int, seed: int, shell: float | None = None,
+                    max_res: int = 512):
+    """SDF-union mesh with about `target_faces` triangles: the face count of
+    marching tetrahedra grows with the square of the grid resolution, so the
+    resolution is scaled from a coarse trial mesh."""
+    V0, F0 = sdf_union_mesh(seed, 48, shell=shell)
+    res = int(round(48 * math.sqrt(target_faces / max(len(F0), 1))))
+    res = max(16, min(res, max_res))
+    return sdf_union_mesh(seed, res, shell=shell)
+
+
 def mesh_stats(V: np.ndarray, F: np.ndarray) -> dict:
     """Closedness / manifoldness / Euler characteristic of a triangle mesh."""
     e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
