@@ -474,3 +474,26 @@ def torus_scene(n_views: int = 8, res: int = 512) -> Workload:
     eyes = views_on_sphere(n_views, 3.0, seed=2)
     cams = [look_at_camera(e, res, res) for e in eyes]
     return Workload("torus-102k", V, F, 1.45, (0.3, 0.3, 0.3), env, cams, 6)
+
+
+def sdf_union_scene(n_views: int = 8, res: int = 800) -> Workload:
+    """Training-step shape: SDF union of 3 tori + 2 spheres (~300k tris, several
+    handles), IoR 1.45, sigma 0.3, 8 views at 800x800, depth 6, environment =
+    frequency-encoded MLP 3 x 64 (bf16 weights)."""
+    V, F = sdf_union_faces(300_000, seed=3)
+    eyes = views_on_sphere(n_views, 3.0, seed=3)
+    cams = [look_at_camera(e, res, res) for e in eyes]
+    Ws, Bs = env_mlp_weights(seed=3, n_layers=3, width=64)
+    return Workload("sdf-union-300k", V, F, 1.45, (0.3, 0.3, 0.3), None, cams, 6,
+                    mlp=(Ws, Bs, 6))
+
+
+def thin_shell_scene(res: int = 2048) -> Workload:
+    """Stress shape: the SDF union turned into a hollow wall |sdf| - 0.01 on a
+    360^3 grid (~2M tris, walls ~4 cells thick, frequent total internal
+    reflection), IoR 1.5, sigma 0.3, one 2048x2048 view, depth 8, environment
+    MLP 4 x 128."""
+    V, F = sdf_union_mesh(seed=5, res=360, shell=0.01)
+    cams = [look_at_camera(views_on_sphere(1, 3.0, seed=5)[0], res, res)]
+    Ws, Bs = env_mlp_weights(seed=5, n_layers=4, width=128)
+    return Workload("thin-shell-2M", V, F, 1.5, (0.3, 0.3, 0.3), None, cams, 8, mlp=(Ws, Bs, 6))

@@ -1,0 +1,105 @@
+"""The training-step and stress configurations at their full sizes, traced in
+full on the device, checked against the oracle on sampled pixels (forward
+radiance and the gradient of a loss restricted to those pixels)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_00413_amd import binding as B
+from paper_2603_00413_amd import synth
+from tests.gpu_helpers import BAD, HARD, device, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _setup(wl, sigma, ior):
+    dev = device()
+    V32 = wl.V.astype(np.float32)
+    mesh = B.Mesh(torch.from_numpy(V32).to(dev), torch.from_numpy(wl.F).to(dev))
+    Ws, Bs, nfq = wl.mlp
+    env = B.Env.mlp(Ws, Bs, nfq, dev)
+    scene = B.Scene(mesh, torch.tensor([ior], dtype=torch.float32, device=dev),
+                    torch.tensor(sigma, dtype=torch.float32, device=dev), env)
+    rays = B.Rays(cameras=wl.cameras)
+    oenv = oracle.Env(mlp=([w.astype(np.float64) for w in Ws], [b.astype(np.float64) for b in Bs], nfq))
+    o, d = [], []
+    for c in wl.cameras:
+        oo, dd = oracle.camera_rays(c)
+        o.append(oo)
+        d.append(dd)
+    return mesh, scene, rays, oenv, V32, np.concatenate(o), np.concatenate(d)
+
+
+def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=None):
+    mesh, scene, rays, oenv, V32, O, D = _setup(wl, sigma, ior)
+    cap = int(1.3 * rays.n_rays)
+    while True:
+        p = B.Params(max_depth=wl.max_depth, checkpoint_stride=stride, queue_capacity=cap)
+        buf = B.Buffers(p, rays, mesh, tape=True)
+        rgb_t, _, fl_t = B.dt_trace_forward(scene, rays, p, buf)
+        st = buf.stats.cpu().numpy()
+        if st[B.STAT_DROPPED] == 0:
+            break
+        cap *= 2
+    counts = st[:wl.max_depth + 1]
+    _print(wl.name, "rays per generation", counts.tolist(), "capacity", cap,
+           "queue use", np.round(counts[1:] / cap, 3).tolist())
+    rgb, fl = rgb_t.cpu().numpy().astype(np.float64), fl_t.cpu().numpy()
+    assert not (fl & HARD).any()
+    rng = np.random.default_rng(3)
+    pix = np.sort(rng.choice(len(O), n_sample, replace=False))
+    orc = oracle.Scene(V32.astype(np.float64), wl.F, float(np.float32(ior)),
+                       np.asarray(sigma, np.float32).astype(np.float64), oenv, wl.max_depth)
+    ref = orc.trace(O[pix], D[pix])
+    ok = ((fl[pix] | ref["flags"]) & BAD) == 0
+    err = rel_err(rgb[pix], ref["rgb"]).max(1)
+    aerr = np.abs(rgb[pix] - ref["rgb"]).max(1) / np.abs(ref["rgb"]).mean()
+    _print(wl.name, "excluded", 1 - ok.mean(), "median err", np.median(err[ok]),
+           "frac > 1e-4", (err[ok] > 1e-4).mean(), "max abs/mean", aerr[ok].max())
+    assert 1 - ok.mean() < 0.05
+    assert np.median(err[ok]) <= 1e-5 and aerr[ok].max() <= 1e-2
+    # gradient of an L2 loss on the sampled pixels
+    if target is not None:
+        tgt = orc.with_(eta=target[0], sigma=target[1]).trace(O[pix], D[pix])["rgb"]
+    else:
+        tgt = np.zeros((len(pix), 3))
+    gs = 2.0 * (rgb[pix] - tgt) / len(pix) * ok[:, None]
+    g = np.zeros_like(rgb)
+    g[pix] = gs
+    dV, de, ds = B.dt_trace_backward(scene, rays, p, buf, torch.from_numpy(g.astype(np.float32)).to(mesh.V.device))
+    dV, de, ds = dV.cpu().numpy(), float(de.cpu()[0]), ds.cpu().numpy()
+    o = orc.trace_grad(O[pix], D[pix], gs)
+    ev = np.linalg.norm(dV - o["dV"]) / np.linalg.norm(o["dV"])
+    ee = abs(de - o["d_eta"]) / abs(o["d_eta"])
+    es = abs(ds.sum() - o["d_sigma"].sum()) / abs(o["d_sigma"].sum())
+    _print(wl.name, "grads: dV", ev, "deta", ee, "dsigma(sum)", es)
+    assert ev <= 1e-3 and ee <= 1e-3 and es <= 1e-3
+    return buf, p, scene, rays, g, (dV, de, ds)
+
+
+def test_training_step_shape_sdf_union_300k():
+    wl = synth.sdf_union_scene()
+    assert 250_000 < len(wl.F) < 350_000
+    buf, p, scene, rays, g, (dV, de, ds) = _check(wl, 1, 2000, target=(1.5, (0.4, 0.25, 0.1)))
+    # the recompute adjoint (checkpoint every 3 generations) gives the same gradients
+    p3 = B.Params(max_depth=wl.max_depth, checkpoint_stride=3, queue_capacity=p.queue_capacity)
+    b3 = B.Buffers(p3, rays, scene.mesh, tape=True)
+    B.dt_trace_forward(scene, rays, p3, b3, want_aux=False)
+    gt = torch.from_numpy(g.astype(np.float32)).to(scene.mesh.V.device)
+    dV3, de3, ds3 = B.dt_trace_backward(scene, rays, p3, b3, gt)
+    assert np.linalg.norm(dV3.cpu().numpy() - dV) <= 1e-6 * np.linalg.norm(dV)
+    assert abs(float(de3.cpu()[0]) - de) <= 1e-6 * abs(de)
+    assert b3.tape_bytes < 0.6 * buf.tape_bytes
+
+
+def test_stress_thin_shell_2m():
+    wl = synth.thin_shell_scene()
+    assert len(wl.F) > 1_500_000
+    buf, *_ = _check(wl, 2, 1500, ior=1.5)
+    st = buf.stats.cpu().numpy()
+    _print("thin shell: BVH height", st[B.STAT_BVH_DEPTH], "total rays", st[B.STAT_TOTAL])
