@@ -366,10 +366,29 @@ __device__ __forceinline__ void put_box(BvhNode* P, int slot, v3 lo, v3 hi) {
 __device__ __forceinline__ v3 vmin(v3 a, v3 b) { return {fminf(a.x, b.x), fminf(a.y, b.y), fminf(a.z, b.z)}; }
 __device__ __forceinline__ v3 vmax(v3 a, v3 b) { return {fmaxf(a.x, b.x), fmaxf(a.y, b.y), fmaxf(a.z, b.z)}; }
 
-// Leaves in Morton order get their triangle; boxes are fitted bottom-up: the
-// second child to arrive at a node merges both boxes and continues upward.
+// Order-preserving map of floats to ints (for integer atomic min / max).
+__device__ __forceinline__ int fenc(float f) {
+  int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+__device__ __forceinline__ float fdec(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7FFFFFFF); }
+
+__global__ void k_fit_init(int* acc, int n_nodes) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 6 * n_nodes; i += gridDim.x * blockDim.x)
+    acc[i] = (i % 6) < 3 ? fenc(INFINITY) : fenc(-INFINITY);
+}
+
+// Leaves in Morton order get their triangle; boxes are fitted bottom-up.
+// Each child writes its box into its slot of the parent node (read only by
+// later kernels) and merges it into the parent's union accumulator with
+// device-scope atomic min / max.  The second child to arrive (arrival
+// counter) reads the finished union back with device-scope atomic loads and
+// carries on upward.  No memory fence is needed: the accumulator is only
+// touched by atomics, which are coherent across the chip, and a wait for
+// their completion orders them before the arrival increment.
 __global__ void k_fit(const float* V, const int32_t* F, int32_t nv, const int32_t* sorted, int n,
-                      BvhNode* nodes, const int32_t* leaf_parent, int32_t* arrive, float4* leaves) {
+                      BvhNode* nodes, const int32_t* leaf_parent, int32_t* arrive, int* acc,
+                      float4* leaves) {
   int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   int f = sorted[j];
@@ -388,15 +407,22 @@ __global__ void k_fit(const float* V, const int32_t* F, int32_t nv, const int32_
     const int* pd = (const int*)&P->d;
     int slot = pd[0] == ref ? 0 : 1;
     put_box(P, slot, lo, hi);
-    __threadfence();
-    int old = atomicAdd(&arrive[p], 1);
+    int* ac = acc + 6 * p;
+    __hip_atomic_fetch_min(ac + 0, fenc(lo.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_min(ac + 1, fenc(lo.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_min(ac + 2, fenc(lo.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(ac + 3, fenc(hi.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(ac + 4, fenc(hi.y), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(ac + 5, fenc(hi.z), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);  // the merges above are performed before the arrival below
+    int old = __hip_atomic_fetch_add(&arrive[p], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == 0) return;
-    __threadfence();
-    const volatile float* fp = (const volatile float*)P;
-    v3 lo0 = mk3(fp[0], fp[1], fp[2]), hi0 = mk3(fp[3], fp[4], fp[5]);
-    v3 lo1 = mk3(fp[6], fp[7], fp[8]), hi1 = mk3(fp[9], fp[10], fp[11]);
-    lo = vmin(lo0, lo1);
-    hi = vmax(hi0, hi1);
+    lo = mk3(fdec(__hip_atomic_load(ac + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
+             fdec(__hip_atomic_load(ac + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
+             fdec(__hip_atomic_load(ac + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+    hi = mk3(fdec(__hip_atomic_load(ac + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
+             fdec(__hip_atomic_load(ac + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)),
+             fdec(__hip_atomic_load(ac + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
     if (p == 0) return;
     ref = p;
     p = pd[2];
@@ -442,6 +468,7 @@ struct BuildWs {
   int32_t* scanp;
   float* bpart;
   int32_t* arrive;
+  int* acc;
   int32_t *vcnt, *cursor;
 };
 
@@ -458,6 +485,7 @@ size_t carve_build(Carver& c, int32_t nv, int32_t nf, BuildWs* w) {
   x.scanp = c.take<int32_t>(SCAN_NB + 1);
   x.bpart = c.take<float>(NBB * 6);
   x.arrive = c.take<int32_t>(nf > 1 ? nf - 1 : 1);
+  x.acc = c.take<int>(6 * (size_t)(nf > 1 ? nf - 1 : 1));
   x.vcnt = c.take<int32_t>(nv);
   x.cursor = c.take<int32_t>(nv);
   if (w) *w = x;
@@ -570,9 +598,12 @@ extern "C" dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, 
   if (nf > 1) {
     hipLaunchKernelGGL(k_karras, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, ki, nf, nodes, lpar);
     if (dt_status st = dt_fill_u32((uint32_t*)w.arrive, 0u, nf - 1, s)) return st;
+    hipLaunchKernelGGL(k_fit_init, dim3(dt_blocks(6 * (int64_t)(nf - 1), 256) < 4096 ?
+                                        dt_blocks(6 * (int64_t)(nf - 1), 256) : 4096),
+                       dim3(256), 0, s, w.acc, nf - 1);
   }
   hipLaunchKernelGGL(k_fit, dim3(dt_blocks(nf, 256)), dim3(256), 0, s, V, F, nv, vi, nf, nodes,
-                     lpar, w.arrive, leaves);
+                     lpar, w.arrive, w.acc, leaves);
   hipLaunchKernelGGL(k_depth, dim3(dt_blocks(nf, 256)), dim3(256), 0, s, nf, nodes, lpar, hdr);
   DT_CHECK_LAUNCH();
   return DT_OK;
