@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-FLAG_DEGEN, FLAG_LEAK, FLAG_GRAZING, FLAG_TIRB, FLAG_TRUNC = 1, 2, 4, 8, 16
+FLAG_DEGEN, FLAG_LEAK, FLAG_GRAZING, FLAG_TIRB, FLAG_TRUNC, FLAG_KINK = 1, 2, 4, 8, 16, 128
 TREE_FIELDS = (["depth", "kind", "tri"] + ["o%d" % i for i in range(3)]
                + ["d%d" % i for i in range(3)] + ["W%d" % i for i in range(3)]
                + ["R", "T"] + ["A%d" % i for i in range(3)]

@@ -204,6 +204,8 @@ enum {
   OR_FLAG_GRAZING = 4,  // cos(theta_i) < 0.1 somewhere on the path
   OR_FLAG_TIRB = 8,     // |1 - sin^2 theta_t| < 1e-2 somewhere (TIR boundary)
   OR_FLAG_TRUNC = 16,   // some hit reached the depth cap
+  OR_FLAG_KINK = 128,   // an environment lookup within 1e-5 rad of a gradient
+                        // discontinuity (bilinear texel-centre line, ReLU kink)
 };
 
 }  // extern "C"
@@ -480,6 +482,8 @@ V3<S> vertex_normal_def(const Shared& sh, int v, Ctx<S>& cx) {
 // ---------------------------------------------------------------------------
 struct EnvOut {
   int cell_x, cell_y;  // discrete texel cell (for path signatures)
+  double kink = 1e300; // angular distance (rad, first order) to the nearest
+                       // direction where the lookup's gradient jumps
 };
 
 // Equirect lookup at a direction (normalised first): phi = atan2(x, -z), theta = acos(y),
@@ -504,6 +508,15 @@ V3<S> env_equirect(const or_env& e, V3<S> dir, EnvOut& eo) {
   long ix0 = (long)x0, iy0 = (long)y0;
   eo.cell_x = (int)ix0;
   eo.cell_y = (int)iy0;
+  {
+    // bilinear weights change slope on texel-centre lines: distance to the
+    // nearest one along phi (scaled by sin theta) and along theta
+    double fxv = val(x) - x0, fyv = val(yy) - y0;
+    double st = std::sqrt(std::max(1.0 - val(y) * val(y), 0.0));
+    double dphi = std::min(fxv, 1.0 - fxv) * 2.0 * PI / e.W * st;
+    double dth = std::min(fyv, 1.0 - fyv) * PI / e.H;
+    eo.kink = std::min(dphi, dth);
+  }
   auto wrapx = [&](long i) { return (int)(((i % e.W) + e.W) % e.W); };
   auto clampy = [&](long i) { return (int)std::min<long>(std::max<long>(i, 0), e.H - 1); };
   int xa = wrapx(ix0), xb = wrapx(ix0 + 1);
@@ -523,11 +536,85 @@ V3<S> env_equirect(const or_env& e, V3<S> dir, EnvOut& eo) {
 // zero-padded; hidden layers with ReLU; linear RGB head.  The encoded input
 // and each post-ReLU activation are rounded to bfloat16; weights are given
 // already on the bfloat16 grid; biases and accumulation are FP64 here.
+// Smallest first-order angular distance to a ReLU kink: for every hidden
+// pre-activation z, |z| / |dz/du| with u the unit direction (the network is
+// piecewise smooth in u; its gradient jumps where a z changes sign).
+double mlp_kink_margin(const or_env& e, V3<double> d) {
+  const double PI = 3.14159265358979323846;
+  V3<double> u = normalize(d);
+  double uc[3] = {u.x, u.y, u.z};
+  int in = e.in_pad;
+  std::vector<double> h((size_t)in, 0.0), J((size_t)in * 3, 0.0);
+  int k = 0;
+  for (int c = 0; c < 3; ++c) {
+    h[k] = uc[c];
+    J[3 * k + c] = 1.0;
+    ++k;
+  }
+  for (int f = 0; f < e.n_freq; ++f) {
+    double w = std::ldexp(PI, f);
+    for (int c = 0; c < 3; ++c) {
+      h[k] = std::sin(w * uc[c]);
+      J[3 * k + c] = w * std::cos(w * uc[c]);
+      ++k;
+    }
+    for (int c = 0; c < 3; ++c) {
+      h[k] = std::cos(w * uc[c]);
+      J[3 * k + c] = -w * std::sin(w * uc[c]);
+      ++k;
+    }
+  }
+  if (!e.exact)
+    for (auto& x : h) x = bf16_round(x);
+  double margin = 1e300;
+  const double* W = e.weights;
+  const double* B = e.biases;
+  for (int l = 0; l < e.n_layers; ++l) {
+    int out = e.width;
+    std::vector<double> z((size_t)out), Jz((size_t)out * 3);
+    for (int j = 0; j < out; ++j) {
+      double acc = B[j], g0 = 0, g1 = 0, g2 = 0;
+      for (int i = 0; i < in; ++i) {
+        double w = W[(size_t)j * in + i];
+        acc += w * h[i];
+        g0 += w * J[3 * i];
+        g1 += w * J[3 * i + 1];
+        g2 += w * J[3 * i + 2];
+      }
+      // only the tangential part of the gradient moves z along the sphere
+      double gu = g0 * u.x + g1 * u.y + g2 * u.z;
+      g0 -= gu * u.x;
+      g1 -= gu * u.y;
+      g2 -= gu * u.z;
+      double gn = std::sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+      if (gn > 0) margin = std::min(margin, std::fabs(acc) / gn);
+      z[j] = acc;
+      Jz[3 * j] = g0;
+      Jz[3 * j + 1] = g1;
+      Jz[3 * j + 2] = g2;
+    }
+    h.assign((size_t)out, 0.0);
+    J.assign((size_t)out * 3, 0.0);
+    for (int j = 0; j < out; ++j)
+      if (z[j] > 0) {
+        h[j] = e.exact ? z[j] : bf16_round(z[j]);
+        J[3 * j] = Jz[3 * j];
+        J[3 * j + 1] = Jz[3 * j + 1];
+        J[3 * j + 2] = Jz[3 * j + 2];
+      }
+    W += (size_t)out * in;
+    B += out;
+    in = out;
+  }
+  return margin;
+}
+
 template <class S>
 V3<S> env_mlp(const or_env& e, V3<S> dir, EnvOut& eo) {
   const double PI = 3.14159265358979323846;
   V3<S> d = normalize(dir);
   eo.cell_x = eo.cell_y = 0;
+  eo.kink = mlp_kink_margin(e, vval(dir));
   std::vector<S> h((size_t)e.in_pad, S(0.0));
   S dc[3] = {d.x, d.y, d.z};
   int k = 0;
@@ -613,6 +700,7 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
     EnvOut eo;
     V3<S> E = env_eval(*sc.env, d, eo);
     pi.mix(0xE0000000ull ^ ((uint64_t)(uint32_t)eo.cell_x << 16) ^ (uint64_t)(uint32_t)eo.cell_y);
+    if (eo.kink < 1e-5) pi.flags |= OR_FLAG_KINK;
     if (tree) {
       rec.kind = 0;
       rec.E[0] = val(E.x);

@@ -14,6 +14,10 @@ from paper_2603_00413_amd import synth
 # the tolerance checks (degenerate normal, leak, grazing, TIR boundary)
 BAD = B.FLAG_DEGEN | B.FLAG_LEAK | B.FLAG_GRAZING | B.FLAG_TIRB
 HARD = B.FLAG_OVERFLOW | B.FLAG_STACK
+# oracle-only flag: an environment lookup within 1e-5 rad of a direction where
+# the environment's gradient jumps (texel-centre line, ReLU kink); FP32 and
+# FP64 paths may straddle it, so gradients (not values) are compared off it
+KINK = oracle.FLAG_KINK
 
 
 def device():

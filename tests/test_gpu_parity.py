@@ -12,7 +12,7 @@ import torch
 import oracle
 from paper_2603_00413_amd import binding as B
 from paper_2603_00413_amd import synth
-from tests.gpu_helpers import BAD, HARD, Pair, device, icosphere_pair, rel_err, torus_pair
+from tests.gpu_helpers import BAD, HARD, KINK, Pair, device, icosphere_pair, rel_err, torus_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -163,6 +163,7 @@ def _grad_check(P, seed=0):
     buf, rgb, wt, fl = P.gpu_forward(tape=True)
     ref = P.orc.trace(P.o, P.d)
     ok = ((fl | ref["flags"]) & (BAD | HARD)) == 0
+    ok &= (ref["flags"] & KINK) == 0
     g = np.random.default_rng(seed).normal(size=rgb.shape) * ok[:, None]
     dV, de, ds = P.gpu_backward(buf, g)
     o = P.orc.trace_grad(P.o, P.d, g)
@@ -235,7 +236,7 @@ def test_full_size_torus_sampled_pixels():
     assert 1 - ok.mean() < 0.05
     assert bad.any(1).mean() < 2e-3
     g = np.zeros_like(rgb)
-    gs = rng.normal(size=(len(pix), 3)) * ok[:, None]
+    gs = rng.normal(size=(len(pix), 3)) * (ok & ((ref["flags"] & KINK) == 0))[:, None]
     g[pix] = gs
     dV, de, ds = P.gpu_backward(buf, g)
     o = P.orc.trace_grad(P.o[pix], P.d[pix], gs)
