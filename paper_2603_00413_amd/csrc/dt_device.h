@@ -195,12 +195,19 @@ __device__ __forceinline__ float box_enter(const RayPre& r, float lx, float ly, 
   return tn <= tf ? tn : INFINITY;
 }
 
-#define DT_STACK 64
+#define DT_STACK 64       // total stack entries per lane (LDS part + global overflow part)
+#define DT_STACK_LDS 16   // entries kept in LDS by the traversal kernels
 
-// Closest hit with an LDS stack: stk points at this lane's column
-// (stride = blockDim.x entries).  Sets *overflow if the stack would overflow.
+// Closest hit.  The stack holds (node, entry distance) pairs: the first SL
+// entries in LDS (stk points at this lane's column, stride entries apart),
+// deeper ones in this lane's global overflow area gstk (gcap entries; may be
+// NULL).  A popped subtree whose box is entered beyond the closest hit found
+// since it was pushed is skipped without fetching its node.  Sets *overflow if
+// the stack would overflow (the result is then incomplete and flagged).
+template <int SL, bool GLOBAL>
 __device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int skip, float t_eps,
-                                           uint32_t* stk, int stride, bool* overflow) {
+                                           uint2* stk, int stride, uint2* gstk, int gcap,
+                                           bool* overflow) {
   Hit h;
   h.tri = -1;
   h.t = INFINITY;
@@ -242,9 +249,14 @@ __device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int sk
     }
     bool h0 = t0 != INFINITY, h1 = t1 != INFINITY;
     if (h0 && h1) {
-      uint32_t nearc = t0 <= t1 ? c0 : c1, farc = t0 <= t1 ? c1 : c0;
-      if (sp < DT_STACK) {
-        stk[sp * stride] = farc;
+      bool first0 = t0 <= t1;
+      uint32_t nearc = first0 ? c0 : c1, farc = first0 ? c1 : c0;
+      uint2 e = make_uint2(farc, __float_as_uint(first0 ? t1 : t0));
+      if (sp < SL) {
+        stk[sp * stride] = e;
+        ++sp;
+      } else if (GLOBAL && sp - SL < gcap) {
+        if constexpr (GLOBAL) gstk[sp - SL] = e;
         ++sp;
       } else {
         *overflow = true;
@@ -260,9 +272,23 @@ __device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int sk
       node = c1;
       continue;
     }
-    if (sp == 0) break;
-    --sp;
-    node = stk[sp * stride];
+    // pop the nearest pending subtree that can still hold a closer hit
+    // (the margin keeps equal-distance ties, decided by triangle id, in play)
+    bool found = false;
+    while (sp > 0) {
+      --sp;
+      uint2 e = make_uint2(0u, 0u);
+      if (sp < SL) {
+        e = stk[sp * stride];
+      } else {
+        if constexpr (GLOBAL) e = gstk[sp - SL];
+      }
+      if (h.tri >= 0 && __uint_as_float(e.y) > h.t * 1.000001f) continue;
+      node = e.x;
+      found = true;
+      break;
+    }
+    if (!found) break;
   }
   return h;
 }

@@ -43,8 +43,10 @@ struct ServeState {
   long long dropped;
 };
 
+constexpr int SERVE_TRACE_BLOCKS = 256 * 20;
+
 struct ServeLayout {
-  size_t state, tables, part0, part1, q[2][3], hit, code, total;
+  size_t state, tables, part0, part1, q[2][3], hit, code, ovf, total;
   int64_t cap, maxchunks;
 };
 
@@ -70,6 +72,8 @@ ServeLayout serve_layout(int64_t cap) {
   o = dt_align(o + 16 * (size_t)cap);
   L.code = o;
   o = dt_align(o + 4 * (size_t)cap);
+  L.ovf = o;
+  o = dt_align(o + 8 * (size_t)SERVE_TRACE_BLOCKS * TBS * (DT_STACK - DT_STACK_LDS));
   L.total = o;
   return L;
 }
@@ -128,8 +132,10 @@ __global__ void k_serve_admit_count(ServeState* st, int64_t added, int64_t cap) 
 }
 
 __global__ void __launch_bounds__(TBS) k_serve_trace(const ServeTables* T, Gen q, ServeState* st,
-                                                     unsigned long long* part, float* pixels) {
-  __shared__ uint32_t stk[DT_STACK * TBS];
+                                                     unsigned long long* part, float* pixels,
+                                                     uint2* ovf) {
+  __shared__ uint2 stk[DT_STACK_LDS * TBS];
+  uint2* gstk = ovf + (size_t)(blockIdx.x * TBS + threadIdx.x) * (DT_STACK - DT_STACK_LDS);
   Counters* ctr = &st->ctr;
   const uint32_t n = ctr->count[0];
   const int lane = threadIdx.x & 63;
@@ -148,7 +154,8 @@ __global__ void __launch_bounds__(TBS) k_serve_trace(const ServeTables* T, Gen q
       uint32_t fl = (uint32_t)__float_as_int(w4.w);
       const SceneDev& sc = T->sc[sf_scene(fl)];
       bool ovf = false;
-      Hit h = closest_hit(sc.bvh, o, d, skip, sc.t_eps, stk + threadIdx.x, TBS, &ovf);
+      Hit h = closest_hit<DT_STACK_LDS, true>(sc.bvh, o, d, skip, sc.t_eps, stk + threadIdx.x, TBS, gstk,
+                                        DT_STACK - DT_STACK_LDS, &ovf);
       q.hit[i] = make_float4(h.t, __int_as_float(h.tri), h.b1, h.b2);
       uint32_t code = 0;
       if (h.tri < 0) {
@@ -421,8 +428,8 @@ extern "C" dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scene
   if (added) hipLaunchKernelGGL(k_serve_admit_count, dim3(1), dim3(64), 0, s, st, added, L.cap);
   DT_CHECK_LAUNCH();
   // one interaction for every live ray
-  hipLaunchKernelGGL(k_serve_trace, dim3(grid_for(L.cap, TBS, 2560)), dim3(TBS), 0, s, Td, qc, st,
-                     part[cur], pixels);
+  hipLaunchKernelGGL(k_serve_trace, dim3(grid_for(L.cap, TBS, SERVE_TRACE_BLOCKS)), dim3(TBS), 0, s,
+                     Td, qc, st, part[cur], pixels, (uint2*)(W + L.ovf));
   if (dt_status e = chunk_scan(&st->ctr, 0, part[cur], part[nxt], L.maxchunks + 1, L.cap, s)) return e;
   hipLaunchKernelGGL(k_serve_emit, dim3((unsigned)L.maxchunks), dim3(EBS), 0, s, Td, qc, qn, st,
                      part[cur], L.cap);

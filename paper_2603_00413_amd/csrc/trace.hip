@@ -26,6 +26,7 @@ constexpr int CHUNK = DT_CHUNK;       // rays per compaction chunk
 constexpr int EB = 256;               // threads per block of the emit kernel
 constexpr int AB = 256;               // threads per block of the adjoint kernel
 constexpr int ADJ_MAX_BLOCKS = 4096;  // grid cap of the adjoint kernel
+constexpr int TRACE_MAX_BLOCKS = 256 * 20;  // grid cap of the traversal kernel (resident waves)
 // ------------------------------------------------------------------ plan
 struct Plan {
   int D, k;
@@ -42,7 +43,7 @@ struct Plan {
   size_t w_ctr, w_part0, w_part1;
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
-  size_t w_dN, w_sbar, w_red, w_miss;
+  size_t w_dN, w_sbar, w_red, w_miss, w_ovf;
   size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
   size_t ws_bytes;
 };
@@ -126,6 +127,8 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = dt_align(o + 16 * (size_t)(DT_MAX_DEPTH + 1) * ADJ_MAX_BLOCKS);
   P.w_miss = o;  // miss list of the current generation (MLP environment)
   o = dt_align(o + 4 * mc);
+  P.w_ovf = o;   // per-lane traversal stack overflow of the traversal grid
+  o = dt_align(o + 8 * (size_t)TRACE_MAX_BLOCKS * TB * (DT_STACK - DT_STACK_LDS));
   size_t kk = P.store_all ? 0 : (size_t)P.k;
   P.w_seg_o = o;
   o = dt_align(o + 16 * mc * kk);
@@ -241,8 +244,10 @@ __device__ __forceinline__ v3 mul3(v3 a, v3 b) { return mk3(a.x * b.x, a.y * b.y
 // ------------------------------------------------------------------ k_trace (a4 + a5 decisions + a6)
 __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
-                                              int32_t* flags, int accumulate, uint32_t* miss_list) {
-  __shared__ uint32_t stk[DT_STACK * TB];
+                                              int32_t* flags, int accumulate, uint32_t* miss_list,
+                                              uint2* ovf) {
+  __shared__ uint2 stk[DT_STACK_LDS * TB];
+  uint2* gstk = ovf + (size_t)(blockIdx.x * TB + threadIdx.x) * (DT_STACK - DT_STACK_LDS);
   const uint32_t n = ctr->count[g];
   const int lane = threadIdx.x & 63;
   while (true) {
@@ -260,7 +265,8 @@ __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counter
       int pix = __float_as_int(d4.w);
       uint32_t rfl = (uint32_t)__float_as_int(w4.w);
       bool ovf = false;
-      Hit h = closest_hit(sc.bvh, o, d, skip, sc.t_eps, stk + threadIdx.x, TB, &ovf);
+      Hit h = closest_hit<DT_STACK_LDS, true>(sc.bvh, o, d, skip, sc.t_eps, stk + threadIdx.x, TB, gstk,
+                                        DT_STACK - DT_STACK_LDS, &ovf);
       q.hit[i] = make_float4(h.t, __int_as_float(h.tri), h.b1, h.b2);
       uint32_t code = 0;
       int pf = ovf ? DT_FLAG_STACK : 0;
@@ -743,14 +749,15 @@ __global__ void k_env_query_bwd(EnvDev e, const float* dirs, int64_t n, const fl
 __global__ void __launch_bounds__(TB) k_intersect(BvhView bv, const float* o, const float* d,
                                                   const int32_t* skip, int64_t n, float t_eps,
                                                   int brute, int32_t* tri, float* t, float* b) {
-  __shared__ uint32_t stk[DT_STACK * TB];
+  __shared__ uint2 stk[DT_STACK * TB];
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   v3 oo = load3(o + 3 * i), dd = load3(d + 3 * i);
   int sk = skip ? skip[i] : -1;
   bool ovf = false;
   Hit h = brute ? closest_brute(bv, oo, dd, sk, t_eps)
-                : closest_hit(bv, oo, dd, sk, t_eps, stk + threadIdx.x, TB, &ovf);
+                : closest_hit<DT_STACK, false>(bv, oo, dd, sk, t_eps, stk + threadIdx.x, TB, nullptr, 0,
+                                        &ovf);
   tri[i] = ovf ? -2 : h.tri;
   t[i] = h.t;
   b[2 * i] = h.b1;
@@ -828,7 +835,7 @@ Gen gen_at(char* base, size_t o, size_t d, size_t w, size_t hit, size_t code, si
 
 unsigned trace_grid(int64_t cap) {
   int64_t waves = (cap + 63) / 64;
-  int64_t lim = 256 * 10;  // resident waves the LDS stack allows on 256 CUs
+  int64_t lim = TRACE_MAX_BLOCKS;  // resident waves the LDS stack allows on 256 CUs
   return (unsigned)(waves < lim ? (waves < 1 ? 1 : waves) : lim);
 }
 
@@ -862,10 +869,10 @@ dt_status record(void* const* ev, int i, hipStream_t s) {
 dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen nxt, Counters* ctr,
                          unsigned long long* part_g, unsigned long long* part_other, float* rgb,
                          float* wtrunc, int32_t* flags, int accumulate, int write_next,
-                         void* const* events, uint32_t* miss_list, hipStream_t s) {
+                         void* const* events, uint32_t* miss_list, uint2* ovf, hipStream_t s) {
   if (dt_status st = record(events, 2 * g, s)) return st;
   hipLaunchKernelGGL(k_trace, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
-                     rgb, wtrunc, flags, accumulate, miss_list);
+                     rgb, wtrunc, flags, accumulate, miss_list, ovf);
   DT_CHECK_LAUNCH();
   if (dt_status st = record(events, 2 * g + 1, s)) return st;
   if (accumulate && sc.env.kind == DT_ENV_MLP)
@@ -1039,7 +1046,8 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
     Gen nxt = g < P.D ? gen_fwd(g + 1) : cur;
     void* const* ev = p->timing ? p->timing->trace_events : nullptr;
     if (dt_status st = run_generation(sc, P, g, cur, nxt, ctr, part[g & 1], part[(g + 1) & 1], rgb,
-                                      wtrunc, flags, 1, 1, ev, (uint32_t*)(W + P.w_miss), s))
+                                      wtrunc, flags, 1, 1, ev, (uint32_t*)(W + P.w_miss),
+                                      (uint2*)(W + P.w_ovf), s))
       return st;
   }
   if (T) hipLaunchKernelGGL(k_save_counters, dim3(1), dim3(64), 0, s, (Counters*)(T + P.tape_hdr), ctr);
@@ -1135,7 +1143,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
         Gen nxt = g < g1 ? seg[j + 1] : seg[j];
         if (dt_status st = run_generation(sc, P, g, seg[j], nxt, ctr, part[g & 1], part[(g + 1) & 1],
                                           nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0, nullptr,
-                                          (uint32_t*)(W + P.w_miss), s))
+                                          (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), s))
           return st;
       }
       for (int g = g1; g >= g0; --g)
