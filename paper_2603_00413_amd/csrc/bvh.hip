@@ -443,6 +443,76 @@ __global__ void k_depth(int n, const BvhNode* nodes, const int32_t* leaf_parent,
   atomicMax(&hdr->depth, dep);
 }
 
+// 1 for an internal node at even depth (root = 0), else 0: walk to the root.
+__global__ void k_even(int32_t n_int, const BvhNode* nodes, int32_t* flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_int) return;
+  int dep = 0, p = i;
+  while (p > 0 && p < n_int && dep < 4096) {
+    p = nodes[p].d.z;
+    ++dep;
+  }
+  flag[i] = (dep & 1) == 0;
+}
+
+// Writes the 4-wide node of every even-depth internal node i at index idx[i]:
+// each leaf child keeps its slot, each internal child hands over its two
+// children (their boxes are stored in that child's node).
+__global__ void k_collapse(int32_t n_int, const BvhNode* nodes, const int32_t* flag,
+                           const int32_t* idx, Bvh4Node* out, int32_t cap4) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_int || !flag[i]) return;
+  int j = idx[i];
+  if (j < 0 || j >= cap4) return;
+  float lo[4][3], hi[4][3];
+  uint32_t ch[4];
+  int k = 0;
+  auto ref = [&](uint32_t c) -> uint32_t {
+    if (c & DT_LEAF_BIT) return c;
+    return c < (uint32_t)n_int ? (uint32_t)idx[c] : DT_NO_CHILD;
+  };
+  auto put = [&](const BvhNode& m, int side, uint32_t c) {
+    const float4 a = m.a, b = m.b, cc = m.c;
+    if (side == 0) {
+      lo[k][0] = a.x, lo[k][1] = a.y, lo[k][2] = a.z;
+      hi[k][0] = a.w, hi[k][1] = b.x, hi[k][2] = b.y;
+    } else {
+      lo[k][0] = b.z, lo[k][1] = b.w, lo[k][2] = cc.x;
+      hi[k][0] = cc.y, hi[k][1] = cc.z, hi[k][2] = cc.w;
+    }
+    ch[k] = ref(c);
+    ++k;
+  };
+  const BvhNode n = nodes[i];
+  uint32_t cs[2] = {(uint32_t)n.d.x, (uint32_t)n.d.y};
+  for (int side = 0; side < 2; ++side) {
+    uint32_t c = cs[side];
+    if ((c & DT_LEAF_BIT) || c >= (uint32_t)n_int) {
+      put(n, side, c);
+    } else {
+      const BvhNode m = nodes[c];
+      put(m, 0, (uint32_t)m.d.x);
+      put(m, 1, (uint32_t)m.d.y);
+    }
+  }
+  int cnt = k;
+  for (; k < 4; ++k) {
+    lo[k][0] = lo[k][1] = lo[k][2] = 0.f;
+    hi[k][0] = hi[k][1] = hi[k][2] = 0.f;
+    ch[k] = DT_NO_CHILD;
+  }
+  Bvh4Node q;
+  q.lox = make_float4(lo[0][0], lo[1][0], lo[2][0], lo[3][0]);
+  q.hix = make_float4(hi[0][0], hi[1][0], hi[2][0], hi[3][0]);
+  q.loy = make_float4(lo[0][1], lo[1][1], lo[2][1], lo[3][1]);
+  q.hiy = make_float4(hi[0][1], hi[1][1], hi[2][1], hi[3][1]);
+  q.loz = make_float4(lo[0][2], lo[1][2], lo[2][2], lo[3][2]);
+  q.hiz = make_float4(hi[0][2], hi[1][2], hi[2][2], hi[3][2]);
+  q.child = make_uint4(ch[0], ch[1], ch[2], ch[3]);
+  q.meta = make_int4(i, cnt, 0, 0);
+  out[j] = q;
+}
+
 __global__ void k_header(BvhHeader* hdr, int32_t nv, int32_t nf) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     hdr->nv = nv;
@@ -469,6 +539,7 @@ struct BuildWs {
   float* bpart;
   int32_t* arrive;
   int* acc;
+  int32_t *flag4, *idx4;
   int32_t *vcnt, *cursor;
 };
 
@@ -486,6 +557,8 @@ size_t carve_build(Carver& c, int32_t nv, int32_t nf, BuildWs* w) {
   x.bpart = c.take<float>(NBB * 6);
   x.arrive = c.take<int32_t>(nf > 1 ? nf - 1 : 1);
   x.acc = c.take<int>(6 * (size_t)(nf > 1 ? nf - 1 : 1));
+  x.flag4 = c.take<int32_t>(nf);
+  x.idx4 = c.take<int32_t>(nf);
   x.vcnt = c.take<int32_t>(nv);
   x.cursor = c.take<int32_t>(nv);
   if (w) *w = x;
@@ -606,6 +679,15 @@ extern "C" dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, 
                      lpar, w.arrive, w.acc, leaves);
   hipLaunchKernelGGL(k_depth, dim3(dt_blocks(nf, 256)), dim3(256), 0, s, nf, nodes, lpar, hdr);
   DT_CHECK_LAUNCH();
+  // 4-wide traversal tree
+  if (nf > 1) {
+    Bvh4Node* nodes4 = (Bvh4Node*)(b + L.nodes4);
+    hipLaunchKernelGGL(k_even, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes, w.flag4);
+    if (dt_status st = dt_scan_exclusive_i32(w.flag4, w.idx4, nf - 1, w.scanp, s)) return st;
+    hipLaunchKernelGGL(k_collapse, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes,
+                       w.flag4, w.idx4, nodes4, bvh4_cap(nf));
+    DT_CHECK_LAUNCH();
+  }
   return DT_OK;
 }
 

@@ -198,12 +198,15 @@ __device__ __forceinline__ float box_enter(const RayPre& r, float lx, float ly, 
 #define DT_STACK 64       // total stack entries per lane (LDS part + global overflow part)
 #define DT_STACK_LDS 16   // entries kept in LDS by the traversal kernels
 
-// Closest hit.  The stack holds (node, entry distance) pairs: the first SL
-// entries in LDS (stk points at this lane's column, stride entries apart),
-// deeper ones in this lane's global overflow area gstk (gcap entries; may be
-// NULL).  A popped subtree whose box is entered beyond the closest hit found
-// since it was pushed is skipped without fetching its node.  Sets *overflow if
-// the stack would overflow (the result is then incomplete and flagged).
+// Closest hit over the 4-wide tree.  The stack holds (node, entry distance)
+// pairs: the first SL entries in LDS (stk points at this lane's column, stride
+// entries apart), deeper ones in this lane's global overflow area gstk (gcap
+// entries; may be NULL).  At a node, leaf children are tested at once; the
+// internal children whose boxes the ray enters are ordered by entry distance,
+// the nearest is visited next and the others are pushed, farthest first.  A
+// popped subtree whose box is entered beyond the closest hit found since it
+// was pushed is skipped without fetching its node.  Sets *overflow if the
+// stack would overflow (the result is then incomplete and flagged).
 template <int SL, bool GLOBAL>
 __device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int skip, float t_eps,
                                            uint2* stk, int stride, uint2* gstk, int gcap,
@@ -219,57 +222,74 @@ __device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int sk
     if (f != skip) tri_test(r, xyz(L[0]), xyz(L[1]), xyz(L[2]), f, t_eps, h);
     return h;
   }
+  const uint32_t cap4 = (uint32_t)bvh4_cap(bv.nf);
+  const uint32_t lmax = (uint32_t)(bv.nf - 1);
   int sp = 0;
   uint32_t node = 0;
-  // a depth-first walk visits each of the nf - 1 internal nodes at most once
-  for (int guard = 0; guard < bv.nf + 64; ++guard) {
-    if (node >= (uint32_t)(bv.nf - 1)) {
+  auto push = [&](uint32_t c, float t) {
+    uint2 e = make_uint2(c, __float_as_uint(t));
+    if (sp < SL) {
+      stk[sp * stride] = e;
+      ++sp;
+    } else if (GLOBAL && sp - SL < gcap) {
+      if constexpr (GLOBAL) gstk[sp - SL] = e;
+      ++sp;
+    } else {
+      *overflow = true;
+    }
+  };
+  auto leaf = [&](uint32_t c) {
+    uint32_t j = min(c & ~DT_LEAF_BIT, lmax);
+    float4 p0 = L[3 * j];
+    int f = __float_as_int(p0.w);
+    if (f != skip) tri_test(r, xyz(p0), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), f, t_eps, h);
+  };
+  // each 4-wide node is visited at most once by a depth-first walk
+  for (uint32_t guard = 0; guard < cap4 + 64; ++guard) {
+    if (node >= cap4) {
       *overflow = true;
       break;
     }
-    const BvhNode& n = bv.nodes[node];
-    float4 a = n.a, b = n.b, c = n.c;
-    int4 ch = n.d;
+    const Bvh4Node& n = bv.nodes4[node];
+    const float4 lx = n.lox, hx = n.hix, ly = n.loy, hy = n.hiy, lz = n.loz, hz = n.hiz;
+    const uint4 cc = n.child;
     float tmax = h.tri >= 0 ? h.t : INFINITY;
-    float t0 = box_enter(r, a.x, a.y, a.z, a.w, b.x, b.y, tmax);
-    float t1 = box_enter(r, b.z, b.w, c.x, c.y, c.z, c.w, tmax);
-    uint32_t c0 = (uint32_t)ch.x, c1 = (uint32_t)ch.y;
-    // leaves are tested right away
-    if (t0 != INFINITY && (c0 & DT_LEAF_BIT)) {
-      uint32_t j = min(c0 & ~DT_LEAF_BIT, (uint32_t)(bv.nf - 1));
-      int f = __float_as_int(L[3 * j].w);
-      if (f != skip) tri_test(r, xyz(L[3 * j]), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), f, t_eps, h);
-      t0 = INFINITY;
-    }
-    if (t1 != INFINITY && (c1 & DT_LEAF_BIT)) {
-      uint32_t j = min(c1 & ~DT_LEAF_BIT, (uint32_t)(bv.nf - 1));
-      int f = __float_as_int(L[3 * j].w);
-      if (f != skip) tri_test(r, xyz(L[3 * j]), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), f, t_eps, h);
-      t1 = INFINITY;
-    }
-    bool h0 = t0 != INFINITY, h1 = t1 != INFINITY;
-    if (h0 && h1) {
-      bool first0 = t0 <= t1;
-      uint32_t nearc = first0 ? c0 : c1, farc = first0 ? c1 : c0;
-      uint2 e = make_uint2(farc, __float_as_uint(first0 ? t1 : t0));
-      if (sp < SL) {
-        stk[sp * stride] = e;
-        ++sp;
-      } else if (GLOBAL && sp - SL < gcap) {
-        if constexpr (GLOBAL) gstk[sp - SL] = e;
-        ++sp;
-      } else {
-        *overflow = true;
+    float t[4];
+    uint32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
+    t[0] = box_enter(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tmax);
+    t[1] = box_enter(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmax);
+    t[2] = box_enter(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmax);
+    t[3] = box_enter(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmax);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (c[k] == DT_NO_CHILD) {
+        t[k] = INFINITY;
+      } else if (t[k] != INFINITY && (c[k] & DT_LEAF_BIT)) {
+        leaf(c[k]);
+        t[k] = INFINITY;
       }
-      node = nearc;
-      continue;
     }
-    if (h0) {
-      node = c0;
-      continue;
-    }
-    if (h1) {
-      node = c1;
+    // order the entered internal children by entry distance (sorting network)
+#define DT_CSWAP(i, j)                 \
+  if (t[j] < t[i]) {                   \
+    float tt = t[i];                   \
+    t[i] = t[j];                       \
+    t[j] = tt;                         \
+    uint32_t cx = c[i];                \
+    c[i] = c[j];                       \
+    c[j] = cx;                         \
+  }
+    DT_CSWAP(0, 1)
+    DT_CSWAP(2, 3)
+    DT_CSWAP(0, 2)
+    DT_CSWAP(1, 3)
+    DT_CSWAP(1, 2)
+#undef DT_CSWAP
+    if (t[0] != INFINITY) {
+      if (t[3] != INFINITY) push(c[3], t[3]);
+      if (t[2] != INFINITY) push(c[2], t[2]);
+      if (t[1] != INFINITY) push(c[1], t[1]);
+      node = c[0];
       continue;
     }
     // pop the nearest pending subtree that can still hold a closer hit

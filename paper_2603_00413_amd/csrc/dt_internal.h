@@ -72,6 +72,26 @@ struct __align__(16) BvhNode {
   int4 d;    // child0 child1 parent unused
 };
 
+// 4-wide node collapsed from the binary tree: a binary internal node at even
+// depth (root = 0) becomes a 4-wide node whose children are its grandchildren
+// (a leaf child stays a leaf), 2 to 4 of them.  Boxes are stored SoA over the
+// four slots; an unused slot has child reference DT_NO_CHILD.  A child
+// reference is a 4-wide node index or (leaf | DT_LEAF_BIT).
+#define DT_NO_CHILD 0xFFFFFFFFu
+
+struct __align__(16) Bvh4Node {
+  float4 lox, hix, loy, hiy, loz, hiz;
+  uint4 child;
+  int4 meta;  // binary node id, number of children, 0, 0
+};
+
+// Upper bound on the number of 4-wide nodes: with E even-depth and O odd-depth
+// internal nodes, every even one but the root has an odd parent with at most
+// two internal children, so E - 1 <= 2 O and E <= (2 (nf - 1) + 1) / 3.
+__host__ __device__ inline int32_t bvh4_cap(int32_t nf) {
+  return nf > 1 ? (int32_t)((2 * (int64_t)(nf - 1) + 1) / 3) : 1;
+}
+
 struct BvhHeader {
   int32_t nv, nf;
   int32_t depth;  // tree height (root = 1), from the build
@@ -81,7 +101,7 @@ struct BvhHeader {
 
 // Byte offsets inside the caller's blob; a pure function of (nv, nf).
 struct BvhLayout {
-  size_t header, nodes, leaves, vnormals, fnormals, csr_off, csr_idx, leaf_parent, total;
+  size_t header, nodes, nodes4, leaves, vnormals, fnormals, csr_off, csr_idx, leaf_parent, total;
 };
 
 __host__ __device__ inline size_t dt_align(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -93,6 +113,8 @@ inline BvhLayout bvh_layout(int32_t nv, int32_t nf) {
   o = dt_align(o + sizeof(BvhHeader));
   L.nodes = o;
   o = dt_align(o + sizeof(BvhNode) * (size_t)(nf > 1 ? nf - 1 : 1));
+  L.nodes4 = o;
+  o = dt_align(o + sizeof(Bvh4Node) * (size_t)bvh4_cap(nf));
   L.leaves = o;
   o = dt_align(o + sizeof(float4) * 3 * (size_t)nf);
   L.vnormals = o;
@@ -113,7 +135,8 @@ inline BvhLayout bvh_layout(int32_t nv, int32_t nf) {
 struct BvhView {
   const BvhHeader* hdr;
   const BvhNode* nodes;
-  const float4* leaves;  // 3 per leaf: v0 (w = tri id bits), v1, v2
+  const Bvh4Node* nodes4;  // traversal tree
+  const float4* leaves;    // 3 per leaf: v0 (w = tri id bits), v1, v2
   const float4* vn;      // vertex normals
   const float4* fn;      // unit face normals (w = 1 if area > 0)
   const int32_t* csr_off;
@@ -127,6 +150,7 @@ inline BvhView bvh_view(const void* blob, int32_t nv, int32_t nf) {
   BvhView v;
   v.hdr = (const BvhHeader*)(b + L.header);
   v.nodes = (const BvhNode*)(b + L.nodes);
+  v.nodes4 = (const Bvh4Node*)(b + L.nodes4);
   v.leaves = (const float4*)(b + L.leaves);
   v.vn = (const float4*)(b + L.vnormals);
   v.fn = (const float4*)(b + L.fnormals);
