@@ -192,14 +192,19 @@ dt_status dt_trace_bytes(const dt_trace_params* p, int64_t n_rays, int32_t nv, i
                          size_t* ws_bytes, size_t* tape_bytes);
 
 /* Forward render.  rgb [npix][3] (required), wtrunc [npix][3] (optional:
- * accumulated weight of truncated rays), flags [npix] (optional), stats
+ * accumulated weight of truncated rays), flags [npix] (optional), path_sig
+ * [npix] (optional: order-independent signature of each pixel's discrete
+ * path, the sum mod 2^64 over its ray segments of SplitMix64's output
+ * function applied to (g << 40) | (tir << 32) | (triangle + 1), with
+ * triangle = -1 for a miss and tir = 0 for a truncated hit; two renders took
+ * the same triangles and branches where the signatures agree), stats
  * [DT_STATS_LEN] int64 (optional).  tape may be NULL for a forward-only
  * render; when given it must be tape_bytes long and is later read by
  * dt_trace_backward with the same scene, rays and params. */
 dt_status dt_trace_forward(const dt_scene* sc, const dt_rays* rays, const dt_trace_params* p,
-                           float* rgb, float* wtrunc, int32_t* flags, int64_t* stats,
-                           void* tape, size_t tape_bytes, void* ws, size_t ws_bytes,
-                           void* stream);
+                           float* rgb, float* wtrunc, int32_t* flags, uint64_t* path_sig,
+                           int64_t* stats, void* tape, size_t tape_bytes, void* ws,
+                           size_t ws_bytes, void* stream);
 
 /* Backward: given dLoss/drgb [npix][3], accumulate nothing and overwrite
  * dV [nv][3], d_ior [1], d_sigma [3] with dLoss/d(V, ior, sigma).  Generations

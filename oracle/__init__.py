@@ -41,8 +41,7 @@ class _Env(C.Structure):
     _fields_ = [("kind", C.c_int), ("W", C.c_int), ("H", C.c_int),
                 ("tex", C.POINTER(C.c_double)), ("n_freq", C.c_int),
                 ("n_layers", C.c_int), ("width", C.c_int), ("in_pad", C.c_int),
-                ("weights", C.POINTER(C.c_double)), ("biases", C.POINTER(C.c_double)),
-                ("exact", C.c_int)]
+                ("weights", C.POINTER(C.c_double)), ("biases", C.POINTER(C.c_double))]
 
 
 class _Scene(C.Structure):
@@ -69,8 +68,9 @@ def lib():
         L.or_intersect.argtypes = [C.POINTER(_Scene), dp, dp, ip, i64, ip, dp, dp, dp]
         L.or_env_eval.argtypes = [C.POINTER(_Env), dp, i64, dp]
         L.or_env_eval_grad.argtypes = [C.POINTER(_Env), dp, i64, dp, dp]
+        L.or_env_kink_margin.argtypes = [C.POINTER(_Env), dp, i64, dp]
         L.or_trace.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, ip,
-                               C.POINTER(C.c_uint64), ip]
+                               C.POINTER(C.c_uint64), ip, C.POINTER(C.c_uint64)]
         L.or_trace_grad.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, dp, dp, dp]
         L.or_trace_tree.argtypes = [C.POINTER(_Scene), dp, dp, dp, C.c_int]
         L.or_num_threads.restype = C.c_int
@@ -87,10 +87,10 @@ def _p(a, t=C.c_double):
 
 
 class Env:
-    """Equirect map [H,W,3] or MLP (weights list [out,in], biases list, n_freq);
-    exact=True evaluates the MLP in plain FP64 without bfloat16 rounding."""
+    """Equirect map [H,W,3] or MLP (weights list [out,in], biases list, n_freq),
+    evaluated in plain FP64."""
 
-    def __init__(self, tex=None, mlp=None, exact=False):
+    def __init__(self, tex=None, mlp=None):
         self._keep = []
         s = _Env()
         if tex is not None:
@@ -109,13 +109,19 @@ class Env:
             s.width = Ws[0].shape[0]
             s.in_pad = Ws[0].shape[1]
             s.weights, s.biases = _p(w), _p(b)
-            s.exact = int(bool(exact))
         self.s = s
 
     def eval(self, dirs):
         d = _d(dirs).reshape(-1, 3)
         out = np.empty_like(d)
         assert lib().or_env_eval(C.byref(self.s), _p(d), len(d), _p(out)) == 0
+        return out
+
+    def kink_margin(self, dirs):
+        """Angular distance (rad) to the nearest gradient discontinuity."""
+        d = _d(dirs).reshape(-1, 3)
+        out = np.empty(len(d))
+        assert lib().or_env_kink_margin(C.byref(self.s), _p(d), len(d), _p(out)) == 0
         return out
 
     def eval_grad(self, dirs, grad_rgb):
@@ -168,17 +174,21 @@ class Scene:
         return sc
 
     def trace(self, o, d):
-        """Returns dict(rgb [n,3], wtrunc [n,3], flags [n], hash [n], nseg [n])."""
+        """Returns dict(rgb [n,3], wtrunc [n,3], flags [n], hash [n], nseg [n],
+        sig [n]).  hash: ordered hash of the depth-first visit (triangles,
+        branches, texel cells); sig: order-independent path signature, the
+        sum mod 2^64 of splitmix64((g << 40) | (tir << 32) | (tri + 1)) over
+        the tree's segments (tri = -1 for a miss, tir = 0 when truncated)."""
         o, d = _d(o).reshape(-1, 3), _d(d).reshape(-1, 3)
         n = len(o)
         rgb, wt = np.empty((n, 3)), np.empty((n, 3))
         fl, ns = np.empty(n, np.int32), np.empty(n, np.int32)
-        hs = np.empty(n, np.uint64)
+        hs, sg = np.empty(n, np.uint64), np.empty(n, np.uint64)
         s = self._s()
         rc = lib().or_trace(C.byref(s), _p(o), _p(d), n, _p(rgb), _p(wt), _p(fl, C.c_int),
-                            _p(hs, C.c_uint64), _p(ns, C.c_int))
+                            _p(hs, C.c_uint64), _p(ns, C.c_int), _p(sg, C.c_uint64))
         assert rc == 0, "or_trace rejected its arguments"
-        return {"rgb": rgb, "wtrunc": wt, "flags": fl, "hash": hs, "nseg": ns}
+        return {"rgb": rgb, "wtrunc": wt, "flags": fl, "hash": hs, "nseg": ns, "sig": sg}
 
     def trace_grad(self, o, d, grad_rgb):
         """Returns dict(rgb, dV [nv,3], d_eta, d_sigma [3])."""

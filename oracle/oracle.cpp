@@ -148,24 +148,6 @@ inline V3<S> normalize(V3<S> a) {
 template <class S>
 inline V3<double> vval(V3<S> a) { return {val(a.x), val(a.y), val(a.z)}; }
 
-// ---------------------------------------------------------------------------
-// bfloat16 rounding (round to nearest, ties to even) of a double value that is
-// first rounded to float.  Used only by the MLP environment.
-// ---------------------------------------------------------------------------
-inline double bf16_round(double x) {
-  float f = (float)x;
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  uint32_t lsb = (u >> 16) & 1u;
-  u = (u + 0x7FFFu + lsb) & 0xFFFF0000u;
-  float g;
-  std::memcpy(&g, &u, 4);
-  return (double)g;
-}
-// Rounding is a step function: derivative taken as identity (straight-through),
-// the same convention as the device's input-gradient of the MLP.
-inline Var bf16_round(Var x) { return mk(bf16_round(x.v), x.i, 1.0); }
-
 }  // namespace
 
 extern "C" {
@@ -181,7 +163,6 @@ typedef struct {
   int in_pad;               // MLP: padded input width
   const double* weights;    // MLP: concatenated row-major [out][in] per layer
   const double* biases;     // MLP: concatenated per layer
-  int exact;                // MLP: 1 = no bfloat16 rounding anywhere (pure FP64 network)
 } or_env;
 
 typedef struct {
@@ -532,10 +513,10 @@ V3<S> env_equirect(const or_env& e, V3<S> dir, EnvOut& eo) {
   return out;
 }
 
-// MLP environment: gamma(d) = [d, sin(2^k pi d), cos(2^k pi d)] for k < n_freq,
-// zero-padded; hidden layers with ReLU; linear RGB head.  The encoded input
-// and each post-ReLU activation are rounded to bfloat16; weights are given
-// already on the bfloat16 grid; biases and accumulation are FP64 here.
+// MLP environment (env_mlp below): gamma(d) = [d, sin(2^k pi d), cos(2^k pi d)]
+// for k < n_freq, zero-padded; hidden layers with ReLU; linear RGB head; plain
+// FP64 throughout (the weights are whatever the caller gives).
+//
 // Smallest first-order angular distance to a ReLU kink: for every hidden
 // pre-activation z, |z| / |dz/du| with u the unit direction (the network is
 // piecewise smooth in u; its gradient jumps where a z changes sign).
@@ -564,8 +545,6 @@ double mlp_kink_margin(const or_env& e, V3<double> d) {
       ++k;
     }
   }
-  if (!e.exact)
-    for (auto& x : h) x = bf16_round(x);
   double margin = 1e300;
   const double* W = e.weights;
   const double* B = e.biases;
@@ -597,7 +576,7 @@ double mlp_kink_margin(const or_env& e, V3<double> d) {
     J.assign((size_t)out * 3, 0.0);
     for (int j = 0; j < out; ++j)
       if (z[j] > 0) {
-        h[j] = e.exact ? z[j] : bf16_round(z[j]);
+        h[j] = z[j];
         J[3 * j] = Jz[3 * j];
         J[3 * j + 1] = Jz[3 * j + 1];
         J[3 * j + 2] = Jz[3 * j + 2];
@@ -624,8 +603,6 @@ V3<S> env_mlp(const or_env& e, V3<S> dir, EnvOut& eo) {
     for (int c = 0; c < 3; ++c) h[k++] = Sin(S(w) * dc[c]);
     for (int c = 0; c < 3; ++c) h[k++] = Cos(S(w) * dc[c]);
   }
-  if (!e.exact)
-    for (auto& x : h) x = bf16_round(x);
   const double* W = e.weights;
   const double* B = e.biases;
   int in = e.in_pad;
@@ -636,7 +613,7 @@ V3<S> env_mlp(const or_env& e, V3<S> dir, EnvOut& eo) {
       S acc = S(B[j]);
       for (int i = 0; i < in; ++i) acc = acc + S(W[(size_t)j * in + i]) * h[i];
       if (l < e.n_layers)
-        z[j] = e.exact ? Relu(acc) : bf16_round(Relu(acc));
+        z[j] = Relu(acc);
       else
         z[j] = acc;
     }
@@ -656,10 +633,27 @@ V3<S> env_eval(const or_env& e, V3<S> d, EnvOut& eo) {
 // ---------------------------------------------------------------------------
 // recursive tracer
 // ---------------------------------------------------------------------------
+// SplitMix64 output function (Steele, Lea and Flood, "Fast splittable
+// pseudorandom number generators", OOPSLA 2014), used as a 64-bit mixer.
+inline uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 struct PathInfo {
   int flags = 0;
   double wtrunc[3] = {0, 0, 0};
   int nseg = 0;
+  // order-independent signature of the discrete path: the sum (mod 2^64) over
+  // the tree's segments of a mix of (generation, triangle hit or -1, TIR)
+  uint64_t sig = 0;
+  void node(int g, int tri, bool tir) {
+    uint64_t key = ((uint64_t)(uint32_t)g << 40) | ((uint64_t)(tir ? 1u : 0u) << 32) |
+                   (uint64_t)(uint32_t)(tri + 1);
+    sig += splitmix64(key);
+  }
   uint64_t hash = 1469598103934665603ull;
   void mix(uint64_t x) {
     for (int i = 0; i < 8; ++i) {
@@ -700,6 +694,7 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
     EnvOut eo;
     V3<S> E = env_eval(*sc.env, d, eo);
     pi.mix(0xE0000000ull ^ ((uint64_t)(uint32_t)eo.cell_x << 16) ^ (uint64_t)(uint32_t)eo.cell_y);
+    pi.node(g, -1, false);
     if (eo.kink < 1e-5) pi.flags |= OR_FLAG_KINK;
     if (tree) {
       rec.kind = 0;
@@ -764,6 +759,7 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
     pi.flags |= OR_FLAG_TRUNC;
     for (int k = 0; k < 3; ++k) pi.wtrunc[k] += W[k] * Av[k];
     pi.mix(0x70000000ull ^ (uint64_t)h.tri);
+    pi.node(g, h.tri, false);
     if (tree) {
       rec.kind = 2;
       tree->push_back(rec);
@@ -782,6 +778,7 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
   V3<S> rdir = normalize(add(d, scl(n, S(2.0) * cos_i)));
   bool tir = val(sin2t) > 1.0;
   pi.mix(((uint64_t)h.tri << 2) ^ (tir ? 1u : 0u) ^ (entering ? 2u : 0u));
+  pi.node(g, h.tri, tir);
   // the child that continues on the same side of the surface as the parent
   // stays outside/inside accordingly
   bool r_inside = !entering, t_inside = entering;
@@ -939,6 +936,21 @@ int or_env_eval(const or_env* env, const double* dirs, int64_t n, double* rgb) {
   return 0;
 }
 
+// Angular distance (radians, first order) from each direction to the nearest
+// direction where the environment's gradient jumps (texel-centre line of the
+// bilinear map, zero of a hidden pre-activation of the MLP).
+int or_env_kink_margin(const or_env* env, const double* dirs, int64_t n, double* margin) {
+  if (!env) return 1;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    EnvOut eo;
+    V3<double> d{dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2]};
+    env_eval<double>(*env, d, eo);
+    margin[i] = eo.kink;
+  }
+  return 0;
+}
+
 // Gradient of sum(grad_rgb * E(dirs)) with respect to the directions.
 int or_env_eval_grad(const or_env* env, const double* dirs, int64_t n, const double* grad_rgb,
                      double* grad_dirs) {
@@ -977,7 +989,7 @@ int or_env_eval_grad(const or_env* env, const double* dirs, int64_t n, const dou
 // truncated weight [n*3], flags [n], path signature hash [n], segment count [n].
 // Any output pointer may be NULL.
 int or_trace(const or_scene* sc, const double* o, const double* d, int64_t n, double* rgb,
-             double* wtrunc, int* flags, uint64_t* hash, int* nseg) {
+             double* wtrunc, int* flags, uint64_t* hash, int* nseg, uint64_t* sig) {
   if (!valid_scene(sc)) return 1;
   Shared sh;
   make_shared(sc, sh, true);
@@ -998,6 +1010,7 @@ int or_trace(const or_scene* sc, const double* o, const double* d, int64_t n, do
     if (flags) flags[i] = pi.flags;
     if (hash) hash[i] = pi.hash;
     if (nseg) nseg[i] = pi.nseg;
+    if (sig) sig[i] = pi.sig;
   }
   return 0;
 }

@@ -90,7 +90,7 @@ def load(path: str = LIB_PATH):
     L.dt_env_query_backward.argtypes = [C.POINTER(_Env), vp, i64, vp, vp, vp]
     L.dt_trace_bytes.argtypes = [C.POINTER(_Params), i64, i32, i32, sz, sz]
     L.dt_trace_forward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params), vp, vp,
-                                   vp, vp, vp, C.c_size_t, vp, C.c_size_t, vp]
+                                   vp, vp, vp, vp, C.c_size_t, vp, C.c_size_t, vp]
     L.dt_trace_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params), vp, vp,
                                     C.c_size_t, vp, vp, vp, vp, C.c_size_t, vp]
     L.dt_intersect.argtypes = [C.POINTER(_Scene), vp, vp, vp, i64, C.c_float, i32, vp, vp, vp, vp]
@@ -335,17 +335,23 @@ class Buffers:
 
 
 def dt_trace_forward(scene: Scene, rays: Rays, params: Params, buf: Buffers,
-                     want_aux: bool = True):
-    """Returns (rgb [npix,3], wtrunc [npix,3] or None, flags [npix] or None)."""
+                     want_aux: bool = True, path_sig: torch.Tensor | None = None):
+    """Returns (rgb [npix,3], wtrunc [npix,3] or None, flags [npix] or None).
+    path_sig: optional int64 [npix] device tensor that receives each pixel's
+    path signature (the bits of the unsigned 64-bit value)."""
     dev = scene.mesh.V.device
     npix = rays.n_pixels
     rgb = torch.empty(npix, 3, dtype=torch.float32, device=dev)
     wtrunc = torch.empty(npix, 3, dtype=torch.float32, device=dev) if want_aux else None
     flags = torch.empty(npix, dtype=torch.int32, device=dev) if want_aux else None
+    if path_sig is not None:
+        _dev_check(path_sig)
+        if path_sig.dtype != torch.int64 or path_sig.numel() != npix:
+            raise DTError("path_sig must be an int64 tensor of n_pixels elements")
     sc, p = scene.c(), params.c()
     tape = buf.tape
     _check(load().dt_trace_forward(C.byref(sc), C.byref(rays.s), C.byref(p), _ptr(rgb), _ptr(wtrunc),
-                                   _ptr(flags), _ptr(buf.stats), _ptr(tape),
+                                   _ptr(flags), _ptr(path_sig), _ptr(buf.stats), _ptr(tape),
                                    0 if tape is None else tape.numel(), _ptr(buf.ws), buf.ws.numel(),
                                    _stream(dev)))
     return rgb, wtrunc, flags

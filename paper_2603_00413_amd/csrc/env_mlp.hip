@@ -2,16 +2,22 @@
 //
 // E(d) = head( relu(... relu(W0 gamma(u) + b0) ...) ), u = d / |d|,
 // gamma(u) = [u, sin(2^k pi u), cos(2^k pi u)]_{k < n_freq}, zero-padded to 64.
-// The encoded input and every post-ReLU activation are rounded to bf16
-// (round to nearest even); weights are bf16, biases and accumulation FP32.
+// Weights are bf16 (exact operands), biases FP32.  Every activation vector
+// (the encoding and each hidden layer's ReLU output) is carried as a pair of
+// bf16 vectors, hi = bf16(x) and lo = bf16(x - hi), and each layer is two
+// MFMAs (W * hi + W * lo) accumulated in FP32, so activations keep about 16
+// significant bits and the network is a continuous function of the direction
+// to that precision (a single bf16 rounding would put steps of 2^-9 relative
+// into it, and its derivative would depend on which side of a step a ray
+// lands).
 //
 // One wave evaluates 16 rays.  Layers are computed transposed,
 // D[out][ray] = W[out][in] * H[in][ray], so W is the MFMA A operand and the
 // activations the B operand; the accumulator layout of one layer (lane l holds
 // rows 4*(l/16)+j of column l%16) is exactly the B layout the next layer
 // needs, and activations never leave registers.  The input gradient runs the
-// same way with W^T as the A operand and the upstream gradient split into two
-// bf16 parts (hi + lo), which keeps ~16 bits of it through the bf16 products.
+// same way with W^T as the A operand and the upstream gradient split the same
+// way into hi + lo.
 #include "dt_queue.h"
 
 namespace {
@@ -70,12 +76,17 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
   constexpr int KB = HID / 16;
   float inv_len = 1.0f / sqrtf(dot(d, d));
   v3 u = d * inv_len;
-  bf16x4 x[IN / 16];
+  bf16x4 xh[IN / 16], xl[IN / 16];
 #pragma unroll
   for (int kb = 0; kb < IN / 16; ++kb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) x[kb][j] = f2bf(enc(kb * 16 + 4 * q + j, u, e.n_freq));
-  bf16x4 act[NL][KB];
+    for (int j = 0; j < 4; ++j) {
+      float v = enc(kb * 16 + 4 * q + j, u, e.n_freq);
+      xh[kb][j] = f2bf(v);
+      xl[kb][j] = f2bf(v - bf2f(xh[kb][j]));
+    }
+  bf16x4 act[NL][KB];  // hi parts of every hidden layer (their signs are the ReLU masks)
+  bf16x4 lo[KB];       // lo part of the latest hidden layer
   const uint16_t* W = e.w;
   const float* B = e.b;
   // first hidden layer, on the encoding
@@ -87,16 +98,22 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
 #pragma unroll
     for (int kb = 0; kb < IN / 16; ++kb) {
       bf16x4 a = *(const bf16x4*)(W + (size_t)(ob * 16 + r16) * IN + kb * 16 + 4 * q);
-      acc = mfma(a, x[kb], acc);
+      acc = mfma(a, xh[kb], acc);
+      acc = mfma(a, xl[kb], acc);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) act[0][ob][j] = f2bf(fmaxf(acc[j], 0.f));
+    for (int j = 0; j < 4; ++j) {
+      float v = fmaxf(acc[j], 0.f);
+      act[0][ob][j] = f2bf(v);
+      lo[ob][j] = f2bf(v - bf2f(act[0][ob][j]));
+    }
   }
   W += (size_t)HID * IN;
   B += HID;
   // further hidden layers
 #pragma unroll
   for (int L = 1; L < NL; ++L) {
+    bf16x4 nlo[KB];
 #pragma unroll
     for (int ob = 0; ob < KB; ++ob) {
       f32x4 acc;
@@ -106,10 +123,17 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
       for (int kb = 0; kb < KB; ++kb) {
         bf16x4 a = *(const bf16x4*)(W + (size_t)(ob * 16 + r16) * HID + kb * 16 + 4 * q);
         acc = mfma(a, act[L - 1][kb], acc);
+        acc = mfma(a, lo[kb], acc);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) act[L][ob][j] = f2bf(fmaxf(acc[j], 0.f));
+      for (int j = 0; j < 4; ++j) {
+        float v = fmaxf(acc[j], 0.f);
+        act[L][ob][j] = f2bf(v);
+        nlo[ob][j] = f2bf(v - bf2f(act[L][ob][j]));
+      }
     }
+#pragma unroll
+    for (int ob = 0; ob < KB; ++ob) lo[ob] = nlo[ob];
     W += (size_t)HID * HID;
     B += HID;
   }
@@ -122,6 +146,7 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
     bf16x4 a = {0, 0, 0, 0};
     if (r16 < 3) a = *(const bf16x4*)(W + (size_t)r16 * HID + kb * 16 + 4 * q);
     out = mfma(a, act[NL - 1][kb], out);
+    out = mfma(a, lo[kb], out);
   }
   v3 E = mk3(out[0], out[1], out[2]);
   if (!GRAD) return E;

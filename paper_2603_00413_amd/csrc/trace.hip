@@ -241,11 +241,21 @@ __device__ __forceinline__ void add_rgb(float* rgb, int pix, v3 v) {
 
 __device__ __forceinline__ v3 mul3(v3 a, v3 b) { return mk3(a.x * b.x, a.y * b.y, a.z * b.z); }
 
+// 64-bit mixer: the SplitMix64 output function (Steele, Lea and Flood,
+// OOPSLA 2014).  Summed over a pixel's segments it gives an order-independent
+// signature of the discrete path (generation, triangle or -1, TIR).
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
 // ------------------------------------------------------------------ k_trace (a4 + a5 decisions + a6)
 __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
-                                              int32_t* flags, int accumulate, uint32_t* miss_list,
-                                              uint2* ovf) {
+                                              int32_t* flags, unsigned long long* sig,
+                                              int accumulate, uint32_t* miss_list, uint2* ovf) {
   __shared__ uint2 stk[DT_STACK_LDS * TB];
   uint2* gstk = ovf + (size_t)(blockIdx.x * TB + threadIdx.x) * (DT_STACK - DT_STACK_LDS);
   const uint32_t n = ctr->count[g];
@@ -305,6 +315,12 @@ __global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counter
       }
       q.code[i] = code;
       if (accumulate && flags && pf) atomicOr(flags + pix, pf);
+      if (accumulate && sig) {
+        bool tir = (code & C_TIR) && !(code & C_TRUNC);
+        uint64_t key = ((uint64_t)(uint32_t)g << 40) | ((uint64_t)(tir ? 1u : 0u) << 32) |
+                       (uint64_t)(uint32_t)(h.tri + 1);
+        atomicAdd(sig + pix, (unsigned long long)mix64(key));
+      }
     }
     uint64_t br = __ballot(has_r), bt = __ballot(has_t), bh = __ballot(hit);
     if (lane == 0 && (br | bt))
@@ -868,11 +884,12 @@ dt_status record(void* const* ev, int i, hipStream_t s) {
 
 dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen nxt, Counters* ctr,
                          unsigned long long* part_g, unsigned long long* part_other, float* rgb,
-                         float* wtrunc, int32_t* flags, int accumulate, int write_next,
-                         void* const* events, uint32_t* miss_list, uint2* ovf, hipStream_t s) {
+                         float* wtrunc, int32_t* flags, unsigned long long* sig, int accumulate,
+                         int write_next, void* const* events, uint32_t* miss_list, uint2* ovf,
+                         hipStream_t s) {
   if (dt_status st = record(events, 2 * g, s)) return st;
   hipLaunchKernelGGL(k_trace, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
-                     rgb, wtrunc, flags, accumulate, miss_list, ovf);
+                     rgb, wtrunc, flags, sig, accumulate, miss_list, ovf);
   DT_CHECK_LAUNCH();
   if (dt_status st = record(events, 2 * g + 1, s)) return st;
   if (accumulate && sc.env.kind == DT_ENV_MLP)
@@ -990,8 +1007,9 @@ extern "C" dt_status dt_trace_bytes(const dt_trace_params* p, int64_t n_rays, in
 
 extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays,
                                       const dt_trace_params* p, float* rgb, float* wtrunc,
-                                      int32_t* flags, int64_t* stats, void* tape, size_t tape_bytes,
-                                      void* ws, size_t ws_bytes, void* stream) {
+                                      int32_t* flags, uint64_t* path_sig, int64_t* stats,
+                                      void* tape, size_t tape_bytes, void* ws, size_t ws_bytes,
+                                      void* stream) {
   SceneDev sc;
   if (dt_status st = make_scene(scene, p, sc)) return st;
   int64_t N, npix;
@@ -1018,6 +1036,7 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
   if (dt_status st = zero_f32(rgb, 3 * npix, s)) return st;
   if (dt_status st = zero_f32(wtrunc, 3 * npix, s)) return st;
   if (dt_status st = zero_f32((float*)flags, npix, s)) return st;
+  if (dt_status st = zero_u64((unsigned long long*)path_sig, npix, s)) return st;
 
   // where generation g lives during the forward pass: on the tape when it is
   // stored there, otherwise in the ping-pong scratch queues of the workspace
@@ -1046,8 +1065,8 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
     Gen nxt = g < P.D ? gen_fwd(g + 1) : cur;
     void* const* ev = p->timing ? p->timing->trace_events : nullptr;
     if (dt_status st = run_generation(sc, P, g, cur, nxt, ctr, part[g & 1], part[(g + 1) & 1], rgb,
-                                      wtrunc, flags, 1, 1, ev, (uint32_t*)(W + P.w_miss),
-                                      (uint2*)(W + P.w_ovf), s))
+                                      wtrunc, flags, (unsigned long long*)path_sig, 1, 1, ev,
+                                      (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), s))
       return st;
   }
   if (T) hipLaunchKernelGGL(k_save_counters, dim3(1), dim3(64), 0, s, (Counters*)(T + P.tape_hdr), ctr);
@@ -1142,7 +1161,8 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
         int j = g - g0;
         Gen nxt = g < g1 ? seg[j + 1] : seg[j];
         if (dt_status st = run_generation(sc, P, g, seg[j], nxt, ctr, part[g & 1], part[(g + 1) & 1],
-                                          nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0, nullptr,
+                                          nullptr, nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0,
+                                          nullptr,
                                           (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), s))
           return st;
       }

@@ -18,6 +18,10 @@ HARD = B.FLAG_OVERFLOW | B.FLAG_STACK
 # the environment's gradient jumps (texel-centre line, ReLU kink); FP32 and
 # FP64 paths may straddle it, so gradients (not values) are compared off it
 KINK = oracle.FLAG_KINK
+# relative L2 bound between two device runs of the same vertex gradient: the
+# per-vertex sums are FP32 atomic additions in run-dependent order, so with
+# cancellation among the terms they agree to a few 1e-6, not bit for bit
+DV_ORDER_TOL = 1e-5
 
 
 def device():
@@ -59,10 +63,13 @@ class Pair:
         self.o, self.d = np.concatenate(o), np.concatenate(d)
 
     def gpu_forward(self, tape=True, params=None):
+        """Device render; also leaves the per-pixel path signatures in self.sig."""
         p = params or self.params
         buf = B.Buffers(p, self.rays, self.mesh, tape=tape)
-        rgb, wt, fl = B.dt_trace_forward(self.scene, self.rays, p, buf)
+        sig = torch.empty(self.rays.n_pixels, dtype=torch.int64, device=self.mesh.V.device)
+        rgb, wt, fl = B.dt_trace_forward(self.scene, self.rays, p, buf, path_sig=sig)
         torch.cuda.synchronize()
+        self.sig = sig.cpu().numpy().view(np.uint64)
         return buf, rgb.cpu().numpy().astype(np.float64), wt.cpu().numpy().astype(np.float64), \
             fl.cpu().numpy()
 
@@ -78,6 +85,23 @@ def rel_err(g, o):
     """Per pixel-channel |g - o| / max(|o|, 1e-3 * mean(o))."""
     floor = 1e-3 * max(np.abs(o).mean(), 1e-30)
     return np.abs(g - o) / np.maximum(np.abs(o), floor)
+
+
+def rgb_rel_err(g, o):
+    """Per pixel ||g - o|| / max(||o||, 1e-3 * mean ||o||) over the RGB triple.
+    Used where the environment is the MLP: its linear head can bring a single
+    channel near zero by cancellation of O(1) terms, where FP32 rounding of
+    those terms is relative noise in that channel alone."""
+    n = np.linalg.norm(o, axis=1)
+    floor = 1e-3 * max(n.mean(), 1e-30)
+    return np.linalg.norm(g - o, axis=1) / np.maximum(n, floor)
+
+
+def l2_upstream(ref_rgb, target_rgb, mask):
+    """dLoss/dC of the L2 image loss sum_i mask_i ||C_i - T_i||^2 / n at the
+    oracle's own render (so both sides take the same upstream gradient, and
+    none of it comes from the device)."""
+    return 2.0 * (ref_rgb - target_rgb) / max(int(mask.sum()), 1) * mask[:, None]
 
 
 def icosphere_pair(sigma=(0.0, 0.0, 0.0), res=64, **kw):

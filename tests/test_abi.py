@@ -47,7 +47,8 @@ def test_host_validation_without_device():
     assert L.dt_trace_bytes(C.byref(p), 4096, 642, 1280, C.byref(a), C.byref(b)) == 0
     assert b.value > tape2          # storing every generation costs more tape
     # a null scene is rejected before anything touches a device
-    assert L.dt_trace_forward(None, None, None, None, None, None, None, None, 0, None, 0, None) == 1
+    assert L.dt_trace_forward(None, None, None, None, None, None, None, None, None, 0, None, 0,
+                              None) == 1
     assert L.dt_status_string(2) == b"workspace too small"
 
 

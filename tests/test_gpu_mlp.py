@@ -1,11 +1,11 @@
-"""Parity of the bf16-MFMA environment MLP with the oracle's emulation.
+"""Parity of the bf16-MFMA environment MLP with the oracle's FP64 network.
 
-Bars: the device rounds the encoded input and each hidden activation to bf16
-after FP32 accumulation, the oracle after FP64 accumulation, so an activation
-can land on the other side of a bf16 rounding boundary ("flip"), which moves
-the output by about 2^-8 of one activation's contribution.  So: rays without a
-flip agree to 1e-4 relative (>= 97% of rays), every ray agrees to 1e-2 of the
-mean output magnitude, and a hand-computed net is reproduced exactly.
+The device keeps every activation as a pair of bf16 values (hi + lo, about 16
+significant bits) and accumulates in FP32, so it evaluates the same
+continuous function as the FP64 network to roughly 2^-17 of each term.  Bars:
+per direction, ||E_dev - E|| / ||E|| <= 1e-4 (the RGB triple: a single channel
+that the linear head brings near zero by cancellation carries relative noise
+alone); the direction gradient to 1e-3 where no ReLU kink lies within 1e-5 rad.
 """
 import numpy as np
 import pytest
@@ -14,7 +14,7 @@ import torch
 import oracle
 from paper_2603_00413_amd import binding as B
 from paper_2603_00413_amd import synth
-from tests.gpu_helpers import BAD, HARD, KINK, device, rel_err
+from tests.gpu_helpers import BAD, HARD, KINK, device, l2_upstream, rgb_rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,10 @@ def _dirs(n, seed):
 
 def test_hand_computed_tiny_net_exact():
     """Same net as the oracle pin: E = (x + 0.5, 2y, 0.5x + 0.25y - 1) with
-    x = bf16(0.6) = 0.6015625, y = bf16(0.8) = 0.80078125 (d = (0.6, 0.8, 0))."""
+    (x, y) = d = (0.6, 0.8, 0), i.e. (1.1, 1.6, -0.5).  The hi + lo pairs of
+    0.6 and 0.8 are 0.6015625 - 0.00156402588 and 0.80078125 - 0.00078201294
+    (each part a bf16), within 1.6e-6 and 7.7e-7 of the inputs, so E is
+    within 2e-6 of the exact values."""
     dev = device()
     Ws = [np.zeros((64, 64), np.float32), np.zeros((3, 64), np.float32)]
     Bs = [np.zeros(64, np.float32), np.array([0.5, 0.0, -1.0], np.float32)]
@@ -44,9 +47,7 @@ def test_hand_computed_tiny_net_exact():
     env = B.Env.mlp(Ws, Bs, 6, dev)
     d = torch.tensor([[0.6, 0.8, 0.0]] * 40, device=dev)
     E = B.dt_env_query(env, d).cpu().numpy()
-    x, y = 0.6015625, 0.80078125
-    expect = np.array([x + 0.5, 2 * y, 0.5 * x + 0.25 * y - 1.0], np.float32)
-    assert np.abs(E - expect).max() <= 2e-7
+    assert np.abs(E - np.array([1.1, 1.6, -0.5])).max() <= 2e-6
 
 
 @pytest.mark.parametrize("width,layers", [(64, 3), (128, 4)])
@@ -58,24 +59,19 @@ def test_mlp_query_vs_oracle(width, layers):
     d = _dirs(20000, width + layers)
     E = B.dt_env_query(env, torch.from_numpy(d).to(dev)).cpu().numpy().astype(np.float64)
     Eo = oenv.eval(d.astype(np.float64))
-    err = rel_err(E, Eo).max(1)
-    aerr = np.abs(E - Eo).max(1) / np.abs(Eo).mean()
-    _print(width, layers, "flip rate (> 1e-4)", (err > 1e-4).mean(), "max abs / mean", aerr.max())
-    assert (err <= 1e-4).mean() >= 0.97
-    # a flip moves the output by ~2^-8 of one activation's share; wider and
-    # deeper nets carry more of them
-    assert aerr.max() <= (1e-2 if width == 64 else 2e-2)
-    # input gradient (bf16 rounding taken as identity on both sides)
+    err = rgb_rel_err(E, Eo)
+    _print(width, layers, "E: median", np.median(err), "max", err.max())
+    assert err.max() <= 1e-4
+    # input gradient, away from the ReLU kinks
     g = np.random.default_rng(1).normal(size=d.shape).astype(np.float32)
     gd = B.dt_env_query_backward(env, torch.from_numpy(d).to(dev),
                                  torch.from_numpy(g).to(dev)).cpu().numpy().astype(np.float64)
     gdo = oenv.eval_grad(d.astype(np.float64), g.astype(np.float64))
-    num = np.linalg.norm(gd - gdo, axis=1)
-    den = np.linalg.norm(gdo, axis=1) + 1e-3 * np.linalg.norm(gdo, axis=1).mean()
-    r = num / den
-    _print(width, layers, "grad frac > 1e-3", (r > 1e-3).mean(), "max", r.max())
-    assert (r <= 1e-3).mean() >= 0.98
-    assert np.median(r) < 1e-4
+    far = oenv.kink_margin(d.astype(np.float64)) > 1e-5
+    r = np.linalg.norm(gd - gdo, axis=1) / np.linalg.norm(gdo, axis=1)
+    _print(width, layers, "grad: kink-free", far.mean(), "median", np.median(r[far]), "max", r[far].max())
+    assert far.mean() > 0.8
+    assert r[far].max() <= 1e-3
 
 
 def test_trace_with_mlp_environment():
@@ -93,15 +89,17 @@ def test_trace_with_mlp_environment():
     buf, rgb, wt, fl = P.gpu_forward(tape=True)
     ref = P.orc.trace(P.o, P.d)
     ok = ((fl | ref["flags"]) & (BAD | HARD)) == 0
-    err = rel_err(rgb, ref["rgb"]).max(1)
-    aerr = np.abs(rgb - ref["rgb"]).max(1) / np.abs(ref["rgb"]).mean()
-    _print("MLP trace: frac > 1e-4", (err[ok] > 1e-4).mean(), "max rel", err[ok].max(),
-           "max abs / mean", aerr[ok].max())
-    # a pixel averages many leaves, each of which may carry a flip
-    assert np.median(err[ok]) <= 1e-5 and aerr[ok].max() <= 1e-2
-    okg = ok & ((ref["flags"] & KINK) == 0)
+    same = P.sig == ref["sig"]
+    err = rgb_rel_err(rgb, ref["rgb"])
+    _print("MLP trace: excluded", 1 - ok.mean(), "median", np.median(err[ok]), "max", err[ok].max(),
+           "paths differing", (~same[ok]).sum())
+    assert 1 - ok.mean() < 0.05
+    assert err[ok].max() <= 1e-4
+    assert (~same[ok]).mean() <= 2e-3
+    okg = ok & same & ((ref["flags"] & KINK) == 0)
     _print("MLP trace: gradient pixels excluded near ReLU kinks", 1 - okg.mean() / ok.mean())
-    g = np.random.default_rng(0).normal(size=rgb.shape) * okg[:, None]
+    tgt = P.orc.with_(eta=1.52, sigma=(0.4, 0.25, 0.15)).trace(P.o, P.d)["rgb"]
+    g = l2_upstream(ref["rgb"], tgt, okg)
     dV, de, ds = P.gpu_backward(buf, g)
     o = P.orc.trace_grad(P.o, P.d, g)
     ev = np.linalg.norm(dV - o["dV"]) / np.linalg.norm(o["dV"])

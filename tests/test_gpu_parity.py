@@ -12,7 +12,8 @@ import torch
 import oracle
 from paper_2603_00413_amd import binding as B
 from paper_2603_00413_amd import synth
-from tests.gpu_helpers import BAD, HARD, KINK, Pair, device, icosphere_pair, rel_err, torus_pair
+from tests.gpu_helpers import (BAD, DV_ORDER_TOL, HARD, KINK, Pair, device, icosphere_pair,
+                               l2_upstream, rel_err, torus_pair)
 
 pytestmark = pytest.mark.gpu
 
@@ -122,9 +123,15 @@ def test_forward_icosphere(sigma):
     assert not (fl & HARD).any()
     ok = ((fl | ref["flags"]) & BAD) == 0
     err = rel_err(rgb, ref["rgb"])
-    _print("C1 sigma", sigma, "excluded", 1 - ok.mean(), "max err", err[ok].max())
+    same = P.sig == ref["sig"]
+    _print("C1 sigma", sigma, "excluded", 1 - ok.mean(), "max err", err[ok].max(),
+           "paths differing", (~same[ok]).sum())
     assert 1 - ok.mean() < 0.05
     assert err[ok].max() <= 1e-4
+    # the discrete path (triangle per segment, TIR branches) is an integer
+    # result: the same on both sides but where a hit falls within FP32
+    # rounding of a shared edge
+    assert (~same[ok]).mean() <= 1e-3
     np.testing.assert_allclose(wt[ok], ref["wtrunc"][ok], rtol=1e-4, atol=1e-6)
 
 
@@ -150,11 +157,14 @@ def test_forward_torus_small():
     ok = ((fl | ref["flags"]) & BAD) == 0
     err = rel_err(rgb, ref["rgb"])
     bad = ok[:, None] & (err > 1e-4)
-    _print("torus excluded", 1 - ok.mean(), "max err", err[ok].max(), "n>1e-4", bad.any(1).sum())
+    same = P.sig == ref["sig"]
+    _print("torus excluded", 1 - ok.mean(), "max err", err[ok].max(), "n>1e-4", bad.any(1).sum(),
+           "paths differing", (~same[ok]).sum())
     stats = buf.stats.cpu().numpy()
     _print("segments gpu", stats[B.STAT_TOTAL], "oracle", ref["nseg"].sum())
     assert 1 - ok.mean() < 0.05
     assert bad.any(1).mean() < 1e-3
+    assert (~same[ok]).mean() < 2e-3
     assert abs(stats[B.STAT_TOTAL] - ref["nseg"].sum()) <= 1e-3 * ref["nseg"].sum()
 
 
@@ -164,6 +174,7 @@ def _grad_check(P, seed=0):
     ref = P.orc.trace(P.o, P.d)
     ok = ((fl | ref["flags"]) & (BAD | HARD)) == 0
     ok &= (ref["flags"] & KINK) == 0
+    ok &= P.sig == ref["sig"]          # interior derivatives of the same discrete path
     g = np.random.default_rng(seed).normal(size=rgb.shape) * ok[:, None]
     dV, de, ds = P.gpu_backward(buf, g)
     o = P.orc.trace_grad(P.o, P.d, g)
@@ -198,7 +209,10 @@ def test_recompute_matches_store_all(stride):
     buf2, rgb2, _, _ = P.gpu_forward(tape=True, params=p2)
     assert np.array_equal(rgb, rgb2) or np.abs(rgb - rgb2).max() < 1e-6
     dV2, de2, ds2 = P.gpu_backward(buf2, g, params=p2)
-    assert np.linalg.norm(dV1 - dV2) <= 1e-6 * np.linalg.norm(dV1) + 1e-9
+    # identical per-node terms; the vertex sums are FP32 atomic additions whose
+    # order varies from run to run (measured up to 2.3e-6 relative), while the
+    # scalar gradients are reduced in a fixed order
+    assert np.linalg.norm(dV1 - dV2) <= DV_ORDER_TOL * np.linalg.norm(dV1) + 1e-9
     assert abs(de1 - de2) <= 1e-6 * abs(de1) + 1e-9
     assert np.all(np.abs(ds1 - ds2) <= 1e-6 * np.abs(ds1) + 1e-9)
     assert buf2.tape_bytes < buf.tape_bytes
@@ -217,7 +231,8 @@ def test_queue_overflow_is_reported():
 def test_full_size_torus_sampled_pixels():
     """The benchmark workload (8 views x 512^2, depth 6, 102,400 tris) traced in
     full on the device; the oracle checks 3,000 sampled pixels one by one, and
-    the gradient of a loss that weights only those pixels."""
+    the gradient of an L2 loss on those pixels against a target the oracle
+    renders with other material parameters."""
     dev = device()
     wl = synth.torus_scene(n_views=8, res=512)
     P = Pair(wl.V, wl.F, wl.ior, wl.sigma, wl.env, wl.cameras, wl.max_depth,
@@ -229,14 +244,20 @@ def test_full_size_torus_sampled_pixels():
     pix = np.sort(rng.choice(len(P.o), 3000, replace=False))
     ref = P.orc.trace(P.o[pix], P.d[pix])
     ok = ((fl[pix] | ref["flags"]) & BAD) == 0
+    same = P.sig[pix] == ref["sig"]
     err = rel_err(rgb[pix], ref["rgb"])
     bad = ok[:, None] & (err > 1e-4)
     _print("full-size sampled: excluded", 1 - ok.mean(), "max err", err[ok].max(),
-           "pixels over 1e-4", bad.any(1).sum())
+           "pixels over 1e-4", bad.any(1).sum(), "paths differing", (~same[ok]).sum())
     assert 1 - ok.mean() < 0.05
     assert bad.any(1).mean() < 2e-3
+    assert (~same[ok]).mean() < 2e-3
+    # gradients where the discrete path (triangles, branches) is the same on
+    # both sides and no environment lookup sits on a gradient kink
+    tgt = P.orc.with_(eta=1.5, sigma=(0.25, 0.3, 0.35)).trace(P.o[pix], P.d[pix])["rgb"]
+    gmask = ok & same & ((ref["flags"] & KINK) == 0)
+    gs = l2_upstream(ref["rgb"], tgt, gmask)
     g = np.zeros_like(rgb)
-    gs = rng.normal(size=(len(pix), 3)) * (ok & ((ref["flags"] & KINK) == 0))[:, None]
     g[pix] = gs
     dV, de, ds = P.gpu_backward(buf, g)
     o = P.orc.trace_grad(P.o[pix], P.d[pix], gs)
@@ -267,8 +288,8 @@ def test_autograd_function_and_memory_policy():
         loss.backward()
         grads.append((V.grad.clone(), ior.grad.clone(), sigma.grad.clone(), tr.stride))
     assert grads[0][3] == 1 and grads[1][3] > 1
-    for a, b in zip(grads[0][:3], grads[1][:3]):
-        assert torch.linalg.norm(a - b) <= 1e-6 * torch.linalg.norm(a) + 1e-9
+    for a, b, tol in zip(grads[0][:3], grads[1][:3], (DV_ORDER_TOL, 1e-6, 1e-6)):
+        assert torch.linalg.norm(a - b) <= tol * torch.linalg.norm(a) + 1e-9
     # direct adjoint with the same upstream gradient
     buf, rgb, _, _ = P.gpu_forward(tape=True)
     g = (2.0 / rgb.size) * (rgb - target.cpu().numpy())

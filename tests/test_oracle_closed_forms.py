@@ -372,3 +372,39 @@ def test_camera_rays_geometry(oracle_lib):
     ang = math.acos(np.dot(top, bot) / np.linalg.norm(top) / np.linalg.norm(bot))
     expect = 2 * math.atan((1 - 1.0 / H) * math.tan(math.radians(fov / 2)))
     assert abs(ang - expect) < 1e-12
+
+
+def _mix64(x):
+    """SplitMix64 output function (Steele, Lea and Flood 2014), in Python integers."""
+    m = (1 << 64) - 1
+    z = (x + 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def test_path_signature(oracle_lib):
+    """The path signature is the sum mod 2^64 of mix64((g << 40) | (tir << 32)
+    | (tri + 1)) over the segments of the ray tree.  A ray that misses at
+    generation 0 has key 0, whose mix is SplitMix64's first output from seed 0,
+    0xE220A8397B1DCDAF; for traced torus pixels the sum over the depth-first
+    tree records (an independent listing of the same segments) matches."""
+    assert _mix64(0) == 0xE220A8397B1DCDAF
+    V, F = synth.displaced_torus(seed=2, nu=64, nv=32)
+    sc = oracle_lib.Scene(V, F, 1.45, 0.3, oracle_lib.Env(tex=synth.env_equirect(32, 16, seed=1)), 5)
+    miss = sc.trace(np.array([[0.0, 0.0, 5.0]]), np.array([[0.0, 0.0, 1.0]]))
+    assert int(miss["sig"][0]) == 0xE220A8397B1DCDAF
+    cam = synth.look_at_camera(np.array([0.3, 2.5, 1.2]), 24, 24)
+    o, d = oracle_lib.camera_rays(cam)
+    tr = sc.trace(o, d)
+    n_checked = 0
+    for i in range(0, len(o), 7):
+        want = 0
+        for r in sc.tree(o[i], d[i]):
+            tri = int(r["tri"]) if r["kind"] != 0 else -1
+            tir = 1 if (r["kind"] == 1 and r["tir"]) else 0
+            want = (want + _mix64((int(r["depth"]) << 40) | (tir << 32) | ((tri + 1) & 0xFFFFFFFF))) \
+                & ((1 << 64) - 1)
+        assert int(tr["sig"][i]) == want
+        n_checked += tr["nseg"][i] > 1
+    assert n_checked > 10
