@@ -2,22 +2,24 @@
 //
 // E(d) = head( relu(... relu(W0 gamma(u) + b0) ...) ), u = d / |d|,
 // gamma(u) = [u, sin(2^k pi u), cos(2^k pi u)]_{k < n_freq}, zero-padded to 64.
-// Weights are bf16 (exact operands), biases FP32.  Every activation vector
-// (the encoding and each hidden layer's ReLU output) is carried as a pair of
-// bf16 vectors, hi = bf16(x) and lo = bf16(x - hi), and each layer is two
-// MFMAs (W * hi + W * lo) accumulated in FP32, so activations keep about 16
-// significant bits and the network is a continuous function of the direction
-// to that precision (a single bf16 rounding would put steps of 2^-9 relative
-// into it, and its derivative would depend on which side of a step a ray
-// lands).
+// Weights are bf16 (exact MFMA operands), biases FP32.  Every activation
+// vector (the encoding and each hidden layer's ReLU output) is carried as
+// three bf16 vectors, hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid),
+// which together hold all 24 bits of the FP32 value, and each layer is three
+// MFMAs (W hi + W mid + W lo) accumulated in FP32: the products of bf16
+// weights and bf16 parts are exact, so a layer is as accurate as an FP32
+// matrix product.  (A single bf16 rounding per activation would put steps of
+// 2^-9 relative into E, and a derivative that depends on which side of a step
+// a ray lands.)  The encoding takes sin(pi t), cos(pi t) of t = 2^k u, which
+// is exact in FP32, so no argument rounding error grows with the frequency.
 //
 // One wave evaluates 16 rays.  Layers are computed transposed,
 // D[out][ray] = W[out][in] * H[in][ray], so W is the MFMA A operand and the
 // activations the B operand; the accumulator layout of one layer (lane l holds
 // rows 4*(l/16)+j of column l%16) is exactly the B layout the next layer
 // needs, and activations never leave registers.  The input gradient runs the
-// same way with W^T as the A operand and the upstream gradient split the same
-// way into hi + lo.
+// same way with W^T as the A operand and the upstream gradient split into
+// hi + lo (about 16 bits; the gradient tolerance is 1e-3).
 #include "dt_queue.h"
 
 namespace {
@@ -36,13 +38,26 @@ __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// three-part bf16 split of an FP32 value (each difference is exact in FP32)
+struct Split3 {
+  short h, m, l;
+};
+__device__ __forceinline__ Split3 split3(float v) {
+  Split3 s;
+  s.h = f2bf(v);
+  float r = v - bf2f(s.h);
+  s.m = f2bf(r);
+  s.l = f2bf(r - bf2f(s.m));
+  return s;
+}
+
 // encoding component k of the unit direction u
 __device__ __forceinline__ float enc(int k, v3 u, int n_freq) {
   if (k < 3) return comp(u, k);
   int r = k - 3, f = r / 6, c = r % 6;
   if (f >= n_freq) return 0.f;
-  float x = ldexpf(DT_PI, f) * comp(u, c < 3 ? c : c - 3);
-  return c < 3 ? sinf(x) : cosf(x);
+  float t = ldexpf(comp(u, c < 3 ? c : c - 3), f);
+  return c < 3 ? sinpif(t) : cospif(t);
 }
 
 // d enc_k / d u (only the component of u it depends on)
@@ -58,8 +73,8 @@ __device__ __forceinline__ void denc(int k, v3 u, int n_freq, float& dx, float& 
   if (f >= n_freq) return;
   int ax = c < 3 ? c : c - 3;
   float w = ldexpf(DT_PI, f);
-  float x = w * comp(u, ax);
-  float v = c < 3 ? w * cosf(x) : -w * sinf(x);
+  float t = ldexpf(comp(u, ax), f);
+  float v = c < 3 ? w * cospif(t) : -w * sinpif(t);
   if (ax == 0) dx += g * v;
   if (ax == 1) dy += g * v;
   if (ax == 2) dz += g * v;
@@ -76,17 +91,18 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
   constexpr int KB = HID / 16;
   float inv_len = 1.0f / sqrtf(dot(d, d));
   v3 u = d * inv_len;
-  bf16x4 xh[IN / 16], xl[IN / 16];
+  bf16x4 xh[IN / 16], xm[IN / 16], xl[IN / 16];
 #pragma unroll
   for (int kb = 0; kb < IN / 16; ++kb)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float v = enc(kb * 16 + 4 * q + j, u, e.n_freq);
-      xh[kb][j] = f2bf(v);
-      xl[kb][j] = f2bf(v - bf2f(xh[kb][j]));
+      Split3 p = split3(enc(kb * 16 + 4 * q + j, u, e.n_freq));
+      xh[kb][j] = p.h;
+      xm[kb][j] = p.m;
+      xl[kb][j] = p.l;
     }
-  bf16x4 act[NL][KB];  // hi parts of every hidden layer (their signs are the ReLU masks)
-  bf16x4 lo[KB];       // lo part of the latest hidden layer
+  bf16x4 act[NL][KB];   // hi parts of every hidden layer (their signs are the ReLU masks)
+  bf16x4 mi[KB], lo[KB];  // mid and lo parts of the latest hidden layer
   const uint16_t* W = e.w;
   const float* B = e.b;
   // first hidden layer, on the encoding
@@ -98,14 +114,16 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
 #pragma unroll
     for (int kb = 0; kb < IN / 16; ++kb) {
       bf16x4 a = *(const bf16x4*)(W + (size_t)(ob * 16 + r16) * IN + kb * 16 + 4 * q);
-      acc = mfma(a, xh[kb], acc);
       acc = mfma(a, xl[kb], acc);
+      acc = mfma(a, xm[kb], acc);
+      acc = mfma(a, xh[kb], acc);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float v = fmaxf(acc[j], 0.f);
-      act[0][ob][j] = f2bf(v);
-      lo[ob][j] = f2bf(v - bf2f(act[0][ob][j]));
+      Split3 p = split3(fmaxf(acc[j], 0.f));
+      act[0][ob][j] = p.h;
+      mi[ob][j] = p.m;
+      lo[ob][j] = p.l;
     }
   }
   W += (size_t)HID * IN;
@@ -113,7 +131,7 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
   // further hidden layers
 #pragma unroll
   for (int L = 1; L < NL; ++L) {
-    bf16x4 nlo[KB];
+    bf16x4 nmi[KB], nlo[KB];
 #pragma unroll
     for (int ob = 0; ob < KB; ++ob) {
       f32x4 acc;
@@ -122,18 +140,23 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
         bf16x4 a = *(const bf16x4*)(W + (size_t)(ob * 16 + r16) * HID + kb * 16 + 4 * q);
-        acc = mfma(a, act[L - 1][kb], acc);
         acc = mfma(a, lo[kb], acc);
+        acc = mfma(a, mi[kb], acc);
+        acc = mfma(a, act[L - 1][kb], acc);
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float v = fmaxf(acc[j], 0.f);
-        act[L][ob][j] = f2bf(v);
-        nlo[ob][j] = f2bf(v - bf2f(act[L][ob][j]));
+        Split3 p = split3(fmaxf(acc[j], 0.f));
+        act[L][ob][j] = p.h;
+        nmi[ob][j] = p.m;
+        nlo[ob][j] = p.l;
       }
     }
 #pragma unroll
-    for (int ob = 0; ob < KB; ++ob) lo[ob] = nlo[ob];
+    for (int ob = 0; ob < KB; ++ob) {
+      mi[ob] = nmi[ob];
+      lo[ob] = nlo[ob];
+    }
     W += (size_t)HID * HID;
     B += HID;
   }
@@ -145,8 +168,9 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
   for (int kb = 0; kb < KB; ++kb) {
     bf16x4 a = {0, 0, 0, 0};
     if (r16 < 3) a = *(const bf16x4*)(W + (size_t)r16 * HID + kb * 16 + 4 * q);
-    out = mfma(a, act[NL - 1][kb], out);
     out = mfma(a, lo[kb], out);
+    out = mfma(a, mi[kb], out);
+    out = mfma(a, act[NL - 1][kb], out);
   }
   v3 E = mk3(out[0], out[1], out[2]);
   if (!GRAD) return E;

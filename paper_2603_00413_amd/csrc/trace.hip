@@ -472,177 +472,269 @@ __device__ __forceinline__ void atomic_add3(float* p, int idx, v3 v) {
   atomicAdd(p + 3 * idx + 2, v.z);
 }
 
-__global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
+// Vertex contributions of one hit node: dLoss/dp_k for its three vertices and
+// dLoss/dN_k for their normals (absent where the geometric normal was used).
+struct VtxAdj {
+  int v[3];  // v[0] < 0: no contributions
+  v3 p0, p1, p2, n0, n1, n2;
+  bool has_n;
+};
+
+// Adjoint of node i of generation g: writes its record (subtree radiance,
+// d/d origin, d/d direction) to cur, adds its dIoR / dsigma terms to acc and
+// returns its vertex contributions.
+__device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, int64_t i,
+                                             const float* grad_rgb, const Adj& nxt, const Adj& cur,
+                                             float4& acc, VtxAdj& out) {
+  float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i], h4 = q.hit[i];
+  uint32_t code = q.code[i];
+  v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
+  int pix = __float_as_int(d4.w);
+  v3 gp = load3(grad_rgb + 3 * pix);
+  v3 gW = mul3(gp, W);
+  if (!(code & C_HIT)) {
+    if (sc.env.kind != DT_ENV_EQUIRECT) return;  // written by the MLP kernel
+    v3 dd;
+    v3 E = env_equirect_grad(sc.env, d, gW, &dd);
+    cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
+    cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    cur.D[i] = make_float4(dd.x, dd.y, dd.z, 0.f);
+    return;
+  }
+  bool trunc = (code & C_TRUNC) != 0u;
+  if (trunc && !sc.terminal_env) {
+    cur.L[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    cur.D[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  float t = h4.x, b1 = h4.z, b2 = h4.w;
+  int tri = __float_as_int(h4.y);
+  HitGeo geo = load_geo(sc, tri);
+  Shade s = shade(sc, geo, o, d, t, b1, b2, code);
+  const bool entering = (code & C_ENTER) != 0u, tir = (code & C_TIR) != 0u;
+  const bool degen = (code & C_DEGEN) != 0u;
+  v3 L, Abar, dbar = mk3(0.f, 0.f, 0.f), xbar = mk3(0.f, 0.f, 0.f), nbar = mk3(0.f, 0.f, 0.f);
+  float cibar = 0.f, ctbar = 0.f, etarbar = 0.f, etaibar = 0.f, etatbar = 0.f;
+  if (trunc) {
+    // terminal mode ENV: L = A * E(d)
+    v3 dd;
+    v3 E = env_equirect_grad(sc.env, d, mul3(gW, s.A), &dd);
+    L = mul3(s.A, E);
+    Abar = mul3(gW, E);
+    dbar = dd;
+  } else {
+    int2 ch = q.child[i];
+    v3 Lr = mk3(0.f, 0.f, 0.f), Lt = mk3(0.f, 0.f, 0.f), drb = Lr, dtb = Lr;
+    if (ch.x >= 0) {
+      Lr = xyz(nxt.L[ch.x]);
+      xbar += xyz(nxt.O[ch.x]);
+      drb = xyz(nxt.D[ch.x]);
+    }
+    if (ch.y >= 0) {
+      Lt = xyz(nxt.L[ch.y]);
+      xbar += xyz(nxt.O[ch.y]);
+      dtb = xyz(nxt.D[ch.y]);
+    }
+    v3 M = Lr * s.R + Lt * s.T;
+    L = mul3(s.A, M);
+    Abar = mul3(gW, M);
+    // reflected direction u_r = d + 2 cos_i n (Eq. 3)
+    v3 urb = norm_bwd(s.ur, s.dr, drb);
+    dbar += urb;
+    cibar += 2.f * dot(s.n, urb);
+    nbar += urb * (2.f * s.cos_i);
+    if (!tir) {
+      // Fresnel weights (Eq. 7-8): dL/dR with T = 1 - R
+      float Rbar = dot(mul3(gW, s.A), Lr - Lt);
+      // refracted direction u_t = d / eta_r + (cos_i / eta_r - cos_t) n (Eq. 4-6)
+      v3 utb = norm_bwd(s.ut, s.dt, dtb);
+      float nu = dot(s.n, utb);
+      float ier = 1.f / s.eta_r;
+      dbar += utb * ier;
+      etarbar += -dot(d, utb) * ier * ier - s.cos_i * ier * ier * nu;
+      cibar += nu * ier;
+      ctbar += -nu;
+      nbar += utb * (s.cos_i * ier - s.cos_t);
+      float a = s.eta_i * s.cos_i, b = s.eta_t * s.cos_t;
+      float c = s.eta_i * s.cos_t, e = s.eta_t * s.cos_i;
+      float rsb = Rbar * s.rs, rpb = Rbar * s.rp;
+      float ab2 = (a + b) * (a + b), ce2 = (c + e) * (c + e);
+      float abar = rsb * 2.f * b / ab2, bbar = -rsb * 2.f * a / ab2;
+      float cbar = rpb * 2.f * e / ce2, ebar = -rpb * 2.f * c / ce2;
+      cibar += abar * s.eta_i + ebar * s.eta_t;
+      ctbar += bbar * s.eta_t + cbar * s.eta_i;
+      etaibar += abar * s.cos_i + cbar * s.cos_t;
+      etatbar += bbar * s.cos_t + ebar * s.cos_i;
+      // cos_t = sqrt(1 - sin^2 t), sin^2 t = (1 - cos_i^2) / eta_r^2
+      if (s.cos_t > 0.f) {
+        float s2b = -ctbar / (2.f * s.cos_t);
+        cibar += s2b * (-2.f * s.cos_i * ier * ier);
+        etarbar += s2b * (-2.f * (1.f - s.cos_i * s.cos_i) * ier * ier * ier);
+      }
+    }
+  }
+  // IoR: entering eta_i = 1, eta_t = eta_r = eta; leaving eta_i = eta, eta_t = 1, eta_r = 1/eta
+  float etabar = entering ? (etatbar + etarbar) : (etaibar - etarbar / (s.eta * s.eta));
+  acc.x += etabar;
+  // absorption A = exp(-sigma t) on interior segments (Eq. 11)
+  float tbar = 0.f;
+  if (!entering) {
+    float sg0 = sc.sigma[0], sg1 = sc.sigma[1], sg2 = sc.sigma[2];
+    acc.y += -Abar.x * t * s.A.x;
+    acc.z += -Abar.y * t * s.A.y;
+    acc.w += -Abar.z * t * s.A.z;
+    tbar += -(Abar.x * sg0 * s.A.x + Abar.y * sg1 * s.A.y + Abar.z * sg2 * s.A.z);
+  }
+  // cos_i = -d . n
+  dbar += s.n * (-cibar);
+  nbar += d * (-cibar);
+  // children start at x = o + t d
+  v3 obar = xbar;
+  dbar += xbar * t;
+  tbar += dot(d, xbar);
+  // shading normal n = +-normalize(m), m = sum b_k N_k (Eq. 12)
+  const float sgn = entering ? 1.f : -1.f;
+  v3 p0b = mk3(0.f, 0.f, 0.f), p1b = p0b, p2b = p0b;
+  float b1bar = 0.f, b2bar = 0.f;
+  v3 e1 = geo.p1 - geo.p0, e2 = geo.p2 - geo.p0;
+  if (!degen) {
+    v3 nh = normalize3(s.m);
+    v3 mbar = norm_bwd(s.m, nh, nbar * sgn);
+    float b0 = 1.f - b1 - b2;
+    out.n0 = mbar * b0;
+    out.n1 = mbar * b1;
+    out.n2 = mbar * b2;
+    out.has_n = true;
+    b1bar += dot(geo.n1 - geo.n0, mbar);
+    b2bar += dot(geo.n2 - geo.n0, mbar);
+  } else {
+    v3 ng = cross(e1, e2);
+    v3 nh = normalize3(ng);
+    v3 ngbar = norm_bwd(ng, nh, nbar * sgn);
+    v3 e1b = cross(e2, ngbar), e2b = cross(ngbar, e1);
+    p1b += e1b;
+    p2b += e2b;
+    p0b += -(e1b + e2b);
+  }
+  // differentiable intersection (t, b1, b2 as functions of o, d, p0, p1, p2)
+  {
+    v3 sv = o - geo.p0;
+    v3 pv = cross(d, e2);
+    float det = dot(e1, pv);
+    float inv = 1.f / det;
+    v3 qv = cross(sv, e1);
+    float invbar = tbar * dot(e2, qv) + b1bar * dot(sv, pv) + b2bar * dot(d, qv);
+    v3 e2b = qv * (tbar * inv);
+    v3 qb = e2 * (tbar * inv) + d * (b2bar * inv);
+    dbar += qv * (b2bar * inv);
+    v3 svb = pv * (b1bar * inv);
+    v3 pb = sv * (b1bar * inv);
+    float detbar = -invbar * inv * inv;
+    v3 e1b = pv * detbar;
+    pb += e1 * detbar;
+    svb += cross(e1, qb);
+    e1b += cross(qb, sv);
+    dbar += cross(e2, pb);
+    e2b += cross(pb, d);
+    obar += svb;
+    p0b += -(svb + e1b + e2b);
+    p1b += e1b;
+    p2b += e2b;
+  }
+  out.v[0] = geo.i0;
+  out.v[1] = geo.i1;
+  out.v[2] = geo.i2;
+  out.p0 = p0b;
+  out.p1 = p1b;
+  out.p2 = p2b;
+  cur.L[i] = make_float4(L.x, L.y, L.z, 0.f);
+  cur.O[i] = make_float4(obar.x, obar.y, obar.z, 0.f);
+  cur.D[i] = make_float4(dbar.x, dbar.y, dbar.z, 0.f);
+}
+
+// Per-block aggregation of the vertex scatter: contributions to the same vertex
+// from the block's nodes are summed in an LDS hash table (vertex -> dV, dN)
+// and written with one set of global atomics per distinct vertex when the
+// table is flushed.  Consecutive nodes of a generation come from neighbouring
+// pixels, so they share many vertices.
+constexpr int ATBL = 1024;          // table slots (power of two)
+constexpr int ATBL_FLUSH = 384;     // flush once more slots than this are taken
+constexpr int ATBL_PROBES = 32;     // linear-probe limit before going straight to memory
+
+__global__ void __launch_bounds__(AB, 4) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
                                                 const float* grad_rgb, Adj nxt, Adj cur, float* dV,
                                                 float* dN, float4* red) {
-  const uint32_t n = ctr->count[g];
-  float acc_eta = 0.f, acc_s0 = 0.f, acc_s1 = 0.f, acc_s2 = 0.f;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i], h4 = q.hit[i];
-    uint32_t code = q.code[i];
-    v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
-    int pix = __float_as_int(d4.w);
-    v3 gp = load3(grad_rgb + 3 * pix);
-    v3 gW = mul3(gp, W);
-    if (!(code & C_HIT)) {
-      if (sc.env.kind != DT_ENV_EQUIRECT) continue;  // written by the MLP kernel
-      v3 dd;
-      v3 E = env_equirect_grad(sc.env, d, gW, &dd);
-      cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
-      cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      cur.D[i] = make_float4(dd.x, dd.y, dd.z, 0.f);
-      continue;
-    }
-    bool trunc = (code & C_TRUNC) != 0u;
-    if (trunc && !sc.terminal_env) {
-      cur.L[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      cur.D[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      continue;
-    }
-    float t = h4.x, b1 = h4.z, b2 = h4.w;
-    int tri = __float_as_int(h4.y);
-    HitGeo geo = load_geo(sc, tri);
-    Shade s = shade(sc, geo, o, d, t, b1, b2, code);
-    const bool entering = (code & C_ENTER) != 0u, tir = (code & C_TIR) != 0u;
-    const bool degen = (code & C_DEGEN) != 0u;
-    v3 L, Abar, dbar = mk3(0.f, 0.f, 0.f), xbar = mk3(0.f, 0.f, 0.f), nbar = mk3(0.f, 0.f, 0.f);
-    float cibar = 0.f, ctbar = 0.f, etarbar = 0.f, etaibar = 0.f, etatbar = 0.f;
-    if (trunc) {
-      // terminal mode ENV: L = A * E(d)
-      v3 dd;
-      v3 E = env_equirect_grad(sc.env, d, mul3(gW, s.A), &dd);
-      L = mul3(s.A, E);
-      Abar = mul3(gW, E);
-      dbar = dd;
-    } else {
-      int2 ch = q.child[i];
-      v3 Lr = mk3(0.f, 0.f, 0.f), Lt = mk3(0.f, 0.f, 0.f), drb = Lr, dtb = Lr;
-      if (ch.x >= 0) {
-        Lr = xyz(nxt.L[ch.x]);
-        xbar += xyz(nxt.O[ch.x]);
-        drb = xyz(nxt.D[ch.x]);
-      }
-      if (ch.y >= 0) {
-        Lt = xyz(nxt.L[ch.y]);
-        xbar += xyz(nxt.O[ch.y]);
-        dtb = xyz(nxt.D[ch.y]);
-      }
-      v3 M = Lr * s.R + Lt * s.T;
-      L = mul3(s.A, M);
-      Abar = mul3(gW, M);
-      // reflected direction u_r = d + 2 cos_i n (Eq. 3)
-      v3 urb = norm_bwd(s.ur, s.dr, drb);
-      dbar += urb;
-      cibar += 2.f * dot(s.n, urb);
-      nbar += urb * (2.f * s.cos_i);
-      if (!tir) {
-        // Fresnel weights (Eq. 7-8): dL/dR with T = 1 - R
-        float Rbar = dot(mul3(gW, s.A), Lr - Lt);
-        // refracted direction u_t = d / eta_r + (cos_i / eta_r - cos_t) n (Eq. 4-6)
-        v3 utb = norm_bwd(s.ut, s.dt, dtb);
-        float nu = dot(s.n, utb);
-        float ier = 1.f / s.eta_r;
-        dbar += utb * ier;
-        etarbar += -dot(d, utb) * ier * ier - s.cos_i * ier * ier * nu;
-        cibar += nu * ier;
-        ctbar += -nu;
-        nbar += utb * (s.cos_i * ier - s.cos_t);
-        float a = s.eta_i * s.cos_i, b = s.eta_t * s.cos_t;
-        float c = s.eta_i * s.cos_t, e = s.eta_t * s.cos_i;
-        float rsb = Rbar * s.rs, rpb = Rbar * s.rp;
-        float ab2 = (a + b) * (a + b), ce2 = (c + e) * (c + e);
-        float abar = rsb * 2.f * b / ab2, bbar = -rsb * 2.f * a / ab2;
-        float cbar = rpb * 2.f * e / ce2, ebar = -rpb * 2.f * c / ce2;
-        cibar += abar * s.eta_i + ebar * s.eta_t;
-        ctbar += bbar * s.eta_t + cbar * s.eta_i;
-        etaibar += abar * s.cos_i + cbar * s.cos_t;
-        etatbar += bbar * s.cos_t + ebar * s.cos_i;
-        // cos_t = sqrt(1 - sin^2 t), sin^2 t = (1 - cos_i^2) / eta_r^2
-        if (s.cos_t > 0.f) {
-          float s2b = -ctbar / (2.f * s.cos_t);
-          cibar += s2b * (-2.f * s.cos_i * ier * ier);
-          etarbar += s2b * (-2.f * (1.f - s.cos_i * s.cos_i) * ier * ier * ier);
-        }
-      }
-    }
-    // IoR: entering eta_i = 1, eta_t = eta_r = eta; leaving eta_i = eta, eta_t = 1, eta_r = 1/eta
-    float etabar = entering ? (etatbar + etarbar) : (etaibar - etarbar / (s.eta * s.eta));
-    acc_eta += etabar;
-    // absorption A = exp(-sigma t) on interior segments (Eq. 11)
-    float tbar = 0.f;
-    if (!entering) {
-      float sg0 = sc.sigma[0], sg1 = sc.sigma[1], sg2 = sc.sigma[2];
-      acc_s0 += -Abar.x * t * s.A.x;
-      acc_s1 += -Abar.y * t * s.A.y;
-      acc_s2 += -Abar.z * t * s.A.z;
-      tbar += -(Abar.x * sg0 * s.A.x + Abar.y * sg1 * s.A.y + Abar.z * sg2 * s.A.z);
-    }
-    // cos_i = -d . n
-    dbar += s.n * (-cibar);
-    nbar += d * (-cibar);
-    // children start at x = o + t d
-    v3 obar = xbar;
-    dbar += xbar * t;
-    tbar += dot(d, xbar);
-    // shading normal n = +-normalize(m), m = sum b_k N_k (Eq. 12)
-    const float sgn = entering ? 1.f : -1.f;
-    v3 p0b = mk3(0.f, 0.f, 0.f), p1b = p0b, p2b = p0b;
-    float b1bar = 0.f, b2bar = 0.f;
-    v3 e1 = geo.p1 - geo.p0, e2 = geo.p2 - geo.p0;
-    if (!degen) {
-      v3 nh = normalize3(s.m);
-      v3 mbar = norm_bwd(s.m, nh, nbar * sgn);
-      float b0 = 1.f - b1 - b2;
-      if (dN) {
-        atomic_add3(dN, geo.i0, mbar * b0);
-        atomic_add3(dN, geo.i1, mbar * b1);
-        atomic_add3(dN, geo.i2, mbar * b2);
-      }
-      b1bar += dot(geo.n1 - geo.n0, mbar);
-      b2bar += dot(geo.n2 - geo.n0, mbar);
-    } else {
-      v3 ng = cross(e1, e2);
-      v3 nh = normalize3(ng);
-      v3 ngbar = norm_bwd(ng, nh, nbar * sgn);
-      v3 e1b = cross(e2, ngbar), e2b = cross(ngbar, e1);
-      p1b += e1b;
-      p2b += e2b;
-      p0b += -(e1b + e2b);
-    }
-    // differentiable intersection (t, b1, b2 as functions of o, d, p0, p1, p2)
-    {
-      v3 sv = o - geo.p0;
-      v3 pv = cross(d, e2);
-      float det = dot(e1, pv);
-      float inv = 1.f / det;
-      v3 qv = cross(sv, e1);
-      float invbar = tbar * dot(e2, qv) + b1bar * dot(sv, pv) + b2bar * dot(d, qv);
-      v3 e2b = qv * (tbar * inv);
-      v3 qb = e2 * (tbar * inv) + d * (b2bar * inv);
-      dbar += qv * (b2bar * inv);
-      v3 svb = pv * (b1bar * inv);
-      v3 pb = sv * (b1bar * inv);
-      float detbar = -invbar * inv * inv;
-      v3 e1b = pv * detbar;
-      pb += e1 * detbar;
-      svb += cross(e1, qb);
-      e1b += cross(qb, sv);
-      dbar += cross(e2, pb);
-      e2b += cross(pb, d);
-      obar += svb;
-      p0b += -(svb + e1b + e2b);
-      p1b += e1b;
-      p2b += e2b;
-    }
-    atomic_add3(dV, geo.i0, p0b);
-    atomic_add3(dV, geo.i1, p1b);
-    atomic_add3(dV, geo.i2, p2b);
-    cur.L[i] = make_float4(L.x, L.y, L.z, 0.f);
-    cur.O[i] = make_float4(obar.x, obar.y, obar.z, 0.f);
-    cur.D[i] = make_float4(dbar.x, dbar.y, dbar.z, 0.f);
+  __shared__ int tkey[ATBL];
+  __shared__ float tval[6][ATBL];
+  __shared__ int tused;
+  for (int k = threadIdx.x; k < ATBL; k += AB) {
+    tkey[k] = -1;
+    for (int c = 0; c < 6; ++c) tval[c][k] = 0.f;
   }
+  if (threadIdx.x == 0) tused = 0;
+  __syncthreads();
+  auto add_vertex = [&](int v, v3 a, v3 b, bool with_n) {
+    uint32_t h = ((uint32_t)v * 2654435761u) >> (32 - 10);
+    for (int probe = 0; probe < ATBL_PROBES; ++probe) {
+      int k = atomicCAS(&tkey[h], -1, v);
+      if (k == -1) atomicAdd(&tused, 1);
+      if (k == -1 || k == v) {
+        atomicAdd(&tval[0][h], a.x);
+        atomicAdd(&tval[1][h], a.y);
+        atomicAdd(&tval[2][h], a.z);
+        if (with_n) {
+          atomicAdd(&tval[3][h], b.x);
+          atomicAdd(&tval[4][h], b.y);
+          atomicAdd(&tval[5][h], b.z);
+        }
+        return;
+      }
+      h = (h + 1) & (ATBL - 1);
+    }
+    atomic_add3(dV, v, a);
+    if (with_n && dN) atomic_add3(dN, v, b);
+  };
+  auto flush = [&]() {
+    for (int k = threadIdx.x; k < ATBL; k += AB) {
+      int v = tkey[k];
+      if (v >= 0) {
+        atomic_add3(dV, v, mk3(tval[0][k], tval[1][k], tval[2][k]));
+        v3 nb = mk3(tval[3][k], tval[4][k], tval[5][k]);
+        if (dN && (nb.x != 0.f || nb.y != 0.f || nb.z != 0.f)) atomic_add3(dN, v, nb);
+        tkey[k] = -1;
+        for (int c = 0; c < 6; ++c) tval[c][k] = 0.f;
+      }
+    }
+  };
+  static_assert(ATBL == 1024, "the hash takes the top 10 bits");
+  const int64_t n = ctr->count[g];
+  // each block takes one contiguous range of the generation, AB nodes a step
+  const int64_t per = ((n + gridDim.x - 1) / gridDim.x + AB - 1) / AB * AB;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int64_t base = lo; base < hi; base += AB) {
+    int64_t i = base + threadIdx.x;
+    VtxAdj va;
+    va.v[0] = -1;
+    va.has_n = false;
+    if (i < hi) adjoint_node(sc, q, i, grad_rgb, nxt, cur, acc, va);
+    if (va.v[0] >= 0) {
+      add_vertex(va.v[0], va.p0, va.n0, va.has_n);
+      add_vertex(va.v[1], va.p1, va.n1, va.has_n);
+      add_vertex(va.v[2], va.p2, va.n2, va.has_n);
+    }
+    __syncthreads();
+    const int used = tused;
+    __syncthreads();  // every thread has read the count before the next step adds to it
+    if (used > ATBL_FLUSH || base + AB >= hi) {
+      flush();
+      if (threadIdx.x == 0) tused = 0;
+      __syncthreads();
+    }
+  }
+  const float acc_eta = acc.x, acc_s0 = acc.y, acc_s1 = acc.z, acc_s2 = acc.w;
   // block reduction of the scalar gradients
   __shared__ float red_s[4][AB];
   red_s[0][threadIdx.x] = acc_eta;
@@ -663,8 +755,11 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
 }
 
 // dIoR, dsigma = ordered sums of the per-(generation, block) partials
-__global__ void k_reduce_scalars(const float4* red, int n, float* d_eta, float* d_sigma) {
-  __shared__ double sh[4][256];
+constexpr int RED_T = 1024;  // threads of the scalar reduction (one block)
+
+__global__ void __launch_bounds__(RED_T) k_reduce_scalars(const float4* red, int n, float* d_eta,
+                                                          float* d_sigma) {
+  __shared__ double sh[4][RED_T];
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     float4 v = red[i];
@@ -675,7 +770,7 @@ __global__ void k_reduce_scalars(const float4* red, int n, float* d_eta, float* 
   }
   for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = a[k];
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = RED_T / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st)
       for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + st];
     __syncthreads();
@@ -1101,7 +1196,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   float* dN = (float*)(W + P.w_dN);
   float4* sbar = (float4*)(W + P.w_sbar);
   float4* red = (float4*)(W + P.w_red);
-  const int nred = (DT_MAX_DEPTH + 1) * ADJ_MAX_BLOCKS;
+  const int nred = (P.D + 1) * ADJ_MAX_BLOCKS;  // slot g * ADJ_MAX_BLOCKS + block
   hipLaunchKernelGGL(k_load_counters, dim3(1), dim3(64), 0, s, ctr, (const Counters*)(T + P.tape_hdr));
   if (dt_status st = zero_f32(dV, 3 * (int64_t)scene->nv, s)) return st;
   if (dt_status st = zero_f32(dN, 3 * (int64_t)scene->nv, s)) return st;
@@ -1170,7 +1265,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
         if (dt_status st = adjoint(g, seg[g - g0])) return st;
     }
   }
-  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(256), 0, s, red, nred, d_ior, d_sigma);
+  hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_T), 0, s, red, nred, d_ior, d_sigma);
   hipLaunchKernelGGL(k_nbwd_vertex, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, dN, sbar);
   hipLaunchKernelGGL(k_nbwd_face, dim3(dt_blocks(scene->nf, 256)), dim3(256), 0, s, sc.bvh, sc.V, sc.F,
                      sbar, dV);

@@ -8,7 +8,8 @@ import torch
 import oracle
 from paper_2603_00413_amd import binding as B
 from paper_2603_00413_amd import synth
-from tests.gpu_helpers import BAD, DV_ORDER_TOL, HARD, KINK, device, l2_upstream, rgb_rel_err
+from tests.gpu_helpers import (BAD, DV_ORDER_TOL, HARD, KINK, device, l2_upstream,
+                               path_ill_conditioned, rgb_rel_err)
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +37,7 @@ def _setup(wl, sigma, ior):
 
 
 def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=(1.5, (0.4, 0.25, 0.1)),
-           max_excluded=0.05, max_diverged=2e-3):
+           max_excluded=0.05, max_diverged=0.01):
     mesh, scene, rays, oenv, V32, O, D = _setup(wl, sigma, ior)
     cap = int(1.3 * rays.n_rays)
     sig_t = torch.empty(rays.n_pixels, dtype=torch.int64, device=mesh.V.device)
@@ -66,8 +67,14 @@ def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=(1.5, (
            "median err", np.median(err[ok & same]), "max err (same path)", err[ok & same].max(),
            "max err (other path)", err[ok & ~same].max() if (ok & ~same).any() else 0.0)
     assert 1 - ok.mean() < max_excluded
-    assert (~same[ok]).mean() <= max_diverged
     assert err[ok & same].max() <= 1e-4
+    # a path may part only where the oracle's own path is ill-conditioned
+    div = ok & ~same
+    assert div.mean() <= max_diverged
+    if div.any():
+        ill = path_ill_conditioned(orc, O[pix][div], D[pix][div], ref["sig"][div])
+        _print(wl.name, "diverging paths that are ill-conditioned in the oracle", ill.mean())
+        assert ill.all()
     # gradient of an L2 loss on the sampled pixels against an oracle-rendered
     # target, on pixels whose discrete path agrees and whose lookups are off
     # the environment's gradient kinks
@@ -107,10 +114,11 @@ def test_training_step_shape_sdf_union_300k():
 def test_stress_thin_shell_2m():
     wl = synth.thin_shell_scene()
     assert len(wl.F) > 1_500_000
-    # thin walls make near-critical hits frequent, and over 8 bounces a few
-    # FP32 paths part from the FP64 ones at shared edges (reported, bounded
-    # at 2 %; their gradients belong to another path and are not compared)
+    # thin walls make near-critical hits frequent, and over 8 bounces some
+    # FP32 paths part from the FP64 ones at shared edges (each one checked to
+    # be ill-conditioned in the oracle; their gradients belong to another path
+    # and are not compared)
     buf, *_ = _check(wl, 2, 1500, ior=1.5, target=(1.55, (0.2, 0.3, 0.4)), max_excluded=0.10,
-                     max_diverged=0.02)
+                     max_diverged=0.10)
     st = buf.stats.cpu().numpy()
     _print("thin shell: BVH height", st[B.STAT_BVH_DEPTH], "total rays", st[B.STAT_TOTAL])

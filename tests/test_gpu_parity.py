@@ -13,7 +13,7 @@ import oracle
 from paper_2603_00413_amd import binding as B
 from paper_2603_00413_amd import synth
 from tests.gpu_helpers import (BAD, DV_ORDER_TOL, HARD, KINK, Pair, device, icosphere_pair,
-                               l2_upstream, rel_err, torus_pair)
+                               l2_upstream, path_ill_conditioned, rel_err, torus_pair)
 
 pytestmark = pytest.mark.gpu
 
@@ -129,9 +129,12 @@ def test_forward_icosphere(sigma):
     assert 1 - ok.mean() < 0.05
     assert err[ok].max() <= 1e-4
     # the discrete path (triangle per segment, TIR branches) is an integer
-    # result: the same on both sides but where a hit falls within FP32
-    # rounding of a shared edge
-    assert (~same[ok]).mean() <= 1e-3
+    # result: the same on both sides but where the oracle's own path is
+    # ill-conditioned (a hit within rounding of a shared edge)
+    div = ok & ~same
+    assert div.mean() <= 1e-3
+    if div.any():
+        assert path_ill_conditioned(P.orc, P.o[div], P.d[div], ref["sig"][div]).all()
     np.testing.assert_allclose(wt[ok], ref["wtrunc"][ok], rtol=1e-4, atol=1e-6)
 
 
@@ -164,7 +167,10 @@ def test_forward_torus_small():
     _print("segments gpu", stats[B.STAT_TOTAL], "oracle", ref["nseg"].sum())
     assert 1 - ok.mean() < 0.05
     assert bad.any(1).mean() < 1e-3
-    assert (~same[ok]).mean() < 2e-3
+    div = ok & ~same
+    assert div.mean() < 2e-3
+    if div.any():
+        assert path_ill_conditioned(P.orc, P.o[div], P.d[div], ref["sig"][div]).all()
     assert abs(stats[B.STAT_TOTAL] - ref["nseg"].sum()) <= 1e-3 * ref["nseg"].sum()
 
 
@@ -251,7 +257,11 @@ def test_full_size_torus_sampled_pixels():
            "pixels over 1e-4", bad.any(1).sum(), "paths differing", (~same[ok]).sum())
     assert 1 - ok.mean() < 0.05
     assert bad.any(1).mean() < 2e-3
-    assert (~same[ok]).mean() < 2e-3
+    # a path may part only where the oracle's own path is ill-conditioned
+    div = ok & ~same
+    assert div.mean() < 5e-3
+    if div.any():
+        assert path_ill_conditioned(P.orc, P.o[pix][div], P.d[pix][div], ref["sig"][div]).all()
     # gradients where the discrete path (triangles, branches) is the same on
     # both sides and no environment lookup sits on a gradient kink
     tgt = P.orc.with_(eta=1.5, sigma=(0.25, 0.3, 0.35)).trace(P.o[pix], P.d[pix])["rgb"]
