@@ -455,6 +455,28 @@ __global__ void k_even(int32_t n_int, const BvhNode* nodes, int32_t* flag) {
   flag[i] = (dep & 1) == 0;
 }
 
+// Exponent e of the quantization step 2^e of one axis of a node box [lo, hi]:
+// 254 steps must span the box (with the origin rounded down to a multiple of
+// the step, 255 then reach past hi), and every p + q 2^e, q in [0, 255], must be
+// exact in FP32, which holds once 2^(e+22) >= max(|lo|, |hi|).
+__device__ __forceinline__ int quant_exponent(float lo, float hi) {
+  float m = fmaxf(fabsf(lo), fabsf(hi));
+  int e = -126;
+  if (m > 0.f) {
+    int em = ilogbf(m) + 1 - 22;  // 2^(ilogb + 1) > m
+    e = em > e ? em : e;
+  }
+  float ext = hi - lo;
+  if (ext > 0.f) {
+    int ee = ilogbf(ext / 254.0f) + 1;  // 2^ee > ext / 254
+    e = ee > e ? ee : e;
+  }
+  // make sure the span fits (the rounded-down origin costs up to one step);
+  // p + 255 s is exact, so the comparison is too
+  while (e < 127 && floorf(ldexpf(lo, -e)) * ldexpf(1.0f, e) + 255.0f * ldexpf(1.0f, e) < hi) ++e;
+  return e;
+}
+
 // Writes the 4-wide node of every even-depth internal node i at index idx[i]:
 // each leaf child keeps its slot, each internal child hands over its two
 // children (their boxes are stored in that child's node).
@@ -502,14 +524,34 @@ __global__ void k_collapse(int32_t n_int, const BvhNode* nodes, const int32_t* f
     ch[k] = DT_NO_CHILD;
   }
   Bvh4Node q;
-  q.lox = make_float4(lo[0][0], lo[1][0], lo[2][0], lo[3][0]);
-  q.hix = make_float4(hi[0][0], hi[1][0], hi[2][0], hi[3][0]);
-  q.loy = make_float4(lo[0][1], lo[1][1], lo[2][1], lo[3][1]);
-  q.hiy = make_float4(hi[0][1], hi[1][1], hi[2][1], hi[3][1]);
-  q.loz = make_float4(lo[0][2], lo[1][2], lo[2][2], lo[3][2]);
-  q.hiz = make_float4(hi[0][2], hi[1][2], hi[2][2], hi[3][2]);
+  float org[3];
+  uint32_t ebits = 0, qlo[3] = {0u, 0u, 0u}, qhi[3] = {0u, 0u, 0u};
+  for (int a = 0; a < 3; ++a) {
+    float nlo = lo[0][a], nhi = hi[0][a];
+    for (int c = 1; c < cnt; ++c) {
+      nlo = fminf(nlo, lo[c][a]);
+      nhi = fmaxf(nhi, hi[c][a]);
+    }
+    int e = quant_exponent(nlo, nhi);
+    float sc = ldexpf(1.0f, e);
+    float p = floorf(ldexpf(nlo, -e)) * sc;  // a multiple of sc, <= nlo
+    org[a] = p;
+    ebits |= (uint32_t)(uint8_t)(int8_t)e << (8 * a);
+    for (int c = 0; c < cnt; ++c) {
+      int ql = (int)floorf(ldexpf(lo[c][a] - p, -e));
+      ql = ql < 0 ? 0 : (ql > 255 ? 255 : ql);
+      while (ql > 0 && p + (float)ql * sc > lo[c][a]) --ql;
+      int qh = (int)ceilf(ldexpf(hi[c][a] - p, -e));
+      qh = qh < 0 ? 0 : (qh > 255 ? 255 : qh);
+      while (qh < 255 && p + (float)qh * sc < hi[c][a]) ++qh;
+      qlo[a] |= (uint32_t)ql << (8 * c);
+      qhi[a] |= (uint32_t)qh << (8 * c);
+    }
+  }
+  q.org = make_float4(org[0], org[1], org[2], __uint_as_float(ebits | ((uint32_t)cnt << 24)));
+  q.qlo = make_uint4(qlo[0], qlo[1], qlo[2], 0u);
+  q.qhi = make_uint4(qhi[0], qhi[1], qhi[2], 0u);
   q.child = make_uint4(ch[0], ch[1], ch[2], ch[3]);
-  q.meta = make_int4(i, cnt, 0, 0);
   out[j] = q;
 }
 

@@ -189,9 +189,12 @@ __device__ __forceinline__ float box_enter(const RayPre& r, float lx, float ly, 
   float t0z = (lz - r.o.z) * r.inv.z, t1z = (hz - r.o.z) * r.inv.z;
   float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
   float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
-  // widen by a few ulps so that a box is never rejected for a triangle the
-  // triangle test would accept (equal-t ties included)
-  tf *= 1.0000005f;
+  // each slab distance carries three roundings (difference, reciprocal,
+  // product), a relative error of at most gamma_3 = 3u / (1 - 3u), u = 2^-24;
+  // widening the exit distance by 1 + 2 gamma_3 (< 1.0000008) keeps every box
+  // the exact ray enters (so no triangle the triangle test would accept, ties
+  // included, is pruned)
+  tf *= 1.0000008f;
   return tn <= tf ? tn : INFINITY;
 }
 
@@ -251,15 +254,27 @@ __device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int sk
       break;
     }
     const Bvh4Node& n = bv.nodes4[node];
-    const float4 lx = n.lox, hx = n.hix, ly = n.loy, hy = n.hiy, lz = n.loz, hz = n.hiz;
-    const uint4 cc = n.child;
+    const float4 org = n.org;
+    const uint4 ql = n.qlo, qh = n.qhi, cc = n.child;
+    // exact decode of the quantized child boxes: lo = p + qlo 2^e, hi = p + qhi 2^e
+    const uint32_t eb = __float_as_uint(org.w);
+    const float sx = __uint_as_float((uint32_t)((int)(int8_t)(eb & 0xFFu) + 127) << 23);
+    const float sy = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 8) & 0xFFu) + 127) << 23);
+    const float sz = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 16) & 0xFFu) + 127) << 23);
     float tmax = h.tri >= 0 ? h.t : INFINITY;
     float t[4];
     uint32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
-    t[0] = box_enter(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tmax);
-    t[1] = box_enter(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmax);
-    t[2] = box_enter(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmax);
-    t[3] = box_enter(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmax);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int sh = 8 * k;
+      float lox = org.x + (float)((ql.x >> sh) & 0xFFu) * sx;
+      float loy = org.y + (float)((ql.y >> sh) & 0xFFu) * sy;
+      float loz = org.z + (float)((ql.z >> sh) & 0xFFu) * sz;
+      float hix = org.x + (float)((qh.x >> sh) & 0xFFu) * sx;
+      float hiy = org.y + (float)((qh.y >> sh) & 0xFFu) * sy;
+      float hiz = org.z + (float)((qh.z >> sh) & 0xFFu) * sz;
+      t[k] = box_enter(r, lox, loy, loz, hix, hiy, hiz, tmax);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (c[k] == DT_NO_CHILD) {

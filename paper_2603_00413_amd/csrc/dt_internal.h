@@ -74,15 +74,23 @@ struct __align__(16) BvhNode {
 
 // 4-wide node collapsed from the binary tree: a binary internal node at even
 // depth (root = 0) becomes a 4-wide node whose children are its grandchildren
-// (a leaf child stays a leaf), 2 to 4 of them.  Boxes are stored SoA over the
-// four slots; an unused slot has child reference DT_NO_CHILD.  A child
-// reference is a 4-wide node index or (leaf | DT_LEAF_BIT).
+// (a leaf child stays a leaf), 2 to 4 of them.  A child reference is a 4-wide
+// node index, (leaf | DT_LEAF_BIT), or DT_NO_CHILD for an unused slot.
+//
+// The child boxes are stored quantized (64 B per node instead of 128): per
+// axis an origin p and a power of two s = 2^e, and per child and axis 8-bit
+// steps, lo = p + qlo * s, hi = p + qhi * s.  The build chooses p a multiple
+// of s and s large enough that every such value is exactly representable in
+// FP32, rounds qlo down and qhi up, and checks the decoded bounds against the
+// exact child box, so the decoded boxes contain the exact ones and the
+// traversal's decisions stay conservative.
 #define DT_NO_CHILD 0xFFFFFFFFu
 
 struct __align__(16) Bvh4Node {
-  float4 lox, hix, loy, hiy, loz, hiz;
-  uint4 child;
-  int4 meta;  // binary node id, number of children, 0, 0
+  float4 org;   // p.x, p.y, p.z; w: bits e_x | e_y << 8 | e_z << 16 (int8 each) | count << 24
+  uint4 qlo;    // x, y, z: the four children's 8-bit lower steps on that axis (child k in byte k)
+  uint4 qhi;    // x, y, z: upper steps; w unused
+  uint4 child;  // child references
 };
 
 // Upper bound on the number of 4-wide nodes: with E even-depth and O odd-depth
