@@ -199,92 +199,114 @@ __device__ __forceinline__ float box_enter(const RayPre& r, float lx, float ly, 
 }
 
 #define DT_STACK 64       // total stack entries per lane (LDS part + global overflow part)
-#define DT_STACK_LDS 16   // entries kept in LDS by the traversal kernels
+#define DT_STACK_LDS 8    // entries kept in LDS by the traversal kernels (4 KB per wave)
 
-// Closest hit over the 4-wide tree.  The stack holds (node, entry distance)
-// pairs: the first SL entries in LDS (stk points at this lane's column, stride
-// entries apart), deeper ones in this lane's global overflow area gstk (gcap
-// entries; may be NULL).  At a node, leaf children are tested at once; the
-// internal children whose boxes the ray enters are ordered by entry distance,
-// the nearest is visited next and the others are pushed, farthest first.  A
-// popped subtree whose box is entered beyond the closest hit found since it
-// was pushed is skipped without fetching its node.  Sets *overflow if the
-// stack would overflow (the result is then incomplete and flagged).
-template <int SL, bool GLOBAL>
-__device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int skip, float t_eps,
-                                           uint2* stk, int stride, uint2* gstk, int gcap,
-                                           bool* overflow) {
+// Closest-hit traversal of the 4-wide tree as a resumable per-lane state, so
+// that a kernel can advance many rays one node at a time and hand a lane a new
+// ray as soon as its current one finishes.  The stack holds (node, entry
+// distance) pairs: the first SL entries in LDS (stk points at this lane's
+// column, stride entries apart), deeper ones in this lane's global overflow
+// area gstk (gcap entries; may be NULL when GLOBAL is false).  At a node, leaf
+// children are tested at once; the internal children whose boxes the ray
+// enters are ordered by entry distance, the nearest is visited next and the
+// others are pushed, farthest first.  A popped subtree whose box is entered
+// beyond the closest hit found since it was pushed is skipped without fetching
+// its node.  overflow is set if the stack would overflow (the result is then
+// incomplete and flagged).
+struct Trav {
+  RayPre r;
   Hit h;
-  h.tri = -1;
-  h.t = INFINITY;
-  h.b1 = h.b2 = 0.f;
-  RayPre r = ray_pre(o, d);
-  const float4* L = bv.leaves;
+  uint32_t node;
+  int sp;
+  int skip;
+  uint32_t steps;
+  bool overflow;
+  bool done;
+};
+
+__device__ __forceinline__ void trav_init(Trav& s, const BvhView& bv, v3 o, v3 d, int skip,
+                                          float t_eps) {
+  s.h.tri = -1;
+  s.h.t = INFINITY;
+  s.h.b1 = s.h.b2 = 0.f;
+  s.r = ray_pre(o, d);
+  s.node = 0;
+  s.sp = 0;
+  s.skip = skip;
+  s.steps = 0;
+  s.overflow = false;
+  s.done = false;
   if (bv.nf == 1) {
+    const float4* L = bv.leaves;
     int f = __float_as_int(L[0].w);
-    if (f != skip) tri_test(r, xyz(L[0]), xyz(L[1]), xyz(L[2]), f, t_eps, h);
-    return h;
+    if (f != skip) tri_test(s.r, xyz(L[0]), xyz(L[1]), xyz(L[2]), f, t_eps, s.h);
+    s.done = true;
   }
+}
+
+// One step: visit the current node and choose the next one (or finish).
+template <int SL, bool GLOBAL>
+__device__ __forceinline__ void trav_step(Trav& s, const BvhView& bv, float t_eps, uint2* stk,
+                                          int stride, uint2* gstk, int gcap) {
   const uint32_t cap4 = (uint32_t)bvh4_cap(bv.nf);
   const uint32_t lmax = (uint32_t)(bv.nf - 1);
-  int sp = 0;
-  uint32_t node = 0;
+  const float4* L = bv.leaves;
+  // a depth-first walk visits each 4-wide node at most once
+  if (s.node >= cap4 || ++s.steps > cap4 + 64) {
+    s.overflow = true;
+    s.done = true;
+    return;
+  }
   auto push = [&](uint32_t c, float t) {
     uint2 e = make_uint2(c, __float_as_uint(t));
-    if (sp < SL) {
-      stk[sp * stride] = e;
-      ++sp;
-    } else if (GLOBAL && sp - SL < gcap) {
-      if constexpr (GLOBAL) gstk[sp - SL] = e;
-      ++sp;
+    if (s.sp < SL) {
+      stk[s.sp * stride] = e;
+      ++s.sp;
+    } else if (GLOBAL && s.sp - SL < gcap) {
+      if constexpr (GLOBAL) gstk[s.sp - SL] = e;
+      ++s.sp;
     } else {
-      *overflow = true;
+      s.overflow = true;
     }
   };
   auto leaf = [&](uint32_t c) {
     uint32_t j = min(c & ~DT_LEAF_BIT, lmax);
     float4 p0 = L[3 * j];
     int f = __float_as_int(p0.w);
-    if (f != skip) tri_test(r, xyz(p0), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), f, t_eps, h);
+    if (f != s.skip) tri_test(s.r, xyz(p0), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), f, t_eps, s.h);
   };
-  // each 4-wide node is visited at most once by a depth-first walk
-  for (uint32_t guard = 0; guard < cap4 + 64; ++guard) {
-    if (node >= cap4) {
-      *overflow = true;
-      break;
-    }
-    const Bvh4Node& n = bv.nodes4[node];
-    const float4 org = n.org;
-    const uint4 ql = n.qlo, qh = n.qhi, cc = n.child;
-    // exact decode of the quantized child boxes: lo = p + qlo 2^e, hi = p + qhi 2^e
-    const uint32_t eb = __float_as_uint(org.w);
-    const float sx = __uint_as_float((uint32_t)((int)(int8_t)(eb & 0xFFu) + 127) << 23);
-    const float sy = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 8) & 0xFFu) + 127) << 23);
-    const float sz = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 16) & 0xFFu) + 127) << 23);
-    float tmax = h.tri >= 0 ? h.t : INFINITY;
-    float t[4];
-    uint32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
+  const Bvh4Node& n = bv.nodes4[s.node];
+  const float4 org = n.org;
+  const uint4 ql = n.qlo, qh = n.qhi, cc = n.child;
+  // exact decode of the quantized child boxes: lo = p + qlo 2^e, hi = p + qhi 2^e
+  const uint32_t eb = __float_as_uint(org.w);
+  const float sx = __uint_as_float((uint32_t)((int)(int8_t)(eb & 0xFFu) + 127) << 23);
+  const float sy = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 8) & 0xFFu) + 127) << 23);
+  const float sz = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 16) & 0xFFu) + 127) << 23);
+  float tmax = s.h.tri >= 0 ? s.h.t : INFINITY;
+  float t[4];
+  uint32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int sh = 8 * k;
-      float lox = org.x + (float)((ql.x >> sh) & 0xFFu) * sx;
-      float loy = org.y + (float)((ql.y >> sh) & 0xFFu) * sy;
-      float loz = org.z + (float)((ql.z >> sh) & 0xFFu) * sz;
-      float hix = org.x + (float)((qh.x >> sh) & 0xFFu) * sx;
-      float hiy = org.y + (float)((qh.y >> sh) & 0xFFu) * sy;
-      float hiz = org.z + (float)((qh.z >> sh) & 0xFFu) * sz;
-      t[k] = box_enter(r, lox, loy, loz, hix, hiy, hiz, tmax);
-    }
+  for (int k = 0; k < 4; ++k) {
+    const int sh = 8 * k;
+    float lox = org.x + (float)((ql.x >> sh) & 0xFFu) * sx;
+    float loy = org.y + (float)((ql.y >> sh) & 0xFFu) * sy;
+    float loz = org.z + (float)((ql.z >> sh) & 0xFFu) * sz;
+    float hix = org.x + (float)((qh.x >> sh) & 0xFFu) * sx;
+    float hiy = org.y + (float)((qh.y >> sh) & 0xFFu) * sy;
+    float hiz = org.z + (float)((qh.z >> sh) & 0xFFu) * sz;
+    t[k] = box_enter(s.r, lox, loy, loz, hix, hiy, hiz, tmax);
+  }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (c[k] == DT_NO_CHILD) {
-        t[k] = INFINITY;
-      } else if (t[k] != INFINITY && (c[k] & DT_LEAF_BIT)) {
-        leaf(c[k]);
-        t[k] = INFINITY;
-      }
+  for (int k = 0; k < 4; ++k) {
+    if (c[k] == DT_NO_CHILD) {
+      t[k] = INFINITY;
+    } else if (t[k] != INFINITY && (c[k] & DT_LEAF_BIT)) {
+      leaf(c[k]);
+      t[k] = INFINITY;
     }
-    // order the entered internal children by entry distance (sorting network)
+  }
+  // order the entered internal children by entry distance (sorting network)
 #define DT_CSWAP(i, j)                 \
   if (t[j] < t[i]) {                   \
     float tt = t[i];                   \
@@ -294,38 +316,46 @@ __device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int sk
     c[i] = c[j];                       \
     c[j] = cx;                         \
   }
-    DT_CSWAP(0, 1)
-    DT_CSWAP(2, 3)
-    DT_CSWAP(0, 2)
-    DT_CSWAP(1, 3)
-    DT_CSWAP(1, 2)
+  DT_CSWAP(0, 1)
+  DT_CSWAP(2, 3)
+  DT_CSWAP(0, 2)
+  DT_CSWAP(1, 3)
+  DT_CSWAP(1, 2)
 #undef DT_CSWAP
-    if (t[0] != INFINITY) {
-      if (t[3] != INFINITY) push(c[3], t[3]);
-      if (t[2] != INFINITY) push(c[2], t[2]);
-      if (t[1] != INFINITY) push(c[1], t[1]);
-      node = c[0];
-      continue;
-    }
-    // pop the nearest pending subtree that can still hold a closer hit
-    // (the margin keeps equal-distance ties, decided by triangle id, in play)
-    bool found = false;
-    while (sp > 0) {
-      --sp;
-      uint2 e = make_uint2(0u, 0u);
-      if (sp < SL) {
-        e = stk[sp * stride];
-      } else {
-        if constexpr (GLOBAL) e = gstk[sp - SL];
-      }
-      if (h.tri >= 0 && __uint_as_float(e.y) > h.t * 1.000001f) continue;
-      node = e.x;
-      found = true;
-      break;
-    }
-    if (!found) break;
+  if (t[0] != INFINITY) {
+    if (t[3] != INFINITY) push(c[3], t[3]);
+    if (t[2] != INFINITY) push(c[2], t[2]);
+    if (t[1] != INFINITY) push(c[1], t[1]);
+    s.node = c[0];
+    return;
   }
-  return h;
+  // pop the nearest pending subtree that can still hold a closer hit
+  // (the margin keeps equal-distance ties, decided by triangle id, in play)
+  while (s.sp > 0) {
+    --s.sp;
+    uint2 e = make_uint2(0u, 0u);
+    if (s.sp < SL) {
+      e = stk[s.sp * stride];
+    } else {
+      if constexpr (GLOBAL) e = gstk[s.sp - SL];
+    }
+    if (s.h.tri >= 0 && __uint_as_float(e.y) > s.h.t * 1.000001f) continue;
+    s.node = e.x;
+    return;
+  }
+  s.done = true;
+}
+
+// Closest hit of one ray (the whole traversal in one call).
+template <int SL, bool GLOBAL>
+__device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int skip, float t_eps,
+                                           uint2* stk, int stride, uint2* gstk, int gcap,
+                                           bool* overflow) {
+  Trav s;
+  trav_init(s, bv, o, d, skip, t_eps);
+  while (!s.done) trav_step<SL, GLOBAL>(s, bv, t_eps, stk, stride, gstk, gcap);
+  if (s.overflow) *overflow = true;
+  return s.h;
 }
 
 // brute force over every triangle with the same predicate

@@ -43,7 +43,7 @@ struct ServeState {
   long long dropped;
 };
 
-constexpr int SERVE_TRACE_BLOCKS = 256 * 20;
+constexpr int SERVE_TRACE_BLOCKS = 256 * 4 * 7;
 
 struct ServeLayout {
   size_t state, tables, part0, part1, q[2][3], hit, code, ovf, total;
@@ -131,7 +131,7 @@ __global__ void k_serve_admit_count(ServeState* st, int64_t added, int64_t cap) 
   }
 }
 
-__global__ void __launch_bounds__(TBS) k_serve_trace(const ServeTables* T, Gen q, ServeState* st,
+__global__ void __launch_bounds__(TBS, 7) k_serve_trace(const ServeTables* T, Gen q, ServeState* st,
                                                      unsigned long long* part, float* pixels,
                                                      uint2* ovf) {
   __shared__ uint2 stk[DT_STACK_LDS * TBS];

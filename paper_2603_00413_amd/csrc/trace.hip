@@ -26,7 +26,7 @@ constexpr int CHUNK = DT_CHUNK;       // rays per compaction chunk
 constexpr int EB = 256;               // threads per block of the emit kernel
 constexpr int AB = 256;               // threads per block of the adjoint kernel
 constexpr int ADJ_MAX_BLOCKS = 4096;  // grid cap of the adjoint kernel
-constexpr int TRACE_MAX_BLOCKS = 256 * 20;  // grid cap of the traversal kernel (resident waves)
+constexpr int TRACE_MAX_BLOCKS = 256 * 4 * 7;  // grid cap of the traversal kernel: 7 resident waves per SIMD
 // ------------------------------------------------------------------ plan
 struct Plan {
   int D, k;
@@ -252,7 +252,7 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 }
 
 // ------------------------------------------------------------------ k_trace (a4 + a5 decisions + a6)
-__global__ void __launch_bounds__(TB) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
+__global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
                                               int32_t* flags, unsigned long long* sig,
                                               int accumulate, uint32_t* miss_list, uint2* ovf) {
