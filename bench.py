@@ -45,8 +45,8 @@ MEASURED_TRAFFIC = {
     "k_trace": {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h"],
-        "sha256": "9d9516d15db72d0af800e7012a5bb28bc73efab85ef7e5bb596f851402214f34",
-        "bytes": (440887.4 * 2.0 + 76724.6) * 1024,
+        "sha256": "a91c85b7f3420ff5ebd3a4ed6e8f9844e5aefb255f2f37bb5d47518b51e8f83d",
+        "bytes": (360793.2 * 2.0 + 77157.2) * 1024,
     },
 }
 
