@@ -170,10 +170,13 @@ __device__ __forceinline__ bool tri_test(const RayPre& r, v3 a, v3 b, v3 c, int 
   float det = U + V + W;
   if (det == 0.f) return false;
   float T = U * (r.Sz * Az) + V * (r.Sz * Bz) + W * (r.Sz * Cz);
-  float t = T / det;
-  if (!(t > t_eps)) return false;
+  // one hardware reciprocal (1 ulp) instead of two IEEE divisions: t and the
+  // barycentrics carry 2 ulps, the same function on every path (so BVH and
+  // brute-force results stay identical), far inside the parity tolerances
+  float inv = __builtin_amdgcn_rcpf(det);
+  float t = T * inv;
+  if (!(t > t_eps) || !(t < INFINITY)) return false;
   if (h.tri >= 0 && (t > h.t || (t == h.t && tri > h.tri))) return false;
-  float inv = 1.0f / det;
   h.t = t;
   h.b1 = V * inv;
   h.b2 = W * inv;
