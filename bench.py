@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=1,
                     help="oracle baseline traces every n-th pixel in x and y")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the MLP-lit training-step leg")
     ap.add_argument("--copy-only", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
@@ -223,11 +224,14 @@ def main():
     log(f"step {ms_step:.2f} ms; forward-only {fwd_ms:.2f} ms; k_trace per gen ms {np.round(tr_ms, 3).tolist()}; "
         f"k_adjoint per gen ms {np.round(ad_ms, 3).tolist()}")
 
+    del buf
+    torch.cuda.empty_cache()
     serving = None
     if not args.no_serve:
-        del buf
-        torch.cuda.empty_cache()
         serving = serving_bench(args, dev)
+    training = None
+    if not args.no_mlp:
+        training = training_step_bench(args, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -269,12 +273,109 @@ def main():
         "step_latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                             "p99": round(float(np.percentile(lat_ms, 99)), 3)},
         "serving": serving,
+        "training_step_mlp": training,
         "plain_forward": {"ms": round(fwd_ms, 3), "Mrays/s": round(segs / fwd_ms / 1e3, 3)},
         "kernel_ms_per_generation": {"k_trace": np.round(tr_ms, 4).tolist(),
                                      "k_adjoint": np.round(ad_ms, 4).tolist()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def mlp_flops(width, layers, in_dim=39):
+    """Multiply-adds x 2 of one evaluation of the environment network:
+    encoding (in_dim) -> layers x width (ReLU) -> 3."""
+    return 2 * (in_dim * width + (layers - 1) * width * width + width * 3)
+
+
+def training_step_bench(args, dev):
+    """The training-step shape: SDF union (~300k triangles), 8 views x 800^2,
+    depth 6, lit by the 3 x 64 environment MLP on bf16 MFMA; forward with tape,
+    L2 loss gradient, adjoint.  Reports Mrays/s and the MLP kernels' achieved
+    rate against the bf16 dense MFMA peak."""
+    import torch
+
+    from paper_2603_00413_amd import binding as B
+    from paper_2603_00413_amd import synth
+    wl = synth.sdf_union_scene()
+    Ws, Bs, n_freq = wl.mlp
+    layers, width = len(Ws) - 1, Ws[0].shape[0]
+    V = torch.from_numpy(wl.V.astype(np.float32)).to(dev)
+    F = torch.from_numpy(wl.F).to(dev)
+    mesh = B.Mesh(V, F)
+    env = B.Env.mlp(Ws, Bs, n_freq, dev)
+    scene = B.Scene(mesh, torch.tensor([wl.ior], dtype=torch.float32, device=dev),
+                    torch.tensor(wl.sigma, dtype=torch.float32, device=dev), env)
+    rays = B.Rays(cameras=wl.cameras)
+    cap = int(1.3 * rays.n_rays)
+    while True:
+        p = B.Params(max_depth=wl.max_depth, queue_capacity=cap)
+        buf = B.Buffers(p, rays, mesh, tape=False)
+        B.dt_trace_forward(scene, rays, p, buf, want_aux=False)
+        st = buf.stats.cpu().numpy()
+        if st[B.STAT_DROPPED] == 0:
+            break
+        cap *= 2
+    del buf
+    G = wl.max_depth + 1
+    counts = st[:G].astype(np.int64)
+    hits = st[B.STAT_HITS:B.STAT_HITS + G].astype(np.int64)
+    segs = int(counts.sum())
+    cap = int(max(counts[1:].max() * 1.05, 2048))
+    timer = B.KernelTimer(wl.max_depth)
+    params = B.Params(max_depth=wl.max_depth, queue_capacity=cap, timing=timer)
+    buf = B.Buffers(params, rays, mesh, tape=True)
+    tscene = B.Scene(mesh, torch.tensor([1.5], device=dev), torch.tensor([0.4, 0.25, 0.1], device=dev), env)
+    target, _, _ = B.dt_trace_forward(tscene, rays, params, buf, want_aux=False)
+    target = target.clone()
+
+    def step():
+        mesh.build()
+        rgb, _, _ = B.dt_trace_forward(scene, rays, params, buf, want_aux=False)
+        grad = (rgb - target) * (2.0 / rgb.numel())
+        return B.dt_trace_backward(scene, rays, params, buf, grad)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 2)
+    fwd_ms, bwd_ms = np.zeros(G), np.zeros(G)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        torch.cuda.synchronize()
+        fwd_ms += np.array(timer.mlp_ms(G)) / steps
+        bwd_ms += np.array(timer.mlp_adjoint_ms(G)) / steps
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    st = buf.stats.cpu().numpy()
+    assert st[B.STAT_DROPPED] == 0 and int(st[B.STAT_TOTAL]) == segs
+    misses = counts - hits
+    fl = mlp_flops(width, layers)
+    # the forward kernel runs the network once per miss; the backward kernel
+    # replays it and runs the transposed chain (about twice the multiply-adds)
+    fwd_tf = misses.sum() * fl / (fwd_ms.sum() * 1e-3) / 1e12
+    bwd_tf = misses.sum() * 2 * fl / (bwd_ms.sum() * 1e-3) / 1e12
+    log(f"training step (MLP): {ms:.2f} ms, {segs / ms / 1e3:.1f} Mrays/s; MLP fwd kernels "
+        f"{fwd_ms.sum():.3f} ms ({fwd_tf:.1f} TFLOP/s), bwd {bwd_ms.sum():.3f} ms ({bwd_tf:.1f} TFLOP/s)")
+    return {
+        "workload": "SDF union %d tris, %d views x %d^2, depth %d, env MLP %d x %d bf16 MFMA, fwd+bwd"
+                    % (len(wl.F), len(wl.cameras), wl.cameras[0].width, wl.max_depth, layers, width),
+        "ms_per_step": round(ms, 3),
+        "Mrays/s": round(segs / ms / 1e3, 3),
+        "segments_per_step": segs,
+        "env_lookups_per_step": int(misses.sum()),
+        "mlp_mfma": {
+            "kernel": "k_mlp_trace_fwd",
+            "achieved": round(float(fwd_tf), 2),
+            "peak": 2500.0,
+            "unit": "TFLOP/s",
+            "frac": round(float(fwd_tf) / 2500.0, 5),
+            "flops_per_lookup": fl,
+            "ms_per_step": round(float(fwd_ms.sum()), 4),
+            "backward_kernel_TFLOP/s": round(float(bwd_tf), 2),
+            "backward_ms_per_step": round(float(bwd_ms.sum()), 4),
+        },
+    }
 
 
 def serving_bench(args, dev):

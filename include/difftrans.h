@@ -142,12 +142,16 @@ typedef struct {
 
 /* Optional kernel timing (HOST struct of caller-created hipEvent_t handles):
  * when given, the forward records trace_events[2g] / [2g+1] around the
- * traversal kernel of generation g, and the backward records
- * adjoint_events[2g] / [2g+1] around the adjoint kernel of generation g.
+ * traversal kernel of generation g and mlp_events[2g] / [2g+1] around the
+ * environment-MLP kernel of generation g (MLP environments only); the
+ * backward records adjoint_events[2g] / [2g+1] around the adjoint kernel of
+ * generation g and mlp_adjoint_events[2g] / [2g+1] around its MLP kernel.
  * Arrays must hold 2 * (max_depth + 1) events; NULL arrays are skipped. */
 typedef struct {
   void* const* trace_events;
   void* const* adjoint_events;
+  void* const* mlp_events;
+  void* const* mlp_adjoint_events;
 } dt_timing;
 
 typedef struct {

@@ -47,7 +47,8 @@ class _Scene(C.Structure):
 
 
 class _Timing(C.Structure):
-    _fields_ = [("trace_events", C.POINTER(C.c_void_p)), ("adjoint_events", C.POINTER(C.c_void_p))]
+    _fields_ = [("trace_events", C.POINTER(C.c_void_p)), ("adjoint_events", C.POINTER(C.c_void_p)),
+                ("mlp_events", C.POINTER(C.c_void_p)), ("mlp_adjoint_events", C.POINTER(C.c_void_p))]
 
 
 class _Params(C.Structure):
@@ -237,8 +238,9 @@ class Params:
 
 
 class KernelTimer:
-    """hipEvent pairs the library records around its traversal and adjoint
-    kernels (one pair per generation), read back as milliseconds."""
+    """hipEvent pairs the library records around its traversal, adjoint and
+    environment-MLP kernels (one pair per generation), read back as
+    milliseconds."""
 
     def __init__(self, max_depth: int):
         # the HIP runtime the library itself is bound to (dlsym searches the
@@ -251,7 +253,9 @@ class KernelTimer:
         self.n = n
         self.trace = (C.c_void_p * n)()
         self.adjoint = (C.c_void_p * n)()
-        for arr in (self.trace, self.adjoint):
+        self.mlp = (C.c_void_p * n)()
+        self.mlp_adjoint = (C.c_void_p * n)()
+        for arr in (self.trace, self.adjoint, self.mlp, self.mlp_adjoint):
             for i in range(n):
                 ev = C.c_void_p()
                 if self.hip.hipEventCreate(C.byref(ev)) != 0:
@@ -260,6 +264,8 @@ class KernelTimer:
         self.s = _Timing()
         self.s.trace_events = C.cast(self.trace, C.POINTER(C.c_void_p))
         self.s.adjoint_events = C.cast(self.adjoint, C.POINTER(C.c_void_p))
+        self.s.mlp_events = C.cast(self.mlp, C.POINTER(C.c_void_p))
+        self.s.mlp_adjoint_events = C.cast(self.mlp_adjoint, C.POINTER(C.c_void_p))
 
     def _ms(self, arr, g):
         self.hip.hipEventSynchronize(arr[2 * g + 1])
@@ -273,6 +279,12 @@ class KernelTimer:
 
     def adjoint_ms(self, gens: int):
         return [self._ms(self.adjoint, g) for g in range(gens)]
+
+    def mlp_ms(self, gens: int):
+        return [self._ms(self.mlp, g) for g in range(gens)]
+
+    def mlp_adjoint_ms(self, gens: int):
+        return [self._ms(self.mlp_adjoint, g) for g in range(gens)]
 
 
 class Rays:

@@ -13,7 +13,11 @@
 // a ray lands.)  The encoding takes sin(pi t), cos(pi t) of t = 2^k u, which
 // is exact in FP32, so no argument rounding error grows with the frequency.
 //
-// One wave evaluates 16 rays.  Layers are computed transposed,
+// A block first copies the whole network into LDS (rows padded by 4 bf16 so
+// the 16 rows an MFMA operand spans fall on different banks; the RGB head
+// padded to 16 zero rows), then its waves loop over groups of 16 rays, so the
+// weights are read from HBM once per block and every MFMA operand comes from
+// LDS.  One wave evaluates 16 rays at a time.  Layers are computed transposed,
 // D[out][ray] = W[out][in] * H[in][ray], so W is the MFMA A operand and the
 // activations the B operand; the accumulator layout of one layer (lane l holds
 // rows 4*(l/16)+j of column l%16) is exactly the B layout the next layer
@@ -81,12 +85,59 @@ __device__ __forceinline__ void denc(int k, v3 u, int n_freq, float& dx, float& 
 }
 
 constexpr int IN = 64;  // padded input width
+// threads per block: 8 waves share one LDS copy of a 64-wide network; the
+// 128-wide one (125 KB of LDS, one block per CU) runs 4 waves of up to 512
+// registers each, which its backward pass needs
+template <int HID>
+constexpr int mlp_threads() {
+  return HID == 64 ? 512 : 256;
+}
+
+// Layout of the LDS image of a (HID, NL) network: bf16 weights row by row with
+// padded row strides (layer 0: HID x (IN + 4); hidden layers: HID x (HID + 4);
+// head: 16 x (HID + 4), rows 3..15 zero), then FP32 biases (NL x HID, head 16).
+template <int HID, int NL>
+struct NetLds {
+  static constexpr int LD0 = IN + 4;
+  static constexpr int LDH = HID + 4;
+  static constexpr int W0 = 0;
+  static constexpr int WH = W0 + HID * LD0;
+  static constexpr int WO = WH + (NL - 1) * HID * LDH;
+  static constexpr int WEND = WO + 16 * LDH;
+  static constexpr int BOFF = (WEND * 2 + 15) / 16 * 16;  // byte offset of the biases
+  static constexpr int NB = NL * HID + 16;
+  static constexpr int BYTES = BOFF + NB * 4;
+  static_assert(BYTES <= 160 * 1024, "network does not fit in LDS");
+};
+
+// Cooperative copy of the network (global layout: W[l] row-major [out][in],
+// biases concatenated) into its LDS image; ends with a barrier.
+template <int HID, int NL>
+__device__ __forceinline__ void load_net(const EnvDev& e, uint16_t* sw, float* sb) {
+  using N = NetLds<HID, NL>;
+  const uint16_t* W = e.w;
+  for (int i = threadIdx.x; i < HID * IN; i += blockDim.x)
+    sw[N::W0 + (i / IN) * N::LD0 + (i % IN)] = W[i];
+  W += HID * IN;
+  for (int l = 1; l < NL; ++l) {
+    for (int i = threadIdx.x; i < HID * HID; i += blockDim.x)
+      sw[N::WH + (l - 1) * HID * N::LDH + (i / HID) * N::LDH + (i % HID)] = W[i];
+    W += HID * HID;
+  }
+  for (int i = threadIdx.x; i < 16 * HID; i += blockDim.x)
+    sw[N::WO + (i / HID) * N::LDH + (i % HID)] = i < 3 * HID ? W[i] : (uint16_t)0;
+  for (int i = threadIdx.x; i < N::NB; i += blockDim.x)
+    sb[i] = i < NL * HID + 3 ? e.b[i] : 0.f;
+  __syncthreads();
+}
 
 // One wave: lane l works on ray l % 16 (all four lane groups q = l / 16 carry
 // the same ray).  Returns E in lanes with q == 0; when GRAD, also returns
 // the direction gradient of dot(gbar, E) with respect to d (all lanes).
 template <int HID, int NL, bool GRAD>
-__device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar) {
+__device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int n_freq, v3 d,
+                                       v3 gbar, v3* dbar) {
+  using N = NetLds<HID, NL>;
   const int l = threadIdx.x & 63, q = l >> 4, r16 = l & 15;
   constexpr int KB = HID / 16;
   float inv_len = 1.0f / sqrtf(dot(d, d));
@@ -96,15 +147,14 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
   for (int kb = 0; kb < IN / 16; ++kb)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      Split3 p = split3(enc(kb * 16 + 4 * q + j, u, e.n_freq));
+      Split3 p = split3(enc(kb * 16 + 4 * q + j, u, n_freq));
       xh[kb][j] = p.h;
       xm[kb][j] = p.m;
       xl[kb][j] = p.l;
     }
   bf16x4 act[NL][KB];   // hi parts of every hidden layer (their signs are the ReLU masks)
   bf16x4 mi[KB], lo[KB];  // mid and lo parts of the latest hidden layer
-  const uint16_t* W = e.w;
-  const float* B = e.b;
+  const float* B = sb;
   // first hidden layer, on the encoding
 #pragma unroll
   for (int ob = 0; ob < KB; ++ob) {
@@ -113,7 +163,7 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
     for (int j = 0; j < 4; ++j) acc[j] = B[ob * 16 + 4 * q + j];
 #pragma unroll
     for (int kb = 0; kb < IN / 16; ++kb) {
-      bf16x4 a = *(const bf16x4*)(W + (size_t)(ob * 16 + r16) * IN + kb * 16 + 4 * q);
+      bf16x4 a = *(const bf16x4*)(sw + N::W0 + (ob * 16 + r16) * N::LD0 + kb * 16 + 4 * q);
       acc = mfma(a, xl[kb], acc);
       acc = mfma(a, xm[kb], acc);
       acc = mfma(a, xh[kb], acc);
@@ -126,7 +176,6 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
       lo[ob][j] = p.l;
     }
   }
-  W += (size_t)HID * IN;
   B += HID;
   // further hidden layers
 #pragma unroll
@@ -139,7 +188,8 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
       for (int j = 0; j < 4; ++j) acc[j] = B[ob * 16 + 4 * q + j];
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        bf16x4 a = *(const bf16x4*)(W + (size_t)(ob * 16 + r16) * HID + kb * 16 + 4 * q);
+        bf16x4 a = *(const bf16x4*)(sw + N::WH + (L - 1) * HID * N::LDH + (ob * 16 + r16) * N::LDH +
+                                    kb * 16 + 4 * q);
         acc = mfma(a, lo[kb], acc);
         acc = mfma(a, mi[kb], acc);
         acc = mfma(a, act[L - 1][kb], acc);
@@ -157,17 +207,15 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
       mi[ob] = nmi[ob];
       lo[ob] = nlo[ob];
     }
-    W += (size_t)HID * HID;
     B += HID;
   }
-  // linear RGB head (3 rows, padded to 16)
+  // linear RGB head (3 rows, padded to 16 zero rows)
   f32x4 out;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) out[j] = (4 * q + j < 3) ? B[4 * q + j] : 0.f;
+  for (int j = 0; j < 4; ++j) out[j] = B[4 * q + j];
 #pragma unroll
   for (int kb = 0; kb < KB; ++kb) {
-    bf16x4 a = {0, 0, 0, 0};
-    if (r16 < 3) a = *(const bf16x4*)(W + (size_t)r16 * HID + kb * 16 + 4 * q);
+    bf16x4 a = *(const bf16x4*)(sw + N::WO + r16 * N::LDH + kb * 16 + 4 * q);
     out = mfma(a, lo[kb], out);
     out = mfma(a, mi[kb], out);
     out = mfma(a, act[NL - 1][kb], out);
@@ -176,14 +224,6 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
   if (!GRAD) return E;
 
   // ---- input gradient: delta_out rows 0..2 = gbar, B layout
-  const uint16_t* Wl[NL + 1];
-  {
-    const uint16_t* p = e.w;
-    for (int L = 0; L <= NL; ++L) {
-      Wl[L] = p;
-      p += (size_t)(L == NL ? 3 : HID) * (L == 0 ? IN : HID);
-    }
-  }
   bf16x4 dh[KB], dl[KB];  // delta of the current layer's output, hi / lo parts
   {
     f32x4 g0;
@@ -202,8 +242,7 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
     bf16x4 a;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      int o = 4 * q + j;
-      a[j] = o < 3 ? (short)Wl[NL][(size_t)o * HID + ib * 16 + r16] : (short)0;
+      a[j] = (short)sw[N::WO + (4 * q + j) * N::LDH + ib * 16 + r16];  // rows >= 3 are zero
     }
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     acc = mfma(a, dh[0], acc);
@@ -227,7 +266,7 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
         bf16x4 a;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          a[j] = (short)Wl[L][(size_t)(kb * 16 + 4 * q + j) * HID + ib * 16 + r16];
+          a[j] = (short)sw[N::WH + (L - 1) * HID * N::LDH + (kb * 16 + 4 * q + j) * N::LDH + ib * 16 + r16];
         acc = mfma(a, nh[kb], acc);
         acc = mfma(a, nl[kb], acc);
       }
@@ -254,13 +293,13 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
       bf16x4 a;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        a[j] = (short)Wl[0][(size_t)(kb * 16 + 4 * q + j) * IN + ib * 16 + r16];
+        a[j] = (short)sw[N::W0 + (kb * 16 + 4 * q + j) * N::LD0 + ib * 16 + r16];
       acc = mfma(a, nh[kb], acc);
       acc = mfma(a, nl[kb], acc);
     }
     // acc[j] = d loss / d enc_k for k = ib*16 + 4q + j of ray r16
 #pragma unroll
-    for (int j = 0; j < 4; ++j) denc(ib * 16 + 4 * q + j, u, e.n_freq, gx, gy, gz, acc[j]);
+    for (int j = 0; j < 4; ++j) denc(ib * 16 + 4 * q + j, u, n_freq, gx, gy, gz, acc[j]);
   }
   // the four lane groups hold different k of the same ray
   gx += __shfl_xor(gx, 16);
@@ -276,92 +315,125 @@ __device__ __forceinline__ v3 mlp_wave(const EnvDev& e, v3 d, v3 gbar, v3* dbar)
 }
 
 // ------------------------------------------------------------------ kernels
-// Each wave takes 16 consecutive items; items past `count` run on a dummy
-// direction and write nothing.
+// Every block loads the network into LDS once, then each of its waves takes
+// groups of 16 consecutive items in turn; items past the count run on a dummy
+// direction and write nothing.  The loops' trip counts are uniform per wave.
+#define DT_MLP_PROLOGUE                                                   \
+  using N = NetLds<HID, NL>;                                              \
+  __shared__ __align__(16) unsigned char net[N::BYTES];                  \
+  uint16_t* sw = (uint16_t*)net;                                          \
+  float* sb = (float*)(net + N::BOFF);                                    \
+  load_net<HID, NL>(e, sw, sb);                                           \
+  const int waves = mlp_threads<HID>() / 64;                              \
+  const int64_t wstep = (int64_t)gridDim.x * waves * 16;                  \
+  const int64_t wfirst = ((int64_t)blockIdx.x * waves + (threadIdx.x >> 6)) * 16;
+
+// An opaque zero offset per group: the weight reads then depend on the loop
+// iteration, so the compiler streams them from LDS in every group instead of
+// hoisting the whole network into registers (which spills for 128-wide nets).
+__device__ __forceinline__ const uint16_t* per_group(const uint16_t* sw) {
+  int z = 0;
+  asm volatile("" : "+s"(z));
+  return sw + z;
+}
+
 template <int HID, int NL>
-__global__ void __launch_bounds__(256) k_mlp_query(EnvDev e, const float* dirs, int64_t n, float* rgb) {
-  int64_t item = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + (threadIdx.x & 15);
-  bool valid = item < n;
-  v3 d = valid ? load3(dirs + 3 * item) : mk3(0.f, 1.f, 0.f);
-  v3 dummy;
-  v3 E = mlp_wave<HID, NL, false>(e, d, mk3(0.f, 0.f, 0.f), &dummy);
-  if (valid && (threadIdx.x & 63) < 16) {
-    rgb[3 * item] = E.x;
-    rgb[3 * item + 1] = E.y;
-    rgb[3 * item + 2] = E.z;
+__global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_query(EnvDev e, const float* dirs, int64_t n,
+                                                           float* rgb) {
+  DT_MLP_PROLOGUE
+  for (int64_t w0 = wfirst; w0 < n; w0 += wstep) {
+    int64_t item = w0 + (threadIdx.x & 15);
+    bool valid = item < n;
+    v3 d = valid ? load3(dirs + 3 * item) : mk3(0.f, 1.f, 0.f);
+    v3 dummy;
+    v3 E = mlp_wave<HID, NL, false>(per_group(sw), sb, e.n_freq, d, mk3(0.f, 0.f, 0.f), &dummy);
+    if (valid && (threadIdx.x & 63) < 16) {
+      rgb[3 * item] = E.x;
+      rgb[3 * item + 1] = E.y;
+      rgb[3 * item + 2] = E.z;
+    }
   }
 }
 
 template <int HID, int NL>
-__global__ void __launch_bounds__(256) k_mlp_query_bwd(EnvDev e, const float* dirs, int64_t n,
-                                                       const float* g, float* gd) {
-  int64_t item = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + (threadIdx.x & 15);
-  bool valid = item < n;
-  v3 d = valid ? load3(dirs + 3 * item) : mk3(0.f, 1.f, 0.f);
-  v3 gb = valid ? load3(g + 3 * item) : mk3(0.f, 0.f, 0.f);
-  v3 db;
-  mlp_wave<HID, NL, true>(e, d, gb, &db);
-  if (valid && (threadIdx.x & 63) < 16) {
-    gd[3 * item] = db.x;
-    gd[3 * item + 1] = db.y;
-    gd[3 * item + 2] = db.z;
+__global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_query_bwd(EnvDev e, const float* dirs, int64_t n,
+                                                               const float* g, float* gd) {
+  DT_MLP_PROLOGUE
+  for (int64_t w0 = wfirst; w0 < n; w0 += wstep) {
+    int64_t item = w0 + (threadIdx.x & 15);
+    bool valid = item < n;
+    v3 d = valid ? load3(dirs + 3 * item) : mk3(0.f, 1.f, 0.f);
+    v3 gb = valid ? load3(g + 3 * item) : mk3(0.f, 0.f, 0.f);
+    v3 db;
+    mlp_wave<HID, NL, true>(per_group(sw), sb, e.n_freq, d, gb, &db);
+    if (valid && (threadIdx.x & 63) < 16) {
+      gd[3 * item] = db.x;
+      gd[3 * item + 1] = db.y;
+      gd[3 * item + 2] = db.z;
+    }
   }
 }
 
 template <int HID, int NL>
-__global__ void __launch_bounds__(256) k_mlp_trace_fwd(EnvDev e, Gen q, const uint32_t* list,
-                                                       const Counters* ctr, int g, float* rgb) {
-  const uint32_t n = ctr->nmiss[g];
-  const int64_t wave0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  if (wave0 >= n) return;  // uniform per wave
-  int64_t item = wave0 + (threadIdx.x & 15);
-  bool valid = item < n;
-  uint32_t i = valid ? list[item] : 0u;
-  float4 d4 = valid ? q.d[i] : make_float4(0.f, 1.f, 0.f, 0.f);
-  v3 dummy;
-  v3 E = mlp_wave<HID, NL, false>(e, xyz(d4), mk3(0.f, 0.f, 0.f), &dummy);
-  if (valid && (threadIdx.x & 63) < 16) {
-    float4 w4 = q.w[i];
-    int pix = __float_as_int(d4.w);
-    atomicAdd(rgb + 3 * pix, w4.x * E.x);
-    atomicAdd(rgb + 3 * pix + 1, w4.y * E.y);
-    atomicAdd(rgb + 3 * pix + 2, w4.z * E.z);
+__global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_trace_fwd(EnvDev e, Gen q, const uint32_t* list,
+                                                               const Counters* ctr, int g, float* rgb) {
+  DT_MLP_PROLOGUE
+  const int64_t n = ctr->nmiss[g];
+  for (int64_t w0 = wfirst; w0 < n; w0 += wstep) {
+    int64_t item = w0 + (threadIdx.x & 15);
+    bool valid = item < n;
+    uint32_t i = valid ? list[item] : 0u;
+    float4 d4 = valid ? q.d[i] : make_float4(0.f, 1.f, 0.f, 0.f);
+    v3 dummy;
+    v3 E = mlp_wave<HID, NL, false>(per_group(sw), sb, e.n_freq, xyz(d4), mk3(0.f, 0.f, 0.f), &dummy);
+    if (valid && (threadIdx.x & 63) < 16) {
+      float4 w4 = q.w[i];
+      int pix = __float_as_int(d4.w);
+      atomicAdd(rgb + 3 * pix, w4.x * E.x);
+      atomicAdd(rgb + 3 * pix + 1, w4.y * E.y);
+      atomicAdd(rgb + 3 * pix + 2, w4.z * E.z);
+    }
   }
 }
 
 template <int HID, int NL>
-__global__ void __launch_bounds__(256) k_mlp_trace_bwd(EnvDev e, Gen q, const uint32_t* list,
-                                                       const Counters* ctr, int g,
-                                                       const float* grad_rgb, Adj cur) {
-  const uint32_t n = ctr->nmiss[g];
-  const int64_t wave0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-  if (wave0 >= n) return;
-  int64_t item = wave0 + (threadIdx.x & 15);
-  bool valid = item < n;
-  uint32_t i = valid ? list[item] : 0u;
-  float4 d4 = valid ? q.d[i] : make_float4(0.f, 1.f, 0.f, 0.f);
-  v3 gb = mk3(0.f, 0.f, 0.f);
-  if (valid) {
-    float4 w4 = q.w[i];
-    int pix = __float_as_int(d4.w);
-    v3 gp = load3(grad_rgb + 3 * pix);
-    gb = mk3(gp.x * w4.x, gp.y * w4.y, gp.z * w4.z);
-  }
-  v3 db;
-  v3 E = mlp_wave<HID, NL, true>(e, xyz(d4), gb, &db);
-  if (valid && (threadIdx.x & 63) < 16) {
-    cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
-    cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    cur.D[i] = make_float4(db.x, db.y, db.z, 0.f);
+__global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_trace_bwd(EnvDev e, Gen q, const uint32_t* list,
+                                                               const Counters* ctr, int g,
+                                                               const float* grad_rgb, Adj cur) {
+  DT_MLP_PROLOGUE
+  const int64_t n = ctr->nmiss[g];
+  for (int64_t w0 = wfirst; w0 < n; w0 += wstep) {
+    int64_t item = w0 + (threadIdx.x & 15);
+    bool valid = item < n;
+    uint32_t i = valid ? list[item] : 0u;
+    float4 d4 = valid ? q.d[i] : make_float4(0.f, 1.f, 0.f, 0.f);
+    v3 gb = mk3(0.f, 0.f, 0.f);
+    if (valid) {
+      float4 w4 = q.w[i];
+      int pix = __float_as_int(d4.w);
+      v3 gp = load3(grad_rgb + 3 * pix);
+      gb = mk3(gp.x * w4.x, gp.y * w4.y, gp.z * w4.z);
+    }
+    v3 db;
+    v3 E = mlp_wave<HID, NL, true>(per_group(sw), sb, e.n_freq, xyz(d4), gb, &db);
+    if (valid && (threadIdx.x & 63) < 16) {
+      cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
+      cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      cur.D[i] = make_float4(db.x, db.y, db.z, 0.f);
+    }
   }
 }
+#undef DT_MLP_PROLOGUE
 
 // dispatch over the supported (hidden width, hidden layers) shapes
 #define DT_MLP_SHAPES(X) X(64, 1) X(64, 2) X(64, 3) X(64, 4) X(128, 1) X(128, 2) X(128, 3) X(128, 4)
 
-unsigned mlp_blocks(int64_t n) {
-  int64_t b = (n + 63) / 64;
-  return (unsigned)(b < 1 ? 1 : b);
+// enough blocks to cover n items (16 per wave), at most a few resident per CU
+unsigned mlp_blocks(int64_t n, int threads) {
+  int64_t per = threads / 4;  // 16 items per wave
+  int64_t b = (n + per - 1) / per;
+  const int64_t cap = 256 * 4;
+  return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
 }  // namespace
@@ -373,13 +445,13 @@ bool mlp_supported(const EnvDev& e) {
 
 #define DT_LAUNCH(H, L, kern, grid, ...)                                                    \
   if (e.hidden == H && e.n_layers == L) {                                                   \
-    hipLaunchKernelGGL((kern<H, L>), dim3(grid), dim3(256), 0, s, __VA_ARGS__);             \
+    hipLaunchKernelGGL((kern<H, L>), dim3(grid), dim3(mlp_threads<H>()), 0, s, __VA_ARGS__); \
     DT_CHECK_LAUNCH();                                                                      \
     return DT_OK;                                                                           \
   }
 
 dt_status mlp_query(const EnvDev& e, const float* dirs, int64_t n, float* rgb, hipStream_t s) {
-#define X(H, L) DT_LAUNCH(H, L, k_mlp_query, mlp_blocks(n), e, dirs, n, rgb)
+#define X(H, L) DT_LAUNCH(H, L, k_mlp_query, mlp_blocks(n, mlp_threads<H>()), e, dirs, n, rgb)
   DT_MLP_SHAPES(X)
 #undef X
   dt_set_error("environment MLP shape (hidden %d, layers %d) is not supported", e.hidden, e.n_layers);
@@ -388,7 +460,7 @@ dt_status mlp_query(const EnvDev& e, const float* dirs, int64_t n, float* rgb, h
 
 dt_status mlp_query_backward(const EnvDev& e, const float* dirs, int64_t n, const float* g,
                              float* gd, hipStream_t s) {
-#define X(H, L) DT_LAUNCH(H, L, k_mlp_query_bwd, mlp_blocks(n), e, dirs, n, g, gd)
+#define X(H, L) DT_LAUNCH(H, L, k_mlp_query_bwd, mlp_blocks(n, mlp_threads<H>()), e, dirs, n, g, gd)
   DT_MLP_SHAPES(X)
 #undef X
   dt_set_error("environment MLP shape (hidden %d, layers %d) is not supported", e.hidden, e.n_layers);
@@ -397,7 +469,7 @@ dt_status mlp_query_backward(const EnvDev& e, const float* dirs, int64_t n, cons
 
 dt_status mlp_trace_forward(const EnvDev& e, Gen q, const uint32_t* list, const Counters* ctr,
                             int g, int64_t cap, float* rgb, hipStream_t s) {
-#define X(H, L) DT_LAUNCH(H, L, k_mlp_trace_fwd, mlp_blocks(cap), e, q, list, ctr, g, rgb)
+#define X(H, L) DT_LAUNCH(H, L, k_mlp_trace_fwd, mlp_blocks(cap, mlp_threads<H>()), e, q, list, ctr, g, rgb)
   DT_MLP_SHAPES(X)
 #undef X
   dt_set_error("environment MLP shape (hidden %d, layers %d) is not supported", e.hidden, e.n_layers);
@@ -406,7 +478,7 @@ dt_status mlp_trace_forward(const EnvDev& e, Gen q, const uint32_t* list, const 
 
 dt_status mlp_trace_backward(const EnvDev& e, Gen q, const uint32_t* list, const Counters* ctr,
                              int g, int64_t cap, const float* grad_rgb, Adj cur, hipStream_t s) {
-#define X(H, L) DT_LAUNCH(H, L, k_mlp_trace_bwd, mlp_blocks(cap), e, q, list, ctr, g, grad_rgb, cur)
+#define X(H, L) DT_LAUNCH(H, L, k_mlp_trace_bwd, mlp_blocks(cap, mlp_threads<H>()), e, q, list, ctr, g, grad_rgb, cur)
   DT_MLP_SHAPES(X)
 #undef X
   dt_set_error("environment MLP shape (hidden %d, layers %d) is not supported", e.hidden, e.n_layers);

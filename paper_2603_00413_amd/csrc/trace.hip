@@ -255,7 +255,7 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
                                               int32_t* flags, unsigned long long* sig,
-                                              int accumulate, uint32_t* miss_list, uint2* ovf) {
+                                              int accumulate, uint2* ovf) {
   __shared__ uint2 stk[DT_STACK_LDS * TB];
   uint2* gstk = ovf + (size_t)(blockIdx.x * TB + threadIdx.x) * (DT_STACK - DT_STACK_LDS);
   const uint32_t n = ctr->count[g];
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
     if (base >= n) break;
     uint32_t i = base + lane;
     bool active = i < n;
-    bool has_r = false, has_t = false, hit = false, listed = false;
+    bool has_r = false, has_t = false, hit = false;
     if (active) {
       float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i];
       v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
@@ -282,12 +282,9 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
       int pf = ovf ? DT_FLAG_STACK : 0;
       if (h.tri < 0) {
         if (rfl & RAY_INSIDE) pf |= DT_FLAG_LEAK;
-        if (accumulate) {
-          if (sc.env.kind == DT_ENV_EQUIRECT)
-            add_rgb(rgb, pix, mul3(W, env_equirect(sc.env, d)));
-          else
-            listed = true;  // evaluated in batches on the matrix cores
-        }
+        // equirect lookups here; MLP lookups are listed afterwards and run in
+        // batches on the matrix cores
+        if (accumulate && sc.env.kind == DT_ENV_EQUIRECT) add_rgb(rgb, pix, mul3(W, env_equirect(sc.env, d)));
       } else {
         hit = true;
         HitGeo geo = load_geo(sc, h.tri);
@@ -327,13 +324,6 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
       atomicAdd(part + base / CHUNK,
                 (unsigned long long)__popcll(br) | ((unsigned long long)__popcll(bt) << 32));
     if (lane == 0 && bh && accumulate) atomicAdd(&ctr->hits[g], (uint32_t)__popcll(bh));
-    uint64_t bm = __ballot(listed);
-    if (bm) {
-      uint32_t mbase = 0;
-      if (lane == 0) mbase = atomicAdd(&ctr->nmiss[g], (uint32_t)__popcll(bm));
-      mbase = (uint32_t)__shfl((int)mbase, 0);
-      if (listed) miss_list[mbase + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = i;
-    }
   }
 }
 
@@ -783,20 +773,36 @@ __global__ void __launch_bounds__(RED_T) k_reduce_scalars(const float4* red, int
   }
 }
 
-// miss list of generation g from the recorded decisions (adjoint, MLP environment)
-__global__ void k_list_misses(Gen q, int g, Counters* ctr, uint32_t* list) {
+// miss list of generation g from the recorded decisions (MLP environment,
+// forward and adjoint).  A block of LB threads ranks its misses in LDS and
+// reserves their slots with one atomic, so the list counter sees one atomic
+// per LB rays instead of one per wave.  The order of the list is irrelevant:
+// every listed ray is evaluated independently.
+constexpr int LB = 1024;
+
+__global__ void __launch_bounds__(LB) k_list_misses(Gen q, int g, Counters* ctr, uint32_t* list) {
+  __shared__ uint32_t wcount[LB / 64];
+  __shared__ uint32_t bbase;
   const uint32_t n = ctr->count[g];
-  const int lane = threadIdx.x & 63;
-  for (int64_t base = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) & ~63ll; base < n;
-       base += (int64_t)gridDim.x * blockDim.x) {
-    int64_t i = base + lane;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t base = (int64_t)blockIdx.x * LB; base < n; base += (int64_t)gridDim.x * LB) {
+    int64_t i = base + threadIdx.x;
     bool miss = i < n && !(q.code[i] & C_HIT);
     uint64_t bm = __ballot(miss);
-    if (!bm) continue;
-    uint32_t mb = 0;
-    if (lane == 0) mb = atomicAdd(&ctr->nmiss[g], (uint32_t)__popcll(bm));
-    mb = (uint32_t)__shfl((int)mb, 0);
-    if (miss) list[mb + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)i;
+    if (lane == 0) wcount[wave] = (uint32_t)__popcll(bm);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (int w = 0; w < LB / 64; ++w) {
+        uint32_t c = wcount[w];
+        wcount[w] = tot;
+        tot += c;
+      }
+      bbase = tot ? atomicAdd(&ctr->nmiss[g], tot) : 0u;
+    }
+    __syncthreads();
+    if (miss) list[bbase + wcount[wave] + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)i;
+    __syncthreads();
   }
 }
 
@@ -944,6 +950,11 @@ Gen gen_at(char* base, size_t o, size_t d, size_t w, size_t hit, size_t code, si
   return g;
 }
 
+unsigned list_grid(int64_t cap) {
+  int64_t b = (cap + LB - 1) / LB;
+  return (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+}
+
 unsigned trace_grid(int64_t cap) {
   int64_t waves = (cap + 63) / 64;
   int64_t lim = TRACE_MAX_BLOCKS;  // resident waves the LDS stack allows on 256 CUs
@@ -980,15 +991,20 @@ dt_status record(void* const* ev, int i, hipStream_t s) {
 dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen nxt, Counters* ctr,
                          unsigned long long* part_g, unsigned long long* part_other, float* rgb,
                          float* wtrunc, int32_t* flags, unsigned long long* sig, int accumulate,
-                         int write_next, void* const* events, uint32_t* miss_list, uint2* ovf,
-                         hipStream_t s) {
+                         int write_next, void* const* events, void* const* mlp_events,
+                         uint32_t* miss_list, uint2* ovf, hipStream_t s) {
   if (dt_status st = record(events, 2 * g, s)) return st;
   hipLaunchKernelGGL(k_trace, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
-                     rgb, wtrunc, flags, sig, accumulate, miss_list, ovf);
+                     rgb, wtrunc, flags, sig, accumulate, ovf);
   DT_CHECK_LAUNCH();
   if (dt_status st = record(events, 2 * g + 1, s)) return st;
-  if (accumulate && sc.env.kind == DT_ENV_MLP)
+  if (accumulate && sc.env.kind == DT_ENV_MLP) {
+    hipLaunchKernelGGL(k_list_misses, dim3(list_grid(P.cap[g])), dim3(LB), 0, s, cur, g, ctr, miss_list);
+    DT_CHECK_LAUNCH();
+    if (dt_status st = record(mlp_events, 2 * g, s)) return st;
     if (dt_status st = mlp_trace_forward(sc.env, cur, miss_list, ctr, g, P.cap[g], rgb, s)) return st;
+    if (dt_status st = record(mlp_events, 2 * g + 1, s)) return st;
+  }
   if (g < P.D) {
     int64_t other_n = (P.cap[g + 1] + CHUNK - 1) / CHUNK + 1;
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctr, g, part_g, part_other, other_n,
@@ -1159,8 +1175,9 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
       if (dt_status st = emit_rays(rays, cur, s)) return st;
     Gen nxt = g < P.D ? gen_fwd(g + 1) : cur;
     void* const* ev = p->timing ? p->timing->trace_events : nullptr;
+    void* const* mev = p->timing ? p->timing->mlp_events : nullptr;
     if (dt_status st = run_generation(sc, P, g, cur, nxt, ctr, part[g & 1], part[(g + 1) & 1], rgb,
-                                      wtrunc, flags, (unsigned long long*)path_sig, 1, 1, ev,
+                                      wtrunc, flags, (unsigned long long*)path_sig, 1, 1, ev, mev,
                                       (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), s))
       return st;
   }
@@ -1208,16 +1225,19 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     adj[b].D = (float4*)(W + P.w_adj[b][2]);
   }
   void* const* aev = p->timing ? p->timing->adjoint_events : nullptr;
+  void* const* maev = p->timing ? p->timing->mlp_adjoint_events : nullptr;
   auto adjoint = [&](int g, Gen q) -> dt_status {
     int64_t blocks = (P.cap[g] + AB - 1) / AB;
     if (blocks > ADJ_MAX_BLOCKS) blocks = ADJ_MAX_BLOCKS;
     if (dt_status st = record(aev, 2 * g, s)) return st;
     if (sc.env.kind == DT_ENV_MLP) {
       uint32_t* ml = (uint32_t*)(W + P.w_miss);
-      hipLaunchKernelGGL(k_list_misses, dim3((unsigned)blocks), dim3(AB), 0, s, q, g, ctr, ml);
+      hipLaunchKernelGGL(k_list_misses, dim3(list_grid(P.cap[g])), dim3(LB), 0, s, q, g, ctr, ml);
       DT_CHECK_LAUNCH();
+      if (dt_status st = record(maev, 2 * g, s)) return st;
       if (dt_status st = mlp_trace_backward(sc.env, q, ml, ctr, g, P.cap[g], grad_rgb, adj[g & 1], s))
         return st;
+      if (dt_status st = record(maev, 2 * g + 1, s)) return st;
     }
     hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
                        adj[(g + 1) & 1], adj[g & 1], dV, dN, red);
@@ -1257,7 +1277,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
         Gen nxt = g < g1 ? seg[j + 1] : seg[j];
         if (dt_status st = run_generation(sc, P, g, seg[j], nxt, ctr, part[g & 1], part[(g + 1) & 1],
                                           nullptr, nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0,
-                                          nullptr,
+                                          nullptr, nullptr,
                                           (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), s))
           return st;
       }
