@@ -1,12 +1,12 @@
-// Environment MLP on bf16 matrix cores (gfx950 MFMA 16x16x16, FP32 accumulate).
+// Environment MLP on bf16 matrix cores (gfx950 MFMA 16x16x32, FP32 accumulate).
 //
 // E(d) = head( relu(... relu(W0 gamma(u) + b0) ...) ), u = d / |d|,
 // gamma(u) = [u, sin(2^k pi u), cos(2^k pi u)]_{k < n_freq}, zero-padded to 64.
 // Weights are bf16 (exact MFMA operands), biases FP32.  Every activation
 // vector (the encoding and each hidden layer's ReLU output) is carried as
-// three bf16 vectors, hi = bf16(x), mid = bf16(x - hi), lo = bf16(x - hi - mid),
-// which together hold all 24 bits of the FP32 value, and each layer is three
-// MFMAs (W hi + W mid + W lo) accumulated in FP32: the products of bf16
+// three bf16 vectors (the top, middle and bottom 8 significant bits of the
+// FP32 value, cut by truncation, so they sum to it exactly), and each layer is
+// three MFMAs (W hi + W mid + W lo) accumulated in FP32: the products of bf16
 // weights and bf16 parts are exact, so a layer is as accurate as an FP32
 // matrix product.  (A single bf16 rounding per activation would put steps of
 // 2^-9 relative into E, and a derivative that depends on which side of a step
@@ -20,9 +20,11 @@
 // LDS.  One wave evaluates 16 rays at a time.  Layers are computed transposed,
 // D[out][ray] = W[out][in] * H[in][ray], so W is the MFMA A operand and the
 // activations the B operand; the accumulator layout of one layer (lane l holds
-// rows 4*(l/16)+j of column l%16) is exactly the B layout the next layer
-// needs, and activations never leave registers.  The input gradient runs the
-// same way with W^T as the A operand and the upstream gradient split into
+// rows 4*(l/16)+j of column l%16) gives each lane four rows of a 16-row
+// block, and two consecutive blocks make the eight k values a lane supplies
+// to one 16x16x32 product (the weights' A operand is gathered with the same k
+// pairing), so activations never leave registers.  The input gradient runs
+// the same way with W^T as the A operand and the upstream gradient split into
 // hi + lo (about 16 bits; the gradient tolerance is 1e-3).
 #include "dt_queue.h"
 
@@ -42,16 +44,21 @@ __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// three-part bf16 split of an FP32 value (each difference is exact in FP32)
+// Three-part bf16 split of an FP32 value by truncation: hi keeps the top 8
+// significant bits, mid the next 8 of the (exact) remainder, lo the last 8,
+// so hi + mid + lo equals the FP32 value exactly (for normal values).
 struct Split3 {
   short h, m, l;
 };
 __device__ __forceinline__ Split3 split3(float v) {
   Split3 s;
-  s.h = f2bf(v);
-  float r = v - bf2f(s.h);
-  s.m = f2bf(r);
-  s.l = f2bf(r - bf2f(s.m));
+  uint32_t a = __float_as_uint(v) & 0xFFFF0000u;
+  float r = v - __uint_as_float(a);
+  uint32_t b = __float_as_uint(r) & 0xFFFF0000u;
+  float t = r - __uint_as_float(b);
+  s.h = (short)(a >> 16);
+  s.m = (short)(b >> 16);
+  s.l = (short)(__float_as_uint(t) >> 16);
   return s;
 }
 
@@ -131,9 +138,44 @@ __device__ __forceinline__ void load_net(const EnvDev& e, uint16_t* sw, float* s
   __syncthreads();
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// K = 32 operand from two K = 16 halves: slots 0..3 take k = 4q + j of the
+// first 16-block, slots 4..7 k = 4q + j of the second.  A and B operands are
+// always built with the same pairing, so the product sums over the same 32 k
+// whatever order the matrix core walks them in.
+__device__ __forceinline__ bf16x8 cat8(bf16x4 lo16, bf16x4 hi16) {
+  s16x8 v = __builtin_shufflevector(lo16, hi16, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, v);
+}
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// A operand of rows r16 of a weight block in LDS: columns c0 + 4q + (0..3) and
+// c0 + 16 + 4q + (0..3) of row `row` (stride ld)
+__device__ __forceinline__ bf16x8 wfrag(const uint16_t* w, int row, int ld, int c0, int q) {
+  bf16x4 x = *(const bf16x4*)(w + row * ld + c0 + 4 * q);
+  bf16x4 y = *(const bf16x4*)(w + row * ld + c0 + 16 + 4 * q);
+  return cat8(x, y);
+}
+// A operand of the transposed weight block: W[k][col] for the same k pairing
+__device__ __forceinline__ bf16x8 wfrag_t(const uint16_t* w, int col, int ld, int k0, int q) {
+  bf16x4 x, y;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    x[j] = (short)w[(k0 + 4 * q + j) * ld + col];
+    y[j] = (short)w[(k0 + 16 + 4 * q + j) * ld + col];
+  }
+  return cat8(x, y);
+}
+
 // One wave: lane l works on ray l % 16 (all four lane groups q = l / 16 carry
 // the same ray).  Returns E in lanes with q == 0; when GRAD, also returns
 // the direction gradient of dot(gbar, E) with respect to d (all lanes).
+// Activations live in 16-row blocks in the MFMA accumulator layout (lane
+// (q, r16) holds rows 4q + j of column r16); two consecutive blocks form the
+// B operand of one 16x16x32 product.
 template <int HID, int NL, bool GRAD>
 __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int n_freq, v3 d,
                                        v3 gbar, v3* dbar) {
@@ -152,7 +194,7 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
       xm[kb][j] = p.m;
       xl[kb][j] = p.l;
     }
-  bf16x4 act[NL][KB];   // hi parts of every hidden layer (their signs are the ReLU masks)
+  bf16x4 act[NL][KB];     // hi parts of every hidden layer (their signs are the ReLU masks)
   bf16x4 mi[KB], lo[KB];  // mid and lo parts of the latest hidden layer
   const float* B = sb;
   // first hidden layer, on the encoding
@@ -162,11 +204,11 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = B[ob * 16 + 4 * q + j];
 #pragma unroll
-    for (int kb = 0; kb < IN / 16; ++kb) {
-      bf16x4 a = *(const bf16x4*)(sw + N::W0 + (ob * 16 + r16) * N::LD0 + kb * 16 + 4 * q);
-      acc = mfma(a, xl[kb], acc);
-      acc = mfma(a, xm[kb], acc);
-      acc = mfma(a, xh[kb], acc);
+    for (int kb = 0; kb < IN / 32; ++kb) {
+      bf16x8 a = wfrag(sw + N::W0, ob * 16 + r16, N::LD0, kb * 32, q);
+      acc = mfma32(a, cat8(xl[2 * kb], xl[2 * kb + 1]), acc);
+      acc = mfma32(a, cat8(xm[2 * kb], xm[2 * kb + 1]), acc);
+      acc = mfma32(a, cat8(xh[2 * kb], xh[2 * kb + 1]), acc);
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -180,6 +222,7 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
   // further hidden layers
 #pragma unroll
   for (int L = 1; L < NL; ++L) {
+    const uint16_t* WL = sw + N::WH + (L - 1) * HID * N::LDH;
     bf16x4 nmi[KB], nlo[KB];
 #pragma unroll
     for (int ob = 0; ob < KB; ++ob) {
@@ -187,12 +230,11 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[j] = B[ob * 16 + 4 * q + j];
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        bf16x4 a = *(const bf16x4*)(sw + N::WH + (L - 1) * HID * N::LDH + (ob * 16 + r16) * N::LDH +
-                                    kb * 16 + 4 * q);
-        acc = mfma(a, lo[kb], acc);
-        acc = mfma(a, mi[kb], acc);
-        acc = mfma(a, act[L - 1][kb], acc);
+      for (int kb = 0; kb < KB / 2; ++kb) {
+        bf16x8 a = wfrag(WL, ob * 16 + r16, N::LDH, kb * 32, q);
+        acc = mfma32(a, cat8(lo[2 * kb], lo[2 * kb + 1]), acc);
+        acc = mfma32(a, cat8(mi[2 * kb], mi[2 * kb + 1]), acc);
+        acc = mfma32(a, cat8(act[L - 1][2 * kb], act[L - 1][2 * kb + 1]), acc);
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -214,39 +256,36 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
 #pragma unroll
   for (int j = 0; j < 4; ++j) out[j] = B[4 * q + j];
 #pragma unroll
-  for (int kb = 0; kb < KB; ++kb) {
-    bf16x4 a = *(const bf16x4*)(sw + N::WO + r16 * N::LDH + kb * 16 + 4 * q);
-    out = mfma(a, lo[kb], out);
-    out = mfma(a, mi[kb], out);
-    out = mfma(a, act[NL - 1][kb], out);
+  for (int kb = 0; kb < KB / 2; ++kb) {
+    bf16x8 a = wfrag(sw + N::WO, r16, N::LDH, kb * 32, q);
+    out = mfma32(a, cat8(lo[2 * kb], lo[2 * kb + 1]), out);
+    out = mfma32(a, cat8(mi[2 * kb], mi[2 * kb + 1]), out);
+    out = mfma32(a, cat8(act[NL - 1][2 * kb], act[NL - 1][2 * kb + 1]), out);
   }
   v3 E = mk3(out[0], out[1], out[2]);
   if (!GRAD) return E;
 
   // ---- input gradient: delta_out rows 0..2 = gbar, B layout
-  bf16x4 dh[KB], dl[KB];  // delta of the current layer's output, hi / lo parts
+  bf16x4 dh0, dl0;  // delta of the head output, hi / lo parts (rows 0..2 of lane group 0)
   {
-    f32x4 g0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) g0[j] = (q == 0 && j < 3) ? comp(gbar, j) : 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      dh[0][j] = f2bf(g0[j]);
-      dl[0][j] = f2bf(g0[j] - bf2f(dh[0][j]));
+      float g0 = (q == 0 && j < 3) ? comp(gbar, j) : 0.f;
+      dh0[j] = f2bf(g0);
+      dl0[j] = f2bf(g0 - bf2f(dh0[j]));
     }
   }
-  // head: delta_hidden = W_head^T delta_out, masked by the last ReLU
+  // head: delta_hidden = W_head^T delta_out (a K = 16 product over the 16
+  // padded head rows), masked by the last ReLU
   bf16x4 nh[KB], nl[KB];
 #pragma unroll
   for (int ib = 0; ib < KB; ++ib) {
     bf16x4 a;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      a[j] = (short)sw[N::WO + (4 * q + j) * N::LDH + ib * 16 + r16];  // rows >= 3 are zero
-    }
+    for (int j = 0; j < 4; ++j) a[j] = (short)sw[N::WO + (4 * q + j) * N::LDH + ib * 16 + r16];
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mfma(a, dh[0], acc);
-    acc = mfma(a, dl[0], acc);
+    acc = mfma(a, dh0, acc);
+    acc = mfma(a, dl0, acc);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       float v = bf2f(act[NL - 1][ib][j]) > 0.f ? acc[j] : 0.f;
@@ -257,18 +296,16 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
   // hidden layers NL-1 .. 1: delta_{L-1} = W_L^T delta_L, masked by relu'(layer L-1)
 #pragma unroll
   for (int L = NL - 1; L >= 1; --L) {
+    const uint16_t* WL = sw + N::WH + (L - 1) * HID * N::LDH;
     bf16x4 th[KB], tl[KB];
 #pragma unroll
     for (int ib = 0; ib < KB; ++ib) {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        bf16x4 a;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          a[j] = (short)sw[N::WH + (L - 1) * HID * N::LDH + (kb * 16 + 4 * q + j) * N::LDH + ib * 16 + r16];
-        acc = mfma(a, nh[kb], acc);
-        acc = mfma(a, nl[kb], acc);
+      for (int kb = 0; kb < KB / 2; ++kb) {
+        bf16x8 a = wfrag_t(WL, ib * 16 + r16, N::LDH, kb * 32, q);
+        acc = mfma32(a, cat8(nh[2 * kb], nh[2 * kb + 1]), acc);
+        acc = mfma32(a, cat8(nl[2 * kb], nl[2 * kb + 1]), acc);
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -289,13 +326,10 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
   for (int ib = 0; ib < IN / 16; ++ib) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < KB; ++kb) {
-      bf16x4 a;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        a[j] = (short)sw[N::W0 + (kb * 16 + 4 * q + j) * N::LD0 + ib * 16 + r16];
-      acc = mfma(a, nh[kb], acc);
-      acc = mfma(a, nl[kb], acc);
+    for (int kb = 0; kb < KB / 2; ++kb) {
+      bf16x8 a = wfrag_t(sw + N::W0, ib * 16 + r16, N::LD0, kb * 32, q);
+      acc = mfma32(a, cat8(nh[2 * kb], nh[2 * kb + 1]), acc);
+      acc = mfma32(a, cat8(nl[2 * kb], nl[2 * kb + 1]), acc);
     }
     // acc[j] = d loss / d enc_k for k = ib*16 + 4q + j of ray r16
 #pragma unroll
