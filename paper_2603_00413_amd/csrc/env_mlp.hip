@@ -33,13 +33,6 @@ namespace {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ short f2bf(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (short)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
-
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
@@ -103,14 +96,21 @@ constexpr int mlp_threads() {
 // Layout of the LDS image of a (HID, NL) network: bf16 weights row by row with
 // padded row strides (layer 0: HID x (IN + 4); hidden layers: HID x (HID + 4);
 // head: 16 x (HID + 4), rows 3..15 zero), then FP32 biases (NL x HID, head 16).
-template <int HID, int NL>
+// For the backward, a 64-wide network also keeps transposed copies of its
+// hidden-layer and first weights ([in][out], stride HID + 4), so the W^T
+// operands are two 8-byte LDS reads instead of eight 2-byte ones; a 128-wide
+// one has no room.
+template <int HID, int NL, bool GRAD>
 struct NetLds {
+  static constexpr bool TRANS = GRAD && HID <= 64;
   static constexpr int LD0 = IN + 4;
   static constexpr int LDH = HID + 4;
   static constexpr int W0 = 0;
   static constexpr int WH = W0 + HID * LD0;
   static constexpr int WO = WH + (NL - 1) * HID * LDH;
-  static constexpr int WEND = WO + 16 * LDH;
+  static constexpr int T0 = WO + 16 * LDH;                            // W0^T: IN x LDH
+  static constexpr int TH = T0 + (TRANS ? IN * LDH : 0);              // W_L^T: HID x LDH each
+  static constexpr int WEND = TH + (TRANS ? (NL - 1) * HID * LDH : 0);
   static constexpr int BOFF = (WEND * 2 + 15) / 16 * 16;  // byte offset of the biases
   static constexpr int NB = NL * HID + 16;
   static constexpr int BYTES = BOFF + NB * 4;
@@ -119,16 +119,20 @@ struct NetLds {
 
 // Cooperative copy of the network (global layout: W[l] row-major [out][in],
 // biases concatenated) into its LDS image; ends with a barrier.
-template <int HID, int NL>
+template <int HID, int NL, bool GRAD>
 __device__ __forceinline__ void load_net(const EnvDev& e, uint16_t* sw, float* sb) {
-  using N = NetLds<HID, NL>;
+  using N = NetLds<HID, NL, GRAD>;
   const uint16_t* W = e.w;
-  for (int i = threadIdx.x; i < HID * IN; i += blockDim.x)
+  for (int i = threadIdx.x; i < HID * IN; i += blockDim.x) {
     sw[N::W0 + (i / IN) * N::LD0 + (i % IN)] = W[i];
+    if (N::TRANS) sw[N::T0 + (i % IN) * N::LDH + (i / IN)] = W[i];
+  }
   W += HID * IN;
   for (int l = 1; l < NL; ++l) {
-    for (int i = threadIdx.x; i < HID * HID; i += blockDim.x)
+    for (int i = threadIdx.x; i < HID * HID; i += blockDim.x) {
       sw[N::WH + (l - 1) * HID * N::LDH + (i / HID) * N::LDH + (i % HID)] = W[i];
+      if (N::TRANS) sw[N::TH + (l - 1) * HID * N::LDH + (i % HID) * N::LDH + (i / HID)] = W[i];
+    }
     W += HID * HID;
   }
   for (int i = threadIdx.x; i < 16 * HID; i += blockDim.x)
@@ -140,6 +144,23 @@ __device__ __forceinline__ void load_net(const EnvDev& e, uint16_t* sw, float* s
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// two-part bf16 split with rounding to nearest (ties to even) of both parts:
+// hi + lo carries about 17 significant bits of the value
+__device__ __forceinline__ short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+struct Split2 {
+  short h, l;
+};
+__device__ __forceinline__ Split2 split2(float v) {
+  Split2 s;
+  s.h = bf16_rne(v);
+  s.l = bf16_rne(v - __uint_as_float((uint32_t)(uint16_t)s.h << 16));
+  return s;
+}
 
 // K = 32 operand from two K = 16 halves: slots 0..3 take k = 4q + j of the
 // first 16-block, slots 4..7 k = 4q + j of the second.  A and B operands are
@@ -179,7 +200,7 @@ __device__ __forceinline__ bf16x8 wfrag_t(const uint16_t* w, int col, int ld, in
 template <int HID, int NL, bool GRAD>
 __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int n_freq, v3 d,
                                        v3 gbar, v3* dbar) {
-  using N = NetLds<HID, NL>;
+  using N = NetLds<HID, NL, GRAD>;
   const int l = threadIdx.x & 63, q = l >> 4, r16 = l & 15;
   constexpr int KB = HID / 16;
   float inv_len = 1.0f / sqrtf(dot(d, d));
@@ -270,9 +291,9 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
   {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float g0 = (q == 0 && j < 3) ? comp(gbar, j) : 0.f;
-      dh0[j] = f2bf(g0);
-      dl0[j] = f2bf(g0 - bf2f(dh0[j]));
+      Split2 p = split2((q == 0 && j < 3) ? comp(gbar, j) : 0.f);
+      dh0[j] = p.h;
+      dl0[j] = p.l;
     }
   }
   // head: delta_hidden = W_head^T delta_out (a K = 16 product over the 16
@@ -288,9 +309,9 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
     acc = mfma(a, dl0, acc);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float v = bf2f(act[NL - 1][ib][j]) > 0.f ? acc[j] : 0.f;
-      nh[ib][j] = f2bf(v);
-      nl[ib][j] = f2bf(v - bf2f(nh[ib][j]));
+      Split2 p = split2(act[NL - 1][ib][j] > 0 ? acc[j] : 0.f);
+      nh[ib][j] = p.h;
+      nl[ib][j] = p.l;
     }
   }
   // hidden layers NL-1 .. 1: delta_{L-1} = W_L^T delta_L, masked by relu'(layer L-1)
@@ -303,15 +324,19 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kb = 0; kb < KB / 2; ++kb) {
-        bf16x8 a = wfrag_t(WL, ib * 16 + r16, N::LDH, kb * 32, q);
+        bf16x8 a;
+        if constexpr (N::TRANS)
+          a = wfrag(sw + N::TH + (L - 1) * HID * N::LDH, ib * 16 + r16, N::LDH, kb * 32, q);
+        else
+          a = wfrag_t(WL, ib * 16 + r16, N::LDH, kb * 32, q);
         acc = mfma32(a, cat8(nh[2 * kb], nh[2 * kb + 1]), acc);
         acc = mfma32(a, cat8(nl[2 * kb], nl[2 * kb + 1]), acc);
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float v = bf2f(act[L - 1][ib][j]) > 0.f ? acc[j] : 0.f;
-        th[ib][j] = f2bf(v);
-        tl[ib][j] = f2bf(v - bf2f(th[ib][j]));
+        Split2 p = split2(act[L - 1][ib][j] > 0 ? acc[j] : 0.f);
+        th[ib][j] = p.h;
+        tl[ib][j] = p.l;
       }
     }
 #pragma unroll
@@ -327,7 +352,11 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < KB / 2; ++kb) {
-      bf16x8 a = wfrag_t(sw + N::W0, ib * 16 + r16, N::LD0, kb * 32, q);
+      bf16x8 a;
+      if constexpr (N::TRANS)
+        a = wfrag(sw + N::T0, ib * 16 + r16, N::LDH, kb * 32, q);
+      else
+        a = wfrag_t(sw + N::W0, ib * 16 + r16, N::LD0, kb * 32, q);
       acc = mfma32(a, cat8(nh[2 * kb], nh[2 * kb + 1]), acc);
       acc = mfma32(a, cat8(nl[2 * kb], nl[2 * kb + 1]), acc);
     }
@@ -352,12 +381,12 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
 // Every block loads the network into LDS once, then each of its waves takes
 // groups of 16 consecutive items in turn; items past the count run on a dummy
 // direction and write nothing.  The loops' trip counts are uniform per wave.
-#define DT_MLP_PROLOGUE                                                   \
-  using N = NetLds<HID, NL>;                                              \
+#define DT_MLP_PROLOGUE(GRAD)                                             \
+  using N = NetLds<HID, NL, GRAD>;                                        \
   __shared__ __align__(16) unsigned char net[N::BYTES];                  \
   uint16_t* sw = (uint16_t*)net;                                          \
   float* sb = (float*)(net + N::BOFF);                                    \
-  load_net<HID, NL>(e, sw, sb);                                           \
+  load_net<HID, NL, GRAD>(e, sw, sb);                                     \
   const int waves = mlp_threads<HID>() / 64;                              \
   const int64_t wstep = (int64_t)gridDim.x * waves * 16;                  \
   const int64_t wfirst = ((int64_t)blockIdx.x * waves + (threadIdx.x >> 6)) * 16;
@@ -374,7 +403,7 @@ __device__ __forceinline__ const uint16_t* per_group(const uint16_t* sw) {
 template <int HID, int NL>
 __global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_query(EnvDev e, const float* dirs, int64_t n,
                                                            float* rgb) {
-  DT_MLP_PROLOGUE
+  DT_MLP_PROLOGUE(false)
   for (int64_t w0 = wfirst; w0 < n; w0 += wstep) {
     int64_t item = w0 + (threadIdx.x & 15);
     bool valid = item < n;
@@ -392,7 +421,7 @@ __global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_query(EnvDev e, cons
 template <int HID, int NL>
 __global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_query_bwd(EnvDev e, const float* dirs, int64_t n,
                                                                const float* g, float* gd) {
-  DT_MLP_PROLOGUE
+  DT_MLP_PROLOGUE(true)
   for (int64_t w0 = wfirst; w0 < n; w0 += wstep) {
     int64_t item = w0 + (threadIdx.x & 15);
     bool valid = item < n;
@@ -411,7 +440,7 @@ __global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_query_bwd(EnvDev e, 
 template <int HID, int NL>
 __global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_trace_fwd(EnvDev e, Gen q, const uint32_t* list,
                                                                const Counters* ctr, int g, float* rgb) {
-  DT_MLP_PROLOGUE
+  DT_MLP_PROLOGUE(false)
   const int64_t n = ctr->nmiss[g];
   for (int64_t w0 = wfirst; w0 < n; w0 += wstep) {
     int64_t item = w0 + (threadIdx.x & 15);
@@ -434,7 +463,7 @@ template <int HID, int NL>
 __global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_trace_bwd(EnvDev e, Gen q, const uint32_t* list,
                                                                const Counters* ctr, int g,
                                                                const float* grad_rgb, Adj cur) {
-  DT_MLP_PROLOGUE
+  DT_MLP_PROLOGUE(true)
   const int64_t n = ctr->nmiss[g];
   for (int64_t w0 = wfirst; w0 < n; w0 += wstep) {
     int64_t item = w0 + (threadIdx.x & 15);
