@@ -45,8 +45,8 @@ MEASURED_TRAFFIC = {
     "k_trace": {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h"],
-        "sha256": "a91c85b7f3420ff5ebd3a4ed6e8f9844e5aefb255f2f37bb5d47518b51e8f83d",
-        "bytes": (360793.2 * 2.0 + 77157.2) * 1024,
+        "sha256": "9d69c440d01878a772ad373b3c2d6f27b28674d7ef41b9e4a008ab161067281d",
+        "bytes": (359865.2 * 2.0 + 77155.9) * 1024,
     },
 }
 
