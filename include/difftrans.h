@@ -256,7 +256,9 @@ typedef struct {            /* a request admitted by this step */
 dt_status dt_serve_bytes(int64_t queue_capacity, size_t* ws_bytes);
 /* Empty the queue (call once before the first step). */
 dt_status dt_serve_reset(void* ws, size_t ws_bytes, int64_t queue_capacity, void* stream);
-/* One step.  scenes, envs, admits: HOST arrays (equirect environments);
+/* One step.  scenes, envs, admits: HOST arrays (equirect or MLP environments;
+ * the misses lit by an MLP environment are listed and evaluated on the matrix
+ * cores after the trace, one environment at a time);
  * pixels: device pool [n_pixels][3] (an admitted request's image is cleared by
  * its admitting step, then accumulated into); slot_live: device
  * [DT_SERVE_MAX_SLOTS], overwritten with each slot's live rays after the step;

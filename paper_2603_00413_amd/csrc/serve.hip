@@ -46,7 +46,7 @@ struct ServeState {
 constexpr int SERVE_TRACE_BLOCKS = 256 * 4 * 7;
 
 struct ServeLayout {
-  size_t state, tables, part0, part1, q[2][3], hit, code, ovf, total;
+  size_t state, tables, part0, part1, q[2][3], hit, code, ovf, miss, total;
   int64_t cap, maxchunks;
 };
 
@@ -74,6 +74,8 @@ ServeLayout serve_layout(int64_t cap) {
   o = dt_align(o + 4 * (size_t)cap);
   L.ovf = o;
   o = dt_align(o + 8 * (size_t)SERVE_TRACE_BLOCKS * TBS * (DT_STACK - DT_STACK_LDS));
+  L.miss = o;  // misses lit by one MLP environment (rebuilt per environment)
+  o = dt_align(o + 4 * (size_t)cap);
   L.total = o;
   return L;
 }
@@ -159,11 +161,15 @@ __global__ void __launch_bounds__(TBS, 7) k_serve_trace(const ServeTables* T, Ge
       q.hit[i] = make_float4(h.t, __int_as_float(h.tri), h.b1, h.b2);
       uint32_t code = 0;
       if (h.tri < 0) {
+        // equirect lookups here; MLP-lit misses are listed per environment
+        // after the trace and evaluated on the matrix cores
         const EnvDev& env = T->env[sf_env(fl)];
-        v3 E = env_equirect(env, d);
-        atomicAdd(pixels + 3 * pix, W.x * E.x);
-        atomicAdd(pixels + 3 * pix + 1, W.y * E.y);
-        atomicAdd(pixels + 3 * pix + 2, W.z * E.z);
+        if (env.kind == DT_ENV_EQUIRECT) {
+          v3 E = env_equirect(env, d);
+          atomicAdd(pixels + 3 * pix, W.x * E.x);
+          atomicAdd(pixels + 3 * pix + 1, W.y * E.y);
+          atomicAdd(pixels + 3 * pix + 2, W.z * E.z);
+        }
       } else {
         HitGeo geo = load_geo(sc, h.tri);
         Shade s = shade(sc, geo, o, d, h.t, h.b1, h.b2, 0u);
@@ -186,6 +192,45 @@ __global__ void __launch_bounds__(TBS, 7) k_serve_trace(const ServeTables* T, Ge
       atomicAdd(part + base / DT_CHUNK,
                 (unsigned long long)__popcll(br) | ((unsigned long long)__popcll(bt) << 32));
   }
+}
+
+// Misses of the current queue lit by environment env, listed for the MLP
+// kernel: a block ranks its matches in LDS and reserves their slots with one
+// atomic on ctr.nmiss[0] (zeroed before each environment's pass).
+constexpr int SLB = 1024;
+
+__global__ void __launch_bounds__(SLB) k_serve_list_env(Gen q, ServeState* st, uint32_t env,
+                                                        uint32_t* list) {
+  __shared__ uint32_t wcount[SLB / 64];
+  __shared__ uint32_t bbase;
+  Counters* ctr = &st->ctr;
+  const uint32_t n = ctr->count[0];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t base = (int64_t)blockIdx.x * SLB; base < n; base += (int64_t)gridDim.x * SLB) {
+    int64_t i = base + threadIdx.x;
+    bool m = false;
+    if (i < n && !(q.code[i] & C_HIT))
+      m = sf_env((uint32_t)__float_as_int(q.w[i].w)) == env;
+    uint64_t bm = __ballot(m);
+    if (lane == 0) wcount[wave] = (uint32_t)__popcll(bm);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (int w = 0; w < SLB / 64; ++w) {
+        uint32_t c = wcount[w];
+        wcount[w] = tot;
+        tot += c;
+      }
+      bbase = tot ? atomicAdd(&ctr->nmiss[0], tot) : 0u;
+    }
+    __syncthreads();
+    if (m) list[bbase + wcount[wave] + (uint32_t)__popcll(bm & ((1ull << lane) - 1ull))] = (uint32_t)i;
+    __syncthreads();
+  }
+}
+
+__global__ void k_serve_zero_nmiss(ServeState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->ctr.nmiss[0] = 0;
 }
 
 __global__ void __launch_bounds__(EBS) k_serve_emit(const ServeTables* T, Gen q, Gen nx,
@@ -380,13 +425,8 @@ extern "C" dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scene
     d.terminal_env = 0;
     d.t_eps = t_eps;
   }
-  for (int i = 0; i < n_envs; ++i) {
+  for (int i = 0; i < n_envs; ++i)
     if (dt_status st = make_env(&envs[i], T.env[i])) return st;
-    if (T.env[i].kind != DT_ENV_EQUIRECT) {
-      dt_set_error("the server takes equirect environments (env %d is not)", i);
-      return DT_ERR_UNSUPPORTED;
-    }
-  }
   int64_t added = 0;
   for (int a = 0; a < n_admits; ++a) {
     const dt_serve_admit& ad = admits[a];
@@ -430,6 +470,16 @@ extern "C" dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scene
   // one interaction for every live ray
   hipLaunchKernelGGL(k_serve_trace, dim3(grid_for(L.cap, TBS, SERVE_TRACE_BLOCKS)), dim3(TBS), 0, s,
                      Td, qc, st, part[cur], pixels, (uint2*)(W + L.ovf));
+  // MLP environments: list each one's misses, evaluate them on the matrix cores
+  for (int e = 0; e < n_envs; ++e) {
+    if (T.env[e].kind != DT_ENV_MLP) continue;
+    uint32_t* list = (uint32_t*)(W + L.miss);
+    hipLaunchKernelGGL(k_serve_zero_nmiss, dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL(k_serve_list_env, dim3(grid_for(L.cap, SLB, 2048)), dim3(SLB), 0, s, qc, st,
+                       (uint32_t)e, list);
+    DT_CHECK_LAUNCH();
+    if (dt_status er = mlp_trace_forward(T.env[e], qc, list, &st->ctr, 0, L.cap, pixels, s)) return er;
+  }
   if (dt_status e = chunk_scan(&st->ctr, 0, part[cur], part[nxt], L.maxchunks + 1, L.cap, s)) return e;
   hipLaunchKernelGGL(k_serve_emit, dim3((unsigned)L.maxchunks), dim3(EBS), 0, s, Td, qc, qn, st,
                      part[cur], L.cap);

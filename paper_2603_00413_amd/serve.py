@@ -119,13 +119,18 @@ class Server:
         self._keep = []
 
     # ------------------------------------------------------------ resident data
-    def add_env(self, texels: np.ndarray) -> int:
+    def add_env(self, env) -> int:
+        """env: equirect texels [H, W, 3] (numpy), or a binding Env (map or MLP)
+        already on this device."""
         if len(self.envs) >= MAX_ENVS:
             raise B.DTError("too many environments")
-        self.envs.append(B.Env(torch.from_numpy(np.ascontiguousarray(texels, np.float32)).to(self.dev)))
+        if not isinstance(env, B.Env):
+            env = B.Env(torch.from_numpy(np.ascontiguousarray(env, np.float32)).to(self.dev))
+        self.envs.append(env)
         return len(self.envs) - 1
 
     def add_scene(self, V, F, ior, sigma, env_texels) -> int:
+        """env_texels: the scene's own environment, as for add_env."""
         if len(self.scenes) >= MAX_SCENES:
             raise B.DTError("too many scenes")
         mesh = B.Mesh(torch.from_numpy(np.asarray(V, np.float32)).to(self.dev),

@@ -77,3 +77,39 @@ def test_admission_waits_for_memory():
     assert not (big[0].admitted < big[1].finished and big[1].admitted < big[0].finished)
     ref = srv.run([_requests(relight)[2]], realtime=False)[0]
     assert _rel(ref.image, reqs[2].image) <= 1e-6
+
+
+def test_mlp_environment_requests():
+    """Requests lit by MLP environments (a scene's own and a relight target)
+    mixed with map-lit ones: each image equals the plain tracer's and its own
+    render alone, within 1e-6 relative."""
+    dev = device()
+    srv = Server(queue_capacity=1 << 20, pixel_pool=1 << 20)
+    V1, F1 = synth.icosphere(3)
+    V2, F2 = synth.displaced_torus(seed=5, nu=120, nv=60)
+    W64, B64 = synth.env_mlp_weights(seed=3, n_layers=3, width=64)
+    W128, B128 = synth.env_mlp_weights(seed=5, n_layers=2, width=128)
+    srv.add_scene(V1, F1, 1.5, (0.5, 0.2, 0.1), B.Env.mlp(W64, B64, 6, dev))
+    srv.add_scene(V2, F2, 1.45, 0.3, synth.env_equirect(128, 64, seed=2))
+    relight = srv.add_env(B.Env.mlp(W128, B128, 6, dev))
+    eyes = synth.views_on_sphere(5, 3.0, seed=13)
+    spec = [(0, 40, 5, None), (1, 48, 6, relight), (0, 32, 4, relight), (1, 56, 7, None),
+            (0, 24, 3, None)]
+
+    def reqs():
+        return [Request(k, sc, synth.look_at_camera(eyes[k], res, res), dep, env,
+                        arrival=1e-4 * (k // 2))
+                for k, (sc, res, dep, env) in enumerate(spec)]
+
+    mixed = srv.run(reqs(), realtime=False)
+    assert srv.dropped == 0
+    for m in mixed:
+        assert np.isfinite(m.image).all() and np.abs(m.image).max() > 0
+    for r in reqs():
+        alone = srv.run([r], realtime=False)[0]
+        _print("mlp request", r.rid, "alone vs mix", _rel(alone.image, mixed[r.rid].image))
+        assert _rel(alone.image, mixed[r.rid].image) <= 1e-6
+    fifo, _ = run_fifo(srv, reqs(), realtime=False)
+    for f in fifo:
+        _print("mlp request", f.rid, "plain vs server", _rel(f.image, mixed[f.rid].image))
+        assert _rel(f.image, mixed[f.rid].image) <= 1e-6
