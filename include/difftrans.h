@@ -80,7 +80,7 @@ typedef int32_t dt_status;
 /* ------------------------------------------------------------------ mesh */
 
 /* Size of the caller-owned acceleration-structure blob and of the build
- * workspace for a mesh of nv vertices and nf faces (nv >= 3, nf >= 1). */
+ * workspace for a mesh of nv vertices and nf faces (nv >= 3, 1 <= nf <= 2^26). */
 dt_status dt_bvh_bytes(int32_t nv, int32_t nf, size_t* bvh_bytes, size_t* ws_bytes);
 
 /* Build the scene acceleration data from V [nv][3] and F [nf][3]: unit face

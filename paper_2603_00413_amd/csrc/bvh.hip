@@ -637,7 +637,7 @@ dt_status dt_scan_exclusive_i32(const int32_t* in, int32_t* out, int32_t n, int3
 // ------------------------------------------------------------------ C ABI
 extern "C" dt_status dt_bvh_bytes(int32_t nv, int32_t nf, size_t* bvh_bytes, size_t* ws_bytes) {
   DT_REQUIRE(nv >= 3 && nf >= 1, "dt_bvh_bytes: need nv >= 3 and nf >= 1 (got %d, %d)", nv, nf);
-  DT_REQUIRE(nf < (1 << 30) && nv < (1 << 30), "dt_bvh_bytes: mesh too large");
+  DT_REQUIRE(nf <= DT_MAX_FACES && nv < (1 << 30), "dt_bvh_bytes: mesh too large (at most 2^26 triangles)");
   DT_REQUIRE(bvh_bytes && ws_bytes, "dt_bvh_bytes: null output pointer");
   *bvh_bytes = bvh_layout(nv, nf).total;
   Carver c(nullptr, 0);
@@ -650,7 +650,7 @@ extern "C" dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, 
                                   void* stream) {
   DT_REQUIRE(V && F && bvh && ws, "dt_build_bvh: null pointer argument");
   DT_REQUIRE(nv >= 3 && nf >= 1, "dt_build_bvh: need nv >= 3 and nf >= 1 (got %d, %d)", nv, nf);
-  DT_REQUIRE(nf < (1 << 30) && nv < (1 << 30), "dt_build_bvh: mesh too large");
+  DT_REQUIRE(nf <= DT_MAX_FACES && nv < (1 << 30), "dt_build_bvh: mesh too large (at most 2^26 triangles)");
   BvhLayout L = bvh_layout(nv, nf);
   if (bvh_bytes < L.total) {
     dt_set_error("dt_build_bvh: bvh blob has %zu bytes, needs %zu", bvh_bytes, L.total);

@@ -184,23 +184,6 @@ __device__ __forceinline__ bool tri_test(const RayPre& r, v3 a, v3 b, v3 c, int 
   return true;
 }
 
-// robust slab test against one child box; returns entry distance or +inf
-__device__ __forceinline__ float box_enter(const RayPre& r, float lx, float ly, float lz, float hx,
-                                           float hy, float hz, float tmax) {
-  float t0x = (lx - r.o.x) * r.inv.x, t1x = (hx - r.o.x) * r.inv.x;
-  float t0y = (ly - r.o.y) * r.inv.y, t1y = (hy - r.o.y) * r.inv.y;
-  float t0z = (lz - r.o.z) * r.inv.z, t1z = (hz - r.o.z) * r.inv.z;
-  float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
-  float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
-  // each slab distance carries three roundings (difference, reciprocal,
-  // product), a relative error of at most gamma_3 = 3u / (1 - 3u), u = 2^-24;
-  // widening the exit distance by 1 + 2 gamma_3 (< 1.0000008) keeps every box
-  // the exact ray enters (so no triangle the triangle test would accept, ties
-  // included, is pruned)
-  tf *= 1.0000008f;
-  return tn <= tf ? tn : INFINITY;
-}
-
 #define DT_STACK 64       // total stack entries per lane (LDS part + global overflow part)
 #define DT_STACK_LDS 8    // entries kept in LDS by the traversal kernels (4 KB per wave)
 
@@ -248,12 +231,13 @@ __device__ __forceinline__ void trav_init(Trav& s, const BvhView& bv, v3 o, v3 d
 }
 
 // One step: visit the current node and choose the next one (or finish).
-template <int SL, bool GLOBAL>
-__device__ __forceinline__ void trav_step(Trav& s, const BvhView& bv, float t_eps, uint2* stk,
-                                          int stride, uint2* gstk, int gcap) {
+// leaf(k, j) receives each leaf child k (leaf index j) whose box the ray
+// enters, in child order.
+template <int SL, bool GLOBAL, class LeafFn>
+__device__ __forceinline__ void trav_visit(Trav& s, const BvhView& bv, uint2* stk, int stride,
+                                           uint2* gstk, int gcap, LeafFn&& leaf) {
   const uint32_t cap4 = (uint32_t)bvh4_cap(bv.nf);
   const uint32_t lmax = (uint32_t)(bv.nf - 1);
-  const float4* L = bv.leaves;
   // a depth-first walk visits each 4-wide node at most once
   if (s.node >= cap4 || ++s.steps > cap4 + 64) {
     s.overflow = true;
@@ -272,12 +256,6 @@ __device__ __forceinline__ void trav_step(Trav& s, const BvhView& bv, float t_ep
       s.overflow = true;
     }
   };
-  auto leaf = [&](uint32_t c) {
-    uint32_t j = min(c & ~DT_LEAF_BIT, lmax);
-    float4 p0 = L[3 * j];
-    int f = __float_as_int(p0.w);
-    if (f != s.skip) tri_test(s.r, xyz(p0), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), f, t_eps, s.h);
-  };
   const Bvh4Node& n = bv.nodes4[s.node];
   const float4 org = n.org;
   const uint4 ql = n.qlo, qh = n.qhi, cc = n.child;
@@ -286,26 +264,51 @@ __device__ __forceinline__ void trav_step(Trav& s, const BvhView& bv, float t_ep
   const float sx = __uint_as_float((uint32_t)((int)(int8_t)(eb & 0xFFu) + 127) << 23);
   const float sy = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 8) & 0xFFu) + 127) << 23);
   const float sz = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 16) & 0xFFu) + 127) << 23);
-  float tmax = s.h.tri >= 0 ? s.h.t : INFINITY;
+  // widened like the exit distances (the closest hit's t carries rounding
+  // too, and boxes entered at exactly that t must stay in play for ties)
+  const float tmaxw = (s.h.tri >= 0 ? s.h.t : INFINITY) * 1.0000008f;
+  // Slab distances straight from the codes: the plane p + q s lies at
+  // t(q) = (p + q s - o) inv = q a + b with a = s inv (exact, s is a power of
+  // two) and b = (p - o) inv, one fused multiply-add per plane.  Against the
+  // exact (p + q s - o) / d the computed value is off by at most about
+  // 6u (255 |a| + |b|), u = 2^-24 (the roundings of b, of inv, of the fma);
+  // each axis's near planes are lowered and far planes raised by
+  // 8u (255 |a| + |b|), so near and far distances bound the exact ones from
+  // below and above and no box the exact ray enters before the closest hit is
+  // rejected.  The near face per axis follows the sign of inv.
+  const float ax = sx * s.r.inv.x, ay = sy * s.r.inv.y, az = sz * s.r.inv.z;
+  const float bx = (org.x - s.r.o.x) * s.r.inv.x;
+  const float by = (org.y - s.r.o.y) * s.r.inv.y;
+  const float bz = (org.z - s.r.o.z) * s.r.inv.z;
+  const float ex = 0x1p-21f * fmaf(255.f, fabsf(ax), fabsf(bx));
+  const float ey = 0x1p-21f * fmaf(255.f, fabsf(ay), fabsf(by));
+  const float ez = 0x1p-21f * fmaf(255.f, fabsf(az), fabsf(bz));
+  const float bnx = bx - ex, bfx = bx + ex, bny = by - ey, bfy = by + ey, bnz = bz - ez, bfz = bz + ez;
+  const bool px = s.r.inv.x >= 0.f, py = s.r.inv.y >= 0.f, pz = s.r.inv.z >= 0.f;
+  const uint32_t nqx = px ? ql.x : qh.x, fqx = px ? qh.x : ql.x;
+  const uint32_t nqy = py ? ql.y : qh.y, fqy = py ? qh.y : ql.y;
+  const uint32_t nqz = pz ? ql.z : qh.z, fqz = pz ? qh.z : ql.z;
   float t[4];
   uint32_t c[4] = {cc.x, cc.y, cc.z, cc.w};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int sh = 8 * k;
-    float lox = org.x + (float)((ql.x >> sh) & 0xFFu) * sx;
-    float loy = org.y + (float)((ql.y >> sh) & 0xFFu) * sy;
-    float loz = org.z + (float)((ql.z >> sh) & 0xFFu) * sz;
-    float hix = org.x + (float)((qh.x >> sh) & 0xFFu) * sx;
-    float hiy = org.y + (float)((qh.y >> sh) & 0xFFu) * sy;
-    float hiz = org.z + (float)((qh.z >> sh) & 0xFFu) * sz;
-    t[k] = box_enter(s.r, lox, loy, loz, hix, hiy, hiz, tmax);
+    const float tnx = fmaf((float)((nqx >> sh) & 0xFFu), ax, bnx);
+    const float tny = fmaf((float)((nqy >> sh) & 0xFFu), ay, bny);
+    const float tnz = fmaf((float)((nqz >> sh) & 0xFFu), az, bnz);
+    const float tfx = fmaf((float)((fqx >> sh) & 0xFFu), ax, bfx);
+    const float tfy = fmaf((float)((fqy >> sh) & 0xFFu), ay, bfy);
+    const float tfz = fmaf((float)((fqz >> sh) & 0xFFu), az, bfz);
+    const float tn = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, 0.0f));
+    const float tf = fminf(fminf(tfx, tfy), fminf(tfz, tmaxw));
+    t[k] = tn <= tf ? tn : INFINITY;
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (c[k] == DT_NO_CHILD) {
       t[k] = INFINITY;
     } else if (t[k] != INFINITY && (c[k] & DT_LEAF_BIT)) {
-      leaf(c[k]);
+      leaf(k, min(c[k] & ~DT_LEAF_BIT, lmax));
       t[k] = INFINITY;
     }
   }
@@ -349,16 +352,144 @@ __device__ __forceinline__ void trav_step(Trav& s, const BvhView& bv, float t_ep
   s.done = true;
 }
 
-// Closest hit of one ray (the whole traversal in one call).
-template <int SL, bool GLOBAL>
-__device__ __forceinline__ Hit closest_hit(const BvhView& bv, v3 o, v3 d, int skip, float t_eps,
-                                           uint2* stk, int stride, uint2* gstk, int gcap,
-                                           bool* overflow) {
+// Closest hits of a wave's 64 rays, leaf tests batched across the wave.
+//
+// A lane's ray visits nodes as in trav_visit, but the leaf children it enters
+// are not tested in place: a node yields 0-4 of them per lane, so per-child
+// tests would run with a handful of the 64 lanes busy.  Instead each candidate
+// (leaf index << 6 | lane) goes into a wave-wide LDS queue, and whenever the
+// queue holds a full round every lane takes one entry, fetches the owner's
+// ray-space constants with cross-lane reads, and runs the triangle test.  A
+// hit meets the owner's best so far as the 64-bit key (t bits << 32 | id),
+// min-reduced with an LDS atomic: t > 0, so its bit pattern orders like the
+// value, and equal t resolves to the smaller id as in tri_test.  The winning
+// leaf is noted, and its test is rerun by the owner at the end for the
+// barycentrics (the same function on the same operands: bit-identical t).
+// Traversal prunes with the best t as of the last round, which is never below
+// the final one, so the result is the exact closest hit as before.
+//
+// Every lane of the wave must call this together (active = false for lanes
+// without a ray).  SCENE_PER_LANE: lanes may trace different scenes (the
+// owner's leaf array and t_eps travel with the candidate).
+#define DT_LQ_CAP 192
+struct LeafQueue {
+  uint32_t req[DT_LQ_CAP];       // (leaf << 6) | owner lane
+  unsigned long long best[64];   // per owner: (t bits << 32) | triangle id
+  uint32_t win[64];              // per owner: leaf of the best key
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int SL, bool GLOBAL, bool SCENE_PER_LANE>
+__device__ __forceinline__ Hit closest_hit_wave(const BvhView& bv, bool active, v3 o, v3 d,
+                                                int skip, float t_eps, uint2* stk, int stride,
+                                                uint2* gstk, int gcap, LeafQueue& lq,
+                                                bool* overflow) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const uint64_t lt = (1ull << lane) - 1ull;
   Trav s;
   trav_init(s, bv, o, d, skip, t_eps);
-  while (!s.done) trav_step<SL, GLOBAL>(s, bv, t_eps, stk, stride, gstk, gcap);
+  if (!active) s.done = true;
+  lq.best[lane] = ~0ull;
+  bool queued = false;  // this lane's best came from the queue
+  uint32_t qn = 0;      // queue fill (wave-uniform)
+  const int kpack = s.r.kx | (s.r.ky << 2) | (s.r.kz << 4);
+  const uint64_t lptr = (uint64_t)(uintptr_t)bv.leaves;
+
+  auto rounds = [&](uint32_t thresh) {
+    while (qn >= thresh && qn > 0u) {
+      const uint32_t take = qn < 64u ? qn : 64u;
+      qn -= take;
+      wave_lds_sync();
+      const bool has = (uint32_t)lane < take;
+      const uint32_t rq = has ? lq.req[qn + (uint32_t)lane] : 0u;
+      const int ow = (int)(rq & 63u);
+      RayPre r;
+      r.o = mk3(__shfl(s.r.o.x, ow), __shfl(s.r.o.y, ow), __shfl(s.r.o.z, ow));
+      r.Sx = __shfl(s.r.Sx, ow);
+      r.Sy = __shfl(s.r.Sy, ow);
+      r.Sz = __shfl(s.r.Sz, ow);
+      const int kp = __shfl(kpack, ow);
+      r.kx = kp & 3;
+      r.ky = (kp >> 2) & 3;
+      r.kz = (kp >> 4) & 3;
+      const int sk = __shfl(s.skip, ow);
+      const float4* L = bv.leaves;
+      float te = t_eps;
+      if constexpr (SCENE_PER_LANE) {
+        const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)lptr, ow);
+        const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(lptr >> 32), ow);
+        L = (const float4*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+        te = __shfl(t_eps, ow);
+      }
+      if (has) {
+        const uint32_t j = rq >> 6;
+        const float4 p0 = L[3 * j], p1 = L[3 * j + 1], p2 = L[3 * j + 2];
+        const int f = __float_as_int(p0.w);
+        Hit h;
+        h.tri = -1;
+        h.t = INFINITY;
+        if (f != sk && tri_test(r, xyz(p0), xyz(p1), xyz(p2), f, te, h)) {
+          const unsigned long long key =
+              ((unsigned long long)__float_as_uint(h.t) << 32) | (unsigned long long)(uint32_t)f;
+          atomicMin(&lq.best[ow], key);
+          wave_lds_sync();
+          if (lq.best[ow] == key) lq.win[ow] = j;
+        }
+      }
+    }
+    wave_lds_sync();
+    const unsigned long long kb = lq.best[lane];
+    if (kb != ~0ull) {
+      s.h.t = __uint_as_float((uint32_t)(kb >> 32));
+      s.h.tri = (int)(uint32_t)kb;
+      queued = true;
+    }
+  };
+
+  uint32_t lf[4] = {0u, 0u, 0u, 0u};
+  uint32_t lm = 0u;
+  auto append = [&](int k) {
+    const bool m = (lm >> k) & 1u;
+    const uint64_t b = __ballot(m);
+    if (m) lq.req[qn + (uint32_t)__popcll(b & lt)] = (lf[k] << 6) | (uint32_t)lane;
+    qn += (uint32_t)__popcll(b);
+  };
+
+  while (__ballot(!s.done) != 0ull) {
+    lm = 0u;
+    if (!s.done)
+      trav_visit<SL, GLOBAL>(s, bv, stk, stride, gstk, gcap, [&](int k, uint32_t j) {
+        lf[k] = j;
+        lm |= 1u << k;
+      });
+    // at most 63 + 2 * 64 entries are held at any time
+    append(0);
+    append(1);
+    rounds(64u);
+    append(2);
+    append(3);
+    rounds(64u);
+  }
+  rounds(1u);
   if (s.overflow) *overflow = true;
-  return s.h;
+  Hit h = s.h;
+  if (queued) {
+    const float4* L = bv.leaves;
+    const uint32_t j = lq.win[lane];
+    const float4 p0 = L[3 * j];
+    Hit r;
+    r.tri = -1;
+    r.t = INFINITY;
+    r.b1 = r.b2 = 0.f;
+    tri_test(s.r, xyz(p0), xyz(L[3 * j + 1]), xyz(L[3 * j + 2]), __float_as_int(p0.w), t_eps, r);
+    h.b1 = r.b1;
+    h.b2 = r.b2;
+  }
+  return h;
 }
 
 // brute force over every triangle with the same predicate

@@ -64,6 +64,9 @@ __device__ __forceinline__ v3 load3(const float* p) { return {p[0], p[1], p[2]};
 // A child reference >= 0 is an internal node; (leaf | LEAF_BIT) is a leaf,
 // leaf j being the j-th triangle in Morton order.
 #define DT_LEAF_BIT 0x80000000u
+// largest triangle count: the wave traversal packs (leaf index << 6 | lane)
+// into 32 bits
+#define DT_MAX_FACES (1 << 26)
 
 struct __align__(16) BvhNode {
   float4 a;  // lo0.x lo0.y lo0.z hi0.x

@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(TBS, 7) k_serve_trace(const ServeTables* T, Ge
                                                      unsigned long long* part, float* pixels,
                                                      uint2* ovf) {
   __shared__ uint2 stk[DT_STACK_LDS * TBS];
+  __shared__ LeafQueue lq;
   uint2* gstk = ovf + (size_t)(blockIdx.x * TBS + threadIdx.x) * (DT_STACK - DT_STACK_LDS);
   Counters* ctr = &st->ctr;
   const uint32_t n = ctr->count[0];
@@ -147,17 +148,29 @@ __global__ void __launch_bounds__(TBS, 7) k_serve_trace(const ServeTables* T, Ge
     base = (uint32_t)__shfl((int)base, 0);
     if (base >= n) break;
     uint32_t i = base + lane;
+    const bool active = i < n;
     bool has_r = false, has_t = false;
-    if (i < n) {
-      float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i];
+    float4 o4 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), d4 = make_float4(0.f, 0.f, 1.f, 0.f);
+    if (active) {
+      o4 = q.o[i];
+      d4 = q.d[i];
+    }
+    // lanes without a ray take scene 0's tree (they only ride along)
+    uint32_t fl = active ? (uint32_t)__float_as_int(q.w[i].w) : 0u;
+    const SceneDev& sc = T->sc[sf_scene(fl)];
+    bool ovf = false;
+    const Hit h = closest_hit_wave<DT_STACK_LDS, true, true>(sc.bvh, active, xyz(o4), xyz(d4),
+                                                             __float_as_int(o4.w), sc.t_eps,
+                                                             stk + threadIdx.x, TBS, gstk,
+                                                             DT_STACK - DT_STACK_LDS, lq, &ovf);
+    if (active) {
+      // reloaded rather than kept in registers through the traversal
+      o4 = q.o[i];
+      d4 = q.d[i];
+      const float4 w4 = q.w[i];
+      fl = (uint32_t)__float_as_int(w4.w);
       v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
-      int skip = __float_as_int(o4.w);
       int pix = __float_as_int(d4.w);
-      uint32_t fl = (uint32_t)__float_as_int(w4.w);
-      const SceneDev& sc = T->sc[sf_scene(fl)];
-      bool ovf = false;
-      Hit h = closest_hit<DT_STACK_LDS, true>(sc.bvh, o, d, skip, sc.t_eps, stk + threadIdx.x, TBS, gstk,
-                                        DT_STACK - DT_STACK_LDS, &ovf);
       q.hit[i] = make_float4(h.t, __int_as_float(h.tri), h.b1, h.b2);
       uint32_t code = 0;
       if (h.tri < 0) {
@@ -411,7 +424,7 @@ extern "C" dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scene
   for (int i = 0; i < n_scenes; ++i) {
     const dt_serve_scene& s = scenes[i];
     DT_REQUIRE(s.V && s.F && s.bvh && s.ior && s.sigma && s.nv >= 3 && s.nf >= 1 &&
-                   s.nf < (1 << 30),
+                   s.nf <= DT_MAX_FACES,
                "scene %d has a NULL pointer or a bad size", i);
     SceneDev& d = T.sc[i];
     d.V = s.V;

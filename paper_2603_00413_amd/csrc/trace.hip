@@ -257,6 +257,7 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
                                               int32_t* flags, unsigned long long* sig,
                                               int accumulate, uint2* ovf) {
   __shared__ uint2 stk[DT_STACK_LDS * TB];
+  __shared__ LeafQueue lq;
   uint2* gstk = ovf + (size_t)(blockIdx.x * TB + threadIdx.x) * (DT_STACK - DT_STACK_LDS);
   const uint32_t n = ctr->count[g];
   const int lane = threadIdx.x & 63;
@@ -268,15 +269,24 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
     uint32_t i = base + lane;
     bool active = i < n;
     bool has_r = false, has_t = false, hit = false;
+    float4 o4 = make_float4(0.f, 0.f, 0.f, __int_as_float(-1)), d4 = make_float4(0.f, 0.f, 1.f, 0.f);
     if (active) {
-      float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i];
+      o4 = q.o[i];
+      d4 = q.d[i];
+    }
+    bool ovf = false;
+    const Hit h = closest_hit_wave<DT_STACK_LDS, true, false>(sc.bvh, active, xyz(o4), xyz(d4),
+                                                              __float_as_int(o4.w), sc.t_eps,
+                                                              stk + threadIdx.x, TB, gstk,
+                                                              DT_STACK - DT_STACK_LDS, lq, &ovf);
+    if (active) {
+      // reloaded rather than kept in registers through the traversal
+      o4 = q.o[i];
+      d4 = q.d[i];
+      const float4 w4 = q.w[i];
       v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
-      int skip = __float_as_int(o4.w);
       int pix = __float_as_int(d4.w);
       uint32_t rfl = (uint32_t)__float_as_int(w4.w);
-      bool ovf = false;
-      Hit h = closest_hit<DT_STACK_LDS, true>(sc.bvh, o, d, skip, sc.t_eps, stk + threadIdx.x, TB, gstk,
-                                        DT_STACK - DT_STACK_LDS, &ovf);
       q.hit[i] = make_float4(h.t, __int_as_float(h.tri), h.b1, h.b2);
       uint32_t code = 0;
       int pf = ovf ? DT_FLAG_STACK : 0;
@@ -867,14 +877,25 @@ __global__ void __launch_bounds__(TB) k_intersect(BvhView bv, const float* o, co
                                                   const int32_t* skip, int64_t n, float t_eps,
                                                   int brute, int32_t* tri, float* t, float* b) {
   __shared__ uint2 stk[DT_STACK * TB];
+  __shared__ LeafQueue lq;
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  v3 oo = load3(o + 3 * i), dd = load3(d + 3 * i);
-  int sk = skip ? skip[i] : -1;
+  if (brute) {
+    if (i >= n) return;
+  }
+  const bool active = i < n;
+  v3 oo = mk3(0.f, 0.f, 0.f), dd = mk3(0.f, 0.f, 1.f);
+  int sk = -1;
+  if (active) {
+    oo = load3(o + 3 * i);
+    dd = load3(d + 3 * i);
+    sk = skip ? skip[i] : -1;
+  }
   bool ovf = false;
+  // the wave traversal needs every lane of the block's wave
   Hit h = brute ? closest_brute(bv, oo, dd, sk, t_eps)
-                : closest_hit<DT_STACK, false>(bv, oo, dd, sk, t_eps, stk + threadIdx.x, TB, nullptr, 0,
-                                        &ovf);
+                : closest_hit_wave<DT_STACK, false, false>(bv, active, oo, dd, sk, t_eps,
+                                                           stk + threadIdx.x, TB, nullptr, 0, lq, &ovf);
+  if (!active) return;
   tri[i] = ovf ? -2 : h.tri;
   t[i] = h.t;
   b[2 * i] = h.b1;
@@ -886,8 +907,8 @@ dt_status make_scene(const dt_scene* sc, const dt_trace_params* p, SceneDev& s) 
   DT_REQUIRE(sc && p, "scene or params is NULL");
   DT_REQUIRE(sc->V && sc->F && sc->bvh && sc->ior && sc->sigma && sc->env,
              "scene has a NULL pointer (V, F, bvh, ior, sigma, env)");
-  DT_REQUIRE(sc->nv >= 3 && sc->nf >= 1 && sc->nf < (1 << 30) && sc->nv < (1 << 30),
-             "scene needs nv >= 3 and 1 <= nf < 2^30 (got %d, %d)", sc->nv, sc->nf);
+  DT_REQUIRE(sc->nv >= 3 && sc->nf >= 1 && sc->nf <= DT_MAX_FACES && sc->nv < (1 << 30),
+             "scene needs nv >= 3 and 1 <= nf <= 2^26 (got %d, %d)", sc->nv, sc->nf);
   DT_REQUIRE(p->max_depth >= 0 && p->max_depth <= DT_MAX_DEPTH, "max_depth must be in [0, %d]",
              DT_MAX_DEPTH);
   DT_REQUIRE(p->t_eps >= 0.f && p->t_eps < 1.f, "t_eps must be in [0, 1)");
@@ -1324,7 +1345,8 @@ extern "C" dt_status dt_intersect(const dt_scene* scene, const float* o, const f
                                   const int32_t* skip, int64_t n, float t_eps, int32_t brute_force,
                                   int32_t* tri, float* t, float* b, void* stream) {
   DT_REQUIRE(scene && scene->bvh && o && d && tri && t && b, "dt_intersect: NULL argument");
-  DT_REQUIRE(scene->nv >= 3 && scene->nf >= 1, "dt_intersect: bad mesh size");
+  DT_REQUIRE(scene->nv >= 3 && scene->nf >= 1 && scene->nf <= DT_MAX_FACES,
+             "dt_intersect: bad mesh size");
   DT_REQUIRE(n >= 0 && n < (1ll << 31), "dt_intersect: bad ray count");
   if (n == 0) return DT_OK;
   BvhView bv = bvh_view(scene->bvh, scene->nv, scene->nf);
