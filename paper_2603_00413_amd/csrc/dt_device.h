@@ -187,17 +187,16 @@ __device__ __forceinline__ bool tri_test(const RayPre& r, v3 a, v3 b, v3 c, int 
 #define DT_STACK 64       // total stack entries per lane (LDS part + global overflow part)
 #define DT_STACK_LDS 8    // entries kept in LDS by the traversal kernels (4 KB per wave)
 
-// Closest-hit traversal of the 4-wide tree as a resumable per-lane state, so
-// that a kernel can advance many rays one node at a time and hand a lane a new
-// ray as soon as its current one finishes.  The stack holds (node, entry
-// distance) pairs: the first SL entries in LDS (stk points at this lane's
-// column, stride entries apart), deeper ones in this lane's global overflow
-// area gstk (gcap entries; may be NULL when GLOBAL is false).  At a node, leaf
-// children are tested at once; the internal children whose boxes the ray
-// enters are ordered by entry distance, the nearest is visited next and the
-// others are pushed, farthest first.  A popped subtree whose box is entered
-// beyond the closest hit found since it was pushed is skipped without fetching
-// its node.  overflow is set if the stack would overflow (the result is then
+// Closest-hit traversal of the 4-wide tree as a resumable per-lane state,
+// advanced one node at a time.  The stack holds (node, entry distance) pairs:
+// the first SL entries in LDS (stk points at this lane's column, stride
+// entries apart), deeper ones in this lane's global overflow area gstk (gcap
+// entries; may be NULL when GLOBAL is false).  At a node, the leaf children
+// whose boxes the ray enters are handed back for testing; the internal ones
+// are ordered by entry distance, the nearest is visited next and the others
+// are pushed, farthest first.  A popped subtree whose box is entered beyond
+// the closest hit known when it is popped is skipped without fetching its
+// node.  overflow is set if the stack would overflow (the result is then
 // incomplete and flagged).
 struct Trav {
   RayPre r;
@@ -231,11 +230,11 @@ __device__ __forceinline__ void trav_init(Trav& s, const BvhView& bv, v3 o, v3 d
 }
 
 // One step: visit the current node and choose the next one (or finish).
-// leaf(k, j) receives each leaf child k (leaf index j) whose box the ray
-// enters, in child order.
-template <int SL, bool GLOBAL, class LeafFn>
+// Bit k of lm is set for each leaf child k whose box the ray enters, with its
+// leaf index in lf[k]; those are left to the caller to test.
+template <int SL, bool GLOBAL>
 __device__ __forceinline__ void trav_visit(Trav& s, const BvhView& bv, uint2* stk, int stride,
-                                           uint2* gstk, int gcap, LeafFn&& leaf) {
+                                           uint2* gstk, int gcap, uint32_t& lm, uint32_t* lf) {
   const uint32_t cap4 = (uint32_t)bvh4_cap(bv.nf);
   const uint32_t lmax = (uint32_t)(bv.nf - 1);
   // a depth-first walk visits each 4-wide node at most once
@@ -303,14 +302,14 @@ __device__ __forceinline__ void trav_visit(Trav& s, const BvhView& bv, uint2* st
     const float tf = fminf(fminf(tfx, tfy), fminf(tfz, tmaxw));
     t[k] = tn <= tf ? tn : INFINITY;
   }
+  // branch-free split of the entered children into leaves and internal nodes
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (c[k] == DT_NO_CHILD) {
-      t[k] = INFINITY;
-    } else if (t[k] != INFINITY && (c[k] & DT_LEAF_BIT)) {
-      leaf(k, min(c[k] & ~DT_LEAF_BIT, lmax));
-      t[k] = INFINITY;
-    }
+    const bool entered = c[k] != DT_NO_CHILD && t[k] != INFINITY;
+    const bool is_leaf = entered && (c[k] & DT_LEAF_BIT) != 0u;
+    lf[k] = min(c[k] & ~DT_LEAF_BIT, lmax);
+    lm |= is_leaf ? (1u << k) : 0u;
+    t[k] = entered && !is_leaf ? t[k] : INFINITY;
   }
   // order the entered internal children by entry distance (sorting network)
 #define DT_CSWAP(i, j)                 \
@@ -461,11 +460,7 @@ __device__ __forceinline__ Hit closest_hit_wave(const BvhView& bv, bool active, 
 
   while (__ballot(!s.done) != 0ull) {
     lm = 0u;
-    if (!s.done)
-      trav_visit<SL, GLOBAL>(s, bv, stk, stride, gstk, gcap, [&](int k, uint32_t j) {
-        lf[k] = j;
-        lm |= 1u << k;
-      });
+    if (!s.done) trav_visit<SL, GLOBAL>(s, bv, stk, stride, gstk, gcap, lm, lf);
     // at most 63 + 2 * 64 entries are held at any time
     append(0);
     append(1);
