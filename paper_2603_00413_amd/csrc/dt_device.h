@@ -258,11 +258,10 @@ __device__ __forceinline__ void trav_visit(Trav& s, const BvhView& bv, uint2* st
   const Bvh4Node& n = bv.nodes4[s.node];
   const float4 org = n.org;
   const uint4 ql = n.qlo, qh = n.qhi, cc = n.child;
-  // exact decode of the quantized child boxes: lo = p + qlo 2^e, hi = p + qhi 2^e
+  // the quantized child boxes: lo = p + qlo s, hi = p + qhi s, s = 2^e per axis
   const uint32_t eb = __float_as_uint(org.w);
-  const float sx = __uint_as_float((uint32_t)((int)(int8_t)(eb & 0xFFu) + 127) << 23);
-  const float sy = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 8) & 0xFFu) + 127) << 23);
-  const float sz = __uint_as_float((uint32_t)((int)(int8_t)((eb >> 16) & 0xFFu) + 127) << 23);
+  const int ebx = (int)(int8_t)(eb & 0xFFu), eby = (int)(int8_t)((eb >> 8) & 0xFFu);
+  const int ebz = (int)(int8_t)((eb >> 16) & 0xFFu);
   // widened like the exit distances (the closest hit's t carries rounding
   // too, and boxes entered at exactly that t must stay in play for ties)
   const float tmaxw = (s.h.tri >= 0 ? s.h.t : INFINITY) * 1.0000008f;
@@ -275,7 +274,7 @@ __device__ __forceinline__ void trav_visit(Trav& s, const BvhView& bv, uint2* st
   // 8u (255 |a| + |b|), so near and far distances bound the exact ones from
   // below and above and no box the exact ray enters before the closest hit is
   // rejected.  The near face per axis follows the sign of inv.
-  const float ax = sx * s.r.inv.x, ay = sy * s.r.inv.y, az = sz * s.r.inv.z;
+  const float ax = ldexpf(s.r.inv.x, ebx), ay = ldexpf(s.r.inv.y, eby), az = ldexpf(s.r.inv.z, ebz);
   const float bx = (org.x - s.r.o.x) * s.r.inv.x;
   const float by = (org.y - s.r.o.y) * s.r.inv.y;
   const float bz = (org.z - s.r.o.z) * s.r.inv.z;

@@ -27,6 +27,16 @@ constexpr int EB = 256;               // threads per block of the emit kernel
 constexpr int AB = 256;               // threads per block of the adjoint kernel
 constexpr int ADJ_MAX_BLOCKS = 4096;  // grid cap of the adjoint kernel
 constexpr int TRACE_MAX_BLOCKS = 256 * 4 * 7;  // grid cap of the traversal kernel: 7 resident waves per SIMD
+// Vertex adjoints of one hit, stored per node and summed per face afterwards:
+// d/d p0, p1, p2 and the shading-normal adjoint mbar with the barycentrics
+// (vertex normal k receives mbar b_k; mbar = 0 on flat-shaded hits).
+struct FaceRec {
+  float4 a;  // p0bar, b1
+  float4 b;  // p1bar, b2
+  float4 c;  // p2bar, -
+  float4 m;  // mbar, -
+};
+
 // ------------------------------------------------------------------ plan
 struct Plan {
   int D, k;
@@ -44,11 +54,13 @@ struct Plan {
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
   size_t w_dN, w_sbar, w_red, w_miss, w_ovf;
+  size_t w_frec, w_fkey, w_fidx, w_fcnt, w_foff, w_fscan, w_fg;  // per-face gathering of vertex adjoints
   size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
   size_t ws_bytes;
 };
 
-bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t nv, Plan& P) {
+bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t nv, int32_t nf,
+               Plan& P) {
   P.D = p->max_depth;
   P.k = p->checkpoint_stride < 1 ? 1 : p->checkpoint_stride;
   if (P.k > P.D + 1) P.k = P.D + 1;
@@ -129,6 +141,20 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = dt_align(o + 4 * mc);
   P.w_ovf = o;   // per-lane traversal stack overflow of the traversal grid
   o = dt_align(o + 8 * (size_t)TRACE_MAX_BLOCKS * TB * (DT_STACK - DT_STACK_LDS));
+  P.w_frec = o;  // vertex-adjoint record of each node of the current generation
+  o = dt_align(o + sizeof(FaceRec) * mc);
+  P.w_fkey = o;  // (face, rank among the face's records) per node
+  o = dt_align(o + 8 * mc);
+  P.w_fidx = o;  // nodes sorted by face
+  o = dt_align(o + 4 * mc);
+  P.w_fcnt = o;  // records per face
+  o = dt_align(o + 4 * ((size_t)nf + 1));
+  P.w_foff = o;  // exclusive scan of the counts
+  o = dt_align(o + 4 * ((size_t)nf + 1));
+  P.w_fscan = o;  // partial sums of the scan
+  o = dt_align(o + 4 * dt_scan_partials_count());
+  P.w_fg = o;     // per-face running totals of the vertex adjoints
+  o = dt_align(o + 4 * 18 * (size_t)nf);
   size_t kk = P.store_all ? 0 : (size_t)P.k;
   P.w_seg_o = o;
   o = dt_align(o + 16 * mc * kk);
@@ -475,9 +501,9 @@ __device__ __forceinline__ void atomic_add3(float* p, int idx, v3 v) {
 // Vertex contributions of one hit node: dLoss/dp_k for its three vertices and
 // dLoss/dN_k for their normals (absent where the geometric normal was used).
 struct VtxAdj {
-  int v[3];  // v[0] < 0: no contributions
-  v3 p0, p1, p2, n0, n1, n2;
-  bool has_n;
+  int f;  // hit face, < 0: no contributions
+  v3 p0, p1, p2, m;
+  float b1, b2;
 };
 
 // Adjoint of node i of generation g: writes its record (subtree radiance,
@@ -601,11 +627,7 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   if (!degen) {
     v3 nh = normalize3(s.m);
     v3 mbar = norm_bwd(s.m, nh, nbar * sgn);
-    float b0 = 1.f - b1 - b2;
-    out.n0 = mbar * b0;
-    out.n1 = mbar * b1;
-    out.n2 = mbar * b2;
-    out.has_n = true;
+    out.m = mbar;
     b1bar += dot(geo.n1 - geo.n0, mbar);
     b2bar += dot(geo.n2 - geo.n0, mbar);
   } else {
@@ -642,9 +664,9 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
     p1b += e1b;
     p2b += e2b;
   }
-  out.v[0] = geo.i0;
-  out.v[1] = geo.i1;
-  out.v[2] = geo.i2;
+  out.f = tri < 0 ? 0 : (tri >= sc.nf ? sc.nf - 1 : tri);
+  out.b1 = b1;
+  out.b2 = b2;
   out.p0 = p0b;
   out.p1 = p1b;
   out.p2 = p2b;
@@ -653,61 +675,16 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   cur.D[i] = make_float4(dbar.x, dbar.y, dbar.z, 0.f);
 }
 
-// Per-block aggregation of the vertex scatter: contributions to the same vertex
-// from the block's nodes are summed in an LDS hash table (vertex -> dV, dN)
-// and written with one set of global atomics per distinct vertex when the
-// table is flushed.  Consecutive nodes of a generation come from neighbouring
-// pixels, so they share many vertices.
-constexpr int ATBL = 1024;          // table slots (power of two)
-constexpr int ATBL_FLUSH = 384;     // flush once more slots than this are taken
-constexpr int ATBL_PROBES = 32;     // linear-probe limit before going straight to memory
-
-__global__ void __launch_bounds__(AB, 4) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
-                                                const float* grad_rgb, Adj nxt, Adj cur, float* dV,
-                                                float* dN, float4* red) {
-  __shared__ int tkey[ATBL];
-  __shared__ float tval[6][ATBL];
-  __shared__ int tused;
-  for (int k = threadIdx.x; k < ATBL; k += AB) {
-    tkey[k] = -1;
-    for (int c = 0; c < 6; ++c) tval[c][k] = 0.f;
-  }
-  if (threadIdx.x == 0) tused = 0;
-  __syncthreads();
-  auto add_vertex = [&](int v, v3 a, v3 b, bool with_n) {
-    uint32_t h = ((uint32_t)v * 2654435761u) >> (32 - 10);
-    for (int probe = 0; probe < ATBL_PROBES; ++probe) {
-      int k = atomicCAS(&tkey[h], -1, v);
-      if (k == -1) atomicAdd(&tused, 1);
-      if (k == -1 || k == v) {
-        atomicAdd(&tval[0][h], a.x);
-        atomicAdd(&tval[1][h], a.y);
-        atomicAdd(&tval[2][h], a.z);
-        if (with_n) {
-          atomicAdd(&tval[3][h], b.x);
-          atomicAdd(&tval[4][h], b.y);
-          atomicAdd(&tval[5][h], b.z);
-        }
-        return;
-      }
-      h = (h + 1) & (ATBL - 1);
-    }
-    atomic_add3(dV, v, a);
-    if (with_n && dN) atomic_add3(dN, v, b);
-  };
-  auto flush = [&]() {
-    for (int k = threadIdx.x; k < ATBL; k += AB) {
-      int v = tkey[k];
-      if (v >= 0) {
-        atomic_add3(dV, v, mk3(tval[0][k], tval[1][k], tval[2][k]));
-        v3 nb = mk3(tval[3][k], tval[4][k], tval[5][k]);
-        if (dN && (nb.x != 0.f || nb.y != 0.f || nb.z != 0.f)) atomic_add3(dN, v, nb);
-        tkey[k] = -1;
-        for (int c = 0; c < 6; ++c) tval[c][k] = 0.f;
-      }
-    }
-  };
-  static_assert(ATBL == 1024, "the hash takes the top 10 bits");
+// The vertex adjoints of a generation are gathered per face without float
+// atomics per hit: each hit node writes its FaceRec and takes a rank among its
+// face's records (one integer atomic); a scan of the per-face counts and a
+// scatter sort the nodes by face; then each face sums its records and adds
+// the totals to its three vertices (18 atomics per hit face instead of 18 per
+// hit).
+__global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
+                                                const float* grad_rgb, Adj nxt, Adj cur,
+                                                FaceRec* frec, int2* fkey, uint32_t* fcnt,
+                                                float4* red) {
   const int64_t n = ctr->count[g];
   // each block takes one contiguous range of the generation, AB nodes a step
   const int64_t per = ((n + gridDim.x - 1) / gridDim.x + AB - 1) / AB * AB;
@@ -716,23 +693,22 @@ __global__ void __launch_bounds__(AB, 4) k_adjoint(SceneDev sc, Gen q, int g, co
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int64_t base = lo; base < hi; base += AB) {
     int64_t i = base + threadIdx.x;
+    if (i >= hi) break;
     VtxAdj va;
-    va.v[0] = -1;
-    va.has_n = false;
-    if (i < hi) adjoint_node(sc, q, i, grad_rgb, nxt, cur, acc, va);
-    if (va.v[0] >= 0) {
-      add_vertex(va.v[0], va.p0, va.n0, va.has_n);
-      add_vertex(va.v[1], va.p1, va.n1, va.has_n);
-      add_vertex(va.v[2], va.p2, va.n2, va.has_n);
+    va.f = -1;
+    va.m = mk3(0.f, 0.f, 0.f);
+    adjoint_node(sc, q, i, grad_rgb, nxt, cur, acc, va);
+    int2 key = make_int2(-1, 0);
+    if (va.f >= 0) {
+      FaceRec r;
+      r.a = make_float4(va.p0.x, va.p0.y, va.p0.z, va.b1);
+      r.b = make_float4(va.p1.x, va.p1.y, va.p1.z, va.b2);
+      r.c = make_float4(va.p2.x, va.p2.y, va.p2.z, 0.f);
+      r.m = make_float4(va.m.x, va.m.y, va.m.z, 0.f);
+      frec[i] = r;
+      key = make_int2(va.f, (int)atomicAdd(fcnt + va.f, 1u));
     }
-    __syncthreads();
-    const int used = tused;
-    __syncthreads();  // every thread has read the count before the next step adds to it
-    if (used > ATBL_FLUSH || base + AB >= hi) {
-      flush();
-      if (threadIdx.x == 0) tused = 0;
-      __syncthreads();
-    }
+    fkey[i] = key;
   }
   const float acc_eta = acc.x, acc_s0 = acc.y, acc_s1 = acc.z, acc_s2 = acc.w;
   // block reduction of the scalar gradients
@@ -752,6 +728,88 @@ __global__ void __launch_bounds__(AB, 4) k_adjoint(SceneDev sc, Gen q, int g, co
   if (threadIdx.x == 0)
     red[(size_t)g * ADJ_MAX_BLOCKS + blockIdx.x] = make_float4(red_s[0][0], red_s[1][0], red_s[2][0],
                                                                red_s[3][0]);
+}
+
+// ------------------------------------------------------------------ per-face gathering
+// nodes of the generation sorted by face: node i goes to off[face] + rank
+__global__ void k_face_scatter(const Counters* ctr, int g, const int2* fkey, const uint32_t* off,
+                               uint32_t* fidx) {
+  const int64_t n = ctr->count[g];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int2 k = fkey[i];
+    if (k.x >= 0) fidx[off[k.x] + (uint32_t)k.y] = (uint32_t)i;
+  }
+}
+
+// Each face's records of the generation summed by a group of FG lanes and
+// added to the face's running totals fg (18 floats per face: for corner k,
+// the position adjoint then the vertex-normal adjoint); the group owns the
+// face, so no atomics.  The face's count is reset for the next generation.
+constexpr int FG = 16;
+constexpr int FR_T = 256;
+
+__global__ void __launch_bounds__(FR_T) k_face_reduce(int32_t nf, const FaceRec* frec,
+                                                      const uint32_t* fidx, const uint32_t* off,
+                                                      uint32_t* fcnt, float* fg) {
+  const int sub = threadIdx.x % FG;
+  const int64_t groups = (int64_t)gridDim.x * (FR_T / FG);
+  for (int64_t f = blockIdx.x * (int64_t)(FR_T / FG) + threadIdx.x / FG; f < nf; f += groups) {
+    const uint32_t b = off[f], e = off[f + 1];
+    if (b == e) continue;  // the whole group agrees
+    v3 p0 = mk3(0.f, 0.f, 0.f), p1 = p0, p2 = p0, n0 = p0, n1 = p0, n2 = p0;
+    for (uint32_t j = b + (uint32_t)sub; j < e; j += FG) {
+      const FaceRec r = frec[fidx[j]];
+      p0 += xyz(r.a);
+      p1 += xyz(r.b);
+      p2 += xyz(r.c);
+      const v3 m = xyz(r.m);
+      const float b1 = r.a.w, b2 = r.b.w;
+      const float b0 = 1.f - b1 - b2;
+      n0 += m * b0;
+      n1 += m * b1;
+      n2 += m * b2;
+    }
+    // sum over the group's lanes
+#pragma unroll
+    for (int st = FG / 2; st > 0; st >>= 1) {
+      p0 += mk3(__shfl_xor(p0.x, st), __shfl_xor(p0.y, st), __shfl_xor(p0.z, st));
+      p1 += mk3(__shfl_xor(p1.x, st), __shfl_xor(p1.y, st), __shfl_xor(p1.z, st));
+      p2 += mk3(__shfl_xor(p2.x, st), __shfl_xor(p2.y, st), __shfl_xor(p2.z, st));
+      n0 += mk3(__shfl_xor(n0.x, st), __shfl_xor(n0.y, st), __shfl_xor(n0.z, st));
+      n1 += mk3(__shfl_xor(n1.x, st), __shfl_xor(n1.y, st), __shfl_xor(n1.z, st));
+      n2 += mk3(__shfl_xor(n2.x, st), __shfl_xor(n2.y, st), __shfl_xor(n2.z, st));
+    }
+    if (sub < 3) {
+      const v3 pv = sub == 0 ? p0 : (sub == 1 ? p1 : p2);
+      const v3 nv = sub == 0 ? n0 : (sub == 1 ? n1 : n2);
+      float* q = fg + (size_t)(3 * f + sub) * 6;
+      q[0] += pv.x;
+      q[1] += pv.y;
+      q[2] += pv.z;
+      q[3] += nv.x;
+      q[4] += nv.y;
+      q[5] += nv.z;
+    } else if (sub == 3) {
+      fcnt[f] = 0u;
+    }
+  }
+}
+
+// after the last generation: each face corner's totals go to its vertex
+__global__ void k_face_to_vertex(SceneDev sc, const float* fg, float* dV, float* dN) {
+  const int64_t n = 3 * (int64_t)sc.nf;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const float* q = fg + 6 * c;
+    const v3 pv = mk3(q[0], q[1], q[2]), nv = mk3(q[3], q[4], q[5]);
+    const bool has_p = pv.x != 0.f || pv.y != 0.f || pv.z != 0.f;
+    const bool has_n = nv.x != 0.f || nv.y != 0.f || nv.z != 0.f;
+    if (!has_p && !has_n) continue;
+    const int v = vclampi(sc.F[c], sc.nv);
+    if (has_p) atomic_add3(dV, v, pv);
+    if (has_n && dN) atomic_add3(dN, v, nv);
+  }
 }
 
 // dIoR, dsigma = ordered sums of the per-(generation, block) partials
@@ -1131,7 +1189,7 @@ extern "C" dt_status dt_trace_bytes(const dt_trace_params* p, int64_t n_rays, in
              DT_MAX_DEPTH);
   DT_REQUIRE(p->checkpoint_stride >= 1 && p->queue_capacity >= 0, "bad checkpoint_stride / capacity");
   Plan P;
-  make_plan(p, n_rays, n_rays, nv, P);
+  make_plan(p, n_rays, n_rays, nv, nf, P);
   *ws_bytes = P.ws_bytes;
   *tape_bytes = P.tape_bytes;
   return DT_OK;
@@ -1148,7 +1206,7 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
   if (dt_status st = ray_counts(rays, N, npix)) return st;
   DT_REQUIRE(rgb && ws, "dt_trace_forward: rgb and ws are required");
   Plan P;
-  make_plan(p, N, npix, scene->nv, P);
+  make_plan(p, N, npix, scene->nv, scene->nf, P);
   if (ws_bytes < P.ws_bytes) {
     dt_set_error("dt_trace_forward: workspace has %zu bytes, needs %zu", ws_bytes, P.ws_bytes);
     return DT_ERR_WORKSPACE_TOO_SMALL;
@@ -1219,7 +1277,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   DT_REQUIRE(grad_rgb && tape && dV && d_ior && d_sigma && ws,
              "dt_trace_backward: grad_rgb, tape, dV, d_ior, d_sigma and ws are required");
   Plan P;
-  make_plan(p, N, npix, scene->nv, P);
+  make_plan(p, N, npix, scene->nv, scene->nf, P);
   if (ws_bytes < P.ws_bytes || tape_bytes < P.tape_bytes) {
     dt_set_error("dt_trace_backward: workspace %zu/%zu or tape %zu/%zu bytes too small", ws_bytes,
                  P.ws_bytes, tape_bytes, P.tape_bytes);
@@ -1234,10 +1292,19 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   float* dN = (float*)(W + P.w_dN);
   float4* sbar = (float4*)(W + P.w_sbar);
   float4* red = (float4*)(W + P.w_red);
+  FaceRec* frec = (FaceRec*)(W + P.w_frec);
+  int2* fkey = (int2*)(W + P.w_fkey);
+  uint32_t* fidx = (uint32_t*)(W + P.w_fidx);
+  uint32_t* fcnt = (uint32_t*)(W + P.w_fcnt);
+  uint32_t* foff = (uint32_t*)(W + P.w_foff);
+  int32_t* fscan = (int32_t*)(W + P.w_fscan);
+  float* fg = (float*)(W + P.w_fg);
   const int nred = (P.D + 1) * ADJ_MAX_BLOCKS;  // slot g * ADJ_MAX_BLOCKS + block
   hipLaunchKernelGGL(k_load_counters, dim3(1), dim3(64), 0, s, ctr, (const Counters*)(T + P.tape_hdr));
   if (dt_status st = zero_f32(dV, 3 * (int64_t)scene->nv, s)) return st;
   if (dt_status st = zero_f32(dN, 3 * (int64_t)scene->nv, s)) return st;
+  if (dt_status st = zero_f32((float*)fcnt, (int64_t)scene->nf + 1, s)) return st;
+  if (dt_status st = zero_f32(fg, 18 * (int64_t)scene->nf, s)) return st;
   if (dt_status st = zero_f32((float*)red, 4 * (int64_t)nred, s)) return st;
   Adj adj[2];
   for (int b = 0; b < 2; ++b) {
@@ -1261,7 +1328,15 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
       if (dt_status st = record(maev, 2 * g + 1, s)) return st;
     }
     hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                       adj[(g + 1) & 1], adj[g & 1], dV, dN, red);
+                       adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
+    // fcnt[nf] stays 0, so foff[nf] is the total
+    if (dt_status st = dt_scan_exclusive_i32((const int32_t*)fcnt, (int32_t*)foff, scene->nf + 1, fscan, s))
+      return st;
+    hipLaunchKernelGGL(k_face_scatter, dim3(dt_blocks(P.cap[g], 256) < 8192 ? dt_blocks(P.cap[g], 256) : 8192),
+                       dim3(256), 0, s, ctr, g, fkey, foff, fidx);
+    const int64_t fgroups = ((int64_t)scene->nf + FR_T / FG - 1) / (FR_T / FG);
+    hipLaunchKernelGGL(k_face_reduce, dim3((unsigned)(fgroups < 8192 ? fgroups : 8192)), dim3(FR_T), 0, s,
+                       scene->nf, frec, fidx, foff, fcnt, fg);
     DT_CHECK_LAUNCH();
     return record(aev, 2 * g + 1, s);
   };
@@ -1307,6 +1382,9 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
   }
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_T), 0, s, red, nred, d_ior, d_sigma);
+  hipLaunchKernelGGL(k_face_to_vertex, dim3(dt_blocks(3 * (int64_t)scene->nf, 256) < 4096
+                                                ? dt_blocks(3 * (int64_t)scene->nf, 256) : 4096),
+                     dim3(256), 0, s, sc, fg, dV, dN);
   hipLaunchKernelGGL(k_nbwd_vertex, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, dN, sbar);
   hipLaunchKernelGGL(k_nbwd_face, dim3(dt_blocks(scene->nf, 256)), dim3(256), 0, s, sc.bvh, sc.V, sc.F,
                      sbar, dV);
