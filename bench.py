@@ -33,7 +33,7 @@ TRACE_PER_RAY = 48 + 16 + 4          # ray record in, hit + decision out
 TRACE_PER_HIT = 12 + 36 + 48         # face row, 3 vertices, 3 vertex normals
 TRACE_PER_MISS = 48 + 12             # 4 texels, pixel accumulation
 ADJ_PER_RAY = 48 + 16 + 4 + 8 + 12 + 48   # ray, hit, decision, children, dL/dC, adjoint out
-ADJ_PER_HIT = 96 + 96 + 36 + 36      # geometry, 2 child adjoints, dV and dN updates
+ADJ_PER_HIT = 96 + 96 + 64 + 8       # geometry, 2 child adjoints, face record and (face, rank) key
 ADJ_PER_MISS = 48                    # 4 texels
 
 # HBM bytes per launch of the dominant kernel on this workload, measured with
@@ -45,15 +45,24 @@ MEASURED_TRAFFIC = {
     "k_trace": {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h"],
-        "sha256": "9d69c440d01878a772ad373b3c2d6f27b28674d7ef41b9e4a008ab161067281d",
-        "bytes": (359865.2 * 2.0 + 77155.9) * 1024,
+        "sha256": "737b8faa0659be534abfcce55c77d8d00409f27b1af7fded29ada56295b26fa5",
+        "bytes": (427599.8 * 2.0 + 85810.6) * 1024,
+        # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:
+        # wave-level VALU instructions per launch, and the share of lanes active
+        # in them
+        "valu_insts": 2.938e8,
+        "lane_utilization": 0.62,
     },
 }
 
 
-def measured_traffic(kernel):
-    """Counter-measured bytes per launch of kernel, or None when the sources
-    changed since the counters were taken."""
+# VALU issue peak: 256 CUs x 4 SIMDs, a wave64 VALU instruction every 4 cycles
+# per SIMD (16 lanes), 2.4 GHz = 614.4 G wave-instructions/s (the FP32 vector
+# peak of 157.3 TFLOP/s counts 2 flops of an FMA on 2 packed values per lane)
+VALU_ISSUE_PEAK_GIPS = 256 * 2.4
+
+
+def _measured(kernel):
     import hashlib
     m = MEASURED_TRAFFIC.get(kernel)
     if m is None:
@@ -62,7 +71,27 @@ def measured_traffic(kernel):
     for f in m["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return int(m["bytes"]) if h.hexdigest() == m["sha256"] else None
+    return m if h.hexdigest() == m["sha256"] else None
+
+
+def measured_traffic(kernel):
+    """Counter-measured bytes per launch of kernel, or None when the sources
+    changed since the counters were taken."""
+    m = _measured(kernel)
+    return int(m["bytes"]) if m else None
+
+
+def valu_issue(kernel, avg_launch_ms):
+    """Counter-measured VALU instruction rate of kernel against the issue peak
+    (None when the sources changed since the counters were taken)."""
+    m = _measured(kernel)
+    if not m or "valu_insts" not in m:
+        return None
+    rate = m["valu_insts"] / (avg_launch_ms * 1e-3) / 1e9
+    return {"insts_per_launch": m["valu_insts"], "achieved": round(rate, 1),
+            "peak": VALU_ISSUE_PEAK_GIPS, "unit": "G wave-instr/s",
+            "frac": round(rate / VALU_ISSUE_PEAK_GIPS, 4),
+            "lane_utilization": m["lane_utilization"]}
 
 
 def parse():
@@ -269,6 +298,8 @@ def main():
             "traffic": measured_traffic(dom),
             "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            # what actually bounds the traversal: VALU issue
+            "valu_issue": valu_issue(dom, avg_ms),
         },
         "step_latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
                             "p99": round(float(np.percentile(lat_ms, 99)), 3)},
