@@ -106,10 +106,13 @@ dt_status dt_bvh_vertex_normals(const void* bvh, int32_t nv, int32_t nf, float* 
  * phi = atan2(x, -z), theta = polar angle from +y, u = phi/2pi + 1/2,
  * v = theta/pi, bilinear at texel coordinates (uW - 1/2, vH - 1/2), wrapping
  * in u, clamping in v.  MLP: input [d, sin(2^k pi d), cos(2^k pi d)] for
- * k < n_freq, zero-padded to in_pad (64); n_layers hidden layers of width
- * `hidden` with ReLU; linear RGB head; bfloat16 weights ([out][in] row-major
- * per layer, concatenated), float32 biases, bfloat16 activations, float32
- * accumulation.  Directions need not be unit: they are normalised first. */
+ * k < n_freq (at most 7), zero-padded to in_pad (64); n_layers (1-4) hidden
+ * layers of width `hidden` (64 or 128) with ReLU; linear RGB head; bfloat16
+ * weights ([out][in] row-major per layer, concatenated), float32 biases;
+ * activations enter the bf16 matrix cores as three bf16 parts whose sum is
+ * their float32 value, with float32 accumulation, so each layer is as accurate
+ * as a float32 product.  Directions need not be unit: they are normalised
+ * first.  Other shapes return DT_ERR_UNSUPPORTED. */
 typedef struct {
   int32_t kind;
   int32_t width, height;

@@ -11,7 +11,9 @@
 // matrix product.  (A single bf16 rounding per activation would put steps of
 // 2^-9 relative into E, and a derivative that depends on which side of a step
 // a ray lands.)  The encoding takes sin(pi t), cos(pi t) of t = 2^k u, which
-// is exact in FP32, so no argument rounding error grows with the frequency.
+// is exact in FP32 (as is its reduction to a fraction of a turn), so no
+// argument rounding error grows with the frequency; the hardware sine and
+// cosine then add at most 1.3e-7.
 //
 // A block first copies the whole network into LDS (rows padded by 4 bf16 so
 // the 16 rows an MFMA operand spans fall on different banks; the RGB head
@@ -55,33 +57,62 @@ __device__ __forceinline__ Split3 split3(float v) {
   return s;
 }
 
-// encoding component k of the unit direction u
-__device__ __forceinline__ float enc(int k, v3 u, int n_freq) {
-  if (k < 3) return comp(u, k);
-  int r = k - 3, f = r / 6, c = r % 6;
-  if (f >= n_freq) return 0.f;
-  float t = ldexpf(comp(u, c < 3 ? c : c - 3), f);
-  return c < 3 ? sinpif(t) : cospif(t);
+// The encoding in the matrix cores' input order.  Lane group q of a wave holds
+// input rows 16 kb + 4 q + j (kb, j < 4) of its ray, so the input rows are
+// renumbered: group q < 3 carries axis q in its 16 slots s = 4 kb + j (slot 0:
+// u_q; slot 1 + 2f: sin(2^f pi u_q); slot 2 + 2f: cos(2^f pi u_q); f < n_freq
+// <= DT_MLP_MAX_FREQ), group 3 and unused slots are zero.  The first layer's
+// weight columns are permuted to match when the network is copied to LDS.
+#define DT_MLP_MAX_FREQ 7
+
+// input column (in the caller's order: u, then per frequency sin xyz, cos xyz)
+// of input row k in the matrix cores' order, or -1 for a zero row
+__device__ __forceinline__ int enc_column(int k, int n_freq) {
+  const int q = (k & 15) >> 2, s = ((k >> 4) << 2) | (k & 3);
+  if (q == 3) return -1;
+  if (s == 0) return q;
+  const int f = (s - 1) >> 1;
+  if (f >= n_freq) return -1;
+  return 3 + 6 * f + ((s & 1) ? q : 3 + q);
 }
 
-// d enc_k / d u (only the component of u it depends on)
-__device__ __forceinline__ void denc(int k, v3 u, int n_freq, float& dx, float& dy, float& dz,
-                                     float g) {
-  if (k < 3) {
-    if (k == 0) dx += g;
-    if (k == 1) dy += g;
-    if (k == 2) dz += g;
-    return;
+// sin(pi 2^f u), cos(pi 2^f u) for f < n_freq by the hardware sine and cosine
+// (arguments in turns: 2^(f-1) u exactly, reduced by its nearest integer,
+// also exact); within 1.3e-7 of the true values over |u| <= 1, f < 7
+struct EncTrig {
+  float sn[DT_MLP_MAX_FREQ], cs[DT_MLP_MAX_FREQ];
+};
+__device__ __forceinline__ EncTrig enc_trig(float uq, int n_freq) {
+  EncTrig t;
+#pragma unroll
+  for (int f = 0; f < DT_MLP_MAX_FREQ; ++f) {
+    t.sn[f] = 0.f;
+    t.cs[f] = 0.f;
+    if (f < n_freq) {
+      float h = uq * (float)(1 << f) * 0.5f;
+      h -= rintf(h);
+      t.sn[f] = __builtin_amdgcn_sinf(h);
+      t.cs[f] = __builtin_amdgcn_cosf(h);
+    }
   }
-  int r = k - 3, f = r / 6, c = r % 6;
-  if (f >= n_freq) return;
-  int ax = c < 3 ? c : c - 3;
-  float w = ldexpf(DT_PI, f);
-  float t = ldexpf(comp(u, ax), f);
-  float v = c < 3 ? w * cospif(t) : -w * sinpif(t);
-  if (ax == 0) dx += g * v;
-  if (ax == 1) dy += g * v;
-  if (ax == 2) dz += g * v;
+  return t;
+}
+
+// slot s of a lane group carrying axis value uq
+__device__ __forceinline__ float enc_slot(int s, float uq, const EncTrig& t, int n_freq) {
+  if (s == 0) return uq;
+  const int f = (s - 1) >> 1;
+  if (f >= DT_MLP_MAX_FREQ || f >= n_freq) return 0.f;
+  return (s & 1) ? t.sn[f] : t.cs[f];
+}
+
+// d slot / d uq
+__device__ __forceinline__ float denc_slot(int s, const EncTrig& t, int n_freq) {
+  if (s == 0) return 1.f;
+  const int f = (s - 1) >> 1;
+  if (f >= DT_MLP_MAX_FREQ || f >= n_freq) return 0.f;
+  const float w = DT_PI * (float)(1 << f);
+  return (s & 1) ? w * t.cs[f] : -w * t.sn[f];
 }
 
 constexpr int IN = 64;  // padded input width
@@ -123,9 +154,12 @@ template <int HID, int NL, bool GRAD>
 __device__ __forceinline__ void load_net(const EnvDev& e, uint16_t* sw, float* sb) {
   using N = NetLds<HID, NL, GRAD>;
   const uint16_t* W = e.w;
+  // first layer: columns in the matrix cores' input order
   for (int i = threadIdx.x; i < HID * IN; i += blockDim.x) {
-    sw[N::W0 + (i / IN) * N::LD0 + (i % IN)] = W[i];
-    if (N::TRANS) sw[N::T0 + (i % IN) * N::LDH + (i / IN)] = W[i];
+    const int col = enc_column(i % IN, e.n_freq);
+    const uint16_t v = col >= 0 ? W[(i / IN) * IN + col] : (uint16_t)0;
+    sw[N::W0 + (i / IN) * N::LD0 + (i % IN)] = v;
+    if (N::TRANS) sw[N::T0 + (i % IN) * N::LDH + (i / IN)] = v;
   }
   W += HID * IN;
   for (int l = 1; l < NL; ++l) {
@@ -205,12 +239,16 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
   constexpr int KB = HID / 16;
   float inv_len = 1.0f / sqrtf(dot(d, d));
   v3 u = d * inv_len;
+  // this lane group's axis (group 3 carries zeros)
+  const float uq = q == 0 ? u.x : (q == 1 ? u.y : (q == 2 ? u.z : 0.f));
+  const int nfq = q == 3 ? 0 : n_freq;
+  const EncTrig trig = enc_trig(uq, nfq);
   bf16x4 xh[IN / 16], xm[IN / 16], xl[IN / 16];
 #pragma unroll
   for (int kb = 0; kb < IN / 16; ++kb)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      Split3 p = split3(enc(kb * 16 + 4 * q + j, u, n_freq));
+      Split3 p = split3(enc_slot(4 * kb + j, uq, trig, nfq));
       xh[kb][j] = p.h;
       xm[kb][j] = p.m;
       xl[kb][j] = p.l;
@@ -345,8 +383,8 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
       nl[ib] = tl[ib];
     }
   }
-  // first layer: delta_enc = W_0^T delta_0 (64 rows), then d enc / d u
-  float gx = 0.f, gy = 0.f, gz = 0.f;
+  // first layer: delta_enc = W_0^T delta_0 (64 rows), then d enc / d u_q
+  float gq = 0.f;
 #pragma unroll
   for (int ib = 0; ib < IN / 16; ++ib) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -360,11 +398,12 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
       acc = mfma32(a, cat8(nh[2 * kb], nh[2 * kb + 1]), acc);
       acc = mfma32(a, cat8(nl[2 * kb], nl[2 * kb + 1]), acc);
     }
-    // acc[j] = d loss / d enc_k for k = ib*16 + 4q + j of ray r16
+    // acc[j] = d loss / d (slot 4 ib + j) of ray r16 in this lane group
 #pragma unroll
-    for (int j = 0; j < 4; ++j) denc(ib * 16 + 4 * q + j, u, n_freq, gx, gy, gz, acc[j]);
+    for (int j = 0; j < 4; ++j) gq += acc[j] * denc_slot(4 * ib + j, trig, nfq);
   }
-  // the four lane groups hold different k of the same ray
+  // lane group q < 3 holds d / d u_q; the groups of one ray are lanes r16 + 16 q
+  float gx = q == 0 ? gq : 0.f, gy = q == 1 ? gq : 0.f, gz = q == 2 ? gq : 0.f;
   gx += __shfl_xor(gx, 16);
   gy += __shfl_xor(gy, 16);
   gz += __shfl_xor(gz, 16);
@@ -503,7 +542,7 @@ unsigned mlp_blocks(int64_t n, int threads) {
 
 bool mlp_supported(const EnvDev& e) {
   return e.in_pad == IN && (e.hidden == 64 || e.hidden == 128) && e.n_layers >= 1 &&
-         e.n_layers <= 4 && e.n_freq >= 0 && 3 + 6 * e.n_freq <= IN && e.w && e.b;
+         e.n_layers <= 4 && e.n_freq >= 0 && e.n_freq <= DT_MLP_MAX_FREQ && e.w && e.b;
 }
 
 #define DT_LAUNCH(H, L, kern, grid, ...)                                                    \
