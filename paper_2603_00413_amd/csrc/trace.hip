@@ -1136,7 +1136,7 @@ dt_status make_env(const dt_env* env, EnvDev& e) {
   e.b = env->biases;
   if (env->kind == DT_ENV_MLP && !mlp_supported(e)) {
     dt_set_error("environment MLP needs weights, biases, in_pad 64, hidden 64 or 128, 1-4 layers, "
-                 "3 + 6 n_freq <= 64 (got in_pad %d hidden %d layers %d n_freq %d)",
+                 "n_freq <= 7 (got in_pad %d hidden %d layers %d n_freq %d)",
                  env->in_pad, env->hidden, env->n_layers, env->n_freq);
     return DT_ERR_UNSUPPORTED;
   }

@@ -61,3 +61,22 @@ def test_queue_capacity_bounds_tape():
     p = B.Params(max_depth=6, queue_capacity=2 << 20).c()
     L.dt_trace_bytes(C.byref(p), 1 << 20, 51200, 102400, C.byref(a), C.byref(b))
     assert b.value < worst / 5
+
+
+def test_unsupported_shapes_are_rejected_on_the_host():
+    """An MLP with more frequencies than the matrix-core input order holds, or
+    a mesh beyond the traversal's 2^26-triangle packing, is refused before any
+    device work (the pointers below are never dereferenced)."""
+    L = B.load()
+    e = B._Env()
+    e.kind = B.ENV_MLP
+    e.n_freq, e.n_layers, e.hidden, e.in_pad = 8, 3, 64, 64
+    e.weights, e.biases = 16, 16          # non-null, never read
+    assert L.dt_env_query(C.byref(e), C.c_void_p(16), 1, C.c_void_p(16), None) == 5
+    assert "n_freq <= 7" in L.dt_last_error().decode()
+    e.n_freq, e.hidden = 6, 96
+    assert L.dt_env_query(C.byref(e), C.c_void_p(16), 1, C.c_void_p(16), None) == 5
+    a, b = C.c_size_t(), C.c_size_t()
+    assert L.dt_bvh_bytes(3, (1 << 26) + 1, C.byref(a), C.byref(b)) == 1
+    assert "2^26" in L.dt_last_error().decode()
+    assert L.dt_bvh_bytes(3, 1 << 26, C.byref(a), C.byref(b)) == 0
