@@ -106,6 +106,7 @@ def parse():
     ap.add_argument("--cpu-stride", type=int, default=1,
                     help="oracle baseline traces every n-th pixel in x and y")
     ap.add_argument("--no-mlp", action="store_true", help="skip the MLP-lit training-step leg")
+    ap.add_argument("--no-stress", action="store_true", help="skip the 2M-triangle thin-shell leg")
     ap.add_argument("--copy-only", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
@@ -261,6 +262,9 @@ def main():
     training = None
     if not args.no_mlp:
         training = training_step_bench(args, dev)
+    stress = None
+    if not args.no_stress:
+        stress = stress_bench(args, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -305,6 +309,7 @@ def main():
                             "p99": round(float(np.percentile(lat_ms, 99)), 3)},
         "serving": serving,
         "training_step_mlp": training,
+        "stress_thin_shell": stress,
         "plain_forward": {"ms": round(fwd_ms, 3), "Mrays/s": round(segs / fwd_ms / 1e3, 3)},
         "kernel_ms_per_generation": {"k_trace": np.round(tr_ms, 4).tolist(),
                                      "k_adjoint": np.round(ad_ms, 4).tolist()},
@@ -406,6 +411,96 @@ def training_step_bench(args, dev):
             "backward_kernel_TFLOP/s": round(float(bwd_tf), 2),
             "backward_ms_per_step": round(float(bwd_ms.sum()), 4),
         },
+    }
+
+
+def stress_bench(args, dev):
+    """The stress shape: thin-shell SDF mesh (~2M triangles, frequent TIR),
+    one 2048^2 view, depth 8, environment MLP 4 x 128; forward with a tape
+    every 2 generations, L2 loss gradient, adjoint recomputing the generations
+    in between.  Reports Mrays/s, the ray queue's compaction efficiency (live
+    rays over allocated slots, per generation) and the traversal kernel's
+    achieved HBM rate."""
+    import torch
+
+    from paper_2603_00413_amd import binding as B
+    from paper_2603_00413_amd import synth
+    wl = synth.thin_shell_scene()
+    Ws, Bs, n_freq = wl.mlp
+    V = torch.from_numpy(wl.V.astype(np.float32)).to(dev)
+    F = torch.from_numpy(wl.F).to(dev)
+    mesh = B.Mesh(V, F)
+    env = B.Env.mlp(Ws, Bs, n_freq, dev)
+    scene = B.Scene(mesh, torch.tensor([wl.ior], dtype=torch.float32, device=dev),
+                    torch.tensor(wl.sigma, dtype=torch.float32, device=dev), env)
+    rays = B.Rays(cameras=wl.cameras)
+    cap = int(1.3 * rays.n_rays)
+    while True:
+        p = B.Params(max_depth=wl.max_depth, queue_capacity=cap)
+        buf = B.Buffers(p, rays, mesh, tape=False)
+        B.dt_trace_forward(scene, rays, p, buf, want_aux=False)
+        st = buf.stats.cpu().numpy()
+        if st[B.STAT_DROPPED] == 0:
+            break
+        cap *= 2
+    del buf
+    G = wl.max_depth + 1
+    counts = st[:G].astype(np.int64)
+    hits = st[B.STAT_HITS:B.STAT_HITS + G].astype(np.int64)
+    segs = int(counts.sum())
+    cap = int(max(counts[1:].max() * 1.05, 2048))
+    stride = 2
+    timer = B.KernelTimer(wl.max_depth)
+    params = B.Params(max_depth=wl.max_depth, queue_capacity=cap, checkpoint_stride=stride,
+                      timing=timer)
+    buf = B.Buffers(params, rays, mesh, tape=True)
+    tscene = B.Scene(mesh, torch.tensor([1.55], device=dev), torch.tensor([0.2, 0.3, 0.4], device=dev),
+                     env)
+    target, _, _ = B.dt_trace_forward(tscene, rays, params, buf, want_aux=False)
+    target = target.clone()
+
+    def step():
+        mesh.build()
+        rgb, _, _ = B.dt_trace_forward(scene, rays, params, buf, want_aux=False)
+        grad = (rgb - target) * (2.0 / rgb.numel())
+        return B.dt_trace_backward(scene, rays, params, buf, grad)
+
+    step()
+    torch.cuda.synchronize()
+    steps = 3
+    tr_ms = np.zeros(G)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+        torch.cuda.synchronize()
+        tr_ms += np.array(timer.trace_ms(G)) / steps
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    st = buf.stats.cpu().numpy()
+    assert st[B.STAT_DROPPED] == 0 and int(st[B.STAT_TOTAL]) == segs
+    miss = counts - hits
+    tr_bytes = counts * TRACE_PER_RAY + hits * TRACE_PER_HIT + miss * TRACE_PER_MISS
+    gbs = float(tr_bytes.sum() / (tr_ms.sum() * 1e-3) / 1e9)
+    # the queue of a generation is dense (stable compaction leaves no holes);
+    # its allocation is the camera rays for generation 0, else the smaller of
+    # the capacity and the worst case 2^g camera rays
+    alloc = [rays.n_rays if g == 0 else min(cap, rays.n_rays << g) for g in range(G)]
+    eff = [round(float(counts[g]) / alloc[g], 4) for g in range(G)]
+    log(f"stress (thin shell): {len(wl.F)} tris, {ms:.2f} ms per step, {segs / ms / 1e3:.1f} Mrays/s; "
+        f"live per generation {counts.tolist()} of capacity {cap}; k_trace {gbs:.1f} GB/s")
+    return {
+        "workload": "thin-shell SDF %d tris, 1 view x %d^2, depth %d, IoR %.2f, env MLP %d x %d bf16, "
+                    "fwd+bwd with a tape every %d generations"
+                    % (len(wl.F), wl.cameras[0].width, wl.max_depth, wl.ior, len(Ws) - 1, Ws[0].shape[0],
+                       stride),
+        "ms_per_step": round(ms, 3),
+        "Mrays/s": round(segs / ms / 1e3, 3),
+        "segments_per_step": segs,
+        "queue": {"capacity": cap, "allocated_per_generation": alloc,
+                  "live_per_generation": counts.tolist(), "compaction_efficiency": eff,
+                  "hits_per_generation": hits.tolist()},
+        "k_trace": {"ms_per_generation": np.round(tr_ms, 4).tolist(),
+                    "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 5)},
     }
 
 
