@@ -88,6 +88,55 @@ def test_bvh_matches_brute_force_bit_exact(which):
     assert ((tri_b >= 0) == (tri_o >= 0)).mean() > 0.999
 
 
+@pytest.mark.parametrize("which", ["torus", "sdf"])
+def test_bvh_exact_on_box_boundaries(which):
+    """Rays that meet leaf boxes exactly at their faces, edges and corners:
+    rays aimed at mesh vertices (equal-t ties between the triangles sharing the
+    vertex), rays leaving a vertex along a mesh edge, axis-aligned rays (zero
+    direction components) and rays starting on a vertex.  The traversal's
+    rounded slab test must keep every box the exact ray touches, so the BVH
+    result equals brute force bit for bit."""
+    dev = device()
+    if which == "torus":
+        V, F = synth.displaced_torus(seed=2, nu=160, nv=80)
+    else:
+        V, F = synth.sdf_union_mesh(seed=3, res=48)
+    V32 = V.astype(np.float32)
+    rng = np.random.default_rng(7)
+    n = 8000
+    vi = rng.integers(0, len(V32), n)
+    o1 = rng.normal(size=(n, 3)).astype(np.float32) * 2.5
+    d1 = V32[vi] - o1                                          # through a vertex
+    fi = rng.integers(0, len(F), n)
+    o2 = V32[F[fi, 0]]
+    d2 = V32[F[fi, 1]] - V32[F[fi, 0]]                          # along an edge from a vertex
+    o3 = V32[rng.integers(0, len(V32), n)] + np.float32(0.0)
+    ax = rng.integers(0, 3, n)
+    d3 = np.zeros((n, 3), np.float32)
+    d3[np.arange(n), ax] = rng.choice([-1.0, 1.0], n)          # axis-aligned, from a vertex
+    o4 = rng.normal(size=(n, 3)).astype(np.float32) * 2.0
+    o4[np.arange(n), ax] = V32[vi, ax]                         # origin on a vertex's plane
+    d4 = np.zeros((n, 3), np.float32)
+    d4[np.arange(n), (ax + 1) % 3] = 1.0
+    o = np.concatenate([o1, o2, o3, o4]).astype(np.float32)
+    d = np.concatenate([d1, d2, d3, d4]).astype(np.float32)
+    keep = np.linalg.norm(d, axis=1) > 0
+    o, d = o[keep], d[keep]
+    m = B.Mesh(torch.from_numpy(V32).to(dev), torch.from_numpy(F).to(dev))
+    env = B.Env(torch.ones(4, 8, 3, device=dev))
+    sc = B.Scene(m, torch.ones(1, device=dev), torch.zeros(3, device=dev), env)
+    ot, dt = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+    tri_b, t_b, b_b = B.dt_intersect(sc, ot, dt, brute_force=False)
+    tri_f, t_f, b_f = B.dt_intersect(sc, ot, dt, brute_force=True)
+    tri_b, tri_f = tri_b.cpu().numpy(), tri_f.cpu().numpy()
+    _print(which, "boundary rays", len(o), "hits", (tri_f >= 0).mean())
+    assert (tri_b != -2).all(), "traversal stack overflow"
+    assert np.array_equal(tri_b, tri_f)
+    hit = tri_b >= 0
+    assert np.array_equal(t_b.cpu().numpy()[hit], t_f.cpu().numpy()[hit])
+    assert np.array_equal(b_b.cpu().numpy()[hit], b_f.cpu().numpy()[hit])
+
+
 # ---------------------------------------------------------------- a6 environment
 def test_env_query_and_backward():
     dev = device()
