@@ -43,8 +43,10 @@ ADJ_PER_MISS = 48                    # 4 texels
 # for the kernel sources with this SHA-256; other sources report null.
 MEASURED_TRAFFIC = {
     "k_trace": {
+        # the traversal kernel and the tree builder whose tree it walks
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
-                    "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h"],
+                    "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h",
+                    "paper_2603_00413_amd/csrc/bvh.hip"],
         "sha256": "737b8faa0659be534abfcce55c77d8d00409f27b1af7fded29ada56295b26fa5",
         "bytes": (427599.8 * 2.0 + 85810.6) * 1024,
         # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:

@@ -10,6 +10,7 @@
 namespace {
 
 constexpr int SCAN_NB = 256;  // blocks (= partial sums) of the chunked device scan
+constexpr int TREELET_PASSES = 4;  // treelet restructuring passes after the box fit
 constexpr int SCAN_T = 256;
 
 // ------------------------------------------------------------------ block scans
@@ -455,6 +456,146 @@ __global__ void k_even(int32_t n_int, const BvhNode* nodes, int32_t* flag) {
   flag[i] = (dep & 1) == 0;
 }
 
+// ------------------------------------------------------------------ treelet restructuring
+// The Morton-order tree groups triangles by space-filling-curve position, not
+// by how much box surface the grouping costs, and the excess sits in the lower
+// levels.  Each pass takes the nodes X at one depth parity as roots of
+// disjoint two-level treelets: X, its internal children, and as treelet leaves
+// the grandchildren (or a child that is itself a triangle), 3 or 4 of them.
+// Among all binary trees over those leaves it keeps the one whose inner nodes
+// have the least total surface area (the root's box, and every box below the
+// treelet leaves, are unchanged), reusing X and its internal children as the
+// inner nodes.  Treelets of one pass share no inner node, and a thread writes
+// only its own inner nodes, the child fields of X (not X's parent link) and
+// the parent links of its treelet leaves, so the threads of a pass are
+// independent.  Alternating parities over passes lets changes travel.
+struct TBox {
+  v3 lo, hi;
+};
+__device__ __forceinline__ TBox tunion(const TBox& a, const TBox& b) {
+  return {vmin(a.lo, b.lo), vmax(a.hi, b.hi)};
+}
+__device__ __forceinline__ float tarea(const TBox& b) {
+  v3 e = vmax(b.hi - b.lo, mk3(0.f, 0.f, 0.f));
+  return 2.f * (e.x * e.y + e.y * e.z + e.z * e.x);
+}
+__device__ __forceinline__ TBox get_box(const BvhNode& n, int slot) {
+  const float* fp = (const float*)&n + slot * 6;
+  return {mk3(fp[0], fp[1], fp[2]), mk3(fp[3], fp[4], fp[5])};
+}
+
+// node i gets children (c0, b0), (c1, b1); with_parent: also its parent link
+__device__ __forceinline__ void set_node(BvhNode* nodes, int i, int c0, const TBox& b0, int c1,
+                                         const TBox& b1, bool with_parent, int parent) {
+  BvhNode* P = &nodes[i];
+  put_box(P, 0, b0.lo, b0.hi);
+  put_box(P, 1, b1.lo, b1.hi);
+  int* pd = (int*)&P->d;
+  pd[0] = c0;
+  pd[1] = c1;
+  if (with_parent) pd[2] = parent;
+}
+
+__device__ __forceinline__ void set_parent(BvhNode* nodes, int32_t* leaf_parent, int ref, int parent) {
+  if ((uint32_t)ref & DT_LEAF_BIT)
+    leaf_parent[(uint32_t)ref & ~DT_LEAF_BIT] = parent;
+  else
+    ((int*)&nodes[ref].d)[2] = parent;
+}
+
+__global__ void k_treelet(int32_t n_int, BvhNode* nodes, int32_t* leaf_parent, const int32_t* even,
+                          int want_even) {
+  const int X = blockIdx.x * blockDim.x + threadIdx.x;
+  if (X >= n_int || (even[X] != 0) != (want_even != 0)) return;
+  int ref[4], inner[3];
+  TBox box[4];
+  int n = 0, m = 1;
+  inner[0] = X;
+  {
+    const BvhNode nx = nodes[X];
+    const int* xd = (const int*)&nx.d;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int c = xd[k];
+      if ((uint32_t)c & DT_LEAF_BIT) {
+        ref[n] = c;
+        box[n++] = get_box(nx, k);
+      } else {
+        inner[m++] = c;
+        const BvhNode nc = nodes[c];
+        const int* cd = (const int*)&nc.d;
+        ref[n] = cd[0];
+        box[n++] = get_box(nc, 0);
+        ref[n] = cd[1];
+        box[n++] = get_box(nc, 1);
+      }
+    }
+  }
+  if (n < 3) return;
+  // candidate topologies, costs = summed areas of the inner nodes below X
+  if (n == 3) {
+    // ((a b) c): the pair with the least box area
+    int bi = 0, bj = 1, bk = 2;
+    float best = tarea(tunion(box[0], box[1]));
+    float c02 = tarea(tunion(box[0], box[2])), c12 = tarea(tunion(box[1], box[2]));
+    if (c02 < best) { best = c02; bi = 0; bj = 2; bk = 1; }
+    if (c12 < best) { best = c12; bi = 1; bj = 2; bk = 0; }
+    const int P1 = inner[1];
+    // current shape: X's internal child holds the pair
+    const TBox pb = tunion(box[bi], box[bj]);
+    set_node(nodes, P1, ref[bi], box[bi], ref[bj], box[bj], true, X);
+    set_node(nodes, X, P1, pb, ref[bk], box[bk], false, 0);
+    set_parent(nodes, leaf_parent, ref[bi], P1);
+    set_parent(nodes, leaf_parent, ref[bj], P1);
+    set_parent(nodes, leaf_parent, ref[bk], X);
+    return;
+  }
+  // four leaves: 3 balanced trees ((a b)(c d)) and 12 chains (((a b) c) d)
+  float pa[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j) pa[i][j] = tarea(tunion(box[i], box[j]));
+  // the current tree is balanced with pairs (0 1)(2 3)
+  float best = pa[0][1] + pa[2][3];
+  int kind = 0, a = 0, b = 1, c = 2, d = 3;
+  if (pa[0][2] + pa[1][3] < best) { best = pa[0][2] + pa[1][3]; kind = 0; a = 0; b = 2; c = 1; d = 3; }
+  if (pa[0][3] + pa[1][2] < best) { best = pa[0][3] + pa[1][2]; kind = 0; a = 0; b = 3; c = 1; d = 2; }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = i + 1; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (k == i || k == j) continue;
+        const int l = 6 - i - j - k;
+        const float cost = pa[i][j] + tarea(tunion(tunion(box[i], box[j]), box[k]));
+        if (cost < best) { best = cost; kind = 1; a = i; b = j; c = k; d = l; }
+      }
+  if (kind == 0 && a == 0 && b == 1) return;  // already the best
+  const int P1 = inner[1], P2 = inner[2];
+  const TBox ab = tunion(box[a], box[b]);
+  if (kind == 0) {
+    const TBox cd = tunion(box[c], box[d]);
+    set_node(nodes, P1, ref[a], box[a], ref[b], box[b], true, X);
+    set_node(nodes, P2, ref[c], box[c], ref[d], box[d], true, X);
+    set_node(nodes, X, P1, ab, P2, cd, false, 0);
+    set_parent(nodes, leaf_parent, ref[a], P1);
+    set_parent(nodes, leaf_parent, ref[b], P1);
+    set_parent(nodes, leaf_parent, ref[c], P2);
+    set_parent(nodes, leaf_parent, ref[d], P2);
+  } else {
+    const TBox abc = tunion(ab, box[c]);
+    set_node(nodes, P2, ref[a], box[a], ref[b], box[b], true, P1);
+    set_node(nodes, P1, P2, ab, ref[c], box[c], true, X);
+    set_node(nodes, X, P1, abc, ref[d], box[d], false, 0);
+    set_parent(nodes, leaf_parent, ref[a], P2);
+    set_parent(nodes, leaf_parent, ref[b], P2);
+    set_parent(nodes, leaf_parent, ref[c], P1);
+    set_parent(nodes, leaf_parent, ref[d], X);
+  }
+}
+
 // Exponent e of the quantization step 2^e of one axis of a node box [lo, hi]:
 // 254 steps must span the box (with the origin rounded down to a multiple of
 // the step, 255 then reach past hi), and every p + q 2^e, q in [0, 255], must be
@@ -719,6 +860,14 @@ extern "C" dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, 
   }
   hipLaunchKernelGGL(k_fit, dim3(dt_blocks(nf, 256)), dim3(256), 0, s, V, F, nv, vi, nf, nodes,
                      lpar, w.arrive, w.acc, leaves);
+  // treelet restructuring: even-depth roots, then odd, twice
+  if (nf > 2) {
+    for (int pass = 0; pass < TREELET_PASSES; ++pass) {
+      hipLaunchKernelGGL(k_even, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes, w.flag4);
+      hipLaunchKernelGGL(k_treelet, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes, lpar,
+                         w.flag4, (pass & 1) == 0 ? 1 : 0);
+    }
+  }
   hipLaunchKernelGGL(k_depth, dim3(dt_blocks(nf, 256)), dim3(256), 0, s, nf, nodes, lpar, hdr);
   DT_CHECK_LAUNCH();
   // 4-wide traversal tree
