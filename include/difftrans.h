@@ -87,7 +87,9 @@ dt_status dt_bvh_bytes(int32_t nv, int32_t nf, size_t* bvh_bytes, size_t* ws_byt
  * normals, vertex normals (Eq. 13: normalised sum of the unit normals of the
  * incident faces, in ascending face order, zero-area faces skipped), and a
  * linear BVH (63-bit Morton codes of face centroids, stable radix sort, binary
- * radix tree with index tie-break, bottom-up box fit).  Call again whenever V
+ * radix tree with index tie-break, bottom-up box fit, then small treelets
+ * restructured for least box surface area, and a quantized 4-wide tree
+ * collapsed from it for traversal).  Call again whenever V
  * changes.  Face indices must lie in [0, nv) (checked on the device only
  * through DT_FLAG results, not here: the caller guarantees it). */
 dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, int32_t nf,
