@@ -86,7 +86,8 @@ dt_status dt_bvh_bytes(int32_t nv, int32_t nf, size_t* bvh_bytes, size_t* ws_byt
 /* Build the scene acceleration data from V [nv][3] and F [nf][3]: unit face
  * normals, vertex normals (Eq. 13: normalised sum of the unit normals of the
  * incident faces, in ascending face order, zero-area faces skipped), and a
- * linear BVH (63-bit Morton codes of face centroids, stable radix sort, binary
+ * linear BVH (63-bit Morton codes of face centroids, their top 32 bits up to
+ * 2^20 faces, stable radix sort, binary
  * radix tree with index tie-break, bottom-up box fit, then small treelets
  * restructured for least box surface area, and a quantized 4-wide tree
  * collapsed from it for traversal).  Call again whenever V

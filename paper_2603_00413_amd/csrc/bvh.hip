@@ -202,8 +202,10 @@ __device__ __forceinline__ uint32_t quant21(float c, float lo, float ext) {
   return (uint32_t)q;
 }
 
+// keys: 63-bit Morton codes of the centroids (21 bits per axis) shifted right
+// by `drop` bits (31 keeps the top 32, about 11 bits per axis)
 __global__ void k_morton(const float* V, const int32_t* F, int32_t nf, int32_t nv, const float* part,
-                         int nparts,
+                         int nparts, int drop,
                          uint64_t* keys, int32_t* vals, BvhHeader* hdr) {
   __shared__ float bb[6];
   if (threadIdx.x < 6) {
@@ -228,7 +230,7 @@ __global__ void k_morton(const float* V, const int32_t* F, int32_t nf, int32_t n
   uint32_t qx = quant21(c.x, bb[0], bb[3] - bb[0]);
   uint32_t qy = quant21(c.y, bb[1], bb[4] - bb[1]);
   uint32_t qz = quant21(c.z, bb[2], bb[5] - bb[2]);
-  keys[f] = (spread21(qx) << 2) | (spread21(qy) << 1) | spread21(qz);
+  keys[f] = ((spread21(qx) << 2) | (spread21(qy) << 1) | spread21(qz)) >> drop;
   vals[f] = f;
 }
 
@@ -830,14 +832,17 @@ extern "C" dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, 
   DT_CHECK_LAUNCH();
   // Morton codes of face centroids
   hipLaunchKernelGGL(k_bounds, dim3(NBB), dim3(256), 0, s, V, F, nf, nv, w.bpart);
+  // up to 2^20 triangles the top 32 bits of the code order them finely enough
+  // (ties fall back to the face index) and halve the sort
+  const int key_bits = nf <= (1 << 20) ? 32 : 64;
   hipLaunchKernelGGL(k_morton, dim3(dt_blocks(nf, 256)), dim3(256), 0, s, V, F, nf, nv, w.bpart, NBB,
-                     w.k0, w.v0, hdr);
+                     key_bits == 32 ? 31 : 0, w.k0, w.v0, hdr);
   DT_CHECK_LAUNCH();
-  // stable LSD radix sort of (key, face), 8 passes of 8 bits (63-bit keys)
+  // stable LSD radix sort of (key, face), passes of 8 bits
   int nt = rs_tiles(nf);
   uint64_t *ki = w.k0, *ko = w.k1;
   int32_t *vi = w.v0, *vo = w.v1;
-  for (int shift = 0; shift < 64; shift += 8) {
+  for (int shift = 0; shift < key_bits; shift += 8) {
     hipLaunchKernelGGL(k_rs_hist, dim3(nt), dim3(RS_T), 0, s, ki, nf, shift, w.hist, nt);
     if (dt_status st = dt_scan_exclusive_i32(w.hist, w.hist, 256 * nt, w.scanp, s)) return st;
     hipLaunchKernelGGL(k_rs_scatter, dim3(nt), dim3(RS_T), 0, s, ki, vi, ko, vo, nf, shift, w.hist,

@@ -796,19 +796,33 @@ __global__ void __launch_bounds__(FR_T) k_face_reduce(int32_t nf, const FaceRec*
   }
 }
 
-// after the last generation: each face corner's totals go to its vertex
-__global__ void k_face_to_vertex(SceneDev sc, const float* fg, float* dV, float* dN) {
-  const int64_t n = 3 * (int64_t)sc.nf;
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    const float* q = fg + 6 * c;
-    const v3 pv = mk3(q[0], q[1], q[2]), nv = mk3(q[3], q[4], q[5]);
-    const bool has_p = pv.x != 0.f || pv.y != 0.f || pv.z != 0.f;
-    const bool has_n = nv.x != 0.f || nv.y != 0.f || nv.z != 0.f;
-    if (!has_p && !has_n) continue;
-    const int v = vclampi(sc.F[c], sc.nv);
-    if (has_p) atomic_add3(dV, v, pv);
-    if (has_n && dN) atomic_add3(dN, v, nv);
+// after the last generation: each vertex sums the totals of the face corners
+// it occupies, over its incident-face list (ascending face order, a face
+// listed once per corner it holds), so no atomics and a fixed summation order
+__global__ void k_vertex_gather(BvhView bv, const int32_t* F, const float* fg, float* dV, float* dN) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= bv.nv) return;
+  v3 p = mk3(0.f, 0.f, 0.f), nn = p;
+  int prev = -1;
+  for (int k = bv.csr_off[v]; k < bv.csr_off[v + 1]; ++k) {
+    const int f = bv.csr_idx[k];
+    if (f == prev) continue;  // every corner of this face holding v was taken below
+    prev = f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (F[3 * f + c] != v) continue;
+      const float* q = fg + 6 * (3 * (int64_t)f + c);
+      p += mk3(q[0], q[1], q[2]);
+      nn += mk3(q[3], q[4], q[5]);
+    }
+  }
+  dV[3 * v] += p.x;
+  dV[3 * v + 1] += p.y;
+  dV[3 * v + 2] += p.z;
+  if (dN) {
+    dN[3 * v] += nn.x;
+    dN[3 * v + 1] += nn.y;
+    dN[3 * v + 2] += nn.z;
   }
 }
 
@@ -1382,9 +1396,8 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
   }
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_T), 0, s, red, nred, d_ior, d_sigma);
-  hipLaunchKernelGGL(k_face_to_vertex, dim3(dt_blocks(3 * (int64_t)scene->nf, 256) < 4096
-                                                ? dt_blocks(3 * (int64_t)scene->nf, 256) : 4096),
-                     dim3(256), 0, s, sc, fg, dV, dN);
+  hipLaunchKernelGGL(k_vertex_gather, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, sc.F, fg,
+                     dV, dN);
   hipLaunchKernelGGL(k_nbwd_vertex, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, dN, sbar);
   hipLaunchKernelGGL(k_nbwd_face, dim3(dt_blocks(scene->nf, 256)), dim3(256), 0, s, sc.bvh, sc.V, sc.F,
                      sbar, dV);
