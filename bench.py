@@ -47,12 +47,12 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h",
                     "paper_2603_00413_amd/csrc/bvh.hip"],
-        "sha256": "737b8faa0659be534abfcce55c77d8d00409f27b1af7fded29ada56295b26fa5",
-        "bytes": (427599.8 * 2.0 + 85810.6) * 1024,
+        "sha256": "8ef46d8cc3db33c84c4a92f08fdd2f8b58640dd83a9c84642e9066285f8db5bb",
+        "bytes": (424496.5 * 2.0 + 85747.6) * 1024,
         # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:
         # wave-level VALU instructions per launch, and the share of lanes active
         # in them
-        "valu_insts": 2.938e8,
+        "valu_insts": 2.605e8,
         "lane_utilization": 0.62,
     },
 }
