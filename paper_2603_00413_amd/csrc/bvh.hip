@@ -204,27 +204,29 @@ __device__ __forceinline__ uint32_t quant21(float c, float lo, float ext) {
 
 // keys: 63-bit Morton codes of the centroids (21 bits per axis) shifted right
 // by `drop` bits (31 keeps the top 32, about 11 bits per axis)
-__global__ void k_morton(const float* V, const int32_t* F, int32_t nf, int32_t nv, const float* part,
-                         int nparts, int drop,
-                         uint64_t* keys, int32_t* vals, BvhHeader* hdr) {
-  __shared__ float bb[6];
-  if (threadIdx.x < 6) {
-    int k = threadIdx.x;
-    float r = k < 3 ? INFINITY : -INFINITY;
-    for (int p = 0; p < nparts; ++p) {
-      float x = part[p * 6 + k];
-      r = k < 3 ? fminf(r, x) : fmaxf(r, x);
-    }
-    bb[k] = r;
-  }
+// the scene bounds of the centroids from the per-block partials (one block of
+// NBB threads), into the header
+__global__ void __launch_bounds__(NBB) k_bounds_final(const float* part, BvhHeader* hdr) {
+  __shared__ float sh[6][NBB];
+  const int t = threadIdx.x;
+  for (int k = 0; k < 6; ++k) sh[k][t] = part[t * 6 + k];
   __syncthreads();
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x < 6) {
-    if (threadIdx.x < 3)
-      hdr->lo[threadIdx.x] = bb[threadIdx.x];
-    else
-      hdr->hi[threadIdx.x - 3] = bb[threadIdx.x];
+  for (int st = NBB / 2; st > 0; st >>= 1) {
+    if (t < st)
+      for (int k = 0; k < 3; ++k) {
+        sh[k][t] = fminf(sh[k][t], sh[k][t + st]);
+        sh[3 + k][t] = fmaxf(sh[3 + k][t], sh[3 + k][t + st]);
+      }
+    __syncthreads();
   }
+  if (t < 3) hdr->lo[t] = sh[t][0];
+  if (t >= 3 && t < 6) hdr->hi[t - 3] = sh[t][0];
+}
+
+__global__ void k_morton(const float* V, const int32_t* F, int32_t nf, int32_t nv, int drop,
+                         const BvhHeader* hdr, uint64_t* keys, int32_t* vals) {
+  const float bb[6] = {hdr->lo[0], hdr->lo[1], hdr->lo[2], hdr->hi[0], hdr->hi[1], hdr->hi[2]};
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
   v3 c = centroid(V, F, f, nv);
   uint32_t qx = quant21(c.x, bb[0], bb[3] - bb[0]);
@@ -432,22 +434,10 @@ __global__ void k_fit(const float* V, const int32_t* F, int32_t nv, const int32_
   }
 }
 
-__global__ void k_depth(int n, const BvhNode* nodes, const int32_t* leaf_parent, BvhHeader* hdr) {
-  int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  int dep = 1;
-  if (n > 1) {
-    int p = leaf_parent[j];
-    while (p >= 0 && p < n - 1 && dep < 256) {
-      ++dep;
-      p = ((const int*)&nodes[p].d)[2];
-    }
-  }
-  atomicMax(&hdr->depth, dep);
-}
-
 // 1 for an internal node at even depth (root = 0), else 0: walk to the root.
-__global__ void k_even(int32_t n_int, const BvhNode* nodes, int32_t* flag) {
+// With hdr, also the tree height (root = 1): the deepest internal node has a
+// leaf child one level below it.
+__global__ void k_even(int32_t n_int, const BvhNode* nodes, int32_t* flag, BvhHeader* hdr) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_int) return;
   int dep = 0, p = i;
@@ -456,6 +446,7 @@ __global__ void k_even(int32_t n_int, const BvhNode* nodes, int32_t* flag) {
     ++dep;
   }
   flag[i] = (dep & 1) == 0;
+  if (hdr) atomicMax(&hdr->depth, dep + 2);
 }
 
 // ------------------------------------------------------------------ treelet restructuring
@@ -702,7 +693,7 @@ __global__ void k_header(BvhHeader* hdr, int32_t nv, int32_t nf) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     hdr->nv = nv;
     hdr->nf = nf;
-    hdr->depth = 0;
+    hdr->depth = nf == 1 ? 1 : 0;  // larger trees: the last depth-parity pass
     hdr->pad0 = 0;
   }
 }
@@ -835,8 +826,9 @@ extern "C" dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, 
   // up to 2^20 triangles the top 32 bits of the code order them finely enough
   // (ties fall back to the face index) and halve the sort
   const int key_bits = nf <= (1 << 20) ? 32 : 64;
-  hipLaunchKernelGGL(k_morton, dim3(dt_blocks(nf, 256)), dim3(256), 0, s, V, F, nf, nv, w.bpart, NBB,
-                     key_bits == 32 ? 31 : 0, w.k0, w.v0, hdr);
+  hipLaunchKernelGGL(k_bounds_final, dim3(1), dim3(NBB), 0, s, w.bpart, hdr);
+  hipLaunchKernelGGL(k_morton, dim3(dt_blocks(nf, 256)), dim3(256), 0, s, V, F, nf, nv,
+                     key_bits == 32 ? 31 : 0, hdr, w.k0, w.v0);
   DT_CHECK_LAUNCH();
   // stable LSD radix sort of (key, face), passes of 8 bits
   int nt = rs_tiles(nf);
@@ -868,17 +860,18 @@ extern "C" dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, 
   // treelet restructuring: even-depth roots, then odd, twice
   if (nf > 2) {
     for (int pass = 0; pass < TREELET_PASSES; ++pass) {
-      hipLaunchKernelGGL(k_even, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes, w.flag4);
+      hipLaunchKernelGGL(k_even, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes, w.flag4,
+                         (BvhHeader*)nullptr);
       hipLaunchKernelGGL(k_treelet, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes, lpar,
                          w.flag4, (pass & 1) == 0 ? 1 : 0);
     }
   }
-  hipLaunchKernelGGL(k_depth, dim3(dt_blocks(nf, 256)), dim3(256), 0, s, nf, nodes, lpar, hdr);
   DT_CHECK_LAUNCH();
   // 4-wide traversal tree
   if (nf > 1) {
     Bvh4Node* nodes4 = (Bvh4Node*)(b + L.nodes4);
-    hipLaunchKernelGGL(k_even, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes, w.flag4);
+    hipLaunchKernelGGL(k_even, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes, w.flag4,
+                       hdr);
     if (dt_status st = dt_scan_exclusive_i32(w.flag4, w.idx4, nf - 1, w.scanp, s)) return st;
     hipLaunchKernelGGL(k_collapse, dim3(dt_blocks(nf - 1, 256)), dim3(256), 0, s, nf - 1, nodes,
                        w.flag4, w.idx4, nodes4, bvh4_cap(nf));

@@ -88,6 +88,34 @@ def test_bvh_matches_brute_force_bit_exact(which):
     assert ((tri_b >= 0) == (tri_o >= 0)).mean() > 0.999
 
 
+@pytest.mark.parametrize("nf", [1, 2, 3, 5, 17])
+def test_bvh_tiny_meshes(nf):
+    """Degenerate tree shapes: a single triangle (no inner node), two (a root
+    with two leaves), and a few (treelets of fewer than four leaves, 4-wide
+    nodes with two or three children).  BVH equals brute force bit for bit."""
+    dev = device()
+    rng = np.random.default_rng(nf)
+    V = rng.uniform(-1.0, 1.0, size=(3 * nf, 3)).astype(np.float32)
+    F = np.arange(3 * nf, dtype=np.int32).reshape(nf, 3)
+    n = 4096
+    o = rng.normal(size=(n, 3)).astype(np.float32) * 2.5
+    tgt = V[rng.integers(0, 3 * nf, n)] * np.float32(0.9)
+    d = (tgt - o).astype(np.float32)
+    m = B.Mesh(torch.from_numpy(V).to(dev), torch.from_numpy(F).to(dev))
+    env = B.Env(torch.ones(4, 8, 3, device=dev))
+    sc = B.Scene(m, torch.ones(1, device=dev), torch.zeros(3, device=dev), env)
+    ot, dt = torch.from_numpy(o).to(dev), torch.from_numpy(d).to(dev)
+    tri_b, t_b, b_b = B.dt_intersect(sc, ot, dt, brute_force=False)
+    tri_f, t_f, b_f = B.dt_intersect(sc, ot, dt, brute_force=True)
+    tri_b, tri_f = tri_b.cpu().numpy(), tri_f.cpu().numpy()
+    _print("nf", nf, "hits", (tri_f >= 0).mean())
+    assert (tri_f >= 0).any()
+    assert np.array_equal(tri_b, tri_f)
+    hit = tri_b >= 0
+    assert np.array_equal(t_b.cpu().numpy()[hit], t_f.cpu().numpy()[hit])
+    assert np.array_equal(b_b.cpu().numpy()[hit], b_f.cpu().numpy()[hit])
+
+
 @pytest.mark.parametrize("which", ["torus", "sdf"])
 def test_bvh_exact_on_box_boundaries(which):
     """Rays that meet leaf boxes exactly at their faces, edges and corners:
