@@ -238,13 +238,24 @@ __global__ void k_stats(const Counters* c, int D, const BvhHeader* hdr, int64_t*
 // ------------------------------------------------------------------ ray generation (a3)
 // Pinhole camera rays through pixel centres; 8x8 pixel tiles are laid out
 // consecutively in the queue so that a wave starts on a coherent patch.
-__global__ void k_raygen(Gen q, CamDev c) {
-  int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t n = (int64_t)c.W * c.H;
-  if (r >= n) return;
+// up to CAM_BATCH cameras per launch, in queue order: thread r of the launch
+// writes ray r of the batch (camera k starts at cam[k].base - cam[0].base)
+constexpr int CAM_BATCH = 8;
+struct CamBatch {
+  CamDev cam[CAM_BATCH];
+  int n;
+};
+
+__global__ void k_raygen(Gen q, CamBatch cb, int64_t total) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= total) return;
+  const int64_t b0 = cb.cam[0].base;
+  int k = 0;
+  while (k + 1 < cb.n && r >= cb.cam[k + 1].base - b0) ++k;
+  const CamDev& c = cb.cam[k];
   int x, y;
-  v3 d = camera_ray(c, r, x, y);
-  int64_t i = c.base + r;
+  v3 d = camera_ray(c, r - (c.base - b0), x, y);
+  int64_t i = b0 + r;
   int pix = (int)(c.pixel_offset + (int64_t)y * c.W + x);
   q.o[i] = make_float4(c.eye[0], c.eye[1], c.eye[2], __int_as_float(-1));
   q.d[i] = make_float4(d.x, d.y, d.z, __int_as_float(pix));
@@ -1062,15 +1073,19 @@ dt_status emit_rays(const dt_rays* r, Gen g0, hipStream_t s) {
     return DT_OK;
   }
   int64_t base = 0;
-  for (int c = 0; c < r->n_cameras; ++c) {
-    const dt_camera& cam = r->cameras[c];
-    CamDev cd;
-    if (dt_status st = make_camera(cam, c, cd)) return st;
-    cd.base = base;
-    int64_t np = (int64_t)cam.width * cam.height;
-    hipLaunchKernelGGL(k_raygen, dim3(dt_blocks(np, 256)), dim3(256), 0, s, g0, cd);
+  for (int c0 = 0; c0 < r->n_cameras; c0 += CAM_BATCH) {
+    CamBatch cb;
+    cb.n = r->n_cameras - c0 < CAM_BATCH ? r->n_cameras - c0 : CAM_BATCH;
+    const int64_t b0 = base;
+    for (int k = 0; k < cb.n; ++k) {
+      const dt_camera& cam = r->cameras[c0 + k];
+      if (dt_status st = make_camera(cam, c0 + k, cb.cam[k])) return st;
+      cb.cam[k].base = base;
+      base += (int64_t)cam.width * cam.height;
+    }
+    for (int k = cb.n; k < CAM_BATCH; ++k) cb.cam[k] = cb.cam[0];
+    hipLaunchKernelGGL(k_raygen, dim3(dt_blocks(base - b0, 256)), dim3(256), 0, s, g0, cb, base - b0);
     DT_CHECK_LAUNCH();
-    base += np;
   }
   return DT_OK;
 }
