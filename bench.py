@@ -47,8 +47,8 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h",
                     "paper_2603_00413_amd/csrc/bvh.hip"],
-        "sha256": "8ef46d8cc3db33c84c4a92f08fdd2f8b58640dd83a9c84642e9066285f8db5bb",
-        "bytes": (424496.5 * 2.0 + 85747.6) * 1024,
+        "sha256": "5fd9df8779babbe8b58a00fba1c2c3b490a1aa6f65b0fc71ca456f5e9a2248c1",
+        "bytes": (423459.7 * 2.0 + 85748.7) * 1024,
         # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:
         # wave-level VALU instructions per launch, and the share of lanes active
         # in them
