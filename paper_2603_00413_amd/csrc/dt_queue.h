@@ -12,11 +12,47 @@ struct Gen {
   int2* child;
 };
 
+// Work distribution of the traversal kernel.  A generation's queue is cut into
+// DT_WORK_PARTS contiguous parts of 64-ray batches, each with a cursor on a
+// cache line of its own.  Every wave claims its next batch with an atomic add
+// on a cursor and waits for the result, so with one cursor for the whole
+// queue the thousands of resident waves queue up on a single address; spread
+// over separate lines the claims proceed in parallel.  (Cursors packed into
+// one line were slower still than a single one.)  Workgroup b starts on part
+// b % DT_WORK_PARTS, which with the device's round-robin hand-out of
+// workgroups to its 8 dies keeps each die on one region of the queue.
+constexpr int DT_WORK_PARTS = 8;
+struct alignas(128) WorkPart {
+  uint32_t next;  // batches of the part handed out so far
+  uint32_t pad[31];
+};
+
+// Next batch for the calling wave (all 64 lanes together): true with its index
+// in batch, false once every part is drained.  nb: batches in the queue; p:
+// the part being drained, starting at x0 = blockIdx.x % DT_WORK_PARTS.  Each
+// part is visited once, so a wave returns false after at most DT_WORK_PARTS
+// empty claims.
+__device__ __forceinline__ bool claim_batch(WorkPart* wp, uint32_t nb, uint32_t x0, uint32_t& p,
+                                            uint32_t& batch) {
+  while (true) {
+    const uint32_t lo = (uint32_t)(((uint64_t)nb * p) / DT_WORK_PARTS);
+    const uint32_t cnt = (uint32_t)(((uint64_t)nb * (p + 1u)) / DT_WORK_PARTS) - lo;
+    uint32_t k = 0;
+    if ((threadIdx.x & 63u) == 0u) k = atomicAdd(&wp[p].next, 1u);
+    k = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
+    if (k < cnt) {
+      batch = lo + k;
+      return true;
+    }
+    p = (p + 1u) % DT_WORK_PARTS;
+    if (p == x0) return false;
+  }
+}
+
 // Device-side counters of a trace (also the tape header).
 struct Counters {
   uint32_t count[DT_MAX_DEPTH + 2];  // rays in generation g
   uint32_t nrefl[DT_MAX_DEPTH + 2];  // reflected children emitted by g (refracted follow them)
-  uint32_t work[DT_MAX_DEPTH + 2];   // work-queue cursor of the traversal kernel
   uint32_t hits[DT_MAX_DEPTH + 2];   // rays of g that hit the mesh
   uint32_t nmiss[DT_MAX_DEPTH + 2];  // length of the miss list of g (MLP environment)
   uint32_t dropped;

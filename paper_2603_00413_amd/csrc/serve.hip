@@ -41,6 +41,7 @@ struct ServeState {
   Counters ctr;            // count[0] = live rays of the current queue
   long long traced;        // rays intersected since the last reset
   long long dropped;
+  WorkPart wp[DT_WORK_PARTS];  // traversal work cursors of the current queue
 };
 
 constexpr int SERVE_TRACE_BLOCKS = 256 * 4 * 7;
@@ -96,7 +97,8 @@ __global__ void k_serve_reset(ServeState* st, unsigned long long* p0, unsigned l
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i == 0) {
     Counters& c = st->ctr;
-    for (int g = 0; g < DT_MAX_DEPTH + 2; ++g) c.count[g] = c.nrefl[g] = c.work[g] = c.hits[g] = c.nmiss[g] = 0;
+    for (int g = 0; g < DT_MAX_DEPTH + 2; ++g) c.count[g] = c.nrefl[g] = c.hits[g] = c.nmiss[g] = 0;
+    for (int x = 0; x < DT_WORK_PARTS; ++x) st->wp[x].next = 0;
     c.dropped = 0;
     st->traced = 0;
     st->dropped = 0;
@@ -142,11 +144,11 @@ __global__ void __launch_bounds__(TBS, 7) k_serve_trace(const ServeTables* T, Ge
   Counters* ctr = &st->ctr;
   const uint32_t n = ctr->count[0];
   const int lane = threadIdx.x & 63;
-  while (true) {
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&ctr->work[0], 64u);
-    base = (uint32_t)__shfl((int)base, 0);
-    if (base >= n) break;
+  const uint32_t nb = (n + 63u) / 64u;
+  const uint32_t x0 = blockIdx.x % (unsigned)DT_WORK_PARTS;
+  uint32_t p = x0, batch = 0;
+  while (claim_batch(st->wp, nb, x0, p, batch)) {
+    const uint32_t base = batch * 64u;
     uint32_t i = base + lane;
     const bool active = i < n;
     bool has_r = false, has_t = false;
@@ -333,8 +335,7 @@ __global__ void k_serve_advance(ServeState* st) {
     c.count[0] = c.count[1];
     c.count[1] = 0;
     c.nrefl[0] = 0;
-    c.work[0] = 0;
-    c.work[1] = 0;
+    for (int x = 0; x < DT_WORK_PARTS; ++x) st->wp[x].next = 0;
   }
 }
 

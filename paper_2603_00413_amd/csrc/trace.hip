@@ -50,7 +50,7 @@ struct Plan {
   size_t t_hit[DT_MAX_DEPTH + 1], t_code[DT_MAX_DEPTH + 1], t_child[DT_MAX_DEPTH + 1];
   size_t tape_bytes;
   // workspace
-  size_t w_ctr, w_part0, w_part1;
+  size_t w_ctr, w_parts, w_part0, w_part1;
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
   size_t w_dN, w_sbar, w_red, w_miss, w_ovf;
@@ -110,6 +110,8 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = 0;
   P.w_ctr = o;
   o = dt_align(o + sizeof(Counters));
+  P.w_parts = o;  // traversal work cursors, per generation and part
+  o = dt_align(o + sizeof(WorkPart) * DT_WORK_PARTS * (DT_MAX_DEPTH + 2));
   P.w_part0 = o;
   o = dt_align(o + 8 * ((size_t)P.maxchunks + 1));
   P.w_part1 = o;
@@ -184,12 +186,12 @@ __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
     p[i] = 0ull;
 }
 
-__global__ void k_init_counters(Counters* c, uint32_t n0) {
+__global__ void k_init_counters(Counters* c, uint32_t n0, WorkPart* wp) {
+  for (int i = threadIdx.x; i < (DT_MAX_DEPTH + 2) * DT_WORK_PARTS; i += blockDim.x) wp[i].next = 0;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     for (int g = 0; g < DT_MAX_DEPTH + 2; ++g) {
       c->count[g] = 0;
       c->nrefl[g] = 0;
-      c->work[g] = 0;
       c->hits[g] = 0;
       c->nmiss[g] = 0;
     }
@@ -201,10 +203,7 @@ __global__ void k_init_counters(Counters* c, uint32_t n0) {
 __global__ void k_load_counters(Counters* c, const Counters* src) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *c = *src;
-    for (int g = 0; g < DT_MAX_DEPTH + 2; ++g) {
-      c->work[g] = 0;
-      c->nmiss[g] = 0;
-    }
+    for (int g = 0; g < DT_MAX_DEPTH + 2; ++g) c->nmiss[g] = 0;
   }
 }
 
@@ -212,8 +211,10 @@ __global__ void k_save_counters(Counters* dst, const Counters* c) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *c;
 }
 
-__global__ void k_reset_work(Counters* c, int g) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) c->work[g] = 0;
+// cursors of generations g and later, before they are traced again
+__global__ void k_reset_work(int g, WorkPart* wp) {
+  for (int i = g * DT_WORK_PARTS + threadIdx.x; i < (DT_MAX_DEPTH + 2) * DT_WORK_PARTS; i += blockDim.x)
+    wp[i].next = 0;
 }
 
 __global__ void k_stats(const Counters* c, int D, const BvhHeader* hdr, int64_t* stats) {
@@ -292,17 +293,18 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
                                               int32_t* flags, unsigned long long* sig,
-                                              int accumulate, uint2* ovf) {
+                                              int accumulate, uint2* ovf, WorkPart* wp) {
   __shared__ uint2 stk[DT_STACK_LDS * TB];
   __shared__ LeafQueue lq;
   uint2* gstk = ovf + (size_t)(blockIdx.x * TB + threadIdx.x) * (DT_STACK - DT_STACK_LDS);
   const uint32_t n = ctr->count[g];
   const int lane = threadIdx.x & 63;
-  while (true) {
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(&ctr->work[g], 64u);
-    base = (uint32_t)__shfl((int)base, 0);
-    if (base >= n) break;
+  const uint32_t nb = (n + 63u) / 64u;
+  const uint32_t x0 = blockIdx.x % (unsigned)DT_WORK_PARTS;
+  uint32_t p = x0, batch = 0;
+  wp += (size_t)g * DT_WORK_PARTS;
+  while (claim_batch(wp, nb, x0, p, batch)) {
+    const uint32_t base = batch * 64u;
     uint32_t i = base + lane;
     bool active = i < n;
     bool has_r = false, has_t = false, hit = false;
@@ -376,8 +378,8 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
 
 // ------------------------------------------------------------------ k_scan (compaction offsets)
 // Single block: exclusive scan of the per-chunk (reflect | refract << 32)
-// counts of generation g, next-generation count, reset of the other
-// partial array and of the next work cursor.
+// counts of generation g, next-generation count and reset of the other
+// partial array.
 __global__ void k_scan(Counters* ctr, int g, unsigned long long* part, unsigned long long* other,
                        int64_t other_n, int64_t cap_next) {
   __shared__ unsigned long long sh[1024];
@@ -407,7 +409,6 @@ __global__ void k_scan(Counters* ctr, int g, unsigned long long* part, unsigned 
     uint64_t tot = (uint64_t)nr + nt;
     ctr->nrefl[g] = nr;
     ctr->count[g + 1] = (uint32_t)(tot < (uint64_t)cap_next ? tot : (uint64_t)cap_next);
-    ctr->work[g + 1] = 0;
   }
 }
 
@@ -1097,13 +1098,13 @@ dt_status record(void* const* ev, int i, hipStream_t s) {
 }
 
 dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen nxt, Counters* ctr,
-                         unsigned long long* part_g, unsigned long long* part_other, float* rgb,
+                         WorkPart* wp, unsigned long long* part_g, unsigned long long* part_other, float* rgb,
                          float* wtrunc, int32_t* flags, unsigned long long* sig, int accumulate,
                          int write_next, void* const* events, void* const* mlp_events,
                          uint32_t* miss_list, uint2* ovf, hipStream_t s) {
   if (dt_status st = record(events, 2 * g, s)) return st;
   hipLaunchKernelGGL(k_trace, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
-                     rgb, wtrunc, flags, sig, accumulate, ovf);
+                     rgb, wtrunc, flags, sig, accumulate, ovf, wp);
   DT_CHECK_LAUNCH();
   if (dt_status st = record(events, 2 * g + 1, s)) return st;
   if (accumulate && sc.env.kind == DT_ENV_MLP) {
@@ -1250,7 +1251,7 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
   Counters* ctr = (Counters*)(W + P.w_ctr);
   unsigned long long* part[2] = {(unsigned long long*)(W + P.w_part0),
                                  (unsigned long long*)(W + P.w_part1)};
-  hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, s, ctr, (uint32_t)N);
+  hipLaunchKernelGGL(k_init_counters, dim3(1), dim3(64), 0, s, ctr, (uint32_t)N, (WorkPart*)(W + P.w_parts));
   if (dt_status st = zero_u64(part[0], P.maxchunks + 1, s)) return st;
   if (dt_status st = zero_f32(rgb, 3 * npix, s)) return st;
   if (dt_status st = zero_f32(wtrunc, 3 * npix, s)) return st;
@@ -1284,7 +1285,8 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
     Gen nxt = g < P.D ? gen_fwd(g + 1) : cur;
     void* const* ev = p->timing ? p->timing->trace_events : nullptr;
     void* const* mev = p->timing ? p->timing->mlp_events : nullptr;
-    if (dt_status st = run_generation(sc, P, g, cur, nxt, ctr, part[g & 1], part[(g + 1) & 1], rgb,
+    if (dt_status st = run_generation(sc, P, g, cur, nxt, ctr, (WorkPart*)(W + P.w_parts), part[g & 1],
+                                      part[(g + 1) & 1], rgb,
                                       wtrunc, flags, (unsigned long long*)path_sig, 1, 1, ev, mev,
                                       (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), s))
       return st;
@@ -1395,12 +1397,13 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
       seg[0].o = (float4*)(T + P.t_o[g0]);
       seg[0].d = (float4*)(T + P.t_d[g0]);
       seg[0].w = (float4*)(T + P.t_w[g0]);
-      hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, s, ctr, g0);
+      hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, s, g0, (WorkPart*)(W + P.w_parts));
       if (dt_status st = zero_u64(part[g0 & 1], P.maxchunks + 1, s)) return st;
       for (int g = g0; g <= g1; ++g) {
         int j = g - g0;
         Gen nxt = g < g1 ? seg[j + 1] : seg[j];
-        if (dt_status st = run_generation(sc, P, g, seg[j], nxt, ctr, part[g & 1], part[(g + 1) & 1],
+        if (dt_status st = run_generation(sc, P, g, seg[j], nxt, ctr, (WorkPart*)(W + P.w_parts),
+                                          part[g & 1], part[(g + 1) & 1],
                                           nullptr, nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0,
                                           nullptr, nullptr,
                                           (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), s))
