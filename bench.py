@@ -47,12 +47,12 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h",
                     "paper_2603_00413_amd/csrc/bvh.hip"],
-        "sha256": "5fd9df8779babbe8b58a00fba1c2c3b490a1aa6f65b0fc71ca456f5e9a2248c1",
-        "bytes": (423459.7 * 2.0 + 85748.7) * 1024,
+        "sha256": "189a4503f323d7d4b6ad16bb496a4714052957fbc8f6bc195adb290cef8c1f42",
+        "bytes": (320923.1 * 2.0 + 85783.4) * 1024,
         # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:
         # wave-level VALU instructions per launch, and the share of lanes active
         # in them
-        "valu_insts": 2.605e8,
+        "valu_insts": 2.610e8,
         "lane_utilization": 0.62,
     },
 }
