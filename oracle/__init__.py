@@ -44,12 +44,19 @@ class _Env(C.Structure):
                 ("weights", C.POINTER(C.c_double)), ("biases", C.POINTER(C.c_double))]
 
 
+class _Absorption(C.Structure):
+    _fields_ = [("mu", C.POINTER(C.c_double)), ("nx", C.c_int), ("ny", C.c_int),
+                ("nz", C.c_int), ("samples", C.c_int),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
 class _Scene(C.Structure):
     _fields_ = [("V", C.POINTER(C.c_double)), ("nv", C.c_int),
                 ("F", C.POINTER(C.c_int)), ("nf", C.c_int),
                 ("eta", C.c_double), ("sigma", C.c_double * 3),
                 ("env", C.POINTER(_Env)), ("max_depth", C.c_int),
-                ("terminal_env", C.c_int), ("t_eps", C.c_double), ("use_bvh", C.c_int)]
+                ("terminal_env", C.c_int), ("t_eps", C.c_double), ("use_bvh", C.c_int),
+                ("absorb", C.POINTER(_Absorption))]
 
 
 _lib = None
@@ -71,7 +78,7 @@ def lib():
         L.or_env_kink_margin.argtypes = [C.POINTER(_Env), dp, i64, dp]
         L.or_trace.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, ip,
                                C.POINTER(C.c_uint64), ip, C.POINTER(C.c_uint64)]
-        L.or_trace_grad.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, dp, dp, dp]
+        L.or_trace_grad.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, dp, dp, dp, dp]
         L.or_trace_tree.argtypes = [C.POINTER(_Scene), dp, dp, dp, C.c_int]
         L.or_num_threads.restype = C.c_int
         _lib = L
@@ -132,11 +139,30 @@ class Env:
         return out
 
 
+class Absorption:
+    """Spatially varying absorption rate: an RGB grid mu [nz, ny, nx, 3] over the
+    box [lo, hi], trilinear, S midpoint samples per interior segment."""
+
+    def __init__(self, mu, lo, hi, samples: int):
+        self.mu = _d(mu)
+        assert self.mu.ndim == 4 and self.mu.shape[3] == 3
+        self.lo = np.asarray(lo, np.float64).reshape(3)
+        self.hi = np.asarray(hi, np.float64).reshape(3)
+        self.samples = int(samples)
+        nz, ny, nx, _ = self.mu.shape
+        self.s = _Absorption()
+        self.s.mu = _p(self.mu)
+        self.s.nx, self.s.ny, self.s.nz, self.s.samples = nx, ny, nz, self.samples
+        for k in range(3):
+            self.s.lo[k], self.s.hi[k] = float(self.lo[k]), float(self.hi[k])
+
+
 class Scene:
     """Mesh + material + environment + tracing parameters for the oracle."""
 
     def __init__(self, V, F, eta, sigma, env: Env, max_depth: int,
-                 terminal_env: bool = False, t_eps: float = 1e-5, use_bvh: bool = True):
+                 terminal_env: bool = False, t_eps: float = 1e-5, use_bvh: bool = True,
+                 absorb: "Absorption | None" = None):
         self.V = _d(V).reshape(-1, 3)
         self.F = np.ascontiguousarray(F, dtype=np.int32).reshape(-1, 3)
         self.env = env
@@ -147,6 +173,7 @@ class Scene:
         self.terminal_env = bool(terminal_env)
         self.t_eps = float(t_eps)
         self.use_bvh = bool(use_bvh)
+        self.absorb = absorb
 
     def _s(self):
         s = _Scene()
@@ -160,11 +187,12 @@ class Scene:
         s.terminal_env = int(self.terminal_env)
         s.t_eps = self.t_eps
         s.use_bvh = int(self.use_bvh)
+        s.absorb = C.pointer(self.absorb.s) if self.absorb is not None else None
         return s
 
     def with_(self, **kw):
         sc = Scene(self.V, self.F, self.eta, self.sigma, self.env, self.max_depth,
-                   self.terminal_env, self.t_eps, self.use_bvh)
+                   self.terminal_env, self.t_eps, self.use_bvh, self.absorb)
         for k, v in kw.items():
             if k == "V":
                 v = _d(v).reshape(-1, 3)
@@ -191,7 +219,7 @@ class Scene:
         return {"rgb": rgb, "wtrunc": wt, "flags": fl, "hash": hs, "nseg": ns, "sig": sg}
 
     def trace_grad(self, o, d, grad_rgb):
-        """Returns dict(rgb, dV [nv,3], d_eta, d_sigma [3])."""
+        """Returns dict(rgb, dV [nv,3], d_eta, d_sigma [3], d_mu [nz,ny,nx,3] or None)."""
         o, d = _d(o).reshape(-1, 3), _d(d).reshape(-1, 3)
         g = _d(grad_rgb).reshape(-1, 3)
         n = len(o)
@@ -199,11 +227,12 @@ class Scene:
         dV = np.empty_like(self.V)
         de = np.zeros(1)
         ds = np.zeros(3)
+        dm = np.zeros_like(self.absorb.mu) if self.absorb is not None else None
         s = self._s()
         rc = lib().or_trace_grad(C.byref(s), _p(o), _p(d), n, _p(g), _p(rgb), _p(dV),
-                                 _p(de), _p(ds))
+                                 _p(de), _p(ds), _p(dm) if dm is not None else None)
         assert rc == 0, "or_trace_grad rejected its arguments"
-        return {"rgb": rgb, "dV": dV, "d_eta": float(de[0]), "d_sigma": ds}
+        return {"rgb": rgb, "dV": dV, "d_eta": float(de[0]), "d_sigma": ds, "d_mu": dm}
 
     def tree(self, o, d, max_rec: int = 4096):
         """Depth-first node records of one camera ray (list of dicts)."""

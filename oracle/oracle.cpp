@@ -14,9 +14,12 @@
 //     (Eq. 4-6), blended with the Fresnel weights R and T = 1 - R (Eq. 7-8),
 //     total internal reflection keeps only the reflected ray, and a hit
 //     reached from inside the object is attenuated by exp(-sigma t), the
-//     Beer-Lambert integral (Eq. 9-11) for a constant absorption rate;
+//     Beer-Lambert integral (Eq. 9-11) for a constant absorption rate, or,
+//     for a spatially varying rate mu_t(x) held in a trilinear RGB grid, the
+//     sum of mu_t at S midpoints of the segment times the step t / S (the
+//     quadrature of Eq. 11);
 //   * gradients of the rendered colours with respect to vertex positions,
-//     IoR and absorption rate, by plain reverse-mode automatic
+//     IoR and absorption rate (or grid values), by plain reverse-mode automatic
 //     differentiation (a Wengert tape per camera ray), with the discrete path
 //     (triangle ids, TIR branches, hit/miss, env texel cell) held fixed.
 //
@@ -165,6 +168,18 @@ typedef struct {
   const double* biases;     // MLP: concatenated per layer
 } or_env;
 
+// Spatially varying absorption rate (Eq. 11 and its quadrature): an RGB grid
+// of nx*ny*nz nodes, node (i, j, k) at lo + (i/(nx-1), j/(ny-1), k/(nz-1)) *
+// (hi - lo), value mu[((k*ny + j)*nx + i)*3 + c]; mu_t(x) is the trilinear
+// interpolant at x clamped into the box; an interior segment of length t from
+// o along d is attenuated by exp(-(t/S) sum_{s<S} mu_t(o + (s + 1/2)(t/S) d)).
+typedef struct {
+  const double* mu;
+  int nx, ny, nz;  // >= 2 each
+  int samples;     // S >= 1
+  double lo[3], hi[3];
+} or_absorption;
+
 typedef struct {
   const double* V;  // [nv*3]
   int nv;
@@ -177,6 +192,7 @@ typedef struct {
   int terminal_env;  // 0: truncated hit returns 0; 1: returns A * E(d)
   double t_eps;      // minimum hit distance
   int use_bvh;       // 1: BVH, 0: brute force over all triangles
+  const or_absorption* absorb;  // NULL: the constant rate sigma
 } or_scene;
 
 enum {
@@ -403,6 +419,10 @@ struct Ctx<double> {
   const Shared* sh;
   double eta;
   double sigma[3];
+  V3<double> mu(int node) const {
+    const double* m = sh->sc->absorb->mu + 3 * (size_t)node;
+    return {m[0], m[1], m[2]};
+  }
   V3<double> pos(int v) const {
     const double* p = sh->sc->V + 3 * v;
     return {p[0], p[1], p[2]};
@@ -423,6 +443,15 @@ struct Ctx<Var> {
   Var sigma[3];
   std::unordered_map<int, V3<Var>> P;   // vertex -> leaf position
   std::unordered_map<int, V3<Var>> N;   // vertex -> normal on the tape
+  std::unordered_map<int, V3<Var>> G;   // absorption grid node -> RGB leaf
+  V3<Var> mu(int node) {
+    auto it = G.find(node);
+    if (it != G.end()) return it->second;
+    const double* m = sh->sc->absorb->mu + 3 * (size_t)node;
+    V3<Var> r{leaf(m[0]), leaf(m[1]), leaf(m[2])};
+    G.emplace(node, r);
+    return r;
+  }
   V3<Var> pos(int v) {
     auto it = P.find(v);
     if (it != P.end()) return it->second;
@@ -456,6 +485,55 @@ V3<S> vertex_normal_def(const Shared& sh, int v, Ctx<S>& cx) {
   }
   if (!(val(dot(acc, acc)) > 0.0)) return acc;
   return normalize(acc);
+}
+
+// ---------------------------------------------------------------------------
+// spatially varying absorption (Eq. 11 with the rate sampled along the segment)
+// ---------------------------------------------------------------------------
+// Trilinear interpolant of the grid at x.  Per axis the position is mapped to
+// grid units u = (x - lo) (n - 1) / (hi - lo); outside [0, n - 1] it is
+// clamped (a constant, so no derivative flows through that axis).  The cell is
+// chosen from the value (held fixed, like every other discrete choice).
+template <class S>
+V3<S> grid_mu(Ctx<S>& cx, V3<S> x) {
+  const or_absorption& G = *cx.sh->sc->absorb;
+  const int n[3] = {G.nx, G.ny, G.nz};
+  const S xs[3] = {x.x, x.y, x.z};
+  int cell[3];
+  S f[3];
+  for (int a = 0; a < 3; ++a) {
+    const double scale = (double)(n[a] - 1) / (G.hi[a] - G.lo[a]);
+    const double u = (val(xs[a]) - G.lo[a]) * scale;
+    if (!(u > 0.0)) {
+      cell[a] = 0;
+      f[a] = S(0.0);
+    } else if (!(u < (double)(n[a] - 1))) {
+      cell[a] = n[a] - 2;
+      f[a] = S(1.0);
+    } else {
+      cell[a] = std::min((int)std::floor(u), n[a] - 2);
+      f[a] = (xs[a] - S(G.lo[a])) * S(scale) - S((double)cell[a]);
+    }
+  }
+  V3<S> acc{S(0.0), S(0.0), S(0.0)};
+  for (int c = 0; c < 8; ++c) {
+    const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+    S w = (dx ? f[0] : S(1.0) - f[0]) * (dy ? f[1] : S(1.0) - f[1]) * (dz ? f[2] : S(1.0) - f[2]);
+    const int node = ((cell[2] + dz) * G.ny + (cell[1] + dy)) * G.nx + (cell[0] + dx);
+    acc = add(acc, scl(cx.mu(node), w));
+  }
+  return acc;
+}
+
+// Optical depth of the segment o + s d, s in [0, t], per channel: the sum of
+// mu_t at the midpoints of S equal steps times the step length.
+template <class S>
+V3<S> grid_tau(Ctx<S>& cx, V3<S> o, V3<S> d, S t) {
+  const int ns = cx.sh->sc->absorb->samples;
+  const S h = t / S((double)ns);
+  V3<S> acc{S(0.0), S(0.0), S(0.0)};
+  for (int k = 0; k < ns; ++k) acc = add(acc, grid_mu(cx, add(o, scl(d, h * S(k + 0.5)))));
+  return scl(acc, h);
 }
 
 // ---------------------------------------------------------------------------
@@ -745,7 +823,12 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
   // travelled (the ray hit the surface from inside)
   V3<S> A{S(1.0), S(1.0), S(1.0)};
   if (!entering) {
-    A = {Exp(-cx.sigma[0] * t), Exp(-cx.sigma[1] * t), Exp(-cx.sigma[2] * t)};
+    if (sc.absorb) {
+      V3<S> tau = grid_tau(cx, o, d, t);
+      A = {Exp(-tau.x), Exp(-tau.y), Exp(-tau.z)};
+    } else {
+      A = {Exp(-cx.sigma[0] * t), Exp(-cx.sigma[1] * t), Exp(-cx.sigma[2] * t)};
+    }
   }
   double Av[3] = {val(A.x), val(A.y), val(A.z)};
   if (tree) {
@@ -842,6 +925,11 @@ void make_shared(const or_scene* sc, Shared& sh, bool need_normals) {
 bool valid_scene(const or_scene* sc) {
   if (!sc || !sc->V || !sc->F || !sc->env || sc->nv <= 0 || sc->nf <= 0) return false;
   if (sc->max_depth < 0 || sc->max_depth > 30) return false;
+  if (const or_absorption* G = sc->absorb) {
+    if (!G->mu || G->nx < 2 || G->ny < 2 || G->nz < 2 || G->samples < 1) return false;
+    for (int a = 0; a < 3; ++a)
+      if (!(G->hi[a] > G->lo[a])) return false;
+  }
   for (int i = 0; i < 3 * sc->nf; ++i)
     if (sc->F[i] < 0 || sc->F[i] >= sc->nv) return false;
   return true;
@@ -1016,10 +1104,12 @@ int or_trace(const or_scene* sc, const double* o, const double* d, int64_t n, do
 }
 
 // Forward + reverse-mode gradient.  The scalar loss is sum_i grad_rgb[i] . C_i.
-// dV [nv*3], d_eta [1], d_sigma [3] are overwritten.  rgb may be NULL.
+// dV [nv*3], d_eta [1], d_sigma [3] are overwritten, and with an absorption
+// grid d_mu [nx*ny*nz*3] too (sigma then has no effect and d_sigma is 0).
+// rgb and d_mu may be NULL.
 int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t n,
                   const double* grad_rgb, double* rgb, double* dV, double* d_eta,
-                  double* d_sigma) {
+                  double* d_sigma, double* d_mu) {
   if (!valid_scene(sc)) return 1;
   Shared sh;
   make_shared(sc, sh, true);
@@ -1029,6 +1119,8 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
 #endif
   std::vector<std::vector<double>> accV(nth);
   std::vector<double> accE(nth, 0.0), accS(3 * (size_t)nth, 0.0);
+  const size_t nmu = sc->absorb ? 3 * (size_t)sc->absorb->nx * sc->absorb->ny * sc->absorb->nz : 0;
+  std::vector<std::vector<double>> accM(nth);
 #pragma omp parallel
   {
     int tid = 0;
@@ -1036,6 +1128,7 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
     tid = omp_get_thread_num();
 #endif
     accV[tid].assign(3 * (size_t)sc->nv, 0.0);
+    accM[tid].assign(nmu, 0.0);
     Tape tape;
     g_tape = &tape;
 #pragma omp for schedule(dynamic, 16)
@@ -1076,17 +1169,26 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
         dst[1] += adj[kv.second.y.i];
         dst[2] += adj[kv.second.z.i];
       }
+      for (auto& kv : cx.G) {
+        double* dst = accM[tid].data() + 3 * (size_t)kv.first;
+        dst[0] += adj[kv.second.x.i];
+        dst[1] += adj[kv.second.y.i];
+        dst[2] += adj[kv.second.z.i];
+      }
     }
     g_tape = nullptr;
   }
   std::memset(dV, 0, sizeof(double) * 3 * (size_t)sc->nv);
   *d_eta = 0.0;
   d_sigma[0] = d_sigma[1] = d_sigma[2] = 0.0;
+  if (d_mu && nmu) std::memset(d_mu, 0, sizeof(double) * nmu);
   for (int t = 0; t < nth; ++t) {
     if (accV[t].empty()) continue;
     for (size_t j = 0; j < 3 * (size_t)sc->nv; ++j) dV[j] += accV[t][j];
     *d_eta += accE[t];
     for (int k = 0; k < 3; ++k) d_sigma[k] += accS[3 * t + k];
+    if (d_mu)
+      for (size_t j = 0; j < nmu; ++j) d_mu[j] += accM[t][j];
   }
   return 0;
 }
