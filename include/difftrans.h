@@ -135,6 +135,27 @@ dt_status dt_env_query_backward(const dt_env* env, const float* dirs, int64_t n,
 
 /* ------------------------------------------------------------- tracing */
 
+/* Spatially varying absorption rate mu_t(x) (Sec. 3.2: the radiance decay
+ * along a ray inside the medium, Eq. 11 evaluated as a sum of the rate at
+ * samples of the segment times their spacing).  An RGB grid of nx*ny*nz
+ * nodes over the box [lo, hi]: node (i, j, k) sits at lo + (i/(nx-1),
+ * j/(ny-1), k/(nz-1)) * (hi - lo) and holds mu[((k*ny + j)*nx + i)*3 + c].
+ * mu_t(x) is the trilinear interpolant at x clamped into the box.  An
+ * interior segment of length t from o along the unit direction d is
+ * attenuated per channel by exp(-(t/S) sum_{s<S} mu_t(o + (s + 1/2)(t/S) d)),
+ * the midpoint rule with S = samples steps.  With a grid the scene's sigma is
+ * not used.  mu and d_mu are device arrays owned by the caller; d_mu (may be
+ * NULL) receives dLoss/dmu from dt_trace_backward, which overwrites it.
+ * Limits: 2 <= nx, ny, nz <= 1024, 1 <= samples <= 256, hi > lo per axis;
+ * otherwise the calls that take the scene return DT_ERR_INVALID_ARGUMENT. */
+typedef struct {
+  const float* mu;     /* [nz][ny][nx][3] */
+  int32_t nx, ny, nz;
+  int32_t samples;
+  float lo[3], hi[3];
+  float* d_mu;         /* [nz][ny][nx][3] or NULL */
+} dt_absorption;
+
 typedef struct {
   const float* V;      /* [nv][3] */
   int32_t nv;
@@ -144,6 +165,7 @@ typedef struct {
   const float* ior;    /* [1]  IoR of the object, ambient medium 1 */
   const float* sigma;  /* [3]  RGB absorption per unit length */
   const dt_env* env;   /* HOST struct describing device data */
+  const dt_absorption* absorb;  /* HOST struct or NULL: the constant rate sigma */
 } dt_scene;
 
 /* Optional kernel timing (HOST struct of caller-created hipEvent_t handles):

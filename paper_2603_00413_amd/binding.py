@@ -40,10 +40,16 @@ class _Env(C.Structure):
                 ("biases", C.c_void_p)]
 
 
+class _Absorption(C.Structure):
+    _fields_ = [("mu", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("samples", C.c_int32), ("lo", C.c_float * 3), ("hi", C.c_float * 3),
+                ("d_mu", C.c_void_p)]
+
+
 class _Scene(C.Structure):
     _fields_ = [("V", C.c_void_p), ("nv", C.c_int32), ("F", C.c_void_p), ("nf", C.c_int32),
                 ("bvh", C.c_void_p), ("ior", C.c_void_p), ("sigma", C.c_void_p),
-                ("env", C.POINTER(_Env))]
+                ("env", C.POINTER(_Env)), ("absorb", C.POINTER(_Absorption))]
 
 
 class _Timing(C.Structure):
@@ -313,12 +319,34 @@ class Rays:
         self.s = r
 
 
-class Scene:
-    """Mesh + device IoR [1] + device sigma [3] + environment."""
+class Absorption:
+    """Spatially varying absorption rate: device float32 grid mu [nz, ny, nx, 3]
+    over the box [lo, hi], trilinear, `samples` midpoint samples per interior
+    segment.  d_mu (same shape) receives dLoss/dmu from dt_trace_backward."""
 
-    def __init__(self, mesh: Mesh, ior: torch.Tensor, sigma: torch.Tensor, env: Env):
+    def __init__(self, mu: torch.Tensor, lo, hi, samples: int, want_grad: bool = True):
+        _dev_check(mu)
+        assert mu.dtype == torch.float32 and mu.dim() == 4 and mu.shape[3] == 3
+        self.mu = mu.contiguous()
+        self.lo, self.hi, self.samples = tuple(map(float, lo)), tuple(map(float, hi)), int(samples)
+        self.d_mu = torch.zeros_like(self.mu) if want_grad else None
+        nz, ny, nx, _ = self.mu.shape
+        self.s = _Absorption()
+        self.s.mu, self.s.nx, self.s.ny, self.s.nz = self.mu.data_ptr(), nx, ny, nz
+        self.s.samples = self.samples
+        for k in range(3):
+            self.s.lo[k], self.s.hi[k] = self.lo[k], self.hi[k]
+        self.s.d_mu = self.d_mu.data_ptr() if self.d_mu is not None else None
+
+
+class Scene:
+    """Mesh + device IoR [1] + device sigma [3] + environment (+ optional
+    absorption grid, which replaces sigma on interior segments)."""
+
+    def __init__(self, mesh: Mesh, ior: torch.Tensor, sigma: torch.Tensor, env: Env,
+                 absorb: Absorption | None = None):
         _dev_check(ior, sigma)
-        self.mesh, self.ior, self.sigma, self.env = mesh, ior, sigma, env
+        self.mesh, self.ior, self.sigma, self.env, self.absorb = mesh, ior, sigma, env, absorb
 
     def c(self) -> _Scene:
         s = _Scene()
@@ -326,6 +354,7 @@ class Scene:
         s.V, s.nv, s.F, s.nf = m.V.data_ptr(), m.nv, m.F.data_ptr(), m.nf
         s.bvh, s.ior, s.sigma = m.blob.data_ptr(), self.ior.data_ptr(), self.sigma.data_ptr()
         s.env = C.pointer(self.env.s)
+        s.absorb = C.pointer(self.absorb.s) if self.absorb is not None else None
         return s
 
 

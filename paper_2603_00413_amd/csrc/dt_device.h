@@ -16,6 +16,15 @@ struct EnvDev {
   const float* b;
 };
 
+// Spatially varying absorption rate: trilinear RGB grid (mu == NULL: the
+// constant rate sigma).  scale = (n - 1) / (hi - lo) grid units per length.
+struct AbsorbDev {
+  const float* mu;
+  float* d_mu;
+  int nx, ny, nz, samples;
+  float lo[3], scale[3];
+};
+
 struct SceneDev {
   const float* V;
   const int32_t* F;
@@ -24,9 +33,57 @@ struct SceneDev {
   const float* ior;
   const float* sigma;
   EnvDev env;
+  AbsorbDev ab;
   int max_depth, terminal_env;
   float t_eps;
 };
+
+// ------------------------------------------------------------------ absorption grid
+// Position along one axis in grid units, clamped into [0, n - 1]; the cell
+// (at most n - 2), the fraction inside it, and whether the position lies
+// strictly inside the box (outside, the clamp is constant: no derivative).
+struct GridAxis {
+  int i;
+  float f;
+  bool in;
+};
+
+__device__ __forceinline__ GridAxis grid_axis(float x, float lo, float scale, int n) {
+  float u = (x - lo) * scale;
+  GridAxis a;
+  a.in = u > 0.f && u < (float)(n - 1);
+  u = fminf(fmaxf(u, 0.f), (float)(n - 1));
+  a.i = min((int)u, n - 2);
+  a.f = u - (float)a.i;
+  return a;
+}
+
+// mu_t(x): trilinear blend of the cell's 8 corner nodes
+__device__ __forceinline__ v3 grid_mu(const AbsorbDev& G, v3 x) {
+  const GridAxis ax = grid_axis(x.x, G.lo[0], G.scale[0], G.nx);
+  const GridAxis ay = grid_axis(x.y, G.lo[1], G.scale[1], G.ny);
+  const GridAxis az = grid_axis(x.z, G.lo[2], G.scale[2], G.nz);
+  const size_t sy = 3 * (size_t)G.nx, sz = sy * (size_t)G.ny;
+  const float* b = G.mu + (size_t)az.i * sz + (size_t)ay.i * sy + 3 * (size_t)ax.i;
+  v3 acc = mk3(0.f, 0.f, 0.f);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+    const float w = (dx ? ax.f : 1.f - ax.f) * (dy ? ay.f : 1.f - ay.f) * (dz ? az.f : 1.f - az.f);
+    const float* q = b + dz * sz + dy * sy + 3 * dx;
+    acc = acc + mk3(q[0], q[1], q[2]) * w;
+  }
+  return acc;
+}
+
+// Optical depth of the segment o + s d, s in [0, t], per channel: the rate at
+// the midpoints of samples equal steps, summed, times the step t / samples.
+__device__ __forceinline__ v3 absorb_tau(const AbsorbDev& G, v3 o, v3 d, float t) {
+  const float h = t / (float)G.samples;
+  v3 acc = mk3(0.f, 0.f, 0.f);
+  for (int k = 0; k < G.samples; ++k) acc = acc + grid_mu(G, o + d * (h * ((float)k + 0.5f)));
+  return acc * h;
+}
 
 // ------------------------------------------------------------------ environment (equirect)
 // Texel lookup at a direction (normalised here): phi = atan2(x, -z),
@@ -554,6 +611,9 @@ struct Shade {
 // Paper Sec. 3.2-3.3.  `code_in` (when nonzero) supplies the discrete
 // decisions recorded by the forward pass so that every later recomputation
 // takes the same branches.
+// GRID: the scene carries an absorption grid (a separate instantiation, so the
+// constant-rate kernels keep their register budget)
+template <bool GRID = false>
 __device__ __forceinline__ Shade shade(const SceneDev& sc, const HitGeo& g, v3 o, v3 d, float t,
                                        float b1, float b2, uint32_t code_in) {
   Shade s;
@@ -580,7 +640,12 @@ __device__ __forceinline__ Shade shade(const SceneDev& sc, const HitGeo& g, v3 o
   if (entering) {
     s.A = mk3(1.f, 1.f, 1.f);
   } else {
-    s.A = mk3(expf(-sc.sigma[0] * t), expf(-sc.sigma[1] * t), expf(-sc.sigma[2] * t));
+    if constexpr (GRID) {
+      const v3 tau = absorb_tau(sc.ab, o, d, t);
+      s.A = mk3(expf(-tau.x), expf(-tau.y), expf(-tau.z));
+    } else {
+      s.A = mk3(expf(-sc.sigma[0] * t), expf(-sc.sigma[1] * t), expf(-sc.sigma[2] * t));
+    }
   }
   s.sin2t = (1.f - ci * ci) / (s.eta_r * s.eta_r);
   bool tir = code_in ? (code_in & C_TIR) != 0u : s.sin2t > 1.f;

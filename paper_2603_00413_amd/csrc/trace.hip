@@ -290,6 +290,7 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
 }
 
 // ------------------------------------------------------------------ k_trace (a4 + a5 decisions + a6)
+template <bool GRID>
 __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
                                               int32_t* flags, unsigned long long* sig,
@@ -337,7 +338,7 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
       } else {
         hit = true;
         HitGeo geo = load_geo(sc, h.tri);
-        Shade s = shade(sc, geo, o, d, h.t, h.b1, h.b2, 0u);
+        Shade s = shade<GRID>(sc, geo, o, d, h.t, h.b1, h.b2, 0u);
         code = s.code;
         if (code & C_DEGEN) pf |= DT_FLAG_DEGEN;
         if (code & C_GRAZE) pf |= DT_FLAG_GRAZING;
@@ -416,6 +417,7 @@ __global__ void k_scan(Counters* ctr, int g, unsigned long long* part, unsigned 
 // Block b re-walks chunk b in order and writes each ray's children at its
 // scanned position: reflected children fill [0, n_r) of the next queue,
 // refracted children [n_r, n_r + n_t).  write_rays = 0 computes indices only.
+template <bool GRID>
 __global__ void __launch_bounds__(EB) k_emit(SceneDev sc, Gen q, Gen nx, int g, Counters* ctr,
                                              const unsigned long long* part, int64_t cap_next,
                                              int write_rays, int32_t* flags) {
@@ -458,7 +460,7 @@ __global__ void __launch_bounds__(EB) k_emit(SceneDev sc, Gen q, Gen nx, int g, 
         int pix = __float_as_int(d4.w);
         int tri = __float_as_int(h4.y);
         HitGeo geo = load_geo(sc, tri);
-        Shade sh = shade(sc, geo, o, d, h4.x, h4.z, h4.w, code);
+        Shade sh = shade<GRID>(sc, geo, o, d, h4.x, h4.z, h4.w, code);
         v3 wa = mul3(W, sh.A);
         bool entering = (code & C_ENTER) != 0u;
         if (hr) {
@@ -512,6 +514,50 @@ __device__ __forceinline__ void atomic_add3(float* p, int idx, v3 v) {
 
 // Vertex contributions of one hit node: dLoss/dp_k for its three vertices and
 // dLoss/dN_k for their normals (absent where the geometric normal was used).
+// Adjoint of tau = absorb_tau(G, o, d, t) for the per-channel taubar: the
+// grid values' terms go to G.d_mu (float atomics: 24 per sample, in no fixed
+// order), the terms of t, o and d are added to tbar, obar and dbar.  Sample k
+// sits at x = o + a d with a = (k + 1/2) t / S, and tau = (t / S) sum mu(x).
+__device__ void absorb_tau_bwd(const AbsorbDev& G, v3 o, v3 d, float t, v3 taubar, float& tbar,
+                               v3& obar, v3& dbar) {
+  const float S = (float)G.samples, h = t / S;
+  const size_t sy = 3 * (size_t)G.nx, sz = sy * (size_t)G.ny;
+  const v3 tw = taubar * h;  // dLoss/d mu(x_k), per channel
+  for (int k = 0; k < G.samples; ++k) {
+    const float a = h * ((float)k + 0.5f);
+    const v3 x = o + d * a;
+    const GridAxis ax = grid_axis(x.x, G.lo[0], G.scale[0], G.nx);
+    const GridAxis ay = grid_axis(x.y, G.lo[1], G.scale[1], G.ny);
+    const GridAxis az = grid_axis(x.z, G.lo[2], G.scale[2], G.nz);
+    const size_t b = (size_t)az.i * sz + (size_t)ay.i * sy + 3 * (size_t)ax.i;
+    v3 mu = mk3(0.f, 0.f, 0.f), gx = mu, gy = mu, gz = mu;  // value, d/du per axis
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+      const float wx = dx ? ax.f : 1.f - ax.f, wy = dy ? ay.f : 1.f - ay.f, wz = dz ? az.f : 1.f - az.f;
+      const float sx = dx ? 1.f : -1.f, sgy = dy ? 1.f : -1.f, sgz = dz ? 1.f : -1.f;
+      const size_t j = b + dz * sz + dy * sy + 3 * dx;
+      const v3 v = mk3(G.mu[j], G.mu[j + 1], G.mu[j + 2]);
+      const float w = wx * wy * wz;
+      mu = mu + v * w;
+      gx = gx + v * (sx * wy * wz);
+      gy = gy + v * (wx * sgy * wz);
+      gz = gz + v * (wx * wy * sgz);
+      if (G.d_mu) {
+        atomicAdd(G.d_mu + j, tw.x * w);
+        atomicAdd(G.d_mu + j + 1, tw.y * w);
+        atomicAdd(G.d_mu + j + 2, tw.z * w);
+      }
+    }
+    // dLoss/dx of the sample: sum_c tw_c grad mu_c (grid units to length)
+    const v3 q = mk3(ax.in ? dot(tw, gx) * G.scale[0] : 0.f, ay.in ? dot(tw, gy) * G.scale[1] : 0.f,
+                     az.in ? dot(tw, gz) * G.scale[2] : 0.f);
+    obar += q;
+    dbar += q * a;
+    tbar += dot(q, d) * (((float)k + 0.5f) / S) + dot(taubar, mu) / S;
+  }
+}
+
 struct VtxAdj {
   int f;  // hit face, < 0: no contributions
   v3 p0, p1, p2, m;
@@ -521,6 +567,7 @@ struct VtxAdj {
 // Adjoint of node i of generation g: writes its record (subtree radiance,
 // d/d origin, d/d direction) to cur, adds its dIoR / dsigma terms to acc and
 // returns its vertex contributions.
+template <bool GRID>
 __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, int64_t i,
                                              const float* grad_rgb, const Adj& nxt, const Adj& cur,
                                              float4& acc, VtxAdj& out) {
@@ -549,7 +596,7 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   float t = h4.x, b1 = h4.z, b2 = h4.w;
   int tri = __float_as_int(h4.y);
   HitGeo geo = load_geo(sc, tri);
-  Shade s = shade(sc, geo, o, d, t, b1, b2, code);
+  Shade s = shade<GRID>(sc, geo, o, d, t, b1, b2, code);
   const bool entering = (code & C_ENTER) != 0u, tir = (code & C_TIR) != 0u;
   const bool degen = (code & C_DEGEN) != 0u;
   v3 L, Abar, dbar = mk3(0.f, 0.f, 0.f), xbar = mk3(0.f, 0.f, 0.f), nbar = mk3(0.f, 0.f, 0.f);
@@ -615,9 +662,13 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   // IoR: entering eta_i = 1, eta_t = eta_r = eta; leaving eta_i = eta, eta_t = 1, eta_r = 1/eta
   float etabar = entering ? (etatbar + etarbar) : (etaibar - etarbar / (s.eta * s.eta));
   acc.x += etabar;
-  // absorption A = exp(-sigma t) on interior segments (Eq. 11)
+  // absorption on interior segments (Eq. 11): A = exp(-tau), tau = sigma t or
+  // the grid's sum over the segment's samples
   float tbar = 0.f;
-  if (!entering) {
+  v3 oabs = mk3(0.f, 0.f, 0.f);
+  if (GRID && !entering) {
+    absorb_tau_bwd(sc.ab, o, d, t, -mul3(Abar, s.A), tbar, oabs, dbar);
+  } else if (!entering) {
     float sg0 = sc.sigma[0], sg1 = sc.sigma[1], sg2 = sc.sigma[2];
     acc.y += -Abar.x * t * s.A.x;
     acc.z += -Abar.y * t * s.A.y;
@@ -628,7 +679,7 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   dbar += s.n * (-cibar);
   nbar += d * (-cibar);
   // children start at x = o + t d
-  v3 obar = xbar;
+  v3 obar = xbar + oabs;
   dbar += xbar * t;
   tbar += dot(d, xbar);
   // shading normal n = +-normalize(m), m = sum b_k N_k (Eq. 12)
@@ -693,6 +744,7 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
 // scatter sort the nodes by face; then each face sums its records and adds
 // the totals to its three vertices (18 atomics per hit face instead of 18 per
 // hit).
+template <bool GRID>
 __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
                                                 const float* grad_rgb, Adj nxt, Adj cur,
                                                 FaceRec* frec, int2* fkey, uint32_t* fcnt,
@@ -709,7 +761,7 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
     VtxAdj va;
     va.f = -1;
     va.m = mk3(0.f, 0.f, 0.f);
-    adjoint_node(sc, q, i, grad_rgb, nxt, cur, acc, va);
+    adjoint_node<GRID>(sc, q, i, grad_rgb, nxt, cur, acc, va);
     int2 key = make_int2(-1, 0);
     if (va.f >= 0) {
       FaceRec r;
@@ -1005,6 +1057,26 @@ dt_status make_scene(const dt_scene* sc, const dt_trace_params* p, SceneDev& s) 
   s.bvh = bvh_view(sc->bvh, sc->nv, sc->nf);
   s.ior = sc->ior;
   s.sigma = sc->sigma;
+  memset(&s.ab, 0, sizeof(s.ab));
+  if (const dt_absorption* G = sc->absorb) {
+    DT_REQUIRE(G->mu, "absorption grid has a NULL mu");
+    DT_REQUIRE(G->nx >= 2 && G->ny >= 2 && G->nz >= 2 && G->nx <= 1024 && G->ny <= 1024 &&
+                   G->nz <= 1024,
+               "absorption grid needs 2..1024 nodes per axis (got %d, %d, %d)", G->nx, G->ny, G->nz);
+    DT_REQUIRE(G->samples >= 1 && G->samples <= 256, "absorption samples must be in [1, 256]");
+    s.ab.mu = G->mu;
+    s.ab.d_mu = G->d_mu;
+    s.ab.nx = G->nx;
+    s.ab.ny = G->ny;
+    s.ab.nz = G->nz;
+    s.ab.samples = G->samples;
+    const int n[3] = {G->nx, G->ny, G->nz};
+    for (int a = 0; a < 3; ++a) {
+      DT_REQUIRE(G->hi[a] > G->lo[a], "absorption grid box needs hi > lo on every axis");
+      s.ab.lo[a] = G->lo[a];
+      s.ab.scale[a] = (float)(n[a] - 1) / (G->hi[a] - G->lo[a]);
+    }
+  }
   if (dt_status st = make_env(sc->env, s.env)) return st;
   if (s.env.kind == DT_ENV_MLP && p->terminal_env) {
     dt_set_error("terminal_env with an MLP environment is not supported");
@@ -1103,8 +1175,12 @@ dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen 
                          int write_next, void* const* events, void* const* mlp_events,
                          uint32_t* miss_list, uint2* ovf, hipStream_t s) {
   if (dt_status st = record(events, 2 * g, s)) return st;
-  hipLaunchKernelGGL(k_trace, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
-                     rgb, wtrunc, flags, sig, accumulate, ovf, wp);
+  if (sc.ab.mu)
+    hipLaunchKernelGGL(k_trace<true>, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
+                       rgb, wtrunc, flags, sig, accumulate, ovf, wp);
+  else
+    hipLaunchKernelGGL(k_trace<false>, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
+                       rgb, wtrunc, flags, sig, accumulate, ovf, wp);
   DT_CHECK_LAUNCH();
   if (dt_status st = record(events, 2 * g + 1, s)) return st;
   if (accumulate && sc.env.kind == DT_ENV_MLP) {
@@ -1119,8 +1195,12 @@ dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen 
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctr, g, part_g, part_other, other_n,
                        P.cap[g + 1]);
     int64_t nch = (P.cap[g] + CHUNK - 1) / CHUNK;
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)nch), dim3(EB), 0, s, sc, cur, nxt, g, ctr, part_g,
-                       P.cap[g + 1], write_next, accumulate ? flags : nullptr);
+    if (sc.ab.mu)
+      hipLaunchKernelGGL(k_emit<true>, dim3((unsigned)nch), dim3(EB), 0, s, sc, cur, nxt, g, ctr, part_g,
+                         P.cap[g + 1], write_next, accumulate ? flags : nullptr);
+    else
+      hipLaunchKernelGGL(k_emit<false>, dim3((unsigned)nch), dim3(EB), 0, s, sc, cur, nxt, g, ctr, part_g,
+                         P.cap[g + 1], write_next, accumulate ? flags : nullptr);
     DT_CHECK_LAUNCH();
   }
   return DT_OK;
@@ -1336,6 +1416,8 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   if (dt_status st = zero_f32(dN, 3 * (int64_t)scene->nv, s)) return st;
   if (dt_status st = zero_f32((float*)fcnt, (int64_t)scene->nf + 1, s)) return st;
   if (dt_status st = zero_f32(fg, 18 * (int64_t)scene->nf, s)) return st;
+  if (sc.ab.d_mu)
+    if (dt_status st = zero_f32(sc.ab.d_mu, 3 * (int64_t)sc.ab.nx * sc.ab.ny * sc.ab.nz, s)) return st;
   if (dt_status st = zero_f32((float*)red, 4 * (int64_t)nred, s)) return st;
   Adj adj[2];
   for (int b = 0; b < 2; ++b) {
@@ -1358,8 +1440,12 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
         return st;
       if (dt_status st = record(maev, 2 * g + 1, s)) return st;
     }
-    hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                       adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
+    if (sc.ab.mu)
+      hipLaunchKernelGGL(k_adjoint<true>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
+                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
+    else
+      hipLaunchKernelGGL(k_adjoint<false>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
+                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
     // fcnt[nf] stays 0, so foff[nf] is the total
     if (dt_status st = dt_scan_exclusive_i32((const int32_t*)fcnt, (int32_t*)foff, scene->nf + 1, fscan, s))
       return st;
