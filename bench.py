@@ -109,6 +109,8 @@ def parse():
                     help="oracle baseline traces every n-th pixel in x and y")
     ap.add_argument("--no-mlp", action="store_true", help="skip the MLP-lit training-step leg")
     ap.add_argument("--no-stress", action="store_true", help="skip the 2M-triangle thin-shell leg")
+    ap.add_argument("--no-grid", action="store_true",
+                    help="skip the spatially varying absorption (grid) leg")
     ap.add_argument("--copy-only", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
@@ -256,6 +258,9 @@ def main():
     log(f"step {ms_step:.2f} ms; forward-only {fwd_ms:.2f} ms; k_trace per gen ms {np.round(tr_ms, 3).tolist()}; "
         f"k_adjoint per gen ms {np.round(ad_ms, 3).tolist()}")
 
+    grid = None
+    if not args.no_grid:
+        grid = grid_bench(args, dev, mesh, rays, env, ior, sigma, wl, cap, target, segs)
     del buf
     torch.cuda.empty_cache()
     serving = None
@@ -312,12 +317,65 @@ def main():
         "serving": serving,
         "training_step_mlp": training,
         "stress_thin_shell": stress,
+        "absorption_grid": grid,
         "plain_forward": {"ms": round(fwd_ms, 3), "Mrays/s": round(segs / fwd_ms / 1e3, 3)},
         "kernel_ms_per_generation": {"k_trace": np.round(tr_ms, 4).tolist(),
                                      "k_adjoint": np.round(ad_ms, 4).tolist()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def grid_bench(args, dev, mesh, rays, env, ior, sigma, wl, cap, target, segs):
+    """The torus fwd+bwd step with a spatially varying absorption rate: a
+    seeded 32^3 RGB grid over the object's box (values 0.1-0.5), 16 midpoint
+    samples per interior segment; the grid gradient is written every step."""
+    import torch
+
+    from paper_2603_00413_amd import binding as B
+    n, S = 32, 16
+    rng = np.random.default_rng(7)
+    mu = torch.from_numpy(rng.uniform(0.1, 0.5, (n, n, n, 3)).astype(np.float32)).to(dev)
+    lo, hi = wl.V.min(0) - 0.01, wl.V.max(0) + 0.01
+    ab = B.Absorption(mu, lo, hi, S)
+    scene = B.Scene(mesh, ior, sigma, env, absorb=ab)
+    params = B.Params(max_depth=wl.max_depth, queue_capacity=cap, checkpoint_stride=args.stride)
+    buf = B.Buffers(params, rays, mesh, tape=True)
+
+    def step():
+        mesh.build()
+        rgb, _, _ = B.dt_trace_forward(scene, rays, params, buf, want_aux=False)
+        grad = (rgb - target) * (2.0 / rgb.numel())
+        return B.dt_trace_backward(scene, rays, params, buf, grad)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    st = buf.stats.cpu().numpy()
+    assert st[B.STAT_DROPPED] == 0 and int(st[B.STAT_TOTAL]) == segs
+    timer = B.KernelTimer(wl.max_depth)
+    pt = B.Params(max_depth=wl.max_depth, queue_capacity=cap, checkpoint_stride=args.stride,
+                  timing=timer)
+    mesh.build()
+    rgb, _, _ = B.dt_trace_forward(scene, rays, pt, buf, want_aux=False)
+    B.dt_trace_backward(scene, rays, pt, buf, (rgb - target) * (2.0 / rgb.numel()))
+    torch.cuda.synchronize()
+    G = wl.max_depth + 1
+    tr, ad = np.array(timer.trace_ms(G)), np.array(timer.adjoint_ms(G))
+    assert torch.isfinite(ab.d_mu).all() and float(ab.d_mu.abs().sum()) > 0
+    log(f"absorption grid {n}^3 x {S} samples: step {ms:.2f} ms; k_trace per gen ms "
+        f"{np.round(tr, 3).tolist()}; k_adjoint per gen ms {np.round(ad, 3).tolist()}")
+    del buf
+    return {"workload": f"torus-102k fwd+bwd as above with a {n}^3 RGB absorption grid, "
+                        f"{S} samples per interior segment, grid gradient written",
+            "ms_per_step": round(ms, 3), "Mrays/s": round(segs / ms / 1e3, 3),
+            "k_trace_ms_per_generation": np.round(tr, 4).tolist(),
+            "k_adjoint_ms_per_generation": np.round(ad, 4).tolist()}
 
 
 def mlp_flops(width, layers, in_dim=39):

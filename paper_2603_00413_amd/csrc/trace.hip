@@ -27,6 +27,7 @@ constexpr int EB = 256;               // threads per block of the emit kernel
 constexpr int AB = 256;               // threads per block of the adjoint kernel
 constexpr int ADJ_MAX_BLOCKS = 4096;  // grid cap of the adjoint kernel
 constexpr int TRACE_MAX_BLOCKS = 256 * 4 * 7;  // grid cap of the traversal kernel: 7 resident waves per SIMD
+constexpr size_t GG_SCRATCH = (size_t)32 << 20;  // workspace bytes for copies of the absorption-grid gradient
 // Vertex adjoints of one hit, stored per node and summed per face afterwards:
 // d/d p0, p1, p2 and the shading-normal adjoint mbar with the barycentrics
 // (vertex normal k receives mbar b_k; mbar = 0 on flat-shaded hits).
@@ -53,7 +54,7 @@ struct Plan {
   size_t w_ctr, w_parts, w_part0, w_part1;
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
-  size_t w_dN, w_sbar, w_red, w_miss, w_ovf;
+  size_t w_dN, w_sbar, w_red, w_miss, w_ovf, w_tau, w_gscr;
   size_t w_frec, w_fkey, w_fidx, w_fcnt, w_foff, w_fscan, w_fg;  // per-face gathering of vertex adjoints
   size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
   size_t ws_bytes;
@@ -141,6 +142,10 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = dt_align(o + 16 * (size_t)(DT_MAX_DEPTH + 1) * ADJ_MAX_BLOCKS);
   P.w_miss = o;  // miss list of the current generation (MLP environment)
   o = dt_align(o + 4 * mc);
+  P.w_tau = o;  // per node: dLoss/d(optical depth) of its interior segment (absorption grid)
+  o = dt_align(o + 16 * mc);
+  P.w_gscr = o;  // copies of the absorption grid's gradient, summed at the end
+  o = dt_align(o + GG_SCRATCH);
   P.w_ovf = o;   // per-lane traversal stack overflow of the traversal grid
   o = dt_align(o + 8 * (size_t)TRACE_MAX_BLOCKS * TB * (DT_STACK - DT_STACK_LDS));
   P.w_frec = o;  // vertex-adjoint record of each node of the current generation
@@ -515,9 +520,9 @@ __device__ __forceinline__ void atomic_add3(float* p, int idx, v3 v) {
 // Vertex contributions of one hit node: dLoss/dp_k for its three vertices and
 // dLoss/dN_k for their normals (absent where the geometric normal was used).
 // Adjoint of tau = absorb_tau(G, o, d, t) for the per-channel taubar: the
-// grid values' terms go to G.d_mu (float atomics: 24 per sample, in no fixed
-// order), the terms of t, o and d are added to tbar, obar and dbar.  Sample k
-// sits at x = o + a d with a = (k + 1/2) t / S, and tau = (t / S) sum mu(x).
+// terms of t, o and d are added to tbar, obar and dbar (the grid values'
+// terms are scattered by k_grid_grad).  Sample k sits at x = o + a d with
+// a = (k + 1/2) t / S, and tau = (t / S) sum mu(x).
 __device__ void absorb_tau_bwd(const AbsorbDev& G, v3 o, v3 d, float t, v3 taubar, float& tbar,
                                v3& obar, v3& dbar) {
   const float S = (float)G.samples, h = t / S;
@@ -538,16 +543,10 @@ __device__ void absorb_tau_bwd(const AbsorbDev& G, v3 o, v3 d, float t, v3 tauba
       const float sx = dx ? 1.f : -1.f, sgy = dy ? 1.f : -1.f, sgz = dz ? 1.f : -1.f;
       const size_t j = b + dz * sz + dy * sy + 3 * dx;
       const v3 v = mk3(G.mu[j], G.mu[j + 1], G.mu[j + 2]);
-      const float w = wx * wy * wz;
-      mu = mu + v * w;
+      mu = mu + v * (wx * wy * wz);
       gx = gx + v * (sx * wy * wz);
       gy = gy + v * (wx * sgy * wz);
       gz = gz + v * (wx * wy * sgz);
-      if (G.d_mu) {
-        atomicAdd(G.d_mu + j, tw.x * w);
-        atomicAdd(G.d_mu + j + 1, tw.y * w);
-        atomicAdd(G.d_mu + j + 2, tw.z * w);
-      }
     }
     // dLoss/dx of the sample: sum_c tw_c grad mu_c (grid units to length)
     const v3 q = mk3(ax.in ? dot(tw, gx) * G.scale[0] : 0.f, ay.in ? dot(tw, gy) * G.scale[1] : 0.f,
@@ -562,6 +561,7 @@ struct VtxAdj {
   int f;  // hit face, < 0: no contributions
   v3 p0, p1, p2, m;
   float b1, b2;
+  float4 tau;  // absorption grid: (dLoss/d tau, 1) of an interior segment, else 0
 };
 
 // Adjoint of node i of generation g: writes its record (subtree radiance,
@@ -667,7 +667,9 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   float tbar = 0.f;
   v3 oabs = mk3(0.f, 0.f, 0.f);
   if (GRID && !entering) {
-    absorb_tau_bwd(sc.ab, o, d, t, -mul3(Abar, s.A), tbar, oabs, dbar);
+    const v3 taubar = -mul3(Abar, s.A);
+    absorb_tau_bwd(sc.ab, o, d, t, taubar, tbar, oabs, dbar);
+    out.tau = make_float4(taubar.x, taubar.y, taubar.z, 1.f);
   } else if (!entering) {
     float sg0 = sc.sigma[0], sg1 = sc.sigma[1], sg2 = sc.sigma[2];
     acc.y += -Abar.x * t * s.A.x;
@@ -748,7 +750,7 @@ template <bool GRID>
 __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
                                                 const float* grad_rgb, Adj nxt, Adj cur,
                                                 FaceRec* frec, int2* fkey, uint32_t* fcnt,
-                                                float4* red) {
+                                                float4* red, float4* tau) {
   const int64_t n = ctr->count[g];
   // each block takes one contiguous range of the generation, AB nodes a step
   const int64_t per = ((n + gridDim.x - 1) / gridDim.x + AB - 1) / AB * AB;
@@ -761,7 +763,9 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
     VtxAdj va;
     va.f = -1;
     va.m = mk3(0.f, 0.f, 0.f);
+    va.tau = make_float4(0.f, 0.f, 0.f, 0.f);
     adjoint_node<GRID>(sc, q, i, grad_rgb, nxt, cur, acc, va);
+    if constexpr (GRID) tau[i] = va.tau;
     int2 key = make_int2(-1, 0);
     if (va.f >= 0) {
       FaceRec r;
@@ -792,6 +796,105 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
   if (threadIdx.x == 0)
     red[(size_t)g * ADJ_MAX_BLOCKS + blockIdx.x] = make_float4(red_s[0][0], red_s[1][0], red_s[2][0],
                                                                red_s[3][0]);
+}
+
+// ------------------------------------------------------------------ absorption grid gradient
+// dLoss/d(grid value) of generation g's interior segments: the segment of
+// node i adds tw w_j(x_k) at the 8 corner nodes j of the cell of each sample
+// x_k (tw = h dLoss/d tau, per channel).  Float atomics to one address from
+// the lanes of one instruction are serialized, and neighbouring rays (the
+// lanes of a wave) mostly sample the same cells, so the updates are merged
+// before they are issued: a lane sums its consecutive samples that fall in
+// the same cell (a run) into 24 values; the wave parks its lanes' runs in LDS;
+// then per distinct cell among them, lanes 0-23 each sum one of the 24 values
+// over the lanes of that cell and add it with one atomic.  The sums go to
+// copy blockIdx.x % copies of the gradient (each 3 nx ny nz floats apart);
+// k_grid_reduce adds the copies up.  Control flow around the LDS exchange
+// stays wave-uniform.
+constexpr int GG_T = 256;
+constexpr int GG_MAX_COPIES = 64;
+__global__ void __launch_bounds__(GG_T) k_grid_grad(AbsorbDev G, Gen q, int g, const Counters* ctr,
+                                                    const float4* tau, float* copies, int n_copies) {
+  __shared__ float runs[GG_T / 64][64][25];  // per wave and lane: a run's 24 sums (+1 pad)
+  const int64_t n = ctr->count[g];
+  const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+  float* dst = copies + (size_t)(blockIdx.x % (unsigned)n_copies) * 3 * G.nx * G.ny * G.nz;
+  const size_t sy = 3 * (size_t)G.nx, sz = sy * (size_t)G.ny;
+  const int S = G.samples;
+  for (int64_t base = (int64_t)blockIdx.x * GG_T; base < n; base += (int64_t)gridDim.x * GG_T) {
+    const int64_t i = base + threadIdx.x;
+    float4 tb = make_float4(0.f, 0.f, 0.f, 0.f);
+    v3 o = mk3(0.f, 0.f, 0.f), d = o;
+    float t = 0.f;
+    if (i < n) {
+      tb = tau[i];
+      if (tb.w != 0.f) {
+        o = xyz(q.o[i]);
+        d = xyz(q.d[i]);
+        t = q.hit[i].x;
+      }
+    }
+    const bool act = tb.w != 0.f;
+    const float h = t / (float)S;
+    const v3 tw = mk3(tb.x, tb.y, tb.z) * h;
+    int k = act ? 0 : S;  // next sample of this lane
+    while (__ballot(k < S)) {
+      // this lane's next run: samples k, k+1, ... in one cell
+      float acc[24];
+#pragma unroll
+      for (int c = 0; c < 24; ++c) acc[c] = 0.f;
+      int key = -1;
+      while (k < S) {
+        const v3 x = o + d * (h * ((float)k + 0.5f));
+        const GridAxis ax = grid_axis(x.x, G.lo[0], G.scale[0], G.nx);
+        const GridAxis ay = grid_axis(x.y, G.lo[1], G.scale[1], G.ny);
+        const GridAxis az = grid_axis(x.z, G.lo[2], G.scale[2], G.nz);
+        const int kk = (az.i * G.ny + ay.i) * G.nx + ax.i;
+        if (key >= 0 && kk != key) break;
+        key = kk;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+          const float w = (dx ? ax.f : 1.f - ax.f) * (dy ? ay.f : 1.f - ay.f) * (dz ? az.f : 1.f - az.f);
+          acc[3 * c] += tw.x * w;
+          acc[3 * c + 1] += tw.y * w;
+          acc[3 * c + 2] += tw.z * w;
+        }
+        ++k;
+      }
+      const bool has = key >= 0;
+#pragma unroll
+      for (int c = 0; c < 24; ++c) runs[wv][lane][c] = acc[c];
+      wave_lds_sync();
+      uint64_t pending = __ballot(has);
+      while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int kl = __builtin_amdgcn_readlane(key, leader);
+        const uint64_t m = __ballot(has && key == kl);
+        pending &= ~m;
+        if (lane < 24) {
+          float sum = 0.f;
+          for (uint64_t mm = m; mm; mm &= mm - 1ull) sum += runs[wv][__ffsll((unsigned long long)mm) - 1][lane];
+          const int cc = lane / 3;  // corner (dx, dy, dz) = bits 0, 1, 2
+          const int az_i = kl / (G.nx * G.ny), ay_i = (kl / G.nx) % G.ny, ax_i = kl % G.nx;
+          atomicAdd(dst + (size_t)(az_i + (cc >> 2)) * sz + (size_t)(ay_i + ((cc >> 1) & 1)) * sy +
+                        3 * (size_t)(ax_i + (cc & 1)) + lane % 3,
+                    sum);
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
+// d_mu = the sum of the gradient copies (fixed order)
+__global__ void k_grid_reduce(const float* copies, int n_copies, int64_t n, float* d_mu) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    float acc = 0.f;
+    for (int r = 0; r < n_copies; ++r) acc += copies[(size_t)r * n + j];
+    d_mu[j] = acc;
+  }
 }
 
 // ------------------------------------------------------------------ per-face gathering
@@ -1410,14 +1513,27 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   uint32_t* foff = (uint32_t*)(W + P.w_foff);
   int32_t* fscan = (int32_t*)(W + P.w_fscan);
   float* fg = (float*)(W + P.w_fg);
+  float4* tau = (float4*)(W + P.w_tau);
   const int nred = (P.D + 1) * ADJ_MAX_BLOCKS;  // slot g * ADJ_MAX_BLOCKS + block
   hipLaunchKernelGGL(k_load_counters, dim3(1), dim3(64), 0, s, ctr, (const Counters*)(T + P.tape_hdr));
   if (dt_status st = zero_f32(dV, 3 * (int64_t)scene->nv, s)) return st;
   if (dt_status st = zero_f32(dN, 3 * (int64_t)scene->nv, s)) return st;
   if (dt_status st = zero_f32((float*)fcnt, (int64_t)scene->nf + 1, s)) return st;
   if (dt_status st = zero_f32(fg, 18 * (int64_t)scene->nf, s)) return st;
-  if (sc.ab.d_mu)
-    if (dt_status st = zero_f32(sc.ab.d_mu, 3 * (int64_t)sc.ab.nx * sc.ab.ny * sc.ab.nz, s)) return st;
+  // absorption grid: as many gradient copies as the scratch region holds (at most 64)
+  const int64_t gsize = sc.ab.mu ? 3 * (int64_t)sc.ab.nx * sc.ab.ny * sc.ab.nz : 0;
+  float* gcopies = (float*)(W + P.w_gscr);
+  int n_copies = 0;
+  if (sc.ab.mu && sc.ab.d_mu) {
+    const int64_t fit = (int64_t)(GG_SCRATCH / sizeof(float)) / gsize;
+    n_copies = (int)(fit < GG_MAX_COPIES ? fit : GG_MAX_COPIES);
+    if (n_copies < 1) {
+      // a grid larger than the scratch region: one copy, the caller's array
+      n_copies = 1;
+      gcopies = sc.ab.d_mu;
+    }
+    if (dt_status st = zero_f32(gcopies, gsize * n_copies, s)) return st;
+  }
   if (dt_status st = zero_f32((float*)red, 4 * (int64_t)nred, s)) return st;
   Adj adj[2];
   for (int b = 0; b < 2; ++b) {
@@ -1442,10 +1558,15 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
     if (sc.ab.mu)
       hipLaunchKernelGGL(k_adjoint<true>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
+                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red, tau);
     else
       hipLaunchKernelGGL(k_adjoint<false>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
+                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red, nullptr);
+    if (sc.ab.mu && sc.ab.d_mu) {
+      const int64_t gb = (P.cap[g] + GG_T - 1) / GG_T;
+      hipLaunchKernelGGL(k_grid_grad, dim3((unsigned)(gb < 8192 ? gb : 8192)), dim3(GG_T), 0, s, sc.ab, q, g,
+                         ctr, tau, gcopies, n_copies);
+    }
     // fcnt[nf] stays 0, so foff[nf] is the total
     if (dt_status st = dt_scan_exclusive_i32((const int32_t*)fcnt, (int32_t*)foff, scene->nf + 1, fscan, s))
       return st;
@@ -1500,6 +1621,9 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
   }
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_T), 0, s, red, nred, d_ior, d_sigma);
+  if (n_copies > 0 && gcopies != sc.ab.d_mu)
+    hipLaunchKernelGGL(k_grid_reduce, dim3(dt_blocks(gsize, 256) < 4096 ? dt_blocks(gsize, 256) : 4096), dim3(256),
+                       0, s, gcopies, n_copies, gsize, sc.ab.d_mu);
   hipLaunchKernelGGL(k_vertex_gather, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, sc.F, fg,
                      dV, dN);
   hipLaunchKernelGGL(k_nbwd_vertex, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, dN, sbar);
