@@ -78,7 +78,7 @@ def lib():
         L.or_env_kink_margin.argtypes = [C.POINTER(_Env), dp, i64, dp]
         L.or_trace.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, ip,
                                C.POINTER(C.c_uint64), ip, C.POINTER(C.c_uint64)]
-        L.or_trace_grad.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, dp, dp, dp, dp]
+        L.or_trace_grad.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, dp, dp, dp, dp, dp]
         L.or_trace_tree.argtypes = [C.POINTER(_Scene), dp, dp, dp, C.c_int]
         L.or_num_threads.restype = C.c_int
         _lib = L
@@ -99,9 +99,11 @@ class Env:
 
     def __init__(self, tex=None, mlp=None):
         self._keep = []
+        self.tex = None
         s = _Env()
         if tex is not None:
             t = _d(tex)
+            self.tex = t
             self._keep.append(t)
             s.kind, s.H, s.W = 0, t.shape[0], t.shape[1]
             s.tex = _p(t)
@@ -219,7 +221,8 @@ class Scene:
         return {"rgb": rgb, "wtrunc": wt, "flags": fl, "hash": hs, "nseg": ns, "sig": sg}
 
     def trace_grad(self, o, d, grad_rgb):
-        """Returns dict(rgb, dV [nv,3], d_eta, d_sigma [3], d_mu [nz,ny,nx,3] or None)."""
+        """Returns dict(rgb, dV [nv,3], d_eta, d_sigma [3], d_mu [nz,ny,nx,3] or None,
+        d_tex [H,W,3] (equirect environment) or None)."""
         o, d = _d(o).reshape(-1, 3), _d(d).reshape(-1, 3)
         g = _d(grad_rgb).reshape(-1, 3)
         n = len(o)
@@ -228,11 +231,14 @@ class Scene:
         de = np.zeros(1)
         ds = np.zeros(3)
         dm = np.zeros_like(self.absorb.mu) if self.absorb is not None else None
+        dt = np.zeros_like(self.env.tex) if getattr(self.env, "tex", None) is not None else None
         s = self._s()
         rc = lib().or_trace_grad(C.byref(s), _p(o), _p(d), n, _p(g), _p(rgb), _p(dV),
-                                 _p(de), _p(ds), _p(dm) if dm is not None else None)
+                                 _p(de), _p(ds), _p(dm) if dm is not None else None,
+                                 _p(dt) if dt is not None else None)
         assert rc == 0, "or_trace_grad rejected its arguments"
-        return {"rgb": rgb, "dV": dV, "d_eta": float(de[0]), "d_sigma": ds, "d_mu": dm}
+        return {"rgb": rgb, "dV": dV, "d_eta": float(de[0]), "d_sigma": ds, "d_mu": dm,
+                "d_tex": dt}
 
     def tree(self, o, d, max_rec: int = 4096):
         """Depth-first node records of one camera ray (list of dicts)."""

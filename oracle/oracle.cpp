@@ -19,7 +19,8 @@
 //     sum of mu_t at S midpoints of the segment times the step t / S (the
 //     quadrature of Eq. 11);
 //   * gradients of the rendered colours with respect to vertex positions,
-//     IoR and absorption rate (or grid values), by plain reverse-mode automatic
+//     IoR, absorption rate (or grid values) and equirect texels, by plain
+//     reverse-mode automatic
 //     differentiation (a Wengert tape per camera ray), with the discrete path
 //     (triangle ids, TIR branches, hit/miss, env texel cell) held fixed.
 //
@@ -545,6 +546,26 @@ struct EnvOut {
                        // direction where the lookup's gradient jumps
 };
 
+// Texel values of the equirect map.  For the gradient pass, g_texleaf (when
+// set) maps a texel to its three channels as tape leaves, so the lookup is
+// differentiable in the texels too.
+thread_local std::unordered_map<int, V3<Var>>* g_texleaf = nullptr;
+template <class S>
+S tex_value(const or_env& e, int r, int c, int ch);
+template <>
+inline double tex_value<double>(const or_env& e, int r, int c, int ch) {
+  return e.tex[((size_t)r * e.W + c) * 3 + ch];
+}
+template <>
+inline Var tex_value<Var>(const or_env& e, int r, int c, int ch) {
+  const double* p = e.tex + ((size_t)r * e.W + c) * 3;
+  if (!g_texleaf) return Var(p[ch]);
+  auto it = g_texleaf->find(r * e.W + c);
+  if (it == g_texleaf->end())
+    it = g_texleaf->emplace(r * e.W + c, V3<Var>{leaf(p[0]), leaf(p[1]), leaf(p[2])}).first;
+  return ch == 0 ? it->second.x : (ch == 1 ? it->second.y : it->second.z);
+}
+
 // Equirect lookup at a direction (normalised first): phi = atan2(x, -z), theta = acos(y),
 // u = phi / 2pi + 1/2, v = theta / pi, texel coords (uW - 1/2, vH - 1/2),
 // bilinear, wrapping in u and clamping in v, row 0 at the zenith.
@@ -580,14 +601,13 @@ V3<S> env_equirect(const or_env& e, V3<S> dir, EnvOut& eo) {
   auto clampy = [&](long i) { return (int)std::min<long>(std::max<long>(i, 0), e.H - 1); };
   int xa = wrapx(ix0), xb = wrapx(ix0 + 1);
   int ya = clampy(iy0), yb = clampy(iy0 + 1);
-  auto T = [&](int r, int c, int ch) { return e.tex[((size_t)r * e.W + c) * 3 + ch]; };
+  auto T = [&](int r, int c, int ch) { return tex_value<S>(e, r, c, ch); };
   S w00 = (S(1.0) - fx) * (S(1.0) - fy), w01 = fx * (S(1.0) - fy);
   S w10 = (S(1.0) - fx) * fy, w11 = fx * fy;
   V3<S> out;
   S* o[3] = {&out.x, &out.y, &out.z};
   for (int ch = 0; ch < 3; ++ch)
-    *o[ch] = w00 * S(T(ya, xa, ch)) + w01 * S(T(ya, xb, ch)) + w10 * S(T(yb, xa, ch)) +
-             w11 * S(T(yb, xb, ch));
+    *o[ch] = w00 * T(ya, xa, ch) + w01 * T(ya, xb, ch) + w10 * T(yb, xa, ch) + w11 * T(yb, xb, ch);
   return out;
 }
 
@@ -1105,11 +1125,11 @@ int or_trace(const or_scene* sc, const double* o, const double* d, int64_t n, do
 
 // Forward + reverse-mode gradient.  The scalar loss is sum_i grad_rgb[i] . C_i.
 // dV [nv*3], d_eta [1], d_sigma [3] are overwritten, and with an absorption
-// grid d_mu [nx*ny*nz*3] too (sigma then has no effect and d_sigma is 0).
-// rgb and d_mu may be NULL.
+// grid d_mu [nx*ny*nz*3] too (sigma then has no effect and d_sigma is 0), and
+// for an equirect environment d_tex [H*W*3].  rgb, d_mu and d_tex may be NULL.
 int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t n,
                   const double* grad_rgb, double* rgb, double* dV, double* d_eta,
-                  double* d_sigma, double* d_mu) {
+                  double* d_sigma, double* d_mu, double* d_tex) {
   if (!valid_scene(sc)) return 1;
   Shared sh;
   make_shared(sc, sh, true);
@@ -1121,6 +1141,8 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
   std::vector<double> accE(nth, 0.0), accS(3 * (size_t)nth, 0.0);
   const size_t nmu = sc->absorb ? 3 * (size_t)sc->absorb->nx * sc->absorb->ny * sc->absorb->nz : 0;
   std::vector<std::vector<double>> accM(nth);
+  const size_t ntex = (d_tex && sc->env->kind == 0) ? 3 * (size_t)sc->env->W * sc->env->H : 0;
+  std::vector<std::vector<double>> accT(nth);
 #pragma omp parallel
   {
     int tid = 0;
@@ -1129,12 +1151,16 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
 #endif
     accV[tid].assign(3 * (size_t)sc->nv, 0.0);
     accM[tid].assign(nmu, 0.0);
+    accT[tid].assign(ntex, 0.0);
     Tape tape;
     g_tape = &tape;
+    std::unordered_map<int, V3<Var>> texleaf;
+    g_texleaf = ntex ? &texleaf : nullptr;
 #pragma omp for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
       const double* g = grad_rgb + 3 * i;
       tape.nodes.clear();
+      texleaf.clear();
       Ctx<Var> cx;
       cx.sh = &sh;
       cx.eta = leaf(sc->eta);
@@ -1175,10 +1201,18 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
         dst[1] += adj[kv.second.y.i];
         dst[2] += adj[kv.second.z.i];
       }
+      for (auto& kv : texleaf) {
+        double* dst = accT[tid].data() + 3 * (size_t)kv.first;
+        dst[0] += adj[kv.second.x.i];
+        dst[1] += adj[kv.second.y.i];
+        dst[2] += adj[kv.second.z.i];
+      }
     }
     g_tape = nullptr;
+    g_texleaf = nullptr;
   }
   std::memset(dV, 0, sizeof(double) * 3 * (size_t)sc->nv);
+  if (ntex) std::memset(d_tex, 0, sizeof(double) * ntex);
   *d_eta = 0.0;
   d_sigma[0] = d_sigma[1] = d_sigma[2] = 0.0;
   if (d_mu && nmu) std::memset(d_mu, 0, sizeof(double) * nmu);
@@ -1189,6 +1223,7 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
     for (int k = 0; k < 3; ++k) d_sigma[k] += accS[3 * t + k];
     if (d_mu)
       for (size_t j = 0; j < nmu; ++j) d_mu[j] += accM[t][j];
+    for (size_t j = 0; j < ntex; ++j) d_tex[j] += accT[t][j];
   }
   return 0;
 }

@@ -164,3 +164,4 @@ def test_vertex_and_eta_gradient_fd_with_grid(oracle_lib):
     ad = sc.trace_grad(o, d, g * ok[:, None])
     fd = float(pix[ok].sum())
     assert abs(fd - ad["d_eta"]) <= 1e-6 * abs(ad["d_eta"]) + 1e-7, (fd, ad["d_eta"])
+
