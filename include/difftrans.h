@@ -115,7 +115,10 @@ dt_status dt_bvh_vertex_normals(const void* bvh, int32_t nv, int32_t nf, float* 
  * activations enter the bf16 matrix cores as three bf16 parts whose sum is
  * their float32 value, with float32 accumulation, so each layer is as accurate
  * as a float32 product.  Directions need not be unit: they are normalised
- * first.  Other shapes return DT_ERR_UNSUPPORTED. */
+ * first.  Other shapes return DT_ERR_UNSUPPORTED.  d_texels (EQUIRECT only;
+ * device [height][width][3], may be NULL): dt_trace_backward overwrites it
+ * with dLoss/dtexel, from every ray that leaves the object (and, with
+ * terminal_env, every ray stopped at the depth cap). */
 typedef struct {
   int32_t kind;
   int32_t width, height;
@@ -123,6 +126,7 @@ typedef struct {
   int32_t n_freq, n_layers, hidden, in_pad;
   const uint16_t* weights;
   const float* biases;
+  float* d_texels;
 } dt_env;
 
 /* rgb[i] = E(dirs[i]) for n directions (dirs, rgb: device [n][3]). */

@@ -37,7 +37,7 @@ class _Env(C.Structure):
     _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
                 ("texels", C.c_void_p), ("n_freq", C.c_int32), ("n_layers", C.c_int32),
                 ("hidden", C.c_int32), ("in_pad", C.c_int32), ("weights", C.c_void_p),
-                ("biases", C.c_void_p)]
+                ("biases", C.c_void_p), ("d_texels", C.c_void_p)]
 
 
 class _Absorption(C.Structure):
@@ -178,10 +178,12 @@ def dt_build_bvh(V, F, blob, ws):
 # ------------------------------------------------------------------ environment
 class Env:
     """Environment on the device: an equirect map [H, W, 3] float32, or (via
-    Env.mlp) a frequency-encoded MLP with bfloat16 weights."""
+    Env.mlp) a frequency-encoded MLP with bfloat16 weights.  With want_grad,
+    d_texels ([H, W, 3]) receives dLoss/dtexel from dt_trace_backward."""
 
-    def __init__(self, texels: torch.Tensor = None):
+    def __init__(self, texels: torch.Tensor = None, want_grad: bool = False):
         s = _Env()
+        self.d_texels = None
         if texels is not None:
             _dev_check(texels)
             assert texels.dtype == torch.float32 and texels.dim() == 3 and texels.shape[2] == 3
@@ -189,6 +191,9 @@ class Env:
             s.kind = ENV_EQUIRECT
             s.height, s.width = texels.shape[0], texels.shape[1]
             s.texels = texels.data_ptr()
+            if want_grad:
+                self.d_texels = torch.zeros_like(texels)
+                s.d_texels = self.d_texels.data_ptr()
         self.s = s
 
     @staticmethod

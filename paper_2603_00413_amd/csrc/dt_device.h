@@ -11,6 +11,7 @@
 struct EnvDev {
   int kind, W, H;
   const float* tex;
+  float* d_tex;  // equirect: dLoss/dtexel target of the backward (may be NULL)
   int n_freq, n_layers, hidden, in_pad;
   const uint16_t* w;
   const float* b;

@@ -54,7 +54,7 @@ struct Plan {
   size_t w_ctr, w_parts, w_part0, w_part1;
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
-  size_t w_dN, w_sbar, w_red, w_miss, w_ovf, w_tau, w_gscr;
+  size_t w_dN, w_sbar, w_red, w_miss, w_ovf, w_tau, w_gscr, w_envbar;
   size_t w_frec, w_fkey, w_fidx, w_fcnt, w_foff, w_fscan, w_fg;  // per-face gathering of vertex adjoints
   size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
   size_t ws_bytes;
@@ -146,6 +146,8 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = dt_align(o + 16 * mc);
   P.w_gscr = o;  // copies of the absorption grid's gradient, summed at the end
   o = dt_align(o + GG_SCRATCH);
+  P.w_envbar = o;  // per node: dLoss/d(environment radiance) of its lookup (texel gradient)
+  o = dt_align(o + 16 * mc);
   P.w_ovf = o;   // per-lane traversal stack overflow of the traversal grid
   o = dt_align(o + 8 * (size_t)TRACE_MAX_BLOCKS * TB * (DT_STACK - DT_STACK_LDS));
   P.w_frec = o;  // vertex-adjoint record of each node of the current generation
@@ -570,7 +572,7 @@ struct VtxAdj {
 template <bool GRID>
 __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, int64_t i,
                                              const float* grad_rgb, const Adj& nxt, const Adj& cur,
-                                             float4& acc, VtxAdj& out) {
+                                             float4& acc, VtxAdj& out, float4* envbar) {
   float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i], h4 = q.hit[i];
   uint32_t code = q.code[i];
   v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
@@ -581,6 +583,7 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
     if (sc.env.kind != DT_ENV_EQUIRECT) return;  // written by the MLP kernel
     v3 dd;
     v3 E = env_equirect_grad(sc.env, d, gW, &dd);
+    if (envbar) envbar[i] = make_float4(gW.x, gW.y, gW.z, 1.f);
     cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
     cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     cur.D[i] = make_float4(dd.x, dd.y, dd.z, 0.f);
@@ -605,6 +608,10 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
     // terminal mode ENV: L = A * E(d)
     v3 dd;
     v3 E = env_equirect_grad(sc.env, d, mul3(gW, s.A), &dd);
+    if (envbar) {
+      const v3 gE = mul3(gW, s.A);
+      envbar[i] = make_float4(gE.x, gE.y, gE.z, 1.f);
+    }
     L = mul3(s.A, E);
     Abar = mul3(gW, E);
     dbar = dd;
@@ -750,7 +757,7 @@ template <bool GRID>
 __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
                                                 const float* grad_rgb, Adj nxt, Adj cur,
                                                 FaceRec* frec, int2* fkey, uint32_t* fcnt,
-                                                float4* red, float4* tau) {
+                                                float4* red, float4* tau, float4* envbar) {
   const int64_t n = ctr->count[g];
   // each block takes one contiguous range of the generation, AB nodes a step
   const int64_t per = ((n + gridDim.x - 1) / gridDim.x + AB - 1) / AB * AB;
@@ -764,7 +771,7 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
     va.f = -1;
     va.m = mk3(0.f, 0.f, 0.f);
     va.tau = make_float4(0.f, 0.f, 0.f, 0.f);
-    adjoint_node<GRID>(sc, q, i, grad_rgb, nxt, cur, acc, va);
+    adjoint_node<GRID>(sc, q, i, grad_rgb, nxt, cur, acc, va, envbar);
     if constexpr (GRID) tau[i] = va.tau;
     int2 key = make_int2(-1, 0);
     if (va.f >= 0) {
@@ -884,6 +891,67 @@ __global__ void __launch_bounds__(GG_T) k_grid_grad(AbsorbDev G, Gen q, int g, c
       }
       wave_lds_sync();
     }
+  }
+}
+
+// dLoss/dtexel of generation g's equirect lookups: the lookup of node i (a
+// miss, or with terminal_env a hit at the depth cap) adds gE w_k at its 4
+// bilinear taps (gE = dLoss/dE per channel, left in envbar by the adjoint).  Merged as in
+// k_grid_grad: the wave parks its lanes' 12 tap values in LDS and, per
+// distinct 2 x 2 texel block among them, lanes 0-11 each sum one tap-channel
+// value over the block's lanes and add it with one atomic.
+__global__ void __launch_bounds__(GG_T) k_env_tex_grad(EnvDev e, Gen q, int g, const Counters* ctr,
+                                                       int terminal_env, const float4* envbar) {
+  __shared__ float taps[GG_T / 64][64][13];  // per wave and lane: 4 taps x 3 channels (+1 pad)
+  const int64_t n = ctr->count[g];
+  const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+  for (int64_t base = (int64_t)blockIdx.x * GG_T; base < n; base += (int64_t)gridDim.x * GG_T) {
+    const int64_t i = base + threadIdx.x;
+    float4 gb = make_float4(0.f, 0.f, 0.f, 0.f);
+    bool has = false;
+    if (i < n) {
+      const uint32_t code = q.code[i];
+      has = !(code & C_HIT) || (terminal_env && (code & C_TRUNC));
+      if (has) gb = envbar[i];
+    }
+    int key = -1;
+    float v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = 0.f;
+    if (has) {
+      EquirectTap tp;
+      equirect_tap(e, xyz(q.d[i]), tp, false);
+      // block key: top-left texel and whether the rows differ (clamped rows coincide)
+      key = ((tp.y0 << 1) | (tp.y1 != tp.y0 ? 1 : 0)) * e.W + tp.x0;
+      const float gx = 1.f - tp.fx, gy = 1.f - tp.fy;
+      const float w[4] = {gx * gy, tp.fx * gy, gx * tp.fy, tp.fx * tp.fy};  // (y0,x0) (y0,x1) (y1,x0) (y1,x1)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        v[3 * k] = gb.x * w[k];
+        v[3 * k + 1] = gb.y * w[k];
+        v[3 * k + 2] = gb.z * w[k];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) taps[wv][lane][c] = v[c];
+    wave_lds_sync();
+    uint64_t pending = __ballot(has);
+    while (pending) {
+      const int leader = __ffsll((unsigned long long)pending) - 1;
+      const int kl = __builtin_amdgcn_readlane(key, leader);
+      const uint64_t m = __ballot(has && key == kl);
+      pending &= ~m;
+      if (lane < 12) {
+        float sum = 0.f;
+        for (uint64_t mm = m; mm; mm &= mm - 1ull) sum += taps[wv][__ffsll((unsigned long long)mm) - 1][lane];
+        const int row = kl / e.W, x0 = kl % e.W;
+        const int y0 = row >> 1, y1 = y0 + (row & 1);
+        const int k = lane / 3;
+        const int y = (k >> 1) ? y1 : y0, x = (k & 1) ? (x0 + 1 == e.W ? 0 : x0 + 1) : x0;
+        atomicAdd(e.d_tex + ((size_t)y * e.W + x) * 3 + lane % 3, sum);
+      }
+    }
+    wave_lds_sync();
   }
 }
 
@@ -1341,6 +1409,7 @@ dt_status make_env(const dt_env* env, EnvDev& e) {
   e.W = env->width;
   e.H = env->height;
   e.tex = env->texels;
+  e.d_tex = env->kind == DT_ENV_EQUIRECT ? env->d_texels : nullptr;
   e.n_freq = env->n_freq;
   e.n_layers = env->n_layers;
   e.hidden = env->hidden;
@@ -1514,6 +1583,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   int32_t* fscan = (int32_t*)(W + P.w_fscan);
   float* fg = (float*)(W + P.w_fg);
   float4* tau = (float4*)(W + P.w_tau);
+  float4* envbar = sc.env.d_tex ? (float4*)(W + P.w_envbar) : nullptr;
   const int nred = (P.D + 1) * ADJ_MAX_BLOCKS;  // slot g * ADJ_MAX_BLOCKS + block
   hipLaunchKernelGGL(k_load_counters, dim3(1), dim3(64), 0, s, ctr, (const Counters*)(T + P.tape_hdr));
   if (dt_status st = zero_f32(dV, 3 * (int64_t)scene->nv, s)) return st;
@@ -1534,6 +1604,8 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
     if (dt_status st = zero_f32(gcopies, gsize * n_copies, s)) return st;
   }
+  if (sc.env.d_tex)
+    if (dt_status st = zero_f32(sc.env.d_tex, 3 * (int64_t)sc.env.W * sc.env.H, s)) return st;
   if (dt_status st = zero_f32((float*)red, 4 * (int64_t)nred, s)) return st;
   Adj adj[2];
   for (int b = 0; b < 2; ++b) {
@@ -1558,10 +1630,15 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
     if (sc.ab.mu)
       hipLaunchKernelGGL(k_adjoint<true>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red, tau);
+                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red, tau, envbar);
     else
       hipLaunchKernelGGL(k_adjoint<false>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red, nullptr);
+                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red, nullptr, envbar);
+    if (envbar) {
+      const int64_t eb = (P.cap[g] + GG_T - 1) / GG_T;
+      hipLaunchKernelGGL(k_env_tex_grad, dim3((unsigned)(eb < 8192 ? eb : 8192)), dim3(GG_T), 0, s, sc.env, q,
+                         g, ctr, sc.terminal_env, envbar);
+    }
     if (sc.ab.mu && sc.ab.d_mu) {
       const int64_t gb = (P.cap[g] + GG_T - 1) / GG_T;
       hipLaunchKernelGGL(k_grid_grad, dim3((unsigned)(gb < 8192 ? gb : 8192)), dim3(GG_T), 0, s, sc.ab, q, g,
