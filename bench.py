@@ -261,6 +261,8 @@ def main():
     grid = None
     if not args.no_grid:
         grid = grid_bench(args, dev, mesh, rays, env, ior, sigma, wl, cap, target, segs)
+        grid["env_texel_gradient"] = texel_grad_bench(args, dev, mesh, rays, ior, sigma, wl, cap,
+                                                      target, segs)
     del buf
     torch.cuda.empty_cache()
     serving = None
@@ -376,6 +378,37 @@ def grid_bench(args, dev, mesh, rays, env, ior, sigma, wl, cap, target, segs):
             "ms_per_step": round(ms, 3), "Mrays/s": round(segs / ms / 1e3, 3),
             "k_trace_ms_per_generation": np.round(tr, 4).tolist(),
             "k_adjoint_ms_per_generation": np.round(ad, 4).tolist()}
+
+
+def texel_grad_bench(args, dev, mesh, rays, ior, sigma, wl, cap, target, segs):
+    """The torus fwd+bwd step with the gradient with respect to the 512x256
+    equirect map's texels written as well."""
+    import torch
+
+    from paper_2603_00413_amd import binding as B
+    env = B.Env(torch.from_numpy(wl.env).to(dev), want_grad=True)
+    scene = B.Scene(mesh, ior, sigma, env)
+    params = B.Params(max_depth=wl.max_depth, queue_capacity=cap, checkpoint_stride=args.stride)
+    buf = B.Buffers(params, rays, mesh, tape=True)
+
+    def step():
+        mesh.build()
+        rgb, _, _ = B.dt_trace_forward(scene, rays, params, buf, want_aux=False)
+        return B.dt_trace_backward(scene, rays, params, buf, (rgb - target) * (2.0 / rgb.numel()))
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    assert torch.isfinite(env.d_texels).all() and float(env.d_texels.abs().sum()) > 0
+    log(f"texel gradient: step {ms:.2f} ms")
+    del buf
+    return {"workload": "torus-102k fwd+bwd with dLoss/dtexel of the 512x256 map",
+            "ms_per_step": round(ms, 3), "Mrays/s": round(segs / ms / 1e3, 3)}
 
 
 def mlp_flops(width, layers, in_dim=39):
