@@ -54,7 +54,7 @@ struct Plan {
   size_t w_ctr, w_parts, w_part0, w_part1;
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
-  size_t w_dN, w_sbar, w_red, w_miss, w_ovf, w_tau, w_gscr, w_envbar;
+  size_t w_dN, w_sbar, w_red, w_miss, w_ovf, w_gscr;
   size_t w_frec, w_fkey, w_fidx, w_fcnt, w_foff, w_fscan, w_fg;  // per-face gathering of vertex adjoints
   size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
   size_t ws_bytes;
@@ -142,12 +142,8 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = dt_align(o + 16 * (size_t)(DT_MAX_DEPTH + 1) * ADJ_MAX_BLOCKS);
   P.w_miss = o;  // miss list of the current generation (MLP environment)
   o = dt_align(o + 4 * mc);
-  P.w_tau = o;  // per node: dLoss/d(optical depth) of its interior segment (absorption grid)
-  o = dt_align(o + 16 * mc);
   P.w_gscr = o;  // copies of the absorption grid's gradient, summed at the end
   o = dt_align(o + GG_SCRATCH);
-  P.w_envbar = o;  // per node: dLoss/d(environment radiance) of its lookup (texel gradient)
-  o = dt_align(o + 16 * mc);
   P.w_ovf = o;   // per-lane traversal stack overflow of the traversal grid
   o = dt_align(o + 8 * (size_t)TRACE_MAX_BLOCKS * TB * (DT_STACK - DT_STACK_LDS));
   P.w_frec = o;  // vertex-adjoint record of each node of the current generation
@@ -563,7 +559,6 @@ struct VtxAdj {
   int f;  // hit face, < 0: no contributions
   v3 p0, p1, p2, m;
   float b1, b2;
-  float4 tau;  // absorption grid: (dLoss/d tau, 1) of an interior segment, else 0
 };
 
 // Adjoint of node i of generation g: writes its record (subtree radiance,
@@ -572,7 +567,7 @@ struct VtxAdj {
 template <bool GRID>
 __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, int64_t i,
                                              const float* grad_rgb, const Adj& nxt, const Adj& cur,
-                                             float4& acc, VtxAdj& out, float4* envbar) {
+                                             float4& acc, VtxAdj& out) {
   float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i], h4 = q.hit[i];
   uint32_t code = q.code[i];
   v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
@@ -583,7 +578,6 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
     if (sc.env.kind != DT_ENV_EQUIRECT) return;  // written by the MLP kernel
     v3 dd;
     v3 E = env_equirect_grad(sc.env, d, gW, &dd);
-    if (envbar) envbar[i] = make_float4(gW.x, gW.y, gW.z, 1.f);
     cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
     cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     cur.D[i] = make_float4(dd.x, dd.y, dd.z, 0.f);
@@ -608,10 +602,6 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
     // terminal mode ENV: L = A * E(d)
     v3 dd;
     v3 E = env_equirect_grad(sc.env, d, mul3(gW, s.A), &dd);
-    if (envbar) {
-      const v3 gE = mul3(gW, s.A);
-      envbar[i] = make_float4(gE.x, gE.y, gE.z, 1.f);
-    }
     L = mul3(s.A, E);
     Abar = mul3(gW, E);
     dbar = dd;
@@ -672,11 +662,10 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   // absorption on interior segments (Eq. 11): A = exp(-tau), tau = sigma t or
   // the grid's sum over the segment's samples
   float tbar = 0.f;
-  v3 oabs = mk3(0.f, 0.f, 0.f);
+  v3 oabs = mk3(0.f, 0.f, 0.f), taubar = oabs;
   if (GRID && !entering) {
-    const v3 taubar = -mul3(Abar, s.A);
+    taubar = -mul3(Abar, s.A);
     absorb_tau_bwd(sc.ab, o, d, t, taubar, tbar, oabs, dbar);
-    out.tau = make_float4(taubar.x, taubar.y, taubar.z, 1.f);
   } else if (!entering) {
     float sg0 = sc.sigma[0], sg1 = sc.sigma[1], sg2 = sc.sigma[2];
     acc.y += -Abar.x * t * s.A.x;
@@ -742,9 +731,11 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   out.p0 = p0b;
   out.p1 = p1b;
   out.p2 = p2b;
-  cur.L[i] = make_float4(L.x, L.y, L.z, 0.f);
-  cur.O[i] = make_float4(obar.x, obar.y, obar.z, 0.f);
-  cur.D[i] = make_float4(dbar.x, dbar.y, dbar.z, 0.f);
+  // the unused fourth components carry dLoss/d(optical depth) of an interior
+  // segment through an absorption grid to k_grid_grad (0 elsewhere)
+  cur.L[i] = make_float4(L.x, L.y, L.z, taubar.x);
+  cur.O[i] = make_float4(obar.x, obar.y, obar.z, taubar.y);
+  cur.D[i] = make_float4(dbar.x, dbar.y, dbar.z, taubar.z);
 }
 
 // The vertex adjoints of a generation are gathered per face without float
@@ -757,7 +748,7 @@ template <bool GRID>
 __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
                                                 const float* grad_rgb, Adj nxt, Adj cur,
                                                 FaceRec* frec, int2* fkey, uint32_t* fcnt,
-                                                float4* red, float4* tau, float4* envbar) {
+                                                float4* red) {
   const int64_t n = ctr->count[g];
   // each block takes one contiguous range of the generation, AB nodes a step
   const int64_t per = ((n + gridDim.x - 1) / gridDim.x + AB - 1) / AB * AB;
@@ -770,9 +761,7 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
     VtxAdj va;
     va.f = -1;
     va.m = mk3(0.f, 0.f, 0.f);
-    va.tau = make_float4(0.f, 0.f, 0.f, 0.f);
-    adjoint_node<GRID>(sc, q, i, grad_rgb, nxt, cur, acc, va, envbar);
-    if constexpr (GRID) tau[i] = va.tau;
+    adjoint_node<GRID>(sc, q, i, grad_rgb, nxt, cur, acc, va);
     int2 key = make_int2(-1, 0);
     if (va.f >= 0) {
       FaceRec r;
@@ -821,7 +810,7 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
 constexpr int GG_T = 256;
 constexpr int GG_MAX_COPIES = 64;
 __global__ void __launch_bounds__(GG_T) k_grid_grad(AbsorbDev G, Gen q, int g, const Counters* ctr,
-                                                    const float4* tau, float* copies, int n_copies) {
+                                                    Adj cur, float* copies, int n_copies) {
   __shared__ float runs[GG_T / 64][64][25];  // per wave and lane: a run's 24 sums (+1 pad)
   const int64_t n = ctr->count[g];
   const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
@@ -830,20 +819,19 @@ __global__ void __launch_bounds__(GG_T) k_grid_grad(AbsorbDev G, Gen q, int g, c
   const int S = G.samples;
   for (int64_t base = (int64_t)blockIdx.x * GG_T; base < n; base += (int64_t)gridDim.x * GG_T) {
     const int64_t i = base + threadIdx.x;
-    float4 tb = make_float4(0.f, 0.f, 0.f, 0.f);
-    v3 o = mk3(0.f, 0.f, 0.f), d = o;
+    v3 tb = mk3(0.f, 0.f, 0.f), o = tb, d = tb;  // tb: dLoss/d tau from the adjoint record
     float t = 0.f;
     if (i < n) {
-      tb = tau[i];
-      if (tb.w != 0.f) {
+      tb = mk3(cur.L[i].w, cur.O[i].w, cur.D[i].w);
+      if (tb.x != 0.f || tb.y != 0.f || tb.z != 0.f) {
         o = xyz(q.o[i]);
         d = xyz(q.d[i]);
         t = q.hit[i].x;
       }
     }
-    const bool act = tb.w != 0.f;
+    const bool act = tb.x != 0.f || tb.y != 0.f || tb.z != 0.f;
     const float h = t / (float)S;
-    const v3 tw = mk3(tb.x, tb.y, tb.z) * h;
+    const v3 tw = tb * h;
     int k = act ? 0 : S;  // next sample of this lane
     while (__ballot(k < S)) {
       // this lane's next run: samples k, k+1, ... in one cell
@@ -896,23 +884,40 @@ __global__ void __launch_bounds__(GG_T) k_grid_grad(AbsorbDev G, Gen q, int g, c
 
 // dLoss/dtexel of generation g's equirect lookups: the lookup of node i (a
 // miss, or with terminal_env a hit at the depth cap) adds gE w_k at its 4
-// bilinear taps (gE = dLoss/dE per channel, left in envbar by the adjoint).  Merged as in
+// bilinear taps, gE = dLoss/dE per channel = grad(pixel) W (times the
+// attenuation A of the last segment for a capped hit).  Merged as in
 // k_grid_grad: the wave parks its lanes' 12 tap values in LDS and, per
 // distinct 2 x 2 texel block among them, lanes 0-11 each sum one tap-channel
 // value over the block's lanes and add it with one atomic.
-__global__ void __launch_bounds__(GG_T) k_env_tex_grad(EnvDev e, Gen q, int g, const Counters* ctr,
-                                                       int terminal_env, const float4* envbar) {
+__global__ void __launch_bounds__(GG_T) k_env_tex_grad(SceneDev sc, Gen q, int g, const Counters* ctr,
+                                                       const float* grad_rgb) {
+  const EnvDev& e = sc.env;
   __shared__ float taps[GG_T / 64][64][13];  // per wave and lane: 4 taps x 3 channels (+1 pad)
   const int64_t n = ctr->count[g];
   const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
   for (int64_t base = (int64_t)blockIdx.x * GG_T; base < n; base += (int64_t)gridDim.x * GG_T) {
     const int64_t i = base + threadIdx.x;
-    float4 gb = make_float4(0.f, 0.f, 0.f, 0.f);
+    v3 gb = mk3(0.f, 0.f, 0.f);
     bool has = false;
+    v3 d = gb;
     if (i < n) {
       const uint32_t code = q.code[i];
-      has = !(code & C_HIT) || (terminal_env && (code & C_TRUNC));
-      if (has) gb = envbar[i];
+      has = !(code & C_HIT) || (sc.terminal_env && (code & C_TRUNC));
+      if (has) {
+        const float4 d4 = q.d[i];
+        d = xyz(d4);
+        gb = mul3(load3(grad_rgb + 3 * __float_as_int(d4.w)), xyz(q.w[i]));
+        if ((code & C_HIT) && !(code & C_ENTER)) {
+          // capped hit reached from inside: the lookup is weighted by A
+          const float t = q.hit[i].x;
+          if (sc.ab.mu) {
+            const v3 tau = absorb_tau(sc.ab, xyz(q.o[i]), d, t);
+            gb = mul3(gb, mk3(expf(-tau.x), expf(-tau.y), expf(-tau.z)));
+          } else {
+            gb = mul3(gb, mk3(expf(-sc.sigma[0] * t), expf(-sc.sigma[1] * t), expf(-sc.sigma[2] * t)));
+          }
+        }
+      }
     }
     int key = -1;
     float v[12];
@@ -920,7 +925,7 @@ __global__ void __launch_bounds__(GG_T) k_env_tex_grad(EnvDev e, Gen q, int g, c
     for (int c = 0; c < 12; ++c) v[c] = 0.f;
     if (has) {
       EquirectTap tp;
-      equirect_tap(e, xyz(q.d[i]), tp, false);
+      equirect_tap(e, d, tp, false);
       // block key: top-left texel and whether the rows differ (clamped rows coincide)
       key = ((tp.y0 << 1) | (tp.y1 != tp.y0 ? 1 : 0)) * e.W + tp.x0;
       const float gx = 1.f - tp.fx, gy = 1.f - tp.fy;
@@ -1582,8 +1587,6 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   uint32_t* foff = (uint32_t*)(W + P.w_foff);
   int32_t* fscan = (int32_t*)(W + P.w_fscan);
   float* fg = (float*)(W + P.w_fg);
-  float4* tau = (float4*)(W + P.w_tau);
-  float4* envbar = sc.env.d_tex ? (float4*)(W + P.w_envbar) : nullptr;
   const int nred = (P.D + 1) * ADJ_MAX_BLOCKS;  // slot g * ADJ_MAX_BLOCKS + block
   hipLaunchKernelGGL(k_load_counters, dim3(1), dim3(64), 0, s, ctr, (const Counters*)(T + P.tape_hdr));
   if (dt_status st = zero_f32(dV, 3 * (int64_t)scene->nv, s)) return st;
@@ -1630,19 +1633,19 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
     if (sc.ab.mu)
       hipLaunchKernelGGL(k_adjoint<true>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red, tau, envbar);
+                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
     else
       hipLaunchKernelGGL(k_adjoint<false>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red, nullptr, envbar);
-    if (envbar) {
+                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
+    if (sc.env.d_tex) {
       const int64_t eb = (P.cap[g] + GG_T - 1) / GG_T;
-      hipLaunchKernelGGL(k_env_tex_grad, dim3((unsigned)(eb < 8192 ? eb : 8192)), dim3(GG_T), 0, s, sc.env, q,
-                         g, ctr, sc.terminal_env, envbar);
+      hipLaunchKernelGGL(k_env_tex_grad, dim3((unsigned)(eb < 8192 ? eb : 8192)), dim3(GG_T), 0, s, sc, q, g,
+                         ctr, grad_rgb);
     }
     if (sc.ab.mu && sc.ab.d_mu) {
       const int64_t gb = (P.cap[g] + GG_T - 1) / GG_T;
       hipLaunchKernelGGL(k_grid_grad, dim3((unsigned)(gb < 8192 ? gb : 8192)), dim3(GG_T), 0, s, sc.ab, q, g,
-                         ctr, tau, gcopies, n_copies);
+                         ctr, adj[g & 1], gcopies, n_copies);
     }
     // fcnt[nf] stays 0, so foff[nf] is the total
     if (dt_status st = dt_scan_exclusive_i32((const int32_t*)fcnt, (int32_t*)foff, scene->nf + 1, fscan, s))
