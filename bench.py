@@ -47,8 +47,8 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h",
                     "paper_2603_00413_amd/csrc/bvh.hip"],
-        "sha256": "d73a003714b538df979be4daf8ec527442740ea22495ec2cb7b6c7d0a4d2fae5",
-        "bytes": (321514.1 * 2.0 + 85783.5) * 1024,
+        "sha256": "8e4a4a6f09c53c75e42c8f36588cc2522a0b9811a5b5912e4cbc80515ee4dbd1",
+        "bytes": (321298.4 * 2.0 + 85782.3) * 1024,
         # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:
         # wave-level VALU instructions per launch, and the share of lanes active
         # in them
