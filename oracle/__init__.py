@@ -220,9 +220,9 @@ class Scene:
         assert rc == 0, "or_trace rejected its arguments"
         return {"rgb": rgb, "wtrunc": wt, "flags": fl, "hash": hs, "nseg": ns, "sig": sg}
 
-    def trace_grad(self, o, d, grad_rgb):
+    def trace_grad(self, o, d, grad_rgb, want_tex: bool = False):
         """Returns dict(rgb, dV [nv,3], d_eta, d_sigma [3], d_mu [nz,ny,nx,3] or None,
-        d_tex [H,W,3] (equirect environment) or None)."""
+        d_tex [H,W,3] (equirect environment, with want_tex) or None)."""
         o, d = _d(o).reshape(-1, 3), _d(d).reshape(-1, 3)
         g = _d(grad_rgb).reshape(-1, 3)
         n = len(o)
@@ -231,7 +231,7 @@ class Scene:
         de = np.zeros(1)
         ds = np.zeros(3)
         dm = np.zeros_like(self.absorb.mu) if self.absorb is not None else None
-        dt = np.zeros_like(self.env.tex) if getattr(self.env, "tex", None) is not None else None
+        dt = np.zeros_like(self.env.tex) if want_tex and self.env.tex is not None else None
         s = self._s()
         rc = lib().or_trace_grad(C.byref(s), _p(o), _p(d), n, _p(g), _p(rgb), _p(dV),
                                  _p(de), _p(ds), _p(dm) if dm is not None else None,

@@ -32,7 +32,7 @@ def _check(P, seed):
     g = np.random.default_rng(seed).normal(size=rgb.shape) * ok[:, None]
     P.gpu_backward(buf, g)
     dt = P.env.d_texels.cpu().numpy().astype(np.float64)
-    o = P.orc.trace_grad(P.o, P.d, g)
+    o = P.orc.trace_grad(P.o, P.d, g, want_tex=True)
     et = np.linalg.norm(dt - o["d_tex"]) / np.linalg.norm(o["d_tex"])
     # Euler: sum d_tex * tex = sum g . C, both from the device
     lhs = float((dt * P.tex.astype(np.float64)).sum())

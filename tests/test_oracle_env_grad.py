@@ -17,7 +17,7 @@ def test_texel_gradient_euler_identity(oracle_lib):
     for absorb in (None, _random_grid(oracle_lib, 3)):
         sc, o, d = _icosphere(oracle_lib, res=20, absorb=absorb)
         g = np.random.default_rng(12).normal(size=o.shape)
-        ad = sc.trace_grad(o, d, g)
+        ad = sc.trace_grad(o, d, g, want_tex=True)
         lhs = float((ad["d_tex"] * sc.env.tex).sum())
         rhs = float((ad["rgb"] * g).sum())
         assert abs(lhs - rhs) <= 1e-11 * abs(rhs) + 1e-12, (lhs, rhs)
@@ -28,7 +28,7 @@ def test_texel_gradient_fd(oracle_lib):
     sc, o, d = _icosphere(oracle_lib, res=16)
     rng = np.random.default_rng(13)
     g = rng.normal(size=o.shape)
-    ad = sc.trace_grad(o, d, g)["d_tex"]
+    ad = sc.trace_grad(o, d, g, want_tex=True)["d_tex"]
     nz = np.argwhere(np.abs(ad) > 1e-3)
     assert len(nz) > 20
     h = 1e-4
