@@ -4,6 +4,8 @@
 mesh (V, F) and returns pixel colours; its backward runs the device adjoint
 and returns dLoss/dV, dLoss/dIoR and dLoss/dsigma (paper Sec. 3.3: vertex
 positions, index of refraction and absorption rate are optimised jointly).
+`render_grid(V, ior, mu, ...)` does the same with a spatially varying
+absorption rate, an RGB grid mu, and returns dLoss/dmu for it (Sec. 3.2).
 
 Memory policy: the forward keeps the per-generation ray state the adjoint
 needs.  When storing every generation fits the memory budget it does so;
@@ -80,12 +82,13 @@ class Tracer:
             self._key = key
         return self._mesh, self._buf
 
-    def forward(self, V: torch.Tensor, ior: torch.Tensor, sigma: torch.Tensor):
+    def forward(self, V: torch.Tensor, ior: torch.Tensor, sigma: torch.Tensor,
+                absorb: B.Absorption | None = None):
         V = V.detach().contiguous().float()
         while True:
             mesh, buf = self._prepare(V)
             scene = B.Scene(mesh, ior.detach().contiguous().float(),
-                            sigma.detach().contiguous().float(), self.env)
+                            sigma.detach().contiguous().float(), self.env, absorb=absorb)
             rgb, _, _ = B.dt_trace_forward(scene, self.rays, self._params(), buf, want_aux=False)
             stats = buf.stats.cpu()          # one small read: did a ray queue overflow?
             self.last_stats = stats
@@ -134,3 +137,27 @@ class _BroadcastSigma(torch.autograd.Function):
     def backward(ctx, grad_rgb):
         dV, d_ior, d_sigma = ctx.tracer.backward(ctx.scene, ctx.buf, grad_rgb, ctx.version)
         return dV, d_ior.reshape(1), d_sigma.sum().reshape(1), None
+
+
+class _DTTraceGrid(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, V, ior, mu, tracer, lo, hi, samples):
+        ab = B.Absorption(mu.detach().contiguous().float(), lo, hi, samples)
+        unused = torch.zeros(3, dtype=torch.float32, device=V.device)   # sigma: replaced by the grid
+        rgb, scene, buf = tracer.forward(V, ior, unused, absorb=ab)
+        ctx.tracer, ctx.scene, ctx.buf, ctx.version, ctx.ab = tracer, scene, buf, tracer.version, ab
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        dV, d_ior, _ = ctx.tracer.backward(ctx.scene, ctx.buf, grad_rgb, ctx.version)
+        return dV, d_ior.reshape(1), ctx.ab.d_mu.clone(), None, None, None, None
+
+
+def render_grid(V: torch.Tensor, ior: torch.Tensor, mu: torch.Tensor, tracer: Tracer, lo, hi,
+                samples: int = 16):
+    """Pixel colours [n_pixels, 3] with a spatially varying absorption rate:
+    mu is an RGB grid [nz, ny, nx, 3] over the box [lo, hi], trilinear,
+    `samples` midpoint samples per interior segment.  Differentiable in V,
+    ior and mu."""
+    return _DTTraceGrid.apply(V, ior, mu, tracer, lo, hi, samples)

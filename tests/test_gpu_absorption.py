@@ -141,3 +141,28 @@ def test_bad_grid_is_rejected_on_the_host():
     with pytest.raises(B.DTError):
         B.dt_trace_forward(B.Scene(P.mesh, P.ior_t, P.sigma_t, P.env, absorb=ab2), P.rays,
                            P.params, buf)
+
+
+def test_autograd_render_grid_matches_the_c_abi():
+    """loss.backward() through render_grid gives the grid, vertex and IoR
+    gradients of the direct C-ABI calls."""
+    from paper_2603_00413_amd.autograd import Tracer, render_grid
+    P = _with_grid(icosphere_pair(), seed=7, samples=8)
+    dev = P.mesh.V.device
+    g = torch.from_numpy(np.random.default_rng(8).normal(size=(P.rays.n_pixels, 3)).astype(np.float32)).to(dev)
+    buf, _, _, _ = P.gpu_forward(tape=True)
+    dV0, de0, _ = P.gpu_backward(buf, g.cpu().numpy())
+    dmu0 = P.absorb.d_mu.cpu().numpy().astype(np.float64)
+    V = torch.from_numpy(P.V32.copy()).to(dev).requires_grad_(True)
+    ior = P.ior_t.clone().requires_grad_(True)
+    mu = P.absorb.mu.clone().requires_grad_(True)
+    tr = Tracer(P.mesh.F, P.env, P.cams, max_depth=P.depth)
+    rgb = render_grid(V, ior, mu, tr, P.absorb.lo, P.absorb.hi, P.absorb.samples)
+    (rgb * g).sum().backward()
+    dV = V.grad.cpu().numpy().astype(np.float64)
+    dmu = mu.grad.cpu().numpy().astype(np.float64)
+    _print("autograd vs C ABI: dV", np.linalg.norm(dV - dV0) / np.linalg.norm(dV0),
+           "dmu", np.linalg.norm(dmu - dmu0) / np.linalg.norm(dmu0))
+    assert np.linalg.norm(dV - dV0) <= DV_ORDER_TOL * np.linalg.norm(dV0)
+    assert np.linalg.norm(dmu - dmu0) <= DV_ORDER_TOL * np.linalg.norm(dmu0)
+    assert abs(float(ior.grad.cpu()[0]) - de0) <= 1e-5 * abs(de0)
