@@ -243,8 +243,15 @@ dt_status dt_trace_forward(const dt_scene* sc, const dt_rays* rays, const dt_tra
                            size_t ws_bytes, void* stream);
 
 /* Backward: given dLoss/drgb [npix][3], accumulate nothing and overwrite
- * dV [nv][3], d_ior [1], d_sigma [3] with dLoss/d(V, ior, sigma).  Generations
- * not stored on the tape are recomputed from the nearest stored one. */
+ * dV [nv][3], d_ior [1], d_sigma [3] with dLoss/d(V, ior, sigma); with an
+ * absorption grid, also its d_mu (when not NULL; d_sigma is then 0), and for
+ * an equirect environment with d_texels set, dLoss/dtexel.  The gradients are
+ * interior derivatives: the discrete path (triangles hit, TIR branches,
+ * hit or miss, texel and grid cells) is held fixed.  Generations not stored on
+ * the tape are recomputed from the nearest stored one.  dV and the grid and
+ * texel gradients are sums whose order varies from run to run (float atomics,
+ * or records ranked by an integer atomic), so their last bits do too; d_ior
+ * and d_sigma are reduced in a fixed order. */
 dt_status dt_trace_backward(const dt_scene* sc, const dt_rays* rays, const dt_trace_params* p,
                             const float* grad_rgb, const void* tape, size_t tape_bytes,
                             float* dV, float* d_ior, float* d_sigma, void* ws, size_t ws_bytes,

@@ -1408,8 +1408,9 @@ dt_status make_env(const dt_env* env, EnvDev& e) {
   DT_REQUIRE(env->kind == DT_ENV_EQUIRECT || env->kind == DT_ENV_MLP, "unknown environment kind %d",
              env->kind);
   if (env->kind == DT_ENV_EQUIRECT)
-    DT_REQUIRE(env->texels && env->width >= 1 && env->height >= 1,
-               "equirect environment needs texels and width, height >= 1");
+    DT_REQUIRE(env->texels && env->width >= 1 && env->height >= 1 &&
+                   (int64_t)env->width * env->height <= ((int64_t)1 << 29),
+               "equirect environment needs texels and width, height >= 1 (at most 2^29 texels)");
   e.kind = env->kind;
   e.W = env->width;
   e.H = env->height;
