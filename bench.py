@@ -227,6 +227,36 @@ def main():
     fwd_ms = 1e3 * (time.perf_counter() - t1) / nf_steps
     del buf_f
 
+    def timed(fn, n):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t) / n
+
+    # the same step without the per-step tree rebuild (the mesh unchanged)
+    def step_no_rebuild():
+        rgb, _, _ = B.dt_trace_forward(scene, rays, params, buf, want_aux=False)
+        return B.dt_trace_backward(scene, rays, params, buf, (rgb - target) * (2.0 / rgb.numel()))
+    norebuild_ms = timed(step_no_rebuild, max(args.steps, 3))
+    # the recompute form: every third generation on the tape, the others
+    # traced again during the backward
+    p3 = B.Params(max_depth=wl.max_depth, queue_capacity=cap, checkpoint_stride=3)
+    buf3 = B.Buffers(p3, rays, mesh, tape=True)
+
+    def step_recompute():
+        mesh.build()
+        rgb, _, _ = B.dt_trace_forward(scene, rays, p3, buf3, want_aux=False)
+        return B.dt_trace_backward(scene, rays, p3, buf3, (rgb - target) * (2.0 / rgb.numel()))
+    recompute_ms = timed(step_recompute, max(args.steps, 3))
+    recompute_mem = (buf3.ws_bytes + buf3.tape_bytes) / 2**30
+    del buf3
+    log(f"without rebuild {norebuild_ms:.2f} ms; recompute (stride 3) {recompute_ms:.2f} ms, "
+        f"{recompute_mem:.2f} GiB workspace + tape")
+
     # per-kernel durations of the instrumented steps, on the library's stream
     timer = B.KernelTimer(wl.max_depth)
     params_t = B.Params(max_depth=wl.max_depth, queue_capacity=cap,
@@ -263,6 +293,7 @@ def main():
         grid = grid_bench(args, dev, mesh, rays, env, ior, sigma, wl, cap, target, segs)
         grid["env_texel_gradient"] = texel_grad_bench(args, dev, mesh, rays, ior, sigma, wl, cap,
                                                       target, segs)
+    buf_bytes = buf.ws_bytes + buf.tape_bytes
     del buf
     torch.cuda.empty_cache()
     serving = None
@@ -321,6 +352,12 @@ def main():
         "stress_thin_shell": stress,
         "absorption_grid": grid,
         "plain_forward": {"ms": round(fwd_ms, 3), "Mrays/s": round(segs / fwd_ms / 1e3, 3)},
+        "recompute_stride3": {"ms_per_step": round(recompute_ms, 3),
+                              "Mrays/s": round(segs / recompute_ms / 1e3, 3),
+                              "workspace_plus_tape_GiB": round(recompute_mem, 3),
+                              "store_all_GiB": round((buf_bytes) / 2**30, 3)},
+        "camera_rays_per_s": {"with_rebuild": round(N / (ms_step * 1e-3)),
+                              "without_rebuild": round(N / (norebuild_ms * 1e-3))},
         "kernel_ms_per_generation": {"k_trace": np.round(tr_ms, 4).tolist(),
                                      "k_adjoint": np.round(ad_ms, 4).tolist()},
         "cpu_baseline": cpu,
