@@ -47,12 +47,12 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h",
                     "paper_2603_00413_amd/csrc/bvh.hip"],
-        "sha256": "8e4a4a6f09c53c75e42c8f36588cc2522a0b9811a5b5912e4cbc80515ee4dbd1",
-        "bytes": (321298.4 * 2.0 + 85782.3) * 1024,
+        "sha256": "3586e9123f84fd1844adb20db1444300699a7585700517fe9acbfb15936b5aae",
+        "bytes": (317329.1 * 2.0 + 79383.1) * 1024,
         # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:
         # wave-level VALU instructions per launch, and the share of lanes active
         # in them
-        "valu_insts": 2.610e8,
+        "valu_insts": 2.605e8,
         "lane_utilization": 0.62,
     },
 }
