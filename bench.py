@@ -9,7 +9,13 @@ shade, compaction, environment, pixel accumulation) with its tape, the
 gradient of an L2 loss, and the adjoint sweep to dV, dIoR, dsigma.
 
 Metric: Mrays/s = ray segments intersected per step (every generation,
-counted once) / step time.  Prints one JSON line.
+counted once) / step time.  Prints one JSON line.  Beside the headline it
+reports the plain forward, the recompute form (stride 3), camera rays/s with
+and without the tree rebuild, and further legs unless switched off: a
+spatially varying absorption grid with its gradient and the texel gradient
+(--no-grid), the serving loop (--no-serve), the MLP-lit training step
+(--no-mlp), the 2M-triangle thin shell (--no-stress) and the oracle's CPU
+rate (--no-cpu-baseline).
 """
 from __future__ import annotations
 
