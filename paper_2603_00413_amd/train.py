@@ -1,0 +1,152 @@
+"""Training-step pieces around the tracer (Sec. 3.3 "Optimization", and the
+regularizers of the appendix on the ray tracer's optimization).
+
+The tracer returns pixel colours and, through `autograd.render` /
+`autograd.render_grid`, their gradients; this module holds the losses the
+paper puts on those colours and on the parameters, and a step that renders,
+adds the losses up and updates the parameters:
+
+* L_color: per pixel the squared norm of (c_hat - c) * c (the error weighted
+  by the ground-truth colour, so over-absorbed dark pixels weigh less),
+  averaged over the batch;
+* L_tone: (1 - cos(c_hat, c))^2 - var(c) per pixel, var the variance of c's
+  three channels (a constant: it shifts the loss, not its gradient);
+* L_mat-smooth: mean over sample points of |mu(v) - mu(v + xi)| (L1 over the
+  channels) for the absorption grid;
+* L_vol: sum over sample points of ||mu(x)||^2;
+* L_edge: mean over mesh edges of (1 - n_i . n_j)^2 with the vertex normals.
+
+The paper optimises the mesh with AdamUniform (a Laplacian-preconditioned
+parameterisation); this step uses plain Adam for every parameter.  The mask
+term needs silhouettes, which the interior-derivative tracer does not give.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import autograd as A
+
+
+def color_loss(pred: torch.Tensor, gt: torch.Tensor) -> torch.Tensor:
+    """mean_i ||(c_hat_i - c_i) * c_i||^2 over pixels [n, 3]."""
+    return (((pred - gt) * gt) ** 2).sum(-1).mean()
+
+
+def tone_loss(pred: torch.Tensor, gt: torch.Tensor, eps: float = 1e-12) -> torch.Tensor:
+    """mean_i (1 - cos(c_hat_i, c_i))^2 - var(c_i), var over the 3 channels."""
+    cos = (pred * gt).sum(-1) / (pred.norm(dim=-1) * gt.norm(dim=-1)).clamp_min(eps)
+    return ((1.0 - cos) ** 2 - gt.var(dim=-1, unbiased=False)).mean()
+
+
+def grid_rate(mu: torch.Tensor, lo, hi, x: torch.Tensor) -> torch.Tensor:
+    """The absorption grid's rate at points x [n, 3]: trilinear over mu
+    [nz, ny, nx, 3] on the box [lo, hi], x clamped into the box (the same
+    definition the tracer uses)."""
+    nz, ny, nx, _ = mu.shape
+    n = torch.tensor([nx, ny, nz], dtype=x.dtype, device=x.device)
+    lo_t = torch.as_tensor(lo, dtype=x.dtype, device=x.device)
+    hi_t = torch.as_tensor(hi, dtype=x.dtype, device=x.device)
+    u = ((x - lo_t) * (n - 1) / (hi_t - lo_t)).clamp(min=0.0)
+    u = torch.minimum(u, n - 1)
+    i = torch.minimum(u.floor(), n - 2).long()
+    f = u - i.to(x.dtype)
+    out = torch.zeros(x.shape[0], 3, dtype=mu.dtype, device=x.device)
+    for c in range(8):
+        dx, dy, dz = c & 1, (c >> 1) & 1, c >> 2
+        w = ((f[:, 0] if dx else 1 - f[:, 0]) * (f[:, 1] if dy else 1 - f[:, 1]) *
+             (f[:, 2] if dz else 1 - f[:, 2]))
+        out = out + w[:, None] * mu[i[:, 2] + dz, i[:, 1] + dy, i[:, 0] + dx]
+    return out
+
+
+def mat_smooth_loss(mu, lo, hi, pts: torch.Tensor, xi: torch.Tensor) -> torch.Tensor:
+    """mean_i |mu(v_i) - mu(v_i + xi_i)| (L1 over the channels)."""
+    return (grid_rate(mu, lo, hi, pts) - grid_rate(mu, lo, hi, pts + xi)).abs().sum(-1).mean()
+
+
+def vol_loss(mu, lo, hi, pts: torch.Tensor) -> torch.Tensor:
+    """sum_i ||mu(x_i)||^2."""
+    return (grid_rate(mu, lo, hi, pts) ** 2).sum()
+
+
+def vertex_normals(V: torch.Tensor, F: torch.Tensor) -> torch.Tensor:
+    """Normalised sum of the unit normals of the faces around each vertex
+    (the tracer's shading normals, Eq. 12-13), differentiable in V."""
+    F = F.long()
+    e1 = V[F[:, 1]] - V[F[:, 0]]
+    e2 = V[F[:, 2]] - V[F[:, 0]]
+    fn = torch.cross(e1, e2, dim=-1)
+    fn = fn / fn.norm(dim=-1, keepdim=True).clamp_min(1e-30)
+    acc = torch.zeros_like(V)
+    for k in range(3):
+        acc = acc.index_add(0, F[:, k], fn)
+    return acc / acc.norm(dim=-1, keepdim=True).clamp_min(1e-30)
+
+
+def mesh_edges(F: torch.Tensor) -> torch.Tensor:
+    """Unique undirected edges [m, 2] of a triangle list."""
+    F = F.long()
+    e = torch.cat([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
+    e = torch.sort(e, dim=1).values
+    return torch.unique(e, dim=0)
+
+
+def edge_loss(V: torch.Tensor, F: torch.Tensor, edges: torch.Tensor | None = None) -> torch.Tensor:
+    """mean over edges (i, j) of (1 - n_i . n_j)^2."""
+    if edges is None:
+        edges = mesh_edges(F)
+    n = vertex_normals(V, F)
+    return ((1.0 - (n[edges[:, 0]] * n[edges[:, 1]]).sum(-1)) ** 2).mean()
+
+
+class Trainer:
+    """One optimisation step of the paper's ray-tracing stage: render with the
+    current parameters, L_total = l_color L_color + l_tone L_tone (+ l_smooth
+    L_mat-smooth + l_vol L_vol with an absorption grid) + l_edge L_edge, Adam
+    on every parameter given as a tensor with requires_grad."""
+
+    def __init__(self, tracer: A.Tracer, V: torch.Tensor, ior: torch.Tensor,
+                 sigma: torch.Tensor | None = None, grid=None, lr: float = 1e-3,
+                 l_color: float = 1.0, l_tone: float = 0.0, l_smooth: float = 0.0,
+                 l_vol: float = 0.0, l_edge: float = 0.0, n_points: int = 4096, seed: int = 0):
+        """grid: (mu, lo, hi, samples) with mu a leaf tensor [nz, ny, nx, 3]."""
+        self.tracer, self.V, self.ior, self.sigma, self.grid = tracer, V, ior, sigma, grid
+        self.w = dict(color=l_color, tone=l_tone, smooth=l_smooth, vol=l_vol, edge=l_edge)
+        params = [p for p in (V, ior, sigma, grid[0] if grid else None)
+                  if p is not None and p.requires_grad]
+        self.opt = torch.optim.Adam(params, lr=lr)
+        self.n_points = n_points
+        self.gen = torch.Generator(device=V.device).manual_seed(seed)
+        self.edges = mesh_edges(tracer.F) if l_edge else None
+
+    def _points(self, lo, hi):
+        lo_t = torch.as_tensor(lo, dtype=torch.float32, device=self.V.device)
+        hi_t = torch.as_tensor(hi, dtype=torch.float32, device=self.V.device)
+        r = torch.rand(self.n_points, 3, generator=self.gen, device=self.V.device)
+        return lo_t + r * (hi_t - lo_t), (hi_t - lo_t)
+
+    def step(self, gt: torch.Tensor) -> dict:
+        self.opt.zero_grad(set_to_none=True)
+        if self.grid is not None:
+            mu, lo, hi, samples = self.grid
+            pred = A.render_grid(self.V, self.ior, mu, self.tracer, lo, hi, samples)
+        else:
+            pred = A.render(self.V, self.ior, self.sigma, self.tracer)
+        terms = {"color": color_loss(pred, gt)}
+        if self.w["tone"]:
+            terms["tone"] = tone_loss(pred, gt)
+        if self.grid is not None and (self.w["smooth"] or self.w["vol"]):
+            pts, ext = self._points(lo, hi)
+            if self.w["smooth"]:
+                xi = (torch.rand(pts.shape, generator=self.gen, device=pts.device) - 0.5) * 0.02 * ext
+                terms["smooth"] = mat_smooth_loss(mu, lo, hi, pts, xi)
+            if self.w["vol"]:
+                terms["vol"] = vol_loss(mu, lo, hi, pts)
+        if self.w["edge"]:
+            terms["edge"] = edge_loss(self.V, self.tracer.F, self.edges)
+        total = sum(self.w[k] * v for k, v in terms.items())
+        total.backward()
+        self.opt.step()
+        out = {k: float(v.detach()) for k, v in terms.items()}
+        out["total"] = float(total.detach())
+        return out

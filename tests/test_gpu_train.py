@@ -1,0 +1,34 @@
+"""A few optimisation steps of the ray-tracing stage through the tracer's
+gradients recover a perturbed IoR (Sec. 3.3 "Optimization")."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_00413_amd import autograd as A
+from paper_2603_00413_amd import binding as B
+from paper_2603_00413_amd import synth
+from paper_2603_00413_amd import train as T
+
+pytestmark = pytest.mark.gpu
+
+
+def test_ior_recovery_with_adam():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    dev = torch.device("cuda:0")
+    wl = synth.icosphere_scene(sigma=(0.5, 0.2, 0.1), res=64)
+    V = torch.from_numpy(wl.V.astype(np.float32)).to(dev)
+    F = torch.from_numpy(wl.F).to(dev)
+    env = B.Env(torch.from_numpy(wl.env).to(dev))
+    sigma = torch.tensor(wl.sigma, dtype=torch.float32, device=dev)
+    tr = A.Tracer(F, env, wl.cameras, max_depth=wl.max_depth)
+    with torch.no_grad():
+        gt = A.render(V, torch.tensor([1.45], device=dev), sigma, tr).clone()
+    ior = torch.tensor([1.38], device=dev, requires_grad=True)
+    trainer = T.Trainer(tr, V, ior, sigma=sigma, lr=0.005, l_color=1.0, l_tone=0.1)
+    first = trainer.step(gt)["total"]
+    for _ in range(60):
+        last = trainer.step(gt)["total"]
+    print("ior", float(ior.detach()), "loss", first, "->", last, flush=True)
+    assert abs(float(ior.detach()) - 1.45) < 0.01
+    assert last < 0.1 * first
