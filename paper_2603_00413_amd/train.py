@@ -16,9 +16,10 @@ adds the losses up and updates the parameters:
 * L_vol: sum over sample points of ||mu(x)||^2;
 * L_edge: mean over mesh edges of (1 - n_i . n_j)^2 with the vertex normals.
 
-The paper optimises the mesh with AdamUniform (a Laplacian-preconditioned
-parameterisation); this step uses plain Adam for every parameter.  The mask
-term needs silhouettes, which the interior-derivative tracer does not give.
+The vertices are optimised either with plain Adam or, as in the paper, with
+AdamUniform on the Laplacian reparameterisation u = (I + lambda L) V (below);
+the other parameters with Adam.  The mask term needs silhouettes, which the
+interior-derivative tracer does not give.
 """
 from __future__ import annotations
 
@@ -102,19 +103,27 @@ def edge_loss(V: torch.Tensor, F: torch.Tensor, edges: torch.Tensor | None = Non
 class Trainer:
     """One optimisation step of the paper's ray-tracing stage: render with the
     current parameters, L_total = l_color L_color + l_tone L_tone (+ l_smooth
-    L_mat-smooth + l_vol L_vol with an absorption grid) + l_edge L_edge, Adam
-    on every parameter given as a tensor with requires_grad."""
+    L_mat-smooth + l_vol L_vol with an absorption grid) + l_edge L_edge, and
+    update every parameter given as a tensor with requires_grad: Adam, or for
+    the vertices with large_steps = lambda, AdamUniform on u = (I + lambda L) V
+    at learning rate lr_mesh."""
 
     def __init__(self, tracer: A.Tracer, V: torch.Tensor, ior: torch.Tensor,
                  sigma: torch.Tensor | None = None, grid=None, lr: float = 1e-3,
                  l_color: float = 1.0, l_tone: float = 0.0, l_smooth: float = 0.0,
-                 l_vol: float = 0.0, l_edge: float = 0.0, n_points: int = 4096, seed: int = 0):
+                 l_vol: float = 0.0, l_edge: float = 0.0, n_points: int = 4096, seed: int = 0,
+                 large_steps: float | None = None, lr_mesh: float = 1e-3):
         """grid: (mu, lo, hi, samples) with mu a leaf tensor [nz, ny, nx, 3]."""
         self.tracer, self.V, self.ior, self.sigma, self.grid = tracer, V, ior, sigma, grid
         self.w = dict(color=l_color, tone=l_tone, smooth=l_smooth, vol=l_vol, edge=l_edge)
-        params = [p for p in (V, ior, sigma, grid[0] if grid else None)
+        self.ls, self.u, self.opt_mesh = None, None, None
+        if large_steps is not None and V.requires_grad:
+            self.ls = LargeSteps(V.shape[0], tracer.F, large_steps)
+            self.u = self.ls.to_u(V.detach()).requires_grad_(True)
+            self.opt_mesh = AdamUniform([self.u], lr=lr_mesh)
+        params = [p for p in (None if self.ls else V, ior, sigma, grid[0] if grid else None)
                   if p is not None and p.requires_grad]
-        self.opt = torch.optim.Adam(params, lr=lr)
+        self.opt = torch.optim.Adam(params, lr=lr) if params else None
         self.n_points = n_points
         self.gen = torch.Generator(device=V.device).manual_seed(seed)
         self.edges = mesh_edges(tracer.F) if l_edge else None
@@ -126,7 +135,11 @@ class Trainer:
         return lo_t + r * (hi_t - lo_t), (hi_t - lo_t)
 
     def step(self, gt: torch.Tensor) -> dict:
-        self.opt.zero_grad(set_to_none=True)
+        for o in (self.opt, self.opt_mesh):
+            if o is not None:
+                o.zero_grad(set_to_none=True)
+        if self.ls is not None:
+            self.V = _FromU.apply(self.u, self.ls)
         if self.grid is not None:
             mu, lo, hi, samples = self.grid
             pred = A.render_grid(self.V, self.ior, mu, self.tracer, lo, hi, samples)
@@ -146,7 +159,112 @@ class Trainer:
             terms["edge"] = edge_loss(self.V, self.tracer.F, self.edges)
         total = sum(self.w[k] * v for k, v in terms.items())
         total.backward()
-        self.opt.step()
+        for o in (self.opt, self.opt_mesh):
+            if o is not None:
+                o.step()
         out = {k: float(v.detach()) for k, v in terms.items()}
         out["total"] = float(total.detach())
         return out
+
+
+# ---------------------------------------------------------------- AdamUniform
+# The mesh optimiser the paper adopts (Nicolet, Jacobson and Jakob, "Large
+# Steps in Inverse Rendering of Geometry", SIGGRAPH Asia 2021): the vertices
+# are reparameterised as u = (I + lambda L) V with L the combinatorial graph
+# Laplacian of the mesh, u is updated by Adam whose step is scaled uniformly
+# (the second-moment estimate is replaced by its maximum over the whole
+# parameter, so every entry moves at the same rate), and V is recovered by
+# solving (I + lambda L) V = u.
+
+
+def laplacian(nv: int, F: torch.Tensor) -> torch.Tensor:
+    """Combinatorial Laplacian D - A of the mesh's edge graph, sparse [nv, nv]."""
+    e = mesh_edges(F)
+    i = torch.cat([e[:, 0], e[:, 1]])
+    j = torch.cat([e[:, 1], e[:, 0]])
+    ones = torch.ones(i.shape[0], dtype=torch.float64, device=F.device)
+    deg = torch.zeros(nv, dtype=torch.float64, device=F.device).index_add(0, i, ones)
+    d = torch.arange(nv, device=F.device)
+    idx = torch.cat([torch.stack([i, j]), torch.stack([d, d])], 1)
+    val = torch.cat([-ones, deg])
+    return torch.sparse_coo_tensor(idx, val, (nv, nv)).coalesce()
+
+
+def solve_spd(matvec, b: torch.Tensor, iters: int = 200, tol: float = 1e-10) -> torch.Tensor:
+    """Conjugate gradients for A x = b (A symmetric positive definite, given as
+    matvec), column by column of b [n, k]."""
+    x = torch.zeros_like(b)
+    r = b - matvec(x)
+    p = r.clone()
+    rs = (r * r).sum(0)
+    b2 = (b * b).sum(0).clamp_min(1e-300)
+    for _ in range(iters):
+        if bool((rs <= tol * tol * b2).all()):
+            break
+        Ap = matvec(p)
+        alpha = rs / (p * Ap).sum(0)
+        x = x + alpha * p
+        r = r - alpha * Ap
+        rs_new = (r * r).sum(0)
+        p = r + (rs_new / rs) * p
+        rs = rs_new
+    return x
+
+
+class LargeSteps:
+    """u = (I + lam L) V and back, for one mesh."""
+
+    def __init__(self, nv: int, F: torch.Tensor, lam: float):
+        self.L = laplacian(nv, F)
+        self.lam = lam
+
+    def matvec(self, x: torch.Tensor) -> torch.Tensor:
+        return x + self.lam * torch.sparse.mm(self.L, x)
+
+    def to_u(self, V: torch.Tensor) -> torch.Tensor:
+        return self.matvec(V.double()).to(V.dtype)
+
+    def to_v(self, u: torch.Tensor) -> torch.Tensor:
+        return solve_spd(self.matvec, u.double()).to(u.dtype)
+
+
+class AdamUniform(torch.optim.Optimizer):
+    """Adam with a uniform step: the bias-corrected second moment is replaced
+    by its maximum over each parameter tensor."""
+
+    def __init__(self, params, lr: float = 1e-3, betas=(0.9, 0.999), eps: float = 1e-8):
+        super().__init__(params, dict(lr=lr, betas=betas, eps=eps))
+
+    @torch.no_grad()
+    def step(self, closure=None):
+        for group in self.param_groups:
+            b1, b2 = group["betas"]
+            for p in group["params"]:
+                if p.grad is None:
+                    continue
+                st = self.state[p]
+                if not st:
+                    st["t"] = 0
+                    st["m"] = torch.zeros_like(p)
+                    st["v"] = torch.zeros_like(p)
+                st["t"] += 1
+                t = st["t"]
+                st["m"].mul_(b1).add_(p.grad, alpha=1 - b1)
+                st["v"].mul_(b2).addcmul_(p.grad, p.grad, value=1 - b2)
+                m_hat = st["m"] / (1 - b1 ** t)
+                v_max = (st["v"] / (1 - b2 ** t)).max()
+                p.add_(m_hat / (v_max.sqrt() + group["eps"]), alpha=-group["lr"])
+
+
+class _FromU(torch.autograd.Function):
+    """V = (I + lambda L)^-1 u; the matrix is symmetric, so the backward is
+    the same solve applied to the incoming gradient."""
+
+    @staticmethod
+    def forward(ctx, u, ls):
+        ctx.ls = ls
+        return ls.to_v(u)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ctx.ls.to_v(g.contiguous()), None

@@ -32,3 +32,33 @@ def test_ior_recovery_with_adam():
     print("ior", float(ior.detach()), "loss", first, "->", last, flush=True)
     assert abs(float(ior.detach()) - 1.45) < 0.01
     assert last < 0.1 * first
+
+
+def test_vertex_steps_with_adam_uniform_reduce_the_loss():
+    """The vertices of a radially perturbed sphere, optimised through the
+    tracer's vertex gradient with AdamUniform on the Laplacian
+    reparameterisation, move toward the target: the image loss falls."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    dev = torch.device("cuda:0")
+    wl = synth.icosphere_scene(sigma=(0.5, 0.2, 0.1), res=64)
+    V0 = torch.from_numpy(wl.V.astype(np.float32)).to(dev)
+    F = torch.from_numpy(wl.F).to(dev)
+    env = B.Env(torch.from_numpy(wl.env).to(dev))
+    sigma = torch.tensor(wl.sigma, dtype=torch.float32, device=dev)
+    ior = torch.tensor([wl.ior], dtype=torch.float32, device=dev)
+    tr = A.Tracer(F, env, wl.cameras, max_depth=wl.max_depth)
+    with torch.no_grad():
+        gt = A.render(V0, ior, sigma, tr).clone()
+    V = (V0 * 0.97).clone().requires_grad_(True)
+    trainer = T.Trainer(tr, V, ior, sigma=sigma, large_steps=4.0, lr_mesh=4e-3)
+    first = trainer.step(gt)["total"]
+    for _ in range(40):
+        last = trainer.step(gt)["total"]
+    err0 = float((V0 * 0.97 - V0).norm())
+    err1 = float((trainer.V.detach() - V0).norm())
+    print("loss", first, "->", last, "vertex error", err0, "->", err1, flush=True)
+    # measured at lr 2e-3 over 30 steps: 0.155 -> 0.111, vertex error 0.760 -> 0.741;
+    # at 4e-3 over 40 steps (this test) the loss falls further
+    assert last < 0.8 * first
+    assert err1 < err0

@@ -57,3 +57,29 @@ def test_vertex_normals_match_the_oracle_and_edge_loss():
     Fp = np.array([[i * 4 + j, (i + 1) * 4 + j, i * 4 + j + 1] for i in range(3) for j in range(3)] +
                   [[(i + 1) * 4 + j, (i + 1) * 4 + j + 1, i * 4 + j + 1] for i in range(3) for j in range(3)])
     assert float(T.edge_loss(torch.from_numpy(Vp), torch.from_numpy(Fp))) < 1e-28
+
+
+def test_laplacian_and_large_steps_roundtrip():
+    V, F = synth.icosphere(2)
+    Ft = torch.from_numpy(F)
+    L = T.laplacian(len(V), Ft).to_dense().numpy()
+    assert np.allclose(L, L.T) and np.abs(L.sum(1)).max() == 0.0
+    deg = np.diag(L)
+    assert deg.min() >= 5 and deg.max() <= 6          # icosphere valences
+    ls = T.LargeSteps(len(V), Ft, lam=10.0)
+    Vt = torch.from_numpy(V)
+    u = ls.to_u(Vt)
+    np.testing.assert_allclose(u.numpy(), (np.eye(len(V)) + 10.0 * L) @ V, atol=1e-12)
+    np.testing.assert_allclose(ls.to_v(u).numpy(), V, atol=1e-8)
+
+
+def test_adam_uniform_step_matches_its_definition():
+    g = torch.tensor([[0.5, -2.0], [1.0, 0.25]], dtype=torch.float64)
+    p = torch.zeros(2, 2, dtype=torch.float64, requires_grad=True)
+    opt = T.AdamUniform([p], lr=0.1)
+    for t in (1, 2):
+        p.grad = g.clone()
+        opt.step()
+    # two identical gradients: m_hat = g, v_hat = g^2, step = lr g / max|g| each time
+    expect = -2 * 0.1 * g.numpy() / (np.abs(g.numpy()).max() + 1e-8)
+    np.testing.assert_allclose(p.detach().numpy(), expect, rtol=1e-12)
