@@ -10,8 +10,9 @@
  * travelled inside the object is attenuated by exp(-sigma t) (Beer-Lambert,
  * Eq. 9-11, constant RGB absorption rate); a ray that leaves the object takes
  * the environment radiance of its direction.  The shading normal is the
- * barycentric blend of vertex normals (Eq. 12), each the normalised mean of the
- * unit normals of the faces around the vertex (Eq. 13).  The hit point is a
+ * barycentric blend of vertex normals (Eq. 12), normalised, each vertex normal
+ * one third of the sum of the unit normals of the faces around the vertex
+ * (Eq. 13, as written: not itself normalised).  The hit point is a
  * differentiable function of the three vertices of the first triangle hit, so
  * pixel losses back-propagate to vertex positions, the index of refraction and
  * the absorption rate (the interior derivative with the discrete path - which
@@ -84,8 +85,8 @@ typedef int32_t dt_status;
 dt_status dt_bvh_bytes(int32_t nv, int32_t nf, size_t* bvh_bytes, size_t* ws_bytes);
 
 /* Build the scene acceleration data from V [nv][3] and F [nf][3]: unit face
- * normals, vertex normals (Eq. 13: normalised sum of the unit normals of the
- * incident faces, in ascending face order, zero-area faces skipped), and a
+ * normals, vertex normals (Eq. 13: one third of the sum of the unit normals of
+ * the incident faces, in ascending face order, zero-area faces skipped), and a
  * linear BVH (63-bit Morton codes of face centroids, their top 32 bits up to
  * 2^20 faces, stable radix sort, binary
  * radix tree with index tie-break, bottom-up box fit, then small treelets

@@ -7,7 +7,8 @@
 //
 // What it computes (paper, Sec. 3.3 "Differentiable Mesh Ray Tracer" and
 // Sec. 3.2 "Light Interaction with Transparent Objects"):
-//   * vertex normals: mean of unit face normals, normalised (Eq. 12-13);
+//   * vertex normals: one third of the sum of the unit face normals (Eq. 13),
+//     blended with the barycentric weights and then normalised (Eq. 12);
 //   * closest-hit ray/triangle intersection ("first triangle the ray hits");
 //   * recursive tracing to a depth cap: a miss returns the environment
 //     radiance, a hit splits into a reflected ray (Eq. 3) and a refracted ray
@@ -26,7 +27,7 @@
 //
 // Readings where the paper is silent or garbled are listed in the design
 // notes; in short: cos(theta_i) = -d.n, eta_r = eta_t/eta_i with ambient IoR
-// 1, normals are renormalised, inside/outside is decided by the geometric
+// 1, the blended shading normal is normalised, inside/outside is decided by the geometric
 // normal of the hit, a ray hitting at the depth cap contributes 0 and its
 // weight is reported as truncated, the environment is at infinity (equirect
 // bilinear lookup or a frequency-encoded MLP of the direction).
@@ -35,8 +36,9 @@
 // Fresnel textbook values, energy conservation, invisible object at eta = 1,
 // brute force vs BVH, central finite differences for every gradient).
 //
-// Everything is FP64.  The MLP environment emulates bfloat16 rounding of its
-// inputs, weights and hidden activations and accumulates in FP64.
+// Everything is FP64.  The MLP environment is a plain FP64 network: its
+// weights are whatever the caller passes (the tests pass the device's bf16
+// weights widened exactly), and every activation, product and sum is FP64.
 
 #include <algorithm>
 #include <cmath>
@@ -470,9 +472,11 @@ struct Ctx<Var> {
   }
 };
 
-// Eq. 12-13: vertex normal = normalised sum of unit face normals of the faces
-// around the vertex (the constant 1/3 cancels in the normalisation).  Faces
-// of zero area contribute nothing.
+// Eq. 13: vertex normal = one third of the sum of the unit normals of the
+// faces around the vertex, as written (not renormalised: its length grows
+// with the valence and shrinks with the spread of the face normals, and so
+// does its weight in the blend of Eq. 12).  Faces of zero area contribute
+// nothing.
 template <class S>
 V3<S> vertex_normal_def(const Shared& sh, int v, Ctx<S>& cx) {
   V3<S> acc{S(0.0), S(0.0), S(0.0)};
@@ -484,8 +488,7 @@ V3<S> vertex_normal_def(const Shared& sh, int v, Ctx<S>& cx) {
     if (!(len2 > 0.0)) continue;
     acc = add(acc, normalize(n));
   }
-  if (!(val(dot(acc, acc)) > 0.0)) return acc;
-  return normalize(acc);
+  return scl(acc, S(1.0 / 3.0));
 }
 
 // ---------------------------------------------------------------------------
@@ -821,7 +824,8 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
   V3<S> ng = cross(e1, e2);
   // Procedure step 2: outside / inside by the geometric normal of the hit
   bool entering = val(dot(d, ng)) < 0.0;
-  // Eq. 12: shading normal = barycentric blend of vertex normals, renormalised
+  // Eq. 12: shading normal = barycentric blend of the vertex normals of Eq. 13,
+  // normalised for Eq. 3-6
   V3<S> m = add(add(scl(cx.nrm(i0), b0), scl(cx.nrm(i1), b1)), scl(cx.nrm(i2), b2));
   V3<S> n = normalize(m);
   if (!entering) n = scl(n, S(-1.0));

@@ -133,15 +133,16 @@ __global__ void k_vsort(const int32_t* off, int32_t nv, int32_t* idx) {
   }
 }
 
-// Eq. 13: normalised sum of the unit normals of the incident faces
+// Eq. 13: one third of the sum of the unit normals of the incident faces, in
+// ascending face order (not renormalised: the shading normal normalises the
+// barycentric blend of Eq. 12 instead)
 __global__ void k_vnormals(const int32_t* off, const int32_t* idx, const float4* fn, int32_t nv,
                            float4* vn) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   v3 s = mk3(0.f, 0.f, 0.f);
   for (int i = off[v]; i < off[v + 1]; ++i) s += xyz(fn[idx[i]]);
-  float l2 = dot(s, s);
-  v3 n = l2 > 0.0f ? s * (1.0f / sqrtf(l2)) : s;
+  v3 n = s * (1.0f / 3.0f);
   vn[v] = make_float4(n.x, n.y, n.z, 0.0f);
 }
 

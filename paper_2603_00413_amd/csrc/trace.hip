@@ -1129,20 +1129,12 @@ __global__ void __launch_bounds__(LB) k_list_misses(Gen q, int g, Counters* ctr,
 }
 
 // ------------------------------------------------------------------ normals backward (Eq. 13)
-// N_v = normalize(s_v), s_v = sum of unit face normals u_f, u_f = normalize(c_f),
+// N_v = s_v / 3, s_v = sum of unit face normals u_f, u_f = normalize(c_f),
 // c_f = (p1 - p0) x (p2 - p0).
 __global__ void k_nbwd_vertex(const BvhView bv, const float* dN, float4* sbar) {
   int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= bv.nv) return;
-  v3 s = mk3(0.f, 0.f, 0.f);
-  for (int k = bv.csr_off[v]; k < bv.csr_off[v + 1]; ++k) s += xyz(bv.fn[bv.csr_idx[k]]);
-  float l2 = dot(s, s);
-  v3 r = mk3(0.f, 0.f, 0.f);
-  if (l2 > 0.f) {
-    v3 N = xyz(bv.vn[v]);
-    v3 g = load3(dN + 3 * v);
-    r = (g - N * dot(N, g)) * (1.0f / sqrtf(l2));
-  }
+  v3 r = load3(dN + 3 * v) * (1.0f / 3.0f);
   sbar[v] = make_float4(r.x, r.y, r.z, 0.f);
 }
 

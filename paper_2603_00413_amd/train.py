@@ -14,7 +14,8 @@ adds the losses up and updates the parameters:
 * L_mat-smooth: mean over sample points of |mu(v) - mu(v + xi)| (L1 over the
   channels) for the absorption grid;
 * L_vol: sum over sample points of ||mu(x)||^2;
-* L_edge: mean over mesh edges of (1 - n_i . n_j)^2 with the vertex normals.
+* L_edge: mean over mesh edges of (1 - n_i . n_j)^2 with the unit vertex
+  normals.
 
 The vertices are optimised either with plain Adam or, as in the paper, with
 AdamUniform on the Laplacian reparameterisation u = (I + lambda L) V (below);
@@ -71,8 +72,9 @@ def vol_loss(mu, lo, hi, pts: torch.Tensor) -> torch.Tensor:
 
 
 def vertex_normals(V: torch.Tensor, F: torch.Tensor) -> torch.Tensor:
-    """Normalised sum of the unit normals of the faces around each vertex
-    (the tracer's shading normals, Eq. 12-13), differentiable in V."""
+    """One third of the sum of the unit normals of the faces around each
+    vertex (Eq. 13, the vertex normals the tracer blends), differentiable in
+    V."""
     F = F.long()
     e1 = V[F[:, 1]] - V[F[:, 0]]
     e2 = V[F[:, 2]] - V[F[:, 0]]
@@ -81,7 +83,7 @@ def vertex_normals(V: torch.Tensor, F: torch.Tensor) -> torch.Tensor:
     acc = torch.zeros_like(V)
     for k in range(3):
         acc = acc.index_add(0, F[:, k], fn)
-    return acc / acc.norm(dim=-1, keepdim=True).clamp_min(1e-30)
+    return acc / 3.0
 
 
 def mesh_edges(F: torch.Tensor) -> torch.Tensor:
@@ -93,10 +95,12 @@ def mesh_edges(F: torch.Tensor) -> torch.Tensor:
 
 
 def edge_loss(V: torch.Tensor, F: torch.Tensor, edges: torch.Tensor | None = None) -> torch.Tensor:
-    """mean over edges (i, j) of (1 - n_i . n_j)^2."""
+    """mean over edges (i, j) of (1 - n_i . n_j)^2, n the unit vertex normals
+    (the direction of Eq. 13's normal, so the dot product is a cosine)."""
     if edges is None:
         edges = mesh_edges(F)
     n = vertex_normals(V, F)
+    n = n / n.norm(dim=-1, keepdim=True).clamp_min(1e-30)
     return ((1.0 - (n[edges[:, 0]] * n[edges[:, 1]]).sum(-1)) ** 2).mean()
 
 
@@ -162,6 +166,10 @@ class Trainer:
         for o in (self.opt, self.opt_mesh):
             if o is not None:
                 o.step()
+        if self.ls is not None:
+            # the mesh the next render will see, so that self.V never lags u
+            with torch.no_grad():
+                self.V = self.ls.to_v(self.u.detach())
         out = {k: float(v.detach()) for k, v in terms.items()}
         out["total"] = float(total.detach())
         return out
@@ -190,9 +198,11 @@ def laplacian(nv: int, F: torch.Tensor) -> torch.Tensor:
     return torch.sparse_coo_tensor(idx, val, (nv, nv)).coalesce()
 
 
-def solve_spd(matvec, b: torch.Tensor, iters: int = 200, tol: float = 1e-10) -> torch.Tensor:
+def solve_spd(matvec, b: torch.Tensor, iters: int = 1000, tol: float = 1e-10) -> torch.Tensor:
     """Conjugate gradients for A x = b (A symmetric positive definite, given as
-    matvec), column by column of b [n, k]."""
+    matvec), column by column of b [n, k], to a residual of tol * |b| per
+    column.  Raises RuntimeError when `iters` iterations do not get there (a
+    mesh taken from an unconverged solve would be silently wrong)."""
     x = torch.zeros_like(b)
     r = b - matvec(x)
     p = r.clone()
@@ -200,7 +210,7 @@ def solve_spd(matvec, b: torch.Tensor, iters: int = 200, tol: float = 1e-10) -> 
     b2 = (b * b).sum(0).clamp_min(1e-300)
     for _ in range(iters):
         if bool((rs <= tol * tol * b2).all()):
-            break
+            return x
         Ap = matvec(p)
         alpha = rs / (p * Ap).sum(0)
         x = x + alpha * p
@@ -208,7 +218,11 @@ def solve_spd(matvec, b: torch.Tensor, iters: int = 200, tol: float = 1e-10) -> 
         rs_new = (r * r).sum(0)
         p = r + (rs_new / rs) * p
         rs = rs_new
-    return x
+    if bool((rs <= tol * tol * b2).all()):
+        return x
+    worst = float((rs / b2).sqrt().max())
+    raise RuntimeError(f"solve_spd: relative residual {worst:.3e} above {tol:.1e} "
+                       f"after {iters} conjugate-gradient iterations")
 
 
 class LargeSteps:

@@ -26,12 +26,16 @@ def test_ior_recovery_with_adam():
         gt = A.render(V, torch.tensor([1.45], device=dev), sigma, tr).clone()
     ior = torch.tensor([1.38], device=dev, requires_grad=True)
     trainer = T.Trainer(tr, V, ior, sigma=sigma, lr=0.005, l_color=1.0, l_tone=0.1)
-    first = trainer.step(gt)["total"]
+    first = trainer.step(gt)
     for _ in range(60):
-        last = trainer.step(gt)["total"]
-    print("ior", float(ior.detach()), "loss", first, "->", last, flush=True)
+        last = trainer.step(gt)
+    print("ior", float(ior.detach()), "colour loss", first["color"], "->", last["color"],
+          "tone loss", first["tone"], "->", last["tone"], flush=True)
+    # the IoR is recovered ...
     assert abs(float(ior.detach()) - 1.45) < 0.01
-    assert last < 0.1 * first
+    # ... and the colour term, which has no constant part (L_tone carries the
+    # constant -var(c), so the total can go negative), falls by 10x
+    assert last["color"] < 0.1 * first["color"]
 
 
 def test_vertex_steps_with_adam_uniform_reduce_the_loss():
@@ -52,13 +56,13 @@ def test_vertex_steps_with_adam_uniform_reduce_the_loss():
         gt = A.render(V0, ior, sigma, tr).clone()
     V = (V0 * 0.97).clone().requires_grad_(True)
     trainer = T.Trainer(tr, V, ior, sigma=sigma, large_steps=4.0, lr_mesh=4e-3)
-    first = trainer.step(gt)["total"]
+    first = trainer.step(gt)["color"]
+    errs = [float((V0 * 0.97 - V0).norm())]
     for _ in range(40):
-        last = trainer.step(gt)["total"]
-    err0 = float((V0 * 0.97 - V0).norm())
-    err1 = float((trainer.V.detach() - V0).norm())
-    print("loss", first, "->", last, "vertex error", err0, "->", err1, flush=True)
-    # measured at lr 2e-3 over 30 steps: 0.155 -> 0.111, vertex error 0.760 -> 0.741;
-    # at 4e-3 over 40 steps (this test) the loss falls further
-    assert last < 0.8 * first
-    assert err1 < err0
+        last = trainer.step(gt)["color"]
+        # trainer.V is the mesh after the step's update
+        errs.append(float((trainer.V.detach() - V0).norm()))
+    print("colour loss", first, "->", last, "vertex error", errs[0], "->", errs[-1],
+          "min", min(errs), flush=True)
+    assert last < 0.5 * first
+    assert errs[-1] < 0.8 * errs[0]

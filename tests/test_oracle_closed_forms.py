@@ -295,27 +295,79 @@ def test_intersection_point_on_triangle(oracle_lib):
 
 # ---------------------------------------------------------------- vertex normals (Eq. 12-13)
 def test_vertex_normals_planar_sheet(oracle_lib):
+    """Eq. 13 as written: one third of the sum of the unit normals of the
+    incident faces, so on a plane it is the plane normal times the vertex's
+    face count over 3 (counted here from the face list)."""
     V, F = synth.planar_sheet(8, seed=1)
     N = oracle_lib.vertex_normals(V, F)
-    np.testing.assert_allclose(N, np.tile([0.0, 0.0, 1.0], (len(V), 1)), atol=1e-15)
+    k = np.bincount(F.ravel(), minlength=len(V)).astype(np.float64)
+    np.testing.assert_allclose(N, np.outer(k / 3.0, [0.0, 0.0, 1.0]), atol=1e-15)
 
 
 def test_vertex_normals_icosphere_symmetry(oracle_lib):
+    """At the 12 vertices of the original icosahedron (valence 5) the normal
+    is radial by symmetry; the 5 unit face normals around it, each at the
+    angle a of the icosahedron's face-centre to vertex, sum to 5 cos a."""
     V, F = synth.icosphere(3)
     N = oracle_lib.vertex_normals(V, F)
-    np.testing.assert_allclose(N[:12], V[:12] / np.linalg.norm(V[:12], axis=1, keepdims=True), atol=1e-14)
-    assert (np.einsum("ij,ij->i", N, V) > 0.99).all()
+    r = V[:12] / np.linalg.norm(V[:12], axis=1, keepdims=True)
+    n = np.linalg.norm(N[:12], axis=1)
+    np.testing.assert_allclose(N[:12] / n[:, None], r, atol=1e-14)
+    # every vertex normal points outward and is a third of a sum of at most 6
+    # unit vectors that nearly agree
+    Nn = N / np.linalg.norm(N, axis=1, keepdims=True)
+    assert (np.einsum("ij,ij->i", Nn, V) > 0.99).all()
+    k = np.bincount(F.ravel(), minlength=len(V))
+    lens = np.linalg.norm(N, axis=1)
+    assert (lens <= k / 3.0 + 1e-12).all() and (lens > 0.99 * k / 3.0).all()
 
 
 def test_vertex_normals_unit_face_weights(oracle_lib):
     """Eq. 13 sums *unit* face normals: a big face and a small face at a
-    right angle weigh the same."""
+    right angle weigh the same, and the sum is not renormalised."""
     V = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 5, 0], [0, 0, 5]], float)
     F = np.array([[0, 1, 2], [0, 3, 4]], np.int32)
     N = oracle_lib.vertex_normals(V, F)
-    np.testing.assert_allclose(N[0], [1 / math.sqrt(2), 0, 1 / math.sqrt(2)], atol=1e-15)
-    np.testing.assert_allclose(N[1], [0, 0, 1], atol=1e-15)
-    np.testing.assert_allclose(N[3], [1, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(N[0], [1 / 3, 0, 1 / 3], atol=1e-15)
+    np.testing.assert_allclose(N[1], [0, 0, 1 / 3], atol=1e-15)
+    np.testing.assert_allclose(N[3], [1 / 3, 0, 0], atol=1e-15)
+
+
+def test_shading_normal_blends_unnormalised_vertex_normals(oracle_lib):
+    """Eq. 12 blends the vertex normals of Eq. 13 with the barycentric weights
+    and only then normalises.  A triangle whose corners have different face
+    counts tells this apart from blending unit vertex normals: the mirror
+    direction of a ray reflected at a known point must use the first."""
+    # a closed square pyramid (4 side faces + 2 base faces): apex valence 4,
+    # base corners valence 3 or 4
+    V = np.array([[-1, 0, -1], [1, 0, -1], [1, 0, 1], [-1, 0, 1], [0, 1.2, 0]], float)
+    F = np.array([[0, 4, 1], [1, 4, 2], [2, 4, 3], [3, 4, 0], [0, 1, 2], [0, 2, 3]], np.int32)
+    N = oracle_lib.vertex_normals(V, F)
+    k = np.bincount(F.ravel(), minlength=len(V))
+    assert len(set(k[[1, 2, 4]])) > 1
+    # ray from outside onto face 1 = (1, 4, 2) at barycentrics (b0, b1, b2)
+    b = np.array([0.5, 0.2, 0.3])
+    x = b @ V[F[1]]
+    ng = np.cross(V[F[1][1]] - V[F[1][0]], V[F[1][2]] - V[F[1][0]])
+    ng /= np.linalg.norm(ng)
+    d = -ng + np.array([0.1, -0.05, 0.07])
+    d /= np.linalg.norm(d)
+    o = x - 2.0 * d
+    env = oracle_lib.Env(tex=synth.env_constant(16, 8))
+    sc = oracle_lib.Scene(V, F, 1.5, 0.0, env, 1)
+    tree = sc.tree(o, d)
+    assert int(tree[0]["tri"]) == 1
+    refl = np.array([tree[1]["d%d" % i] for i in range(3)])
+
+    def mirror(n):
+        n = n / np.linalg.norm(n)
+        r = d - 2.0 * (d @ n) * n
+        return r / np.linalg.norm(r)
+    blend_eq12 = b @ N[F[1]]
+    Nu = N / np.linalg.norm(N, axis=1, keepdims=True)
+    blend_unit = b @ Nu[F[1]]
+    np.testing.assert_allclose(refl, mirror(blend_eq12), atol=1e-12)
+    assert np.abs(mirror(blend_unit) - mirror(blend_eq12)).max() > 1e-3
 
 
 # ---------------------------------------------------------------- environment
