@@ -35,7 +35,8 @@
  *    the ABI.  Data problems found on the device (a ray that leaves the object
  *    from inside, a shading normal on the wrong side, a full ray queue) are
  *    reported per pixel in the optional `flags` output and in `stats`.
- *  - The library keeps no global state besides that error string.
+ *  - The library keeps no global state besides that error string and the
+ *    per-device build array of dt_build_bvh_noalloc.
  */
 #ifndef DIFFTRANS_H
 #define DIFFTRANS_H
@@ -96,6 +97,23 @@ dt_status dt_bvh_bytes(int32_t nv, int32_t nf, size_t* bvh_bytes, size_t* ws_byt
  * through DT_FLAG results, not here: the caller guarantees it). */
 dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, int32_t nf,
                        void* bvh, size_t bvh_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* dt_build_bvh for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops that must not call hipMalloc): the build
+ * workspace is an array the library holds on each device (file-scope device
+ * memory, DT_BVH_SCRATCH_BYTES per GPU, kept until the process ends) instead
+ * of a caller-owned buffer.  Same outputs and conventions as dt_build_bvh; the
+ * caller still owns V, F and the bvh blob.  Meshes whose build workspace
+ * (dt_bvh_bytes' ws_bytes, about 65 bytes per face) exceeds
+ * DT_BVH_SCRATCH_BYTES (about 500k faces) return DT_ERR_CAPACITY with nothing
+ * queued.  No device memory is allocated, ever.  All calls on one GPU share
+ * the one array, which keeps the last call's contents (the build clears what
+ * it needs itself): two calls whose work overlaps on the same GPU (different
+ * streams, or different host threads) race and corrupt each other's BVH, so
+ * the caller must order them, e.g. on one stream. */
+#define DT_BVH_SCRATCH_BYTES ((size_t)32 << 20)
+dt_status dt_build_bvh_noalloc(const float* V, int32_t nv, const int32_t* F, int32_t nf,
+                               void* bvh, size_t bvh_bytes, void* stream);
 
 /* Copy the vertex normals held in a blob built for (nv, nf) to N [nv][3]. */
 dt_status dt_bvh_vertex_normals(const void* bvh, int32_t nv, int32_t nf, float* N, void* stream);

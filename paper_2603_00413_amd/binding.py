@@ -75,7 +75,7 @@ class _Rays(C.Structure):
 
 
 _lib = None
-EXPORTS = ["dt_bvh_bytes", "dt_build_bvh", "dt_bvh_vertex_normals", "dt_env_query",
+EXPORTS = ["dt_bvh_bytes", "dt_build_bvh", "dt_build_bvh_noalloc", "dt_bvh_vertex_normals", "dt_env_query",
            "dt_env_query_backward", "dt_trace_bytes", "dt_trace_forward", "dt_trace_backward",
            "dt_intersect", "dt_status_string", "dt_last_error"]
 
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
     vp, sz, i32, i64 = C.c_void_p, C.POINTER(C.c_size_t), C.c_int32, C.c_int64
     L.dt_bvh_bytes.argtypes = [i32, i32, sz, sz]
     L.dt_build_bvh.argtypes = [vp, i32, vp, i32, vp, C.c_size_t, vp, C.c_size_t, vp]
+    L.dt_build_bvh_noalloc.argtypes = [vp, i32, vp, i32, vp, C.c_size_t, vp]
     L.dt_bvh_vertex_normals.argtypes = [vp, i32, i32, vp, vp]
     L.dt_env_query.argtypes = [C.POINTER(_Env), vp, i64, vp, vp]
     L.dt_env_query_backward.argtypes = [C.POINTER(_Env), vp, i64, vp, vp, vp]
@@ -173,6 +174,15 @@ def dt_build_bvh(V, F, blob, ws):
     _dev_check(V, F, blob, ws)
     _check(load().dt_build_bvh(_ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(blob), blob.numel(),
                                _ptr(ws), ws.numel(), _stream(V.device)))
+
+
+def dt_build_bvh_noalloc(V, F, blob):
+    """dt_build_bvh with the library's own per-device build array as its
+    workspace: nothing is allocated (meshes up to DT_BVH_SCRATCH_BYTES of
+    build workspace, about 500k faces)."""
+    _dev_check(V, F, blob)
+    _check(load().dt_build_bvh_noalloc(_ptr(V), V.shape[0], _ptr(F), F.shape[0], _ptr(blob),
+                                       blob.numel(), _stream(V.device)))
 
 
 # ------------------------------------------------------------------ environment

@@ -5,6 +5,8 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
+
 #include "dt_internal.h"
 
 namespace {
@@ -879,6 +881,58 @@ extern "C" dt_status dt_build_bvh(const float* V, int32_t nv, const int32_t* F, 
     DT_CHECK_LAUNCH();
   }
   return DT_OK;
+}
+
+// ------------------------------------------------------------------ build without allocation
+// Build workspace held by the library itself, for callers that cannot
+// allocate device memory.  Every GPU the library runs on holds its own copy
+// from module load until the process ends.  In host code `scratch` only names
+// the array: its device address is looked up once per device and kept in
+// g_scratch_ptr, which is what the kernels are given.
+static __device__ __align__(256) unsigned char scratch[DT_BVH_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+dt_status scratch_address(void** out) {
+  int dev = -1;
+  DT_CHECK_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    dt_set_error("dt_build_bvh_noalloc: device ordinal %d out of range", dev);
+    return DT_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    // with device `dev` current: this device's copy of the array
+    DT_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DT_OK;
+}
+}  // namespace
+
+extern "C" dt_status dt_build_bvh_noalloc(const float* V, int32_t nv, const int32_t* F, int32_t nf,
+                                          void* bvh, size_t bvh_bytes, void* stream) {
+  DT_REQUIRE(V && F && bvh, "dt_build_bvh_noalloc: null pointer argument");
+  DT_REQUIRE(nv >= 3 && nf >= 1, "dt_build_bvh_noalloc: need nv >= 3 and nf >= 1 (got %d, %d)", nv,
+             nf);
+  DT_REQUIRE(nf <= DT_MAX_FACES && nv < (1 << 30),
+             "dt_build_bvh_noalloc: mesh too large (at most 2^26 triangles)");
+  Carver c(nullptr, 0);
+  const size_t need = carve_build(c, nv, nf, nullptr);
+  if (need > (size_t)DT_BVH_SCRATCH_BYTES) {
+    dt_set_error("dt_build_bvh_noalloc: a mesh of %d vertices and %d faces needs %zu bytes of "
+                 "build workspace, more than the library's %zu (use dt_build_bvh with a "
+                 "caller-owned workspace)", nv, nf, need, (size_t)DT_BVH_SCRATCH_BYTES);
+    return DT_ERR_CAPACITY;
+  }
+  void* ws = nullptr;
+  if (dt_status st = scratch_address(&ws)) return st;
+  return dt_build_bvh(V, nv, F, nf, bvh, bvh_bytes, ws, (size_t)DT_BVH_SCRATCH_BYTES, stream);
 }
 
 extern "C" dt_status dt_bvh_vertex_normals(const void* bvh, int32_t nv, int32_t nf, float* N,

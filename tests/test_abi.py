@@ -80,3 +80,18 @@ def test_unsupported_shapes_are_rejected_on_the_host():
     assert L.dt_bvh_bytes(3, (1 << 26) + 1, C.byref(a), C.byref(b)) == 1
     assert "2^26" in L.dt_last_error().decode()
     assert L.dt_bvh_bytes(3, 1 << 26, C.byref(a), C.byref(b)) == 0
+
+
+def test_noalloc_build_rejects_meshes_beyond_its_array():
+    """The no-allocation build refuses, on the host, a mesh whose build
+    workspace exceeds the library's per-device array (about 500k faces)."""
+    L = B.load()
+    a, b = C.c_size_t(), C.c_size_t()
+    fake = C.c_void_p(16)            # never dereferenced: rejected before any device call
+    assert L.dt_build_bvh_noalloc(fake, 1 << 20, fake, 2 << 20, fake, 1 << 30, None) == 3
+    msg = L.dt_last_error().decode()
+    assert "dt_build_bvh_noalloc" in msg and "workspace" in msg
+    assert L.dt_build_bvh_noalloc(None, 642, fake, 1280, fake, 1 << 20, None) == 1
+    # the largest serving scene (500k faces) fits
+    L.dt_bvh_bytes(250_000, 500_000, C.byref(a), C.byref(b))
+    assert b.value <= 32 << 20
