@@ -78,8 +78,13 @@ def lib():
         L.or_env_kink_margin.argtypes = [C.POINTER(_Env), dp, i64, dp]
         L.or_trace.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, ip,
                                C.POINTER(C.c_uint64), ip, C.POINTER(C.c_uint64)]
-        L.or_trace_grad.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, dp, dp, dp, dp, dp]
+        L.or_trace_grad.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, dp, dp, dp, dp, dp, dp,
+                                    C.c_int]
         L.or_trace_tree.argtypes = [C.POINTER(_Scene), dp, dp, dp, C.c_int]
+        L.or_trace_errbound.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp]
+        L.or_mask.argtypes = [C.POINTER(_Scene), dp, C.c_int, C.c_int, dp]
+        L.or_mask_grad.argtypes = [C.POINTER(_Scene), dp, C.c_int, C.c_int, dp, C.c_double, dp,
+                                   C.POINTER(C.c_int64)]
         L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -100,6 +105,7 @@ class Env:
     def __init__(self, tex=None, mlp=None):
         self._keep = []
         self.tex = None
+        self.mlp_shapes = None
         s = _Env()
         if tex is not None:
             t = _d(tex)
@@ -112,6 +118,8 @@ class Env:
             w = _d(np.concatenate([np.asarray(x, np.float64).ravel() for x in Ws]))
             b = _d(np.concatenate([np.asarray(x, np.float64).ravel() for x in Bs]))
             self._keep += [w, b]
+            self.mlp_shapes = [(np.asarray(x).shape, np.asarray(y).shape) for x, y in zip(Ws, Bs)]
+            self.n_weights, self.n_params = w.size, w.size + b.size
             s.kind = 1
             s.n_freq = n_freq
             s.n_layers = len(Ws) - 1
@@ -119,6 +127,20 @@ class Env:
             s.in_pad = Ws[0].shape[1]
             s.weights, s.biases = _p(w), _p(b)
         self.s = s
+
+    def split_params(self, flat):
+        """Flat MLP parameter vector (every weight, then every bias) ->
+        (list of weight matrices [out, in], list of bias vectors)."""
+        Ws, Bs, k = [], [], 0
+        for ws, _ in self.mlp_shapes:
+            n = int(np.prod(ws))
+            Ws.append(flat[k:k + n].reshape(ws))
+            k += n
+        for _, bs in self.mlp_shapes:
+            n = int(np.prod(bs))
+            Bs.append(flat[k:k + n].reshape(bs))
+            k += n
+        return Ws, Bs
 
     def eval(self, dirs):
         d = _d(dirs).reshape(-1, 3)
@@ -220,9 +242,14 @@ class Scene:
         assert rc == 0, "or_trace rejected its arguments"
         return {"rgb": rgb, "wtrunc": wt, "flags": fl, "hash": hs, "nseg": ns, "sig": sg}
 
-    def trace_grad(self, o, d, grad_rgb, want_tex: bool = False):
+    def trace_grad(self, o, d, grad_rgb, want_tex: bool = False, want_mlp: bool = False,
+                   absolute: bool = False):
         """Returns dict(rgb, dV [nv,3], d_eta, d_sigma [3], d_mu [nz,ny,nx,3] or None,
-        d_tex [H,W,3] (equirect environment, with want_tex) or None)."""
+        d_tex [H,W,3] (equirect environment, with want_tex) or None, d_mlp
+        (MLP environment, with want_mlp: (weight gradients [out, in] per
+        layer, bias gradients per layer)) or None).  absolute: every gradient
+        is instead the sum over camera rays of the magnitude of each ray's
+        contribution."""
         o, d = _d(o).reshape(-1, 3), _d(d).reshape(-1, 3)
         g = _d(grad_rgb).reshape(-1, 3)
         n = len(o)
@@ -232,13 +259,49 @@ class Scene:
         ds = np.zeros(3)
         dm = np.zeros_like(self.absorb.mu) if self.absorb is not None else None
         dt = np.zeros_like(self.env.tex) if want_tex and self.env.tex is not None else None
+        dw = np.zeros(self.env.n_params) if want_mlp and self.env.mlp_shapes else None
         s = self._s()
         rc = lib().or_trace_grad(C.byref(s), _p(o), _p(d), n, _p(g), _p(rgb), _p(dV),
                                  _p(de), _p(ds), _p(dm) if dm is not None else None,
-                                 _p(dt) if dt is not None else None)
+                                 _p(dt) if dt is not None else None,
+                                 _p(dw) if dw is not None else None, int(bool(absolute)))
         assert rc == 0, "or_trace_grad rejected its arguments"
         return {"rgb": rgb, "dV": dV, "d_eta": float(de[0]), "d_sigma": ds, "d_mu": dm,
-                "d_tex": dt}
+                "d_tex": dt, "d_mlp": self.env.split_params(dw) if dw is not None else None}
+
+    def errbound(self, o, d):
+        """First-order bound on the rounding error of an FP32 evaluation of
+        each pixel's radiance, per channel [n, 3] (with the FP64 rgb [n, 3])."""
+        o, d = _d(o).reshape(-1, 3), _d(d).reshape(-1, 3)
+        n = len(o)
+        rgb, b = np.empty((n, 3)), np.empty((n, 3))
+        s = self._s()
+        assert lib().or_trace_errbound(C.byref(s), _p(o), _p(d), n, _p(rgb), _p(b)) == 0
+        return rgb, b
+
+    def mask(self, cam):
+        """Centre-sample coverage [H*W] of one camera (1 = the pixel centre's
+        ray hits the mesh)."""
+        a = _d(cam.as_array())
+        out = np.empty(cam.width * cam.height)
+        s = self._s()
+        assert lib().or_mask(C.byref(s), _p(a), cam.width, cam.height, _p(out)) == 0
+        return out
+
+    def mask_grad(self, cam, grad_mask, rho: float = 2.0):
+        """Gradient of sum_p grad_mask[p] M_p with respect to the vertices
+        [nv, 3] through the motion of the outline (quadrature at rho points
+        per pixel of projected edge length); also (points in the image,
+        points on the outline)."""
+        a = _d(cam.as_array())
+        g = _d(grad_mask).reshape(-1)
+        assert g.size == cam.width * cam.height
+        dV = np.empty_like(self.V)
+        cnt = np.zeros(2, np.int64)
+        s = self._s()
+        assert lib().or_mask_grad(C.byref(s), _p(a), cam.width, cam.height, _p(g), float(rho),
+                                  _p(dV), _p(cnt, C.c_int64)) == 0
+        return dV, (int(cnt[0]), int(cnt[1]))
 
     def tree(self, o, d, max_rec: int = 4096):
         """Depth-first node records of one camera ray (list of dicts)."""

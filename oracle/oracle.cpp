@@ -58,15 +58,25 @@ namespace {
 struct TapeNode {
   int a, b;
   double da, db;
+  double v;      // the node's value (used by the rounding-error bound)
+  float u;       // relative rounding error its FP32 evaluation may carry
 };
 
 struct Tape {
   std::vector<TapeNode> nodes;
-  int push(int a, double da, int b, double db) {
-    nodes.push_back({a, b, da, db});
+  int push(int a, double da, int b, double db, double v, float u) {
+    nodes.push_back({a, b, da, db, v, u});
     return (int)nodes.size() - 1;
   }
 };
+
+// Relative error charged to one FP32 operation by the rounding-error bound:
+// the unit roundoff 2^-24 for correctly rounded arithmetic and square roots,
+// twice that for the library functions (exp, atan2, acos, sin, cos, within
+// two units in the last place) and for results the other side computes in
+// several FP32 steps from exact inputs (a camera ray direction).
+constexpr float kU32 = 5.9604644775390625e-08f;
+constexpr float kUlp32x2 = 1.1920928955078125e-07f;
 
 thread_local Tape* g_tape = nullptr;
 
@@ -77,20 +87,22 @@ struct Var {
   Var(double x) : v(x), i(-1) {}
 };
 
-inline Var mk(double v, int a, double da, int b = -1, double db = 0.0) {
+inline Var mk(double v, int a, double da, int b = -1, double db = 0.0, float u = kU32) {
   Var r;
   r.v = v;
   if (a < 0 && b < 0) {
     r.i = -1;
   } else {
-    r.i = g_tape->push(a, da, b, db);
+    r.i = g_tape->push(a, da, b, db, v, u);
   }
   return r;
 }
-inline Var leaf(double v) {
+// An input: exact (u = 0) unless it is itself the result of FP32 arithmetic
+// on the other side (a camera ray direction: u = kUlp32x2).
+inline Var leaf(double v, float u = 0.0f) {
   Var r;
   r.v = v;
-  r.i = g_tape->push(-1, 0.0, -1, 0.0);
+  r.i = g_tape->push(-1, 0.0, -1, 0.0, v, u);
   return r;
 }
 inline Var operator+(Var x, Var y) { return mk(x.v + y.v, x.i, 1.0, y.i, 1.0); }
@@ -106,18 +118,18 @@ inline Var Sqrt(Var x) {
 }
 inline Var Exp(Var x) {
   double e = std::exp(x.v);
-  return mk(e, x.i, e);
+  return mk(e, x.i, e, -1, 0.0, kUlp32x2);
 }
 inline Var Acos(Var x) {
   double s = std::sqrt(std::max(1.0 - x.v * x.v, 0.0));
-  return mk(std::acos(x.v), x.i, -1.0 / s);
+  return mk(std::acos(x.v), x.i, -1.0 / s, -1, 0.0, kUlp32x2);
 }
 inline Var Atan2(Var y, Var x) {
   double r2 = x.v * x.v + y.v * y.v;
-  return mk(std::atan2(y.v, x.v), y.i, x.v / r2, x.i, -y.v / r2);
+  return mk(std::atan2(y.v, x.v), y.i, x.v / r2, x.i, -y.v / r2, kUlp32x2);
 }
-inline Var Sin(Var x) { return mk(std::sin(x.v), x.i, std::cos(x.v)); }
-inline Var Cos(Var x) { return mk(std::cos(x.v), x.i, -std::sin(x.v)); }
+inline Var Sin(Var x) { return mk(std::sin(x.v), x.i, std::cos(x.v), -1, 0.0, kUlp32x2); }
+inline Var Cos(Var x) { return mk(std::cos(x.v), x.i, -std::sin(x.v), -1, 0.0, kUlp32x2); }
 inline Var Relu(Var x) { return x.v > 0.0 ? x : Var(0.0); }
 inline double val(Var x) { return x.v; }
 
@@ -689,6 +701,48 @@ double mlp_kink_margin(const or_env& e, V3<double> d) {
   return margin;
 }
 
+// Total number of MLP parameters (weights, then biases, in the layout of or_env).
+inline size_t mlp_param_count(const or_env& e) {
+  size_t nw = (size_t)e.width * e.in_pad, nb = (size_t)e.width;
+  for (int l = 1; l < e.n_layers; ++l) {
+    nw += (size_t)e.width * e.width;
+    nb += (size_t)e.width;
+  }
+  nw += 3 * (size_t)e.width;
+  nb += 3;
+  return nw + nb;
+}
+inline size_t mlp_weight_count(const or_env& e) {
+  size_t nw = (size_t)e.width * e.in_pad;
+  for (int l = 1; l < e.n_layers; ++l) nw += (size_t)e.width * e.width;
+  return nw + 3 * (size_t)e.width;
+}
+
+// For the gradient pass: when set, the network's weights and biases are tape
+// leaves (created on first use for the current camera ray, weights first,
+// then biases), so every lookup is differentiable in them too.
+thread_local std::vector<Var>* g_mlpleaf = nullptr;
+template <class S>
+S mlp_param(const or_env& e, size_t k);
+template <>
+inline double mlp_param<double>(const or_env& e, size_t k) {
+  size_t nw = mlp_weight_count(e);
+  return k < nw ? e.weights[k] : e.biases[k - nw];
+}
+template <>
+inline Var mlp_param<Var>(const or_env& e, size_t k) {
+  size_t nw = mlp_weight_count(e);
+  double v = k < nw ? e.weights[k] : e.biases[k - nw];
+  if (!g_mlpleaf) return Var(v);
+  if (g_mlpleaf->empty()) {
+    size_t np = mlp_param_count(e);
+    g_mlpleaf->reserve(np);
+    for (size_t j = 0; j < np; ++j)
+      g_mlpleaf->push_back(leaf(j < nw ? e.weights[j] : e.biases[j - nw]));
+  }
+  return (*g_mlpleaf)[k];
+}
+
 template <class S>
 V3<S> env_mlp(const or_env& e, V3<S> dir, EnvOut& eo) {
   const double PI = 3.14159265358979323846;
@@ -704,22 +758,23 @@ V3<S> env_mlp(const or_env& e, V3<S> dir, EnvOut& eo) {
     for (int c = 0; c < 3; ++c) h[k++] = Sin(S(w) * dc[c]);
     for (int c = 0; c < 3; ++c) h[k++] = Cos(S(w) * dc[c]);
   }
-  const double* W = e.weights;
-  const double* B = e.biases;
+  // parameter k of the flat list: weights of all layers, then their biases
+  const size_t nw = mlp_weight_count(e);
+  size_t wo = 0, bo = nw;
   int in = e.in_pad;
   for (int l = 0; l <= e.n_layers; ++l) {
     int out = l < e.n_layers ? e.width : 3;
     std::vector<S> z((size_t)out);
     for (int j = 0; j < out; ++j) {
-      S acc = S(B[j]);
-      for (int i = 0; i < in; ++i) acc = acc + S(W[(size_t)j * in + i]) * h[i];
+      S acc = mlp_param<S>(e, bo + j);
+      for (int i = 0; i < in; ++i) acc = acc + mlp_param<S>(e, wo + (size_t)j * in + i) * h[i];
       if (l < e.n_layers)
         z[j] = Relu(acc);
       else
         z[j] = acc;
     }
-    W += (size_t)out * in;
-    B += out;
+    wo += (size_t)out * in;
+    bo += out;
     h.swap(z);
     in = out;
   }
@@ -1129,11 +1184,15 @@ int or_trace(const or_scene* sc, const double* o, const double* d, int64_t n, do
 
 // Forward + reverse-mode gradient.  The scalar loss is sum_i grad_rgb[i] . C_i.
 // dV [nv*3], d_eta [1], d_sigma [3] are overwritten, and with an absorption
-// grid d_mu [nx*ny*nz*3] too (sigma then has no effect and d_sigma is 0), and
-// for an equirect environment d_tex [H*W*3].  rgb, d_mu and d_tex may be NULL.
+// grid d_mu [nx*ny*nz*3] too (sigma then has no effect and d_sigma is 0), for
+// an equirect environment d_tex [H*W*3], and for an MLP environment d_mlp
+// (every weight, then every bias, in the order of or_env).  rgb, d_mu, d_tex
+// and d_mlp may be NULL.  absolute = 1: every output is instead the sum over
+// camera rays of the magnitude of each ray's contribution (the scale against
+// which a sum that cancels is compared).
 int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t n,
                   const double* grad_rgb, double* rgb, double* dV, double* d_eta,
-                  double* d_sigma, double* d_mu, double* d_tex) {
+                  double* d_sigma, double* d_mu, double* d_tex, double* d_mlp, int absolute) {
   if (!valid_scene(sc)) return 1;
   Shared sh;
   make_shared(sc, sh, true);
@@ -1147,6 +1206,8 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
   std::vector<std::vector<double>> accM(nth);
   const size_t ntex = (d_tex && sc->env->kind == 0) ? 3 * (size_t)sc->env->W * sc->env->H : 0;
   std::vector<std::vector<double>> accT(nth);
+  const size_t nmlp = (d_mlp && sc->env->kind == 1) ? mlp_param_count(*sc->env) : 0;
+  std::vector<std::vector<double>> accW(nth);
 #pragma omp parallel
   {
     int tid = 0;
@@ -1156,15 +1217,19 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
     accV[tid].assign(3 * (size_t)sc->nv, 0.0);
     accM[tid].assign(nmu, 0.0);
     accT[tid].assign(ntex, 0.0);
+    accW[tid].assign(nmlp, 0.0);
     Tape tape;
     g_tape = &tape;
     std::unordered_map<int, V3<Var>> texleaf;
     g_texleaf = ntex ? &texleaf : nullptr;
+    std::vector<Var> mlpleaf;
+    g_mlpleaf = nmlp ? &mlpleaf : nullptr;
 #pragma omp for schedule(dynamic, 16)
     for (int64_t i = 0; i < n; ++i) {
       const double* g = grad_rgb + 3 * i;
       tape.nodes.clear();
       texleaf.clear();
+      mlpleaf.clear();
       Ctx<Var> cx;
       cx.sh = &sh;
       cx.eta = leaf(sc->eta);
@@ -1191,35 +1256,40 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
         if (tn.a >= 0) adj[tn.a] += tn.da * a;
         if (tn.b >= 0) adj[tn.b] += tn.db * a;
       }
-      accE[tid] += adj[cx.eta.i];
-      for (int k = 0; k < 3; ++k) accS[3 * tid + k] += adj[cx.sigma[k].i];
+      // absolute = 1: each camera ray's contribution enters by its magnitude
+      auto A = [&](int i) { return absolute ? std::fabs(adj[i]) : adj[i]; };
+      accE[tid] += A(cx.eta.i);
+      for (int k = 0; k < 3; ++k) accS[3 * tid + k] += A(cx.sigma[k].i);
       for (auto& kv : cx.P) {
         double* dst = accV[tid].data() + 3 * (size_t)kv.first;
-        dst[0] += adj[kv.second.x.i];
-        dst[1] += adj[kv.second.y.i];
-        dst[2] += adj[kv.second.z.i];
+        dst[0] += A(kv.second.x.i);
+        dst[1] += A(kv.second.y.i);
+        dst[2] += A(kv.second.z.i);
       }
       for (auto& kv : cx.G) {
         double* dst = accM[tid].data() + 3 * (size_t)kv.first;
-        dst[0] += adj[kv.second.x.i];
-        dst[1] += adj[kv.second.y.i];
-        dst[2] += adj[kv.second.z.i];
+        dst[0] += A(kv.second.x.i);
+        dst[1] += A(kv.second.y.i);
+        dst[2] += A(kv.second.z.i);
       }
       for (auto& kv : texleaf) {
         double* dst = accT[tid].data() + 3 * (size_t)kv.first;
-        dst[0] += adj[kv.second.x.i];
-        dst[1] += adj[kv.second.y.i];
-        dst[2] += adj[kv.second.z.i];
+        dst[0] += A(kv.second.x.i);
+        dst[1] += A(kv.second.y.i);
+        dst[2] += A(kv.second.z.i);
       }
+      for (size_t k = 0; k < mlpleaf.size(); ++k) accW[tid][k] += A(mlpleaf[k].i);
     }
     g_tape = nullptr;
     g_texleaf = nullptr;
+    g_mlpleaf = nullptr;
   }
   std::memset(dV, 0, sizeof(double) * 3 * (size_t)sc->nv);
   if (ntex) std::memset(d_tex, 0, sizeof(double) * ntex);
   *d_eta = 0.0;
   d_sigma[0] = d_sigma[1] = d_sigma[2] = 0.0;
   if (d_mu && nmu) std::memset(d_mu, 0, sizeof(double) * nmu);
+  if (nmlp) std::memset(d_mlp, 0, sizeof(double) * nmlp);
   for (int t = 0; t < nth; ++t) {
     if (accV[t].empty()) continue;
     for (size_t j = 0; j < 3 * (size_t)sc->nv; ++j) dV[j] += accV[t][j];
@@ -1228,6 +1298,283 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
     if (d_mu)
       for (size_t j = 0; j < nmu; ++j) d_mu[j] += accM[t][j];
     for (size_t j = 0; j < ntex; ++j) d_tex[j] += accT[t][j];
+    for (size_t j = 0; j < nmlp; ++j) d_mlp[j] += accW[t][j];
+  }
+  return 0;
+}
+
+// First-order bound on the rounding error of an FP32 evaluation of each
+// pixel's radiance (running error analysis by automatic differentiation:
+// an operation z computed as z (1 + e), |e| <= u, moves the pixel by
+// dC/dz z e, so |C_fp32 - C| <= sum over the computation's operations of
+// |dC/dz| |z| u, to first order in u; Iri, "History of automatic
+// differentiation and rounding error estimation", 1991, and Higham,
+// "Accuracy and Stability of Numerical Algorithms", 2002, Sec. 3.3).  The
+// sum runs over every operation of the recursion on the pixel's discrete
+// path, each charged the unit roundoff 2^-24 (2^-23 for library functions);
+// the mesh, IoR, absorption, environment and camera origin are exact FP32
+// inputs shared by both sides, the camera direction is charged as an FP32
+// result (2^-23).  bound [n*3] per channel; rgb
+// [n*3] may be NULL.
+int or_trace_errbound(const or_scene* sc, const double* o, const double* d, int64_t n,
+                      double* rgb, double* bound) {
+  if (!valid_scene(sc)) return 1;
+  Shared sh;
+  make_shared(sc, sh, true);
+#pragma omp parallel
+  {
+    Tape tape;
+    g_tape = &tape;
+    // texels and network parameters are exact inputs: constants here
+    g_texleaf = nullptr;
+    g_mlpleaf = nullptr;
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+      tape.nodes.clear();
+      Ctx<Var> cx;
+      cx.sh = &sh;
+      cx.eta = leaf(sc->eta);
+      for (int k = 0; k < 3; ++k) cx.sigma[k] = leaf(sc->sigma[k]);
+      PathInfo pi;
+      double W[3] = {1, 1, 1};
+      V3<Var> oo{leaf(o[3 * i]), leaf(o[3 * i + 1]), leaf(o[3 * i + 2])};
+      V3<Var> dd{leaf(d[3 * i], kUlp32x2), leaf(d[3 * i + 1], kUlp32x2), leaf(d[3 * i + 2], kUlp32x2)};
+      V3<Var> L = trace<Var>(cx, oo, dd, -1, 0, W, false, pi, nullptr);
+      const Var Lc[3] = {L.x, L.y, L.z};
+      std::vector<double> adj(tape.nodes.size());
+      for (int c = 0; c < 3; ++c) {
+        if (rgb) rgb[3 * i + c] = Lc[c].v;
+        double b = 0.0;
+        if (Lc[c].i >= 0) {
+          std::fill(adj.begin(), adj.end(), 0.0);
+          adj[Lc[c].i] = 1.0;
+          for (int k = (int)tape.nodes.size() - 1; k >= 0; --k) {
+            double a = adj[k];
+            if (a == 0.0) continue;
+            const TapeNode& tn = tape.nodes[k];
+            b += std::fabs(a * tn.v) * (double)tn.u;
+            if (tn.a >= 0) adj[tn.a] += tn.da * a;
+            if (tn.b >= 0) adj[tn.b] += tn.db * a;
+          }
+        }
+        bound[3 * i + c] = b;
+      }
+    }
+    g_tape = nullptr;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Silhouette (mask) term: the coverage of each pixel by the object and the
+// gradient of a loss on it with respect to the vertices, through the motion
+// of the object's outline (the visibility gradient the interior derivatives
+// above do not carry; the paper's mask loss, Sec. 3.1 "Mask-based Geometry
+// Initialization" and the appendix on the ray tracer's mesh regularization).
+//
+// Readings: the mask of pixel p is the fraction of its unit square in
+// continuous image coordinates (pixel (x, y) = [x, x+1) x [y, y+1)) covered by
+// the object's projection; its value is taken at the pixel centre (1 when the
+// centre's camera ray hits the mesh), its derivative is the boundary integral
+// dM_p/dtheta = int over the outline inside p of (dx/dtheta . n_out) dl, with
+// n_out the image-plane normal pointing away from the covered side.  The
+// outline is made of silhouette edges (one adjacent face facing the eye, the
+// other not; an edge with one face counts too) at points whose camera ray
+// meets no other triangle anywhere along it.  The integral is taken by a
+// fixed quadrature: an edge whose projection is l pixels long gets
+// n = max(1, ceil(rho l)) points at the midpoints t_k = (k + 1/2)/n of the
+// segment's 3D parameter, weight |dx/dt| / n, each assigned to the pixel
+// containing its projection; a point moves with its two vertices with
+// weights 1 - t_k and t_k.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CamBasis {
+  V3<double> eye, f, r, u;
+  double th, aspect;
+  int W, H;
+};
+
+CamBasis cam_basis(const double* cam, int W, int H) {
+  const double PI = 3.14159265358979323846;
+  CamBasis c;
+  c.eye = {cam[0], cam[1], cam[2]};
+  V3<double> tgt{cam[3], cam[4], cam[5]}, up{cam[6], cam[7], cam[8]};
+  c.f = normalize(sub(tgt, c.eye));
+  c.r = normalize(cross(c.f, up));
+  c.u = cross(c.r, c.f);
+  c.th = std::tan(0.5 * cam[9] * PI / 180.0);
+  c.aspect = (double)W / (double)H;
+  c.W = W;
+  c.H = H;
+  return c;
+}
+
+// continuous image position of a 3D point in front of the camera (z > 0),
+// and its Jacobian d(xi, yi)/dX (rows jx, jy)
+bool project(const CamBasis& c, V3<double> X, double& xi, double& yi, V3<double>* jx, V3<double>* jy) {
+  V3<double> w = sub(X, c.eye);
+  double z = dot(w, c.f);
+  if (!(z > 1e-9)) return false;
+  double a = dot(w, c.r), b = dot(w, c.u);
+  double sx = 0.5 * c.W / (c.th * c.aspect), sy = 0.5 * c.H / c.th;
+  xi = sx * (a / z) + 0.5 * c.W;
+  yi = 0.5 * c.H - sy * (b / z);
+  if (jx) *jx = scl(sub(scl(c.r, 1.0 / z), scl(c.f, a / (z * z))), sx);
+  if (jy) *jy = scl(sub(scl(c.u, 1.0 / z), scl(c.f, b / (z * z))), -sy);
+  return true;
+}
+
+// any triangle other than f1, f2 met by the line eye + s (X - eye), s > 0
+bool line_blocked(const or_scene& sc, const BVH& b, V3<double> eye, V3<double> X, int f1, int f2) {
+  double o[3] = {eye.x, eye.y, eye.z};
+  V3<double> dv = sub(X, eye);
+  double d[3] = {dv.x, dv.y, dv.z};
+  if (b.nodes.empty()) return false;
+  int stack[128];
+  int sp = 0;
+  stack[sp++] = 0;
+  while (sp) {
+    const BNode& n = b.nodes[stack[--sp]];
+    if (box_enter(n, o, d, INFINITY) == INFINITY) continue;
+    if (n.left < 0) {
+      for (int i = n.first; i < n.first + n.count; ++i) {
+        int f = b.order[i];
+        if (f == f1 || f == f2) continue;
+        double t, b1, b2;
+        if (mt_hit(sc, f, o, d, t, b1, b2)) return true;
+      }
+    } else {
+      stack[sp++] = n.right;
+      stack[sp++] = n.left;
+    }
+  }
+  return false;
+}
+
+struct MeshEdge {
+  int a, b, f1, f2;  // f2 = -1 for an edge with one face
+};
+
+std::vector<MeshEdge> mesh_edges(const or_scene& sc) {
+  std::unordered_map<uint64_t, int> seen;
+  std::vector<MeshEdge> E;
+  for (int f = 0; f < sc.nf; ++f)
+    for (int k = 0; k < 3; ++k) {
+      int a = sc.F[3 * f + k], b = sc.F[3 * f + (k + 1) % 3];
+      uint64_t key = ((uint64_t)(uint32_t)std::min(a, b) << 32) | (uint32_t)std::max(a, b);
+      auto it = seen.find(key);
+      if (it == seen.end()) {
+        seen.emplace(key, (int)E.size());
+        E.push_back({std::min(a, b), std::max(a, b), f, -1});
+      } else {
+        E[it->second].f2 = f;
+      }
+    }
+  return E;
+}
+
+bool front_facing(const or_scene& sc, int f, V3<double> eye) {
+  const double* p0 = sc.V + 3 * sc.F[3 * f];
+  const double* p1 = sc.V + 3 * sc.F[3 * f + 1];
+  const double* p2 = sc.V + 3 * sc.F[3 * f + 2];
+  V3<double> v0{p0[0], p0[1], p0[2]}, v1{p1[0], p1[1], p1[2]}, v2{p2[0], p2[1], p2[2]};
+  return dot(cross(sub(v1, v0), sub(v2, v0)), sub(v0, eye)) < 0.0;
+}
+
+}  // namespace
+
+// Centre-sample mask of one camera: mask [W*H] = 1 where the pixel centre's
+// camera ray hits the mesh (t > t_eps), else 0.
+int or_mask(const or_scene* sc, const double* cam, int W, int H, double* mask) {
+  if (!valid_scene(sc)) return 1;
+  Shared sh;
+  make_shared(sc, sh, false);
+  std::vector<double> o(3 * (size_t)W * H), d(3 * (size_t)W * H);
+  or_camera_rays(cam, W, H, o.data(), d.data());
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < (int64_t)W * H; ++i) {
+    Hit h = sc->use_bvh ? closest_bvh(*sc, sh.bvh, o.data() + 3 * i, d.data() + 3 * i, -1)
+                        : closest_brute(*sc, o.data() + 3 * i, d.data() + 3 * i, -1);
+    mask[i] = h.tri >= 0 ? 1.0 : 0.0;
+  }
+  return 0;
+}
+
+// Gradient of sum_p grad_mask[p] M_p with respect to the vertices, by the
+// outline quadrature above at density rho (points per pixel of projected
+// edge length).  dV [nv*3] is overwritten.  Optional counts [2]: silhouette
+// points in the image whose pixel has a nonzero grad_mask, and of those the
+// ones on the outline (visible).
+int or_mask_grad(const or_scene* sc, const double* cam, int W, int H, const double* grad_mask,
+                 double rho, double* dV, int64_t* counts) {
+  if (!valid_scene(sc) || !(rho > 0.0)) return 1;
+  Shared sh;
+  make_shared(sc, sh, false);
+  CamBasis c = cam_basis(cam, W, H);
+  std::vector<MeshEdge> E = mesh_edges(*sc);
+  std::memset(dV, 0, sizeof(double) * 3 * (size_t)sc->nv);
+  int64_t n_in = 0, n_vis = 0;
+  auto P = [&](int v) {
+    const double* p = sc->V + 3 * v;
+    return V3<double>{p[0], p[1], p[2]};
+  };
+  for (const MeshEdge& e : E) {
+    bool fa = front_facing(*sc, e.f1, c.eye);
+    int front = e.f1;
+    if (e.f2 >= 0) {
+      bool fb = front_facing(*sc, e.f2, c.eye);
+      if (fa == fb) continue;
+      front = fa ? e.f1 : e.f2;
+    }
+    V3<double> A = P(e.a), Bv = P(e.b);
+    double xa, ya, xb, yb;
+    if (!project(c, A, xa, ya, nullptr, nullptr) || !project(c, Bv, xb, yb, nullptr, nullptr)) continue;
+    // the front face's third vertex lies on the covered side
+    int cv = sc->F[3 * front] + sc->F[3 * front + 1] + sc->F[3 * front + 2] - e.a - e.b;
+    double xc, yc;
+    if (!project(c, P(cv), xc, yc, nullptr, nullptr)) continue;
+    double ex = xb - xa, ey = yb - ya;
+    double len = std::sqrt(ex * ex + ey * ey);
+    if (!(len > 0.0)) continue;
+    double nx = -ey / len, ny = ex / len;
+    if (nx * (xc - xa) + ny * (yc - ya) > 0.0) {
+      nx = -nx;
+      ny = -ny;
+    }
+    int ns = std::max(1, (int)std::ceil(rho * len));
+    for (int k = 0; k < ns; ++k) {
+      double t = (k + 0.5) / ns;
+      V3<double> X = add(scl(A, 1.0 - t), scl(Bv, t));
+      double xi, yi;
+      V3<double> jx, jy;
+      if (!project(c, X, xi, yi, &jx, &jy)) continue;
+      if (!(xi >= 0.0 && xi < W && yi >= 0.0 && yi < H)) continue;
+      int px = std::min((int)std::floor(xi), W - 1), py = std::min((int)std::floor(yi), H - 1);
+      double g = grad_mask[(size_t)py * W + px];
+      if (g == 0.0) continue;
+      ++n_in;
+      if (line_blocked(*sc, sh.bvh, c.eye, X, e.f1, e.f2)) continue;
+      ++n_vis;
+      V3<double> BA = sub(Bv, A);
+      double dxt = dot(jx, BA), dyt = dot(jy, BA);
+      double w = std::sqrt(dxt * dxt + dyt * dyt) / ns;
+      // normal velocity per unit move of the point: n . J
+      V3<double> nJ = add(scl(jx, nx), scl(jy, ny));
+      V3<double> ca = scl(nJ, g * w * (1.0 - t)), cb = scl(nJ, g * w * t);
+      double* da = dV + 3 * (size_t)e.a;
+      double* db = dV + 3 * (size_t)e.b;
+      da[0] += ca.x;
+      da[1] += ca.y;
+      da[2] += ca.z;
+      db[0] += cb.x;
+      db[1] += cb.y;
+      db[2] += cb.z;
+    }
+  }
+  if (counts) {
+    counts[0] = n_in;
+    counts[1] = n_vis;
   }
   return 0;
 }
