@@ -50,13 +50,19 @@ class _Absorption(C.Structure):
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
 
 
+class _Field(C.Structure):
+    _fields_ = [("grid", C.POINTER(C.c_double)), ("nx", C.c_int), ("ny", C.c_int),
+                ("nz", C.c_int), ("planes", C.POINTER(C.c_double)), ("res", C.c_int),
+                ("samples", C.c_int), ("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
 class _Scene(C.Structure):
     _fields_ = [("V", C.POINTER(C.c_double)), ("nv", C.c_int),
                 ("F", C.POINTER(C.c_int)), ("nf", C.c_int),
                 ("eta", C.c_double), ("sigma", C.c_double * 3),
                 ("env", C.POINTER(_Env)), ("max_depth", C.c_int),
                 ("terminal_env", C.c_int), ("t_eps", C.c_double), ("use_bvh", C.c_int),
-                ("absorb", C.POINTER(_Absorption))]
+                ("absorb", C.POINTER(_Absorption)), ("field", C.POINTER(_Field))]
 
 
 _lib = None
@@ -79,7 +85,7 @@ def lib():
         L.or_trace.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, ip,
                                C.POINTER(C.c_uint64), ip, C.POINTER(C.c_uint64)]
         L.or_trace_grad.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp, dp, dp, dp, dp, dp, dp,
-                                    C.c_int]
+                                    dp, C.c_int]
         L.or_trace_tree.argtypes = [C.POINTER(_Scene), dp, dp, dp, C.c_int]
         L.or_trace_errbound.argtypes = [C.POINTER(_Scene), dp, dp, i64, dp, dp]
         L.or_mask.argtypes = [C.POINTER(_Scene), dp, C.c_int, C.c_int, dp]
@@ -181,12 +187,42 @@ class Absorption:
             self.s.lo[k], self.s.hi[k] = float(self.lo[k]), float(self.hi[k])
 
 
+class Field:
+    """Volumetric environment field outside the object: a dense grid
+    [nz, ny, nx, 4] and three planes [3, res, res, 4] over the box [lo, hi]
+    (channel 0 -> density by softplus, 1-3 -> RGB), S midpoint samples per
+    exterior segment."""
+
+    def __init__(self, grid, planes, lo, hi, samples: int):
+        self.grid, self.planes = _d(grid), _d(planes)
+        assert self.grid.ndim == 4 and self.grid.shape[3] == 4
+        assert self.planes.ndim == 4 and self.planes.shape[0] == 3 and self.planes.shape[3] == 4
+        assert self.planes.shape[1] == self.planes.shape[2]
+        self.lo = np.asarray(lo, np.float64).reshape(3)
+        self.hi = np.asarray(hi, np.float64).reshape(3)
+        self.samples = int(samples)
+        nz, ny, nx, _ = self.grid.shape
+        self.s = _Field()
+        self.s.grid, self.s.nx, self.s.ny, self.s.nz = _p(self.grid), nx, ny, nz
+        self.s.planes, self.s.res, self.s.samples = _p(self.planes), self.planes.shape[1], self.samples
+        for k in range(3):
+            self.s.lo[k], self.s.hi[k] = float(self.lo[k]), float(self.hi[k])
+
+    @property
+    def n_params(self):
+        return self.grid.size + self.planes.size
+
+    def split(self, flat):
+        """Flat parameter vector -> (grid-shaped, planes-shaped) arrays."""
+        return flat[:self.grid.size].reshape(self.grid.shape), flat[self.grid.size:].reshape(self.planes.shape)
+
+
 class Scene:
     """Mesh + material + environment + tracing parameters for the oracle."""
 
     def __init__(self, V, F, eta, sigma, env: Env, max_depth: int,
                  terminal_env: bool = False, t_eps: float = 1e-5, use_bvh: bool = True,
-                 absorb: "Absorption | None" = None):
+                 absorb: "Absorption | None" = None, field: "Field | None" = None):
         self.V = _d(V).reshape(-1, 3)
         self.F = np.ascontiguousarray(F, dtype=np.int32).reshape(-1, 3)
         self.env = env
@@ -198,6 +234,7 @@ class Scene:
         self.t_eps = float(t_eps)
         self.use_bvh = bool(use_bvh)
         self.absorb = absorb
+        self.field = field
 
     def _s(self):
         s = _Scene()
@@ -212,11 +249,12 @@ class Scene:
         s.t_eps = self.t_eps
         s.use_bvh = int(self.use_bvh)
         s.absorb = C.pointer(self.absorb.s) if self.absorb is not None else None
+        s.field = C.pointer(self.field.s) if self.field is not None else None
         return s
 
     def with_(self, **kw):
         sc = Scene(self.V, self.F, self.eta, self.sigma, self.env, self.max_depth,
-                   self.terminal_env, self.t_eps, self.use_bvh, self.absorb)
+                   self.terminal_env, self.t_eps, self.use_bvh, self.absorb, self.field)
         for k, v in kw.items():
             if k == "V":
                 v = _d(v).reshape(-1, 3)
@@ -260,14 +298,17 @@ class Scene:
         dm = np.zeros_like(self.absorb.mu) if self.absorb is not None else None
         dt = np.zeros_like(self.env.tex) if want_tex and self.env.tex is not None else None
         dw = np.zeros(self.env.n_params) if want_mlp and self.env.mlp_shapes else None
+        df = np.zeros(self.field.n_params) if self.field is not None else None
         s = self._s()
         rc = lib().or_trace_grad(C.byref(s), _p(o), _p(d), n, _p(g), _p(rgb), _p(dV),
                                  _p(de), _p(ds), _p(dm) if dm is not None else None,
                                  _p(dt) if dt is not None else None,
-                                 _p(dw) if dw is not None else None, int(bool(absolute)))
+                                 _p(dw) if dw is not None else None,
+                                 _p(df) if df is not None else None, int(bool(absolute)))
         assert rc == 0, "or_trace_grad rejected its arguments"
         return {"rgb": rgb, "dV": dV, "d_eta": float(de[0]), "d_sigma": ds, "d_mu": dm,
-                "d_tex": dt, "d_mlp": self.env.split_params(dw) if dw is not None else None}
+                "d_tex": dt, "d_mlp": self.env.split_params(dw) if dw is not None else None,
+                "d_field": self.field.split(df) if df is not None else None}
 
     def errbound(self, o, d):
         """First-order bound on the rounding error of an FP32 evaluation of

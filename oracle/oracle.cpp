@@ -41,6 +41,7 @@
 // weights widened exactly), and every activation, product and sum is FP64.
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -208,7 +209,31 @@ typedef struct {
   double t_eps;      // minimum hit distance
   int use_bvh;       // 1: BVH, 0: brute force over all triangles
   const or_absorption* absorb;  // NULL: the constant rate sigma
+  const struct or_field* field; // NULL: no volumetric environment field
 } or_scene;
+
+// Volumetric environment field outside the object (the exterior half of the
+// sampling split of Sec. 3.3, a radiance field of a coarse dense grid and
+// triplanes as in Sec. 3.1 "Environment Initialization").  Inside the box
+// [lo, hi] the feature of a point x is the trilinear interpolant of the grid
+// (node (i, j, k) at lo + (i/(nx-1), j/(ny-1), k/(nz-1)) (hi - lo), value
+// grid[((k ny + j) nx + i) 4 + ch]) plus the bilinear interpolants of three
+// planes of res x res nodes over the box's faces: plane 0 over (x, y), 1 over
+// (x, z), 2 over (y, z), node (i, j) of plane p (i along its first axis, j
+// along its second) at planes[((p res + j) res + i) 4 + ch].  Channel 0 gives
+// the density softplus(f0) = log(1 + e^f0), channels 1-3 the RGB colour.  An
+// exterior segment is clipped to the box and sampled at the midpoints of S
+// equal steps of length h: alpha_k = 1 - exp(-sigma_k h), transmittance
+// T_k = prod_{j<k} (1 - alpha_j), emitted C = sum_k T_k alpha_k c_k, and the
+// segment passes T = prod_k (1 - alpha_k) of what lies beyond it.
+typedef struct or_field {
+  const double* grid;    // [nz][ny][nx][4]
+  int nx, ny, nz;        // >= 2 each
+  const double* planes;  // [3][res][res][4]
+  int res;               // >= 2
+  int samples;           // S >= 1
+  double lo[3], hi[3];
+} or_field;
 
 enum {
   OR_FLAG_DEGEN = 1,    // shading normal on the wrong side, geometric normal used
@@ -442,6 +467,13 @@ struct Ctx<double> {
     const double* p = sh->sc->V + 3 * v;
     return {p[0], p[1], p[2]};
   }
+  // field parameter k (grid nodes first, then plane nodes), 4 channels
+  void fpar(int64_t k, double* out) const {
+    const or_field& f = *sh->sc->field;
+    const int64_t ng = (int64_t)f.nx * f.ny * f.nz;
+    const double* p = k < ng ? f.grid + 4 * k : f.planes + 4 * (k - ng);
+    for (int c = 0; c < 4; ++c) out[c] = p[c];
+  }
   V3<double> nrm(int v) {
     const double* p = sh->Nv.data() + 3 * v;
     return {p[0], p[1], p[2]};
@@ -459,6 +491,17 @@ struct Ctx<Var> {
   std::unordered_map<int, V3<Var>> P;   // vertex -> leaf position
   std::unordered_map<int, V3<Var>> N;   // vertex -> normal on the tape
   std::unordered_map<int, V3<Var>> G;   // absorption grid node -> RGB leaf
+  std::unordered_map<int64_t, std::array<Var, 4>> FP;  // field parameter -> 4 leaves
+  void fpar(int64_t k, Var* out) {
+    auto it = FP.find(k);
+    if (it == FP.end()) {
+      const or_field& f = *sh->sc->field;
+      const int64_t ng = (int64_t)f.nx * f.ny * f.nz;
+      const double* p = k < ng ? f.grid + 4 * k : f.planes + 4 * (k - ng);
+      it = FP.emplace(k, std::array<Var, 4>{leaf(p[0]), leaf(p[1]), leaf(p[2]), leaf(p[3])}).first;
+    }
+    for (int c = 0; c < 4; ++c) out[c] = it->second[c];
+  }
   V3<Var> mu(int node) {
     auto it = G.find(node);
     if (it != G.end()) return it->second;
@@ -550,6 +593,122 @@ V3<S> grid_tau(Ctx<S>& cx, V3<S> o, V3<S> d, S t) {
   V3<S> acc{S(0.0), S(0.0), S(0.0)};
   for (int k = 0; k < ns; ++k) acc = add(acc, grid_mu(cx, add(o, scl(d, h * S(k + 0.5)))));
   return scl(acc, h);
+}
+
+// ---------------------------------------------------------------------------
+// volumetric environment field (exterior segments)
+// ---------------------------------------------------------------------------
+inline double Softplus(double x) { return x > 30.0 ? x : std::log1p(std::exp(x)); }
+inline Var Softplus(Var x) {
+  double e = std::exp(-std::fabs(x.v));
+  double v = x.v > 0 ? x.v + std::log1p(e) : std::log1p(std::exp(x.v));
+  double dv = 1.0 / (1.0 + std::exp(-x.v));
+  return mk(v, x.i, dv, -1, 0.0, kUlp32x2);
+}
+
+// Position along one axis in node units u = (x - lo)(n - 1)/(hi - lo), the
+// cell (held fixed) and the fraction in it; margin: distance (node units) to
+// the nearest cell boundary.
+template <class S>
+void field_axis(S x, double lo, double hi, int n, int& cell, S& frac, double& margin) {
+  const double scale = (double)(n - 1) / (hi - lo);
+  const double u = (val(x) - lo) * scale;
+  if (!(u > 0.0)) {
+    cell = 0;
+    frac = S(0.0);
+    margin = 0.0;
+  } else if (!(u < (double)(n - 1))) {
+    cell = n - 2;
+    frac = S(1.0);
+    margin = 0.0;
+  } else {
+    cell = std::min((int)std::floor(u), n - 2);
+    frac = (x - S(lo)) * S(scale) - S((double)cell);
+    margin = std::min(u - cell, cell + 1 - u);
+  }
+}
+
+// Feature (4 channels) at x inside the box; margin: the smallest distance,
+// in cell units, from x to a cell boundary of the grid or a plane.
+template <class S>
+void field_feature(Ctx<S>& cx, V3<S> x, S out[4], double& margin) {
+  const or_field& F = *cx.sh->sc->field;
+  const S xs[3] = {x.x, x.y, x.z};
+  int cg[3];
+  S fg[3];
+  double mg[3];
+  const int n[3] = {F.nx, F.ny, F.nz};
+  for (int a = 0; a < 3; ++a) field_axis(xs[a], F.lo[a], F.hi[a], n[a], cg[a], fg[a], mg[a]);
+  int cp[3];
+  S fp[3];
+  double mp[3];
+  for (int a = 0; a < 3; ++a) field_axis(xs[a], F.lo[a], F.hi[a], F.res, cp[a], fp[a], mp[a]);
+  margin = std::min({mg[0], mg[1], mg[2], mp[0], mp[1], mp[2]});
+  for (int c = 0; c < 4; ++c) out[c] = S(0.0);
+  S v[4];
+  for (int k = 0; k < 8; ++k) {
+    const int dx = k & 1, dy = (k >> 1) & 1, dz = (k >> 2) & 1;
+    S w = (dx ? fg[0] : S(1.0) - fg[0]) * (dy ? fg[1] : S(1.0) - fg[1]) * (dz ? fg[2] : S(1.0) - fg[2]);
+    const int64_t node = ((int64_t)(cg[2] + dz) * F.ny + (cg[1] + dy)) * F.nx + (cg[0] + dx);
+    cx.fpar(node, v);
+    for (int c = 0; c < 4; ++c) out[c] = out[c] + w * v[c];
+  }
+  const int64_t ng = (int64_t)F.nx * F.ny * F.nz;
+  const int ax[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+  for (int p = 0; p < 3; ++p) {
+    const int a = ax[p][0], b = ax[p][1];
+    for (int k = 0; k < 4; ++k) {
+      const int di = k & 1, dj = k >> 1;
+      S w = (di ? fp[a] : S(1.0) - fp[a]) * (dj ? fp[b] : S(1.0) - fp[b]);
+      const int64_t node = ng + ((int64_t)p * F.res + (cp[b] + dj)) * F.res + (cp[a] + di);
+      cx.fpar(node, v);
+      for (int c = 0; c < 4; ++c) out[c] = out[c] + w * v[c];
+    }
+  }
+}
+
+// Emission C and transmittance T of the exterior segment o + s d, s in
+// [0, t_end] (t_end = +inf for a ray that leaves), clipped to the field's
+// box.  The clip distances depend on o and d (and t_end); which box faces
+// clip is a discrete choice held fixed.  kink: set when a sample lies within
+// 1e-5 cell units of a cell boundary (the field's gradient jumps there).
+template <class S>
+void field_segment(Ctx<S>& cx, V3<S> o, V3<S> d, S t_end, bool open, V3<S>& C, S& T, bool& kink) {
+  const or_field& F = *cx.sh->sc->field;
+  C = {S(0.0), S(0.0), S(0.0)};
+  T = S(1.0);
+  const S os[3] = {o.x, o.y, o.z}, ds[3] = {d.x, d.y, d.z};
+  S s0 = S(0.0), s1 = t_end;
+  bool have1 = !open;
+  for (int a = 0; a < 3; ++a) {
+    if (val(ds[a]) == 0.0) {
+      if (val(os[a]) < F.lo[a] || val(os[a]) > F.hi[a]) return;
+      continue;
+    }
+    S ta = (S(F.lo[a]) - os[a]) / ds[a], tb = (S(F.hi[a]) - os[a]) / ds[a];
+    if (val(ta) > val(tb)) std::swap(ta, tb);
+    if (val(ta) > val(s0)) s0 = ta;
+    if (!have1 || val(tb) < val(s1)) {
+      s1 = tb;
+      have1 = true;
+    }
+  }
+  if (!(val(s1) > val(s0))) return;
+  const int ns = F.samples;
+  const S h = (s1 - s0) / S((double)ns);
+  S trans = S(1.0);
+  for (int k = 0; k < ns; ++k) {
+    V3<S> x = add(o, scl(d, s0 + h * S(k + 0.5)));
+    S f[4];
+    double margin;
+    field_feature(cx, x, f, margin);
+    if (margin < 1e-5) kink = true;
+    S a = Exp(-(Softplus(f[0]) * h));   // 1 - alpha_k
+    S w = trans * (S(1.0) - a);
+    C = add(C, V3<S>{w * f[1], w * f[2], w * f[3]});
+    trans = trans * a;
+  }
+  T = trans;
 }
 
 // ---------------------------------------------------------------------------
@@ -859,6 +1018,15 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
       rec.E[2] = val(E.z);
       tree->push_back(rec);
     }
+    if (sc.field && !inside) {
+      // the exterior segment to the field's far side, then the environment
+      V3<S> Cf;
+      S Tf;
+      bool kink = false;
+      field_segment(cx, o, d, S(INFINITY), true, Cf, Tf, kink);
+      if (kink) pi.flags |= OR_FLAG_KINK;
+      return add(Cf, scl(E, Tf));
+    }
     return E;
   }
   const int* F = sc.F;
@@ -901,6 +1069,8 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
   // Procedure step 5 / Eq. 11: attenuation over the interior segment just
   // travelled (the ray hit the surface from inside)
   V3<S> A{S(1.0), S(1.0), S(1.0)};
+  // emission of the exterior segment just travelled (volumetric field)
+  V3<S> Cem{S(0.0), S(0.0), S(0.0)};
   if (!entering) {
     if (sc.absorb) {
       V3<S> tau = grid_tau(cx, o, d, t);
@@ -908,6 +1078,14 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
     } else {
       A = {Exp(-cx.sigma[0] * t), Exp(-cx.sigma[1] * t), Exp(-cx.sigma[2] * t)};
     }
+  } else if (sc.field) {
+    // Procedure step 4: the radiance beyond the hit is mixed with the
+    // environment field sampled before it
+    S Tf;
+    bool kink = false;
+    field_segment(cx, o, d, t, false, Cem, Tf, kink);
+    if (kink) pi.flags |= OR_FLAG_KINK;
+    A = {Tf, Tf, Tf};
   }
   double Av[3] = {val(A.x), val(A.y), val(A.z)};
   if (tree) {
@@ -929,9 +1107,9 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
     if (sc.terminal_env) {
       EnvOut eo;
       V3<S> E = env_eval(*sc.env, d, eo);
-      return {A.x * E.x, A.y * E.y, A.z * E.z};
+      return add(Cem, V3<S>{A.x * E.x, A.y * E.y, A.z * E.z});
     }
-    return {S(0.0), S(0.0), S(0.0)};
+    return Cem;
   }
   // Snell: sin^2(theta_t) = sin^2(theta_i) / eta_r^2
   S sin2t = (S(1.0) - cos_i * cos_i) / (eta_r * eta_r);
@@ -955,7 +1133,7 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
     }
     double Wr[3] = {W[0] * Av[0], W[1] * Av[1], W[2] * Av[2]};
     V3<S> Lr = trace(cx, x, rdir, h.tri, g + 1, Wr, r_inside, pi, tree);
-    return {A.x * Lr.x, A.y * Lr.y, A.z * Lr.z};
+    return add(Cem, V3<S>{A.x * Lr.x, A.y * Lr.y, A.z * Lr.z});
   }
   S cos_t = Sqrt(S(1.0) - sin2t);
   // Eq. 7-8
@@ -980,7 +1158,8 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
   // Procedure step 4: trace both children and blend with R and T
   V3<S> Lr = trace(cx, x, rdir, h.tri, g + 1, Wr, r_inside, pi, tree);
   V3<S> Lt = trace(cx, x, tdir, h.tri, g + 1, Wt, t_inside, pi, tree);
-  return {A.x * (R * Lr.x + T * Lt.x), A.y * (R * Lr.y + T * Lt.y), A.z * (R * Lr.z + T * Lt.z)};
+  return add(Cem, V3<S>{A.x * (R * Lr.x + T * Lt.x), A.y * (R * Lr.y + T * Lt.y),
+                        A.z * (R * Lr.z + T * Lt.z)});
 }
 
 void make_shared(const or_scene* sc, Shared& sh, bool need_normals) {
@@ -1008,6 +1187,13 @@ bool valid_scene(const or_scene* sc) {
     if (!G->mu || G->nx < 2 || G->ny < 2 || G->nz < 2 || G->samples < 1) return false;
     for (int a = 0; a < 3; ++a)
       if (!(G->hi[a] > G->lo[a])) return false;
+  }
+  if (const or_field* Fd = sc->field) {
+    if (!Fd->grid || !Fd->planes || Fd->nx < 2 || Fd->ny < 2 || Fd->nz < 2 || Fd->res < 2 ||
+        Fd->samples < 1)
+      return false;
+    for (int a = 0; a < 3; ++a)
+      if (!(Fd->hi[a] > Fd->lo[a])) return false;
   }
   for (int i = 0; i < 3 * sc->nf; ++i)
     if (sc->F[i] < 0 || sc->F[i] >= sc->nv) return false;
@@ -1185,14 +1371,16 @@ int or_trace(const or_scene* sc, const double* o, const double* d, int64_t n, do
 // Forward + reverse-mode gradient.  The scalar loss is sum_i grad_rgb[i] . C_i.
 // dV [nv*3], d_eta [1], d_sigma [3] are overwritten, and with an absorption
 // grid d_mu [nx*ny*nz*3] too (sigma then has no effect and d_sigma is 0), for
-// an equirect environment d_tex [H*W*3], and for an MLP environment d_mlp
-// (every weight, then every bias, in the order of or_env).  rgb, d_mu, d_tex
-// and d_mlp may be NULL.  absolute = 1: every output is instead the sum over
+// an equirect environment d_tex [H*W*3], for an MLP environment d_mlp
+// (every weight, then every bias, in the order of or_env), and with a
+// volumetric field d_field (grid nodes, then plane nodes, 4 channels each).
+// rgb, d_mu, d_tex, d_mlp and d_field may be NULL.  absolute = 1: every output is instead the sum over
 // camera rays of the magnitude of each ray's contribution (the scale against
 // which a sum that cancels is compared).
 int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t n,
                   const double* grad_rgb, double* rgb, double* dV, double* d_eta,
-                  double* d_sigma, double* d_mu, double* d_tex, double* d_mlp, int absolute) {
+                  double* d_sigma, double* d_mu, double* d_tex, double* d_mlp, double* d_field,
+                  int absolute) {
   if (!valid_scene(sc)) return 1;
   Shared sh;
   make_shared(sc, sh, true);
@@ -1208,6 +1396,11 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
   std::vector<std::vector<double>> accT(nth);
   const size_t nmlp = (d_mlp && sc->env->kind == 1) ? mlp_param_count(*sc->env) : 0;
   std::vector<std::vector<double>> accW(nth);
+  const size_t nfld = (d_field && sc->field)
+                          ? 4 * ((size_t)sc->field->nx * sc->field->ny * sc->field->nz +
+                                 3 * (size_t)sc->field->res * sc->field->res)
+                          : 0;
+  std::vector<std::vector<double>> accF(nth);
 #pragma omp parallel
   {
     int tid = 0;
@@ -1218,6 +1411,7 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
     accM[tid].assign(nmu, 0.0);
     accT[tid].assign(ntex, 0.0);
     accW[tid].assign(nmlp, 0.0);
+    accF[tid].assign(nfld, 0.0);
     Tape tape;
     g_tape = &tape;
     std::unordered_map<int, V3<Var>> texleaf;
@@ -1279,6 +1473,9 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
         dst[2] += A(kv.second.z.i);
       }
       for (size_t k = 0; k < mlpleaf.size(); ++k) accW[tid][k] += A(mlpleaf[k].i);
+      if (nfld)
+        for (auto& kv : cx.FP)
+          for (int c = 0; c < 4; ++c) accF[tid][4 * (size_t)kv.first + c] += A(kv.second[c].i);
     }
     g_tape = nullptr;
     g_texleaf = nullptr;
@@ -1290,6 +1487,7 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
   d_sigma[0] = d_sigma[1] = d_sigma[2] = 0.0;
   if (d_mu && nmu) std::memset(d_mu, 0, sizeof(double) * nmu);
   if (nmlp) std::memset(d_mlp, 0, sizeof(double) * nmlp);
+  if (nfld) std::memset(d_field, 0, sizeof(double) * nfld);
   for (int t = 0; t < nth; ++t) {
     if (accV[t].empty()) continue;
     for (size_t j = 0; j < 3 * (size_t)sc->nv; ++j) dV[j] += accV[t][j];
@@ -1299,6 +1497,7 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
       for (size_t j = 0; j < nmu; ++j) d_mu[j] += accM[t][j];
     for (size_t j = 0; j < ntex; ++j) d_tex[j] += accT[t][j];
     for (size_t j = 0; j < nmlp; ++j) d_mlp[j] += accW[t][j];
+    for (size_t j = 0; j < nfld; ++j) d_field[j] += accF[t][j];
   }
   return 0;
 }
