@@ -62,7 +62,8 @@ class _Scene(C.Structure):
                 ("eta", C.c_double), ("sigma", C.c_double * 3),
                 ("env", C.POINTER(_Env)), ("max_depth", C.c_int),
                 ("terminal_env", C.c_int), ("t_eps", C.c_double), ("use_bvh", C.c_int),
-                ("absorb", C.POINTER(_Absorption)), ("field", C.POINTER(_Field))]
+                ("absorb", C.POINTER(_Absorption)), ("field", C.POINTER(_Field)),
+                ("jitter", C.c_double), ("jitter_seed", C.c_uint64)]
 
 
 _lib = None
@@ -235,6 +236,10 @@ class Scene:
         self.use_bvh = bool(use_bvh)
         self.absorb = absorb
         self.field = field
+        # test instrument (0 = off): every ray the tracer starts is scaled per
+        # component by (1 + jitter xi), xi uniform in [-1, 1), seeded
+        self.jitter = 0.0
+        self.jitter_seed = 0
 
     def _s(self):
         s = _Scene()
@@ -250,11 +255,13 @@ class Scene:
         s.use_bvh = int(self.use_bvh)
         s.absorb = C.pointer(self.absorb.s) if self.absorb is not None else None
         s.field = C.pointer(self.field.s) if self.field is not None else None
+        s.jitter, s.jitter_seed = float(self.jitter), int(self.jitter_seed)
         return s
 
     def with_(self, **kw):
         sc = Scene(self.V, self.F, self.eta, self.sigma, self.env, self.max_depth,
                    self.terminal_env, self.t_eps, self.use_bvh, self.absorb, self.field)
+        sc.jitter, sc.jitter_seed = self.jitter, self.jitter_seed
         for k, v in kw.items():
             if k == "V":
                 v = _d(v).reshape(-1, 3)

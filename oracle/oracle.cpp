@@ -210,6 +210,14 @@ typedef struct {
   int use_bvh;       // 1: BVH, 0: brute force over all triangles
   const or_absorption* absorb;  // NULL: the constant rate sigma
   const struct or_field* field; // NULL: no volumetric environment field
+  // Test instrument, not part of the method (0 = off): every ray the tracer
+  // starts (camera rays and every child) has each component of its origin and
+  // direction scaled by (1 + jitter xi), xi uniform in [-1, 1) from a
+  // counter-based hash of (jitter_seed, ray index, node number).  A parity
+  // test measures with it how much a result moves when every ray is rounded
+  // the way a float32 evaluation rounds it.
+  double jitter;
+  uint64_t jitter_seed;
 } or_scene;
 
 // Volumetric environment field outside the object (the exterior half of the
@@ -959,6 +967,11 @@ inline uint64_t splitmix64(uint64_t x) {
 
 struct PathInfo {
   int flags = 0;
+  uint64_t jkey = 0;  // jitter stream of this camera ray, and rays started so far
+  uint64_t jn = 0;
+  void start(const or_scene* sc, int64_t ray) {
+    jkey = splitmix64(sc->jitter_seed ^ (0xD1B54A32D192ED03ull * (uint64_t)(ray + 1)));
+  }
   double wtrunc[3] = {0, 0, 0};
   int nseg = 0;
   // order-independent signature of the discrete path: the sum (mod 2^64) over
@@ -991,6 +1004,14 @@ V3<S> trace(Ctx<S>& cx, V3<S> o, V3<S> d, int skip, int g, const double W[3], bo
   const Shared& sh = *cx.sh;
   const or_scene& sc = *sh.sc;
   pi.nseg++;
+  if (sc.jitter > 0.0) {
+    const uint64_t b = splitmix64(pi.jkey + 0x632BE59BD9B4E019ull * ++pi.jn);
+    double xi[6];
+    for (int k = 0; k < 6; ++k)
+      xi[k] = 1.0 + sc.jitter * ((double)(splitmix64(b + (uint64_t)k) >> 11) * 0x1.0p-52 - 1.0);
+    o = {o.x * S(xi[0]), o.y * S(xi[1]), o.z * S(xi[2])};
+    d = {d.x * S(xi[3]), d.y * S(xi[4]), d.z * S(xi[5])};
+  }
   double od[3] = {val(o.x), val(o.y), val(o.z)}, dd[3] = {val(d.x), val(d.y), val(d.z)};
   Hit h = sc.use_bvh ? closest_bvh(sc, sh.bvh, od, dd, skip) : closest_brute(sc, od, dd, skip);
   TreeRec rec{};
@@ -1183,6 +1204,7 @@ void make_shared(const or_scene* sc, Shared& sh, bool need_normals) {
 bool valid_scene(const or_scene* sc) {
   if (!sc || !sc->V || !sc->F || !sc->env || sc->nv <= 0 || sc->nf <= 0) return false;
   if (sc->max_depth < 0 || sc->max_depth > 30) return false;
+  if (!(sc->jitter >= 0.0 && sc->jitter <= 1e-3)) return false;
   if (const or_absorption* G = sc->absorb) {
     if (!G->mu || G->nx < 2 || G->ny < 2 || G->nz < 2 || G->samples < 1) return false;
     for (int a = 0; a < 3; ++a)
@@ -1350,6 +1372,7 @@ int or_trace(const or_scene* sc, const double* o, const double* d, int64_t n, do
   for (int64_t i = 0; i < n; ++i) {
     Ctx<double> cx{&sh, sc->eta, {sc->sigma[0], sc->sigma[1], sc->sigma[2]}};
     PathInfo pi;
+    pi.start(sc, i);
     double W[3] = {1, 1, 1};
     V3<double> oo{o[3 * i], o[3 * i + 1], o[3 * i + 2]}, dd{d[3 * i], d[3 * i + 1], d[3 * i + 2]};
     V3<double> L = trace<double>(cx, oo, dd, -1, 0, W, false, pi, nullptr);
@@ -1429,6 +1452,7 @@ int or_trace_grad(const or_scene* sc, const double* o, const double* d, int64_t 
       cx.eta = leaf(sc->eta);
       for (int k = 0; k < 3; ++k) cx.sigma[k] = leaf(sc->sigma[k]);
       PathInfo pi;
+      pi.start(sc, i);
       double W[3] = {1, 1, 1};
       V3<Var> oo{Var(o[3 * i]), Var(o[3 * i + 1]), Var(o[3 * i + 2])};
       V3<Var> dd{Var(d[3 * i]), Var(d[3 * i + 1]), Var(d[3 * i + 2])};
@@ -1535,6 +1559,7 @@ int or_trace_errbound(const or_scene* sc, const double* o, const double* d, int6
       cx.eta = leaf(sc->eta);
       for (int k = 0; k < 3; ++k) cx.sigma[k] = leaf(sc->sigma[k]);
       PathInfo pi;
+      pi.start(sc, i);
       double W[3] = {1, 1, 1};
       V3<Var> oo{leaf(o[3 * i]), leaf(o[3 * i + 1]), leaf(o[3 * i + 2])};
       V3<Var> dd{leaf(d[3 * i], kUlp32x2), leaf(d[3 * i + 1], kUlp32x2), leaf(d[3 * i + 2], kUlp32x2)};
@@ -1788,6 +1813,7 @@ int or_trace_tree(const or_scene* sc, const double* o, const double* d, double* 
   make_shared(sc, sh, true);
   Ctx<double> cx{&sh, sc->eta, {sc->sigma[0], sc->sigma[1], sc->sigma[2]}};
   PathInfo pi;
+  pi.start(sc, 0);
   double W[3] = {1, 1, 1};
   std::vector<TreeRec> tree;
   trace<double>(cx, {o[0], o[1], o[2]}, {d[0], d[1], d[2]}, -1, 0, W, false, pi, &tree);

@@ -85,3 +85,37 @@ def test_bound_grows_toward_the_critical_angle(oracle_lib):
     o, dd = slab_ray(30.0, H_SLAB)
     rgb, b = sc.errbound(o[None], dd[None])
     assert (b / np.abs(rgb)).max() < 1e-5
+
+
+def test_jitter_instrument(oracle_lib):
+    """The ray jitter used to size gradient allowances: off, it leaves every
+    output bit-identical; on, it is deterministic per seed, changes the
+    radiance by an amount of the order of the jitter (within the first-order
+    bound scaled by the jitter over float32's unit roundoff, on pixels whose
+    path stays), and is refused beyond 1e-3."""
+    sc, o, d = _torus(oracle_lib)
+    r0 = sc.trace(o, d)
+    s0 = sc.with_(jitter=0.0, jitter_seed=5).trace(o, d)
+    for k in ("rgb", "sig", "flags"):
+        np.testing.assert_array_equal(r0[k], s0[k])
+    u = 2.0 ** -23
+    j1 = sc.with_(jitter=u, jitter_seed=5)
+    a, b = j1.trace(o, d), j1.trace(o, d)
+    np.testing.assert_array_equal(a["rgb"], b["rgb"])
+    c = sc.with_(jitter=u, jitter_seed=6).trace(o, d)
+    assert not np.array_equal(a["rgb"], c["rgb"])
+    same = (a["sig"] == r0["sig"]) & (c["sig"] == r0["sig"])
+    assert same.mean() > 0.98
+    _, bound = sc.errbound(o, d)
+    moved = np.abs(a["rgb"] - r0["rgb"])[same]
+    assert moved.max() > 0
+    # the bound charges each operation 2^-24; the jitter moves every ray by up
+    # to u = 2^-23 per component, and FP64 itself adds nothing visible
+    assert (moved <= 4 * (u / 2.0 ** -24) * bound[same] + 1e-15).all()
+    g = np.random.default_rng(1).normal(size=r0["rgb"].shape)
+    g0 = sc.trace_grad(o, d, g)
+    g1 = j1.trace_grad(o, d, g)
+    assert 0 < np.linalg.norm(g1["dV"] - g0["dV"]) <= 1e-3 * np.linalg.norm(g0["dV"])
+    import pytest
+    with pytest.raises(AssertionError):
+        sc.with_(jitter=2e-3).trace(o, d)
