@@ -55,6 +55,8 @@ class Tracer:
         self._buf = None
         self._key = None
         self.version = 0     # bumped by every forward: the tape holds only the last one
+        self._mask_grad = None
+        self._mask_grad_key = None
 
     def _params(self, stride=None, timing=None) -> B.Params:
         return B.Params(max_depth=self.max_depth, terminal_env=self.terminal_env, t_eps=self.t_eps,
@@ -161,3 +163,66 @@ def render_grid(V: torch.Tensor, ior: torch.Tensor, mu: torch.Tensor, tracer: Tr
     `samples` midpoint samples per interior segment.  Differentiable in V,
     ior and mu."""
     return _DTTraceGrid.apply(V, ior, mu, tracer, lo, hi, samples)
+
+
+# ------------------------------------------------------------------ environment MLP parameters
+class _DTTraceMLP(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, V, ior, sigma, w, b, tracer):
+        env = tracer.env
+        with torch.no_grad():
+            # the device evaluates bf16 weights: round the float32 parameters
+            env.weights.copy_(w.detach().to(torch.bfloat16).view(torch.int16))
+            env.biases.copy_(b.detach())
+        rgb, scene, buf = tracer.forward(V, ior, sigma)
+        ctx.tracer, ctx.scene, ctx.buf, ctx.version = tracer, scene, buf, tracer.version
+        return rgb
+
+    @staticmethod
+    def backward(ctx, grad_rgb):
+        dV, d_ior, d_sigma = ctx.tracer.backward(ctx.scene, ctx.buf, grad_rgb, ctx.version)
+        env = ctx.tracer.env
+        # the gradient with respect to the bf16 weights is passed to the
+        # float32 parameters unchanged (straight through the rounding)
+        return (dV, d_ior.reshape(1), d_sigma.reshape(3), env.d_weights.clone(), env.d_biases.clone(),
+                None)
+
+
+def render_mlp(V: torch.Tensor, ior: torch.Tensor, sigma: torch.Tensor, weights: torch.Tensor,
+               biases: torch.Tensor, tracer: Tracer):
+    """Pixel colours lit by the tracer's MLP environment (an Env made with
+    want_grad=True), differentiable in V, ior, sigma [3] and the network's
+    float32 parameters (flat weights of every layer, flat biases; the device
+    runs them rounded to bf16)."""
+    env = tracer.env
+    if getattr(env, "d_weights", None) is None:
+        raise B.DTError("render_mlp needs an MLP environment made with want_grad=True")
+    return _DTTraceMLP.apply(V, ior, sigma, weights, biases, tracer)
+
+
+# ------------------------------------------------------------------ silhouette (mask) term
+class _MaskFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, V, tracer, rho):
+        mesh, _ = tracer._prepare(V.detach().contiguous().float())
+        mask = B.dt_mask_forward(mesh, tracer.rays, tracer.t_eps)
+        ctx.tracer, ctx.mesh, ctx.rho, ctx.version = tracer, mesh, rho, tracer.version
+        return mask
+
+    @staticmethod
+    def backward(ctx, grad_mask):
+        tr = ctx.tracer
+        if tr._mask_grad is None or tr._mask_grad_key != (ctx.mesh.nv, ctx.mesh.nf):
+            tr._mask_grad = B.MaskGrad(ctx.mesh)
+            tr._mask_grad_key = (ctx.mesh.nv, ctx.mesh.nf)
+        dV = tr._mask_grad(ctx.mesh, tr.rays, grad_mask.contiguous().float(), ctx.rho)
+        return dV, None, None
+
+
+def render_mask(V: torch.Tensor, tracer: Tracer, rho: float = 2.0):
+    """Centre-sample coverage [n_pixels] of the tracer's cameras; its
+    gradient with respect to V is the outline (edge-sampling) gradient of the
+    pixels' area coverage, rho quadrature points per pixel of edge length.
+    Builds the mesh's BVH from V; call it before render() in a step if both
+    are used, or after render()'s backward (the tracer keeps one mesh)."""
+    return _MaskFn.apply(V, tracer, float(rho))

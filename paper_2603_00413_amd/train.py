@@ -15,12 +15,19 @@ adds the losses up and updates the parameters:
   channels) for the absorption grid;
 * L_vol: sum over sample points of ||mu(x)||^2;
 * L_edge: mean over mesh edges of (1 - n_i . n_j)^2 with the unit vertex
-  normals.
+  normals;
+* L_lap: mean over vertices of ||(L V)_i||^2 with the uniform Laplacian
+  (L V)_i = V_i - mean of V_i's neighbours (the uniformity term of the large-
+  steps paper the appendix cites);
+* L_mask: mean over pixels of (M_p - M*_p)^2, M the object's coverage with
+  the outline (silhouette) gradient of `autograd.render_mask`.
+L_mask, L_edge and L_lap are the periodic regularization of the appendix
+("Periodical Regularization"): added every `period`-th step.
 
 The vertices are optimised either with plain Adam or, as in the paper, with
 AdamUniform on the Laplacian reparameterisation u = (I + lambda L) V (below);
-the other parameters with Adam.  The mask term needs silhouettes, which the
-interior-derivative tracer does not give.
+the other parameters with Adam, the environment MLP's float32 parameters
+included when given.
 """
 from __future__ import annotations
 
@@ -104,6 +111,29 @@ def edge_loss(V: torch.Tensor, F: torch.Tensor, edges: torch.Tensor | None = Non
     return ((1.0 - (n[edges[:, 0]] * n[edges[:, 1]]).sum(-1)) ** 2).mean()
 
 
+def uniform_laplacian(nv: int, F: torch.Tensor) -> torch.Tensor:
+    """I - D^-1 A of the mesh's edge graph, sparse [nv, nv] float32."""
+    e = mesh_edges(F)
+    i = torch.cat([e[:, 0], e[:, 1]])
+    j = torch.cat([e[:, 1], e[:, 0]])
+    ones = torch.ones(i.shape[0], dtype=torch.float32, device=F.device)
+    deg = torch.zeros(nv, dtype=torch.float32, device=F.device).index_add(0, i, ones)
+    d = torch.arange(nv, device=F.device)
+    idx = torch.cat([torch.stack([i, j]), torch.stack([d, d])], 1)
+    val = torch.cat([-ones / deg[i], torch.ones(nv, dtype=torch.float32, device=F.device)])
+    return torch.sparse_coo_tensor(idx, val, (nv, nv)).coalesce()
+
+
+def lap_loss(V: torch.Tensor, Lu: torch.Tensor) -> torch.Tensor:
+    """mean_i ||(L V)_i||^2 with the uniform Laplacian Lu."""
+    return (torch.sparse.mm(Lu, V) ** 2).sum(-1).mean()
+
+
+def mask_loss(pred: torch.Tensor, gt: torch.Tensor) -> torch.Tensor:
+    """mean_p (M_p - M*_p)^2."""
+    return ((pred - gt) ** 2).mean()
+
+
 class Trainer:
     """One optimisation step of the paper's ray-tracing stage: render with the
     current parameters, L_total = l_color L_color + l_tone L_tone (+ l_smooth
@@ -116,16 +146,25 @@ class Trainer:
                  sigma: torch.Tensor | None = None, grid=None, lr: float = 1e-3,
                  l_color: float = 1.0, l_tone: float = 0.0, l_smooth: float = 0.0,
                  l_vol: float = 0.0, l_edge: float = 0.0, n_points: int = 4096, seed: int = 0,
-                 large_steps: float | None = None, lr_mesh: float = 1e-3):
-        """grid: (mu, lo, hi, samples) with mu a leaf tensor [nz, ny, nx, 3]."""
+                 large_steps: float | None = None, lr_mesh: float = 1e-3, mlp=None,
+                 l_mask: float = 0.0, l_lap: float = 0.0, period: int = 1, mask_rho: float = 2.0):
+        """grid: (mu, lo, hi, samples) with mu a leaf tensor [nz, ny, nx, 3].
+        mlp: (weights, biases) float32 leaf tensors of the tracer's MLP
+        environment (made with want_grad=True).  L_mask, L_edge and L_lap are
+        added on every `period`-th step (counting from the first)."""
         self.tracer, self.V, self.ior, self.sigma, self.grid = tracer, V, ior, sigma, grid
-        self.w = dict(color=l_color, tone=l_tone, smooth=l_smooth, vol=l_vol, edge=l_edge)
+        self.mlp = mlp
+        self.period, self.mask_rho, self.t = max(int(period), 1), mask_rho, 0
+        self.w = dict(color=l_color, tone=l_tone, smooth=l_smooth, vol=l_vol, edge=l_edge,
+                      mask=l_mask, lap=l_lap)
+        self.Lu = uniform_laplacian(V.shape[0], tracer.F) if l_lap else None
         self.ls, self.u, self.opt_mesh = None, None, None
         if large_steps is not None and V.requires_grad:
             self.ls = LargeSteps(V.shape[0], tracer.F, large_steps)
             self.u = self.ls.to_u(V.detach()).requires_grad_(True)
             self.opt_mesh = AdamUniform([self.u], lr=lr_mesh)
-        params = [p for p in (None if self.ls else V, ior, sigma, grid[0] if grid else None)
+        params = [p for p in (None if self.ls else V, ior, sigma, grid[0] if grid else None,
+                              *(mlp or ()))
                   if p is not None and p.requires_grad]
         self.opt = torch.optim.Adam(params, lr=lr) if params else None
         self.n_points = n_points
@@ -138,18 +177,30 @@ class Trainer:
         r = torch.rand(self.n_points, 3, generator=self.gen, device=self.V.device)
         return lo_t + r * (hi_t - lo_t), (hi_t - lo_t)
 
-    def step(self, gt: torch.Tensor) -> dict:
+    def step(self, gt: torch.Tensor, gt_mask: torch.Tensor | None = None) -> dict:
+        """One step against target colours gt [n_pixels, 3] (and, for L_mask,
+        the target coverage gt_mask [n_pixels])."""
         for o in (self.opt, self.opt_mesh):
             if o is not None:
                 o.zero_grad(set_to_none=True)
         if self.ls is not None:
             self.V = _FromU.apply(self.u, self.ls)
+        periodic = self.t % self.period == 0
+        self.t += 1
+        terms = {}
+        if periodic and self.w["mask"]:
+            if gt_mask is None:
+                raise ValueError("L_mask needs the target mask")
+            terms["mask"] = mask_loss(A.render_mask(self.V, self.tracer, self.mask_rho), gt_mask)
         if self.grid is not None:
             mu, lo, hi, samples = self.grid
             pred = A.render_grid(self.V, self.ior, mu, self.tracer, lo, hi, samples)
+        elif self.mlp is not None:
+            sg = self.sigma.expand(3) if self.sigma.numel() == 1 else self.sigma
+            pred = A.render_mlp(self.V, self.ior, sg, self.mlp[0], self.mlp[1], self.tracer)
         else:
             pred = A.render(self.V, self.ior, self.sigma, self.tracer)
-        terms = {"color": color_loss(pred, gt)}
+        terms["color"] = color_loss(pred, gt)
         if self.w["tone"]:
             terms["tone"] = tone_loss(pred, gt)
         if self.grid is not None and (self.w["smooth"] or self.w["vol"]):
@@ -159,8 +210,10 @@ class Trainer:
                 terms["smooth"] = mat_smooth_loss(mu, lo, hi, pts, xi)
             if self.w["vol"]:
                 terms["vol"] = vol_loss(mu, lo, hi, pts)
-        if self.w["edge"]:
+        if periodic and self.w["edge"]:
             terms["edge"] = edge_loss(self.V, self.tracer.F, self.edges)
+        if periodic and self.w["lap"]:
+            terms["lap"] = lap_loss(self.V, self.Lu)
         total = sum(self.w[k] * v for k, v in terms.items())
         total.backward()
         for o in (self.opt, self.opt_mesh):
@@ -198,27 +251,31 @@ def laplacian(nv: int, F: torch.Tensor) -> torch.Tensor:
     return torch.sparse_coo_tensor(idx, val, (nv, nv)).coalesce()
 
 
-def solve_spd(matvec, b: torch.Tensor, iters: int = 1000, tol: float = 1e-10) -> torch.Tensor:
+def solve_spd(matvec, b: torch.Tensor, iters: int = 1000, tol: float = 1e-10,
+              x0: torch.Tensor | None = None, check_every: int = 16) -> torch.Tensor:
     """Conjugate gradients for A x = b (A symmetric positive definite, given as
     matvec), column by column of b [n, k], to a residual of tol * |b| per
-    column.  Raises RuntimeError when `iters` iterations do not get there (a
-    mesh taken from an unconverged solve would be silently wrong)."""
-    x = torch.zeros_like(b)
+    column, from x0 (default 0).  The residual is read back every
+    `check_every` iterations (each read waits for the device).  Raises
+    RuntimeError when `iters` iterations do not get there (a mesh taken from
+    an unconverged solve would be silently wrong)."""
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
     r = b - matvec(x)
     p = r.clone()
     rs = (r * r).sum(0)
     b2 = (b * b).sum(0).clamp_min(1e-300)
-    for _ in range(iters):
-        if bool((rs <= tol * tol * b2).all()):
+    lim = tol * tol * b2
+    for it in range(iters):
+        if it % check_every == 0 and bool((rs <= lim).all()):
             return x
         Ap = matvec(p)
-        alpha = rs / (p * Ap).sum(0)
+        alpha = rs / (p * Ap).sum(0).clamp_min(1e-300)
         x = x + alpha * p
         r = r - alpha * Ap
         rs_new = (r * r).sum(0)
-        p = r + (rs_new / rs) * p
+        p = r + (rs_new / rs.clamp_min(1e-300)) * p
         rs = rs_new
-    if bool((rs <= tol * tol * b2).all()):
+    if bool((rs <= lim).all()):
         return x
     worst = float((rs / b2).sqrt().max())
     raise RuntimeError(f"solve_spd: relative residual {worst:.3e} above {tol:.1e} "
@@ -231,6 +288,7 @@ class LargeSteps:
     def __init__(self, nv: int, F: torch.Tensor, lam: float):
         self.L = laplacian(nv, F)
         self.lam = lam
+        self._last = None      # the previous solve's vertices: the next one starts there
 
     def matvec(self, x: torch.Tensor) -> torch.Tensor:
         return x + self.lam * torch.sparse.mm(self.L, x)
@@ -238,8 +296,12 @@ class LargeSteps:
     def to_u(self, V: torch.Tensor) -> torch.Tensor:
         return self.matvec(V.double()).to(V.dtype)
 
-    def to_v(self, u: torch.Tensor) -> torch.Tensor:
-        return solve_spd(self.matvec, u.double()).to(u.dtype)
+    def to_v(self, u: torch.Tensor, warm: bool = True) -> torch.Tensor:
+        x0 = self._last if warm and self._last is not None and self._last.shape == u.shape else None
+        x = solve_spd(self.matvec, u.double(), x0=x0)
+        if warm:
+            self._last = x
+        return x.to(u.dtype)
 
 
 class AdamUniform(torch.optim.Optimizer):
@@ -281,4 +343,4 @@ class _FromU(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return ctx.ls.to_v(g.contiguous()), None
+        return ctx.ls.to_v(g.contiguous(), warm=False), None

@@ -39,9 +39,10 @@ def test_ior_recovery_with_adam():
 
 
 def test_vertex_steps_with_adam_uniform_reduce_the_loss():
-    """The vertices of a radially perturbed sphere, optimised through the
-    tracer's vertex gradient with AdamUniform on the Laplacian
-    reparameterisation, move toward the target: the image loss falls."""
+    """The vertices of a sphere shrunk by 3 %, optimised through the tracer's
+    vertex gradient with AdamUniform on the Laplacian reparameterisation (lambda
+    20) from four views, move to the target: the colour loss falls 10x and the
+    vertex error to under 40 % of its start (0.76 -> 0.15 measured)."""
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
     dev = torch.device("cuda:0")
@@ -51,18 +52,52 @@ def test_vertex_steps_with_adam_uniform_reduce_the_loss():
     env = B.Env(torch.from_numpy(wl.env).to(dev))
     sigma = torch.tensor(wl.sigma, dtype=torch.float32, device=dev)
     ior = torch.tensor([wl.ior], dtype=torch.float32, device=dev)
-    tr = A.Tracer(F, env, wl.cameras, max_depth=wl.max_depth)
+    # one view sees a shrunk sphere mostly through its silhouette, which the
+    # interior derivatives do not move; four views constrain the shape
+    cams = [synth.look_at_camera(e, 64, 64) for e in synth.views_on_sphere(4, 3.0, seed=7)]
+    tr = A.Tracer(F, env, cams, max_depth=wl.max_depth)
     with torch.no_grad():
         gt = A.render(V0, ior, sigma, tr).clone()
     V = (V0 * 0.97).clone().requires_grad_(True)
-    trainer = T.Trainer(tr, V, ior, sigma=sigma, large_steps=4.0, lr_mesh=4e-3)
+    trainer = T.Trainer(tr, V, ior, sigma=sigma, large_steps=20.0, lr_mesh=2e-2)
     first = trainer.step(gt)["color"]
     errs = [float((V0 * 0.97 - V0).norm())]
-    for _ in range(40):
+    for _ in range(60):
         last = trainer.step(gt)["color"]
         # trainer.V is the mesh after the step's update
         errs.append(float((trainer.V.detach() - V0).norm()))
     print("colour loss", first, "->", last, "vertex error", errs[0], "->", errs[-1],
           "min", min(errs), flush=True)
-    assert last < 0.5 * first
-    assert errs[-1] < 0.8 * errs[0]
+    assert last < 0.1 * first
+    assert errs[-1] < 0.4 * errs[0]
+
+
+def test_mask_term_moves_the_outline():
+    """The periodic mask term alone (L_mask with the outline gradient) pulls a
+    sphere shrunk by 5 % back to its silhouettes in four views: the mask loss
+    falls 5x and the vertex error to under half of its start."""
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    dev = torch.device("cuda:0")
+    wl = synth.icosphere_scene(sigma=(0.5, 0.2, 0.1), res=64)
+    V0 = torch.from_numpy(wl.V.astype(np.float32)).to(dev)
+    F = torch.from_numpy(wl.F).to(dev)
+    env = B.Env(torch.from_numpy(wl.env).to(dev))
+    sigma = torch.tensor(wl.sigma, dtype=torch.float32, device=dev)
+    ior = torch.tensor([wl.ior], dtype=torch.float32, device=dev)
+    cams = [synth.look_at_camera(e, 64, 64) for e in synth.views_on_sphere(4, 3.0, seed=7)]
+    tr = A.Tracer(F, env, cams, max_depth=wl.max_depth)
+    with torch.no_grad():
+        gt = A.render(V0, ior, sigma, tr).clone()
+        gt_mask = A.render_mask(V0, tr).clone()
+    V = (V0 * 0.95).clone().requires_grad_(True)
+    trainer = T.Trainer(tr, V, ior, sigma=sigma, l_color=0.0, l_mask=1.0, period=1,
+                        large_steps=20.0, lr_mesh=2e-2)
+    first = trainer.step(gt, gt_mask)["mask"]
+    errs = [float((V0 * 0.95 - V0).norm())]
+    for _ in range(40):
+        last = trainer.step(gt, gt_mask)["mask"]
+        errs.append(float((trainer.V.detach() - V0).norm()))
+    print("mask loss", first, "->", last, "vertex error", errs[0], "->", errs[-1], flush=True)
+    assert last < 0.2 * first
+    assert errs[-1] < 0.5 * errs[0]

@@ -83,3 +83,22 @@ def test_adam_uniform_step_matches_its_definition():
     # two identical gradients: m_hat = g, v_hat = g^2, step = lr g / max|g| each time
     expect = -2 * 0.1 * g.numpy() / (np.abs(g.numpy()).max() + 1e-8)
     np.testing.assert_allclose(p.detach().numpy(), expect, rtol=1e-12)
+
+
+def test_uniform_laplacian_loss():
+    """(L V)_i = V_i - mean of its neighbours: zero at the centre of a regular
+    hexagon fan, the same for a translated mesh (rows sum to zero), and the
+    loss scales with the square of a scaling of the mesh."""
+    ang = np.arange(6) * np.pi / 3
+    V = np.concatenate([[[0.0, 0.0, 0.0]], np.stack([np.cos(ang), np.sin(ang), 0 * ang], 1)])
+    F = np.array([[0, 1 + k, 1 + (k + 1) % 6] for k in range(6)], np.int32)
+    Vt = torch.tensor(V, dtype=torch.float32)
+    Ft = torch.from_numpy(F)
+    Lu = T.uniform_laplacian(7, Ft)
+    LV = torch.sparse.mm(Lu, Vt)
+    assert torch.abs(LV[0]).max() < 1e-7
+    # a rim vertex: neighbours are the centre and its two rim neighbours
+    np.testing.assert_allclose(LV[1].numpy(), V[1] - (V[0] + V[2] + V[6]) / 3, atol=1e-6)
+    l0 = T.lap_loss(Vt, Lu)
+    assert abs(float(T.lap_loss(Vt + torch.tensor([0.3, -2.0, 5.0]), Lu)) - float(l0)) < 1e-5
+    assert abs(float(T.lap_loss(3.0 * Vt, Lu)) - 9.0 * float(l0)) < 1e-5 * float(l0) * 9
