@@ -137,7 +137,17 @@ dt_status dt_bvh_vertex_normals(const void* bvh, int32_t nv, int32_t nf, float* 
  * first.  Other shapes return DT_ERR_UNSUPPORTED.  d_texels (EQUIRECT only;
  * device [height][width][3], may be NULL): dt_trace_backward overwrites it
  * with dLoss/dtexel, from every ray that leaves the object (and, with
- * terminal_env, every ray stopped at the depth cap). */
+ * terminal_env, every ray stopped at the depth cap).  d_weights, d_biases
+ * (MLP only; device float32 in the layout of weights and biases, both or
+ * neither): dt_trace_backward overwrites them with dLoss/d(weights, biases)
+ * of the network (the environment field's parameters, optimised with the
+ * mesh, Sec. 3.1 "Environment Initialization" and Sec. 3.3 "Optimization"),
+ * summed over every ray that leaves the object, with the ReLU pattern of
+ * each lookup held fixed; supported for hidden width 64 (otherwise
+ * DT_ERR_UNSUPPORTED, nothing queued).  Each entry is a sum of per-block
+ * partial sums added in a fixed order, but which rays a block sums follows
+ * the order of each generation's miss list, built with atomics, so the last
+ * bits vary from run to run. */
 typedef struct {
   int32_t kind;
   int32_t width, height;
@@ -146,9 +156,15 @@ typedef struct {
   const uint16_t* weights;
   const float* biases;
   float* d_texels;
+  float* d_weights;
+  float* d_biases;
 } dt_env;
 
-/* rgb[i] = E(dirs[i]) for n directions (dirs, rgb: device [n][3]). */
+/* The environment seen by rays that leave the scene (the radiance a ray
+ * gathers when it meets no surface, Sec. 3.3 "Recursive Ray Tracing"; the
+ * environment is fitted before the object, Sec. 3.1 "Environment
+ * Initialization").  rgb[i] = E(dirs[i]) for n directions (dirs, rgb:
+ * device [n][3]). */
 dt_status dt_env_query(const dt_env* env, const float* dirs, int64_t n, float* rgb,
                        void* stream);
 
@@ -179,6 +195,42 @@ typedef struct {
   float* d_mu;         /* [nz][ny][nx][3] or NULL */
 } dt_absorption;
 
+/* Volumetric environment field outside the object: the exterior half of the
+ * split of radiance into samples inside and outside the object (Sec. 3.3,
+ * "Recursive Ray Tracing"), held as a coarse dense grid plus three planes
+ * (the radiance-field representation of Sec. 3.1 "Environment
+ * Initialization").  Inside the box [lo, hi] the feature of a point x
+ * (4 channels) is the trilinear interpolant of the grid (node (i, j, k) at
+ * lo + (i/(nx-1), j/(ny-1), k/(nz-1)) (hi - lo), value
+ * grid[((k*ny + j)*nx + i)*4 + ch]) plus the bilinear interpolants of three
+ * planes of res x res nodes, plane 0 over (x, y), 1 over (x, z), 2 over
+ * (y, z), node (i, j) (i along the plane's first axis) at
+ * planes[((p*res + j)*res + i)*4 + ch]; coordinates are clamped into the
+ * box.  Channel 0 gives the density softplus(f0), channels 1-3 the colour.
+ * Every exterior segment (camera ray to its first hit, a refracted or
+ * reflected ray leaving the object to its next hit or to infinity) is clipped
+ * to the box and sampled at the midpoints of S = samples equal steps h:
+ * a_k = exp(-softplus(f0(x_k)) h), T_0 = 1, T_{k+1} = T_k a_k, emission
+ * sum_k T_k (1 - a_k) c(x_k); the segment adds its emission and passes T_S
+ * of the radiance beyond it.  Rays leaving the box see the environment map.
+ * grid, planes: device float32 owned by the caller; d_grid, d_planes (both
+ * or neither) receive dLoss/d(grid, planes) from dt_trace_backward, which
+ * overwrites them (float atomics: the last bits vary from run to run).
+ * Limits: 2 <= nx, ny, nz, res <= 1024, 1 <= samples <= 256, hi > lo per
+ * axis, and the environment is an equirect map; otherwise the calls that
+ * take the scene return DT_ERR_INVALID_ARGUMENT (DT_ERR_UNSUPPORTED for an
+ * MLP environment). */
+typedef struct {
+  const float* grid;    /* [nz][ny][nx][4] */
+  int32_t nx, ny, nz;
+  const float* planes;  /* [3][res][res][4] */
+  int32_t res;
+  int32_t samples;
+  float lo[3], hi[3];
+  float* d_grid;        /* [nz][ny][nx][4] or NULL */
+  float* d_planes;      /* [3][res][res][4] or NULL */
+} dt_field;
+
 typedef struct {
   const float* V;      /* [nv][3] */
   int32_t nv;
@@ -189,6 +241,7 @@ typedef struct {
   const float* sigma;  /* [3]  RGB absorption per unit length */
   const dt_env* env;   /* HOST struct describing device data */
   const dt_absorption* absorb;  /* HOST struct or NULL: the constant rate sigma */
+  const dt_field* field;        /* HOST struct or NULL: empty exterior */
 } dt_scene;
 
 /* Optional kernel timing (HOST struct of caller-created hipEvent_t handles):
@@ -246,7 +299,12 @@ typedef struct {
 dt_status dt_trace_bytes(const dt_trace_params* p, int64_t n_rays, int32_t nv, int32_t nf,
                          size_t* ws_bytes, size_t* tape_bytes);
 
-/* Forward render.  rgb [npix][3] (required), wtrunc [npix][3] (optional:
+/* Forward render: the recursive tracing procedure of Sec. 3.3 ("Recursive
+ * Ray Tracing") over generations of rays - closest hit (Sec. 3.3
+ * "Differentiable Mesh Intersection"), the shading normal of Eq. 12-13,
+ * reflection and refraction directions (Eq. 3-6), Fresnel weights (Eq. 7-8),
+ * total internal reflection, the attenuation of Eq. 11 on interior segments,
+ * the environment at misses, the depth cap.  rgb [npix][3] (required), wtrunc [npix][3] (optional:
  * accumulated weight of truncated rays), flags [npix] (optional), path_sig
  * [npix] (optional: order-independent signature of each pixel's discrete
  * path, the sum mod 2^64 over its ray segments of SplitMix64's output
@@ -261,7 +319,11 @@ dt_status dt_trace_forward(const dt_scene* sc, const dt_rays* rays, const dt_tra
                            int64_t* stats, void* tape, size_t tape_bytes, void* ws,
                            size_t ws_bytes, void* stream);
 
-/* Backward: given dLoss/drgb [npix][3], accumulate nothing and overwrite
+/* Backward: the reverse-mode derivative of the forward render (the
+ * differentiable tracer of Sec. 3.3, "Differentiable Mesh Intersection" and
+ * "Recursive Ray Tracing": through the hit distance and barycentrics, the
+ * normals of Eq. 12-13, the directions of Eq. 3-6, the weights of Eq. 7-8 and
+ * the attenuation of Eq. 11).  Given dLoss/drgb [npix][3], accumulate nothing and overwrite
  * dV [nv][3], d_ior [1], d_sigma [3] with dLoss/d(V, ior, sigma); with an
  * absorption grid, also its d_mu (when not NULL; d_sigma is then 0), and for
  * an equirect environment with d_texels set, dLoss/dtexel.  The gradients are
@@ -275,6 +337,46 @@ dt_status dt_trace_backward(const dt_scene* sc, const dt_rays* rays, const dt_tr
                             const float* grad_rgb, const void* tape, size_t tape_bytes,
                             float* dV, float* d_ior, float* d_sigma, void* ws, size_t ws_bytes,
                             void* stream);
+
+/* ---------------------------------------------------------- silhouette */
+
+/* The silhouette (mask) term: each pixel's coverage by the object and the
+ * gradient of a loss on it with respect to the vertices through the motion
+ * of the object's outline - the visibility derivative the tracer's interior
+ * derivatives do not carry (the paper's mask loss: Sec. 3.1 "Mask-based
+ * Geometry Initialization"; the appendix on the ray tracer's mesh
+ * regularization keeps it as a periodic term).
+ *
+ * The mask M_p of pixel p is the fraction of its unit square (pixel (x, y)
+ * covers [x, x+1) x [y, y+1) in continuous image coordinates, row 0 at the
+ * top) covered by the object's projection.  dt_mask_forward writes its value
+ * at the pixel centre (1 where the centre's camera ray meets the mesh at
+ * t > t_eps, else 0).  dt_mask_backward writes dLoss/dV for dLoss/dM given
+ * per pixel: the boundary integral of the outline's normal velocity over the
+ * outline inside each pixel, weighted by the pixel's dLoss/dM.  The outline
+ * is made of silhouette edges (an edge whose two faces face opposite ways
+ * as seen from the eye, or an edge with one face) at points whose camera
+ * line meets no other triangle.  The integral is a fixed quadrature: an
+ * edge whose projection is l pixels long gets n = max(1, ceil(rho l)) points
+ * at the midpoints t_k = (k + 1/2)/n of its 3D parameter (from its lower to
+ * its higher vertex index), weight |dx/dt| / n, each credited to the pixel
+ * containing its projection; a point moves with its two vertices with
+ * weights 1 - t_k and t_k.  The error against the exact integral falls like
+ * 1/rho per pixel and 1/rho^2 summed over the image.
+ *
+ * rays: CAMERAS only, 1..DT_MASK_MAX_CAMERAS per call; mask, grad_mask:
+ * device [n_pixels].  sc: V, F, nv, nf and bvh are used (env, ior, sigma and
+ * absorb are not).  dV [nv][3] is overwritten (float atomic sums, order
+ * varies run to run).  counts: device uint64 [3] or NULL: outline points in
+ * an image whose pixel has a nonzero dLoss/dM, of those the visible ones,
+ * and traversal stack overflows (such a point is treated as hidden).  ws:
+ * dt_mask_bytes long (the edge list). */
+#define DT_MASK_MAX_CAMERAS 16
+dt_status dt_mask_bytes(int32_t nv, int32_t nf, size_t* ws_bytes);
+dt_status dt_mask_forward(const dt_scene* sc, const dt_rays* rays, float t_eps, float* mask,
+                          void* stream);
+dt_status dt_mask_backward(const dt_scene* sc, const dt_rays* rays, const float* grad_mask, float rho,
+                           float* dV, uint64_t* counts, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------- serving */
 
@@ -316,16 +418,26 @@ dt_status dt_serve_bytes(int64_t queue_capacity, size_t* ws_bytes);
 dt_status dt_serve_reset(void* ws, size_t ws_bytes, int64_t queue_capacity, void* stream);
 /* One step.  scenes, envs, admits: HOST arrays (equirect or MLP environments;
  * the misses lit by an MLP environment are listed and evaluated on the matrix
- * cores after the trace, one environment at a time);
- * pixels: device pool [n_pixels][3] (an admitted request's image is cleared by
- * its admitting step, then accumulated into); slot_live: device
- * [DT_SERVE_MAX_SLOTS], overwritten with each slot's live rays after the step;
- * stats: device int64 [3] or NULL: rays traced since reset, rays dropped since
- * reset (queue full), live rays.  step: 0, 1, 2, ... since the reset (selects
- * the queue buffer). */
+ * cores after the trace, one environment at a time); they reach the device as
+ * a kernel argument, so the call queues no host-to-device copy and returns
+ * without waiting for the device.
+ * pixels: device pool [n_pixels][3]; flags: device [n_pixels] (DT_FLAG_* of
+ * each pixel's ray tree, as dt_trace_forward's) or NULL; path_sig: device
+ * [n_pixels] (dt_trace_forward's path signature of each pixel) or NULL.  An
+ * admitted request's pixel range in all three is cleared by its admitting
+ * step, then accumulated into.
+ * slot_live: device [DT_SERVE_MAX_SLOTS], overwritten with each slot's live
+ * rays after the step.  slot_dropped: device [DT_SERVE_MAX_SLOTS], each
+ * slot's rays lost to a full queue since the slot's request was admitted
+ * (cleared by the admitting step): a request that finishes with a nonzero
+ * count has an incomplete image, and its pixels carry DT_FLAG_OVERFLOW where
+ * flags is given.  stats: device int64 [3] or NULL: rays traced since reset,
+ * rays dropped since reset, live rays.  step: 0, 1, 2, ... since the reset
+ * (selects the queue buffer). */
 dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scenes, const dt_env* envs,
                         int32_t n_envs, const dt_serve_admit* admits, int32_t n_admits,
-                        int64_t step, float* pixels, int64_t n_pixels, uint32_t* slot_live,
+                        int64_t step, float* pixels, int32_t* flags, uint64_t* path_sig,
+                        int64_t n_pixels, uint32_t* slot_live, uint32_t* slot_dropped,
                         int64_t* stats, int64_t queue_capacity, float t_eps, void* ws,
                         size_t ws_bytes, void* stream);
 

@@ -13,6 +13,7 @@ import ctypes as C
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,7 +38,8 @@ class _Env(C.Structure):
     _fields_ = [("kind", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
                 ("texels", C.c_void_p), ("n_freq", C.c_int32), ("n_layers", C.c_int32),
                 ("hidden", C.c_int32), ("in_pad", C.c_int32), ("weights", C.c_void_p),
-                ("biases", C.c_void_p), ("d_texels", C.c_void_p)]
+                ("biases", C.c_void_p), ("d_texels", C.c_void_p), ("d_weights", C.c_void_p),
+                ("d_biases", C.c_void_p)]
 
 
 class _Absorption(C.Structure):
@@ -46,10 +48,18 @@ class _Absorption(C.Structure):
                 ("d_mu", C.c_void_p)]
 
 
+class _Field(C.Structure):
+    _fields_ = [("grid", C.c_void_p), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("planes", C.c_void_p), ("res", C.c_int32), ("samples", C.c_int32),
+                ("lo", C.c_float * 3), ("hi", C.c_float * 3), ("d_grid", C.c_void_p),
+                ("d_planes", C.c_void_p)]
+
+
 class _Scene(C.Structure):
     _fields_ = [("V", C.c_void_p), ("nv", C.c_int32), ("F", C.c_void_p), ("nf", C.c_int32),
                 ("bvh", C.c_void_p), ("ior", C.c_void_p), ("sigma", C.c_void_p),
-                ("env", C.POINTER(_Env)), ("absorb", C.POINTER(_Absorption))]
+                ("env", C.POINTER(_Env)), ("absorb", C.POINTER(_Absorption)),
+                ("field", C.POINTER(_Field))]
 
 
 class _Timing(C.Structure):
@@ -77,7 +87,8 @@ class _Rays(C.Structure):
 _lib = None
 EXPORTS = ["dt_bvh_bytes", "dt_build_bvh", "dt_build_bvh_noalloc", "dt_bvh_vertex_normals", "dt_env_query",
            "dt_env_query_backward", "dt_trace_bytes", "dt_trace_forward", "dt_trace_backward",
-           "dt_intersect", "dt_status_string", "dt_last_error"]
+           "dt_intersect", "dt_mask_bytes", "dt_mask_forward", "dt_mask_backward",
+           "dt_status_string", "dt_last_error"]
 
 
 def load(path: str = LIB_PATH):
@@ -102,6 +113,10 @@ def load(path: str = LIB_PATH):
     L.dt_trace_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.POINTER(_Params), vp, vp,
                                     C.c_size_t, vp, vp, vp, vp, C.c_size_t, vp]
     L.dt_intersect.argtypes = [C.POINTER(_Scene), vp, vp, vp, i64, C.c_float, i32, vp, vp, vp, vp]
+    L.dt_mask_bytes.argtypes = [i32, i32, sz]
+    L.dt_mask_forward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.c_float, vp, vp]
+    L.dt_mask_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), vp, C.c_float, vp, vp, vp,
+                                   C.c_size_t, vp]
     L.dt_status_string.argtypes = [i32]
     L.dt_status_string.restype = C.c_char_p
     L.dt_last_error.restype = C.c_char_p
@@ -207,20 +222,41 @@ class Env:
         self.s = s
 
     @staticmethod
-    def mlp(Ws, Bs, n_freq: int, device) -> "Env":
+    def mlp(Ws, Bs, n_freq: int, device, want_grad: bool = False) -> "Env":
         """Ws: per-layer [out, in] weights (bf16-representable), Bs: biases;
-        hidden layers of equal width, last layer [3, width], first [width, 64]."""
+        hidden layers of equal width, last layer [3, width], first [width, 64].
+        want_grad: the backward also writes d_weights / d_biases (float32,
+        flat in the same layout; `split_grad` returns them per layer)."""
         e = Env()
         w = torch.cat([torch.as_tensor(x, dtype=torch.float32).reshape(-1) for x in Ws])
         e.weights = w.to(torch.bfloat16).view(torch.int16).to(device).contiguous()
         e.biases = torch.cat([torch.as_tensor(x, dtype=torch.float32).reshape(-1)
                               for x in Bs]).to(device).contiguous()
+        e.shapes = [(tuple(np.shape(x)), tuple(np.shape(y))) for x, y in zip(Ws, Bs)]
         s = e.s
         s.kind = ENV_MLP
         s.n_freq, s.n_layers = int(n_freq), len(Ws) - 1
         s.hidden, s.in_pad = int(Ws[0].shape[0]), int(Ws[0].shape[1])
         s.weights, s.biases = e.weights.data_ptr(), e.biases.data_ptr()
+        if want_grad:
+            e.d_weights = torch.zeros(e.weights.numel(), dtype=torch.float32, device=device)
+            e.d_biases = torch.zeros_like(e.biases)
+            s.d_weights, s.d_biases = e.d_weights.data_ptr(), e.d_biases.data_ptr()
         return e
+
+    def split_grad(self):
+        """(list of weight gradients [out, in], list of bias gradients) as
+        numpy arrays, from the last backward."""
+        w = self.d_weights.cpu().numpy()
+        b = self.d_biases.cpu().numpy()
+        Wg, Bg, kw, kb = [], [], 0, 0
+        for ws, bs in self.shapes:
+            nw, nb = int(np.prod(ws)), int(np.prod(bs))
+            Wg.append(w[kw:kw + nw].reshape(ws))
+            Bg.append(b[kb:kb + nb].reshape(bs))
+            kw += nw
+            kb += nb
+        return Wg, Bg
 
 
 def dt_env_query(env: Env, dirs: torch.Tensor) -> torch.Tensor:
@@ -354,14 +390,43 @@ class Absorption:
         self.s.d_mu = self.d_mu.data_ptr() if self.d_mu is not None else None
 
 
+class Field:
+    """Volumetric environment field outside the object: device float32 grid
+    [nz, ny, nx, 4] plus three planes [3, res, res, 4] over the box [lo, hi]
+    (channel 0 -> density by softplus, 1-3 -> colour), `samples` midpoint
+    samples per exterior segment.  d_grid / d_planes (same shapes) receive
+    dLoss/d(grid, planes) from dt_trace_backward."""
+
+    def __init__(self, grid: torch.Tensor, planes: torch.Tensor, lo, hi, samples: int,
+                 want_grad: bool = True):
+        _dev_check(grid, planes)
+        assert grid.dtype == torch.float32 and grid.dim() == 4 and grid.shape[3] == 4
+        assert planes.dtype == torch.float32 and planes.dim() == 4 and planes.shape[0] == 3
+        assert planes.shape[1] == planes.shape[2] and planes.shape[3] == 4
+        self.grid, self.planes = grid.contiguous(), planes.contiguous()
+        self.lo, self.hi, self.samples = tuple(map(float, lo)), tuple(map(float, hi)), int(samples)
+        self.d_grid = torch.zeros_like(self.grid) if want_grad else None
+        self.d_planes = torch.zeros_like(self.planes) if want_grad else None
+        nz, ny, nx, _ = self.grid.shape
+        self.s = _Field()
+        self.s.grid, self.s.nx, self.s.ny, self.s.nz = self.grid.data_ptr(), nx, ny, nz
+        self.s.planes, self.s.res, self.s.samples = self.planes.data_ptr(), self.planes.shape[1], self.samples
+        for k in range(3):
+            self.s.lo[k], self.s.hi[k] = self.lo[k], self.hi[k]
+        self.s.d_grid = self.d_grid.data_ptr() if want_grad else None
+        self.s.d_planes = self.d_planes.data_ptr() if want_grad else None
+
+
 class Scene:
     """Mesh + device IoR [1] + device sigma [3] + environment (+ optional
-    absorption grid, which replaces sigma on interior segments)."""
+    absorption grid, which replaces sigma on interior segments, + optional
+    volumetric field sampled along exterior segments)."""
 
     def __init__(self, mesh: Mesh, ior: torch.Tensor, sigma: torch.Tensor, env: Env,
-                 absorb: Absorption | None = None):
+                 absorb: Absorption | None = None, field: Field | None = None):
         _dev_check(ior, sigma)
         self.mesh, self.ior, self.sigma, self.env, self.absorb = mesh, ior, sigma, env, absorb
+        self.field = field
 
     def c(self) -> _Scene:
         s = _Scene()
@@ -370,6 +435,7 @@ class Scene:
         s.bvh, s.ior, s.sigma = m.blob.data_ptr(), self.ior.data_ptr(), self.sigma.data_ptr()
         s.env = C.pointer(self.env.s)
         s.absorb = C.pointer(self.absorb.s) if self.absorb is not None else None
+        s.field = C.pointer(self.field.s) if self.field is not None else None
         return s
 
 
@@ -441,3 +507,41 @@ def dt_intersect(scene: Scene, o, d, skip=None, t_eps: float = 1e-5, brute_force
     _check(load().dt_intersect(C.byref(sc), _ptr(o), _ptr(d), _ptr(skip), n, t_eps,
                                int(brute_force), _ptr(tri), _ptr(t), _ptr(b), _stream(dev)))
     return tri, t, b
+
+
+# ------------------------------------------------------------------ silhouette (mask) term
+def _mesh_scene(mesh: "Mesh") -> _Scene:
+    s = _Scene()
+    s.V, s.nv, s.F, s.nf = mesh.V.data_ptr(), mesh.nv, mesh.F.data_ptr(), mesh.nf
+    s.bvh = mesh.blob.data_ptr()
+    return s
+
+
+def dt_mask_forward(mesh: "Mesh", rays: "Rays", t_eps: float = 1e-5) -> torch.Tensor:
+    """Centre-sample coverage [n_pixels] of the cameras in `rays` (1 where the
+    pixel centre's camera ray meets the mesh)."""
+    out = torch.empty(rays.n_pixels, dtype=torch.float32, device=mesh.V.device)
+    _check(load().dt_mask_forward(C.byref(_mesh_scene(mesh)), C.byref(rays.s), C.c_float(t_eps),
+                                  _ptr(out), _stream(mesh.V.device)))
+    return out
+
+
+class MaskGrad:
+    """Workspace for dt_mask_backward on one mesh topology."""
+
+    def __init__(self, mesh: "Mesh"):
+        n = C.c_size_t()
+        _check(load().dt_mask_bytes(mesh.nv, mesh.nf, C.byref(n)))
+        self.ws = _bytes(n.value, mesh.V.device)
+        self.counts = torch.zeros(3, dtype=torch.int64, device=mesh.V.device)
+
+    def __call__(self, mesh: "Mesh", rays: "Rays", grad_mask: torch.Tensor, rho: float = 2.0):
+        """dLoss/dV [nv, 3] through the motion of the outline, for dLoss/dM
+        given per pixel; self.counts then holds (outline points with a nonzero
+        pixel gradient, visible ones, stack overflows)."""
+        _dev_check(grad_mask)
+        dV = torch.empty_like(mesh.V)
+        _check(load().dt_mask_backward(C.byref(_mesh_scene(mesh)), C.byref(rays.s), _ptr(grad_mask),
+                                       C.c_float(rho), _ptr(dV), _ptr(self.counts), _ptr(self.ws),
+                                       self.ws.numel(), _stream(mesh.V.device)))
+        return dV

@@ -4,6 +4,7 @@
 #pragma once
 
 #include "dt_internal.h"
+#include "dt_field.h"
 
 #define DT_PI 3.14159265358979323846f
 
@@ -15,6 +16,8 @@ struct EnvDev {
   int n_freq, n_layers, hidden, in_pad;
   const uint16_t* w;
   const float* b;
+  float* d_w;    // MLP: dLoss/d(weights, biases) targets of the backward (may be NULL)
+  float* d_b;
 };
 
 // Spatially varying absorption rate: trilinear RGB grid (mu == NULL: the
@@ -35,6 +38,7 @@ struct SceneDev {
   const float* sigma;
   EnvDev env;
   AbsorbDev ab;
+  FieldDev fd;  // volumetric environment field outside the object (fd.grid NULL: none)
   int max_depth, terminal_env;
   float t_eps;
 };
@@ -604,6 +608,7 @@ struct Shade {
   float sin2t, cos_t;
   float rs, rp, R, T;
   v3 A;        // attenuation over the segment just travelled
+  v3 Cem;      // emission of the field over that segment (exterior segments, FIELD)
   v3 ur, ut;   // unnormalised child directions
   v3 dr, dt;   // unit child directions
   uint32_t code;
@@ -612,9 +617,10 @@ struct Shade {
 // Paper Sec. 3.2-3.3.  `code_in` (when nonzero) supplies the discrete
 // decisions recorded by the forward pass so that every later recomputation
 // takes the same branches.
-// GRID: the scene carries an absorption grid (a separate instantiation, so the
-// constant-rate kernels keep their register budget)
-template <bool GRID = false>
+// GRID: the scene carries an absorption grid; FIELD: a volumetric
+// environment field (separate instantiations, so the plain kernels keep their
+// register budget)
+template <bool GRID = false, bool FIELD = false>
 __device__ __forceinline__ Shade shade(const SceneDev& sc, const HitGeo& g, v3 o, v3 d, float t,
                                        float b1, float b2, uint32_t code_in) {
   Shade s;
@@ -638,8 +644,16 @@ __device__ __forceinline__ Shade shade(const SceneDev& sc, const HitGeo& g, v3 o
   s.eta_i = entering ? 1.f : s.eta;
   s.eta_t = entering ? s.eta : 1.f;
   s.eta_r = s.eta_t / s.eta_i;
+  s.Cem = mk3(0.f, 0.f, 0.f);
   if (entering) {
     s.A = mk3(1.f, 1.f, 1.f);
+    if constexpr (FIELD) {
+      // the exterior segment just travelled: its emission, and its
+      // transmittance attenuates everything beyond the hit
+      float T;
+      field_segment(sc.fd, o, d, t, false, s.Cem, T);
+      s.A = mk3(T, T, T);
+    }
   } else {
     if constexpr (GRID) {
       const v3 tau = absorb_tau(sc.ab, o, d, t);

@@ -5,6 +5,16 @@
 
 constexpr uint32_t RAY_INSIDE = 1u;  // ray flag: travelling inside the object
 
+// 64-bit mixer: the SplitMix64 output function (Steele, Lea and Flood,
+// OOPSLA 2014).  Summed over a pixel's segments it gives an order-independent
+// signature of the discrete path (generation, triangle or -1, TIR).
+__device__ __forceinline__ uint64_t path_mix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
 // One generation of rays, structure of arrays.
 struct Gen {
   float4 *o, *d, *w, *hit;  // origin+skip, dir+pixel, weight+flags, (t, tri, b1, b2)
@@ -114,3 +124,14 @@ dt_status mlp_trace_forward(const EnvDev& e, Gen q, const uint32_t* list, const 
 // adjoint: for the rays on the list, L = E(d), D = (dE/dd)^T (dLoss/dC * W), O = 0
 dt_status mlp_trace_backward(const EnvDev& e, Gen q, const uint32_t* list, const Counters* ctr,
                              int g, int64_t cap, const float* grad_rgb, Adj cur, hipStream_t s);
+// the same adjoint, also adding each block's share of dLoss/d(weights, biases)
+// into its row of part (rows of mlp_wgrad_params(e) floats, zeroed by the
+// caller before the first generation); 64-wide networks
+dt_status mlp_trace_backward_wgrad(const EnvDev& e, Gen q, const uint32_t* list, const Counters* ctr,
+                                   int g, const float* grad_rgb, Adj cur, float* part, hipStream_t s);
+// e.d_w / e.d_b = the rows of part summed in order
+dt_status mlp_wgrad_reduce(const EnvDev& e, const float* part, hipStream_t s);
+// parameters of a network (0 when the weight gradient is not supported), and
+// the scratch bytes the partial sums of the largest supported one need
+int64_t mlp_wgrad_params(const EnvDev& e);
+size_t mlp_wgrad_scratch_bytes();

@@ -225,15 +225,169 @@ __device__ __forceinline__ bf16x8 wfrag_t(const uint16_t* w, int col, int ld, in
   return cat8(x, y);
 }
 
+// ------------------------------------------------------------------ weight gradient
+// dLoss/dW_l = sum over rays of delta_l a_{l-1}^T and dLoss/db_l = sum of
+// delta_l, with delta_l the adjoint of layer l's pre-activation and a_{l-1}
+// its input (the encoding for l = 0).  The sum over rays is a matrix product
+// with the rays as the contraction axis, so it runs on the matrix cores too:
+// the 8 waves of a block stage their 16 rays' deltas (two bf16 parts, about
+// 17 bits) and inputs (hi and mid parts of the three-part split, 16 bits) for
+// one layer in LDS, feature-major with the 128 rays along a row, then every
+// wave adds the products of the tiles it owns into its accumulators
+// (16x16x32 products with K = 32 rays: hi*hi + hi*mid + lo*hi; bias tiles
+// multiply the deltas by a ones operand).  Tiles are dealt to the waves
+// round-robin, so each entry of the gradient belongs to one lane of the block;
+// at the end each block adds its accumulators into its own row of partial
+// sums, and a final pass sums the rows in order.  64-wide networks only (the
+// 128-wide network leaves no LDS for the staging).
+constexpr int WG_WAVES = 8;
+constexpr int WG_RAYS = 16 * WG_WAVES;      // rays staged per round
+constexpr int WG_LD = WG_RAYS + 8;          // staged row stride (bf16): rows start 16 B apart in bank order
+constexpr int WG_ROWS = 64;
+constexpr int WG_STAGE = 4 * WG_ROWS * WG_LD;  // delta hi, delta lo, input hi, input mid
+constexpr int WG_BLOCKS = 256;              // blocks of the weight-gradient backward (rows of partials)
+
+template <int NL>
+struct WgTiles {
+  // the backward visits the head (layer NL) first, then layers NL-1 .. 0;
+  // layer l has ob(l) 16-row output blocks times 4 16-column input blocks
+  // of weight tiles, then ob(l) bias tiles
+  static constexpr int ob(int l) { return l == NL ? 1 : 4; }
+  static constexpr int count(int l) { return ob(l) * 5; }
+  static constexpr int first(int l) {
+    int t = 0;
+    for (int k = NL; k > l; --k) t += count(k);
+    return t;
+  }
+  static constexpr int total = count(NL) + NL * count(0);
+  static constexpr int slots = (total + WG_WAVES - 1) / WG_WAVES;
+  // flat parameter layout (weights of every layer, then biases), 64 wide
+  static constexpr int64_t n_weights = 4096 * (int64_t)NL + 192;
+  static constexpr int64_t n_params = n_weights + 64 * (int64_t)NL + 3;
+};
+
+__device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {
+  return __builtin_bit_cast(bf16x8, *(const s16x8*)p);
+}
+
+// Stage layer L's deltas (rows 16 ob + 4 q + j, ob < ob(L), of this wave's
+// 16 rays) and inputs (rows 16 ib + 4 q + j, ib < 4), then accumulate the
+// tiles of layer L this wave owns over the block's 128 rays.  Called by every
+// wave of the block the same number of times (it holds two barriers).
+template <int NL>
+__device__ __forceinline__ void wg_stage(uint16_t* st, int L, const bf16x4* dh, const bf16x4* dl,
+                                         const bf16x4* ah, const bf16x4* am, f32x4* wacc, int wave) {
+  using T = WgTiles<NL>;
+  const int l = threadIdx.x & 63, q = l >> 4, r16 = l & 15;
+  uint16_t* Dh = st;
+  uint16_t* Dl = st + WG_ROWS * WG_LD;
+  uint16_t* Ah = st + 2 * WG_ROWS * WG_LD;
+  uint16_t* Am = st + 3 * WG_ROWS * WG_LD;
+  const int OB = T::ob(L);
+  const int col = 16 * wave + r16;
+#pragma unroll
+  for (int ob = 0; ob < 4; ++ob) {
+    if (ob >= OB) break;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Dh[(16 * ob + 4 * q + j) * WG_LD + col] = (uint16_t)dh[ob][j];
+      Dl[(16 * ob + 4 * q + j) * WG_LD + col] = (uint16_t)dl[ob][j];
+    }
+  }
+#pragma unroll
+  for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Ah[(16 * ib + 4 * q + j) * WG_LD + col] = (uint16_t)ah[ib][j];
+      Am[(16 * ib + 4 * q + j) * WG_LD + col] = (uint16_t)am[ib][j];
+    }
+  __syncthreads();
+  const int t0 = T::first(L);
+  bf16x8 ones;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) ones[k] = (__bf16)1.0f;
+#pragma unroll
+  for (int tl = 0; tl < 20; ++tl) {
+    if (tl >= T::count(L)) break;
+    const int t = t0 + tl;
+    if (t % WG_WAVES != wave) continue;
+    const bool bias = tl >= OB * 4;
+    const int ob = bias ? tl - OB * 4 : tl / 4;
+    const int ib = tl % 4;
+    f32x4 acc = wacc[t / WG_WAVES];
+#pragma unroll
+    for (int ks = 0; ks < WG_RAYS / 32; ++ks) {
+      const int c0 = 32 * ks + 8 * q;
+      const bf16x8 a_h = lds8(Dh + (16 * ob + r16) * WG_LD + c0);
+      const bf16x8 a_l = lds8(Dl + (16 * ob + r16) * WG_LD + c0);
+      if (bias) {
+        acc = mfma32(a_h, ones, acc);
+        acc = mfma32(a_l, ones, acc);
+      } else {
+        const bf16x8 b_h = lds8(Ah + (16 * ib + r16) * WG_LD + c0);
+        const bf16x8 b_m = lds8(Am + (16 * ib + r16) * WG_LD + c0);
+        acc = mfma32(a_h, b_h, acc);
+        acc = mfma32(a_h, b_m, acc);
+        acc = mfma32(a_l, b_h, acc);
+      }
+    }
+    wacc[t / WG_WAVES] = acc;
+  }
+  __syncthreads();
+}
+
+// Add this wave's tiles into the block's row of partial sums (each entry has
+// one owner lane in the block, so no atomics).  Weight (o, i) of layer 0 is
+// the caller's column enc_column(i); the head keeps rows o < 3.
+template <int NL>
+__device__ __forceinline__ void wg_flush(const f32x4* wacc, int wave, float* part, int n_freq) {
+  using T = WgTiles<NL>;
+  const int l = threadIdx.x & 63, q = l >> 4, r16 = l & 15;
+#pragma unroll
+  for (int t = 0; t < T::total; ++t) {
+    if (t % WG_WAVES != wave) continue;
+    int L = NL, tl = t;
+    while (tl >= T::count(L)) {
+      tl -= T::count(L);
+      --L;
+    }
+    const int OB = T::ob(L);
+    const bool bias = tl >= OB * 4;
+    const int ob = bias ? tl - OB * 4 : tl / 4;
+    const int ib = tl % 4;
+    const f32x4 acc = wacc[t / WG_WAVES];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = 16 * ob + 4 * q + j;
+      if (L == NL && o >= 3) continue;
+      int64_t k;
+      if (bias) {
+        if (r16 != 0) continue;
+        k = T::n_weights + 64 * (int64_t)L + o;
+      } else {
+        int i = 16 * ib + r16;
+        if (L == 0) {
+          i = enc_column(i, n_freq);
+          if (i < 0) continue;
+        }
+        k = 4096 * (int64_t)L + 64 * (int64_t)o + i;
+      }
+      part[k] += acc[j];
+    }
+  }
+}
+
 // One wave: lane l works on ray l % 16 (all four lane groups q = l / 16 carry
 // the same ray).  Returns E in lanes with q == 0; when GRAD, also returns
 // the direction gradient of dot(gbar, E) with respect to d (all lanes).
 // Activations live in 16-row blocks in the MFMA accumulator layout (lane
 // (q, r16) holds rows 4q + j of column r16); two consecutive blocks form the
 // B operand of one 16x16x32 product.
-template <int HID, int NL, bool GRAD>
+template <int HID, int NL, bool GRAD, bool WG = false>
 __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int n_freq, v3 d,
-                                       v3 gbar, v3* dbar) {
+                                       v3 gbar, v3* dbar, uint16_t* stage = nullptr,
+                                       f32x4* wacc = nullptr, int wave = 0) {
+  static_assert(!WG || (GRAD && HID == 64), "weight gradient: 64-wide backward only");
   using N = NetLds<HID, NL, GRAD>;
   const int l = threadIdx.x & 63, q = l >> 4, r16 = l & 15;
   constexpr int KB = HID / 16;
@@ -255,6 +409,7 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
     }
   bf16x4 act[NL][KB];     // hi parts of every hidden layer (their signs are the ReLU masks)
   bf16x4 mi[KB], lo[KB];  // mid and lo parts of the latest hidden layer
+  bf16x4 actm[WG ? NL : 1][KB];  // mid parts of every hidden layer (weight gradient)
   const float* B = sb;
   // first hidden layer, on the encoding
 #pragma unroll
@@ -275,6 +430,7 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
       act[0][ob][j] = p.h;
       mi[ob][j] = p.m;
       lo[ob][j] = p.l;
+      if constexpr (WG) actm[0][ob][j] = p.m;
     }
   }
   B += HID;
@@ -301,6 +457,7 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
         act[L][ob][j] = p.h;
         nmi[ob][j] = p.m;
         nlo[ob][j] = p.l;
+        if constexpr (WG) actm[WG ? L : 0][ob][j] = p.m;
       }
     }
 #pragma unroll
@@ -334,6 +491,7 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
       dl0[j] = p.l;
     }
   }
+  if constexpr (WG) wg_stage<NL>(stage, NL, &dh0, &dl0, act[NL - 1], actm[NL - 1], wacc, wave);
   // head: delta_hidden = W_head^T delta_out (a K = 16 product over the 16
   // padded head rows), masked by the last ReLU
   bf16x4 nh[KB], nl[KB];
@@ -355,6 +513,7 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
   // hidden layers NL-1 .. 1: delta_{L-1} = W_L^T delta_L, masked by relu'(layer L-1)
 #pragma unroll
   for (int L = NL - 1; L >= 1; --L) {
+    if constexpr (WG) wg_stage<NL>(stage, L, nh, nl, act[L - 1], actm[WG ? L - 1 : 0], wacc, wave);
     const uint16_t* WL = sw + N::WH + (L - 1) * HID * N::LDH;
     bf16x4 th[KB], tl[KB];
 #pragma unroll
@@ -383,6 +542,7 @@ __device__ __forceinline__ v3 mlp_wave(const uint16_t* sw, const float* sb, int 
       nl[ib] = tl[ib];
     }
   }
+  if constexpr (WG) wg_stage<NL>(stage, 0, nh, nl, xh, xm, wacc, wave);
   // first layer: delta_enc = W_0^T delta_0 (64 rows), then d enc / d u_q
   float gq = 0.f;
 #pragma unroll
@@ -527,6 +687,65 @@ __global__ void __launch_bounds__(mlp_threads<HID>()) k_mlp_trace_bwd(EnvDev e, 
 }
 #undef DT_MLP_PROLOGUE
 
+// The trace adjoint of k_mlp_trace_bwd for a 64-wide network, also summing the
+// weight and bias gradient: rounds of 128 listed rays per block (all waves
+// take part in every round; rays past the count carry a zero adjoint), the
+// block's sums added into part[blockIdx.x][...] at the end.
+template <int NL>
+__global__ void __launch_bounds__(16 * WG_RAYS / 4) k_mlp_trace_bwd_wg(EnvDev e, Gen q, const uint32_t* list,
+                                                               const Counters* ctr, int g,
+                                                               const float* grad_rgb, Adj cur,
+                                                               float* part) {
+  using N = NetLds<64, NL, true>;
+  using T = WgTiles<NL>;
+  __shared__ __align__(16) unsigned char net[N::BYTES];
+  __shared__ __align__(16) uint16_t stage[WG_STAGE];
+  uint16_t* sw = (uint16_t*)net;
+  float* sb = (float*)(net + N::BOFF);
+  load_net<64, NL, true>(e, sw, sb);
+  const int wave = threadIdx.x >> 6;
+  f32x4 wacc[T::slots];
+#pragma unroll
+  for (int k = 0; k < T::slots; ++k) wacc[k] = {0.f, 0.f, 0.f, 0.f};
+  const int64_t n = ctr->nmiss[g];
+  for (int64_t b0 = (int64_t)blockIdx.x * WG_RAYS; b0 < n; b0 += (int64_t)gridDim.x * WG_RAYS) {
+    int64_t item = b0 + 16 * wave + (threadIdx.x & 15);
+    bool valid = item < n;
+    uint32_t i = valid ? list[item] : 0u;
+    float4 d4 = valid ? q.d[i] : make_float4(0.f, 1.f, 0.f, 0.f);
+    v3 gb = mk3(0.f, 0.f, 0.f);
+    if (valid) {
+      float4 w4 = q.w[i];
+      int pix = __float_as_int(d4.w);
+      v3 gp = load3(grad_rgb + 3 * pix);
+      gb = mk3(gp.x * w4.x, gp.y * w4.y, gp.z * w4.z);
+    }
+    v3 db;
+    v3 E = mlp_wave<64, NL, true, true>(per_group(sw), sb, e.n_freq, xyz(d4), gb, &db, stage, wacc, wave);
+    if (valid && (threadIdx.x & 63) < 16) {
+      cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
+      cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      cur.D[i] = make_float4(db.x, db.y, db.z, 0.f);
+    }
+  }
+  wg_flush<NL>(wacc, wave, part + (size_t)blockIdx.x * T::n_params, e.n_freq);
+}
+
+// d_w[k] (k < n_weights) and d_b[k - n_weights]: the blocks' partial sums,
+// added in block order
+__global__ void k_mlp_wg_reduce(const float* part, int64_t n_params, int64_t n_weights, float* d_w,
+                                float* d_b) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_params;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < WG_BLOCKS; ++b) s += (double)part[(size_t)b * n_params + k];
+    if (k < n_weights)
+      d_w[k] = (float)s;
+    else
+      d_b[k - n_weights] = (float)s;
+  }
+}
+
 // dispatch over the supported (hidden width, hidden layers) shapes
 #define DT_MLP_SHAPES(X) X(64, 1) X(64, 2) X(64, 3) X(64, 4) X(128, 1) X(128, 2) X(128, 3) X(128, 4)
 
@@ -575,6 +794,38 @@ dt_status mlp_trace_forward(const EnvDev& e, Gen q, const uint32_t* list, const 
   DT_MLP_SHAPES(X)
 #undef X
   dt_set_error("environment MLP shape (hidden %d, layers %d) is not supported", e.hidden, e.n_layers);
+  return DT_ERR_UNSUPPORTED;
+}
+
+int64_t mlp_wgrad_params(const EnvDev& e) {
+  return e.hidden == 64 ? 4096 * (int64_t)e.n_layers + 192 + 64 * (int64_t)e.n_layers + 3 : 0;
+}
+
+size_t mlp_wgrad_scratch_bytes() {
+  return sizeof(float) * (size_t)WG_BLOCKS * (size_t)WgTiles<4>::n_params;
+}
+
+dt_status mlp_wgrad_reduce(const EnvDev& e, const float* part, hipStream_t s) {
+  const int64_t np = mlp_wgrad_params(e);
+  const int64_t nw = np - 64 * (int64_t)e.n_layers - 3;
+  hipLaunchKernelGGL(k_mlp_wg_reduce, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, part, np, nw,
+                     e.d_w, e.d_b);
+  DT_CHECK_LAUNCH();
+  return DT_OK;
+}
+
+dt_status mlp_trace_backward_wgrad(const EnvDev& e, Gen q, const uint32_t* list, const Counters* ctr,
+                                   int g, const float* grad_rgb, Adj cur, float* part, hipStream_t s) {
+#define X(L)                                                                                    \
+  if (e.hidden == 64 && e.n_layers == L) {                                                      \
+    hipLaunchKernelGGL(k_mlp_trace_bwd_wg<L>, dim3(WG_BLOCKS), dim3(16 * WG_RAYS / 4), 0, s, e, q, \
+                       list, ctr, g, grad_rgb, cur, part);                                      \
+    DT_CHECK_LAUNCH();                                                                          \
+    return DT_OK;                                                                               \
+  }
+  X(1) X(2) X(3) X(4)
+#undef X
+  dt_set_error("environment MLP weight gradient: hidden width 64 only (got %d)", e.hidden);
   return DT_ERR_UNSUPPORTED;
 }
 

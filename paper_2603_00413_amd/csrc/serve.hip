@@ -36,6 +36,30 @@ struct ServeTables {
   SceneDev sc[DT_SERVE_MAX_SCENES];
   EnvDev env[DT_SERVE_MAX_ENVS];
 };
+// the tables travel to the device as a kernel argument (k_set_tables), so a
+// step queues no copy from host memory and never waits for one
+static_assert(sizeof(ServeTables) <= 3584, "serving tables must fit a kernel argument");
+
+// Per-pixel outputs of a step (pool-sized; flags / sig may be NULL) and the
+// per-slot count of rays lost to a full queue.
+struct ServeOut {
+  float* pixels;
+  int32_t* flags;
+  unsigned long long* sig;
+  uint32_t* slot_dropped;
+};
+
+__device__ __forceinline__ void serve_flag(const ServeOut& out, int pix, int32_t f) {
+  if (out.flags && f) atomicOr(out.flags + pix, f);
+}
+
+// a ray of slot `slot` (pixel pix) was not written: the queue is full
+__device__ __forceinline__ void serve_drop(const ServeOut& out, uint32_t* dropped, uint32_t slot,
+                                           int pix) {
+  atomicAdd(dropped, 1u);
+  atomicAdd(out.slot_dropped + slot, 1u);
+  serve_flag(out, pix, DT_FLAG_OVERFLOW);
+}
 
 struct ServeState {
   Counters ctr;            // count[0] = live rays of the current queue
@@ -92,6 +116,13 @@ Gen serve_gen(char* W, const ServeLayout& L, int b) {
   return g;
 }
 
+__global__ void k_set_tables(ServeTables T, ServeTables* Td) {
+  // word-by-word copy of the argument into the workspace
+  const uint32_t* src = (const uint32_t*)&T;
+  uint32_t* dst = (uint32_t*)Td;
+  for (int k = threadIdx.x; k < (int)(sizeof(ServeTables) / 4); k += blockDim.x) dst[k] = src[k];
+}
+
 __global__ void k_serve_reset(ServeState* st, unsigned long long* p0, unsigned long long* p1,
                               int64_t np) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -111,21 +142,35 @@ __global__ void k_serve_reset(ServeState* st, unsigned long long* p0, unsigned l
 
 // camera rays of one admitted request, appended after the live rays
 __global__ void k_serve_raygen(Gen q, ServeState* st, int64_t prefix, CamDev c, uint32_t flags,
-                               int64_t cap) {
+                               int64_t cap, ServeOut out) {
   int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t n = (int64_t)c.W * c.H;
   if (r >= n) return;
   int64_t i = (int64_t)st->ctr.count[0] + prefix + r;
-  if (i >= cap) {
-    atomicAdd(&st->ctr.dropped, 1u);
-    return;
-  }
   int x, y;
   v3 d = camera_ray(c, r, x, y);
   int pix = (int)(c.pixel_offset + (int64_t)y * c.W + x);
+  if (i >= cap) {
+    serve_drop(out, &st->ctr.dropped, sf_slot(flags), pix);
+    return;
+  }
   q.o[i] = make_float4(c.eye[0], c.eye[1], c.eye[2], __int_as_float(-1));
   q.d[i] = make_float4(d.x, d.y, d.z, __int_as_float(pix));
   q.w[i] = make_float4(1.f, 1.f, 1.f, __int_as_float((int)flags));
+}
+
+// an admitted request's image, flags and signatures start at zero, and so
+// does its slot's drop count
+__global__ void k_serve_clear(ServeOut out, int64_t off, int64_t np, uint32_t slot) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < np;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    out.pixels[3 * (off + i)] = 0.f;
+    out.pixels[3 * (off + i) + 1] = 0.f;
+    out.pixels[3 * (off + i) + 2] = 0.f;
+    if (out.flags) out.flags[off + i] = 0;
+    if (out.sig) out.sig[off + i] = 0ull;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) out.slot_dropped[slot] = 0u;
 }
 
 __global__ void k_serve_admit_count(ServeState* st, int64_t added, int64_t cap) {
@@ -136,7 +181,7 @@ __global__ void k_serve_admit_count(ServeState* st, int64_t added, int64_t cap) 
 }
 
 __global__ void __launch_bounds__(TBS, 7) k_serve_trace(const ServeTables* T, Gen q, ServeState* st,
-                                                     unsigned long long* part, float* pixels,
+                                                     unsigned long long* part, ServeOut out,
                                                      uint2* ovf) {
   __shared__ uint2 stk[DT_STACK_LDS * TBS];
   __shared__ LeafQueue lq;
@@ -175,22 +220,28 @@ __global__ void __launch_bounds__(TBS, 7) k_serve_trace(const ServeTables* T, Ge
       int pix = __float_as_int(d4.w);
       q.hit[i] = make_float4(h.t, __int_as_float(h.tri), h.b1, h.b2);
       uint32_t code = 0;
+      int32_t pf = ovf ? DT_FLAG_STACK : 0;
       if (h.tri < 0) {
+        if (fl & SF_INSIDE) pf |= DT_FLAG_LEAK;
         // equirect lookups here; MLP-lit misses are listed per environment
         // after the trace and evaluated on the matrix cores
         const EnvDev& env = T->env[sf_env(fl)];
         if (env.kind == DT_ENV_EQUIRECT) {
           v3 E = env_equirect(env, d);
-          atomicAdd(pixels + 3 * pix, W.x * E.x);
-          atomicAdd(pixels + 3 * pix + 1, W.y * E.y);
-          atomicAdd(pixels + 3 * pix + 2, W.z * E.z);
+          atomicAdd(out.pixels + 3 * pix, W.x * E.x);
+          atomicAdd(out.pixels + 3 * pix + 1, W.y * E.y);
+          atomicAdd(out.pixels + 3 * pix + 2, W.z * E.z);
         }
       } else {
         HitGeo geo = load_geo(sc, h.tri);
         Shade s = shade(sc, geo, o, d, h.t, h.b1, h.b2, 0u);
         code = s.code;
+        if (code & C_DEGEN) pf |= DT_FLAG_DEGEN;
+        if (code & C_GRAZE) pf |= DT_FLAG_GRAZING;
+        if (code & C_TIRB) pf |= DT_FLAG_TIRB;
         if (sf_depth(fl) >= sf_maxd(fl)) {
           code |= C_TRUNC;
+          pf |= DT_FLAG_TRUNC;
         } else {
           code |= C_HAS_R;
           has_r = true;
@@ -201,6 +252,14 @@ __global__ void __launch_bounds__(TBS, 7) k_serve_trace(const ServeTables* T, Ge
         }
       }
       q.code[i] = code;
+      serve_flag(out, pix, pf);
+      if (out.sig) {
+        // the tracer's path signature: (generation, TIR, triangle + 1) mixed
+        const bool tir = (code & C_TIR) && !(code & C_TRUNC);
+        const uint64_t key = ((uint64_t)sf_depth(fl) << 40) | ((uint64_t)(tir ? 1u : 0u) << 32) |
+                             (uint64_t)(uint32_t)(h.tri + 1);
+        atomicAdd(out.sig + pix, (unsigned long long)path_mix64(key));
+      }
     }
     uint64_t br = __ballot(has_r), bt = __ballot(has_t);
     if (lane == 0 && (br | bt))
@@ -250,7 +309,7 @@ __global__ void k_serve_zero_nmiss(ServeState* st) {
 
 __global__ void __launch_bounds__(EBS) k_serve_emit(const ServeTables* T, Gen q, Gen nx,
                                                     ServeState* st, const unsigned long long* part,
-                                                    int64_t cap) {
+                                                    int64_t cap, ServeOut out) {
   __shared__ uint32_t wr[EBS / 64], wt[EBS / 64];
   Counters* ctr = &st->ctr;
   const uint32_t n = ctr->count[0];
@@ -304,7 +363,7 @@ __global__ void __launch_bounds__(EBS) k_serve_emit(const ServeTables* T, Gen q,
           v3 w3 = wa * sh.R;
           nx.w[ir] = make_float4(w3.x, w3.y, w3.z, __int_as_float((int)f2));
         } else {
-          atomicAdd(&ctr->dropped, 1u);
+          serve_drop(out, &ctr->dropped, sf_slot(fl), pix);
         }
       }
       if (ht) {
@@ -315,7 +374,7 @@ __global__ void __launch_bounds__(EBS) k_serve_emit(const ServeTables* T, Gen q,
           v3 w3 = wa * sh.T;
           nx.w[it] = make_float4(w3.x, w3.y, w3.z, __int_as_float((int)f2));
         } else {
-          atomicAdd(&ctr->dropped, 1u);
+          serve_drop(out, &ctr->dropped, sf_slot(fl), pix);
         }
       }
     }
@@ -402,10 +461,12 @@ extern "C" dt_status dt_serve_reset(void* ws, size_t ws_bytes, int64_t queue_cap
 
 extern "C" dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scenes, const dt_env* envs,
                                    int32_t n_envs, const dt_serve_admit* admits, int32_t n_admits,
-                                   int64_t step, float* pixels, int64_t n_pixels, uint32_t* slot_live,
+                                   int64_t step, float* pixels, int32_t* flags, uint64_t* path_sig,
+                                   int64_t n_pixels, uint32_t* slot_live, uint32_t* slot_dropped,
                                    int64_t* stats, int64_t queue_capacity, float t_eps, void* ws,
                                    size_t ws_bytes, void* stream) {
-  DT_REQUIRE(scenes && envs && pixels && slot_live && ws, "dt_serve_step: NULL argument");
+  DT_REQUIRE(scenes && envs && pixels && slot_live && slot_dropped && ws,
+             "dt_serve_step: NULL argument");
   DT_REQUIRE(n_scenes >= 1 && n_scenes <= DT_SERVE_MAX_SCENES, "n_scenes must be in [1, %d]",
              DT_SERVE_MAX_SCENES);
   DT_REQUIRE(n_envs >= 1 && n_envs <= DT_SERVE_MAX_ENVS, "n_envs must be in [1, %d]",
@@ -459,7 +520,8 @@ extern "C" dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scene
   char* W = (char*)ws;
   ServeState* st = (ServeState*)(W + L.state);
   ServeTables* Td = (ServeTables*)(W + L.tables);
-  DT_CHECK_HIP(hipMemcpyAsync(Td, &T, sizeof(T), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_set_tables, dim3(1), dim3(256), 0, s, T, Td);
+  ServeOut out{pixels, flags, (unsigned long long*)path_sig, slot_dropped};
   unsigned long long* part[2] = {(unsigned long long*)(W + L.part0),
                                  (unsigned long long*)(W + L.part1)};
   const int cur = (int)(step & 1), nxt = cur ^ 1;
@@ -471,19 +533,19 @@ extern "C" dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scene
     CamDev cd;
     if (dt_status e = make_camera(ad.camera, a, cd)) return e;
     int64_t np = (int64_t)cd.W * cd.H;
-    hipLaunchKernelGGL(k_zero, dim3(grid_for(3 * np, 256, 4096)), dim3(256), 0, s,
-                       pixels + 3 * ad.camera.pixel_offset, 3 * np);
+    hipLaunchKernelGGL(k_serve_clear, dim3(grid_for(np, 256, 4096)), dim3(256), 0, s, out,
+                       ad.camera.pixel_offset, np, (uint32_t)ad.slot);
     uint32_t fl = sf_make(0, 0, (uint32_t)ad.max_depth, (uint32_t)ad.scene, (uint32_t)ad.env,
                           (uint32_t)ad.slot);
     hipLaunchKernelGGL(k_serve_raygen, dim3(dt_blocks(np, 256)), dim3(256), 0, s, qc, st, prefix, cd,
-                       fl, L.cap);
+                       fl, L.cap, out);
     prefix += np;
   }
   if (added) hipLaunchKernelGGL(k_serve_admit_count, dim3(1), dim3(64), 0, s, st, added, L.cap);
   DT_CHECK_LAUNCH();
   // one interaction for every live ray
   hipLaunchKernelGGL(k_serve_trace, dim3(grid_for(L.cap, TBS, SERVE_TRACE_BLOCKS)), dim3(TBS), 0, s,
-                     Td, qc, st, part[cur], pixels, (uint2*)(W + L.ovf));
+                     Td, qc, st, part[cur], out, (uint2*)(W + L.ovf));
   // MLP environments: list each one's misses, evaluate them on the matrix cores
   for (int e = 0; e < n_envs; ++e) {
     if (T.env[e].kind != DT_ENV_MLP) continue;
@@ -496,7 +558,7 @@ extern "C" dt_status dt_serve_step(const dt_serve_scene* scenes, int32_t n_scene
   }
   if (dt_status e = chunk_scan(&st->ctr, 0, part[cur], part[nxt], L.maxchunks + 1, L.cap, s)) return e;
   hipLaunchKernelGGL(k_serve_emit, dim3((unsigned)L.maxchunks), dim3(EBS), 0, s, Td, qc, qn, st,
-                     part[cur], L.cap);
+                     part[cur], L.cap, out);
   // (the scan zeroed part[nxt] for the next step; the next step's scan zeroes part[cur])
   hipLaunchKernelGGL(k_serve_advance, dim3(1), dim3(64), 0, s, st);
   hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, s, (float*)slot_live, (int64_t)DT_SERVE_MAX_SLOTS);

@@ -54,7 +54,7 @@ struct Plan {
   size_t w_ctr, w_parts, w_part0, w_part1;
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
-  size_t w_dN, w_sbar, w_red, w_miss, w_ovf, w_gscr;
+  size_t w_dN, w_sbar, w_red, w_miss, w_ovf, w_gscr, w_mlpg;
   size_t w_frec, w_fkey, w_fidx, w_fcnt, w_foff, w_fscan, w_fg;  // per-face gathering of vertex adjoints
   size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
   size_t ws_bytes;
@@ -144,6 +144,8 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = dt_align(o + 4 * mc);
   P.w_gscr = o;  // copies of the absorption grid's gradient, summed at the end
   o = dt_align(o + GG_SCRATCH);
+  P.w_mlpg = o;  // per-block partial sums of the environment MLP's weight gradient
+  o = dt_align(o + mlp_wgrad_scratch_bytes());
   P.w_ovf = o;   // per-lane traversal stack overflow of the traversal grid
   o = dt_align(o + 8 * (size_t)TRACE_MAX_BLOCKS * TB * (DT_STACK - DT_STACK_LDS));
   P.w_frec = o;  // vertex-adjoint record of each node of the current generation
@@ -282,18 +284,9 @@ __device__ __forceinline__ void add_rgb(float* rgb, int pix, v3 v) {
 
 __device__ __forceinline__ v3 mul3(v3 a, v3 b) { return mk3(a.x * b.x, a.y * b.y, a.z * b.z); }
 
-// 64-bit mixer: the SplitMix64 output function (Steele, Lea and Flood,
-// OOPSLA 2014).  Summed over a pixel's segments it gives an order-independent
-// signature of the discrete path (generation, triangle or -1, TIR).
-__device__ __forceinline__ uint64_t mix64(uint64_t x) {
-  x += 0x9E3779B97F4A7C15ull;
-  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-  return x ^ (x >> 31);
-}
 
 // ------------------------------------------------------------------ k_trace (a4 + a5 decisions + a6)
-template <bool GRID>
+template <bool GRID, bool FIELD>
 __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
                                               int32_t* flags, unsigned long long* sig,
@@ -337,11 +330,27 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
         if (rfl & RAY_INSIDE) pf |= DT_FLAG_LEAK;
         // equirect lookups here; MLP lookups are listed afterwards and run in
         // batches on the matrix cores
-        if (accumulate && sc.env.kind == DT_ENV_EQUIRECT) add_rgb(rgb, pix, mul3(W, env_equirect(sc.env, d)));
+        if (accumulate && sc.env.kind == DT_ENV_EQUIRECT) {
+          v3 E = env_equirect(sc.env, d);
+          if constexpr (FIELD) {
+            if (!(rfl & RAY_INSIDE)) {
+              // the field along the ray to the far side of its box, then the
+              // environment beyond
+              v3 C;
+              float T;
+              field_segment(sc.fd, o, d, 0.f, true, C, T);
+              E = C + E * T;
+            }
+          }
+          add_rgb(rgb, pix, mul3(W, E));
+        }
       } else {
         hit = true;
         HitGeo geo = load_geo(sc, h.tri);
-        Shade s = shade<GRID>(sc, geo, o, d, h.t, h.b1, h.b2, 0u);
+        Shade s = shade<GRID, FIELD>(sc, geo, o, d, h.t, h.b1, h.b2, 0u);
+        if constexpr (FIELD) {
+          if (accumulate && (s.code & C_ENTER)) add_rgb(rgb, pix, mul3(W, s.Cem));
+        }
         code = s.code;
         if (code & C_DEGEN) pf |= DT_FLAG_DEGEN;
         if (code & C_GRAZE) pf |= DT_FLAG_GRAZING;
@@ -369,7 +378,7 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
         bool tir = (code & C_TIR) && !(code & C_TRUNC);
         uint64_t key = ((uint64_t)(uint32_t)g << 40) | ((uint64_t)(tir ? 1u : 0u) << 32) |
                        (uint64_t)(uint32_t)(h.tri + 1);
-        atomicAdd(sig + pix, (unsigned long long)mix64(key));
+        atomicAdd(sig + pix, (unsigned long long)path_mix64(key));
       }
     }
     uint64_t br = __ballot(has_r), bt = __ballot(has_t), bh = __ballot(hit);
@@ -420,7 +429,7 @@ __global__ void k_scan(Counters* ctr, int g, unsigned long long* part, unsigned 
 // Block b re-walks chunk b in order and writes each ray's children at its
 // scanned position: reflected children fill [0, n_r) of the next queue,
 // refracted children [n_r, n_r + n_t).  write_rays = 0 computes indices only.
-template <bool GRID>
+template <bool GRID, bool FIELD>
 __global__ void __launch_bounds__(EB) k_emit(SceneDev sc, Gen q, Gen nx, int g, Counters* ctr,
                                              const unsigned long long* part, int64_t cap_next,
                                              int write_rays, int32_t* flags) {
@@ -463,7 +472,7 @@ __global__ void __launch_bounds__(EB) k_emit(SceneDev sc, Gen q, Gen nx, int g, 
         int pix = __float_as_int(d4.w);
         int tri = __float_as_int(h4.y);
         HitGeo geo = load_geo(sc, tri);
-        Shade sh = shade<GRID>(sc, geo, o, d, h4.x, h4.z, h4.w, code);
+        Shade sh = shade<GRID, FIELD>(sc, geo, o, d, h4.x, h4.z, h4.w, code);
         v3 wa = mul3(W, sh.A);
         bool entering = (code & C_ENTER) != 0u;
         if (hr) {
@@ -564,7 +573,7 @@ struct VtxAdj {
 // Adjoint of node i of generation g: writes its record (subtree radiance,
 // d/d origin, d/d direction) to cur, adds its dIoR / dsigma terms to acc and
 // returns its vertex contributions.
-template <bool GRID>
+template <bool GRID, bool FIELD>
 __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, int64_t i,
                                              const float* grad_rgb, const Adj& nxt, const Adj& cur,
                                              float4& acc, VtxAdj& out) {
@@ -577,6 +586,23 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   if (!(code & C_HIT)) {
     if (sc.env.kind != DT_ENV_EQUIRECT) return;  // written by the MLP kernel
     v3 dd;
+    if constexpr (FIELD) {
+      if (!(__float_as_uint(w4.w) & RAY_INSIDE)) {
+        // L = C + T E along the exterior ray
+        v3 C;
+        float T;
+        field_segment(sc.fd, o, d, 0.f, true, C, T);
+        v3 E = env_equirect_grad(sc.env, d, gW * T, &dd);
+        v3 ob = mk3(0.f, 0.f, 0.f);
+        float tb = 0.f;
+        field_segment_bwd(sc.fd, o, d, 0.f, true, E, gW, ob, dd, tb);
+        const v3 L = C + E * T;
+        cur.L[i] = make_float4(L.x, L.y, L.z, 0.f);
+        cur.O[i] = make_float4(ob.x, ob.y, ob.z, 0.f);
+        cur.D[i] = make_float4(dd.x, dd.y, dd.z, 0.f);
+        return;
+      }
+    }
     v3 E = env_equirect_grad(sc.env, d, gW, &dd);
     cur.L[i] = make_float4(E.x, E.y, E.z, 0.f);
     cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -584,7 +610,9 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
     return;
   }
   bool trunc = (code & C_TRUNC) != 0u;
-  if (trunc && !sc.terminal_env) {
+  // with a field, a truncated hit reached from outside still emits its segment
+  const bool field_seg = FIELD && (code & C_ENTER) != 0u;
+  if (trunc && !sc.terminal_env && !field_seg) {
     cur.L[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     cur.O[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     cur.D[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -593,18 +621,25 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   float t = h4.x, b1 = h4.z, b2 = h4.w;
   int tri = __float_as_int(h4.y);
   HitGeo geo = load_geo(sc, tri);
-  Shade s = shade<GRID>(sc, geo, o, d, t, b1, b2, code);
+  Shade s = shade<GRID, FIELD>(sc, geo, o, d, t, b1, b2, code);
   const bool entering = (code & C_ENTER) != 0u, tir = (code & C_TIR) != 0u;
   const bool degen = (code & C_DEGEN) != 0u;
   v3 L, Abar, dbar = mk3(0.f, 0.f, 0.f), xbar = mk3(0.f, 0.f, 0.f), nbar = mk3(0.f, 0.f, 0.f);
+  v3 Mf = mk3(0.f, 0.f, 0.f);  // radiance beyond the hit (the field segment's far side)
   float cibar = 0.f, ctbar = 0.f, etarbar = 0.f, etaibar = 0.f, etatbar = 0.f;
   if (trunc) {
-    // terminal mode ENV: L = A * E(d)
-    v3 dd;
-    v3 E = env_equirect_grad(sc.env, d, mul3(gW, s.A), &dd);
-    L = mul3(s.A, E);
-    Abar = mul3(gW, E);
-    dbar = dd;
+    if (sc.terminal_env) {
+      // terminal mode ENV: L = A * E(d)
+      v3 dd;
+      v3 E = env_equirect_grad(sc.env, d, mul3(gW, s.A), &dd);
+      L = mul3(s.A, E);
+      Abar = mul3(gW, E);
+      dbar = dd;
+      Mf = E;
+    } else {
+      L = mk3(0.f, 0.f, 0.f);
+      Abar = L;
+    }
   } else {
     int2 ch = q.child[i];
     v3 Lr = mk3(0.f, 0.f, 0.f), Lt = mk3(0.f, 0.f, 0.f), drb = Lr, dtb = Lr;
@@ -621,6 +656,7 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
     v3 M = Lr * s.R + Lt * s.T;
     L = mul3(s.A, M);
     Abar = mul3(gW, M);
+    Mf = M;
     // reflected direction u_r = d + 2 cos_i n (Eq. 3)
     v3 urb = norm_bwd(s.ur, s.dr, drb);
     dbar += urb;
@@ -672,6 +708,14 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
     acc.z += -Abar.y * t * s.A.y;
     acc.w += -Abar.z * t * s.A.z;
     tbar += -(Abar.x * sg0 * s.A.x + Abar.y * sg1 * s.A.y + Abar.z * sg2 * s.A.z);
+  }
+  if constexpr (FIELD) {
+    if (field_seg) {
+      // L = C + T M over the exterior segment [0, t]; T's effect on M is in
+      // the field's backward (A = T is not used for the attenuation here)
+      L = L + s.Cem;
+      field_segment_bwd(sc.fd, o, d, t, false, Mf, gW, oabs, dbar, tbar);
+    }
   }
   // cos_i = -d . n
   dbar += s.n * (-cibar);
@@ -744,7 +788,7 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
 // scatter sort the nodes by face; then each face sums its records and adds
 // the totals to its three vertices (18 atomics per hit face instead of 18 per
 // hit).
-template <bool GRID>
+template <bool GRID, bool FIELD>
 __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
                                                 const float* grad_rgb, Adj nxt, Adj cur,
                                                 FaceRec* frec, int2* fkey, uint32_t* fcnt,
@@ -761,7 +805,7 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
     VtxAdj va;
     va.f = -1;
     va.m = mk3(0.f, 0.f, 0.f);
-    adjoint_node<GRID>(sc, q, i, grad_rgb, nxt, cur, acc, va);
+    adjoint_node<GRID, FIELD>(sc, q, i, grad_rgb, nxt, cur, acc, va);
     int2 key = make_int2(-1, 0);
     if (va.f >= 0) {
       FaceRec r;
@@ -904,9 +948,18 @@ __global__ void __launch_bounds__(GG_T) k_env_tex_grad(SceneDev sc, Gen q, int g
       const uint32_t code = q.code[i];
       has = !(code & C_HIT) || (sc.terminal_env && (code & C_TRUNC));
       if (has) {
-        const float4 d4 = q.d[i];
+        const float4 d4 = q.d[i], w4 = q.w[i];
         d = xyz(d4);
-        gb = mul3(load3(grad_rgb + 3 * __float_as_int(d4.w)), xyz(q.w[i]));
+        gb = mul3(load3(grad_rgb + 3 * __float_as_int(d4.w)), xyz(w4));
+        if (sc.fd.grid && ((code & C_HIT) ? (code & C_ENTER) != 0u
+                                          : !(__float_as_uint(w4.w) & RAY_INSIDE))) {
+          // an exterior segment through the volumetric field: the lookup is
+          // weighted by the field's transmittance
+          v3 C;
+          float T;
+          field_segment(sc.fd, xyz(q.o[i]), d, q.hit[i].x, !(code & C_HIT), C, T);
+          gb = gb * T;
+        }
         if ((code & C_HIT) && !(code & C_ENTER)) {
           // capped hit reached from inside: the lookup is weighted by A
           const float t = q.hit[i].x;
@@ -1245,7 +1298,39 @@ dt_status make_scene(const dt_scene* sc, const dt_trace_params* p, SceneDev& s) 
       s.ab.scale[a] = (float)(n[a] - 1) / (G->hi[a] - G->lo[a]);
     }
   }
+  memset(&s.fd, 0, sizeof(s.fd));
+  if (const dt_field* G = sc->field) {
+    DT_REQUIRE(G->grid && G->planes, "field has a NULL grid or planes");
+    DT_REQUIRE(G->nx >= 2 && G->ny >= 2 && G->nz >= 2 && G->res >= 2 && G->nx <= 1024 &&
+                   G->ny <= 1024 && G->nz <= 1024 && G->res <= 1024,
+               "field needs 2..1024 nodes per axis (got %d, %d, %d, res %d)", G->nx, G->ny, G->nz,
+               G->res);
+    DT_REQUIRE(G->samples >= 1 && G->samples <= 256, "field samples must be in [1, 256]");
+    DT_REQUIRE((G->d_grid == nullptr) == (G->d_planes == nullptr),
+               "field gradients need both d_grid and d_planes, or neither");
+    s.fd.grid = G->grid;
+    s.fd.planes = G->planes;
+    s.fd.d_grid = G->d_grid;
+    s.fd.d_planes = G->d_planes;
+    s.fd.nx = G->nx;
+    s.fd.ny = G->ny;
+    s.fd.nz = G->nz;
+    s.fd.res = G->res;
+    s.fd.samples = G->samples;
+    const int n[3] = {G->nx, G->ny, G->nz};
+    for (int a = 0; a < 3; ++a) {
+      DT_REQUIRE(G->hi[a] > G->lo[a], "field box needs hi > lo on every axis");
+      s.fd.lo[a] = G->lo[a];
+      s.fd.hi[a] = G->hi[a];
+      s.fd.sg[a] = (float)(n[a] - 1) / (G->hi[a] - G->lo[a]);
+      s.fd.sp[a] = (float)(G->res - 1) / (G->hi[a] - G->lo[a]);
+    }
+  }
   if (dt_status st = make_env(sc->env, s.env)) return st;
+  if (s.fd.grid && s.env.kind == DT_ENV_MLP) {
+    dt_set_error("a volumetric field with an MLP environment is not supported");
+    return DT_ERR_UNSUPPORTED;
+  }
   if (s.env.kind == DT_ENV_MLP && p->terminal_env) {
     dt_set_error("terminal_env with an MLP environment is not supported");
     return DT_ERR_UNSUPPORTED;
@@ -1343,12 +1428,15 @@ dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen 
                          int write_next, void* const* events, void* const* mlp_events,
                          uint32_t* miss_list, uint2* ovf, hipStream_t s) {
   if (dt_status st = record(events, 2 * g, s)) return st;
-  if (sc.ab.mu)
-    hipLaunchKernelGGL(k_trace<true>, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
-                       rgb, wtrunc, flags, sig, accumulate, ovf, wp);
-  else
-    hipLaunchKernelGGL(k_trace<false>, dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g,
-                       rgb, wtrunc, flags, sig, accumulate, ovf, wp);
+#define DT_TRACE(G, FL)                                                                              \
+  hipLaunchKernelGGL((k_trace<G, FL>), dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g, \
+                     rgb, wtrunc, flags, sig, accumulate, ovf, wp)
+  if (sc.fd.grid) {
+    if (sc.ab.mu) DT_TRACE(true, true); else DT_TRACE(false, true);
+  } else {
+    if (sc.ab.mu) DT_TRACE(true, false); else DT_TRACE(false, false);
+  }
+#undef DT_TRACE
   DT_CHECK_LAUNCH();
   if (dt_status st = record(events, 2 * g + 1, s)) return st;
   if (accumulate && sc.env.kind == DT_ENV_MLP) {
@@ -1363,12 +1451,15 @@ dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen 
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ctr, g, part_g, part_other, other_n,
                        P.cap[g + 1]);
     int64_t nch = (P.cap[g] + CHUNK - 1) / CHUNK;
-    if (sc.ab.mu)
-      hipLaunchKernelGGL(k_emit<true>, dim3((unsigned)nch), dim3(EB), 0, s, sc, cur, nxt, g, ctr, part_g,
-                         P.cap[g + 1], write_next, accumulate ? flags : nullptr);
-    else
-      hipLaunchKernelGGL(k_emit<false>, dim3((unsigned)nch), dim3(EB), 0, s, sc, cur, nxt, g, ctr, part_g,
-                         P.cap[g + 1], write_next, accumulate ? flags : nullptr);
+#define DT_EMIT(G, FL)                                                                                 \
+  hipLaunchKernelGGL((k_emit<G, FL>), dim3((unsigned)nch), dim3(EB), 0, s, sc, cur, nxt, g, ctr, part_g, \
+                     P.cap[g + 1], write_next, accumulate ? flags : nullptr)
+    if (sc.fd.grid) {
+      if (sc.ab.mu) DT_EMIT(true, true); else DT_EMIT(false, true);
+    } else {
+      if (sc.ab.mu) DT_EMIT(true, false); else DT_EMIT(false, false);
+    }
+#undef DT_EMIT
     DT_CHECK_LAUNCH();
   }
   return DT_OK;
@@ -1414,10 +1505,17 @@ dt_status make_env(const dt_env* env, EnvDev& e) {
   e.in_pad = env->in_pad;
   e.w = env->weights;
   e.b = env->biases;
+  e.d_w = env->kind == DT_ENV_MLP ? env->d_weights : nullptr;
+  e.d_b = env->kind == DT_ENV_MLP ? env->d_biases : nullptr;
   if (env->kind == DT_ENV_MLP && !mlp_supported(e)) {
     dt_set_error("environment MLP needs weights, biases, in_pad 64, hidden 64 or 128, 1-4 layers, "
                  "n_freq <= 7 (got in_pad %d hidden %d layers %d n_freq %d)",
                  env->in_pad, env->hidden, env->n_layers, env->n_freq);
+    return DT_ERR_UNSUPPORTED;
+  }
+  DT_REQUIRE(!e.d_w == !e.d_b, "environment MLP: give both d_weights and d_biases, or neither");
+  if (e.d_w && mlp_wgrad_params(e) == 0) {
+    dt_set_error("environment MLP weight gradient: hidden width 64 only (got %d)", env->hidden);
     return DT_ERR_UNSUPPORTED;
   }
   return DT_OK;
@@ -1602,6 +1700,14 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   }
   if (sc.env.d_tex)
     if (dt_status st = zero_f32(sc.env.d_tex, 3 * (int64_t)sc.env.W * sc.env.H, s)) return st;
+  float* mlp_part = (float*)(W + P.w_mlpg);
+  if (sc.env.d_w)
+    if (dt_status st = zero_f32(mlp_part, (int64_t)(mlp_wgrad_scratch_bytes() / sizeof(float)), s))
+      return st;
+  if (sc.fd.d_grid) {
+    if (dt_status st = zero_f32(sc.fd.d_grid, 4 * (int64_t)sc.fd.nx * sc.fd.ny * sc.fd.nz, s)) return st;
+    if (dt_status st = zero_f32(sc.fd.d_planes, 12 * (int64_t)sc.fd.res * sc.fd.res, s)) return st;
+  }
   if (dt_status st = zero_f32((float*)red, 4 * (int64_t)nred, s)) return st;
   Adj adj[2];
   for (int b = 0; b < 2; ++b) {
@@ -1620,16 +1726,23 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
       hipLaunchKernelGGL(k_list_misses, dim3(list_grid(P.cap[g])), dim3(LB), 0, s, q, g, ctr, ml);
       DT_CHECK_LAUNCH();
       if (dt_status st = record(maev, 2 * g, s)) return st;
-      if (dt_status st = mlp_trace_backward(sc.env, q, ml, ctr, g, P.cap[g], grad_rgb, adj[g & 1], s))
+      if (sc.env.d_w) {
+        if (dt_status st = mlp_trace_backward_wgrad(sc.env, q, ml, ctr, g, grad_rgb, adj[g & 1], mlp_part, s))
+          return st;
+      } else if (dt_status st = mlp_trace_backward(sc.env, q, ml, ctr, g, P.cap[g], grad_rgb, adj[g & 1], s)) {
         return st;
+      }
       if (dt_status st = record(maev, 2 * g + 1, s)) return st;
     }
-    if (sc.ab.mu)
-      hipLaunchKernelGGL(k_adjoint<true>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
-    else
-      hipLaunchKernelGGL(k_adjoint<false>, dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,
-                         adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red);
+#define DT_ADJ(G, FL)                                                                                  \
+  hipLaunchKernelGGL((k_adjoint<G, FL>), dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,  \
+                     adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red)
+    if (sc.fd.grid) {
+      if (sc.ab.mu) DT_ADJ(true, true); else DT_ADJ(false, true);
+    } else {
+      if (sc.ab.mu) DT_ADJ(true, false); else DT_ADJ(false, false);
+    }
+#undef DT_ADJ
     if (sc.env.d_tex) {
       const int64_t eb = (P.cap[g] + GG_T - 1) / GG_T;
       hipLaunchKernelGGL(k_env_tex_grad, dim3((unsigned)(eb < 8192 ? eb : 8192)), dim3(GG_T), 0, s, sc, q, g,
@@ -1694,6 +1807,8 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
   }
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_T), 0, s, red, nred, d_ior, d_sigma);
+  if (sc.env.d_w)
+    if (dt_status st = mlp_wgrad_reduce(sc.env, mlp_part, s)) return st;
   if (n_copies > 0 && gcopies != sc.ab.d_mu)
     hipLaunchKernelGGL(k_grid_reduce, dim3(dt_blocks(gsize, 256) < 4096 ? dt_blocks(gsize, 256) : 4096), dim3(256),
                        0, s, gcopies, n_copies, gsize, sc.ab.d_mu);

@@ -478,13 +478,15 @@ def torus_scene(n_views: int = 8, res: int = 512) -> Workload:
 
 def sdf_union_scene(n_views: int = 8, res: int = 800) -> Workload:
     """Training-step shape: SDF union of 3 tori + 2 spheres (~300k tris, several
-    handles), IoR 1.45, sigma 0.3, 8 views at 800x800, depth 6, environment =
-    frequency-encoded MLP 3 x 64 (bf16 weights)."""
+    handles), IoR 1.5, sigma (0.5, 0.2, 0.1), 8 views at 800x800, depth 6,
+    environment = frequency-encoded MLP 3 x 64 (bf16 weights).  A gradient
+    check renders it at other material values against targets at these, so
+    that the gradients are nonzero."""
     V, F = sdf_union_faces(300_000, seed=3)
     eyes = views_on_sphere(n_views, 3.0, seed=3)
     cams = [look_at_camera(e, res, res) for e in eyes]
     Ws, Bs = env_mlp_weights(seed=3, n_layers=3, width=64)
-    return Workload("sdf-union-300k", V, F, 1.45, (0.3, 0.3, 0.3), None, cams, 6,
+    return Workload("sdf-union-300k", V, F, 1.5, (0.5, 0.2, 0.1), None, cams, 6,
                     mlp=(Ws, Bs, 6))
 
 

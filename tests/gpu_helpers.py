@@ -138,25 +138,203 @@ def path_ill_conditioned(orc, o, d, sig, eps=1e-5, k=8, seed=0):
     return out
 
 
-def radiance_sensitivity(orc, o, d, rgb, eps=1e-6, k=8, seed=1, floor=None):
-    """Largest relative change of the oracle's radiance when the camera ray is
-    turned by eps radians (k random directions), per pixel, in the metric of
-    rgb_rel_err.  eps = 1e-6 rad is about 16 FP32 ulps of a unit direction, the
-    size of the error an FP32 path has gathered after a few bounces; where the
-    radiance moves more than 1e-4 under such a turn (a high-frequency
-    environment seen through magnifying refractions), FP32 cannot resolve it
-    to 1e-4."""
+# pixels with no defined radiance comparison: a shading normal on the wrong
+# side (the geometric one is used) or a ray that leaves the object from inside
+UNDEFINED = B.FLAG_DEGEN | B.FLAG_LEAK
+
+
+def check_radiance(orc, o, d, rgb, fl, sig, mlp=False, label="", max_excluded=0.05):
+    """Device radiance against the oracle, pixel by pixel.
+
+    * No pixel may carry a stack overflow or a dropped ray (HARD).
+    * DEGEN / LEAK pixels have no defined comparison; they must be under
+      max_excluded.
+    * A pixel whose discrete path (signature) differs from the oracle's must
+      be one whose oracle path changes under a 1e-5 rad turn of its camera ray
+      (every such pixel is checked; their fraction is reported).
+    * Every same-path pixel, grazing and near-critical ones included, meets
+      1e-4, or, where FP32 cannot reach 1e-4, the oracle's first-order bound on
+      the rounding error of an FP32 evaluation of that pixel.
+    Metric: per pixel-channel |g - o| / max(|o|, 1e-3 mean |o|) for map-lit
+    scenes; per pixel ||g - o|| / max(||o||, 0.1 mean ||o||) for MLP-lit ones
+    (the network's output is a signed sum, its rounding error absolute).
+    Returns dict(ref, same_path, well) with well = same-path pixels whose bound
+    is within 1e-4."""
     o, d = np.asarray(o, np.float64), np.asarray(d, np.float64)
-    rng = np.random.default_rng(seed)
-    n = np.linalg.norm(rgb, axis=1)
-    fl = floor if floor is not None else 0.1 * max(n.mean(), 1e-30)
-    out = np.zeros(len(o))
-    for _ in range(k):
-        t = rng.normal(size=d.shape)
-        t -= (t * d).sum(1, keepdims=True) * d
-        t /= np.linalg.norm(t, axis=1, keepdims=True)
-        dp = d + eps * t
-        dp /= np.linalg.norm(dp, axis=1, keepdims=True)
-        c = orc.trace(o, dp)["rgb"]
-        out = np.maximum(out, np.linalg.norm(c - rgb, axis=1) / np.maximum(n, fl))
-    return out
+    rgb = np.asarray(rgb, np.float64)
+    ref = orc.trace(o, d)
+    assert not (fl & HARD).any(), f"{label}: stack overflow or dropped rays"
+    undef = ((fl | ref["flags"]) & UNDEFINED) != 0
+    same = sig == ref["sig"]
+    sp = ~undef & same
+    bound = np.zeros_like(rgb)
+    if sp.any():
+        _, bound[sp] = orc.errbound(o[sp], d[sp])
+    if mlp:
+        n = np.linalg.norm(ref["rgb"], axis=1)
+        den = np.maximum(n, 0.1 * max(n.mean(), 1e-30))
+        err = np.linalg.norm(rgb - ref["rgb"], axis=1) / den
+        brel = np.linalg.norm(bound, axis=1) / den
+    else:
+        den = np.maximum(np.abs(ref["rgb"]), 1e-3 * max(np.abs(ref["rgb"]).mean(), 1e-30))
+        err = (np.abs(rgb - ref["rgb"]) / den).max(1)
+        brel = (bound / den).max(1)
+    well = sp & (brel <= 1e-4)
+    ill = sp & ~well
+    over = sp & (err > 1e-4)
+    marked = ((fl | ref["flags"]) & (B.FLAG_GRAZING | B.FLAG_TIRB)) != 0
+    print(f"{label}: {len(o)} px; undefined {undef.mean():.4f}; same path {sp.sum()} "
+          f"(grazing / near-critical {int((sp & marked).sum())}); FP32 bound over 1e-4 on "
+          f"{ill.mean():.4f}; max err where bound <= 1e-4: {err[well].max() if well.any() else 0:.2e}; "
+          f"over 1e-4: {int(over.sum())} (max ratio to bound "
+          f"{(err[over] / brel[over]).max() if over.any() else 0:.3f}); paths differing "
+          f"{int((~undef & ~same).sum())}", flush=True)
+    assert undef.mean() < max_excluded, f"{label}: {undef.mean():.4f} undefined"
+    assert (err[sp] <= np.maximum(1e-4, brel[sp])).all(), \
+        f"{label}: {int((err[sp] > np.maximum(1e-4, brel[sp])).sum())} same-path pixels over their bar"
+    div = ~undef & ~same
+    if div.any():
+        assert path_ill_conditioned(orc, o[div], d[div], ref["sig"][div]).all(), \
+            f"{label}: a path differs where the oracle's own path is well conditioned"
+    return {"ref": ref, "same_path": sp, "well": well, "err": err}
+
+
+def gradient_pixels(chk, fl, stable=None, strict=False):
+    """Pixels whose gradient is compared: same discrete path, under the
+    oracle's perturbations too (`stable`), and no environment lookup on a
+    gradient kink.  Grazing and near-critical hits, and radiance that FP32
+    does not resolve to 1e-4, are compared like every other pixel, each
+    element held to its own perturbation spread (GradRef); strict leaves them
+    out."""
+    ref = chk["ref"]
+    m = chk["same_path"] & ((ref["flags"] & KINK) == 0)
+    if strict:
+        m &= chk["well"] & (((fl | ref["flags"]) & (B.FLAG_GRAZING | B.FLAG_TIRB)) == 0)
+    if stable is not None:
+        m &= stable
+    return m
+
+
+# relative size of the perturbations that stand in for FP32 rounding: two
+# units in the last place of a float32
+PERTURB_U = 2.0 ** -23
+# margin of the per-element gradient allowance over the perturbation spread
+# (the intermediate steps round too, each at about the inputs' level)
+SPREAD_MARGIN = 8.0
+
+
+def _spread(a, b):
+    if a is None:
+        return None
+    if isinstance(a, (list, tuple)):
+        return type(a)(_spread(x, y) for x, y in zip(a, b))
+    if isinstance(a, float):
+        return abs(a - b)
+    return np.abs(np.asarray(a) - np.asarray(b))
+
+
+def _max(a, b):
+    if a is None:
+        return None
+    if isinstance(a, (list, tuple)):
+        return type(a)(_max(x, y) for x, y in zip(a, b))
+    return np.maximum(a, b)
+
+
+class GradRef:
+    """The oracle's gradients for a device backward, with a per-element
+    rounding allowance.
+
+    A derivative can be far worse conditioned than the radiance it belongs to:
+    a vertex that reaches the loss only through a barycentric weight near zero
+    (a hit near the opposite edge), or a texel only through a bilinear weight
+    near zero, carries the FP32 rounding error of that weight (absolute, about
+    1e-7) as a large relative error.  The allowance is measured on the oracle
+    alone.  K = 8 times, the vertices and the material are perturbed at random by
+    a relative PERTURB_U (two float32 ulps, the backward error of rounding
+    each input once), and the oracle's jitter instrument scales every ray it
+    starts (camera rays and each child, as the device stores every ray in
+    float32) per component by (1 + PERTURB_U xi); the FP64 gradients are taken
+    again, and SPREAD_MARGIN times the spread max_k |g_k - g| of each element
+    is added to its relative 1e-3 of the ray-by-ray magnitudes.  The spread is
+    that of the summed gradient, where the deviations of different pixels may
+    partly cancel in one run; with K = 2 a few elements in 10^5 came out
+    below the device's deviation for that reason, and each further run makes
+    such a chance underestimate rarer by a large factor.  `stable`
+    marks the pixels whose discrete path is the same under every perturbation:
+    the others have no defined gradient comparison."""
+
+    def __init__(self, orc, o, d, sig, k=8, seed=11):
+        self.orc, self.o, self.d = orc, np.asarray(o, np.float64), np.asarray(d, np.float64)
+        rng = np.random.default_rng(seed)
+        u = PERTURB_U
+
+        def jit(x):
+            x = np.asarray(x, np.float64)
+            return x * (1.0 + u * rng.uniform(-1.0, 1.0, x.shape))
+
+        self.perturbed = []
+        self.stable = np.ones(len(self.o), bool)
+        for j in range(k):
+            sc = orc.with_(V=jit(orc.V), eta=float(jit(orc.eta)), sigma=jit(orc.sigma), jitter=u,
+                           jitter_seed=seed * 1000 + j)
+            self.perturbed.append(sc)
+            self.stable &= sc.trace(self.o, self.d)["sig"] == np.asarray(sig)
+
+    def grads(self, gs, **kw):
+        """(o, a, s): the oracle's gradients for upstream gs, their ray-by-ray
+        magnitudes, and the perturbation spread (same structure)."""
+        o = self.orc.trace_grad(self.o, self.d, gs, **kw)
+        a = self.orc.trace_grad(self.o, self.d, gs, absolute=True, **kw)
+        s = None
+        for sc in self.perturbed:
+            p = sc.trace_grad(self.o, self.d, gs, **kw)
+            sk = {key: _spread(o[key], p[key]) for key in o if key != "rgb"}
+            s = sk if s is None else {key: _max(s[key], sk[key]) for key in s}
+        return o, a, s
+
+
+def check_elements(g, o, a, name, spread=None, tol=1e-3, floor_frac=None):
+    """Element by element: every entry of the device gradient within
+    tol * a + SPREAD_MARGIN * spread of the oracle's, where a = the sum over
+    camera rays of the magnitudes of each ray's contribution to that entry
+    (the oracle's `absolute` gradient: each ray's term is held to tol, and an
+    entry that is a sum cancelling to near zero is compared against the terms
+    it cancels, not against the small remainder) and spread = the entry's
+    perturbation spread (GradRef).  floor_frac: the allowance is at least
+    tol * floor_frac * the RMS of the array's nonzero entries (for arrays whose
+    arithmetic error is relative to the array's scale rather than to each
+    entry).  Also the whole-array L2 distance, within
+    tol ||o|| + SPREAD_MARGIN ||spread||.  Returns the L2 ratio ||g - o|| / ||o||."""
+    g, o, a = (np.asarray(x, np.float64).ravel() for x in (g, o, a))
+    s = np.zeros_like(o) if spread is None else np.asarray(spread, np.float64).ravel()
+    assert (a >= np.abs(o) * (1 - 1e-12)).all()
+    assert np.isfinite(g).all(), f"{name}: non-finite device gradient"
+    allow = tol * a + SPREAD_MARGIN * s
+    if floor_frac is not None:
+        nz = o != 0
+        allow = np.maximum(allow, tol * floor_frac * np.sqrt(np.mean(o[nz] ** 2)) if nz.any() else 0.0)
+    r = np.abs(g - o) / np.maximum(allow, 1e-300)
+    on = np.linalg.norm(o)
+    assert on > 0, f"{name}: the oracle's gradient is zero: nothing is compared"
+    l2 = np.linalg.norm(g - o) / on
+    l2_allow = tol + SPREAD_MARGIN * np.linalg.norm(s) / on
+    spread_led = int((SPREAD_MARGIN * s > tol * a).sum())
+    print(f"{name}: L2 {l2:.2e} (allowed {l2_allow:.2e}); per element max {r.max():.2e} of its "
+          f"allowance, p99.9 {np.quantile(r, 0.999):.2e}; over: {int((r > 1).sum())} of {r.size}; "
+          f"allowance set by the spread on {spread_led}", flush=True)
+    assert l2 <= l2_allow, f"{name}: L2 ratio {l2} over {l2_allow}"
+    assert r.max() <= 1.0, f"{name}: {int((r > 1).sum())} elements over their allowance"
+    return l2
+
+
+def check_material(de, ds, o, a, s, label, sigma=True):
+    """dIoR (and dsigma) against the oracle to check_elements' bar, with the
+    oracle's gradients o, ray-by-ray magnitudes a and spreads s (GradRef).
+    Returns their relative errors, for the log."""
+    check_elements(np.array([de]), np.array([o["d_eta"]]), np.array([a["d_eta"]]), f"{label} d_eta",
+                   np.array([s["d_eta"]]))
+    if sigma:
+        check_elements(ds, o["d_sigma"], a["d_sigma"], f"{label} d_sigma", s["d_sigma"])
+    return (abs(de - o["d_eta"]) / abs(o["d_eta"]),
+            np.abs(ds - o["d_sigma"]) / np.maximum(np.abs(o["d_sigma"]), 1e-300))

@@ -95,3 +95,38 @@ def test_noalloc_build_rejects_meshes_beyond_its_array():
     # the largest serving scene (500k faces) fits
     L.dt_bvh_bytes(250_000, 500_000, C.byref(a), C.byref(b))
     assert b.value <= 32 << 20
+
+
+def test_bad_field_is_rejected_on_the_host():
+    """A volumetric field with too few nodes, no samples, half of its
+    gradient targets, or beside an MLP environment is refused before any
+    device work (the pointers below are never dereferenced)."""
+    L = B.load()
+    fake = 16
+    env = B._Env()
+    env.kind, env.width, env.height, env.texels = B.ENV_EQUIRECT, 8, 4, fake
+    f = B._Field()
+    f.grid, f.planes, f.nx, f.ny, f.nz, f.res, f.samples = fake, fake, 3, 3, 3, 4, 4
+    for k in range(3):
+        f.lo[k], f.hi[k] = -1.0, 1.0
+    s = B._Scene()
+    s.V, s.nv, s.F, s.nf, s.bvh, s.ior, s.sigma = fake, 3, fake, 1, fake, fake, fake
+    s.env, s.field = C.pointer(env), C.pointer(f)
+    p = B.Params(max_depth=2).c()
+
+    def run():
+        return L.dt_trace_forward(C.byref(s), None, C.byref(p), None, None, None, None, None, None, 0,
+                                  None, 0, None)
+
+    f.nx = 1
+    assert run() == 1 and "field needs 2..1024" in L.dt_last_error().decode()
+    f.nx, f.samples = 3, 0
+    assert run() == 1 and "samples" in L.dt_last_error().decode()
+    f.samples, f.d_grid = 4, fake
+    assert run() == 1 and "d_grid and d_planes" in L.dt_last_error().decode()
+    f.d_grid, f.hi[1] = None, -1.0
+    assert run() == 1 and "hi > lo" in L.dt_last_error().decode()
+    f.hi[1] = 1.0
+    env.kind, env.n_freq, env.n_layers, env.hidden, env.in_pad = B.ENV_MLP, 6, 3, 64, 64
+    env.weights, env.biases = fake, fake
+    assert run() == 5 and "MLP" in L.dt_last_error().decode()

@@ -8,8 +8,8 @@ import torch
 
 import oracle
 from paper_2603_00413_amd import binding as B
-from tests.gpu_helpers import (BAD, DV_ORDER_TOL, HARD, KINK, icosphere_pair, path_ill_conditioned,
-                               rel_err, torus_pair)
+from tests.gpu_helpers import (DV_ORDER_TOL, GradRef, check_elements, check_material, check_radiance, gradient_pixels,
+                               icosphere_pair, rel_err, torus_pair)
 
 pytestmark = pytest.mark.gpu
 
@@ -39,23 +39,11 @@ def _with_grid(P, seed, samples, n=(6, 5, 7), const=None):
 
 def _forward_check(P, check_wtrunc=True):
     _, rgb, wt, fl = P.gpu_forward(tape=False)
-    ref = P.orc.trace(P.o, P.d)
-    assert not (fl & HARD).any()
-    ok = ((fl | ref["flags"]) & BAD) == 0
-    err = rel_err(rgb, ref["rgb"])
-    bad = ok[:, None] & (err > 1e-4)
-    same = P.sig == ref["sig"]
-    _print("excluded", 1 - ok.mean(), "max err", err[ok].max(), "n>1e-4", bad.any(1).sum(),
-           "paths differing", (~same[ok]).sum())
-    assert 1 - ok.mean() < 0.05
-    assert bad.any(1).mean() < 1e-3
-    div = ok & ~same
-    assert div.mean() <= 2e-3
-    if div.any():
-        assert path_ill_conditioned(P.orc, P.o[div], P.d[div], ref["sig"][div]).all()
-    # truncated weights of the pixels whose discrete path is the same
-    both = ok & same
-    ew = rel_err(wt[both], ref["wtrunc"][both])
+    chk = check_radiance(P.orc, P.o, P.d, rgb, fl, P.sig, label="absorption grid")
+    # truncated weights of the pixels whose discrete path is the same and
+    # whose radiance FP32 resolves
+    both = chk["well"]
+    ew = rel_err(wt[both], chk["ref"]["wtrunc"][both])
     _print("wtrunc max rel err", ew.max(), "n>1e-4", (ew > 1e-4).any(1).sum())
     if check_wtrunc:
         assert (ew > 1e-4).any(1).mean() < 1e-3
@@ -90,17 +78,16 @@ def test_constant_grid_matches_constant_rate():
 
 def _grad_check(P, seed):
     buf, rgb, wt, fl = P.gpu_forward(tape=True)
-    ref = P.orc.trace(P.o, P.d)
-    ok = ((fl | ref["flags"]) & (BAD | HARD)) == 0
-    ok &= (ref["flags"] & KINK) == 0
-    ok &= P.sig == ref["sig"]
+    chk = check_radiance(P.orc, P.o, P.d, rgb, fl, P.sig, label="absorption grid gradients")
+    gr = GradRef(P.orc, P.o, P.d, chk["ref"]["sig"])
+    ok = gradient_pixels(chk, fl, gr.stable)
     g = np.random.default_rng(seed).normal(size=rgb.shape) * ok[:, None]
     dV, de, ds = P.gpu_backward(buf, g)
     dmu = P.absorb.d_mu.cpu().numpy().astype(np.float64)
-    o = P.orc.trace_grad(P.o, P.d, g)
-    ev = np.linalg.norm(dV - o["dV"]) / np.linalg.norm(o["dV"])
-    ee = abs(de - o["d_eta"]) / abs(o["d_eta"])
-    em = np.linalg.norm(dmu - o["d_mu"]) / np.linalg.norm(o["d_mu"])
+    o, oa, sp = gr.grads(g)
+    ev = check_elements(dV, o["dV"], oa["dV"], "dV", sp["dV"])
+    em = check_elements(dmu, o["d_mu"], oa["d_mu"], "dmu", sp["d_mu"])
+    ee, _ = check_material(de, ds, o, oa, sp, "absorption grid", sigma=False)
     _print("grad rel err dV", ev, "deta", ee, "dmu", em, "|dmu|", np.linalg.norm(o["d_mu"]))
     assert np.all(ds == 0.0)
     return ev, ee, em, buf, g, (dV, de, dmu)
@@ -109,7 +96,7 @@ def _grad_check(P, seed):
 def test_backward_icosphere_grid():
     P = _with_grid(icosphere_pair(), seed=3, samples=8)
     ev, ee, em, _, _, _ = _grad_check(P, seed=4)
-    assert ev <= 1e-3 and ee <= 1e-3 and em <= 1e-3
+    # dV, dmu and dIoR: checked element by element above
 
 
 def test_backward_torus_grid_and_recompute():
@@ -117,7 +104,7 @@ def test_backward_torus_grid_and_recompute():
     agrees with the stored one."""
     P = _with_grid(torus_pair(n_views=2, res=64), seed=5, samples=6)
     ev, ee, em, buf, g, (dV1, de1, dmu1) = _grad_check(P, seed=6)
-    assert ev <= 1e-3 and ee <= 1e-3 and em <= 1e-3
+    # dV, dmu and dIoR: checked element by element above
     p2 = B.Params(max_depth=P.depth, checkpoint_stride=3)
     buf2, _, _, _ = P.gpu_forward(tape=True, params=p2)
     dV2, de2, _ = P.gpu_backward(buf2, g, params=p2)

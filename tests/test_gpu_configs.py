@@ -8,8 +8,8 @@ import torch
 import oracle
 from paper_2603_00413_amd import binding as B
 from paper_2603_00413_amd import synth
-from tests.gpu_helpers import (BAD, DV_ORDER_TOL, HARD, KINK, device, l2_upstream,
-                               path_ill_conditioned, radiance_sensitivity, rgb_rel_err)
+from tests.gpu_helpers import (DV_ORDER_TOL, HARD, KINK, GradRef, check_elements, check_material, check_radiance, device,
+                               gradient_pixels, l2_upstream)
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +37,7 @@ def _setup(wl, sigma, ior):
 
 
 def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=(1.5, (0.4, 0.25, 0.1)),
-           max_excluded=0.05, max_diverged=0.01, max_ill=0.15):
+           max_excluded=0.05, strict=False):
     mesh, scene, rays, oenv, V32, O, D = _setup(wl, sigma, ior)
     cap = int(1.3 * rays.n_rays)
     sig_t = torch.empty(rays.n_pixels, dtype=torch.int64, device=mesh.V.device)
@@ -55,65 +55,58 @@ def _check(wl, stride, n_sample, ior=1.45, sigma=(0.3, 0.3, 0.3), target=(1.5, (
     rgb, fl = rgb_t.cpu().numpy().astype(np.float64), fl_t.cpu().numpy()
     sig = sig_t.cpu().numpy().view(np.uint64)
     assert not (fl & HARD).any()
-    rng = np.random.default_rng(3)
-    pix = np.sort(rng.choice(len(O), n_sample, replace=False))
     orc = oracle.Scene(V32.astype(np.float64), wl.F, float(np.float32(ior)),
                        np.asarray(sigma, np.float32).astype(np.float64), oenv, wl.max_depth)
-    ref = orc.trace(O[pix], D[pix])
-    ok = ((fl[pix] | ref["flags"]) & BAD) == 0
-    same = sig[pix] == ref["sig"]
-    err = rgb_rel_err(rgb[pix], ref["rgb"])
-    _print(wl.name, "excluded", 1 - ok.mean(), "paths differing", (~same[ok]).mean(),
-           "median err", np.median(err[ok & same]), "max err (same path)", err[ok & same].max(),
-           "max err (other path)", err[ok & ~same].max() if (ok & ~same).any() else 0.0)
-    assert 1 - ok.mean() < max_excluded
-    # a path may part only where the oracle's own path is ill-conditioned
-    div = ok & ~same
-    assert div.mean() <= max_diverged
-    if div.any():
-        ill = path_ill_conditioned(orc, O[pix][div], D[pix][div], ref["sig"][div])
-        _print(wl.name, "diverging paths that are ill-conditioned in the oracle", ill.mean())
-        assert ill.all()
-    # same-path pixels agree to 1e-4 where the radiance is resolvable in FP32:
-    # a pixel whose oracle radiance moves by more than 1e-4 when the camera ray
-    # turns by an FP32-sized 1e-6 rad is ill-conditioned, and its error must
-    # stay within that movement
-    floor = 0.1 * np.linalg.norm(ref["rgb"], axis=1).mean()
-    sp = ok & same
-    sens = np.zeros(len(pix))
-    sens[sp] = radiance_sensitivity(orc, O[pix][sp], D[pix][sp], ref["rgb"][sp], floor=floor)
-    well = sp & (sens <= 1e-4)
-    over = sp & (err > 1e-4)
-    _print(wl.name, "same-path pixels", sp.sum(), "ill-conditioned", (sp & ~well).sum(),
-           "over 1e-4", over.sum(), "max err where well-conditioned", err[well].max())
-    assert (sp & ~well).mean() <= max_ill
-    assert err[well].max() <= 1e-4
-    assert (err[over] <= sens[over]).all()
+    # a quarter of the sample at random, the rest among pixels whose camera
+    # ray the oracle finds hitting the object (the gradient lives there)
+    rng = np.random.default_rng(3)
+    cand = rng.choice(len(O), 4 * n_sample, replace=False)
+    half = n_sample // 4
+    rest = cand[half:]
+    on_obj = rest[orc.trace(O[rest], D[rest])["nseg"] > 1][:n_sample - half]
+    pix = np.sort(np.concatenate([cand[:half], on_obj]))
+    # same-path pixels meet 1e-4, or the oracle's FP32 rounding bound where
+    # that is larger; a path may part only where the oracle's own path is
+    # ill-conditioned
+    chk = check_radiance(orc, O[pix], D[pix], rgb[pix], fl[pix], sig[pix], mlp=True,
+                         label=f"{wl.name}, {n_sample} sampled pixels", max_excluded=max_excluded)
+    ref = chk["ref"]
     # gradient of an L2 loss on the sampled pixels against an oracle-rendered
-    # target, on well-conditioned same-path pixels whose lookups are off the
-    # environment's gradient kinks
+    # target, on same-path pixels (under the oracle's perturbations too) off
+    # the environment's gradient kinks
     tgt = orc.with_(eta=target[0], sigma=target[1]).trace(O[pix], D[pix])["rgb"]
-    okg = well & ((ref["flags"] & KINK) == 0)
-    _print(wl.name, "gradient pixels near an environment kink (excluded)",
-           1 - okg.mean() / well.mean())
+    gr = GradRef(orc, O[pix], D[pix], ref["sig"])
+    okg = gradient_pixels(chk, fl[pix], gr.stable, strict=strict)
+    hits = okg & (ref["nseg"] > 1)
+    kink = (ref["flags"] & KINK) != 0
+    _print(wl.name, "sampled pixels hitting the object", int((ref["nseg"] > 1).sum()), "of", len(pix),
+           "; same path", int(chk["same_path"].sum()), "; path stable under the perturbations",
+           int(gr.stable.sum()), "; on a kink", int(kink.sum()), "; gradient pixels", int(okg.sum()),
+           "of which hit the object", int(hits.sum()))
+    # the MLP-lit scenes put many lookups within 1e-5 rad of a ReLU kink
+    # (a 4 x 128 network has 512 of them, a path up to ~20 lookups), and
+    # those pixels' gradients are not compared
+    assert hits.sum() >= 50
     gs = l2_upstream(ref["rgb"], tgt, okg)
     g = np.zeros_like(rgb)
     g[pix] = gs
     dV, de, ds = B.dt_trace_backward(scene, rays, p, buf, torch.from_numpy(g.astype(np.float32)).to(mesh.V.device))
     dV, de, ds = dV.cpu().numpy(), float(de.cpu()[0]), ds.cpu().numpy()
-    o = orc.trace_grad(O[pix], D[pix], gs)
-    ev = np.linalg.norm(dV - o["dV"]) / np.linalg.norm(o["dV"])
-    ee = abs(de - o["d_eta"]) / abs(o["d_eta"])
-    es = np.abs(ds - o["d_sigma"]) / np.abs(o["d_sigma"])
+    o, oa, sp = gr.grads(gs)
+    ev = check_elements(dV, o["dV"], oa["dV"], f"{wl.name} dV", sp["dV"])
+    ee, es = check_material(de, ds, o, oa, sp, wl.name)
     _print(wl.name, "grads: dV", ev, "deta", ee, "dsigma", es)
-    assert ev <= 1e-3 and ee <= 1e-3 and (es <= 1e-3).all()
     return buf, p, scene, rays, g, (dV, de, ds)
 
 
 def test_training_step_shape_sdf_union_300k():
     wl = synth.sdf_union_scene()
     assert 250_000 < len(wl.F) < 350_000
-    buf, p, scene, rays, g, (dV, de, ds) = _check(wl, 1, 2000)
+    assert wl.ior == 1.5 and tuple(wl.sigma) == (0.5, 0.2, 0.1)
+    # rendered at eta 1.45, sigma 0.3 against targets the oracle renders at
+    # eta* 1.5, sigma* (0.4, 0.25, 0.1), so every gradient is nonzero
+    buf, p, scene, rays, g, (dV, de, ds) = _check(wl, 1, 2000, ior=1.45, sigma=(0.3, 0.3, 0.3),
+                                                  target=(1.5, (0.4, 0.25, 0.1)), strict=False)
     # the recompute adjoint (checkpoint every 3 generations) gives the same gradients
     p3 = B.Params(max_depth=wl.max_depth, checkpoint_stride=3, queue_capacity=p.queue_capacity)
     b3 = B.Buffers(p3, rays, scene.mesh, tape=True)
@@ -128,11 +121,11 @@ def test_training_step_shape_sdf_union_300k():
 def test_stress_thin_shell_2m():
     wl = synth.thin_shell_scene()
     assert len(wl.F) > 1_500_000
-    # thin walls make near-critical hits frequent, and over 8 bounces some
-    # FP32 paths part from the FP64 ones at shared edges (each one checked to
-    # be ill-conditioned in the oracle; their gradients belong to another path
-    # and are not compared)
-    buf, *_ = _check(wl, 2, 1500, ior=1.5, target=(1.55, (0.2, 0.3, 0.4)), max_excluded=0.10,
-                     max_diverged=0.10, max_ill=0.25)
+    # thin walls make near-critical hits frequent (held to the FP32 rounding
+    # bound, like every pixel), and over 8 bounces some FP32 paths part from
+    # the FP64 ones at shared edges (each one checked to be ill-conditioned
+    # in the oracle; their gradients belong to another path and are not
+    # compared)
+    buf, *_ = _check(wl, 2, 1500, ior=1.5, target=(1.55, (0.2, 0.3, 0.4)))
     st = buf.stats.cpu().numpy()
     _print("thin shell: BVH height", st[B.STAT_BVH_DEPTH], "total rays", st[B.STAT_TOTAL])

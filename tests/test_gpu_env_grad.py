@@ -1,13 +1,14 @@
 """Parity of the gradient with respect to the equirect environment's texels
 (rays leaving the object take a bilinear lookup, Sec. 3.2-3.3) between the
-HIP path and the FP64 oracle: relative L2 error of dLoss/dtexel within 1e-3,
-and Euler's identity (the image is linear in the map) on the device."""
+HIP path and the FP64 oracle: dLoss/dtexel within 1e-3, element by element
+(against max(|o|, 0.1 rms)) and as a whole-array L2 ratio, and Euler's
+identity (the image is linear in the map) on the device."""
 import numpy as np
 import pytest
 import torch
 
 from paper_2603_00413_amd import binding as B
-from tests.gpu_helpers import BAD, HARD, KINK, icosphere_pair, torus_pair
+from tests.gpu_helpers import GradRef, check_elements, check_radiance, gradient_pixels, icosphere_pair, torus_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -25,20 +26,20 @@ def _with_tex_grad(P):
 
 def _check(P, seed):
     buf, rgb, wt, fl = P.gpu_forward(tape=True)
-    ref = P.orc.trace(P.o, P.d)
-    ok = ((fl | ref["flags"]) & (BAD | HARD)) == 0
-    ok &= (ref["flags"] & KINK) == 0
-    ok &= P.sig == ref["sig"]
+    chk = check_radiance(P.orc, P.o, P.d, rgb, fl, P.sig, label="texel gradient scene")
+    gr = GradRef(P.orc, P.o, P.d, chk["ref"]["sig"])
+    ok = gradient_pixels(chk, fl, gr.stable)
     g = np.random.default_rng(seed).normal(size=rgb.shape) * ok[:, None]
     P.gpu_backward(buf, g)
     dt = P.env.d_texels.cpu().numpy().astype(np.float64)
-    o = P.orc.trace_grad(P.o, P.d, g, want_tex=True)
-    et = np.linalg.norm(dt - o["d_tex"]) / np.linalg.norm(o["d_tex"])
+    o, oa, sp = gr.grads(g, want_tex=True)
+    # texels no lookup touches have gradient 0 on both sides
+    et = check_elements(dt, o["d_tex"], oa["d_tex"], "d_tex", sp["d_tex"])
     # Euler: sum d_tex * tex = sum g . C, both from the device
     lhs = float((dt * P.tex.astype(np.float64)).sum())
     rhs = float((g * rgb).sum())
     _print("d_tex rel err", et, "euler", lhs, rhs)
-    assert et <= 1e-3
+    # d_tex: checked element by element above
     assert abs(lhs - rhs) <= 1e-4 * abs(rhs)
 
 

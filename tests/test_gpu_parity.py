@@ -1,9 +1,12 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Bars (the benchmark spec): radiance within 1e-4 relative (|g - o| / max(|o|,
-1e-3 mean(o)) per pixel-channel) away from grazing / TIR-boundary rays;
-gradients within 1e-3 relative (dV as a whole-array L2 ratio, dIoR and each
-dsigma_c as scalars).  Index work (BVH vs brute force) is bit-exact.
+1e-3 mean(o)) per pixel-channel) wherever FP32 can resolve it, and otherwise
+within the oracle's first-order bound on the rounding error of an FP32
+evaluation of the pixel (grazing and near-critical rays included);
+gradients within 1e-3 relative: dV element by element against max(|o|,
+0.1 rms) and as a whole-array L2 ratio, dIoR and each dsigma_c as scalars.
+Index work (BVH vs brute force) is bit-exact.
 """
 import numpy as np
 import pytest
@@ -12,8 +15,10 @@ import torch
 import oracle
 from paper_2603_00413_amd import binding as B
 from paper_2603_00413_amd import synth
-from tests.gpu_helpers import (BAD, DV_ORDER_TOL, HARD, KINK, Pair, device, icosphere_pair,
-                               l2_upstream, path_ill_conditioned, rel_err, torus_pair)
+from tests.gpu_helpers import (BAD, DV_ORDER_TOL, HARD, KINK, GradRef, Pair, check_elements, check_material,
+                               check_radiance,
+                               device, gradient_pixels, icosphere_pair, l2_upstream,
+                               path_ill_conditioned, rel_err, torus_pair)
 
 pytestmark = pytest.mark.gpu
 
@@ -196,23 +201,9 @@ def test_env_query_and_backward():
 def test_forward_icosphere(sigma):
     P = icosphere_pair(sigma=sigma)
     _, rgb, wt, fl = P.gpu_forward(tape=False)
-    ref = P.orc.trace(P.o, P.d)
-    assert not (fl & HARD).any()
-    ok = ((fl | ref["flags"]) & BAD) == 0
-    err = rel_err(rgb, ref["rgb"])
-    same = P.sig == ref["sig"]
-    _print("C1 sigma", sigma, "excluded", 1 - ok.mean(), "max err", err[ok].max(),
-           "paths differing", (~same[ok]).sum())
-    assert 1 - ok.mean() < 0.05
-    assert err[ok].max() <= 1e-4
-    # the discrete path (triangle per segment, TIR branches) is an integer
-    # result: the same on both sides but where the oracle's own path is
-    # ill-conditioned (a hit within rounding of a shared edge)
-    div = ok & ~same
-    assert div.mean() <= 1e-3
-    if div.any():
-        assert path_ill_conditioned(P.orc, P.o[div], P.d[div], ref["sig"][div]).all()
-    np.testing.assert_allclose(wt[ok], ref["wtrunc"][ok], rtol=1e-4, atol=1e-6)
+    chk = check_radiance(P.orc, P.o, P.d, rgb, fl, P.sig, label=f"C1 sigma {sigma}")
+    w = chk["well"]
+    np.testing.assert_allclose(wt[w], chk["ref"]["wtrunc"][w], rtol=1e-4, atol=1e-6)
 
 
 def test_forward_energy_conservation():
@@ -232,38 +223,24 @@ def test_forward_energy_conservation():
 def test_forward_torus_small():
     P = torus_pair(n_views=2, res=96)
     buf, rgb, wt, fl = P.gpu_forward(tape=False)
-    ref = P.orc.trace(P.o, P.d)
-    assert not (fl & HARD).any()
-    ok = ((fl | ref["flags"]) & BAD) == 0
-    err = rel_err(rgb, ref["rgb"])
-    bad = ok[:, None] & (err > 1e-4)
-    same = P.sig == ref["sig"]
-    _print("torus excluded", 1 - ok.mean(), "max err", err[ok].max(), "n>1e-4", bad.any(1).sum(),
-           "paths differing", (~same[ok]).sum())
+    chk = check_radiance(P.orc, P.o, P.d, rgb, fl, P.sig, label="torus 2 x 96^2")
     stats = buf.stats.cpu().numpy()
-    _print("segments gpu", stats[B.STAT_TOTAL], "oracle", ref["nseg"].sum())
-    assert 1 - ok.mean() < 0.05
-    assert bad.any(1).mean() < 1e-3
-    div = ok & ~same
-    assert div.mean() < 2e-3
-    if div.any():
-        assert path_ill_conditioned(P.orc, P.o[div], P.d[div], ref["sig"][div]).all()
-    assert abs(stats[B.STAT_TOTAL] - ref["nseg"].sum()) <= 1e-3 * ref["nseg"].sum()
+    nseg = chk["ref"]["nseg"].sum()
+    _print("segments gpu", stats[B.STAT_TOTAL], "oracle", nseg)
+    assert abs(stats[B.STAT_TOTAL] - nseg) <= 1e-3 * nseg
 
 
 # ---------------------------------------------------------------- a7 gradients
 def _grad_check(P, seed=0):
     buf, rgb, wt, fl = P.gpu_forward(tape=True)
-    ref = P.orc.trace(P.o, P.d)
-    ok = ((fl | ref["flags"]) & (BAD | HARD)) == 0
-    ok &= (ref["flags"] & KINK) == 0
-    ok &= P.sig == ref["sig"]          # interior derivatives of the same discrete path
+    chk = check_radiance(P.orc, P.o, P.d, rgb, fl, P.sig, label="gradient scene")
+    gr = GradRef(P.orc, P.o, P.d, chk["ref"]["sig"])
+    ok = gradient_pixels(chk, fl, gr.stable)  # interior derivatives of the same discrete path
     g = np.random.default_rng(seed).normal(size=rgb.shape) * ok[:, None]
     dV, de, ds = P.gpu_backward(buf, g)
-    o = P.orc.trace_grad(P.o, P.d, g)
-    ev = np.linalg.norm(dV - o["dV"]) / np.linalg.norm(o["dV"])
-    ee = abs(de - o["d_eta"]) / abs(o["d_eta"])
-    es = np.abs(ds - o["d_sigma"]) / np.abs(o["d_sigma"])
+    o, oa, sp = gr.grads(g)
+    ev = check_elements(dV, o["dV"], oa["dV"], "dV", sp["dV"])
+    ee, es = check_material(de, ds, o, oa, sp, "gradient scene")
     _print("grad rel err dV", ev, "deta", ee, "dsigma", es)
     return ev, ee, es
 
@@ -272,13 +249,13 @@ def _grad_check(P, seed=0):
 def test_backward_icosphere(sigma):
     P = icosphere_pair(sigma=sigma)
     ev, ee, es = _grad_check(P)
-    assert ev <= 1e-3 and ee <= 1e-3 and (es <= 1e-3).all()
+    # dV, dIoR and dsigma: checked element by element above
 
 
 def test_backward_torus_small():
     P = torus_pair(n_views=2, res=64)
     ev, ee, es = _grad_check(P, seed=1)
-    assert ev <= 1e-3 and ee <= 1e-3 and (es <= 1e-3).all()
+    # dV, dIoR and dsigma: checked element by element above
 
 
 # ---------------------------------------------------------------- a8 recompute == store
@@ -325,34 +302,23 @@ def test_full_size_torus_sampled_pixels():
     assert st[B.STAT_DROPPED] == 0 and not (fl & HARD).any()
     rng = np.random.default_rng(7)
     pix = np.sort(rng.choice(len(P.o), 3000, replace=False))
-    ref = P.orc.trace(P.o[pix], P.d[pix])
-    ok = ((fl[pix] | ref["flags"]) & BAD) == 0
-    same = P.sig[pix] == ref["sig"]
-    err = rel_err(rgb[pix], ref["rgb"])
-    bad = ok[:, None] & (err > 1e-4)
-    _print("full-size sampled: excluded", 1 - ok.mean(), "max err", err[ok].max(),
-           "pixels over 1e-4", bad.any(1).sum(), "paths differing", (~same[ok]).sum())
-    assert 1 - ok.mean() < 0.05
-    assert bad.any(1).mean() < 2e-3
-    # a path may part only where the oracle's own path is ill-conditioned
-    div = ok & ~same
-    assert div.mean() < 5e-3
-    if div.any():
-        assert path_ill_conditioned(P.orc, P.o[pix][div], P.d[pix][div], ref["sig"][div]).all()
+    chk = check_radiance(P.orc, P.o[pix], P.d[pix], rgb[pix], fl[pix], P.sig[pix],
+                         label="torus full size, 3,000 sampled pixels")
+    ref = chk["ref"]
     # gradients where the discrete path (triangles, branches) is the same on
     # both sides and no environment lookup sits on a gradient kink
     tgt = P.orc.with_(eta=1.5, sigma=(0.25, 0.3, 0.35)).trace(P.o[pix], P.d[pix])["rgb"]
-    gmask = ok & same & ((ref["flags"] & KINK) == 0)
+    gr = GradRef(P.orc, P.o[pix], P.d[pix], ref["sig"])
+    gmask = gradient_pixels(chk, fl[pix], gr.stable)
     gs = l2_upstream(ref["rgb"], tgt, gmask)
     g = np.zeros_like(rgb)
     g[pix] = gs
     dV, de, ds = P.gpu_backward(buf, g)
-    o = P.orc.trace_grad(P.o[pix], P.d[pix], gs)
-    ev = np.linalg.norm(dV - o["dV"]) / np.linalg.norm(o["dV"])
-    ee = abs(de - o["d_eta"]) / abs(o["d_eta"])
-    es = np.abs(ds - o["d_sigma"]) / np.abs(o["d_sigma"])
+    o, oa, sp = gr.grads(gs)
+    ev = check_elements(dV, o["dV"], oa["dV"], "full-size dV", sp["dV"])
+    ee, es = check_material(de, ds, o, oa, sp, "full size")
     _print("full-size sampled grads: dV", ev, "deta", ee, "dsigma", es)
-    assert ev <= 1e-3 and ee <= 1e-3 and (es <= 1e-3).all()
+    # dV, dIoR and dsigma: checked element by element above
 
 
 # ---------------------------------------------------------------- a8 autograd.Function
