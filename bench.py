@@ -53,13 +53,13 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h",
                     "paper_2603_00413_amd/csrc/bvh.hip"],
-        "sha256": "3586e9123f84fd1844adb20db1444300699a7585700517fe9acbfb15936b5aae",
-        "bytes": (317329.1 * 2.0 + 79383.1) * 1024,
+        "sha256": "5831c67a380f31707db6932e1e02fa5e1e7497b1e41d07f87452a077fca86f58",
+        "bytes": (316782.3 * 2.0 + 79345.0) * 1024,
         # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:
         # wave-level VALU instructions per launch, and the share of lanes active
         # in them
         "valu_insts": 2.605e8,
-        "lane_utilization": 0.62,
+        "lane_utilization": 0.619,
     },
 }
 
@@ -305,9 +305,10 @@ def main():
     serving = None
     if not args.no_serve:
         serving = serving_bench(args, dev)
-    training = None
+    training = trainer = None
     if not args.no_mlp:
         training = training_step_bench(args, dev)
+        trainer = trainer_bench(args, dev)
     stress = None
     if not args.no_stress:
         stress = stress_bench(args, dev)
@@ -355,6 +356,7 @@ def main():
                             "p99": round(float(np.percentile(lat_ms, 99)), 3)},
         "serving": serving,
         "training_step_mlp": training,
+        "trainer_step_training_shape": trainer,
         "stress_thin_shell": stress,
         "absorption_grid": grid,
         "plain_forward": {"ms": round(fwd_ms, 3), "Mrays/s": round(segs / fwd_ms / 1e3, 3)},
@@ -367,6 +369,7 @@ def main():
         "kernel_ms_per_generation": {"k_trace": np.round(tr_ms, 4).tolist(),
                                      "k_adjoint": np.round(ad_ms, 4).tolist()},
         "cpu_baseline": cpu,
+        "paper_timings": PAPER_TIMINGS,
     }
     print(json.dumps(out), flush=True)
 
@@ -550,6 +553,67 @@ def training_step_bench(args, dev):
     }
 
 
+def trainer_bench(args, dev):
+    """The ray-tracing stage's optimisation step at the training-step shape
+    (`train.Trainer`): SDF union (~300k triangles), 8 views x 800^2, depth 6,
+    lit by the 3 x 64 environment MLP whose weights are trained too (bf16
+    MFMA forward, MFMA weight gradient); L_color + 0.1 L_tone against a target
+    rendered with other material parameters (eta 1.5, sigma (0.4, 0.25, 0.1)),
+    AdamUniform on the Laplacian reparameterisation of the vertices (lambda
+    20), Adam on IoR, sigma and the network; every 10th step adds the
+    periodic L_mask (outline gradient), L_edge and L_lap.  The BVH is rebuilt
+    from the updated vertices every step."""
+    import torch
+
+    from paper_2603_00413_amd import autograd as A
+    from paper_2603_00413_amd import binding as B
+    from paper_2603_00413_amd import synth
+    from paper_2603_00413_amd import train as T
+    wl = synth.sdf_union_scene()
+    Ws, Bs, n_freq = wl.mlp
+    V0 = torch.from_numpy(wl.V.astype(np.float32)).to(dev)
+    F = torch.from_numpy(wl.F).to(dev)
+    env = B.Env.mlp(Ws, Bs, n_freq, dev, want_grad=True)
+    tr = A.Tracer(F, env, wl.cameras, max_depth=wl.max_depth)
+    w0 = torch.cat([torch.as_tensor(x).reshape(-1) for x in Ws]).to(dev)
+    b0 = torch.cat([torch.as_tensor(x).reshape(-1) for x in Bs]).to(dev)
+    with torch.no_grad():
+        gt = A.render_mlp(V0, torch.tensor([1.5], device=dev), torch.tensor([0.4, 0.25, 0.1], device=dev),
+                          w0, b0, tr).clone()
+        gt_mask = A.render_mask(V0, tr).clone()
+    V = V0.clone().requires_grad_(True)
+    ior = torch.tensor([wl.ior], device=dev, requires_grad=True)
+    sigma = torch.tensor(wl.sigma, dtype=torch.float32, device=dev, requires_grad=True)
+    w = w0.clone().requires_grad_(True)
+    b = b0.clone().requires_grad_(True)
+    trainer = T.Trainer(tr, V, ior, sigma=sigma, lr=1e-3, l_color=1.0, l_tone=0.1, l_edge=0.01,
+                        l_mask=0.1, l_lap=0.01, period=10, large_steps=20.0, lr_mesh=1e-3,
+                        mlp=(w, b))
+    for _ in range(2):
+        trainer.step(gt, gt_mask)
+    torch.cuda.synchronize()
+    steps = 20
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = trainer.step(gt, gt_mask)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    st = tr.last_stats.numpy()
+    segs = int(st[B.STAT_TOTAL])
+    log(f"trainer step (training-step shape, MLP trained): {ms:.2f} ms, {segs / ms / 1e3:.1f} Mrays/s, "
+        f"loss terms {out}")
+    return {
+        "workload": "Trainer: SDF union %d tris, %d views x %d^2, depth %d, env MLP 3 x 64 trained, "
+                    "AdamUniform (lambda 20) on V, Adam on IoR / sigma / MLP, periodic L_mask + L_edge "
+                    "+ L_lap every 10 steps, BVH rebuilt every step"
+                    % (len(wl.F), len(wl.cameras), wl.cameras[0].width, wl.max_depth),
+        "ms_per_step": round(ms, 3),
+        "Mrays/s": round(segs / ms / 1e3, 3),
+        "segments_per_step": segs,
+        "checkpoint_stride": tr.stride,
+    }
+
+
 def stress_bench(args, dev):
     """The stress shape: thin-shell SDF mesh (~2M triangles, frequent TIR),
     one 2048^2 view, depth 8, environment MLP 4 x 128; forward with a tape
@@ -642,7 +706,10 @@ def stress_bench(args, dev):
 
 def serving_bench(args, dev):
     """Render server on four resident scenes under a Poisson request stream,
-    against one-request-at-a-time plain tracing of the same stream."""
+    against one-request-at-a-time plain tracing of the same stream: at
+    saturation (every request waiting at t = 0) and at offered loads of 0.3,
+    0.5, 0.7 and 0.9 of the one-at-a-time capacity."""
+    from paper_2603_00413_amd import binding as B
     from paper_2603_00413_amd import synth
     from paper_2603_00413_amd.serve import Request, Server, run_fifo
     rng = np.random.default_rng(4)
@@ -654,13 +721,18 @@ def serving_bench(args, dev):
         nf.append(len(F))
         srv.add_scene(V, F, float(rng.uniform(1.37, 1.6)), tuple(rng.uniform(0.05, 0.5, 3)),
                       synth.env_equirect(512, 256, seed=100 + k))
-    relight = [srv.add_env(synth.env_equirect(512, 256, seed=200 + k)) for k in range(4)]
-    eyes = synth.views_on_sphere(args.serve_requests, 3.0, seed=5)
+    # relight targets: two maps and two environment MLPs
+    relight = [srv.add_env(synth.env_equirect(512, 256, seed=200 + k)) for k in range(2)]
+    for k, (layers, width) in enumerate([(3, 64), (2, 128)]):
+        Wm, Bm = synth.env_mlp_weights(seed=210 + k, n_layers=layers, width=width)
+        relight.append(srv.add_env(B.Env.mlp(Wm, Bm, 6, dev)))
+    n_req = args.serve_requests
+    eyes = synth.views_on_sphere(n_req, 3.0, seed=5)
 
     def make_stream(times):
         r2 = np.random.default_rng(6)
         out = []
-        for i in range(args.serve_requests):
+        for i in range(n_req):
             res = int(r2.choice([128, 256, 512, 1024]))
             sc = int(r2.integers(0, 4))
             env = None if r2.uniform() < 0.7 else relight[int(r2.integers(0, 4))]
@@ -668,44 +740,93 @@ def serving_bench(args, dev):
                                int(r2.integers(4, 9)), env, arrival=float(times[i])))
         return out
 
-    # one-at-a-time capacity: the same requests back to back
-    warm = make_stream(np.zeros(args.serve_requests))[:16]
-    run_fifo(srv, warm, realtime=False)
-    solo = make_stream(np.zeros(args.serve_requests))
-    t = time.perf_counter()
-    _, traced_solo = run_fifo(srv, solo, realtime=False)
-    solo_s = time.perf_counter() - t
-    mu = args.serve_requests / solo_s
-    lam = args.serve_load * mu
-    arrivals = np.cumsum(np.random.default_rng(7).exponential(1.0 / lam, args.serve_requests))
-    log(f"serving: scenes {nf} faces; one-at-a-time {mu:.1f} req/s; offered {lam:.1f} req/s")
+    def pct(reqs, q):
+        return round(float(np.percentile(np.array([r.latency for r in reqs]) * 1e3, q)), 3)
 
+    # one-at-a-time capacity: the same requests back to back
+    warm = make_stream(np.zeros(n_req))[:16]
+    run_fifo(srv, warm, realtime=False)
+    srv.run(make_stream(np.zeros(n_req))[:16], realtime=True)
     t = time.perf_counter()
-    served = srv.run(make_stream(arrivals), realtime=True)
-    span = time.perf_counter() - t
-    assert srv.dropped == 0
-    lat = np.array([r.latency for r in served]) * 1e3
+    _, traced_solo = run_fifo(srv, make_stream(np.zeros(n_req)), realtime=False)
+    solo_s = time.perf_counter() - t
+    mu = n_req / solo_s
+    # saturation: the whole stream waiting at t = 0
     t = time.perf_counter()
-    fifo, traced_fifo = run_fifo(srv, make_stream(arrivals), realtime=True)
-    span_f = time.perf_counter() - t
-    lat_f = np.array([r.latency for r in fifo]) * 1e3
-    out = {
+    sat = srv.run(make_stream(np.zeros(n_req)), realtime=True)
+    sat_s = time.perf_counter() - t
+    assert all(r.image is not None for r in sat)
+    saturation = {"server_Mrays/s": round(srv.traced / sat_s / 1e6, 2),
+                  "server_requests_per_s": round(n_req / sat_s, 2),
+                  "server_retries": srv.retries,
+                  "fifo_Mrays/s": round(traced_solo / solo_s / 1e6, 2),
+                  "fifo_requests_per_s": round(mu, 2)}
+    log(f"serving: scenes {nf} faces; saturation: server {saturation['server_Mrays/s']} Mrays/s "
+        f"({saturation['server_requests_per_s']} req/s), one at a time {saturation['fifo_Mrays/s']} "
+        f"Mrays/s ({mu:.1f} req/s)")
+    sweep = []
+    for load in (0.3, 0.5, 0.7, 0.9):
+        lam = load * mu
+        arrivals = np.cumsum(np.random.default_rng(7).exponential(1.0 / lam, n_req))
+        t = time.perf_counter()
+        served = srv.run(make_stream(arrivals), realtime=True)
+        span = time.perf_counter() - t
+        t = time.perf_counter()
+        fifo, traced_fifo = run_fifo(srv, make_stream(arrivals), realtime=True)
+        span_f = time.perf_counter() - t
+        row = {"load": load, "requests_per_s_offered": round(lam, 2),
+               "p50_ms": pct(served, 50), "p99_ms": pct(served, 99),
+               "Mrays/s": round(srv.traced / span / 1e6, 2), "device_steps": srv.steps,
+               "retries": srv.retries,
+               "fifo_p50_ms": pct(fifo, 50), "fifo_p99_ms": pct(fifo, 99),
+               "fifo_Mrays/s": round(traced_fifo / span_f / 1e6, 2)}
+        sweep.append(row)
+        log(f"serving load {load}: p50 {row['p50_ms']} / p99 {row['p99_ms']} ms, {row['Mrays/s']} Mrays/s; "
+            f"fifo p50 {row['fifo_p50_ms']} / p99 {row['fifo_p99_ms']} ms")
+    head = next(r for r in sweep if r["load"] == args.serve_load) if args.serve_load in (0.3, 0.5, 0.7, 0.9) \
+        else sweep[2]
+    return {
         "workload": "4 resident SDF-union scenes (%s tris), Poisson stream of %d requests "
-                    "(70%% render / 30%% relight, 128^2-1024^2, depth 4-8), offered load %.2f of "
-                    "one-at-a-time capacity" % ("/".join(str(x) for x in nf), args.serve_requests,
-                                                 args.serve_load),
-        "requests_per_s_offered": round(lam, 2),
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "Mrays/s": round(srv.traced / span / 1e6, 2),
-        "device_steps": srv.steps,
-        "fifo_plain_tracer": {"p50_ms": round(float(np.percentile(lat_f, 50)), 3),
-                              "p99_ms": round(float(np.percentile(lat_f, 99)), 3),
-                              "Mrays/s": round(traced_fifo / span_f / 1e6, 2)},
+                    "(70%% render / 30%% relight on 2 maps and 2 MLPs, 128^2-1024^2, depth 4-8)"
+                    % ("/".join(str(x) for x in nf), n_req),
+        "load": head["load"],
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "Mrays/s": head["Mrays/s"],
+        "fifo_plain_tracer": {"p50_ms": head["fifo_p50_ms"], "p99_ms": head["fifo_p99_ms"],
+                              "Mrays/s": head["fifo_Mrays/s"]},
+        "saturation": saturation,
+        "load_sweep": sweep,
     }
-    log(f"serving: p50 {out['p50_ms']} ms p99 {out['p99_ms']} ms {out['Mrays/s']} Mrays/s; "
-        f"fifo p50 {out['fifo_plain_tracer']['p50_ms']} ms p99 {out['fifo_plain_tracer']['p99_ms']} ms")
-    return out
+
+
+def host_cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# The paper's own timings, with the hardware they were taken on (its appendix
+# on computational and training efficiency, and on implementation details):
+# one NVIDIA RTX 3090 (24 GB) beside an Intel Core i7-10700K; training a scene
+# takes 1-2 hours with batches of 5,000 rays and at most 4 bounces (8 at
+# inference), using about 20 GB of GPU memory.  It states no rays-per-second
+# figure, so there is no number for vs_baseline.
+PAPER_TIMINGS = {
+    "hardware": "1x NVIDIA RTX 3090 (24 GB), Intel Core i7-10700K, 64 GB RAM",
+    "training_time_per_scene_h": [1, 2],
+    "rays_per_batch": 5000,
+    "max_bounces_training": 4,
+    "max_bounces_inference": 8,
+    "training_gpu_memory_GB": 20,
+    "rays_per_second": None,
+}
 
 
 def cpu_baseline(wl, stride):
@@ -730,7 +851,7 @@ def cpu_baseline(wl, stride):
     el = time.perf_counter() - t
     log(f"cpu baseline: {len(o)} camera rays, {segs} segments, {el:.1f} s")
     return {"value": round(segs / el / 1e6, 4), "unit": "Mrays/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": host_cpu_model(),
             "sample": f"every {stride}th pixel in x and y of all {len(wl.cameras)} views "
                       f"({len(o)} camera rays, {segs} segments); FP64 forward + reverse-mode "
                       f"gradient in one pass per camera ray",

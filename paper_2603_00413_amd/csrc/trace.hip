@@ -290,7 +290,7 @@ template <bool GRID, bool FIELD>
 __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
                                               int32_t* flags, unsigned long long* sig,
-                                              int accumulate, uint2* ovf, WorkPart* wp) {
+                                              int accumulate, uint2* ovf, WorkPart* wp, float4* att) {
   __shared__ uint2 stk[DT_STACK_LDS * TB];
   __shared__ LeafQueue lq;
   uint2* gstk = ovf + (size_t)(blockIdx.x * TB + threadIdx.x) * (DT_STACK - DT_STACK_LDS);
@@ -350,6 +350,11 @@ __global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Coun
         Shade s = shade<GRID, FIELD>(sc, geo, o, d, h.t, h.b1, h.b2, 0u);
         if constexpr (FIELD) {
           if (accumulate && (s.code & C_ENTER)) add_rgb(rgb, pix, mul3(W, s.Cem));
+        }
+        // the segment's attenuation (a sum over samples of the grid or the
+        // field) handed to k_emit
+        if constexpr (GRID || FIELD) {
+          if (att) att[i] = make_float4(s.A.x, s.A.y, s.A.z, 0.f);
         }
         code = s.code;
         if (code & C_DEGEN) pf |= DT_FLAG_DEGEN;
@@ -432,7 +437,7 @@ __global__ void k_scan(Counters* ctr, int g, unsigned long long* part, unsigned 
 template <bool GRID, bool FIELD>
 __global__ void __launch_bounds__(EB) k_emit(SceneDev sc, Gen q, Gen nx, int g, Counters* ctr,
                                              const unsigned long long* part, int64_t cap_next,
-                                             int write_rays, int32_t* flags) {
+                                             int write_rays, int32_t* flags, const float4* att) {
   __shared__ uint32_t wr[EB / 64], wt[EB / 64];
   const uint32_t n = ctr->count[g];
   const int64_t base = (int64_t)blockIdx.x * CHUNK;
@@ -472,7 +477,19 @@ __global__ void __launch_bounds__(EB) k_emit(SceneDev sc, Gen q, Gen nx, int g, 
         int pix = __float_as_int(d4.w);
         int tri = __float_as_int(h4.y);
         HitGeo geo = load_geo(sc, tri);
-        Shade sh = shade<GRID, FIELD>(sc, geo, o, d, h4.x, h4.z, h4.w, code);
+        Shade sh;
+        if constexpr (GRID || FIELD) {
+          if (att) {
+            // the decisions from the code and the attenuation k_trace computed
+            // (bit for bit what shade<GRID, FIELD> gives here)
+            sh = shade<false, false>(sc, geo, o, d, h4.x, h4.z, h4.w, code);
+            sh.A = xyz(att[i]);
+          } else {
+            sh = shade<GRID, FIELD>(sc, geo, o, d, h4.x, h4.z, h4.w, code);
+          }
+        } else {
+          sh = shade<false, false>(sc, geo, o, d, h4.x, h4.z, h4.w, code);
+        }
         v3 wa = mul3(W, sh.A);
         bool entering = (code & C_ENTER) != 0u;
         if (hr) {
@@ -1426,11 +1443,12 @@ dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen 
                          WorkPart* wp, unsigned long long* part_g, unsigned long long* part_other, float* rgb,
                          float* wtrunc, int32_t* flags, unsigned long long* sig, int accumulate,
                          int write_next, void* const* events, void* const* mlp_events,
-                         uint32_t* miss_list, uint2* ovf, hipStream_t s) {
+                         uint32_t* miss_list, uint2* ovf, float4* att, hipStream_t s) {
+  if (!sc.ab.mu && !sc.fd.grid) att = nullptr;  // the constant rate: recomputing it is cheaper
   if (dt_status st = record(events, 2 * g, s)) return st;
 #define DT_TRACE(G, FL)                                                                              \
   hipLaunchKernelGGL((k_trace<G, FL>), dim3(trace_grid(P.cap[g])), dim3(TB), 0, s, sc, cur, g, ctr, part_g, \
-                     rgb, wtrunc, flags, sig, accumulate, ovf, wp)
+                     rgb, wtrunc, flags, sig, accumulate, ovf, wp, att)
   if (sc.fd.grid) {
     if (sc.ab.mu) DT_TRACE(true, true); else DT_TRACE(false, true);
   } else {
@@ -1453,7 +1471,7 @@ dt_status run_generation(const SceneDev& sc, const Plan& P, int g, Gen cur, Gen 
     int64_t nch = (P.cap[g] + CHUNK - 1) / CHUNK;
 #define DT_EMIT(G, FL)                                                                                 \
   hipLaunchKernelGGL((k_emit<G, FL>), dim3((unsigned)nch), dim3(EB), 0, s, sc, cur, nxt, g, ctr, part_g, \
-                     P.cap[g + 1], write_next, accumulate ? flags : nullptr)
+                     P.cap[g + 1], write_next, accumulate ? flags : nullptr, att)
     if (sc.fd.grid) {
       if (sc.ab.mu) DT_EMIT(true, true); else DT_EMIT(false, true);
     } else {
@@ -1636,7 +1654,8 @@ extern "C" dt_status dt_trace_forward(const dt_scene* scene, const dt_rays* rays
     if (dt_status st = run_generation(sc, P, g, cur, nxt, ctr, (WorkPart*)(W + P.w_parts), part[g & 1],
                                       part[(g + 1) & 1], rgb,
                                       wtrunc, flags, (unsigned long long*)path_sig, 1, 1, ev, mev,
-                                      (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), s))
+                                      (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf),
+                                      (float4*)(W + P.w_adj[0][0]), s))
       return st;
   }
   if (T) hipLaunchKernelGGL(k_save_counters, dim3(1), dim3(64), 0, s, (Counters*)(T + P.tape_hdr), ctr);
@@ -1792,6 +1811,9 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
       seg[0].w = (float4*)(T + P.t_w[g0]);
       hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, s, g0, (WorkPart*)(W + P.w_parts));
       if (dt_status st = zero_u64(part[g0 & 1], P.maxchunks + 1, s)) return st;
+      // adj[(g1 + 1) & 1] holds generation g1 + 1's adjoint records, which the
+      // segment's first adjoint reads; adj[g1 & 1] is free until it writes
+      // it, and carries the attenuation from k_trace to k_emit meanwhile
       for (int g = g0; g <= g1; ++g) {
         int j = g - g0;
         Gen nxt = g < g1 ? seg[j + 1] : seg[j];
@@ -1799,7 +1821,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
                                           part[g & 1], part[(g + 1) & 1],
                                           nullptr, nullptr, nullptr, nullptr, 0, g < g1 ? 1 : 0,
                                           nullptr, nullptr,
-                                          (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), s))
+                                          (uint32_t*)(W + P.w_miss), (uint2*)(W + P.w_ovf), adj[g1 & 1].L, s))
           return st;
       }
       for (int g = g1; g >= g0; --g)

@@ -93,8 +93,11 @@ def _grad_check(P, seed):
     return ev, ee, em, buf, g, (dV, de, dmu)
 
 
-def test_backward_icosphere_grid():
-    P = _with_grid(icosphere_pair(), seed=3, samples=8)
+# grid shapes: small, 40 x 40 x 20 nodes, and 100 x 90 x 3 (a node plane of
+# 27,000 values)
+@pytest.mark.parametrize("n", [(6, 5, 7), (40, 40, 20), (100, 90, 3)])
+def test_backward_icosphere_grid(n):
+    P = _with_grid(icosphere_pair(), seed=3, samples=8, n=n)
     ev, ee, em, _, _, _ = _grad_check(P, seed=4)
     # dV, dmu and dIoR: checked element by element above
 
