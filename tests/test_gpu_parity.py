@@ -358,3 +358,56 @@ def test_autograd_function_and_memory_policy():
         out1.sum().backward()
     k = choose_stride(6, 1 << 20, 51200, 102400, 2 << 20, 1 << 62)
     assert k == 1
+
+
+# ---------------------------------------------------------------- ragged sizes and shallow depths
+@pytest.mark.parametrize("depth", [1, 6])
+@pytest.mark.parametrize("terminal_env", [False, True])
+def test_ragged_cameras(depth, terminal_env):
+    """Cameras whose sizes are not multiples of the 8 x 8 ray tile (37 x 23
+    and 5 x 3: the last wave, block and compaction chunk of every generation
+    are partial), at depths 1 and 6, with and without terminal_env:
+    radiance and gradients against the oracle."""
+    wl = synth.icosphere_scene(sigma=(0.5, 0.2, 0.1), res=64)
+    eyes = synth.views_on_sphere(2, 3.0, seed=13)
+    cams = [synth.look_at_camera(eyes[0], 37, 23), synth.look_at_camera(eyes[1], 5, 3)]
+    P = Pair(wl.V, wl.F, wl.ior, wl.sigma, wl.env, cams, depth, terminal_env=terminal_env)
+    assert P.rays.n_rays == 37 * 23 + 15
+    _grad_check(P, seed=depth + 2 * terminal_env)
+
+
+@pytest.mark.parametrize("terminal_env", [False, True])
+def test_depth_zero(terminal_env):
+    """Depth 0: every hit is truncated at once.  A pixel is its miss's
+    environment radiance, or 0 (terminal_env: the environment seen through
+    no attenuation, the camera ray having travelled outside); nothing depends
+    on the vertices or the material, so every gradient is exactly 0."""
+    wl = synth.icosphere_scene(sigma=(0.5, 0.2, 0.1), res=32)
+    P = Pair(wl.V, wl.F, wl.ior, wl.sigma, wl.env, wl.cameras, 0, terminal_env=terminal_env)
+    buf, rgb, wt, fl = P.gpu_forward(tape=True)
+    check_radiance(P.orc, P.o, P.d, rgb, fl, P.sig, label=f"depth 0, terminal_env {terminal_env}")
+    hit = (fl & B.FLAG_TRUNC) != 0
+    assert hit.any() and (~hit).any()
+    if not terminal_env:
+        assert np.all(rgb[hit] == 0.0)
+    g = np.random.default_rng(5).normal(size=rgb.shape)
+    dV, de, ds = P.gpu_backward(buf, g)
+    assert np.all(dV == 0.0) and de == 0.0 and np.all(ds == 0.0)
+
+
+@pytest.mark.parametrize("n", [1, 65])
+def test_explicit_rays(n):
+    """Explicit ray lists of 1 and 65 rays (one full wave plus one lane):
+    radiance against the oracle ray by ray."""
+    dev = device()
+    wl = synth.icosphere_scene(sigma=(0.5, 0.2, 0.1), res=32)
+    P = Pair(wl.V, wl.F, wl.ior, wl.sigma, wl.env, wl.cameras, wl.max_depth)
+    rng = np.random.default_rng(n)
+    idx = rng.choice(len(P.o), n, replace=False)
+    o32, d32 = P.o[idx].astype(np.float32), P.d[idx].astype(np.float32)
+    rays = B.Rays(o=torch.from_numpy(o32).to(dev), d=torch.from_numpy(d32).to(dev))
+    buf = B.Buffers(P.params, rays, P.mesh, tape=False)
+    sig = torch.empty(n, dtype=torch.int64, device=dev)
+    rgb, _, fl = B.dt_trace_forward(P.scene, rays, P.params, buf, path_sig=sig)
+    check_radiance(P.orc, o32.astype(np.float64), d32.astype(np.float64), rgb.cpu().numpy().astype(np.float64),
+                   fl.cpu().numpy(), sig.cpu().numpy().view(np.uint64), label=f"{n} explicit rays")

@@ -55,7 +55,8 @@ def test_mask_and_outline_gradient(which):
         n = c.width * c.height
         mo = orc.mask(c)
         # centre samples: the same hit or miss but where the oracle's own first
-        # hit changes under a 1e-5 rad turn (a ray grazing the outline)
+        # hit changes when the rays are jittered by eight float32 ulps (a ray
+        # grazing the outline)
         diff = np.flatnonzero(mask[off:off + n] != mo)
         if diff.size:
             o, d = oracle.camera_rays(c)
