@@ -314,7 +314,7 @@ class GradRef:
         return o, a, s
 
 
-def check_elements(g, o, a, name, spread=None, tol=1e-3, floor_frac=None):
+def check_elements(g, o, a, name, spread=None, tol=1e-3, floor_frac=None, allow_zero=False):
     """Element by element: every entry of the device gradient within
     tol * a + SPREAD_MARGIN * spread of the oracle's, where a = the sum over
     camera rays of the magnitudes of each ray's contribution to that entry
@@ -325,7 +325,10 @@ def check_elements(g, o, a, name, spread=None, tol=1e-3, floor_frac=None):
     tol * floor_frac * the RMS of the array's nonzero entries (for arrays whose
     arithmetic error is relative to the array's scale rather than to each
     entry).  Also the whole-array L2 distance, within
-    tol ||o|| + SPREAD_MARGIN ||spread||.  Returns the L2 ratio ||g - o|| / ||o||."""
+    tol ||o|| + SPREAD_MARGIN ||spread||.  An oracle gradient that is exactly
+    zero is an error (nothing would be compared) unless allow_zero, and then
+    the device's must be exactly zero too.  Returns the L2 ratio
+    ||g - o|| / ||o||."""
     g, o, a = (np.asarray(x, np.float64).ravel() for x in (g, o, a))
     s = np.zeros_like(o) if spread is None else np.asarray(spread, np.float64).ravel()
     assert (a >= np.abs(o) * (1 - 1e-12)).all()
@@ -336,6 +339,10 @@ def check_elements(g, o, a, name, spread=None, tol=1e-3, floor_frac=None):
         allow = np.maximum(allow, tol * floor_frac * np.sqrt(np.mean(o[nz] ** 2)) if nz.any() else 0.0)
     r = np.abs(g - o) / np.maximum(allow, 1e-300)
     on = np.linalg.norm(o)
+    if on == 0 and allow_zero:
+        assert np.all(g == 0.0) and np.all(a == 0.0), f"{name}: the oracle's gradient is zero, the device's not"
+        print(f"{name}: zero on both sides", flush=True)
+        return 0.0
     assert on > 0, f"{name}: the oracle's gradient is zero: nothing is compared"
     l2 = np.linalg.norm(g - o) / on
     l2_allow = tol + SPREAD_MARGIN * np.linalg.norm(s) / on
@@ -355,6 +362,8 @@ def check_material(de, ds, o, a, s, label, sigma=True):
     check_elements(np.array([de]), np.array([o["d_eta"]]), np.array([a["d_eta"]]), f"{label} d_eta",
                    np.array([s["d_eta"]]))
     if sigma:
-        check_elements(ds, o["d_sigma"], a["d_sigma"], f"{label} d_sigma", s["d_sigma"])
+        # zero where no interior segment reaches the image (depth 1 without
+        # terminal_env: the rays inside end at the cap)
+        check_elements(ds, o["d_sigma"], a["d_sigma"], f"{label} d_sigma", s["d_sigma"], allow_zero=True)
     return (abs(de - o["d_eta"]) / abs(o["d_eta"]),
             np.abs(ds - o["d_sigma"]) / np.maximum(np.abs(o["d_sigma"]), 1e-300))

@@ -18,7 +18,7 @@ from paper_2603_00413_amd import synth
 from tests.gpu_helpers import (BAD, DV_ORDER_TOL, HARD, KINK, GradRef, Pair, check_elements, check_material,
                                check_radiance,
                                device, gradient_pixels, icosphere_pair, l2_upstream,
-                               path_ill_conditioned, rel_err, torus_pair)
+                               rel_err, torus_pair)
 
 pytestmark = pytest.mark.gpu
 
