@@ -55,6 +55,7 @@ typedef int32_t dt_status;
 #define DT_ERR_CAPACITY 3
 #define DT_ERR_HIP 4
 #define DT_ERR_UNSUPPORTED 5
+#define DT_ERR_NOT_CONVERGED 6
 
 /* per-pixel flags (bit set if any node of the pixel's ray tree had it) */
 #define DT_FLAG_DEGEN 1     /* shading normal faced away; geometric normal used */
@@ -337,6 +338,28 @@ dt_status dt_trace_backward(const dt_scene* sc, const dt_rays* rays, const dt_tr
                             const float* grad_rgb, const void* tape, size_t tape_bytes,
                             float* dV, float* d_ior, float* d_sigma, void* ws, size_t ws_bytes,
                             void* stream);
+
+/* ------------------------------------------------- vertex reparameterisation */
+
+/* The mesh optimiser's reparameterisation of the vertices, u = (I + lambda L) V
+ * with L the combinatorial Laplacian D - A of the mesh's edge graph (the
+ * preconditioned vertex update the appendix's training scheme takes from the
+ * large-steps method it cites): solves (I + lambda L) x = b for the three
+ * coordinate columns by conjugate gradients on the device.  adj_off
+ * [nv + 1], adj [adj_off[nv]]: each vertex's neighbours along edges (int32,
+ * device, each undirected edge listed from both ends, no repeats).  b, x:
+ * device float64 [nv][3]; x holds the starting guess on entry and the
+ * solution on return.  Stops when every column's residual is within tol of
+ * |b| (read back every 16 iterations: this call waits for the device, unlike
+ * the others), or after max_iters iterations, returning DT_ERR_NOT_CONVERGED
+ * then with x the last iterate.  iters_out, resid_out (HOST, may be NULL): the
+ * iterations run and the largest relative residual.  The sums are reduced in
+ * a fixed order, so the solve is bit-reproducible. */
+dt_status dt_smooth_bytes(int32_t nv, size_t* ws_bytes);
+dt_status dt_smooth_solve(const int32_t* adj_off, const int32_t* adj, int32_t nv, double lambda,
+                          const double* b, double* x, double tol, int32_t max_iters,
+                          int32_t* iters_out, double* resid_out, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* ---------------------------------------------------------- silhouette */
 

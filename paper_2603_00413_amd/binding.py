@@ -20,6 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdifftrans.so")
 
 DT_OK = 0
+(DT_ERR_INVALID_ARGUMENT, DT_ERR_WORKSPACE_TOO_SMALL, DT_ERR_CAPACITY, DT_ERR_HIP, DT_ERR_UNSUPPORTED,
+ DT_ERR_NOT_CONVERGED) = 1, 2, 3, 4, 5, 6
 FLAG_DEGEN, FLAG_LEAK, FLAG_GRAZING, FLAG_TIRB, FLAG_TRUNC, FLAG_OVERFLOW, FLAG_STACK = \
     1, 2, 4, 8, 16, 32, 64
 MAX_DEPTH = 16
@@ -88,7 +90,7 @@ _lib = None
 EXPORTS = ["dt_bvh_bytes", "dt_build_bvh", "dt_build_bvh_noalloc", "dt_bvh_vertex_normals", "dt_env_query",
            "dt_env_query_backward", "dt_trace_bytes", "dt_trace_forward", "dt_trace_backward",
            "dt_intersect", "dt_mask_bytes", "dt_mask_forward", "dt_mask_backward",
-           "dt_status_string", "dt_last_error"]
+           "dt_smooth_bytes", "dt_smooth_solve", "dt_status_string", "dt_last_error"]
 
 
 def load(path: str = LIB_PATH):
@@ -117,6 +119,9 @@ def load(path: str = LIB_PATH):
     L.dt_mask_forward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), C.c_float, vp, vp]
     L.dt_mask_backward.argtypes = [C.POINTER(_Scene), C.POINTER(_Rays), vp, C.c_float, vp, vp, vp,
                                    C.c_size_t, vp]
+    L.dt_smooth_bytes.argtypes = [i32, sz]
+    L.dt_smooth_solve.argtypes = [vp, vp, i32, C.c_double, vp, vp, C.c_double, i32, C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_double), vp, C.c_size_t, vp]
     L.dt_status_string.argtypes = [i32]
     L.dt_status_string.restype = C.c_char_p
     L.dt_last_error.restype = C.c_char_p
@@ -545,3 +550,39 @@ class MaskGrad:
                                        C.c_float(rho), _ptr(dV), _ptr(self.counts), _ptr(self.ws),
                                        self.ws.numel(), _stream(mesh.V.device)))
         return dV
+
+
+# ------------------------------------------------------------------ vertex reparameterisation
+class Smooth:
+    """(I + lam L) x = b on the device for one mesh topology, L the
+    combinatorial Laplacian of its edge graph given as a CSR adjacency
+    (adj_off [nv + 1], adj: int32 neighbour lists, both ends of every edge)."""
+
+    def __init__(self, adj_off: torch.Tensor, adj: torch.Tensor, lam: float):
+        _dev_check(adj_off, adj)
+        if adj_off.dtype != torch.int32 or adj.dtype != torch.int32:
+            raise DTError("Smooth: the adjacency must be int32")
+        self.adj_off, self.adj, self.lam = adj_off.contiguous(), adj.contiguous(), float(lam)
+        self.nv = adj_off.numel() - 1
+        n = C.c_size_t()
+        _check(load().dt_smooth_bytes(self.nv, C.byref(n)))
+        self.ws = _bytes(n.value, adj.device)
+        self.iters, self.resid = 0, 0.0
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor, tol: float = 1e-10, max_iters: int = 1000) -> torch.Tensor:
+        """Solves in place into x (float64 [nv, 3], holding the starting guess)
+        and returns it; self.iters / self.resid: the iterations run and the
+        final relative residual.  Raises DTError when the solve does not
+        converge within max_iters."""
+        b = b.contiguous()
+        _dev_check(b, x)
+        if b.dtype != torch.float64 or x.dtype != torch.float64 or b.shape != (self.nv, 3) or x.shape != b.shape \
+                or not x.is_contiguous():
+            raise DTError("Smooth.solve: b and x must be float64 [nv, 3], x contiguous")
+        it, res = C.c_int32(), C.c_double()
+        st = load().dt_smooth_solve(_ptr(self.adj_off), _ptr(self.adj), self.nv, self.lam, _ptr(b), _ptr(x),
+                                    tol, max_iters, C.byref(it), C.byref(res), _ptr(self.ws), self.ws.numel(),
+                                    _stream(x.device))
+        self.iters, self.resid = it.value, res.value
+        _check(st)
+        return x

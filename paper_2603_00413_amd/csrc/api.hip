@@ -25,6 +25,7 @@ extern "C" const char* dt_status_string(dt_status s) {
     case DT_ERR_CAPACITY: return "ray queue capacity exceeded";
     case DT_ERR_HIP: return "HIP runtime error";
     case DT_ERR_UNSUPPORTED: return "unsupported";
+    case DT_ERR_NOT_CONVERGED: return "not converged";
     default: return "unknown status";
   }
 }

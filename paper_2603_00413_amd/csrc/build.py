@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "libdifftrans.so")
-SOURCES = ["api.hip", "bvh.hip", "trace.hip", "env_mlp.hip", "serve.hip", "mask.hip"]
+SOURCES = ["api.hip", "bvh.hip", "trace.hip", "env_mlp.hip", "serve.hip", "mask.hip", "smooth.hip"]
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -34,6 +34,7 @@ from __future__ import annotations
 import torch
 
 from . import autograd as A
+from . import binding as B
 
 
 def color_loss(pred: torch.Tensor, gt: torch.Tensor) -> torch.Tensor:
@@ -251,44 +252,32 @@ def laplacian(nv: int, F: torch.Tensor) -> torch.Tensor:
     return torch.sparse_coo_tensor(idx, val, (nv, nv)).coalesce()
 
 
-def solve_spd(matvec, b: torch.Tensor, iters: int = 1000, tol: float = 1e-10,
-              x0: torch.Tensor | None = None, check_every: int = 16) -> torch.Tensor:
-    """Conjugate gradients for A x = b (A symmetric positive definite, given as
-    matvec), column by column of b [n, k], to a residual of tol * |b| per
-    column, from x0 (default 0).  The residual is read back every
-    `check_every` iterations (each read waits for the device).  Raises
-    RuntimeError when `iters` iterations do not get there (a mesh taken from
-    an unconverged solve would be silently wrong)."""
-    x = torch.zeros_like(b) if x0 is None else x0.clone()
-    r = b - matvec(x)
-    p = r.clone()
-    rs = (r * r).sum(0)
-    b2 = (b * b).sum(0).clamp_min(1e-300)
-    lim = tol * tol * b2
-    for it in range(iters):
-        if it % check_every == 0 and bool((rs <= lim).all()):
-            return x
-        Ap = matvec(p)
-        alpha = rs / (p * Ap).sum(0).clamp_min(1e-300)
-        x = x + alpha * p
-        r = r - alpha * Ap
-        rs_new = (r * r).sum(0)
-        p = r + (rs_new / rs.clamp_min(1e-300)) * p
-        rs = rs_new
-    if bool((rs <= lim).all()):
-        return x
-    worst = float((rs / b2).sqrt().max())
-    raise RuntimeError(f"solve_spd: relative residual {worst:.3e} above {tol:.1e} "
-                       f"after {iters} conjugate-gradient iterations")
+def adjacency_csr(nv: int, F: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor]:
+    """The edge graph as int32 CSR: off [nv + 1], adj [2 m] with vertex i's
+    neighbours (ascending) in adj[off[i]:off[i + 1]], every edge from both ends."""
+    e = mesh_edges(F)
+    i = torch.cat([e[:, 0], e[:, 1]])
+    j = torch.cat([e[:, 1], e[:, 0]])
+    order = torch.argsort(i * nv + j)
+    off = torch.zeros(nv + 1, dtype=torch.int64, device=F.device)
+    off[1:] = torch.cumsum(torch.bincount(i, minlength=nv), 0)
+    return off.to(torch.int32), j[order].to(torch.int32)
 
 
 class LargeSteps:
-    """u = (I + lam L) V and back, for one mesh."""
+    """u = (I + lam L) V and back, for one mesh on the device; the solve runs
+    in the library's conjugate-gradient kernels (float64, to a relative
+    residual of 1e-10 per coordinate column), each from the previous solve of
+    its kind: vertices from the last vertices, a gradient from the last
+    gradient."""
 
-    def __init__(self, nv: int, F: torch.Tensor, lam: float):
+    def __init__(self, nv: int, F: torch.Tensor, lam: float, tol: float = 1e-10, max_iters: int = 1000):
+        if not F.is_cuda:
+            raise ValueError("LargeSteps solves on the device: F must be a device tensor")
         self.L = laplacian(nv, F)
-        self.lam = lam
-        self._last = None      # the previous solve's vertices: the next one starts there
+        self.lam, self.tol, self.max_iters = lam, tol, max_iters
+        self.solver = B.Smooth(*adjacency_csr(nv, F), lam)
+        self._last = {}        # the previous solve of each kind: the next one starts there
 
     def matvec(self, x: torch.Tensor) -> torch.Tensor:
         return x + self.lam * torch.sparse.mm(self.L, x)
@@ -296,11 +285,15 @@ class LargeSteps:
     def to_u(self, V: torch.Tensor) -> torch.Tensor:
         return self.matvec(V.double()).to(V.dtype)
 
-    def to_v(self, u: torch.Tensor, warm: bool = True) -> torch.Tensor:
-        x0 = self._last if warm and self._last is not None and self._last.shape == u.shape else None
-        x = solve_spd(self.matvec, u.double(), x0=x0)
-        if warm:
-            self._last = x
+    def to_v(self, u: torch.Tensor, slot: str | None = "v") -> torch.Tensor:
+        """(I + lam L)^-1 u, started from the last solution kept under `slot`
+        (None: from zero, nothing kept)."""
+        b = u.detach().double().contiguous()
+        x0 = self._last.get(slot) if slot is not None else None
+        x = x0.clone() if x0 is not None and x0.shape == b.shape else torch.zeros_like(b)
+        self.solver.solve(b, x, tol=self.tol, max_iters=self.max_iters)
+        if slot is not None:
+            self._last[slot] = x
         return x.to(u.dtype)
 
 
@@ -343,4 +336,4 @@ class _FromU(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        return ctx.ls.to_v(g.contiguous(), warm=False), None
+        return ctx.ls.to_v(g.contiguous(), slot="g"), None

@@ -50,6 +50,12 @@ def test_host_validation_without_device():
     assert L.dt_trace_forward(None, None, None, None, None, None, None, None, None, 0, None, 0,
                               None) == 1
     assert L.dt_status_string(2) == b"workspace too small"
+    # the reparameterisation's solve: workspace sizing and null pointers
+    assert L.dt_smooth_bytes(0, C.byref(a)) == 1
+    assert L.dt_smooth_bytes(1000, C.byref(a)) == 0
+    assert a.value >= 3 * 3 * 1000 * 8
+    assert L.dt_smooth_solve(None, None, 1000, 1.0, None, None, 1e-10, 100, None, None, None, 0, None) == 1
+    assert L.dt_status_string(6) == b"not converged"
 
 
 def test_queue_capacity_bounds_tape():

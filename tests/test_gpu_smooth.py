@@ -1,0 +1,121 @@
+"""The device solve of the vertex reparameterisation, (I + lambda L) x = b
+with L the combinatorial Laplacian of the mesh's edge graph (the mesh
+optimiser of Sec. 3.3 "Optimization", from the large-steps method the
+appendix's training scheme cites): against the dense solve of the same
+system on small meshes, and by its residual (a property at any size) on a
+300k-face mesh."""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_00413_amd import binding as B
+from paper_2603_00413_amd import synth
+from paper_2603_00413_amd import train as T
+from tests.gpu_helpers import device
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _dense(nv, F, lam):
+    L = np.zeros((nv, nv))
+    for a, b in ((0, 1), (1, 2), (2, 0)):
+        L[F[:, a], F[:, b]] = -1.0
+        L[F[:, b], F[:, a]] = -1.0
+    L[np.arange(nv), np.arange(nv)] = -L.sum(1)
+    return np.eye(nv) + lam * L
+
+
+def _solver(nv, F, lam, dev):
+    off, adj = T.adjacency_csr(nv, torch.from_numpy(F).to(dev))
+    return B.Smooth(off, adj, lam)
+
+
+@pytest.mark.parametrize("lam", [0.0, 1.0, 20.0])
+def test_matches_the_dense_solve(lam):
+    dev = device()
+    V, F = synth.icosphere(3)
+    # two vertices no face uses (rows of the identity) and a ragged count
+    nv = len(V) + 2
+    A = _dense(nv, F, lam)
+    rng = np.random.default_rng(int(lam) + 1)
+    b = rng.normal(size=(nv, 3))
+    ref = np.linalg.solve(A, b)
+    s = _solver(nv, F, lam, dev)
+    x = torch.zeros(nv, 3, dtype=torch.float64, device=dev)
+    s.solve(torch.from_numpy(b).to(dev), x)
+    x = x.cpu().numpy()
+    err = np.abs(x - ref).max() / np.abs(ref).max()
+    _print(f"lambda {lam}: {s.iters} iterations, residual {s.resid:.2e}, max rel error {err:.2e}")
+    # relative residual 1e-10 and cond(A) <= 1 + 2 lambda max(deg) = 241
+    assert s.resid <= 1e-10 and err <= 1e-8
+    np.testing.assert_allclose(x[-2:], b[-2:], rtol=1e-12)
+
+
+def test_large_mesh_residual_warm_start_and_reproducibility():
+    dev = device()
+    wl = synth.sdf_union_scene()
+    nv, lam = len(wl.V), 20.0
+    Ft = torch.from_numpy(wl.F).to(dev)
+    ls = T.LargeSteps(nv, Ft, lam)
+    V = torch.from_numpy(wl.V).to(dev)
+    u = ls.to_u(V)
+    x = ls.to_v(u)
+    it1 = ls.solver.iters
+    # the residual of the float64 system, by torch's sparse product
+    r = (u - ls.matvec(x)).norm(dim=0) / u.norm(dim=0)
+    err = float((x - V).abs().max())
+    _print(f"{nv} vertices: {it1} iterations, residual per column {r.tolist()}, max |V - x| {err:.2e}")
+    assert float(r.max()) <= 1.01e-10 and err <= 1e-6
+    # started from its own solution the solve stops at once
+    x2 = ls.to_v(u)
+    assert ls.solver.iters == 0 and torch.equal(x2, x)
+    # a cold start repeats the first solve bit for bit (fixed-order sums)
+    xa = ls.to_v(u, slot=None)
+    xb = ls.to_v(u, slot=None)
+    assert torch.equal(xa, xb) and torch.equal(xa, x)
+
+
+def test_roundtrip_and_trainer_pieces():
+    dev = device()
+    V, F = synth.icosphere(2)
+    Ft = torch.from_numpy(F).to(dev)
+    ls = T.LargeSteps(len(V), Ft, lam=10.0)
+    Vt = torch.from_numpy(V).to(dev)
+    u = ls.to_u(Vt)
+    np.testing.assert_allclose(u.cpu().numpy(), _dense(len(V), F, 10.0) @ V, atol=1e-12)
+    np.testing.assert_allclose(ls.to_v(u).cpu().numpy(), V, atol=1e-8)
+    # float32 in, float32 out; the gradient slot is kept apart from the vertices
+    g = torch.randn(len(V), 3, device=dev)
+    xg = ls.to_v(g, slot="g")
+    assert xg.dtype == torch.float32 and set(ls._last) == {"v", "g"}
+    np.testing.assert_allclose(xg.double().cpu().numpy(),
+                               np.linalg.solve(_dense(len(V), F, 10.0), g.double().cpu().numpy()), atol=1e-5)
+
+
+def test_errors_on_the_host():
+    dev = device()
+    V, F = synth.icosphere(2)
+    s = _solver(len(V), F, 50.0, dev)
+    b = torch.from_numpy(np.random.default_rng(0).normal(size=(len(V), 3))).to(dev)
+    x = torch.zeros_like(b)
+    # three iterations cannot reach 1e-15 at lambda 50
+    with pytest.raises(B.DTError, match="not converged"):
+        s.solve(b, x, tol=1e-15, max_iters=3)
+    assert s.iters == 3 and s.resid > 1e-15
+    L = B.load()
+    st = L.dt_smooth_solve(B._ptr(s.adj_off), B._ptr(s.adj), len(V), 50.0, B._ptr(b), B._ptr(x), 1e-10, 100,
+                           None, None, B._ptr(s.ws), 64, None)
+    assert st == B.DT_ERR_WORKSPACE_TOO_SMALL
+    st = L.dt_smooth_solve(B._ptr(s.adj_off), B._ptr(s.adj), len(V), -1.0, B._ptr(b), B._ptr(x), 1e-10, 100,
+                           None, None, B._ptr(s.ws), s.ws.numel(), None)
+    assert st == B.DT_ERR_INVALID_ARGUMENT
+    n = C.c_size_t()
+    assert L.dt_smooth_bytes(0, C.byref(n)) == B.DT_ERR_INVALID_ARGUMENT
+    with pytest.raises(B.DTError):
+        s.solve(b.float(), x)

@@ -3,6 +3,7 @@ regularizers) against their definitions written out in numpy, and the
 torch vertex normals against the oracle's (an independent implementation of
 Eq. 12-13)."""
 import numpy as np
+import pytest
 import torch
 
 import oracle
@@ -66,11 +67,21 @@ def test_laplacian_and_large_steps_roundtrip():
     assert np.allclose(L, L.T) and np.abs(L.sum(1)).max() == 0.0
     deg = np.diag(L)
     assert deg.min() >= 5 and deg.max() <= 6          # icosphere valences
-    ls = T.LargeSteps(len(V), Ft, lam=10.0)
-    Vt = torch.from_numpy(V)
-    u = ls.to_u(Vt)
-    np.testing.assert_allclose(u.numpy(), (np.eye(len(V)) + 10.0 * L) @ V, atol=1e-12)
-    np.testing.assert_allclose(ls.to_v(u).numpy(), V, atol=1e-8)
+    # the CSR adjacency the device solve takes: the off-diagonal pattern of L,
+    # neighbours ascending, degrees the diagonal
+    off, adj = T.adjacency_csr(len(V), Ft)
+    assert off.dtype == torch.int32 and adj.dtype == torch.int32
+    off, adj = off.numpy(), adj.numpy()
+    assert off[0] == 0 and off[-1] == len(adj) and np.array_equal(np.diff(off), deg.astype(np.int64))
+    A = np.zeros_like(L)
+    for i in range(len(V)):
+        nb = adj[off[i]:off[i + 1]]
+        assert np.all(np.diff(nb) > 0)
+        A[i, nb] = 1.0
+    np.testing.assert_array_equal(np.diag(deg) - A, L)
+    # the solve is device-only: no host fallback
+    with pytest.raises(ValueError, match="device"):
+        T.LargeSteps(len(V), Ft, lam=10.0)
 
 
 def test_adam_uniform_step_matches_its_definition():
