@@ -546,12 +546,14 @@ __device__ __forceinline__ void atomic_add3(float* p, int idx, v3 v) {
 // Adjoint of tau = absorb_tau(G, o, d, t) for the per-channel taubar: the
 // terms of t, o and d are added to tbar, obar and dbar (the grid values'
 // terms are scattered by k_grid_grad).  Sample k sits at x = o + a d with
-// a = (k + 1/2) t / S, and tau = (t / S) sum mu(x).
+// a = (k + 1/2) t / S, and tau = (t / S) sum mu(x).  Only taubar . mu(x) and
+// its gradient are needed, so the corners are projected on taubar first and
+// the scalar field is interpolated axis by axis (x, then y, then z), its
+// partial derivatives read off the same differences.
 __device__ void absorb_tau_bwd(const AbsorbDev& G, v3 o, v3 d, float t, v3 taubar, float& tbar,
                                v3& obar, v3& dbar) {
   const float S = (float)G.samples, h = t / S;
   const size_t sy = 3 * (size_t)G.nx, sz = sy * (size_t)G.ny;
-  const v3 tw = taubar * h;  // dLoss/d mu(x_k), per channel
   for (int k = 0; k < G.samples; ++k) {
     const float a = h * ((float)k + 0.5f);
     const v3 x = o + d * a;
@@ -559,25 +561,36 @@ __device__ void absorb_tau_bwd(const AbsorbDev& G, v3 o, v3 d, float t, v3 tauba
     const GridAxis ay = grid_axis(x.y, G.lo[1], G.scale[1], G.ny);
     const GridAxis az = grid_axis(x.z, G.lo[2], G.scale[2], G.nz);
     const size_t b = (size_t)az.i * sz + (size_t)ay.i * sy + 3 * (size_t)ax.i;
-    v3 mu = mk3(0.f, 0.f, 0.f), gx = mu, gy = mu, gz = mu;  // value, d/du per axis
+    // u[c] = taubar . mu at corner c = (dx, dy, dz) = bits 0, 1, 2
+    float u[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
-      const float wx = dx ? ax.f : 1.f - ax.f, wy = dy ? ay.f : 1.f - ay.f, wz = dz ? az.f : 1.f - az.f;
-      const float sx = dx ? 1.f : -1.f, sgy = dy ? 1.f : -1.f, sgz = dz ? 1.f : -1.f;
-      const size_t j = b + dz * sz + dy * sy + 3 * dx;
-      const v3 v = mk3(G.mu[j], G.mu[j + 1], G.mu[j + 2]);
-      mu = mu + v * (wx * wy * wz);
-      gx = gx + v * (sx * wy * wz);
-      gy = gy + v * (wx * sgy * wz);
-      gz = gz + v * (wx * wy * sgz);
+      const size_t j = b + (c >> 2) * sz + ((c >> 1) & 1) * sy + 3 * (c & 1);
+      u[c] = taubar.x * G.mu[j] + taubar.y * G.mu[j + 1] + taubar.z * G.mu[j + 2];
     }
-    // dLoss/dx of the sample: sum_c tw_c grad mu_c (grid units to length)
-    const v3 q = mk3(ax.in ? dot(tw, gx) * G.scale[0] : 0.f, ay.in ? dot(tw, gy) * G.scale[1] : 0.f,
-                     az.in ? dot(tw, gz) * G.scale[2] : 0.f);
+    // along x: differences ex and values lx on the 4 (y, z) edges
+    float ex[4], lx[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ex[e] = u[2 * e + 1] - u[2 * e];
+      lx[e] = u[2 * e] + ax.f * ex[e];
+    }
+    // along y (edges e = dy + 2 dz), then z
+    const float ey0 = lx[1] - lx[0], ey1 = lx[3] - lx[2];
+    const float ly0 = lx[0] + ay.f * ey0, ly1 = lx[2] + ay.f * ey1;
+    const float ez = ly1 - ly0;
+    const float mu = ly0 + az.f * ez;  // taubar . mu(x)
+    // partial derivatives in grid units: the x differences interpolated in
+    // (y, z), the y differences in z, the z difference
+    const float gx0 = ex[0] + ay.f * (ex[1] - ex[0]), gx1 = ex[2] + ay.f * (ex[3] - ex[2]);
+    const float gx = gx0 + az.f * (gx1 - gx0);
+    const float gy = ey0 + az.f * (ey1 - ey0);
+    // dLoss/dx of the sample: h times the gradient (grid units to length)
+    const v3 q = mk3(ax.in ? gx * G.scale[0] * h : 0.f, ay.in ? gy * G.scale[1] * h : 0.f,
+                     az.in ? ez * G.scale[2] * h : 0.f);
     obar += q;
     dbar += q * a;
-    tbar += dot(q, d) * (((float)k + 0.5f) / S) + dot(taubar, mu) / S;
+    tbar += dot(q, d) * (((float)k + 0.5f) / S) + mu / S;
   }
 }
 
@@ -858,24 +871,32 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
 // ------------------------------------------------------------------ absorption grid gradient
 // dLoss/d(grid value) of generation g's interior segments: the segment of
 // node i adds tw w_j(x_k) at the 8 corner nodes j of the cell of each sample
-// x_k (tw = h dLoss/d tau, per channel).  Float atomics to one address from
-// the lanes of one instruction are serialized, and neighbouring rays (the
-// lanes of a wave) mostly sample the same cells, so the updates are merged
-// before they are issued: a lane sums its consecutive samples that fall in
-// the same cell (a run) into 24 values; the wave parks its lanes' runs in LDS;
-// then per distinct cell among them, lanes 0-23 each sum one of the 24 values
-// over the lanes of that cell and add it with one atomic.  The sums go to
-// copy blockIdx.x % copies of the gradient (each 3 nx ny nz floats apart);
-// k_grid_reduce adds the copies up.  Control flow around the LDS exchange
-// stays wave-uniform.
+// x_k (tw = h dLoss/d tau per channel, the same for every sample of the
+// segment).  Float atomics to one address from the lanes of one instruction
+// are serialized, and neighbouring rays (the lanes of a wave) mostly sample
+// the same cells, so the updates are merged before they are issued: a lane
+// sums the 8 corner weights of its consecutive samples that fall in the same
+// cell (a run), scales them by tw into 24 values; the wave parks its lanes'
+// runs in LDS; then per distinct cell among them, lanes 0-23 each sum one of
+// the 24 values over the lanes of that cell and add it with one atomic.
+// CELL: the sums go to per-cell records of GG_CELL floats (8 corners x 3
+// channels, padded to one 128-byte line, so a cell's 24 atomics are one
+// memory request), in copy blockIdx.x % copies; k_grid_gather turns the
+// records into node values.  Otherwise (a grid whose records do not fit the
+// scratch region) they go to the node array itself.  Control flow around the
+// LDS exchange stays wave-uniform.
 constexpr int GG_T = 256;
 constexpr int GG_MAX_COPIES = 64;
+constexpr int GG_CELL = 32;
+template <bool CELL>
 __global__ void __launch_bounds__(GG_T) k_grid_grad(AbsorbDev G, Gen q, int g, const Counters* ctr,
                                                     Adj cur, float* copies, int n_copies) {
   __shared__ float runs[GG_T / 64][64][25];  // per wave and lane: a run's 24 sums (+1 pad)
   const int64_t n = ctr->count[g];
   const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
-  float* dst = copies + (size_t)(blockIdx.x % (unsigned)n_copies) * 3 * G.nx * G.ny * G.nz;
+  const int cx = G.nx - 1, cy = G.ny - 1, cz = G.nz - 1;  // cells per axis
+  const size_t copy_size = CELL ? (size_t)GG_CELL * cx * cy * cz : 3 * (size_t)G.nx * G.ny * G.nz;
+  float* dst = copies + (size_t)(blockIdx.x % (unsigned)n_copies) * copy_size;
   const size_t sy = 3 * (size_t)G.nx, sz = sy * (size_t)G.ny;
   const int S = G.samples;
   for (int64_t base = (int64_t)blockIdx.x * GG_T; base < n; base += (int64_t)gridDim.x * GG_T) {
@@ -896,31 +917,34 @@ __global__ void __launch_bounds__(GG_T) k_grid_grad(AbsorbDev G, Gen q, int g, c
     int k = act ? 0 : S;  // next sample of this lane
     while (__ballot(k < S)) {
       // this lane's next run: samples k, k+1, ... in one cell
-      float acc[24];
+      float ws[8];
 #pragma unroll
-      for (int c = 0; c < 24; ++c) acc[c] = 0.f;
+      for (int c = 0; c < 8; ++c) ws[c] = 0.f;
       int key = -1;
       while (k < S) {
         const v3 x = o + d * (h * ((float)k + 0.5f));
         const GridAxis ax = grid_axis(x.x, G.lo[0], G.scale[0], G.nx);
         const GridAxis ay = grid_axis(x.y, G.lo[1], G.scale[1], G.ny);
         const GridAxis az = grid_axis(x.z, G.lo[2], G.scale[2], G.nz);
-        const int kk = (az.i * G.ny + ay.i) * G.nx + ax.i;
+        const int kk = (az.i * cy + ay.i) * cx + ax.i;
         if (key >= 0 && kk != key) break;
         key = kk;
+        const float wy[2] = {1.f - ay.f, ay.f}, wz[2] = {1.f - az.f, az.f};
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
-          const float w = (dx ? ax.f : 1.f - ax.f) * (dy ? ay.f : 1.f - ay.f) * (dz ? az.f : 1.f - az.f);
-          acc[3 * c] += tw.x * w;
-          acc[3 * c + 1] += tw.y * w;
-          acc[3 * c + 2] += tw.z * w;
+        for (int c = 0; c < 4; ++c) {
+          const float yz = wy[c & 1] * wz[c >> 1];
+          ws[2 * c] += (1.f - ax.f) * yz;
+          ws[2 * c + 1] += ax.f * yz;
         }
         ++k;
       }
       const bool has = key >= 0;
 #pragma unroll
-      for (int c = 0; c < 24; ++c) runs[wv][lane][c] = acc[c];
+      for (int c = 0; c < 8; ++c) {
+        runs[wv][lane][3 * c] = tw.x * ws[c];
+        runs[wv][lane][3 * c + 1] = tw.y * ws[c];
+        runs[wv][lane][3 * c + 2] = tw.z * ws[c];
+      }
       wave_lds_sync();
       uint64_t pending = __ballot(has);
       while (pending) {
@@ -931,11 +955,15 @@ __global__ void __launch_bounds__(GG_T) k_grid_grad(AbsorbDev G, Gen q, int g, c
         if (lane < 24) {
           float sum = 0.f;
           for (uint64_t mm = m; mm; mm &= mm - 1ull) sum += runs[wv][__ffsll((unsigned long long)mm) - 1][lane];
-          const int cc = lane / 3;  // corner (dx, dy, dz) = bits 0, 1, 2
-          const int az_i = kl / (G.nx * G.ny), ay_i = (kl / G.nx) % G.ny, ax_i = kl % G.nx;
-          atomicAdd(dst + (size_t)(az_i + (cc >> 2)) * sz + (size_t)(ay_i + ((cc >> 1) & 1)) * sy +
-                        3 * (size_t)(ax_i + (cc & 1)) + lane % 3,
-                    sum);
+          if (CELL) {
+            atomicAdd(dst + (size_t)kl * GG_CELL + lane, sum);
+          } else {
+            const int cc = lane / 3;  // corner (dx, dy, dz) = bits 0, 1, 2
+            const int az_i = kl / (cx * cy), ay_i = (kl / cx) % cy, ax_i = kl % cx;
+            atomicAdd(dst + (size_t)(az_i + (cc >> 2)) * sz + (size_t)(ay_i + ((cc >> 1) & 1)) * sy +
+                          3 * (size_t)(ax_i + (cc & 1)) + lane % 3,
+                      sum);
+          }
         }
       }
       wave_lds_sync();
@@ -1030,12 +1058,28 @@ __global__ void __launch_bounds__(GG_T) k_env_tex_grad(SceneDev sc, Gen q, int g
   }
 }
 
-// d_mu = the sum of the gradient copies (fixed order)
-__global__ void k_grid_reduce(const float* copies, int n_copies, int64_t n, float* d_mu) {
+// d_mu from the per-cell records: node (x, y, z) is corner (dx, dy, dz) of
+// cell (x - dx, y - dy, z - dz) where that cell exists; summed over corners,
+// then copies, in a fixed order
+__global__ void k_grid_gather(const float* copies, int n_copies, int nx, int ny, int nz, float* d_mu) {
+  const int cx = nx - 1, cy = ny - 1, cz = nz - 1;
+  const size_t copy_size = (size_t)GG_CELL * cx * cy * cz;
+  const int64_t n = 3 * (int64_t)nx * ny * nz;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
+    const int ch = (int)(j % 3);
+    const int64_t node = j / 3;
+    const int x = (int)(node % nx), y = (int)((node / nx) % ny), z = (int)(node / ((int64_t)nx * ny));
     float acc = 0.f;
-    for (int r = 0; r < n_copies; ++r) acc += copies[(size_t)r * n + j];
+    for (int r = 0; r < n_copies; ++r) {
+      const float* cp = copies + (size_t)r * copy_size;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int ux = x - (c & 1), uy = y - ((c >> 1) & 1), uz = z - (c >> 2);
+        if (ux >= 0 && ux < cx && uy >= 0 && uy < cy && uz >= 0 && uz < cz)
+          acc += cp[((size_t)(uz * cy + uy) * cx + ux) * GG_CELL + 3 * c + ch];
+      }
+    }
     d_mu[j] = acc;
   }
 }
@@ -1703,19 +1747,24 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   if (dt_status st = zero_f32(dN, 3 * (int64_t)scene->nv, s)) return st;
   if (dt_status st = zero_f32((float*)fcnt, (int64_t)scene->nf + 1, s)) return st;
   if (dt_status st = zero_f32(fg, 18 * (int64_t)scene->nf, s)) return st;
-  // absorption grid: as many gradient copies as the scratch region holds (at most 64)
+  // absorption grid: as many copies of the per-cell records as the scratch
+  // region holds (at most 64)
   const int64_t gsize = sc.ab.mu ? 3 * (int64_t)sc.ab.nx * sc.ab.ny * sc.ab.nz : 0;
+  const int64_t csize =
+      sc.ab.mu ? (int64_t)GG_CELL * (sc.ab.nx - 1) * (int64_t)(sc.ab.ny - 1) * (sc.ab.nz - 1) : 0;
   float* gcopies = (float*)(W + P.w_gscr);
   int n_copies = 0;
+  bool gcell = true;
   if (sc.ab.mu && sc.ab.d_mu) {
-    const int64_t fit = (int64_t)(GG_SCRATCH / sizeof(float)) / gsize;
+    const int64_t fit = (int64_t)(GG_SCRATCH / sizeof(float)) / csize;
     n_copies = (int)(fit < GG_MAX_COPIES ? fit : GG_MAX_COPIES);
     if (n_copies < 1) {
-      // a grid larger than the scratch region: one copy, the caller's array
+      // records larger than the scratch region: node sums straight into the caller's array
       n_copies = 1;
       gcopies = sc.ab.d_mu;
+      gcell = false;
     }
-    if (dt_status st = zero_f32(gcopies, gsize * n_copies, s)) return st;
+    if (dt_status st = zero_f32(gcopies, gcell ? csize * n_copies : gsize, s)) return st;
   }
   if (sc.env.d_tex)
     if (dt_status st = zero_f32(sc.env.d_tex, 3 * (int64_t)sc.env.W * sc.env.H, s)) return st;
@@ -1769,8 +1818,12 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
     if (sc.ab.mu && sc.ab.d_mu) {
       const int64_t gb = (P.cap[g] + GG_T - 1) / GG_T;
-      hipLaunchKernelGGL(k_grid_grad, dim3((unsigned)(gb < 8192 ? gb : 8192)), dim3(GG_T), 0, s, sc.ab, q, g,
-                         ctr, adj[g & 1], gcopies, n_copies);
+      if (gcell)
+        hipLaunchKernelGGL(k_grid_grad<true>, dim3((unsigned)(gb < 8192 ? gb : 8192)), dim3(GG_T), 0, s, sc.ab,
+                           q, g, ctr, adj[g & 1], gcopies, n_copies);
+      else
+        hipLaunchKernelGGL(k_grid_grad<false>, dim3((unsigned)(gb < 8192 ? gb : 8192)), dim3(GG_T), 0, s,
+                           sc.ab, q, g, ctr, adj[g & 1], gcopies, n_copies);
     }
     // fcnt[nf] stays 0, so foff[nf] is the total
     if (dt_status st = dt_scan_exclusive_i32((const int32_t*)fcnt, (int32_t*)foff, scene->nf + 1, fscan, s))
@@ -1831,9 +1884,9 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_T), 0, s, red, nred, d_ior, d_sigma);
   if (sc.env.d_w)
     if (dt_status st = mlp_wgrad_reduce(sc.env, mlp_part, s)) return st;
-  if (n_copies > 0 && gcopies != sc.ab.d_mu)
-    hipLaunchKernelGGL(k_grid_reduce, dim3(dt_blocks(gsize, 256) < 4096 ? dt_blocks(gsize, 256) : 4096), dim3(256),
-                       0, s, gcopies, n_copies, gsize, sc.ab.d_mu);
+  if (n_copies > 0 && gcell)
+    hipLaunchKernelGGL(k_grid_gather, dim3(dt_blocks(gsize, 256) < 4096 ? dt_blocks(gsize, 256) : 4096), dim3(256),
+                       0, s, gcopies, n_copies, sc.ab.nx, sc.ab.ny, sc.ab.nz, sc.ab.d_mu);
   hipLaunchKernelGGL(k_vertex_gather, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, sc.F, fg,
                      dV, dN);
   hipLaunchKernelGGL(k_nbwd_vertex, dim3(dt_blocks(scene->nv, 256)), dim3(256), 0, s, sc.bvh, dN, sbar);

@@ -93,9 +93,11 @@ def _grad_check(P, seed):
     return ev, ee, em, buf, g, (dV, de, dmu)
 
 
-# grid shapes: small, 40 x 40 x 20 nodes, and 100 x 90 x 3 (a node plane of
-# 27,000 values)
-@pytest.mark.parametrize("n", [(6, 5, 7), (40, 40, 20), (100, 90, 3)])
+# grid shapes: small, 40 x 40 x 20 nodes, 100 x 90 x 3 (a node plane of
+# 27,000 values), and 72 x 70 x 68, whose per-cell gradient records (128 bytes
+# for each of 328k cells) exceed the 32 MB scratch region, so the gradient is
+# scattered to the nodes directly
+@pytest.mark.parametrize("n", [(6, 5, 7), (40, 40, 20), (100, 90, 3), (72, 70, 68)])
 def test_backward_icosphere_grid(n):
     P = _with_grid(icosphere_pair(), seed=3, samples=8, n=n)
     ev, ee, em, _, _, _ = _grad_check(P, seed=4)
