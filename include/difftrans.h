@@ -345,7 +345,9 @@ dt_status dt_trace_backward(const dt_scene* sc, const dt_rays* rays, const dt_tr
  * with L the combinatorial Laplacian D - A of the mesh's edge graph (the
  * preconditioned vertex update the appendix's training scheme takes from the
  * large-steps method it cites): solves (I + lambda L) x = b for the three
- * coordinate columns by conjugate gradients on the device.  adj_off
+ * coordinate columns on the device, by Chebyshev iteration over the interval
+ * [1, 1 + lambda m] that holds the matrix's eigenvalues (m: the largest
+ * d_i + d_j over the edges, an upper bound of L's largest eigenvalue).  adj_off
  * [nv + 1], adj [adj_off[nv]]: each vertex's neighbours along edges (int32,
  * device, each undirected edge listed from both ends, no repeats).  b, x:
  * device float64 [nv][3]; x holds the starting guess on entry and the

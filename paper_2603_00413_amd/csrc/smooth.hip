@@ -1,16 +1,15 @@
 // The vertex reparameterisation of the mesh optimiser: solves
 // (I + lambda L) x = b for the three coordinate columns, L the combinatorial
-// Laplacian D - A of the mesh's edge graph, by conjugate gradients on the
-// device, in the Chronopoulos-Gear arrangement (both inner products of an
-// iteration taken in one pass, so an iteration needs one global sum):
-// w = A r with the partial sums of r . r and w . r per block; then the
-// scalars and the updates of p, s = A p, x and r.  Each kernel first sums the
-// previous kernel's block partials in a fixed order (every block the same
-// way), so the scalars never leave the device and the whole solve is
-// deterministic.  The host reads the verdict back every CHECK iterations to
-// stop.  (One cooperative launch with grid barriers in place of the kernel
-// boundaries measured ten times slower: each barrier has to make every
-// block's writes visible across the chip.)
+// Laplacian D - A of the mesh's edge graph, by Chebyshev iteration on the
+// device.  The matrix's eigenvalues lie in [1, 1 + lambda m], m = the largest
+// d_i + d_j over the edges (i, j) (an upper bound of L's largest eigenvalue,
+// Anderson and Morley 1985), and on a known interval the Chebyshev
+// recurrence's scalars are fixed numbers, computed on the host: an iteration
+// takes no inner product, so it is one kernel (the product with the last
+// correction, over an int32 CSR adjacency, and the updates), where conjugate
+// gradients need two with a global sum each.  The residual's norm is summed
+// every CHECK iterations (block partials, then one block, in a fixed order)
+// and read back to stop; the solve is deterministic.
 #include "dt_internal.h"
 
 namespace {
@@ -21,15 +20,10 @@ constexpr int CHECK = 16;        // iterations between residual read-backs
 
 struct SmoothWs {
   double* r;        // [nv][3] residual
-  double* w;        // [nv][3] A r
-  double* p;        // [nv][3] direction
-  double* s;        // [nv][3] A p
-  double* part_a;   // [blocks][3] partial r . r
-  double* part_b;   // [blocks][3] partial w . r
-  double* part_c;   // [blocks][3] partial b . b
-  double* sc;       // [2][6] gamma and alpha of the last two iterations
-  double* b2;       // [3] b . b
-  double* state;    // [4] done, gamma per column (of the last update)
+  double* d[2];     // [nv][3] corrections: iteration k reads d[k & 1] and writes d[(k + 1) & 1]
+  double* part;     // [2][blocks][3] partial b . b and r . r
+  int* bmax;        // [blocks] largest d_i + d_j over the block's vertices' edges
+  double* sums;     // [8]: b . b, r . r per column; [6] the edge bound m
 };
 
 size_t smooth_layout(int32_t nv, SmoothWs* w, char* base) {
@@ -42,16 +36,12 @@ size_t smooth_layout(int32_t nv, SmoothWs* w, char* base) {
   const size_t col = 3 * (size_t)nv * sizeof(double);
   SmoothWs t;
   t.r = take(col);
-  t.w = take(col);
-  t.p = take(col);
-  t.s = take(col);
+  t.d[0] = take(col);
+  t.d[1] = take(col);
   const size_t nb = dt_blocks(nv, ST);
-  t.part_a = take(3 * nb * sizeof(double));
-  t.part_b = take(3 * nb * sizeof(double));
-  t.part_c = take(3 * nb * sizeof(double));
-  t.sc = take(12 * sizeof(double));
-  t.b2 = take(3 * sizeof(double));
-  t.state = take(4 * sizeof(double));
+  t.part = take(6 * nb * sizeof(double));
+  t.bmax = (int*)take(nb * sizeof(int));
+  t.sums = take(8 * sizeof(double));
   if (w) *w = t;
   return o;
 }
@@ -62,8 +52,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// the block's sums of v[0..2] over its threads, in a fixed order, into every
-// thread's out[0..2]
+// the block's sums of v[0..2] over its threads, in a fixed order
 __device__ __forceinline__ void block_sum3(const double v[3], double out[3]) {
   __shared__ double sh[3][WAVES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -81,17 +70,6 @@ __device__ __forceinline__ void block_sum3(const double v[3], double out[3]) {
     out[c] = s;
   }
   __syncthreads();
-}
-
-// the sum over blocks of a [blocks][3] partial array, the same bits in every block
-__device__ __forceinline__ void sum_partials(const double* part, int nb, double out[3]) {
-  double a[3] = {0.0, 0.0, 0.0};
-  for (int k = threadIdx.x; k < nb; k += ST) {
-    a[0] += part[3 * k];
-    a[1] += part[3 * k + 1];
-    a[2] += part[3 * k + 2];
-  }
-  block_sum3(a, out);
 }
 
 // this block's sums of v[0..2] into part[blockIdx]
@@ -120,93 +98,101 @@ __device__ __forceinline__ void apply_row(const int32_t* off, const int32_t* adj
   y[2] = dg * v[i3 + 2] - lambda * s2;
 }
 
-// r = b - A x; partials of b . b
+// r = b - A x, and a copy of r in d[0] (the first correction is r / theta,
+// scaled where it is read); partials of b . b (part[0 .. nb)) and r . r
+// (part[nb .. 2 nb))
 __global__ void __launch_bounds__(ST) k_sm_init(const int32_t* off, const int32_t* adj, int nv, double lambda,
                                                 const double* b, const double* x, SmoothWs w) {
   const int i = blockIdx.x * ST + threadIdx.x;
-  double bb[3] = {0.0, 0.0, 0.0};
+  double bb[3] = {0.0, 0.0, 0.0}, rr[3] = {0.0, 0.0, 0.0};
   if (i < nv) {
     double ax[3];
     apply_row(off, adj, i, lambda, x, ax);
     for (int c = 0; c < 3; ++c) {
       const int64_t k = 3 * (int64_t)i + c;
-      w.r[k] = b[k] - ax[c];
+      const double r = b[k] - ax[c];
+      w.r[k] = r;
+      w.d[0][k] = r;
       bb[c] = b[k] * b[k];
-    }
-  }
-  block_partial(bb, w.part_c);
-}
-
-__global__ void __launch_bounds__(ST) k_sm_init_sums(int nb, SmoothWs w) {
-  double bb[3];
-  sum_partials(w.part_c, nb, bb);
-  if (threadIdx.x == 0)
-    for (int c = 0; c < 3; ++c) w.b2[c] = bb[c];
-}
-
-// w = A r; partials of gamma = r . r and delta = w . r
-__global__ void __launch_bounds__(ST) k_sm_apply(const int32_t* off, const int32_t* adj, int nv, double lambda,
-                                                 SmoothWs w) {
-  const int i = blockIdx.x * ST + threadIdx.x;
-  double rr[3] = {0.0, 0.0, 0.0}, wr[3] = {0.0, 0.0, 0.0};
-  if (i < nv) {
-    double y[3];
-    apply_row(off, adj, i, lambda, w.r, y);
-    for (int c = 0; c < 3; ++c) {
-      const int64_t k = 3 * (int64_t)i + c;
-      const double r = w.r[k];
-      w.w[k] = y[c];
       rr[c] = r * r;
-      wr[c] = y[c] * r;
     }
   }
-  block_partial(rr, w.part_a);
-  block_partial(wr, w.part_b);
+  block_partial(bb, w.part);
+  block_partial(rr, w.part + 3 * gridDim.x);
 }
 
-// Iteration it: gamma = r . r, delta = w . r from the partials; unless every
-// column already meets the tolerance (then nothing changes and block 0 marks
-// the solve done), beta = gamma / gamma', alpha = gamma / (delta - beta gamma
-// / alpha') (alpha = gamma / delta, beta = 0 at it = 0), p = r + beta p,
-// s = w + beta s (= A p), x += alpha p, r -= alpha s.  Block 0 keeps gamma and
-// alpha in slot it & 1 (every block reads the other slot's).  report_only:
-// only the verdict, nothing updated (the iteration budget is spent).
-__global__ void __launch_bounds__(ST) k_sm_update(int nv, int nb, int it, double lim0, double lim1, double lim2,
-                                                  int report_only, double* x, SmoothWs w) {
-  double ga[3], de[3];
-  sum_partials(w.part_a, nb, ga);
-  sum_partials(w.part_b, nb, de);
-  const bool done = ga[0] <= lim0 && ga[1] <= lim1 && ga[2] <= lim2;
-  double al[3], be[3];
-  const double* prev = w.sc + 6 * ((it + 1) & 1);  // gamma', alpha'
-  for (int c = 0; c < 3; ++c) {
-    be[c] = it > 0 && prev[c] > 0.0 ? ga[c] / prev[c] : 0.0;
-    const double corr = be[c] > 0.0 && prev[3 + c] > 0.0 ? be[c] * ga[c] / prev[3 + c] : 0.0;
-    const double den = de[c] - corr;
-    al[c] = den > 0.0 ? ga[c] / den : 0.0;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double* cur = w.sc + 6 * (it & 1);
-    for (int c = 0; c < 3; ++c) {
-      cur[c] = ga[c];
-      cur[3 + c] = al[c];
-    }
-    w.state[0] = done ? 1.0 : 0.0;
-    for (int c = 0; c < 3; ++c) w.state[1 + c] = ga[c];
-  }
-  if (done || report_only) return;
+// per block, the largest d_i + d_j over its vertices' edges (i, j)
+__global__ void __launch_bounds__(ST) k_sm_bound(const int32_t* off, const int32_t* adj, int nv, int* bmax) {
+  __shared__ int sh[WAVES];
   const int i = blockIdx.x * ST + threadIdx.x;
-  if (i < nv)
+  int m = 0;
+  if (i < nv) {
+    const int a = off[i], e = off[i + 1];
+    for (int k = a; k < e; ++k) {
+      const int j = adj[k];
+      m = max(m, (e - a) + (off[j + 1] - off[j]));
+    }
+  }
+  for (int s = 32; s > 0; s >>= 1) m = max(m, __shfl_xor(m, s, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < WAVES; ++k) m = max(m, sh[k]);
+    bmax[blockIdx.x] = max(m, sh[0]);
+  }
+}
+
+// sums[0..3) = sum of part[0 .. nb) (with both), sums[3..6) = sum of
+// part[nb .. 2 nb), in block order; with both, sums[6] = the largest bmax
+__global__ void __launch_bounds__(ST) k_sm_sums(int nb, int both, SmoothWs w) {
+  for (int h = both ? 0 : 1; h < 2; ++h) {
+    double a[3] = {0.0, 0.0, 0.0};
+    const double* part = w.part + 3 * (size_t)nb * h;
+    for (int k = threadIdx.x; k < nb; k += ST)
+      for (int c = 0; c < 3; ++c) a[c] += part[3 * k + c];
+    double s[3];
+    block_sum3(a, s);
+    if (threadIdx.x == 0)
+      for (int c = 0; c < 3; ++c) w.sums[3 * h + c] = s[c];
+  }
+  if (both) {
+    __shared__ int sh[WAVES];
+    int m = 0;
+    for (int k = threadIdx.x; k < nb; k += ST) m = max(m, w.bmax[k]);
+    for (int s = 32; s > 0; s >>= 1) m = max(m, __shfl_xor(m, s, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int k = 0; k < WAVES; ++k) m = max(m, sh[k]);
+      w.sums[6] = (double)m;
+    }
+  }
+}
+
+// One Chebyshev step: x += d, r -= A d, d' = c1 d + c2 r (the new r); with
+// partial, the partials of the new r . r into part[nb .. 2 nb).  first: d
+// holds r and the correction is d / theta.
+__global__ void __launch_bounds__(ST) k_sm_step(const int32_t* off, const int32_t* adj, int nv, double lambda,
+                                                int first, double inv_theta, const double* d, double* dn,
+                                                double c1, double c2, double* x, int partial, SmoothWs w) {
+  const double* src = d;
+  const double sc = first ? inv_theta : 1.0;
+  const int i = blockIdx.x * ST + threadIdx.x;
+  double rr[3] = {0.0, 0.0, 0.0};
+  if (i < nv) {
+    double ad[3];
+    apply_row(off, adj, i, lambda, src, ad);
     for (int c = 0; c < 3; ++c) {
       const int64_t k = 3 * (int64_t)i + c;
-      const double r = w.r[k];
-      const double pk = it > 0 ? r + be[c] * w.p[k] : r;
-      const double sk = it > 0 ? w.w[k] + be[c] * w.s[k] : w.w[k];
-      w.p[k] = pk;
-      w.s[k] = sk;
-      x[k] += al[c] * pk;
-      w.r[k] = r - al[c] * sk;
+      const double dk = sc * src[k];
+      x[k] += dk;
+      const double r = w.r[k] - sc * ad[c];
+      w.r[k] = r;
+      dn[k] = c1 * dk + c2 * r;
+      rr[c] = r * r;
     }
+  }
+  if (partial) block_partial(rr, w.part + 3 * gridDim.x);
 }
 
 }  // namespace
@@ -235,40 +221,59 @@ extern "C" dt_status dt_smooth_solve(const int32_t* adj_off, const int32_t* adj,
   smooth_layout(nv, &w, (char*)ws);
   hipStream_t s = (hipStream_t)stream;
   const int nb = (int)dt_blocks(nv, ST);
+  hipLaunchKernelGGL(k_sm_bound, dim3(nb), dim3(ST), 0, s, adj_off, adj, nv, w.bmax);
   hipLaunchKernelGGL(k_sm_init, dim3(nb), dim3(ST), 0, s, adj_off, adj, nv, lambda, b, x, w);
-  hipLaunchKernelGGL(k_sm_init_sums, dim3(1), dim3(ST), 0, s, nb, w);
-  hipLaunchKernelGGL(k_sm_apply, dim3(nb), dim3(ST), 0, s, adj_off, adj, nv, lambda, w);
+  hipLaunchKernelGGL(k_sm_sums, dim3(1), dim3(ST), 0, s, nb, 1, w);
   DT_CHECK_LAUNCH();
-  double b2[3], st[4];
-  DT_CHECK_HIP(hipMemcpyAsync(b2, w.b2, sizeof(b2), hipMemcpyDeviceToHost, s));
+  double sums[7];
+  DT_CHECK_HIP(hipMemcpyAsync(sums, w.sums, sizeof(sums), hipMemcpyDeviceToHost, s));
   DT_CHECK_HIP(hipStreamSynchronize(s));
-  double lim[3];
+  // eigenvalues in [1, 1 + lambda m]
+  const double lo = 1.0, hi = 1.0 + lambda * sums[6];
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+  double b2[3], lim[3];
   for (int c = 0; c < 3; ++c) {
-    b2[c] = b2[c] > 1e-300 ? b2[c] : 1e-300;
+    b2[c] = sums[c] > 1e-300 ? sums[c] : 1e-300;
     lim[c] = tol * tol * b2[c];
   }
-  int it = 0;
-  double worst = 0.0;
-  bool done = false;
-  while (true) {
-    // the update finds the residual of `it` iterations and, if it meets the
-    // tolerance, stops there; the host reads its verdict at the first
-    // iteration, every CHECK iterations and at max_iters
-    const bool last = it == max_iters;
-    hipLaunchKernelGGL(k_sm_update, dim3(nb), dim3(ST), 0, s, nv, nb, it, lim[0], lim[1], lim[2], (int)last, x,
-                       w);
-    DT_CHECK_LAUNCH();
-    if (it % CHECK == 0 || last) {
-      DT_CHECK_HIP(hipMemcpyAsync(st, w.state, sizeof(st), hipMemcpyDeviceToHost, s));
-      DT_CHECK_HIP(hipStreamSynchronize(s));
-      done = st[0] != 0.0;
-      worst = 0.0;
-      for (int c = 0; c < 3; ++c) worst = fmax(worst, st[1 + c] / b2[c]);
-      if (done || last) break;
+  auto verdict = [&](const double* rr, double& worst) {
+    bool ok = true;
+    worst = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      ok = ok && rr[c] <= lim[c];
+      worst = fmax(worst, rr[c] / b2[c]);
     }
-    hipLaunchKernelGGL(k_sm_apply, dim3(nb), dim3(ST), 0, s, adj_off, adj, nv, lambda, w);
-    DT_CHECK_LAUNCH();
+    return ok;
+  };
+  double worst = 0.0;
+  bool done = verdict(sums + 3, worst);
+  int it = 0;
+  // rho_0 = delta / theta, rho_{k+1} = 1 / (2 sigma - rho_k), sigma = theta / delta;
+  // d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) r_{k+1} (a matrix with
+  // one eigenvalue, delta = 0, is solved by the first step alone)
+  const bool single = delta <= 1e-12 * theta;
+  const double sigma = single ? 0.0 : theta / delta;
+  double rho = single ? 0.0 : delta / theta;
+  while (!done && it < max_iters) {
+    double c1 = 0.0, c2 = 0.0;
+    if (!single) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      c1 = rn * rho;
+      c2 = 2.0 * rn / delta;
+      rho = rn;
+    }
     ++it;
+    const bool check = it % CHECK == 0 || it == max_iters || single;
+    hipLaunchKernelGGL(k_sm_step, dim3(nb), dim3(ST), 0, s, adj_off, adj, nv, lambda, (int)(it == 1),
+                       1.0 / theta, w.d[(it - 1) & 1], w.d[it & 1], c1, c2, x, (int)check, w);
+    DT_CHECK_LAUNCH();
+    if (check) {
+      hipLaunchKernelGGL(k_sm_sums, dim3(1), dim3(ST), 0, s, nb, 0, w);
+      DT_CHECK_LAUNCH();
+      DT_CHECK_HIP(hipMemcpyAsync(sums + 3, w.sums + 3, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      DT_CHECK_HIP(hipStreamSynchronize(s));
+      done = verdict(sums + 3, worst);
+    }
   }
   if (iters_out) *iters_out = it;
   if (resid_out) *resid_out = sqrt(worst);

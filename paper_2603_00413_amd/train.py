@@ -266,7 +266,7 @@ def adjacency_csr(nv: int, F: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor]
 
 class LargeSteps:
     """u = (I + lam L) V and back, for one mesh on the device; the solve runs
-    in the library's conjugate-gradient kernels (float64, to a relative
+    in the library's Chebyshev-iteration kernels (float64, to a relative
     residual of 1e-10 per coordinate column), each from the previous solve of
     its kind: vertices from the last vertices, a gradient from the last
     gradient."""

@@ -54,7 +54,8 @@ def test_matches_the_dense_solve(lam):
     _print(f"lambda {lam}: {s.iters} iterations, residual {s.resid:.2e}, max rel error {err:.2e}")
     # relative residual 1e-10 and cond(A) <= 1 + 2 lambda max(deg) = 241
     assert s.resid <= 1e-10 and err <= 1e-8
-    np.testing.assert_allclose(x[-2:], b[-2:], rtol=1e-12)
+    # the unused vertices' rows are the identity: x = b there, to the solve's tolerance
+    assert np.abs(x[-2:] - b[-2:]).max() <= 1e-9 * np.abs(b).max()
 
 
 def test_large_mesh_residual_warm_start_and_reproducibility():
