@@ -543,55 +543,73 @@ __device__ __forceinline__ void atomic_add3(float* p, int idx, v3 v) {
 
 // Vertex contributions of one hit node: dLoss/dp_k for its three vertices and
 // dLoss/dN_k for their normals (absent where the geometric normal was used).
-// Adjoint of tau = absorb_tau(G, o, d, t) for the per-channel taubar: the
-// terms of t, o and d are added to tbar, obar and dbar (the grid values'
-// terms are scattered by k_grid_grad).  Sample k sits at x = o + a d with
-// a = (k + 1/2) t / S, and tau = (t / S) sum mu(x).  Only taubar . mu(x) and
-// its gradient are needed, so the corners are projected on taubar first and
-// the scalar field is interpolated axis by axis (x, then y, then z), its
-// partial derivatives read off the same differences.
-__device__ void absorb_tau_bwd(const AbsorbDev& G, v3 o, v3 d, float t, v3 taubar, float& tbar,
-                               v3& obar, v3& dbar) {
+// Adjoint of tau = absorb_tau(G, o, d, t), in one pass over the interior
+// segment's samples that also gives tau itself (the same operations as
+// absorb_tau, so the same bits).  Sample k sits at x_k = o + a_k d with
+// a_k = (k + 1/2) t / S, and tau = (t / S) sum_k mu(x_k), so for the
+// per-channel taubar the adjoint adds h taubar . grad mu(x_k) to obar,
+// a_k times that to dbar and, through h and a_k, (k + 1/2)/S of its dot with
+// d plus taubar . mu(x_k) / S to tbar.  Being linear in taubar (not known
+// until the attenuation A = exp(-tau) has been used), it is kept per channel
+// c: G_c = sum_k h grad mu_c(x_k), D_c = sum_k a_k h grad mu_c(x_k) and
+// T_c = sum_k (k + 1/2)/S h grad mu_c(x_k) . d + sum_k mu_c(x_k) / S, then
+// obar += sum_c taubar_c G_c, dbar += sum_c taubar_c D_c and
+// tbar += sum_c taubar_c T_c.  The gradient of the trilinear interpolant is
+// read off the differences along x, then y, then z; the grid values' own
+// terms are scattered by k_grid_grad.
+struct TauSums {
+  v3 tau;
+  v3 G[3], D[3];
+  float T[3];
+};
+
+__device__ __forceinline__ void absorb_tau_sums(const AbsorbDev& G, v3 o, v3 d, float t, TauSums& r) {
   const float S = (float)G.samples, h = t / S;
   const size_t sy = 3 * (size_t)G.nx, sz = sy * (size_t)G.ny;
+  v3 acc = mk3(0.f, 0.f, 0.f);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    r.G[c] = mk3(0.f, 0.f, 0.f);
+    r.D[c] = r.G[c];
+    r.T[c] = 0.f;
+  }
   for (int k = 0; k < G.samples; ++k) {
     const float a = h * ((float)k + 0.5f);
     const v3 x = o + d * a;
+    acc = acc + grid_mu(G, x);
     const GridAxis ax = grid_axis(x.x, G.lo[0], G.scale[0], G.nx);
     const GridAxis ay = grid_axis(x.y, G.lo[1], G.scale[1], G.ny);
     const GridAxis az = grid_axis(x.z, G.lo[2], G.scale[2], G.nz);
     const size_t b = (size_t)az.i * sz + (size_t)ay.i * sy + 3 * (size_t)ax.i;
-    // u[c] = taubar . mu at corner c = (dx, dy, dz) = bits 0, 1, 2
-    float u[8];
+    const float wk = ((float)k + 0.5f) / S;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const size_t j = b + (c >> 2) * sz + ((c >> 1) & 1) * sy + 3 * (c & 1);
-      u[c] = taubar.x * G.mu[j] + taubar.y * G.mu[j + 1] + taubar.z * G.mu[j + 2];
-    }
-    // along x: differences ex and values lx on the 4 (y, z) edges
-    float ex[4], lx[4];
+    for (int c = 0; c < 3; ++c) {
+      float u[8];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      ex[e] = u[2 * e + 1] - u[2 * e];
-      lx[e] = u[2 * e] + ax.f * ex[e];
+      for (int q = 0; q < 8; ++q) u[q] = G.mu[b + (q >> 2) * sz + ((q >> 1) & 1) * sy + 3 * (q & 1) + c];
+      // x differences on the 4 (y, z) edges, values along x; then y, then z
+      float ex[4], lx[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        ex[e] = u[2 * e + 1] - u[2 * e];
+        lx[e] = u[2 * e] + ax.f * ex[e];
+      }
+      const float ey0 = lx[1] - lx[0], ey1 = lx[3] - lx[2];
+      const float ez = (lx[2] + ay.f * ey1) - (lx[0] + ay.f * ey0);
+      const float gx0 = ex[0] + ay.f * (ex[1] - ex[0]), gx1 = ex[2] + ay.f * (ex[3] - ex[2]);
+      const float gx = gx0 + az.f * (gx1 - gx0);
+      const float gy = ey0 + az.f * (ey1 - ey0);
+      const v3 q = mk3(ax.in ? gx * G.scale[0] * h : 0.f, ay.in ? gy * G.scale[1] * h : 0.f,
+                       az.in ? ez * G.scale[2] * h : 0.f);
+      r.G[c] += q;
+      r.D[c] += q * a;
+      r.T[c] += dot(q, d) * wk;
     }
-    // along y (edges e = dy + 2 dz), then z
-    const float ey0 = lx[1] - lx[0], ey1 = lx[3] - lx[2];
-    const float ly0 = lx[0] + ay.f * ey0, ly1 = lx[2] + ay.f * ey1;
-    const float ez = ly1 - ly0;
-    const float mu = ly0 + az.f * ez;  // taubar . mu(x)
-    // partial derivatives in grid units: the x differences interpolated in
-    // (y, z), the y differences in z, the z difference
-    const float gx0 = ex[0] + ay.f * (ex[1] - ex[0]), gx1 = ex[2] + ay.f * (ex[3] - ex[2]);
-    const float gx = gx0 + az.f * (gx1 - gx0);
-    const float gy = ey0 + az.f * (ey1 - ey0);
-    // dLoss/dx of the sample: h times the gradient (grid units to length)
-    const v3 q = mk3(ax.in ? gx * G.scale[0] * h : 0.f, ay.in ? gy * G.scale[1] * h : 0.f,
-                     az.in ? ez * G.scale[2] * h : 0.f);
-    obar += q;
-    dbar += q * a;
-    tbar += dot(q, d) * (((float)k + 0.5f) / S) + mu / S;
   }
+  r.tau = acc * h;
+  const float Ms[3] = {acc.x, acc.y, acc.z};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) r.T[c] += Ms[c] / S;
 }
 
 struct VtxAdj {
@@ -651,8 +669,17 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   float t = h4.x, b1 = h4.z, b2 = h4.w;
   int tri = __float_as_int(h4.y);
   HitGeo geo = load_geo(sc, tri);
-  Shade s = shade<GRID, FIELD>(sc, geo, o, d, t, b1, b2, code);
+  // with the grid, the interior segment's attenuation and its adjoint sums
+  // come from one pass over its samples (shade<false> leaves A to it)
+  Shade s = shade<false, FIELD>(sc, geo, o, d, t, b1, b2, code);
   const bool entering = (code & C_ENTER) != 0u, tir = (code & C_TIR) != 0u;
+  TauSums ts;
+  if constexpr (GRID) {
+    if (!entering) {
+      absorb_tau_sums(sc.ab, o, d, t, ts);
+      s.A = mk3(expf(-ts.tau.x), expf(-ts.tau.y), expf(-ts.tau.z));
+    }
+  }
   const bool degen = (code & C_DEGEN) != 0u;
   v3 L, Abar, dbar = mk3(0.f, 0.f, 0.f), xbar = mk3(0.f, 0.f, 0.f), nbar = mk3(0.f, 0.f, 0.f);
   v3 Mf = mk3(0.f, 0.f, 0.f);  // radiance beyond the hit (the field segment's far side)
@@ -731,7 +758,15 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
   v3 oabs = mk3(0.f, 0.f, 0.f), taubar = oabs;
   if (GRID && !entering) {
     taubar = -mul3(Abar, s.A);
-    absorb_tau_bwd(sc.ab, o, d, t, taubar, tbar, oabs, dbar);
+    if constexpr (GRID) {
+      const float tb[3] = {taubar.x, taubar.y, taubar.z};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        oabs += ts.G[c] * tb[c];
+        dbar += ts.D[c] * tb[c];
+        tbar += ts.T[c] * tb[c];
+      }
+    }
   } else if (!entering) {
     float sg0 = sc.sigma[0], sg1 = sc.sigma[1], sg2 = sc.sigma[2];
     acc.y += -Abar.x * t * s.A.x;
