@@ -53,8 +53,8 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h",
                     "paper_2603_00413_amd/csrc/bvh.hip"],
-        "sha256": "ab87cc74e10053de21cc2fb8f36c6436cb7fb617db90f012417771054ea2f05e",
-        "bytes": (316753.3 * 2.0 + 79345.2) * 1024,
+        "sha256": "76366e28640e05cdc6e80599cf57e7889ba43392cb475348bc074c7d7c080efa",
+        "bytes": (317148.9 * 2.0 + 79343.1) * 1024,
         # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:
         # wave-level VALU instructions per launch, and the share of lanes active
         # in them
