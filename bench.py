@@ -12,8 +12,8 @@ Metric: Mrays/s = ray segments intersected per step (every generation,
 counted once) / step time.  Prints one JSON line.  Beside the headline it
 reports the plain forward, the recompute form (stride 3), camera rays/s with
 and without the tree rebuild, and further legs unless switched off: a
-spatially varying absorption grid with its gradient and the texel gradient
-(--no-grid), the serving loop (--no-serve), the MLP-lit training step
+spatially varying absorption grid with its gradient, the texel gradient and a
+volumetric exterior field with its gradient (--no-grid), the serving loop (--no-serve), the MLP-lit training step
 (--no-mlp), the 2M-triangle thin shell (--no-stress) and the oracle's CPU
 rate (--no-cpu-baseline).
 """
@@ -116,7 +116,7 @@ def parse():
     ap.add_argument("--no-mlp", action="store_true", help="skip the MLP-lit training-step leg")
     ap.add_argument("--no-stress", action="store_true", help="skip the 2M-triangle thin-shell leg")
     ap.add_argument("--no-grid", action="store_true",
-                    help="skip the spatially varying absorption (grid) leg")
+                    help="skip the absorption-grid, texel-gradient and volumetric-field legs")
     ap.add_argument("--copy-only", action="store_true",
                     help="run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
@@ -299,6 +299,7 @@ def main():
         grid = grid_bench(args, dev, mesh, rays, env, ior, sigma, wl, cap, target, segs)
         grid["env_texel_gradient"] = texel_grad_bench(args, dev, mesh, rays, ior, sigma, wl, cap,
                                                       target, segs)
+        grid["volumetric_field"] = field_bench(args, dev, mesh, rays, env, ior, sigma, wl, cap, target, segs)
     buf_bytes = buf.ws_bytes + buf.tape_bytes
     del buf
     torch.cuda.empty_cache()
@@ -421,6 +422,66 @@ def grid_bench(args, dev, mesh, rays, env, ior, sigma, wl, cap, target, segs):
     del buf
     return {"workload": f"torus-102k fwd+bwd as above with a {n}^3 RGB absorption grid, "
                         f"{S} samples per interior segment, grid gradient written",
+            "ms_per_step": round(ms, 3), "Mrays/s": round(segs / ms / 1e3, 3),
+            "k_trace_ms_per_generation": np.round(tr, 4).tolist(),
+            "k_adjoint_ms_per_generation": np.round(ad, 4).tolist()}
+
+
+def field_bench(args, dev, mesh, rays, env, ior, sigma, wl, cap, target, segs):
+    """The torus fwd+bwd step with a volumetric exterior field: a seeded 32^3
+    grid plus three 64^2 planes (4 channels: density before the softplus,
+    colour) over a box 0.3 wider than the object on every side, 8 midpoint
+    samples per exterior segment inside the box; the field's gradient is
+    written every step."""
+    import torch
+
+    from paper_2603_00413_amd import binding as B
+    n, res, S = 32, 64, 8
+    rng = np.random.default_rng(11)
+    grid = np.empty((n, n, n, 4), np.float32)
+    grid[..., 0] = -1.5 + rng.normal(0.0, 0.6, (n, n, n))
+    grid[..., 1:] = rng.uniform(0.0, 0.5, (n, n, n, 3))
+    planes = np.empty((3, res, res, 4), np.float32)
+    planes[..., 0] = rng.normal(0.0, 0.4, (3, res, res))
+    planes[..., 1:] = rng.uniform(-0.1, 0.2, (3, res, res, 3))
+    lo, hi = wl.V.min(0) - 0.3, wl.V.max(0) + 0.3
+    field = B.Field(torch.from_numpy(grid).to(dev), torch.from_numpy(planes).to(dev), lo, hi, S)
+    scene = B.Scene(mesh, ior, sigma, env, field=field)
+    params = B.Params(max_depth=wl.max_depth, queue_capacity=cap, checkpoint_stride=args.stride)
+    buf = B.Buffers(params, rays, mesh, tape=True)
+
+    def step():
+        mesh.build()
+        rgb, _, _ = B.dt_trace_forward(scene, rays, params, buf, want_aux=False)
+        return B.dt_trace_backward(scene, rays, params, buf, (rgb - target) * (2.0 / rgb.numel()))
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    st = buf.stats.cpu().numpy()
+    assert st[B.STAT_DROPPED] == 0 and int(st[B.STAT_TOTAL]) == segs
+    timer = B.KernelTimer(wl.max_depth)
+    pt = B.Params(max_depth=wl.max_depth, queue_capacity=cap, checkpoint_stride=args.stride,
+                  timing=timer)
+    mesh.build()
+    rgb, _, _ = B.dt_trace_forward(scene, rays, pt, buf, want_aux=False)
+    B.dt_trace_backward(scene, rays, pt, buf, (rgb - target) * (2.0 / rgb.numel()))
+    torch.cuda.synchronize()
+    G = wl.max_depth + 1
+    tr, ad = np.array(timer.trace_ms(G)), np.array(timer.adjoint_ms(G))
+    assert torch.isfinite(field.d_grid).all() and float(field.d_grid.abs().sum()) > 0
+    assert torch.isfinite(field.d_planes).all() and float(field.d_planes.abs().sum()) > 0
+    log(f"volumetric field {n}^3 + 3 x {res}^2 x {S} samples: step {ms:.2f} ms; k_trace per gen ms "
+        f"{np.round(tr, 3).tolist()}; k_adjoint per gen ms {np.round(ad, 3).tolist()}")
+    del buf
+    return {"workload": f"torus-102k fwd+bwd as above with a volumetric exterior field ({n}^3 grid + "
+                        f"3 x {res}^2 planes, 4 channels, {S} samples per exterior segment in a box "
+                        f"0.3 wider than the object), field gradient written",
             "ms_per_step": round(ms, 3), "Mrays/s": round(segs / ms / 1e3, 3),
             "k_trace_ms_per_generation": np.round(tr, 4).tolist(),
             "k_adjoint_ms_per_generation": np.round(ad, 4).tolist()}

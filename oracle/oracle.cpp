@@ -616,11 +616,15 @@ inline Var Softplus(Var x) {
 
 // Position along one axis in node units u = (x - lo)(n - 1)/(hi - lo), the
 // cell (held fixed) and the fraction in it; margin: distance (node units) to
-// the nearest cell boundary.
+// the nearest cell boundary, less what float32 arithmetic can move u by (x,
+// the bounds and the scale each rounded, about 2^-24 (3 |u| + 4 |x| scale)
+// in node units, taken 8 times): a sample closer than that to a boundary may
+// fall in the other cell in float32, where the field's gradient jumps.
 template <class S>
 void field_axis(S x, double lo, double hi, int n, int& cell, S& frac, double& margin) {
   const double scale = (double)(n - 1) / (hi - lo);
   const double u = (val(x) - lo) * scale;
+  const double slack = 8.0 * 0x1p-24 * (3.0 * std::fabs(u) + 4.0 * std::fabs(val(x)) * scale);
   if (!(u > 0.0)) {
     cell = 0;
     frac = S(0.0);
@@ -632,7 +636,7 @@ void field_axis(S x, double lo, double hi, int n, int& cell, S& frac, double& ma
   } else {
     cell = std::min((int)std::floor(u), n - 2);
     frac = (x - S(lo)) * S(scale) - S((double)cell);
-    margin = std::min(u - cell, cell + 1 - u);
+    margin = std::min(u - cell, cell + 1 - u) - slack;
   }
 }
 
@@ -679,7 +683,8 @@ void field_feature(Ctx<S>& cx, V3<S> x, S out[4], double& margin) {
 // [0, t_end] (t_end = +inf for a ray that leaves), clipped to the field's
 // box.  The clip distances depend on o and d (and t_end); which box faces
 // clip is a discrete choice held fixed.  kink: set when a sample lies within
-// 1e-5 cell units of a cell boundary (the field's gradient jumps there).
+// 1e-5 cell units, beyond the float32 slack of field_axis, of a cell boundary
+// (the field's gradient jumps there).
 template <class S>
 void field_segment(Ctx<S>& cx, V3<S> o, V3<S> d, S t_end, bool open, V3<S>& C, S& T, bool& kink) {
   const or_field& F = *cx.sh->sc->field;

@@ -28,6 +28,7 @@ constexpr int AB = 256;               // threads per block of the adjoint kernel
 constexpr int ADJ_MAX_BLOCKS = 4096;  // grid cap of the adjoint kernel
 constexpr int TRACE_MAX_BLOCKS = 256 * 4 * 7;  // grid cap of the traversal kernel: 7 resident waves per SIMD
 constexpr size_t GG_SCRATCH = (size_t)32 << 20;  // workspace bytes for copies of the absorption-grid gradient
+constexpr size_t FG_SCRATCH = (size_t)32 << 20;  // workspace bytes for copies of the field gradient's cell records
 // Vertex adjoints of one hit, stored per node and summed per face afterwards:
 // d/d p0, p1, p2 and the shading-normal adjoint mbar with the barycentrics
 // (vertex normal k receives mbar b_k; mbar = 0 on flat-shaded hits).
@@ -54,7 +55,7 @@ struct Plan {
   size_t w_ctr, w_parts, w_part0, w_part1;
   size_t w_ro[2], w_rd[2], w_rw[2], w_hit, w_code;
   size_t w_adj[2][3];
-  size_t w_dN, w_sbar, w_red, w_miss, w_ovf, w_gscr, w_mlpg;
+  size_t w_dN, w_sbar, w_red, w_miss, w_ovf, w_gscr, w_mlpg, w_fscr, w_fseg;
   size_t w_frec, w_fkey, w_fidx, w_fcnt, w_foff, w_fscan, w_fg;  // per-face gathering of vertex adjoints
   size_t w_seg_o, w_seg_d, w_seg_w, w_seg_hit, w_seg_code, w_seg_child;  // k generations each
   size_t ws_bytes;
@@ -144,6 +145,10 @@ bool make_plan(const dt_trace_params* p, int64_t n_rays, int64_t npix, int32_t n
   o = dt_align(o + 4 * mc);
   P.w_gscr = o;  // copies of the absorption grid's gradient, summed at the end
   o = dt_align(o + GG_SCRATCH);
+  P.w_fscr = o;  // copies of the volumetric field's per-cell gradient records
+  o = dt_align(o + FG_SCRATCH);
+  P.w_fseg = o;  // per node of the current generation: its exterior field segment for k_field_grad
+  o = dt_align(o + 32 * mc);
   P.w_mlpg = o;  // per-block partial sums of the environment MLP's weight gradient
   o = dt_align(o + mlp_wgrad_scratch_bytes());
   P.w_ovf = o;   // per-lane traversal stack overflow of the traversal grid
@@ -287,7 +292,7 @@ __device__ __forceinline__ v3 mul3(v3 a, v3 b) { return mk3(a.x * b.x, a.y * b.y
 
 // ------------------------------------------------------------------ k_trace (a4 + a5 decisions + a6)
 template <bool GRID, bool FIELD>
-__global__ void __launch_bounds__(TB, 7) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
+__global__ void __launch_bounds__(TB, FIELD ? 4 : 7) k_trace(SceneDev sc, Gen q, int g, Counters* ctr,
                                               unsigned long long* part, float* rgb, float* wtrunc,
                                               int32_t* flags, unsigned long long* sig,
                                               int accumulate, uint2* ovf, WorkPart* wp, float4* att) {
@@ -624,13 +629,24 @@ struct VtxAdj {
 template <bool GRID, bool FIELD>
 __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, int64_t i,
                                              const float* grad_rgb, const Adj& nxt, const Adj& cur,
-                                             float4& acc, VtxAdj& out) {
+                                             float4& acc, VtxAdj& out, float4* fseg) {
   float4 o4 = q.o[i], d4 = q.d[i], w4 = q.w[i], h4 = q.hit[i];
   uint32_t code = q.code[i];
   v3 o = xyz(o4), d = xyz(d4), W = xyz(w4);
   int pix = __float_as_int(d4.w);
   v3 gp = load3(grad_rgb + 3 * pix);
   v3 gW = mul3(gp, W);
+  // With fseg, the field parameters' gradient is left to k_field_grad: this
+  // node's exterior segment (radiance beyond it, its upstream gradient, end
+  // and kind) goes to fseg and the backward here takes the ray's terms only.
+  FieldDev fdv = sc.fd;
+  if constexpr (FIELD) {
+    if (fseg) {
+      fdv.d_grid = nullptr;
+      fdv.d_planes = nullptr;
+      fseg[2 * i + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
   if (!(code & C_HIT)) {
     if (sc.env.kind != DT_ENV_EQUIRECT) return;  // written by the MLP kernel
     v3 dd;
@@ -643,7 +659,11 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
         v3 E = env_equirect_grad(sc.env, d, gW * T, &dd);
         v3 ob = mk3(0.f, 0.f, 0.f);
         float tb = 0.f;
-        field_segment_bwd(sc.fd, o, d, 0.f, true, E, gW, ob, dd, tb);
+        field_segment_bwd(fdv, o, d, 0.f, true, E, gW, ob, dd, tb);
+        if (fseg) {
+          fseg[2 * i] = make_float4(E.x, E.y, E.z, 0.f);
+          fseg[2 * i + 1] = make_float4(gW.x, gW.y, gW.z, 2.f);  // open segment
+        }
         const v3 L = C + E * T;
         cur.L[i] = make_float4(L.x, L.y, L.z, 0.f);
         cur.O[i] = make_float4(ob.x, ob.y, ob.z, 0.f);
@@ -779,7 +799,11 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
       // L = C + T M over the exterior segment [0, t]; T's effect on M is in
       // the field's backward (A = T is not used for the attenuation here)
       L = L + s.Cem;
-      field_segment_bwd(sc.fd, o, d, t, false, Mf, gW, oabs, dbar, tbar);
+      field_segment_bwd(fdv, o, d, t, false, Mf, gW, oabs, dbar, tbar);
+      if (fseg) {
+        fseg[2 * i] = make_float4(Mf.x, Mf.y, Mf.z, t);
+        fseg[2 * i + 1] = make_float4(gW.x, gW.y, gW.z, 1.f);  // closed segment [0, t]
+      }
     }
   }
   // cos_i = -d . n
@@ -857,7 +881,7 @@ template <bool GRID, bool FIELD>
 __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
                                                 const float* grad_rgb, Adj nxt, Adj cur,
                                                 FaceRec* frec, int2* fkey, uint32_t* fcnt,
-                                                float4* red) {
+                                                float4* red, float4* fseg) {
   const int64_t n = ctr->count[g];
   // each block takes one contiguous range of the generation, AB nodes a step
   const int64_t per = ((n + gridDim.x - 1) / gridDim.x + AB - 1) / AB * AB;
@@ -870,7 +894,7 @@ __global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const
     VtxAdj va;
     va.f = -1;
     va.m = mk3(0.f, 0.f, 0.f);
-    adjoint_node<GRID, FIELD>(sc, q, i, grad_rgb, nxt, cur, acc, va);
+    adjoint_node<GRID, FIELD>(sc, q, i, grad_rgb, nxt, cur, acc, va, fseg);
     int2 key = make_int2(-1, 0);
     if (va.f >= 0) {
       FaceRec r;
@@ -1116,6 +1140,197 @@ __global__ void k_grid_gather(const float* copies, int n_copies, int nx, int ny,
       }
     }
     d_mu[j] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ volumetric field gradient
+// dLoss/d(field values) of generation g's exterior segments.  Every sample x_k
+// of a segment adds fb_k w_j(x_k) at its 20 taps (fb_k: dLoss/d(feature) of
+// the sample, 4 channels; the samples and fb_k as in field_segment_bwd, from
+// the radiance beyond the segment and its upstream gradient that k_adjoint
+// left in fseg).  The taps of one sample fall in one grid cell (8 corners)
+// and one cell of each plane (4 corners), so a sample's contributions are a
+// record of 32 values for its grid cell and 16 for each plane cell.  Waves
+// step through the samples together; per sample the wave parks its lanes'
+// records in LDS and, per distinct cell among them, sums them and adds the
+// sums with one atomic per value into that cell's record (grid records of
+// FG_GREC floats, plane records of FG_PREC), in copy blockIdx.x % copies;
+// k_field_gather turns the records into node values.  Neighbouring rays
+// sample the same cells, so a wave's atomics shrink to a few per cell.
+constexpr int FG_T = 256;
+constexpr int FG_GREC = 32;  // 8 corners x 4 channels
+constexpr int FG_PREC = 16;  // 4 corners x 4 channels
+constexpr int FG_MAX_COPIES = 16;
+
+__device__ __forceinline__ size_t field_rec_floats(const FieldDev& F) {
+  const size_t pc = (size_t)(F.res - 1);
+  return (size_t)FG_GREC * (F.nx - 1) * (F.ny - 1) * (F.nz - 1) + 3 * FG_PREC * pc * pc;
+}
+
+// the wave's parked records (nv values and a key per lane) summed per distinct
+// key and added to base + key * nv + value
+__device__ __forceinline__ void merge_add(float (*park)[FG_GREC + 1], int nv, int key, float* base) {
+  const int lane = (int)(threadIdx.x & 63u);
+  park[lane][FG_GREC] = __int_as_float(key);
+  wave_lds_sync();
+  uint64_t pending = __ballot(key >= 0);
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int kl = __builtin_amdgcn_readlane(key, leader);
+    const uint64_t m = __ballot(key == kl);
+    pending &= ~m;
+    if (lane < nv) {
+      float sum = 0.f;
+      for (uint64_t mm = m; mm; mm &= mm - 1ull) sum += park[__ffsll((unsigned long long)mm) - 1][lane];
+      if (sum != 0.f) atomicAdd(base + (size_t)kl * nv + lane, sum);
+    }
+  }
+  wave_lds_sync();
+}
+
+__global__ void __launch_bounds__(FG_T) k_field_grad(FieldDev F, Gen q, int g, const Counters* ctr,
+                                                     const float4* fseg, float* copies, int n_copies) {
+  __shared__ float park[FG_T / 64][64][FG_GREC + 1];
+  const int64_t n = ctr->count[g];
+  const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
+  const int cx = F.nx - 1, cy = F.ny - 1, pc = F.res - 1;
+  float* gdst = copies + (size_t)(blockIdx.x % (unsigned)n_copies) * field_rec_floats(F);
+  float* pdst = gdst + (size_t)FG_GREC * cx * cy * (F.nz - 1);
+  const int S = F.samples;
+  for (int64_t base = (int64_t)blockIdx.x * FG_T; base < n; base += (int64_t)gridDim.x * FG_T) {
+    const int64_t i = base + threadIdx.x;
+    bool act = false, open = false;
+    v3 o = mk3(0.f, 0.f, 0.f), d = o, M = o, Lb = o;
+    float tend = 0.f;
+    if (i < n) {
+      const float4 b = fseg[2 * i + 1];
+      if (b.w != 0.f) {
+        const float4 a = fseg[2 * i];
+        act = true;
+        open = b.w > 1.5f;
+        M = xyz(a);
+        tend = a.w;
+        Lb = xyz(b);
+        o = xyz(q.o[i]);
+        d = xyz(q.d[i]);
+      }
+    }
+    FieldClip cl;
+    cl.s0 = cl.s1 = 0.f;
+    if (act && !field_clip(F, o, d, tend, open, cl)) act = false;
+    const float h = act ? (cl.s1 - cl.s0) / (float)S : 0.f;
+    // the segment's emission and transmittance (field_segment_bwd's first pass)
+    v3 Ctot = mk3(0.f, 0.f, 0.f);
+    float T = 1.f;
+    if (act)
+      for (int k = 0; k < S; ++k) {
+        float f[4];
+        field_feature(F, o + d * (cl.s0 + h * ((float)k + 0.5f)), f);
+        const float a = expf(-softplusf(f[0]) * h);
+        Ctot = Ctot + mk3(f[1], f[2], f[3]) * (T * (1.f - a));
+        T *= a;
+      }
+    const v3 tail = M * T;
+    v3 P = mk3(0.f, 0.f, 0.f);
+    float Tk = 1.f;
+    for (int k = 0; k < S; ++k) {
+      float fb[4] = {0.f, 0.f, 0.f, 0.f};
+      v3 xk = mk3(0.f, 0.f, 0.f);
+      if (act) {
+        xk = o + d * (cl.s0 + h * ((float)k + 0.5f));
+        float f[4];
+        field_feature(F, xk, f);
+        const float sig = softplusf(f[0]);
+        const float a = expf(-sig * h);
+        const v3 c = mk3(f[1], f[2], f[3]);
+        const float w = Tk * (1.f - a);
+        P = P + c * w;
+        const float Tn = Tk * a;
+        const v3 after = (Ctot - P) + tail;
+        const float gg = dot(Lb, c * Tn - after);
+        fb[0] = h * gg / (1.f + expf(-f[0]));
+        fb[1] = w * Lb.x;
+        fb[2] = w * Lb.y;
+        fb[3] = w * Lb.z;
+        Tk = Tn;
+      }
+      const float xs[3] = {xk.x, xk.y, xk.z};
+      FieldAxis ga[3], pa[3];
+      const int nn[3] = {F.nx, F.ny, F.nz};
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        ga[ax] = field_axis(xs[ax], F.lo[ax], F.sg[ax], nn[ax]);
+        pa[ax] = field_axis(xs[ax], F.lo[ax], F.sp[ax], F.res);
+      }
+      // the grid cell's record: corner c = (dx, dy, dz) bits 0-2, channel ch
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const float wx = (c & 1) ? ga[0].f : 1.f - ga[0].f, wy = ((c >> 1) & 1) ? ga[1].f : 1.f - ga[1].f;
+        const float wz = (c >> 2) ? ga[2].f : 1.f - ga[2].f;
+        const float wc = wx * wy * wz;
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) park[wv][lane][4 * c + ch] = wc * fb[ch];
+      }
+      merge_add(park[wv], FG_GREC, act ? (ga[2].i * cy + ga[1].i) * cx + ga[0].i : -1, gdst);
+      // each plane's cell: (x, y), (x, z), (y, z); corner (di, dj), channel ch
+#pragma unroll
+      for (int qp = 0; qp < 3; ++qp) {
+        const int a = qp == 2 ? 1 : 0, b = qp == 0 ? 1 : 2;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float wa = (c & 1) ? pa[a].f : 1.f - pa[a].f, wb = (c >> 1) ? pa[b].f : 1.f - pa[b].f;
+#pragma unroll
+          for (int ch = 0; ch < 4; ++ch) park[wv][lane][4 * c + ch] = wa * wb * fb[ch];
+        }
+        merge_add(park[wv], FG_PREC, act ? (qp * pc + pa[b].i) * pc + pa[a].i : -1, pdst);
+      }
+    }
+  }
+}
+
+// d_grid and d_planes from the cell records: a node is corner (dx, dy, dz) of
+// the grid cell (x - dx, y - dy, z - dz), or corner (di, dj) of the plane
+// cell (i - di, j - dj), where that cell exists; summed over corners, then
+// copies, in a fixed order
+__global__ void k_field_gather(FieldDev F, const float* copies, int n_copies) {
+  const int nx = F.nx, ny = F.ny, nz = F.nz, res = F.res;
+  const int cx = nx - 1, cy = ny - 1, cz = nz - 1, pc = res - 1;
+  const size_t copy = field_rec_floats(F);
+  const size_t gfl = (size_t)FG_GREC * cx * cy * cz;
+  const int64_t ng = 4 * (int64_t)nx * ny * nz, np = 12 * (int64_t)res * res;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ng + np;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    float acc = 0.f;
+    if (j < ng) {
+      const int ch = (int)(j & 3);
+      const int64_t node = j >> 2;
+      const int x = (int)(node % nx), y = (int)((node / nx) % ny), z = (int)(node / ((int64_t)nx * ny));
+      for (int r = 0; r < n_copies; ++r) {
+        const float* cp = copies + (size_t)r * copy;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int ux = x - (c & 1), uy = y - ((c >> 1) & 1), uz = z - (c >> 2);
+          if (ux >= 0 && ux < cx && uy >= 0 && uy < cy && uz >= 0 && uz < cz)
+            acc += cp[((size_t)(uz * cy + uy) * cx + ux) * FG_GREC + 4 * c + ch];
+        }
+      }
+      F.d_grid[j] = acc;
+    } else {
+      const int64_t jp = j - ng;
+      const int ch = (int)(jp & 3);
+      const int64_t node = jp >> 2;
+      const int qp = (int)(node / ((int64_t)res * res)), jj = (int)((node / res) % res), ii = (int)(node % res);
+      for (int r = 0; r < n_copies; ++r) {
+        const float* cp = copies + (size_t)r * copy + gfl;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int ui = ii - (c & 1), uj = jj - (c >> 1);
+          if (ui >= 0 && ui < pc && uj >= 0 && uj < pc)
+            acc += cp[((size_t)(qp * pc + uj) * pc + ui) * FG_PREC + 4 * c + ch];
+        }
+      }
+      F.d_planes[jp] = acc;
+    }
   }
 }
 
@@ -1807,9 +2022,25 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   if (sc.env.d_w)
     if (dt_status st = zero_f32(mlp_part, (int64_t)(mlp_wgrad_scratch_bytes() / sizeof(float)), s))
       return st;
+  // volumetric field: as many copies of the per-cell records as the scratch
+  // region holds (at most FG_MAX_COPIES); a field whose records do not fit has
+  // its gradient added in place by the adjoint instead
+  float* fcopies = (float*)(W + P.w_fscr);
+  int f_copies = 0;
+  float4* fseg = nullptr;
   if (sc.fd.d_grid) {
-    if (dt_status st = zero_f32(sc.fd.d_grid, 4 * (int64_t)sc.fd.nx * sc.fd.ny * sc.fd.nz, s)) return st;
-    if (dt_status st = zero_f32(sc.fd.d_planes, 12 * (int64_t)sc.fd.res * sc.fd.res, s)) return st;
+    const int64_t pc = sc.fd.res - 1;
+    const int64_t rec = (int64_t)FG_GREC * (sc.fd.nx - 1) * (sc.fd.ny - 1) * (sc.fd.nz - 1) + 3 * FG_PREC * pc * pc;
+    const int64_t fit = (int64_t)(FG_SCRATCH / sizeof(float)) / rec;
+    f_copies = (int)(fit < FG_MAX_COPIES ? fit : FG_MAX_COPIES);
+    if (f_copies >= 1) {
+      fseg = (float4*)(W + P.w_fseg);
+      if (dt_status st = zero_f32(fcopies, rec * f_copies, s)) return st;
+    } else {
+      f_copies = 0;
+      if (dt_status st = zero_f32(sc.fd.d_grid, 4 * (int64_t)sc.fd.nx * sc.fd.ny * sc.fd.nz, s)) return st;
+      if (dt_status st = zero_f32(sc.fd.d_planes, 12 * (int64_t)sc.fd.res * sc.fd.res, s)) return st;
+    }
   }
   if (dt_status st = zero_f32((float*)red, 4 * (int64_t)nred, s)) return st;
   Adj adj[2];
@@ -1839,7 +2070,7 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
     }
 #define DT_ADJ(G, FL)                                                                                  \
   hipLaunchKernelGGL((k_adjoint<G, FL>), dim3((unsigned)blocks), dim3(AB), 0, s, sc, q, g, ctr, grad_rgb,  \
-                     adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red)
+                     adj[(g + 1) & 1], adj[g & 1], frec, fkey, fcnt, red, fseg)
     if (sc.fd.grid) {
       if (sc.ab.mu) DT_ADJ(true, true); else DT_ADJ(false, true);
     } else {
@@ -1850,6 +2081,11 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
       const int64_t eb = (P.cap[g] + GG_T - 1) / GG_T;
       hipLaunchKernelGGL(k_env_tex_grad, dim3((unsigned)(eb < 8192 ? eb : 8192)), dim3(GG_T), 0, s, sc, q, g,
                          ctr, grad_rgb);
+    }
+    if (fseg) {
+      const int64_t fb = (P.cap[g] + FG_T - 1) / FG_T;
+      hipLaunchKernelGGL(k_field_grad, dim3((unsigned)(fb < 8192 ? fb : 8192)), dim3(FG_T), 0, s, sc.fd, q, g,
+                         ctr, fseg, fcopies, f_copies);
     }
     if (sc.ab.mu && sc.ab.d_mu) {
       const int64_t gb = (P.cap[g] + GG_T - 1) / GG_T;
@@ -1919,6 +2155,11 @@ extern "C" dt_status dt_trace_backward(const dt_scene* scene, const dt_rays* ray
   hipLaunchKernelGGL(k_reduce_scalars, dim3(1), dim3(RED_T), 0, s, red, nred, d_ior, d_sigma);
   if (sc.env.d_w)
     if (dt_status st = mlp_wgrad_reduce(sc.env, mlp_part, s)) return st;
+  if (fseg) {
+    const int64_t nfe = 4 * (int64_t)sc.fd.nx * sc.fd.ny * sc.fd.nz + 12 * (int64_t)sc.fd.res * sc.fd.res;
+    hipLaunchKernelGGL(k_field_gather, dim3(dt_blocks(nfe, 256) < 4096 ? dt_blocks(nfe, 256) : 4096), dim3(256), 0,
+                       s, sc.fd, fcopies, f_copies);
+  }
   if (n_copies > 0 && gcell)
     hipLaunchKernelGGL(k_grid_gather, dim3(dt_blocks(gsize, 256) < 4096 ? dt_blocks(gsize, 256) : 4096), dim3(256),
                        0, s, gcopies, n_copies, sc.ab.nx, sc.ab.ny, sc.ab.nz, sc.ab.d_mu);

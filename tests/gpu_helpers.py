@@ -280,7 +280,12 @@ class GradRef:
     that of the summed gradient, where the deviations of different pixels may
     partly cancel in one run; with K = 2 a few elements in 10^5 came out
     below the device's deviation for that reason, and each further run makes
-    such a chance underestimate rarer by a large factor.  `stable`
+    such a chance underestimate rarer by a large factor.  An absorption grid's
+    or a volumetric field's box is perturbed too, each bound by PERTURB_U of
+    the box's extent: the device holds the bounds and the per-axis scale
+    (n - 1) / (hi - lo) in float32, which moves a sample's grid coordinate by
+    up to about n 2^-24, and a node reached only through a trilinear weight
+    near zero carries that as a large relative error.  `stable`
     marks the pixels whose discrete path is the same under every perturbation:
     the others have no defined gradient comparison."""
 
@@ -295,9 +300,20 @@ class GradRef:
 
         self.perturbed = []
         self.stable = np.ones(len(self.o), bool)
+        def box(b):
+            ext = b.hi - b.lo
+            return b.lo + u * rng.uniform(-1.0, 1.0, 3) * ext, b.hi + u * rng.uniform(-1.0, 1.0, 3) * ext
+
         for j in range(k):
+            extra = {}
+            if orc.absorb is not None:
+                lo, hi = box(orc.absorb)
+                extra["absorb"] = oracle.Absorption(orc.absorb.mu, lo, hi, orc.absorb.samples)
+            if orc.field is not None:
+                lo, hi = box(orc.field)
+                extra["field"] = oracle.Field(orc.field.grid, orc.field.planes, lo, hi, orc.field.samples)
             sc = orc.with_(V=jit(orc.V), eta=float(jit(orc.eta)), sigma=jit(orc.sigma), jitter=u,
-                           jitter_seed=seed * 1000 + j)
+                           jitter_seed=seed * 1000 + j, **extra)
             self.perturbed.append(sc)
             self.stable &= sc.trace(self.o, self.d)["sig"] == np.asarray(sig)
 

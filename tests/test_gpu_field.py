@@ -113,6 +113,14 @@ def test_backward_icosphere_field():
     _grad_check(P, seed=5, label="icosphere field")
 
 
+def test_backward_large_field_in_place():
+    """A 70 x 68 x 72 grid, whose per-cell gradient records (128 bytes for each
+    of its 328k cells) exceed the 32 MB scratch region: the adjoint adds the
+    field's gradient in place instead of handing its segments on."""
+    P = _with_field(icosphere_pair(sigma=(0.5, 0.2, 0.1)), seed=12, samples=6, n=(70, 68, 72), res=9)
+    _grad_check(P, seed=13, label="large field")
+
+
 def test_backward_wide_box_and_texels():
     """Camera rays that start inside the box (no entry face), with the
     equirect texel gradient weighted by the field's transmittance."""
