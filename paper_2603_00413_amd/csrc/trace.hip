@@ -877,8 +877,10 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
 // scatter sort the nodes by face; then each face sums its records and adds
 // the totals to its three vertices (18 atomics per hit face instead of 18 per
 // hit).
+// (the field's instantiations, whose segment replays hold some 300 registers
+// a lane, are held to 256 so that two waves share a SIMD)
 template <bool GRID, bool FIELD>
-__global__ void __launch_bounds__(AB) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
+__global__ void __launch_bounds__(AB, FIELD ? 2 : 1) k_adjoint(SceneDev sc, Gen q, int g, const Counters* ctr,
                                                 const float* grad_rgb, Adj nxt, Adj cur,
                                                 FaceRec* frec, int2* fkey, uint32_t* fcnt,
                                                 float4* red, float4* fseg) {
@@ -1167,11 +1169,13 @@ __device__ __forceinline__ size_t field_rec_floats(const FieldDev& F) {
   return (size_t)FG_GREC * (F.nx - 1) * (F.ny - 1) * (F.nz - 1) + 3 * FG_PREC * pc * pc;
 }
 
-// the wave's parked records (nv values and a key per lane) summed per distinct
-// key and added to base + key * nv + value
-__device__ __forceinline__ void merge_add(float (*park)[FG_GREC + 1], int nv, int key, float* base) {
+constexpr int FG_PARK = 52;  // per lane: up to 48 parked values, then up to 3 keys
+
+// the wave's parked grid records (FG_GREC values and a key per lane) summed
+// per distinct key and added to base + key * FG_GREC + value
+__device__ __forceinline__ void merge_grid(float (*park)[FG_PARK], int key, float* base) {
   const int lane = (int)(threadIdx.x & 63u);
-  park[lane][FG_GREC] = __int_as_float(key);
+  park[lane][48] = __int_as_float(key);
   wave_lds_sync();
   uint64_t pending = __ballot(key >= 0);
   while (pending) {
@@ -1179,10 +1183,46 @@ __device__ __forceinline__ void merge_add(float (*park)[FG_GREC + 1], int nv, in
     const int kl = __builtin_amdgcn_readlane(key, leader);
     const uint64_t m = __ballot(key == kl);
     pending &= ~m;
-    if (lane < nv) {
+    if (lane < FG_GREC) {
       float sum = 0.f;
       for (uint64_t mm = m; mm; mm &= mm - 1ull) sum += park[__ffsll((unsigned long long)mm) - 1][lane];
-      if (sum != 0.f) atomicAdd(base + (size_t)kl * nv + lane, sum);
+      if (sum != 0.f) atomicAdd(base + (size_t)kl * FG_GREC + lane, sum);
+    }
+  }
+  wave_lds_sync();
+}
+
+// the same for the three planes' records at once (plane q's FG_PREC values
+// parked at 16 q, its key k[q]): lanes 16 q .. 16 q + 15 take plane q's
+// distinct cells, so a pass adds up to one cell of each plane
+__device__ __forceinline__ void merge_planes(float (*park)[FG_PARK], const int k[3], float* base) {
+  const int lane = (int)(threadIdx.x & 63u), grp = lane >> 4, comp = lane & 15;
+  uint64_t pend0 = __ballot(k[0] >= 0), pend1 = __ballot(k[1] >= 0), pend2 = __ballot(k[2] >= 0);
+  wave_lds_sync();
+  while (pend0 | pend1 | pend2) {
+    int k0 = -1, k1 = -1, k2 = -1;
+    uint64_t m0 = 0ull, m1 = 0ull, m2 = 0ull;
+    if (pend0) {
+      k0 = __builtin_amdgcn_readlane(k[0], __ffsll((unsigned long long)pend0) - 1);
+      m0 = __ballot(k[0] == k0);
+      pend0 &= ~m0;
+    }
+    if (pend1) {
+      k1 = __builtin_amdgcn_readlane(k[1], __ffsll((unsigned long long)pend1) - 1);
+      m1 = __ballot(k[1] == k1);
+      pend1 &= ~m1;
+    }
+    if (pend2) {
+      k2 = __builtin_amdgcn_readlane(k[2], __ffsll((unsigned long long)pend2) - 1);
+      m2 = __ballot(k[2] == k2);
+      pend2 &= ~m2;
+    }
+    const int kg = grp == 0 ? k0 : (grp == 1 ? k1 : (grp == 2 ? k2 : -1));
+    if (kg >= 0) {
+      float sum = 0.f;
+      for (uint64_t mm = grp == 0 ? m0 : (grp == 1 ? m1 : m2); mm; mm &= mm - 1ull)
+        sum += park[__ffsll((unsigned long long)mm) - 1][16 * grp + comp];
+      if (sum != 0.f) atomicAdd(base + (size_t)kg * FG_PREC + comp, sum);
     }
   }
   wave_lds_sync();
@@ -1190,7 +1230,7 @@ __device__ __forceinline__ void merge_add(float (*park)[FG_GREC + 1], int nv, in
 
 __global__ void __launch_bounds__(FG_T) k_field_grad(FieldDev F, Gen q, int g, const Counters* ctr,
                                                      const float4* fseg, float* copies, int n_copies) {
-  __shared__ float park[FG_T / 64][64][FG_GREC + 1];
+  __shared__ float park[FG_T / 64][64][FG_PARK];
   const int64_t n = ctr->count[g];
   const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
   const int cx = F.nx - 1, cy = F.ny - 1, pc = F.res - 1;
@@ -1271,8 +1311,9 @@ __global__ void __launch_bounds__(FG_T) k_field_grad(FieldDev F, Gen q, int g, c
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) park[wv][lane][4 * c + ch] = wc * fb[ch];
       }
-      merge_add(park[wv], FG_GREC, act ? (ga[2].i * cy + ga[1].i) * cx + ga[0].i : -1, gdst);
+      merge_grid(park[wv], act ? (ga[2].i * cy + ga[1].i) * cx + ga[0].i : -1, gdst);
       // each plane's cell: (x, y), (x, z), (y, z); corner (di, dj), channel ch
+      int kp[3];
 #pragma unroll
       for (int qp = 0; qp < 3; ++qp) {
         const int a = qp == 2 ? 1 : 0, b = qp == 0 ? 1 : 2;
@@ -1280,10 +1321,11 @@ __global__ void __launch_bounds__(FG_T) k_field_grad(FieldDev F, Gen q, int g, c
         for (int c = 0; c < 4; ++c) {
           const float wa = (c & 1) ? pa[a].f : 1.f - pa[a].f, wb = (c >> 1) ? pa[b].f : 1.f - pa[b].f;
 #pragma unroll
-          for (int ch = 0; ch < 4; ++ch) park[wv][lane][4 * c + ch] = wa * wb * fb[ch];
+          for (int ch = 0; ch < 4; ++ch) park[wv][lane][16 * qp + 4 * c + ch] = wa * wb * fb[ch];
         }
-        merge_add(park[wv], FG_PREC, act ? (qp * pc + pa[b].i) * pc + pa[a].i : -1, pdst);
+        kp[qp] = act ? (qp * pc + pa[b].i) * pc + pa[a].i : -1;
       }
+      merge_planes(park[wv], kp, pdst);
     }
   }
 }
