@@ -168,27 +168,17 @@ __device__ __forceinline__ void field_segment(const FieldDev& F, v3 o, v3 d, flo
 }
 
 // Backward of L = C + T_S M for the upstream gradient Lbar (M: the radiance
-// beyond the segment, its own gradient T_S Lbar is the caller's): adds the
-// gradients of the origin, the direction and (closed segments ending inside
-// the box) of t_end, and scatters the field parameters' gradients (float
-// atomics) when the field has gradient targets.
+// beyond the segment, its own gradient T_S Lbar is the caller's; Ltot = C +
+// T_S M, the segment's radiance, which the caller has from field_segment):
+// adds the gradients of the origin, the direction and (closed segments
+// ending inside the box) of t_end, and scatters the field parameters'
+// gradients (float atomics) when the field has gradient targets.
 __device__ __forceinline__ void field_segment_bwd(const FieldDev& F, v3 o, v3 d, float t_end, bool open,
-                                                  v3 M, v3 Lbar, v3& obar, v3& dbar, float& tbar) {
+                                                  v3 Ltot, v3 Lbar, v3& obar, v3& dbar, float& tbar) {
   FieldClip cl;
   if (!field_clip(F, o, d, t_end, open, cl)) return;
   const int S = F.samples;
   const float h = (cl.s1 - cl.s0) / (float)S;
-  // forward: the total emission and transmittance
-  v3 Ctot = mk3(0.f, 0.f, 0.f);
-  float T = 1.f;
-  for (int k = 0; k < S; ++k) {
-    float f[4];
-    field_feature(F, o + d * (cl.s0 + h * ((float)k + 0.5f)), f);
-    const float a = expf(-softplusf(f[0]) * h);
-    Ctot = Ctot + mk3(f[1], f[2], f[3]) * (T * (1.f - a));
-    T *= a;
-  }
-  const v3 tail = M * T;  // T_S M
   // backward, front to back with the running prefix of the emission
   v3 P = mk3(0.f, 0.f, 0.f);
   float Tk = 1.f, hbar = 0.f, s0bar = 0.f;
@@ -204,7 +194,7 @@ __device__ __forceinline__ void field_segment_bwd(const FieldDev& F, v3 o, v3 d,
     P = P + c * w;
     const float Tn = Tk * a;
     // everything after sample k, and dL/dsigma_k = h (T_{k+1} c_k - after_k) . Lbar
-    const v3 after = (Ctot - P) + tail;
+    const v3 after = Ltot - P;
     const float g = dot(Lbar, c * Tn - after);
     const float sigbar = h * g;
     hbar += sig * g;

@@ -659,12 +659,12 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
         v3 E = env_equirect_grad(sc.env, d, gW * T, &dd);
         v3 ob = mk3(0.f, 0.f, 0.f);
         float tb = 0.f;
-        field_segment_bwd(fdv, o, d, 0.f, true, E, gW, ob, dd, tb);
+        const v3 L = C + E * T;
+        field_segment_bwd(fdv, o, d, 0.f, true, L, gW, ob, dd, tb);
         if (fseg) {
-          fseg[2 * i] = make_float4(E.x, E.y, E.z, 0.f);
+          fseg[2 * i] = make_float4(L.x, L.y, L.z, 0.f);
           fseg[2 * i + 1] = make_float4(gW.x, gW.y, gW.z, 2.f);  // open segment
         }
-        const v3 L = C + E * T;
         cur.L[i] = make_float4(L.x, L.y, L.z, 0.f);
         cur.O[i] = make_float4(ob.x, ob.y, ob.z, 0.f);
         cur.D[i] = make_float4(dd.x, dd.y, dd.z, 0.f);
@@ -799,9 +799,11 @@ __device__ __forceinline__ void adjoint_node(const SceneDev& sc, const Gen& q, i
       // L = C + T M over the exterior segment [0, t]; T's effect on M is in
       // the field's backward (A = T is not used for the attenuation here)
       L = L + s.Cem;
-      field_segment_bwd(fdv, o, d, t, false, Mf, gW, oabs, dbar, tbar);
+      // the segment's radiance C + T M (A = T here)
+      const v3 Lseg = s.Cem + Mf * s.A.x;
+      field_segment_bwd(fdv, o, d, t, false, Lseg, gW, oabs, dbar, tbar);
       if (fseg) {
-        fseg[2 * i] = make_float4(Mf.x, Mf.y, Mf.z, t);
+        fseg[2 * i] = make_float4(Lseg.x, Lseg.y, Lseg.z, t);
         fseg[2 * i + 1] = make_float4(gW.x, gW.y, gW.z, 1.f);  // closed segment [0, t]
       }
     }
@@ -1149,8 +1151,8 @@ __global__ void k_grid_gather(const float* copies, int n_copies, int nx, int ny,
 // dLoss/d(field values) of generation g's exterior segments.  Every sample x_k
 // of a segment adds fb_k w_j(x_k) at its 20 taps (fb_k: dLoss/d(feature) of
 // the sample, 4 channels; the samples and fb_k as in field_segment_bwd, from
-// the radiance beyond the segment and its upstream gradient that k_adjoint
-// left in fseg).  The taps of one sample fall in one grid cell (8 corners)
+// the segment's radiance and its upstream gradient that k_adjoint left in
+// fseg).  The taps of one sample fall in one grid cell (8 corners)
 // and one cell of each plane (4 corners), so a sample's contributions are a
 // record of 32 values for its grid cell and 16 for each plane cell.  Waves
 // step through the samples together; per sample the wave parks its lanes'
@@ -1240,7 +1242,7 @@ __global__ void __launch_bounds__(FG_T) k_field_grad(FieldDev F, Gen q, int g, c
   for (int64_t base = (int64_t)blockIdx.x * FG_T; base < n; base += (int64_t)gridDim.x * FG_T) {
     const int64_t i = base + threadIdx.x;
     bool act = false, open = false;
-    v3 o = mk3(0.f, 0.f, 0.f), d = o, M = o, Lb = o;
+    v3 o = mk3(0.f, 0.f, 0.f), d = o, Lt = o, Lb = o;
     float tend = 0.f;
     if (i < n) {
       const float4 b = fseg[2 * i + 1];
@@ -1248,7 +1250,7 @@ __global__ void __launch_bounds__(FG_T) k_field_grad(FieldDev F, Gen q, int g, c
         const float4 a = fseg[2 * i];
         act = true;
         open = b.w > 1.5f;
-        M = xyz(a);
+        Lt = xyz(a);
         tend = a.w;
         Lb = xyz(b);
         o = xyz(q.o[i]);
@@ -1259,18 +1261,6 @@ __global__ void __launch_bounds__(FG_T) k_field_grad(FieldDev F, Gen q, int g, c
     cl.s0 = cl.s1 = 0.f;
     if (act && !field_clip(F, o, d, tend, open, cl)) act = false;
     const float h = act ? (cl.s1 - cl.s0) / (float)S : 0.f;
-    // the segment's emission and transmittance (field_segment_bwd's first pass)
-    v3 Ctot = mk3(0.f, 0.f, 0.f);
-    float T = 1.f;
-    if (act)
-      for (int k = 0; k < S; ++k) {
-        float f[4];
-        field_feature(F, o + d * (cl.s0 + h * ((float)k + 0.5f)), f);
-        const float a = expf(-softplusf(f[0]) * h);
-        Ctot = Ctot + mk3(f[1], f[2], f[3]) * (T * (1.f - a));
-        T *= a;
-      }
-    const v3 tail = M * T;
     v3 P = mk3(0.f, 0.f, 0.f);
     float Tk = 1.f;
     for (int k = 0; k < S; ++k) {
@@ -1286,7 +1276,7 @@ __global__ void __launch_bounds__(FG_T) k_field_grad(FieldDev F, Gen q, int g, c
         const float w = Tk * (1.f - a);
         P = P + c * w;
         const float Tn = Tk * a;
-        const v3 after = (Ctot - P) + tail;
+        const v3 after = Lt - P;
         const float gg = dot(Lb, c * Tn - after);
         fb[0] = h * gg / (1.f + expf(-f[0]));
         fb[1] = w * Lb.x;
