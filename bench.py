@@ -53,8 +53,8 @@ MEASURED_TRAFFIC = {
         "sources": ["paper_2603_00413_amd/csrc/trace.hip", "paper_2603_00413_amd/csrc/dt_device.h",
                     "paper_2603_00413_amd/csrc/dt_internal.h", "paper_2603_00413_amd/csrc/dt_queue.h",
                     "paper_2603_00413_amd/csrc/bvh.hip"],
-        "sha256": "27fe50c19a34e559de5baeb14a5a345c36b5adeee8c125f96807996755d8c6e7",
-        "bytes": (317033.6 * 2.0 + 79343.8) * 1024,
+        "sha256": "3f81142cced588f5d14840ca135c9dcc59b1b8a4dbcf75baa9ab5206c1062c94",
+        "bytes": (316911.5 * 2.0 + 79344.9) * 1024,
         # rocprofv3 --pmc SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_ACTIVE_INST_VALU:
         # wave-level VALU instructions per launch, and the share of lanes active
         # in them
