@@ -185,8 +185,22 @@ __device__ __forceinline__ void field_segment_bwd(const FieldDev& F, v3 o, v3 d,
   for (int k = 0; k < S; ++k) {
     const float sk = cl.s0 + h * ((float)k + 0.5f);
     const v3 xk = o + d * sk;
-    float f[4];
-    field_feature(F, xk, f);
+    // the feature and, per channel, its gradient in x, from one pass over the
+    // taps (the feature's operations are field_feature's, so the same bits)
+    float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f;
+    v3 G0 = mk3(0.f, 0.f, 0.f), G1 = G0, G2 = G0, G3 = G0;
+    field_for_taps(F, xk, [&](int64_t j, float wj, v3 dwj) {
+      const float4 v = *(const float4*)field_param(F, j);
+      f0 += wj * v.x;
+      f1 += wj * v.y;
+      f2 += wj * v.z;
+      f3 += wj * v.w;
+      G0 = G0 + dwj * v.x;
+      G1 = G1 + dwj * v.y;
+      G2 = G2 + dwj * v.z;
+      G3 = G3 + dwj * v.w;
+    });
+    const float f[4] = {f0, f1, f2, f3};
     const float sig = softplusf(f[0]);
     const float a = expf(-sig * h);
     const v3 c = mk3(f[1], f[2], f[3]);
@@ -199,18 +213,15 @@ __device__ __forceinline__ void field_segment_bwd(const FieldDev& F, v3 o, v3 d,
     const float sigbar = h * g;
     hbar += sig * g;
     const float fb[4] = {sigbar / (1.f + expf(-f[0])), w * Lbar.x, w * Lbar.y, w * Lbar.z};
-    v3 xbar = mk3(0.f, 0.f, 0.f);
-    field_for_taps(F, xk, [&](int64_t j, float wj, v3 dwj) {
-      const float4 v = *(const float4*)field_param(F, j);
-      xbar = xbar + dwj * (fb[0] * v.x + fb[1] * v.y + fb[2] * v.z + fb[3] * v.w);
-      if (F.d_grid) {
+    const v3 xbar = G0 * fb[0] + G1 * fb[1] + G2 * fb[2] + G3 * fb[3];
+    if (F.d_grid)
+      field_for_taps(F, xk, [&](int64_t j, float wj, v3) {
         float* q = field_dparam(F, j);
         atomicAdd(q, wj * fb[0]);
         atomicAdd(q + 1, wj * fb[1]);
         atomicAdd(q + 2, wj * fb[2]);
         atomicAdd(q + 3, wj * fb[3]);
-      }
-    });
+      });
     // x_k = o + (s0 + (k + 1/2) h) d
     obar = obar + xbar;
     dbar = dbar + xbar * sk;
