@@ -236,7 +236,7 @@ extern "C" dt_status dt_smooth_solve(const int32_t* adj_off, const int32_t* adj,
     b2[c] = sums[c] > 1e-300 ? sums[c] : 1e-300;
     lim[c] = tol * tol * b2[c];
   }
-  auto verdict = [&](const double* rr, double& worst) {
+  auto within_tol = [&](const double* rr, double& worst) {
     bool ok = true;
     worst = 0.0;
     for (int c = 0; c < 3; ++c) {
@@ -246,7 +246,7 @@ extern "C" dt_status dt_smooth_solve(const int32_t* adj_off, const int32_t* adj,
     return ok;
   };
   double worst = 0.0;
-  bool done = verdict(sums + 3, worst);
+  bool done = within_tol(sums + 3, worst);
   int it = 0;
   // rho_0 = delta / theta, rho_{k+1} = 1 / (2 sigma - rho_k), sigma = theta / delta;
   // d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) r_{k+1} (a matrix with
@@ -272,7 +272,7 @@ extern "C" dt_status dt_smooth_solve(const int32_t* adj_off, const int32_t* adj,
       DT_CHECK_LAUNCH();
       DT_CHECK_HIP(hipMemcpyAsync(sums + 3, w.sums + 3, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
       DT_CHECK_HIP(hipStreamSynchronize(s));
-      done = verdict(sums + 3, worst);
+      done = within_tol(sums + 3, worst);
     }
   }
   if (iters_out) *iters_out = it;
