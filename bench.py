@@ -913,8 +913,9 @@ def cpu_baseline(wl, stride):
     log(f"cpu baseline: {len(o)} camera rays, {segs} segments, {el:.1f} s")
     return {"value": round(segs / el / 1e6, 4), "unit": "Mrays/s", "cores": oracle.num_threads(),
             "kind": "oracle", "cpu_model": host_cpu_model(),
-            "sample": f"every {stride}th pixel in x and y of all {len(wl.cameras)} views "
-                      f"({len(o)} camera rays, {segs} segments); FP64 forward + reverse-mode "
+            "sample": (f"every pixel of all {len(wl.cameras)} views" if stride == 1 else
+                       f"every {stride}th pixel in x and y of all {len(wl.cameras)} views")
+                      + f" ({len(o)} camera rays, {segs} segments); FP64 forward + reverse-mode "
                       f"gradient in one pass per camera ray",
             "seconds": round(el, 2)}
 
